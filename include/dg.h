@@ -1,0 +1,168 @@
+/*
+ * dg.h -- C ABI of the MI355X matrix-free discontinuous Galerkin library.
+ *
+ * The library evaluates, on one gfx950 GPU, the hot path of a high-order
+ * modal DG discretisation of the compressible Navier-Stokes equations with
+ * BR2 viscous fluxes (Franciolini, Botti, Colombo, Crivellini,
+ * arXiv:1809.00866):
+ *
+ *   dg_residual             residual f_h of eq. (NSdiscrRes), Sec. 2.2
+ *   dg_jvp                  Jacobian-vector product j_h (Sec. 2.2), exact
+ *                           tangent or the finite difference of
+ *                           eqs. (matrix-free)/(epsdef), Sec. 2.3
+ *   dg_block_precond_setup  element-wise block Jacobi (EWBJ, Sec. 2.3):
+ *   dg_block_precond_apply  LU of the diagonal blocks of G = shift*I + J
+ *   dg_fgmres_solve         flexible GMRES (Sec. 2.5) on G dw = b,
+ *                           eq. (rosSysOp) with M = I (orthonormal basis)
+ *
+ * Conventions (all entry points):
+ *  - Every vector is FP64, device memory, caller-owned, contiguous, in the
+ *    DOF layout  idx(e, c, b) = (c*Nb + b)*n_elem + e  (element index
+ *    fastest; c = conserved variable rho, rho*u_1..d, rho*E; b = mode).
+ *  - `stream` is a hipStream_t passed as void*; NULL means the default
+ *    stream.  Calls are stream-ordered and asynchronous unless stated.
+ *  - Inputs and outputs must not alias unless stated.
+ *  - The library owns its tables, scratch vectors, block factors and Krylov
+ *    bases; they are allocated by dg_create / setup calls and released by
+ *    dg_destroy.
+ *  - Argument and state errors are returned synchronously; asynchronous
+ *    device faults surface at the next call or at dg_sync.  dg_last_error()
+ *    returns a thread-local message for the last non-OK status.
+ */
+#ifndef DG_H
+#define DG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dg_context dg_context;
+
+typedef enum {
+  DG_OK = 0,
+  DG_NOT_CONVERGED = 1,       /* status, not an error: x holds the last iterate */
+  DG_ERR_ARG = -1,            /* invalid argument or unsupported configuration */
+  DG_ERR_HIP = -2,            /* a HIP runtime call failed */
+  DG_ERR_OOM = -3,            /* device allocation failed */
+  DG_ERR_STATE = -4,          /* e.g. block apply before block setup */
+  DG_ERR_SINGULAR_BLOCK = -5, /* zero pivot in a diagonal block */
+  DG_ERR_NONFINITE = -6       /* NaN/Inf met where a finite value is required */
+} dg_status;
+
+enum { DG_BASIS_PK = 0, DG_BASIS_QK = 1 };          /* total degree / tensor degree */
+enum { DG_FLUX_LF = 0, DG_FLUX_ROE = 1 };           /* convective numerical flux */
+enum { DG_JVP_EXACT = 0, DG_JVP_FD = 1 };           /* Jv mode */
+enum { DG_FP64 = 0, DG_FP32 = 1, DG_BF16 = 2 };     /* block-factor storage */
+enum { DG_PREC_NONE = 0, DG_PREC_BJ = 1 };          /* FGMRES preconditioner */
+
+/* Discretisation parameters.
+ *  dim 2 or 3; order k >= 0; basis DG_BASIS_PK (paper's total-degree space,
+ *  Sec. 2.1) or DG_BASIS_QK; nq1d Gauss points per direction (volume rule
+ *  nq1d^dim, face rule nq1d^(dim-1)); flux DG_FLUX_LF or DG_FLUX_ROE;
+ *  gamma, prandtl, mu: perfect gas, constant viscosity; eta_br2: BR2
+ *  stabilisation (must exceed the number of faces of an element, Sec. 2.1;
+ *  <= 0 selects 2*dim+1); entropy_fix: Harten fix width of the Roe flux as a
+ *  fraction of |u.n| + c (<= 0 selects 0.1). */
+typedef struct {
+  int dim, order, basis, nq1d, flux;
+  double gamma, prandtl, mu, eta_br2, entropy_fix;
+} dg_params;
+
+/* Mesh (host memory, read during dg_create only).
+ *  elem_xyz [n_elem][2^dim][dim]: corner coordinates, corners lexicographic
+ *  (v = v0 + 2*v1 + 4*v2, v_i = 0/1 low/high end along axis i), unwrapped
+ *  across periodic boundaries.  elem_nbr [n_elem][2*dim]: face neighbours in
+ *  the order -x,+x,-y,+y,-z,+z; the +p neighbour's -p neighbour must be the
+ *  element itself.  This version requires every element to be the same
+ *  axis-aligned box (uniform periodic lattice); other meshes return
+ *  DG_ERR_ARG. */
+typedef struct {
+  int64_t n_elem;
+  const double* elem_xyz;
+  const int64_t* elem_nbr;
+} dg_mesh;
+
+/* Create a context (allocates tables and scratch on the current device). */
+dg_status dg_create(const dg_params* params, const dg_mesh* mesh, dg_context** out);
+void dg_destroy(dg_context* ctx);
+
+/* Sizes: DOFs = n_elem*nvar*nbasis; nq = volume points per element. */
+int64_t dg_ndof(const dg_context* ctx);
+int dg_nbasis(const dg_context* ctx);
+int dg_nvar(const dg_context* ctx);
+int dg_nq(const dg_context* ctx);
+
+/* Physical coordinates of the volume quadrature points, device output
+ * xyz[dim][nq][n_elem]. */
+dg_status dg_volume_points(dg_context* ctx, double* xyz, void* stream);
+
+/* L2 projection onto the orthonormal basis: w_b = sum_q w_q |J_q| phi_b(x_q) f(x_q).
+ * f: device input [nvar][nq][n_elem] (values at the volume points); w: DOFs. */
+dg_status dg_project(dg_context* ctx, const double* f, double* w, void* stream);
+
+/* Residual r = f_h(w) (eq. NSdiscrRes): -volume flux against grad(phi) plus
+ * the numerical flux against the jump of phi; BR2 corrected gradients. */
+dg_status dg_residual(dg_context* ctx, const double* w, double* r, void* stream);
+
+/* out = shift*v + J(w) v.
+ *  mode DG_JVP_EXACT: exact directional derivative of the residual (the
+ *  Jacobian forms j_h of Sec. 2.2 applied to v), FP64.
+ *  mode DG_JVP_FD: (f_h(w + D v) - f_h(w))/D with D = 1e-9*sqrt(1+||w||)/||v||
+ *  (eqs. matrix-free, epsdef; L2 norms = DOF 2-norms).  r_w may pass f_h(w)
+ *  (device, nullable) to skip its evaluation.  ||v|| = 0 gives out = 0 + shift*v.
+ *  out may not alias w, v or r_w. */
+dg_status dg_jvp(dg_context* ctx, const double* w, const double* r_w, const double* v, double shift,
+                 int mode, double* out, void* stream);
+
+/* EWBJ setup: D_K = shift*I + dR_K/dU_K for every element (exact, by
+ * coloured probing with exact Jv), factored by Gauss-Jordan with partial
+ * pivoting into explicit inverses, stored as `storage` (DG_FP64 or DG_FP32).
+ * Returns DG_ERR_SINGULAR_BLOCK if a pivot is exactly zero or non-finite
+ * (synchronises the stream). */
+dg_status dg_block_precond_setup(dg_context* ctx, const double* w, double shift, int storage, void* stream);
+
+/* z_K = D_K^{-1} r_K for every element (needs a prior setup; DG_ERR_STATE
+ * otherwise).  r and z may not alias. */
+dg_status dg_block_precond_apply(dg_context* ctx, const double* r, double* z, void* stream);
+
+typedef struct {
+  int restart;     /* Krylov subspace size m (default 30) */
+  int max_iter;    /* total iteration cap */
+  double rtol;     /* ||b - G x|| <= rtol*||b|| on the true residual */
+  int precond;     /* DG_PREC_NONE or DG_PREC_BJ (block setup must exist) */
+  int jvp_mode;    /* DG_JVP_EXACT or DG_JVP_FD for G z */
+} dg_solve_opts;
+
+typedef struct {
+  int iters, restarts, converged;
+  double rel_res_est, rel_res_true, rho; /* rho: convergence factor */
+  double ms_solve;
+} dg_solve_stats;
+
+/* Right-preconditioned flexible GMRES(m) for (shift*I + J(w)) x = b.
+ * Classical Gram-Schmidt with one re-orthogonalisation, Givens rotations,
+ * restarts from the true residual.  x: device, in = initial guess, out =
+ * solution.  b = 0 returns x = 0.  Synchronises the stream once per
+ * iteration.  opts/stats are host memory; stats may be NULL. */
+dg_status dg_fgmres_solve(dg_context* ctx, const double* w, double shift, const double* b, double* x,
+                          const dg_solve_opts* opts, dg_solve_stats* stats, void* stream);
+
+/* max over volume points of |u| + c, returned to host memory (synchronises). */
+dg_status dg_max_wave_speed(dg_context* ctx, const double* w, double* out, void* stream);
+
+/* Per-kernel timing: when enabled, the library records HIP events around
+ * each launch on the launch stream; dg_kernel_time returns the accumulated
+ * milliseconds and launch count of a named kernel ("face_jvp", "vol_jvp",
+ * "face_res", "vol_res", "block_apply", ...) and resets it.  Synchronises. */
+dg_status dg_set_profiling(dg_context* ctx, int on);
+dg_status dg_kernel_time(dg_context* ctx, const char* name, double* ms, int64_t* launches);
+
+const char* dg_last_error(void);
+dg_status dg_sync(dg_context* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DG_H */

@@ -291,12 +291,16 @@ class DGOracle:
         return D
 
     # --------------------------------------------------------------- projection
-    def project(self, f, elems=None):
-        """L2 projection of f(x)[..., n] onto the physical orthonormal basis."""
+    def project(self, f, elems=None, chunk=4096):
+        """L2 projection of f(x)[..., n] onto the physical orthonormal basis
+        (elements processed in chunks to bound memory)."""
         el = np.arange(self.ne) if elems is None else np.asarray(elems)
-        et = self.elem_tables(el)
-        vals = f(et["x"])  # [E, Q, n]
-        return _ein("eq,eqc,eqb->ecb", et["wdet"], vals, et["phi"])
+        out = np.empty((len(el), self.nvar, self.nb))
+        for s in range(0, len(el), chunk):
+            et = self.elem_tables(el[s:s + chunk])
+            vals = f(et["x"])  # [E, Q, n]
+            out[s:s + chunk] = _ein("eq,eqc,eqb->ecb", et["wdet"], vals, et["phi"])
+        return out
 
     def evaluate(self, U, xi, elems=None):
         """u at reference points xi[Q, d] of each element (for error norms)."""

@@ -1,0 +1,100 @@
+"""ctypes view of include/dg.h (argument marshalling only).
+
+Loading fails loudly: there is no fallback implementation.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdg.so")
+
+DG_OK, DG_NOT_CONVERGED = 0, 1
+STATUS_NAMES = {0: "DG_OK", 1: "DG_NOT_CONVERGED", -1: "DG_ERR_ARG", -2: "DG_ERR_HIP", -3: "DG_ERR_OOM",
+                -4: "DG_ERR_STATE", -5: "DG_ERR_SINGULAR_BLOCK", -6: "DG_ERR_NONFINITE"}
+DG_BASIS_PK, DG_BASIS_QK = 0, 1
+DG_FLUX_LF, DG_FLUX_ROE = 0, 1
+DG_JVP_EXACT, DG_JVP_FD = 0, 1
+DG_FP64, DG_FP32, DG_BF16 = 0, 1, 2
+DG_PREC_NONE, DG_PREC_BJ = 0, 1
+
+EXPORTED = ["dg_create", "dg_destroy", "dg_ndof", "dg_nbasis", "dg_nvar", "dg_nq", "dg_volume_points",
+            "dg_project", "dg_residual", "dg_jvp", "dg_block_precond_setup", "dg_block_precond_apply",
+            "dg_fgmres_solve", "dg_max_wave_speed", "dg_set_profiling", "dg_kernel_time", "dg_last_error",
+            "dg_sync"]
+
+
+class DGParams(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("order", ctypes.c_int), ("basis", ctypes.c_int), ("nq1d", ctypes.c_int),
+                ("flux", ctypes.c_int), ("gamma", ctypes.c_double), ("prandtl", ctypes.c_double),
+                ("mu", ctypes.c_double), ("eta_br2", ctypes.c_double), ("entropy_fix", ctypes.c_double)]
+
+
+class DGMesh(ctypes.Structure):
+    _fields_ = [("n_elem", ctypes.c_int64), ("elem_xyz", ctypes.POINTER(ctypes.c_double)),
+                ("elem_nbr", ctypes.POINTER(ctypes.c_int64))]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("restart", ctypes.c_int), ("max_iter", ctypes.c_int), ("rtol", ctypes.c_double),
+                ("precond", ctypes.c_int), ("jvp_mode", ctypes.c_int)]
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("restarts", ctypes.c_int), ("converged", ctypes.c_int),
+                ("rel_res_est", ctypes.c_double), ("rel_res_true", ctypes.c_double), ("rho", ctypes.c_double),
+                ("ms_solve", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load():
+    """Load libdg.so and declare signatures; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1809_00866_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, d, i, i64 = ctypes.c_void_p, ctypes.c_double, ctypes.c_int, ctypes.c_int64
+    ctx = ctypes.c_void_p
+    sig = {
+        "dg_create": (i, [ctypes.POINTER(DGParams), ctypes.POINTER(DGMesh), ctypes.POINTER(ctypes.c_void_p)]),
+        "dg_destroy": (None, [ctx]),
+        "dg_ndof": (i64, [ctx]),
+        "dg_nbasis": (i, [ctx]),
+        "dg_nvar": (i, [ctx]),
+        "dg_nq": (i, [ctx]),
+        "dg_volume_points": (i, [ctx, vp, vp]),
+        "dg_project": (i, [ctx, vp, vp, vp]),
+        "dg_residual": (i, [ctx, vp, vp, vp]),
+        "dg_jvp": (i, [ctx, vp, vp, vp, d, i, vp, vp]),
+        "dg_block_precond_setup": (i, [ctx, vp, d, i, vp]),
+        "dg_block_precond_apply": (i, [ctx, vp, vp, vp]),
+        "dg_fgmres_solve": (i, [ctx, vp, d, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats), vp]),
+        "dg_max_wave_speed": (i, [ctx, vp, ctypes.POINTER(ctypes.c_double), vp]),
+        "dg_set_profiling": (i, [ctx, i]),
+        "dg_kernel_time": (i, [ctx, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
+        "dg_last_error": (ctypes.c_char_p, []),
+        "dg_sync": (i, [ctx]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+class DGError(RuntimeError):
+    def __init__(self, status, where):
+        lib = load()
+        msg = lib.dg_last_error().decode()
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def check(status, where, allow_not_converged=False):
+    if status == DG_OK or (allow_not_converged and status == DG_NOT_CONVERGED):
+        return status
+    raise DGError(status, where)

@@ -1,0 +1,153 @@
+"""Thin torch wrapper over the C ABI: device tensors in, device tensors out.
+
+Every numerical step runs in libdg.so; this module only checks tensor
+shapes/dtypes/devices and passes raw pointers plus the current HIP stream.
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+_FLUX = {"lf": L.DG_FLUX_LF, "roe": L.DG_FLUX_ROE}
+_BASIS = {"P": L.DG_BASIS_PK, "Q": L.DG_BASIS_QK}
+_MODE = {"exact": L.DG_JVP_EXACT, "fd": L.DG_JVP_FD}
+_STORAGE = {"fp64": L.DG_FP64, "fp32": L.DG_FP32}
+_PREC = {"none": L.DG_PREC_NONE, "bj": L.DG_PREC_BJ}
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+class DG:
+    """A DG discretisation on a periodic lattice (see include/dg.h)."""
+
+    def __init__(self, mesh, order, basis="P", nq1d=None, flux="roe", gamma=1.4, prandtl=0.72, mu=1e-3,
+                 eta=0.0, entropy_fix=0.0, device="cuda"):
+        self.lib = L.load()
+        self.dim = int(mesh["dim"])
+        self.order = int(order)
+        self.nq1d = int(nq1d if nq1d is not None else order + 1)
+        self.device = torch.device(device)
+        prm = L.DGParams(self.dim, self.order, _BASIS[basis], self.nq1d, _FLUX[flux], gamma, prandtl, mu, eta,
+                         entropy_fix)
+        xyz = np.ascontiguousarray(mesh["elem_xyz"], dtype=np.float64)
+        nbr = np.ascontiguousarray(mesh["elem_nbr"], dtype=np.int64)
+        m = L.DGMesh(xyz.shape[0], xyz.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                     nbr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            L.check(self.lib.dg_create(ctypes.byref(prm), ctypes.byref(m), ctypes.byref(h)), "dg_create")
+        self.ctx = h
+        self.ne = xyz.shape[0]
+        self.ndof = self.lib.dg_ndof(h)
+        self.nb = self.lib.dg_nbasis(h)
+        self.nv = self.lib.dg_nvar(h)
+        self.nq = self.lib.dg_nq(h)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.dg_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- helpers
+    def _vec(self, t, name):
+        if not (isinstance(t, torch.Tensor) and t.dtype == torch.float64 and t.is_cuda and t.is_contiguous()
+                and t.numel() == self.ndof):
+            raise ValueError(f"{name} must be a contiguous float64 CUDA tensor with {self.ndof} entries")
+        return t
+
+    def empty(self):
+        return torch.empty(self.ndof, dtype=torch.float64, device=self.device)
+
+    # ---------------------------------------------------------------- entry points
+    def volume_points(self):
+        xyz = torch.empty((self.dim, self.nq, self.ne), dtype=torch.float64, device=self.device)
+        L.check(self.lib.dg_volume_points(self.ctx, _ptr(xyz), _stream()), "dg_volume_points")
+        return xyz
+
+    def project(self, f):
+        """f: [nvar][nq][n_elem] values at the volume points -> DOF vector."""
+        f = f.contiguous()
+        if f.shape != (self.nv, self.nq, self.ne) or f.dtype != torch.float64 or not f.is_cuda:
+            raise ValueError("f must be float64 CUDA [nvar, nq, n_elem]")
+        w = self.empty()
+        L.check(self.lib.dg_project(self.ctx, _ptr(f), _ptr(w), _stream()), "dg_project")
+        return w
+
+    def project_field(self, field):
+        """Evaluate a host field function at the volume points and project on the GPU."""
+        xyz = self.volume_points().cpu().numpy()            # [dim, nq, ne]
+        vals = field(np.moveaxis(xyz, 0, -1))                # [nq, ne, nvar]
+        f = torch.from_numpy(np.ascontiguousarray(np.moveaxis(vals, -1, 0))).to(self.device)
+        return self.project(f)
+
+    def residual(self, w, out=None):
+        self._vec(w, "w")
+        out = self.empty() if out is None else self._vec(out, "out")
+        L.check(self.lib.dg_residual(self.ctx, _ptr(w), _ptr(out), _stream()), "dg_residual")
+        return out
+
+    def jvp(self, w, v, shift=0.0, mode="exact", r_w=None, out=None):
+        self._vec(w, "w")
+        self._vec(v, "v")
+        if r_w is not None:
+            self._vec(r_w, "r_w")
+        out = self.empty() if out is None else self._vec(out, "out")
+        L.check(self.lib.dg_jvp(self.ctx, _ptr(w), _ptr(r_w), _ptr(v), float(shift), _MODE[mode], _ptr(out),
+                                _stream()), "dg_jvp")
+        return out
+
+    def block_setup(self, w, shift, storage="fp64"):
+        self._vec(w, "w")
+        L.check(self.lib.dg_block_precond_setup(self.ctx, _ptr(w), float(shift), _STORAGE[storage], _stream()),
+                "dg_block_precond_setup")
+
+    def block_apply(self, r, out=None):
+        self._vec(r, "r")
+        out = self.empty() if out is None else self._vec(out, "out")
+        L.check(self.lib.dg_block_precond_apply(self.ctx, _ptr(r), _ptr(out), _stream()), "dg_block_precond_apply")
+        return out
+
+    def fgmres(self, w, shift, b, x=None, restart=30, max_iter=1000, rtol=1e-8, precond="bj", jvp_mode="exact"):
+        self._vec(w, "w")
+        self._vec(b, "b")
+        x = torch.zeros_like(b) if x is None else self._vec(x, "x")
+        opts = L.SolveOpts(restart, max_iter, rtol, _PREC[precond], _MODE[jvp_mode])
+        st = L.SolveStats()
+        status = self.lib.dg_fgmres_solve(self.ctx, _ptr(w), float(shift), _ptr(b), _ptr(x), ctypes.byref(opts),
+                                          ctypes.byref(st), _stream())
+        L.check(status, "dg_fgmres_solve", allow_not_converged=True)
+        stats = {k: getattr(st, k) for k, _ in L.SolveStats._fields_}
+        return x, stats
+
+    def max_wave_speed(self, w):
+        self._vec(w, "w")
+        out = ctypes.c_double()
+        L.check(self.lib.dg_max_wave_speed(self.ctx, _ptr(w), ctypes.byref(out), _stream()), "dg_max_wave_speed")
+        return out.value
+
+    def set_profiling(self, on=True):
+        L.check(self.lib.dg_set_profiling(self.ctx, int(bool(on))), "dg_set_profiling")
+
+    def kernel_time(self, name):
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        L.check(self.lib.dg_kernel_time(self.ctx, name.encode(), ctypes.byref(ms), ctypes.byref(n)),
+                "dg_kernel_time")
+        return ms.value, n.value
+
+    def sync(self):
+        L.check(self.lib.dg_sync(self.ctx), "dg_sync")

@@ -1,0 +1,617 @@
+// extern "C" entry points of the DG library: context management, residual,
+// Jacobian-vector products, element block-Jacobi preconditioner and the
+// flexible GMRES driver.  Every entry point validates its arguments on the
+// host and enqueues HIP kernels on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "dg_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+dg_status fail(dg_status s, const std::string& m) {
+  g_err = m;
+  return s;
+}
+
+#define HIPCHK(call)                                                                           \
+  do {                                                                                         \
+    hipError_t e_ = (call);                                                                    \
+    if (e_ != hipSuccess) return fail(DG_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+struct Timer {
+  double ms = 0.0;
+  int64_t n = 0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+};
+
+}  // namespace
+
+struct dg_context {
+  dg_params prm{};
+  int dim = 0, nv = 0, nb = 0, nq1 = 0, nq = 0, nfq = 0, cfg = -1;
+  int64_t ne = 0, ndof = 0;
+  dgk::Tables tb{};
+  dgk::Mesh mesh{};
+  dgk::Phys ph{};
+  double* d_tab = nullptr;
+  int64_t* d_nbr = nullptr;
+  double* d_x0 = nullptr;
+  double* d_H = nullptr;
+  double* d_t1 = nullptr;
+  double* d_t2 = nullptr;
+  double* d_t3 = nullptr;
+  double* d_rw = nullptr;
+  double* d_red = nullptr;
+  double* d_scal = nullptr;
+  int* d_flag = nullptr;
+  int* d_color = nullptr;
+  int ncolor = 0;
+  double* d_D64 = nullptr;
+  void* d_Dinv = nullptr;
+  int blk_storage = -1;
+  bool blk_ready = false;
+  double* d_V = nullptr;
+  double* d_Z = nullptr;
+  int kry_m = 0;
+  double* h_pin = nullptr;
+  bool prof = false;
+  std::map<std::string, Timer> timers;
+};
+
+namespace {
+
+// Records HIP events around a launch on its stream when profiling is on.
+struct ProfScope {
+  dg_context* c;
+  const char* name;
+  hipStream_t s;
+  hipEvent_t a = nullptr, b = nullptr;
+  ProfScope(dg_context* ctx, const char* nm, hipStream_t st) : c(ctx), name(nm), s(st) {
+    if (c->prof) {
+      (void)hipEventCreate(&a);
+      (void)hipEventCreate(&b);
+      (void)hipEventRecord(a, s);
+    }
+  }
+  ~ProfScope() {
+    if (c->prof) {
+      (void)hipEventRecord(b, s);
+      c->timers[name].ev.push_back({a, b});
+    }
+  }
+};
+
+dg_status eval_residual(dg_context* c, bool jvp, const double* w, const double* v, double shift, double* out,
+                        hipStream_t s) {
+  {
+    ProfScope ps(c, jvp ? "face_jvp" : "face_res", s);
+    HIPCHK(dgk::launch_face(c->cfg, jvp, w, v, c->d_H, c->tb, c->mesh, c->ph, s));
+  }
+  {
+    ProfScope ps(c, jvp ? "vol_jvp" : "vol_res", s);
+    HIPCHK(dgk::launch_volume(c->cfg, jvp, w, v, c->d_H, out, shift, c->tb, c->mesh, c->ph, s));
+  }
+  return DG_OK;
+}
+
+dg_status norm2(dg_context* c, const double* x, double* dout, hipStream_t s) {
+  HIPCHK(dgk::launch_dot_partials(x, x, c->ndof, c->d_red, s));
+  HIPCHK(dgk::launch_sum_partials(c->d_red, dgk::kRedBlocks, dout, 1, s));
+  return DG_OK;
+}
+
+dg_status jvp_impl(dg_context* c, const double* w, const double* r_w, const double* v, double shift, int mode,
+                   double* out, hipStream_t s) {
+  if (mode == DG_JVP_EXACT) return eval_residual(c, true, w, v, shift, out, s);
+  // finite difference of eqs. (matrix-free)/(epsdef)
+  const double* r0 = r_w;
+  dg_status st;
+  if (!r0) {
+    if ((st = eval_residual(c, false, w, nullptr, 0.0, c->d_t1, s)) != DG_OK) return st;
+    r0 = c->d_t1;
+  }
+  if ((st = norm2(c, w, c->d_scal + 0, s)) != DG_OK) return st;
+  if ((st = norm2(c, v, c->d_scal + 1, s)) != DG_OK) return st;
+  HIPCHK(dgk::launch_fd_delta(c->d_scal, 1e-9, s));
+  HIPCHK(dgk::launch_axpy_dev(c->ndof, w, c->d_scal + 2, 1.0, v, c->d_t2, s));
+  if ((st = eval_residual(c, false, c->d_t2, nullptr, 0.0, c->d_t3, s)) != DG_OK) return st;
+  HIPCHK(dgk::launch_fd_combine(c->ndof, c->d_t3, r0, c->d_scal + 3, v, shift, out, s));
+  return DG_OK;
+}
+
+template <class T>
+dg_status dalloc(T** p, size_t n) {
+  if (*p) return DG_OK;
+  if (hipMalloc((void**)p, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return fail(DG_ERR_OOM, "hipMalloc of " + std::to_string(n * sizeof(T)) + " bytes failed");
+  }
+  return DG_OK;
+}
+
+void dfree(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dg_last_error(void) { return g_err.c_str(); }
+
+dg_status dg_create(const dg_params* prm, const dg_mesh* mesh, dg_context** out) {
+  if (!prm || !mesh || !out) return fail(DG_ERR_ARG, "null argument");
+  *out = nullptr;
+  const int dim = prm->dim;
+  if (dim != 2 && dim != 3) return fail(DG_ERR_ARG, "dim must be 2 or 3");
+  if (prm->order < 0 || prm->nq1d < 1) return fail(DG_ERR_ARG, "order must be >= 0 and nq1d >= 1");
+  if (prm->basis != DG_BASIS_PK && prm->basis != DG_BASIS_QK) return fail(DG_ERR_ARG, "unknown basis");
+  if (prm->flux != DG_FLUX_LF && prm->flux != DG_FLUX_ROE) return fail(DG_ERR_ARG, "unknown flux");
+  if (!(prm->gamma > 1.0) || !(prm->prandtl > 0.0) || !(prm->mu >= 0.0))
+    return fail(DG_ERR_ARG, "need gamma > 1, prandtl > 0, mu >= 0");
+  const int64_t ne = mesh->n_elem;
+  if (ne < 1 || !mesh->elem_xyz || !mesh->elem_nbr) return fail(DG_ERR_ARG, "empty mesh");
+  if (ne > (int64_t)1 << 31) return fail(DG_ERR_ARG, "too many elements");
+  const int nvtx = 1 << dim;
+  // uniform axis-aligned lattice check
+  double h[3] = {1.0, 1.0, 1.0};
+  for (int i = 0; i < dim; ++i) h[i] = mesh->elem_xyz[(size_t)(1 << i) * dim + i] - mesh->elem_xyz[i];
+  for (int i = 0; i < dim; ++i)
+    if (!(h[i] > 0.0)) return fail(DG_ERR_ARG, "element 0 is not an axis-aligned box with positive edges");
+  for (int64_t e = 0; e < ne; ++e) {
+    const double* X = mesh->elem_xyz + (size_t)e * nvtx * dim;
+    for (int v = 0; v < nvtx; ++v)
+      for (int i = 0; i < dim; ++i) {
+        const double expect = X[i] + (((v >> i) & 1) ? h[i] : 0.0);
+        if (std::fabs(X[(size_t)v * dim + i] - expect) > 1e-10 * h[i])
+          return fail(DG_ERR_ARG, "element " + std::to_string(e) +
+                                      " is not the same axis-aligned box as element 0 (only uniform lattices "
+                                      "are supported)");
+      }
+  }
+  for (int64_t e = 0; e < ne; ++e)
+    for (int p = 0; p < dim; ++p) {
+      const int64_t a = mesh->elem_nbr[e * 2 * dim + 2 * p], b = mesh->elem_nbr[e * 2 * dim + 2 * p + 1];
+      if (a < 0 || a >= ne || b < 0 || b >= ne) return fail(DG_ERR_ARG, "neighbour index out of range");
+      if (mesh->elem_nbr[b * 2 * dim + 2 * p] != e)
+        return fail(DG_ERR_ARG, "inconsistent neighbour table at element " + std::to_string(e));
+    }
+
+  dgh::HostTables T;
+  try {
+    T = dgh::build_tables(dim, prm->order, prm->basis, prm->nq1d, h);
+  } catch (const std::exception& ex) {
+    return fail(DG_ERR_ARG, ex.what());
+  }
+  const int cfg = dgk::config_index(dim, T.nb, prm->nq1d);
+  if (cfg < 0)
+    return fail(DG_ERR_ARG, "no kernel compiled for dim=" + std::to_string(dim) + " nbasis=" + std::to_string(T.nb) +
+                                " nq1d=" + std::to_string(prm->nq1d));
+
+  auto* c = new dg_context();
+  c->prm = *prm;
+  c->dim = dim;
+  c->nv = dim + 2;
+  c->nb = T.nb;
+  c->nq1 = prm->nq1d;
+  c->nq = T.nq;
+  c->nfq = T.nfq;
+  c->cfg = cfg;
+  c->ne = ne;
+  c->ndof = ne * c->nv * c->nb;
+  c->ph.gamma = prm->gamma;
+  c->ph.prandtl = prm->prandtl;
+  c->ph.mu = prm->mu;
+  c->ph.eta = prm->eta_br2 > 0.0 ? prm->eta_br2 : 2.0 * dim + 1.0;
+  c->ph.efix = prm->entropy_fix > 0.0 ? prm->entropy_fix : 0.1;
+  c->ph.flux = prm->flux;
+
+  auto cleanup = [&](dg_status st) {
+    dg_destroy(c);
+    return st;
+  };
+
+  // packed tables
+  std::vector<const std::vector<double>*> parts = {&T.vPhi, &T.vWD, &T.vWPhi, &T.vLift, &T.fPhi,
+                                                   &T.fDphi, &T.fLift, &T.fWPhi, &T.vXi};
+  size_t tot = 0;
+  for (auto* v : parts) tot += v->size();
+  dg_status st;
+  if ((st = dalloc(&c->d_tab, tot)) != DG_OK) return cleanup(st);
+  std::vector<double> packed;
+  packed.reserve(tot);
+  std::vector<size_t> off;
+  for (auto* v : parts) {
+    off.push_back(packed.size());
+    packed.insert(packed.end(), v->begin(), v->end());
+  }
+  if (hipMemcpy(c->d_tab, packed.data(), tot * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+    return cleanup(fail(DG_ERR_HIP, "table upload failed"));
+  c->tb.vPhi = c->d_tab + off[0];
+  c->tb.vWD = c->d_tab + off[1];
+  c->tb.vWPhi = c->d_tab + off[2];
+  c->tb.vLift = c->d_tab + off[3];
+  c->tb.fPhi = c->d_tab + off[4];
+  c->tb.fDphi = c->d_tab + off[5];
+  c->tb.fLift = c->d_tab + off[6];
+  c->tb.fWPhi = c->d_tab + off[7];
+  c->tb.vXi = c->d_tab + off[8];
+
+  // neighbours transposed to [2*dim][ne], low corners [dim][ne]
+  std::vector<int64_t> nbrT((size_t)2 * dim * ne);
+  std::vector<double> x0((size_t)dim * ne);
+  for (int64_t e = 0; e < ne; ++e) {
+    for (int k = 0; k < 2 * dim; ++k) nbrT[(size_t)k * ne + e] = mesh->elem_nbr[e * 2 * dim + k];
+    for (int i = 0; i < dim; ++i) x0[(size_t)i * ne + e] = mesh->elem_xyz[(size_t)e * nvtx * dim + i];
+  }
+  if ((st = dalloc(&c->d_nbr, nbrT.size())) != DG_OK) return cleanup(st);
+  if ((st = dalloc(&c->d_x0, x0.size())) != DG_OK) return cleanup(st);
+  if (hipMemcpy(c->d_nbr, nbrT.data(), nbrT.size() * sizeof(int64_t), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->d_x0, x0.data(), x0.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+    return cleanup(fail(DG_ERR_HIP, "mesh upload failed"));
+  c->mesh.ne = ne;
+  c->mesh.nbr = c->d_nbr;
+  c->mesh.x0 = c->d_x0;
+  for (int i = 0; i < 3; ++i) c->mesh.h[i] = h[i];
+
+  // greedy colouring of the face-neighbour graph (self loops ignored)
+  std::vector<int> color(ne, -1);
+  int ncol = 0;
+  for (int64_t e = 0; e < ne; ++e) {
+    uint64_t used = 0;
+    for (int k = 0; k < 2 * dim; ++k) {
+      const int64_t n = mesh->elem_nbr[e * 2 * dim + k];
+      if (n != e && color[n] >= 0 && color[n] < 64) used |= (uint64_t)1 << color[n];
+    }
+    int col = 0;
+    while (used & ((uint64_t)1 << col)) ++col;
+    color[e] = col;
+    ncol = std::max(ncol, col + 1);
+  }
+  c->ncolor = ncol;
+  if ((st = dalloc(&c->d_color, (size_t)ne)) != DG_OK) return cleanup(st);
+  if (hipMemcpy(c->d_color, color.data(), ne * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+    return cleanup(fail(DG_ERR_HIP, "colour upload failed"));
+
+  if ((st = dalloc(&c->d_H, (size_t)dim * c->nv * c->nfq * ne)) != DG_OK) return cleanup(st);
+  if ((st = dalloc(&c->d_t1, (size_t)c->ndof)) != DG_OK) return cleanup(st);
+  if ((st = dalloc(&c->d_t2, (size_t)c->ndof)) != DG_OK) return cleanup(st);
+  if ((st = dalloc(&c->d_t3, (size_t)c->ndof)) != DG_OK) return cleanup(st);
+  if ((st = dalloc(&c->d_red, (size_t)64 * dgk::kRedBlocks)) != DG_OK) return cleanup(st);
+  if ((st = dalloc(&c->d_scal, (size_t)256)) != DG_OK) return cleanup(st);
+  if ((st = dalloc(&c->d_flag, (size_t)16)) != DG_OK) return cleanup(st);
+  if (hipHostMalloc((void**)&c->h_pin, 256 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    c->h_pin = nullptr;
+    return cleanup(fail(DG_ERR_OOM, "pinned host allocation failed"));
+  }
+  *out = c;
+  return DG_OK;
+}
+
+void dg_destroy(dg_context* c) {
+  if (!c) return;
+  for (auto& kv : c->timers)
+    for (auto& ab : kv.second.ev) {
+      (void)hipEventDestroy(ab.first);
+      (void)hipEventDestroy(ab.second);
+    }
+  dfree(c->d_tab);
+  dfree(c->d_nbr);
+  dfree(c->d_x0);
+  dfree(c->d_H);
+  dfree(c->d_t1);
+  dfree(c->d_t2);
+  dfree(c->d_t3);
+  dfree(c->d_rw);
+  dfree(c->d_red);
+  dfree(c->d_scal);
+  dfree(c->d_flag);
+  dfree(c->d_color);
+  dfree(c->d_D64);
+  if (c->d_Dinv != c->d_D64) dfree(c->d_Dinv);
+  dfree(c->d_V);
+  dfree(c->d_Z);
+  if (c->h_pin) (void)hipHostFree(c->h_pin);
+  delete c;
+}
+
+int64_t dg_ndof(const dg_context* c) { return c ? c->ndof : -1; }
+int dg_nbasis(const dg_context* c) { return c ? c->nb : -1; }
+int dg_nvar(const dg_context* c) { return c ? c->nv : -1; }
+int dg_nq(const dg_context* c) { return c ? c->nq : -1; }
+
+dg_status dg_volume_points(dg_context* c, double* xyz, void* stream) {
+  if (!c || !xyz) return fail(DG_ERR_ARG, "null argument");
+  HIPCHK(dgk::launch_points(c->cfg, xyz, c->tb, c->mesh, (hipStream_t)stream));
+  return DG_OK;
+}
+
+dg_status dg_project(dg_context* c, const double* f, double* w, void* stream) {
+  if (!c || !f || !w) return fail(DG_ERR_ARG, "null argument");
+  HIPCHK(dgk::launch_project(c->cfg, f, w, c->tb, c->mesh, (hipStream_t)stream));
+  return DG_OK;
+}
+
+dg_status dg_residual(dg_context* c, const double* w, double* r, void* stream) {
+  if (!c || !w || !r) return fail(DG_ERR_ARG, "null argument");
+  if (w == r) return fail(DG_ERR_ARG, "w and r may not alias");
+  return eval_residual(c, false, w, nullptr, 0.0, r, (hipStream_t)stream);
+}
+
+dg_status dg_jvp(dg_context* c, const double* w, const double* r_w, const double* v, double shift, int mode,
+                 double* out, void* stream) {
+  if (!c || !w || !v || !out) return fail(DG_ERR_ARG, "null argument");
+  if (out == w || out == v || (r_w && out == r_w)) return fail(DG_ERR_ARG, "out may not alias w, v or r_w");
+  if (mode != DG_JVP_EXACT && mode != DG_JVP_FD) return fail(DG_ERR_ARG, "unknown jvp mode");
+  return jvp_impl(c, w, r_w, v, shift, mode, out, (hipStream_t)stream);
+}
+
+dg_status dg_block_precond_setup(dg_context* c, const double* w, double shift, int storage, void* stream) {
+  if (!c || !w) return fail(DG_ERR_ARG, "null argument");
+  if (storage != DG_FP64 && storage != DG_FP32) return fail(DG_ERR_ARG, "storage must be DG_FP64 or DG_FP32");
+  hipStream_t s = (hipStream_t)stream;
+  const int m = c->nv * c->nb;
+  if (m > 256) return fail(DG_ERR_ARG, "block size above 256");
+  dg_status st;
+  if ((st = dalloc(&c->d_D64, (size_t)c->ne * m * m)) != DG_OK) return st;
+  if (storage == DG_FP32) {
+    if (c->d_Dinv == c->d_D64) c->d_Dinv = nullptr;
+    if (c->blk_storage != DG_FP32 && c->d_Dinv) {
+      dfree(c->d_Dinv);
+      c->d_Dinv = nullptr;
+    }
+    float* f = static_cast<float*>(c->d_Dinv);
+    if ((st = dalloc(&f, (size_t)c->ne * m * m)) != DG_OK) return st;
+    c->d_Dinv = f;
+  } else {
+    if (c->d_Dinv && c->d_Dinv != c->d_D64) dfree(c->d_Dinv);
+    c->d_Dinv = c->d_D64;
+  }
+  c->blk_ready = false;
+  {
+    ProfScope ps(c, "block_probe", s);
+    for (int col = 0; col < c->ncolor; ++col)
+      for (int l = 0; l < m; ++l) {
+        HIPCHK(dgk::launch_probe_vector(c->d_t1, c->d_color, col, l, c->nb, c->nv, c->ne, s));
+        if ((st = eval_residual(c, true, w, c->d_t1, shift, c->d_t2, s)) != DG_OK) return st;
+        HIPCHK(dgk::launch_extract_column(c->d_t2, c->d_color, col, l, m, c->ne, shift, c->d_D64, s));
+      }
+  }
+  int zero = 0;
+  HIPCHK(hipMemcpyAsync(c->d_flag, &zero, sizeof(int), hipMemcpyHostToDevice, s));
+  {
+    ProfScope ps(c, "block_invert", s);
+    HIPCHK(dgk::launch_block_invert(storage, c->d_D64, c->d_Dinv, m, c->ne, c->d_flag, s));
+  }
+  int bad = 0;
+  HIPCHK(hipMemcpyAsync(&bad, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (bad) return fail(DG_ERR_SINGULAR_BLOCK, "a diagonal block has a zero or non-finite pivot");
+  c->blk_storage = storage;
+  c->blk_ready = true;
+  return DG_OK;
+}
+
+dg_status dg_block_precond_apply(dg_context* c, const double* r, double* z, void* stream) {
+  if (!c || !r || !z) return fail(DG_ERR_ARG, "null argument");
+  if (r == z) return fail(DG_ERR_ARG, "r and z may not alias");
+  if (!c->blk_ready) return fail(DG_ERR_STATE, "dg_block_precond_setup has not succeeded");
+  hipStream_t s = (hipStream_t)stream;
+  ProfScope ps(c, "block_apply", s);
+  HIPCHK(dgk::launch_block_apply(c->blk_storage, c->d_Dinv, c->nv * c->nb, c->ne, r, z, s));
+  return DG_OK;
+}
+
+dg_status dg_max_wave_speed(dg_context* c, const double* w, double* out, void* stream) {
+  if (!c || !w || !out) return fail(DG_ERR_ARG, "null argument");
+  hipStream_t s = (hipStream_t)stream;
+  const int nblk = 1024;
+  HIPCHK(dgk::launch_wave_speed(c->cfg, w, c->d_red, nblk, c->tb, c->mesh, c->ph, s));
+  HIPCHK(dgk::launch_max_partials(c->d_red, nblk, c->d_scal + 200, s));
+  HIPCHK(hipMemcpyAsync(c->h_pin, c->d_scal + 200, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  *out = c->h_pin[0];
+  return DG_OK;
+}
+
+dg_status dg_fgmres_solve(dg_context* c, const double* w, double shift, const double* b, double* x,
+                          const dg_solve_opts* opts, dg_solve_stats* stats, void* stream) {
+  if (!c || !w || !b || !x || !opts) return fail(DG_ERR_ARG, "null argument");
+  if (x == b || x == w) return fail(DG_ERR_ARG, "x may not alias w or b");
+  const int m = opts->restart > 0 ? opts->restart : 30;
+  if (m > 60) return fail(DG_ERR_ARG, "restart above 60");
+  if (opts->precond != DG_PREC_NONE && opts->precond != DG_PREC_BJ) return fail(DG_ERR_ARG, "unknown precond");
+  if (opts->precond == DG_PREC_BJ && !c->blk_ready) return fail(DG_ERR_STATE, "block preconditioner not set up");
+  if (opts->jvp_mode != DG_JVP_EXACT && opts->jvp_mode != DG_JVP_FD) return fail(DG_ERR_ARG, "unknown jvp mode");
+  const double rtol = opts->rtol > 0.0 ? opts->rtol : 1e-8;
+  const int max_iter = opts->max_iter > 0 ? opts->max_iter : 1000;
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t n = c->ndof;
+  dg_status st;
+  auto t0 = std::chrono::steady_clock::now();
+  if (c->kry_m < m) {
+    dfree(c->d_V);
+    dfree(c->d_Z);
+    c->d_V = c->d_Z = nullptr;
+    c->kry_m = 0;
+    if ((st = dalloc(&c->d_V, (size_t)(m + 1) * n)) != DG_OK) return st;
+    if ((st = dalloc(&c->d_Z, (size_t)m * n)) != DG_OK) return st;
+    c->kry_m = m;
+  }
+  const double* rw = nullptr;
+  if (opts->jvp_mode == DG_JVP_FD) {
+    if ((st = dalloc(&c->d_rw, (size_t)n)) != DG_OK) return st;
+    if ((st = eval_residual(c, false, w, nullptr, 0.0, c->d_rw, s)) != DG_OK) return st;
+    rw = c->d_rw;
+  }
+  auto applyG = [&](const double* z, double* outv) { return jvp_impl(c, w, rw, z, shift, opts->jvp_mode, outv, s); };
+  auto applyM = [&](const double* v, double* z) -> dg_status {
+    if (opts->precond == DG_PREC_BJ) {
+      ProfScope ps(c, "block_apply", s);
+      HIPCHK(dgk::launch_block_apply(c->blk_storage, c->d_Dinv, c->nv * c->nb, c->ne, v, z, s));
+      return DG_OK;
+    }
+    HIPCHK(dgk::launch_axpby(n, 1.0, v, 0.0, v, z, s));
+    return DG_OK;
+  };
+  auto readback = [&](const double* dptr, int cnt) -> dg_status {
+    HIPCHK(hipMemcpyAsync(c->h_pin, dptr, cnt * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return DG_OK;
+  };
+  // device scalars: [0] |b|, [1] beta, [2] |w0|, [3] h_{j+1,j}; [16..] h pass 1; [80..] h pass 2; [144..] y
+  double* dS = c->d_scal;
+  if ((st = norm2(c, b, dS + 0, s)) != DG_OK) return st;
+  if ((st = readback(dS + 0, 1)) != DG_OK) return st;
+  const double bnorm = c->h_pin[0];
+  dg_solve_stats S{};
+  if (!std::isfinite(bnorm)) return fail(DG_ERR_NONFINITE, "right-hand side is not finite");
+  if (bnorm == 0.0) {
+    HIPCHK(dgk::launch_fill(x, n, 0.0, s));
+    S.converged = 1;
+    if (stats) *stats = S;
+    return DG_OK;
+  }
+  double* V = c->d_V;
+  double* Z = c->d_Z;
+  // r0 = b - G x
+  if ((st = applyG(x, c->d_t1)) != DG_OK) return st;
+  HIPCHK(dgk::launch_axpby(n, 1.0, b, -1.0, c->d_t1, V, s));
+  if ((st = norm2(c, V, dS + 1, s)) != DG_OK) return st;
+  if ((st = readback(dS + 1, 1)) != DG_OK) return st;
+  double beta = c->h_pin[0];
+  const double d0 = beta;
+  int iters = 0;
+  double est = beta;
+  bool converged = false;
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  while (true) {
+    if (!std::isfinite(beta)) return fail(DG_ERR_NONFINITE, "residual is not finite");
+    if (beta <= rtol * bnorm) {
+      converged = true;
+      break;
+    }
+    if (iters >= max_iter) break;
+    HIPCHK(dgk::launch_scale_dev(n, V, dS + 1, V, s));
+    std::fill(H.begin(), H.end(), 0.0);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int k = 0;
+    for (int j = 0; j < m; ++j) {
+      double* Vj = V + (size_t)j * n;
+      double* Zj = Z + (size_t)j * n;
+      double* Wn = V + (size_t)(j + 1) * n;
+      if ((st = applyM(Vj, Zj)) != DG_OK) return st;
+      if ((st = applyG(Zj, Wn)) != DG_OK) return st;
+      if ((st = norm2(c, Wn, dS + 2, s)) != DG_OK) return st;
+      {
+        ProfScope ps(c, "arnoldi", s);
+        HIPCHK(dgk::launch_mdot(V, j + 1, n, Wn, c->d_red, s));
+        HIPCHK(dgk::launch_msum(c->d_red, j + 1, dS + 16, s));
+        HIPCHK(dgk::launch_mupdate(V, j + 1, n, dS + 16, Wn, s));
+        HIPCHK(dgk::launch_mdot(V, j + 1, n, Wn, c->d_red, s));
+        HIPCHK(dgk::launch_msum(c->d_red, j + 1, dS + 80, s));
+        HIPCHK(dgk::launch_mupdate(V, j + 1, n, dS + 80, Wn, s));
+      }
+      if ((st = norm2(c, Wn, dS + 3, s)) != DG_OK) return st;
+      if ((st = readback(dS, 144)) != DG_OK) return st;
+      const double* hp = c->h_pin;
+      const double w0 = hp[2], hn = hp[3];
+      if (!std::isfinite(hn)) return fail(DG_ERR_NONFINITE, "Arnoldi vector is not finite");
+      double* Hc = &H[(size_t)j * (m + 1)];  // column j, rows 0..j+1
+      for (int i = 0; i <= j; ++i) Hc[i] = hp[16 + i] + hp[80 + i];
+      Hc[j + 1] = hn;
+      for (int i = 0; i < j; ++i) {
+        const double t = cs[i] * Hc[i] + sn[i] * Hc[i + 1];
+        Hc[i + 1] = -sn[i] * Hc[i] + cs[i] * Hc[i + 1];
+        Hc[i] = t;
+      }
+      const double den = std::hypot(Hc[j], Hc[j + 1]);
+      cs[j] = den > 0.0 ? Hc[j] / den : 1.0;
+      sn[j] = den > 0.0 ? Hc[j + 1] / den : 0.0;
+      Hc[j] = den;
+      Hc[j + 1] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      k = j + 1;
+      ++iters;
+      est = std::fabs(g[j + 1]);
+      const bool brk = hn <= 1e-14 * w0;
+      if (est <= rtol * bnorm || brk || iters >= max_iter) break;
+      HIPCHK(dgk::launch_scale_dev(n, Wn, dS + 3, Wn, s));
+    }
+    // y = H_k^{-1} g (upper triangular back substitution)
+    for (int i = k - 1; i >= 0; --i) {
+      double a = g[i];
+      for (int l = i + 1; l < k; ++l) a -= H[(size_t)l * (m + 1) + i] * y[l];
+      const double d = H[(size_t)i * (m + 1) + i];
+      y[i] = d != 0.0 ? a / d : 0.0;
+    }
+    for (int i = 0; i < k; ++i) c->h_pin[144 + i] = y[i];
+    HIPCHK(hipMemcpyAsync(dS + 144, c->h_pin + 144, k * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(dgk::launch_mupdate_add(Z, k, n, dS + 144, x, s));
+    if ((st = applyG(x, c->d_t1)) != DG_OK) return st;
+    HIPCHK(dgk::launch_axpby(n, 1.0, b, -1.0, c->d_t1, V, s));
+    if ((st = norm2(c, V, dS + 1, s)) != DG_OK) return st;
+    if ((st = readback(dS + 1, 1)) != DG_OK) return st;
+    beta = c->h_pin[0];
+    ++S.restarts;
+  }
+  S.iters = iters;
+  S.converged = converged ? 1 : 0;
+  S.rel_res_est = est / bnorm;
+  S.rel_res_true = beta / bnorm;
+  S.rho = (iters > 0 && beta > 0.0 && d0 > 0.0) ? std::exp(std::log(beta / d0) / iters) : 0.0;
+  S.ms_solve = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (stats) *stats = S;
+  return converged ? DG_OK : DG_NOT_CONVERGED;
+}
+
+dg_status dg_set_profiling(dg_context* c, int on) {
+  if (!c) return fail(DG_ERR_ARG, "null context");
+  c->prof = on != 0;
+  return DG_OK;
+}
+
+dg_status dg_kernel_time(dg_context* c, const char* name, double* ms, int64_t* launches) {
+  if (!c || !name) return fail(DG_ERR_ARG, "null argument");
+  auto it = c->timers.find(name);
+  double tot = 0.0;
+  int64_t cnt = 0;
+  if (it != c->timers.end()) {
+    for (auto& ab : it->second.ev) {
+      HIPCHK(hipEventSynchronize(ab.second));
+      float t = 0.0f;
+      HIPCHK(hipEventElapsedTime(&t, ab.first, ab.second));
+      tot += t;
+      ++cnt;
+      (void)hipEventDestroy(ab.first);
+      (void)hipEventDestroy(ab.second);
+    }
+    it->second.ev.clear();
+  }
+  if (ms) *ms = tot;
+  if (launches) *launches = cnt;
+  return DG_OK;
+}
+
+dg_status dg_sync(dg_context* c) {
+  (void)c;
+  HIPCHK(hipDeviceSynchronize());
+  HIPCHK(hipGetLastError());
+  return DG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,225 @@
+// Element-wise block Jacobi (EWBJ, Sec. 2.3: LU factorisation of the
+// diagonal blocks of the global operator G = shift*I + J).
+//
+// Setup: the diagonal block D_K = shift*I + dR_K/dU_K is probed column by
+// column with the exact Jacobian-vector product, one colour class of
+// elements at a time (no two elements of a class are face neighbours, so the
+// product restricted to K only sees K's own perturbation).  Each block is then
+// inverted in place by Gauss-Jordan elimination with partial (row) pivoting
+// and stored explicitly (column-major, A[j*m + i] = entry (i, j)), in FP64 or
+// FP32, so the apply is a batched matrix-vector product bound by HBM.
+#include "dg_internal.h"
+
+namespace dgk {
+
+namespace {
+
+__global__ void k_probe(double* __restrict__ P, const int* __restrict__ color, int col, int l, int nb, int nv,
+                        int64_t ne) {
+  const int64_t n = (int64_t)nv * nb * ne;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = i % ne;
+    const int r = (int)(i / ne);
+    P[i] = (r == l && color[e] == col) ? 1.0 : 0.0;
+  }
+}
+
+// D[e][l][r] = Jv[r*ne + e] for every element of colour `col` (Jv already includes shift*P)
+__global__ void k_extract(const double* __restrict__ Jv, const int* __restrict__ color, int col, int l, int m,
+                          int64_t ne, double* __restrict__ D) {
+  const int64_t n = (int64_t)m * ne;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = i % ne;
+    const int r = (int)(i / ne);
+    if (color[e] == col) D[((size_t)e * m + l) * m + r] = Jv[i];
+  }
+}
+
+// In-place Gauss-Jordan inversion with row pivoting of one m x m column-major
+// block per workgroup.  S is the arithmetic/storage type of the working copy
+// A (LDS when it fits, else the block's own global storage).
+template <class S>
+__device__ void gauss_jordan(S* A, int m, S* colk, S* rowk, int* ipiv, double* rv, int* ri, int* bad) {
+  const int tid = threadIdx.x;
+  for (int k = 0; k < m; ++k) {
+    // pivot: max |A[i][k]|, i >= k; ties keep the smallest row index
+    double best = -1.0;
+    int bi = k;
+    for (int i = k + tid; i < m; i += 256) {
+      const double a = fabs((double)A[(size_t)k * m + i]);
+      if (a > best || (a != a)) {
+        best = (a != a) ? 1e308 : a;
+        bi = i;
+      }
+    }
+    rv[tid] = best;
+    ri[tid] = bi;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if (tid < s) {
+        const double o = rv[tid + s];
+        const int oi = ri[tid + s];
+        if (o > rv[tid] || (o == rv[tid] && oi < ri[tid])) {
+          rv[tid] = o;
+          ri[tid] = oi;
+        }
+      }
+      __syncthreads();
+    }
+    const int piv = ri[0];
+    if (tid == 0) ipiv[k] = piv;
+    // swap rows k and piv
+    if (piv != k)
+      for (int j = tid; j < m; j += 256) {
+        const S t = A[(size_t)j * m + k];
+        A[(size_t)j * m + k] = A[(size_t)j * m + piv];
+        A[(size_t)j * m + piv] = t;
+      }
+    __syncthreads();
+    const S pv = A[(size_t)k * m + k];
+    if (tid == 0 && !(pv != (S)0 && (double)pv - (double)pv == 0.0)) *bad = 1;
+    const S pinv = (pv != (S)0) ? (S)1 / pv : (S)0;
+    // scaled pivot row (entry k becomes pinv) and the old column k
+    for (int j = tid; j < m; j += 256) rowk[j] = (j == k) ? pinv : A[(size_t)j * m + k] * pinv;
+    for (int i = tid; i < m; i += 256) colk[i] = A[(size_t)k * m + i];
+    __syncthreads();
+    for (size_t idx = tid; idx < (size_t)m * m; idx += 256) {
+      const int i = (int)(idx % m), j = (int)(idx / m);
+      if (i == k) {
+        A[idx] = rowk[j];
+      } else {
+        const S base = (j == k) ? (S)0 : A[idx];
+        A[idx] = base - colk[i] * rowk[j];
+      }
+    }
+    __syncthreads();
+  }
+  // undo the row interchanges as column interchanges, last first
+  for (int k = m - 1; k >= 0; --k) {
+    const int p = ipiv[k];
+    if (p != k)
+      for (int i = tid; i < m; i += 256) {
+        const S t = A[(size_t)k * m + i];
+        A[(size_t)k * m + i] = A[(size_t)p * m + i];
+        A[(size_t)p * m + i] = t;
+      }
+    __syncthreads();
+  }
+}
+
+// FP64 working copy in global memory (in place).
+__global__ __launch_bounds__(256) void k_invert_global64(double* __restrict__ D, int m, int* __restrict__ info) {
+  __shared__ double colk[256], rowk[256], rv[256];
+  __shared__ int ipiv[256], ri[256], bad;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  double* A = D + (size_t)blockIdx.x * m * m;
+  gauss_jordan<double>(A, m, colk, rowk, ipiv, rv, ri, &bad);
+  if (threadIdx.x == 0 && bad) info[0] = 1;
+}
+
+// LDS working copy of type S; result written to `out` (type S) or, for
+// FP64 in place, back into D.
+template <class S>
+__global__ __launch_bounds__(256) void k_invert_lds(const double* __restrict__ D, S* __restrict__ out, int m,
+                                                    int* __restrict__ info) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  S* A = reinterpret_cast<S*>(smem);
+  __shared__ S colk[256], rowk[256];
+  __shared__ double rv[256];
+  __shared__ int ipiv[256], ri[256], bad;
+  if (threadIdx.x == 0) bad = 0;
+  const double* Dg = D + (size_t)blockIdx.x * m * m;
+  for (size_t i = threadIdx.x; i < (size_t)m * m; i += 256) A[i] = (S)Dg[i];
+  __syncthreads();
+  gauss_jordan<S>(A, m, colk, rowk, ipiv, rv, ri, &bad);
+  S* O = out + (size_t)blockIdx.x * m * m;
+  for (size_t i = threadIdx.x; i < (size_t)m * m; i += 256) O[i] = A[i];
+  if (threadIdx.x == 0 && bad) info[0] = 1;
+}
+
+// z_K = Dinv_K r_K; 64 lanes over rows, 4 waves over column quarters.
+template <class S>
+__global__ __launch_bounds__(256) void k_apply(const S* __restrict__ Dinv, int m, int64_t ne,
+                                               const double* __restrict__ r, double* __restrict__ z) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* rk = reinterpret_cast<double*>(smem);   // [m]
+  double* part = rk + m;                          // [4][m]
+  const int64_t e = blockIdx.x;
+  for (int j = threadIdx.x; j < m; j += 256) rk[j] = r[(size_t)j * ne + e];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const S* A = Dinv + (size_t)e * m * m;
+  for (int i0 = 0; i0 < m; i0 += 64) {
+    const int i = i0 + lane;
+    double a = 0.0;
+    if (i < m)
+      for (int j = w; j < m; j += 4) a += (double)A[(size_t)j * m + i] * rk[j];
+    if (i < m) part[w * m + i] = a;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < m; i += 256)
+    z[(size_t)i * ne + e] = (part[i] + part[m + i]) + (part[2 * m + i] + part[3 * m + i]);
+}
+
+unsigned grid_for(int64_t n) {
+  int64_t g = (n + 255) / 256;
+  if (g > 8192) g = 8192;
+  if (g < 1) g = 1;
+  return (unsigned)g;
+}
+
+}  // namespace
+
+hipError_t launch_probe_vector(double* P, const int* color, int col, int l, int nb, int nv, int64_t ne,
+                               hipStream_t s) {
+  k_probe<<<grid_for((int64_t)nv * nb * ne), 256, 0, s>>>(P, color, col, l, nb, nv, ne);
+  return hipGetLastError();
+}
+
+hipError_t launch_extract_column(const double* Jv, const int* color, int col, int l, int m, int64_t ne,
+                                 double /*shift*/, double* D, hipStream_t s) {
+  k_extract<<<grid_for((int64_t)m * ne), 256, 0, s>>>(Jv, color, col, l, m, ne, D);
+  return hipGetLastError();
+}
+
+static constexpr size_t kMaxLds = 160 * 1024;
+
+hipError_t launch_block_invert(int storage, double* D64, void* Dout, int m, int64_t ne, int* info, hipStream_t s) {
+  if (m > 256) return hipErrorInvalidValue;
+  // static LDS of the kernels: pivot row/column, reduction scratch
+  const size_t static_lds = 2 * 256 * sizeof(double) + 256 * sizeof(double) + 2 * 256 * sizeof(int) + 64;
+  if (storage == DG_FP64) {
+    const size_t need = (size_t)m * m * sizeof(double);
+    if (need + static_lds <= kMaxLds) {
+      hipFuncSetAttribute((const void*)k_invert_lds<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)need);
+      k_invert_lds<double><<<(unsigned)ne, 256, need, s>>>(D64, static_cast<double*>(Dout), m, info);
+    } else {
+      if (Dout != D64) return hipErrorInvalidValue;
+      k_invert_global64<<<(unsigned)ne, 256, 0, s>>>(D64, m, info);
+    }
+    return hipGetLastError();
+  }
+  if (storage == DG_FP32) {
+    const size_t need = (size_t)m * m * sizeof(float);
+    if (need + static_lds > kMaxLds) return hipErrorInvalidValue;
+    hipFuncSetAttribute((const void*)k_invert_lds<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)need);
+    k_invert_lds<float><<<(unsigned)ne, 256, need, s>>>(D64, static_cast<float*>(Dout), m, info);
+    return hipGetLastError();
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_block_apply(int storage, const void* Dinv, int m, int64_t ne, const double* r, double* z,
+                              hipStream_t s) {
+  const size_t lds = (size_t)5 * m * sizeof(double);
+  if (storage == DG_FP64)
+    k_apply<double><<<(unsigned)ne, 256, lds, s>>>(static_cast<const double*>(Dinv), m, ne, r, z);
+  else if (storage == DG_FP32)
+    k_apply<float><<<(unsigned)ne, 256, lds, s>>>(static_cast<const float*>(Dinv), m, ne, r, z);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+}  // namespace dgk

@@ -1,0 +1,108 @@
+// Internal declarations shared by the HIP kernels and the C ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "dg.h"
+
+namespace dgk {
+
+// Device tables of a uniform affine lattice (every element the same box of
+// edge lengths h).  The physical orthonormal basis is phi = psi / sqrt|J|
+// with psi the tensor Legendre basis of the reference cube.  All tables are
+// FP64, row-major in the index order written next to them.
+struct Tables {
+  const double* vPhi;    // [NQ][NB]                 phi_b at volume points
+  const double* vWD;     // [DIM][NQ][NB]            w_q|J| d phi_b / d x_j
+  const double* vWPhi;   // [NQ][NB]                 w_q|J| phi_b (projection)
+  const double* vLift;   // [DIM][3][NB][NB]         modal corrected gradient, see below
+  const double* fPhi;    // [DIM][2][NFQ][NB]        traces; side 0: xi_p=-1, 1: xi_p=+1
+  const double* fDphi;   // [DIM][2][DIM][NFQ][NB]   trace of d phi_b / d x_j
+  const double* fLift;   // [DIM][2][NFQ][NB]        averaged local lifting at face points
+  const double* fWPhi;   // [DIM][2][NFQ][NB]        w_f|J_f| phi_b (face projection)
+  const double* vXi;     // [NQ][DIM]                reference volume points
+};
+// vLift[p][0] (self), [p][1] (+p neighbour), [p][2] (-p neighbour) give the
+// modal coefficients of G_p = d U/dx_p + R^K_p (R^K the elemental lifting):
+//   Ghat_p = vLift[p][0] U_e + vLift[p][1] U_{e+p} + vLift[p][2] U_{e-p}.
+// fLift[p][0] / [p][1] map the owner / neighbour modes to {r^sigma} at the
+// face points (normal component; the lattice normal is +e_p).
+
+struct Phys {
+  double gamma, prandtl, mu, eta, efix;
+  int flux;  // DG_FLUX_LF / DG_FLUX_ROE
+};
+
+struct Mesh {
+  int64_t ne;
+  const int64_t* nbr;  // [2*DIM][ne]
+  const double* x0;    // [DIM][ne] low corner of every element
+  double h[3];
+};
+
+// Kernel configuration id -> (dim, nb, nq1d).  Returns -1 if not compiled.
+int config_index(int dim, int nb, int nq1d);
+
+// Launchers (asynchronous on `stream`).
+hipError_t launch_face(int cfg, bool jvp, const double* U, const double* V, double* H, const Tables& tb,
+                       const Mesh& m, const Phys& ph, hipStream_t stream);
+hipError_t launch_volume(int cfg, bool jvp, const double* U, const double* V, const double* H, double* out,
+                         double shift, const Tables& tb, const Mesh& m, const Phys& ph, hipStream_t stream);
+hipError_t launch_project(int cfg, const double* f, double* w, const Tables& tb, const Mesh& m, hipStream_t s);
+hipError_t launch_points(int cfg, double* xyz, const Tables& tb, const Mesh& m, hipStream_t s);
+hipError_t launch_wave_speed(int cfg, const double* w, double* partial, int nblocks, const Tables& tb,
+                             const Mesh& m, const Phys& ph, hipStream_t s);
+
+// Vector kernels (FP64, deterministic reductions: fixed block partials + one-block final sum).
+constexpr int kRedBlocks = 1024;
+hipError_t launch_dot_partials(const double* x, const double* y, int64_t n, double* partial, hipStream_t s);
+hipError_t launch_sum_partials(const double* partial, int np, double* out, int sqrt_flag, hipStream_t s);
+hipError_t launch_axpby(int64_t n, double a, const double* x, double b, const double* y, double* z, hipStream_t s);
+// z = a*x + s*y where s = *dscale (device scalar) times c
+hipError_t launch_axpy_dev(int64_t n, const double* x, const double* dscale, double c, const double* y, double* z,
+                           hipStream_t s);
+hipError_t launch_fd_combine(int64_t n, const double* rp, const double* r0, const double* dinv, const double* v,
+                             double shift, double* out, hipStream_t s);
+hipError_t launch_scale_dev(int64_t n, const double* x, const double* dnorm, double* y, hipStream_t s);
+// Multi-dot h[j] = V_j . w for j < k (V row-major [k][n]); partial buffer [k][kRedBlocks]
+hipError_t launch_mdot(const double* V, int k, int64_t n, const double* w, double* partial, hipStream_t s);
+hipError_t launch_msum(const double* partial, int k, double* h, hipStream_t s);
+// w -= sum_j h[j] V_j
+hipError_t launch_mupdate(const double* V, int k, int64_t n, const double* h, double* w, hipStream_t s);
+// x += sum_j y[j] Z_j
+hipError_t launch_mupdate_add(const double* Z, int k, int64_t n, const double* y, double* x, hipStream_t s);
+hipError_t launch_fill(double* x, int64_t n, double v, hipStream_t s);
+hipError_t launch_fd_delta(double* d, double eps, hipStream_t s);
+hipError_t launch_max_partials(const double* partial, int np, double* out, hipStream_t s);
+hipError_t launch_nonfinite_check(const double* x, int64_t n, int* flag, hipStream_t s);
+
+// Block-Jacobi kernels.
+hipError_t launch_probe_vector(double* P, const int* color, int col, int l, int nb, int nv, int64_t ne,
+                               hipStream_t s);
+hipError_t launch_extract_column(const double* Jv, const int* color, int col, int l, int m, int64_t ne,
+                                 double shift, double* D, hipStream_t s);
+hipError_t launch_block_invert(int storage, double* D64, void* Dout, int m, int64_t ne, int* info, hipStream_t s);
+hipError_t launch_block_apply(int storage, const void* Dinv, int m, int64_t ne, const double* r, double* z,
+                              hipStream_t s);
+
+}  // namespace dgk
+
+namespace dgh {
+
+// Host-side table construction (C++, FP64).
+struct HostTables {
+  int dim = 0, nb = 0, nq1 = 0, nq = 0, nfq = 0;
+  std::vector<double> vPhi, vWD, vWPhi, vLift, fPhi, fDphi, fLift, fWPhi, vXi;
+  std::vector<int> alpha;  // [nb][dim]
+};
+
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
+void legendre_orthonormal(int kmax, double x, double* L, double* dL);
+std::vector<int> multi_indices(int k, int dim, int basis);
+HostTables build_tables(int dim, int order, int basis, int nq1d, const double h[3]);
+
+}  // namespace dgh

@@ -1,0 +1,575 @@
+// DG residual and Jacobian-vector product kernels for gfx950 (FP64).
+//
+// Residual of eq. (NSdiscrRes) (Sec. 2.2):
+//   R_Kbc = - sum_q w_q|J| sum_j F_jc(U_q, G_q) d_j phi_b(x_q)
+//           + sum_{faces} (+/-) sum_f w_f|J_f| Hn_c(x_f) phi_b(x_f)
+// with F = F^c - F^v, the BR2 corrected gradient G = grad U + R^K in the
+// volume and the face flux
+//   Hn = H^c(U_L, U_R, n) - F^v({U}, {grad U} + eta {r}) . n
+// (Sec. 2.1, eq. vflux, with the lifting sign of the consistent gradient).
+//
+// Two kernels per evaluation:
+//   face   : one lane per (face, face point); traces of both sides, averaged
+//            local lifting, numerical flux -> Hn at the face points
+//            (layout [p][c][fq][e], e = owner element of the +p face).
+//   volume : a tile of TE elements per workgroup; modal corrected gradients
+//            (derivative + elemental lifting, exact on affine elements),
+//            pointwise volume flux, weighted-transpose projection, plus the
+//            2*dim face contributions gathered from Hn (no atomics).
+// The Jacobian-vector product runs the same kernels on dual numbers
+// (value, tangent): forward-mode differentiation of the residual, i.e. the
+// Jacobian forms j_h of Sec. 2.2 applied to v.  Branches (|.|, max, entropy
+// fix) follow the value part; ties take the first operand.
+#include <type_traits>
+
+#include "dg_internal.h"
+
+namespace dgk {
+
+#define DEV __device__ __forceinline__
+
+// ------------------------------------------------------------------ dual numbers
+struct dual {
+  double v, d;
+  DEV dual() = default;
+  DEV dual(double x) : v(x), d(0.0) {}
+  DEV dual(double x, double y) : v(x), d(y) {}
+};
+DEV dual operator+(dual a, dual b) { return dual(a.v + b.v, a.d + b.d); }
+DEV dual operator-(dual a, dual b) { return dual(a.v - b.v, a.d - b.d); }
+DEV dual operator*(dual a, dual b) { return dual(a.v * b.v, a.d * b.v + a.v * b.d); }
+DEV dual operator/(dual a, dual b) {
+  double q = a.v / b.v;
+  return dual(q, (a.d - q * b.d) / b.v);
+}
+DEV dual operator-(dual a) { return dual(-a.v, -a.d); }
+DEV dual operator*(double s, dual a) { return dual(s * a.v, s * a.d); }
+DEV dual operator*(dual a, double s) { return dual(s * a.v, s * a.d); }
+DEV dual operator+(dual a, double s) { return dual(a.v + s, a.d); }
+DEV dual operator+(double s, dual a) { return dual(a.v + s, a.d); }
+DEV dual operator-(dual a, double s) { return dual(a.v - s, a.d); }
+DEV dual operator-(double s, dual a) { return dual(s - a.v, -a.d); }
+DEV dual operator/(dual a, double s) { return dual(a.v / s, a.d / s); }
+DEV dual operator/(double s, dual a) {
+  double q = s / a.v;
+  return dual(q, -q * a.d / a.v);
+}
+DEV dual& operator+=(dual& a, dual b) { a = a + b; return a; }
+DEV dual& operator-=(dual& a, dual b) { a = a - b; return a; }
+DEV dual dsqrt(dual a) {
+  double r = sqrt(a.v);
+  return dual(r, 0.5 * a.d / r);
+}
+DEV double dsqrt(double a) { return sqrt(a); }
+DEV double val(double a) { return a; }
+DEV double val(dual a) { return a.v; }
+DEV double out_part(double a) { return a; }
+DEV double out_part(dual a) { return a.d; }
+template <class T> DEV T rabs(T a) { return val(a) >= 0.0 ? a : -a; }
+template <class T> DEV T rmax(T a, T b) { return val(a) >= val(b) ? a : b; }
+
+template <bool JVP> struct Scalar { using type = double; };
+template <> struct Scalar<true> { using type = dual; };
+
+template <bool JVP> DEV typename Scalar<JVP>::type load2(const double* __restrict__ U, const double* __restrict__ V,
+                                                         size_t i);
+template <> DEV double load2<false>(const double* __restrict__ U, const double* __restrict__, size_t i) { return U[i]; }
+template <> DEV dual load2<true>(const double* __restrict__ U, const double* __restrict__ V, size_t i) {
+  return dual(U[i], V[i]);
+}
+
+constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
+
+// ------------------------------------------------------------------ physics
+// Conserved variables U = (rho, rho*u_1..d, rho*E); perfect gas.
+template <class T, int DIM>
+DEV void primitives(const T* U, double g, T& rinv, T* u, T& p) {
+  rinv = 1.0 / U[0];
+  T ke = 0.0;
+  for (int j = 0; j < DIM; ++j) {
+    u[j] = U[1 + j] * rinv;
+    ke += U[1 + j] * u[j];
+  }
+  p = (g - 1.0) * (U[DIM + 1] - 0.5 * ke);
+}
+
+// Convective flux in direction P: (rho u_P, rho u_P u + p e_P, u_P (rho E + p)).
+template <class T, int DIM>
+DEV void conv_flux_dir(const T* U, const T* u, const T& p, int P, T* F) {
+  F[0] = U[1 + P];
+  for (int j = 0; j < DIM; ++j) F[1 + j] = U[1 + P] * u[j];
+  F[1 + P] += p;
+  F[DIM + 1] = u[P] * (U[DIM + 1] + p);
+}
+
+// Numerical convective flux across a face of unit normal +e_P, L -> R.
+template <class T, int DIM>
+DEV void num_flux(const T* UL, const T* UR, int P, const Phys& ph, T* H) {
+  constexpr int NV = DIM + 2;
+  const double g = ph.gamma;
+  T rinvL, uL[DIM], pL, rinvR, uR[DIM], pR;
+  primitives<T, DIM>(UL, g, rinvL, uL, pL);
+  primitives<T, DIM>(UR, g, rinvR, uR, pR);
+  T FL[NV], FR[NV];
+  conv_flux_dir<T, DIM>(UL, uL, pL, P, FL);
+  conv_flux_dir<T, DIM>(UR, uR, pR, P, FR);
+  for (int c = 0; c < NV; ++c) H[c] = 0.5 * (FL[c] + FR[c]);
+  if (ph.flux == DG_FLUX_LF) {
+    // Lax-Friedrichs with the larger of the two normal wave speeds.
+    T cL = dsqrt(g * pL * rinvL), cR = dsqrt(g * pR * rinvR);
+    T lam = rmax(rabs(uL[P]) + cL, rabs(uR[P]) + cR);
+    for (int c = 0; c < NV; ++c) H[c] -= 0.5 * lam * (UR[c] - UL[c]);
+    return;
+  }
+  // Roe: |A~|(U_R - U_L) as a sum of waves, Harten entropy fix on every wave.
+  T sL = dsqrt(UL[0]), sR = dsqrt(UR[0]);
+  T HL = (UL[DIM + 1] + pL) * rinvL, HR = (UR[DIM + 1] + pR) * rinvR;
+  T iw = 1.0 / (sL + sR);
+  T ut[DIM], q2 = 0.0;
+  for (int j = 0; j < DIM; ++j) {
+    ut[j] = (sL * uL[j] + sR * uR[j]) * iw;
+    q2 += ut[j] * ut[j];
+  }
+  T Ht = (sL * HL + sR * HR) * iw;
+  T ct2 = (g - 1.0) * (Ht - 0.5 * q2);
+  T ct = dsqrt(ct2);
+  T ict2 = 1.0 / ct2;
+  T unt = ut[P];
+  T rhot = sL * sR;
+  T dr = UR[0] - UL[0];
+  T dp = pR - pL;
+  T du[DIM];
+  for (int j = 0; j < DIM; ++j) du[j] = uR[j] - uL[j];
+  T dun = du[P];
+  T a1 = (dp - rhot * ct * dun) * (0.5 * ict2);
+  T a5 = (dp + rhot * ct * dun) * (0.5 * ict2);
+  T a2 = dr - dp * ict2;
+  T delta = ph.efix * (rabs(unt) + ct);
+  auto fix = [&](T lam) {
+    T al = rabs(lam);
+    return val(al) < val(delta) ? (lam * lam + delta * delta) / (2.0 * delta) : al;
+  };
+  T l1 = fix(unt - ct), l2 = fix(unt), l5 = fix(unt + ct);
+  T w1 = l1 * a1, w5 = l5 * a5, w2 = l2 * a2;
+  T sh = 0.0;  // u~ . du_t
+  H[0] -= 0.5 * (w1 + w2 + w5);
+  for (int j = 0; j < DIM; ++j) {
+    T dut = (j == P) ? T(0.0) : du[j];
+    sh += ut[j] * dut;
+    T dj = w1 * ut[j] + w2 * ut[j] + l2 * rhot * dut + w5 * ut[j];
+    if (j == P) dj += (w5 - w1) * ct;
+    H[1 + j] -= 0.5 * dj;
+  }
+  T de = w1 * (Ht - ct * unt) + w2 * (0.5 * q2) + l2 * rhot * sh + w5 * (Ht + ct * unt);
+  H[DIM + 1] -= 0.5 * de;
+}
+
+// Velocity and p/rho gradients from the corrected conservative gradient G[c][j].
+template <class T, int DIM>
+struct ViscPrep {
+  T u[DIM];
+  T gu[DIM][DIM];  // d u_i / d x_j
+  T gpr[DIM];      // d (p/rho) / d x_j
+  T div;
+};
+
+template <class T, int DIM>
+DEV void visc_prep(const T* U, const T (*G)[DIM], double g, ViscPrep<T, DIM>& vp) {
+  T rinv = 1.0 / U[0];
+  for (int i = 0; i < DIM; ++i) vp.u[i] = U[1 + i] * rinv;
+  T e = U[DIM + 1] * rinv;
+  vp.div = 0.0;
+  for (int j = 0; j < DIM; ++j) {
+    T s = 0.0;
+    for (int i = 0; i < DIM; ++i) {
+      vp.gu[i][j] = (G[1 + i][j] - vp.u[i] * G[0][j]) * rinv;
+      s += vp.u[i] * vp.gu[i][j];
+    }
+    T ge = (G[DIM + 1][j] - e * G[0][j]) * rinv;
+    vp.gpr[j] = (g - 1.0) * (ge - s);
+  }
+  for (int i = 0; i < DIM; ++i) vp.div += vp.gu[i][i];
+}
+
+// Viscous flux in direction P: (0, tau_P., sum_j tau_Pj u_j + kappa d_P(p/rho)),
+// tau = mu (grad u + grad u^T - 2/3 div u I), kappa = mu gamma / (Pr (gamma-1)).
+template <class T, int DIM>
+DEV void visc_flux_dir(const ViscPrep<T, DIM>& vp, int P, double mu, double kap, T* Fv) {
+  Fv[0] = 0.0;
+  T work = 0.0;
+  for (int j = 0; j < DIM; ++j) {
+    T tau = mu * (vp.gu[j][P] + vp.gu[P][j]);
+    if (j == P) tau -= (2.0 / 3.0) * mu * vp.div;
+    Fv[1 + j] = tau;
+    work += tau * vp.u[j];
+  }
+  Fv[DIM + 1] = work + kap * vp.gpr[P];
+}
+
+// ------------------------------------------------------------------ face kernel
+// Body for one face direction p (a compile-time constant, so every index into
+// the per-lane arrays is static and nothing spills to scratch).
+template <int DIM, int NB, int NQ1, bool JVP, int p>
+DEV void face_body(const double* __restrict__ U, const double* __restrict__ V, double* __restrict__ H,
+                   const Tables& tb, const Mesh& m, const Phys& ph) {
+  using T = typename Scalar<JVP>::type;
+  constexpr int NV = DIM + 2;
+  constexpr int NFQ = ipow(NQ1, DIM - 1);
+  const int lane = threadIdx.x & 63;
+  const int slot = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t ne = m.ne;
+  const int64_t e = (int64_t)blockIdx.x * 64 + lane;
+  if (e >= ne) return;
+  const int64_t er = m.nbr[(2 * p + 1) * ne + e];
+  const double kap = ph.mu * ph.gamma / (ph.prandtl * (ph.gamma - 1.0));
+  for (int fq = slot; fq < NFQ; fq += 4) {
+    T uL[NV], uR[NV], gL[NV][DIM], gR[NV][DIM], rb[NV];
+    for (int c = 0; c < NV; ++c) {
+      uL[c] = 0.0;
+      uR[c] = 0.0;
+      rb[c] = 0.0;
+      for (int j = 0; j < DIM; ++j) {
+        gL[c][j] = 0.0;
+        gR[c][j] = 0.0;
+      }
+    }
+    const double* phP = tb.fPhi + ((size_t)(p * 2 + 1) * NFQ + fq) * NB;
+    const double* phM = tb.fPhi + ((size_t)(p * 2 + 0) * NFQ + fq) * NB;
+    const double* lfL = tb.fLift + ((size_t)(p * 2 + 0) * NFQ + fq) * NB;
+    const double* lfR = tb.fLift + ((size_t)(p * 2 + 1) * NFQ + fq) * NB;
+    for (int c = 0; c < NV; ++c) {
+#pragma unroll 4
+      for (int b = 0; b < NB; ++b) {
+        const size_t i = (size_t)(c * NB + b) * ne;
+        T a = load2<JVP>(U, V, i + e);
+        T r = load2<JVP>(U, V, i + er);
+        uL[c] += phP[b] * a;
+        uR[c] += phM[b] * r;
+        rb[c] += lfL[b] * a + lfR[b] * r;
+        for (int j = 0; j < DIM; ++j) {
+          gL[c][j] += tb.fDphi[((size_t)((p * 2 + 1) * DIM + j) * NFQ + fq) * NB + b] * a;
+          gR[c][j] += tb.fDphi[((size_t)((p * 2 + 0) * DIM + j) * NFQ + fq) * NB + b] * r;
+        }
+      }
+    }
+    T Hn[NV];
+    num_flux<T, DIM>(uL, uR, p, ph, Hn);
+    T ua[NV], Ga[NV][DIM];
+    for (int c = 0; c < NV; ++c) {
+      ua[c] = 0.5 * (uL[c] + uR[c]);
+      for (int j = 0; j < DIM; ++j) Ga[c][j] = 0.5 * (gL[c][j] + gR[c][j]);
+      Ga[c][p] += ph.eta * rb[c];
+    }
+    ViscPrep<T, DIM> vp;
+    visc_prep<T, DIM>(ua, Ga, ph.gamma, vp);
+    T Fv[NV];
+    visc_flux_dir<T, DIM>(vp, p, ph.mu, kap, Fv);
+    for (int c = 0; c < NV; ++c) H[((size_t)(p * NV + c) * NFQ + fq) * ne + e] = out_part(Hn[c] - Fv[c]);
+  }
+}
+
+template <int DIM, int NB, int NQ1, bool JVP>
+__global__ __launch_bounds__(256) void k_face(const double* __restrict__ U, const double* __restrict__ V,
+                                              double* __restrict__ H, Tables tb, Mesh m, Phys ph) {
+  switch (blockIdx.y) {
+    case 0: face_body<DIM, NB, NQ1, JVP, 0>(U, V, H, tb, m, ph); break;
+    case 1: face_body<DIM, NB, NQ1, JVP, 1>(U, V, H, tb, m, ph); break;
+    default:
+      if constexpr (DIM == 3) face_body<DIM, NB, NQ1, JVP, 2>(U, V, H, tb, m, ph);
+      break;
+  }
+}
+
+// ------------------------------------------------------------------ volume kernel
+template <int DIM, int NB, int NQ1, bool JVP, int TE, int QC>
+__global__ __launch_bounds__(256) void k_volume(const double* __restrict__ U, const double* __restrict__ V,
+                                                const double* __restrict__ H, double* __restrict__ out, double shift,
+                                                Tables tb, Mesh m, Phys ph) {
+  using T = typename Scalar<JVP>::type;
+  constexpr int NV = DIM + 2;
+  constexpr int NQ = ipow(NQ1, DIM);
+  constexpr int NFQ = ipow(NQ1, DIM - 1);
+  constexpr int NS = JVP ? 2 : 1;
+  // sX[s][f][c][b][t]: s = value/tangent, f = 0 modal U, f = 1+j modal G_j
+  __shared__ double sX[NS][1 + DIM][NV][NB][TE];
+  __shared__ double sF[DIM][NV][QC][TE];
+  const int tid = threadIdx.x;
+  const int64_t ne = m.ne;
+  const int64_t e0 = (int64_t)blockIdx.x * TE;
+  const double kap = ph.mu * ph.gamma / (ph.prandtl * (ph.gamma - 1.0));
+
+  for (int it = tid; it < NV * NB * TE; it += 256) {
+    const int t = it % TE, cb = it / TE;
+    const int64_t e = e0 + t;
+    double a = 0.0, d = 0.0;
+    if (e < ne) {
+      a = U[(size_t)cb * ne + e];
+      if (JVP) d = V[(size_t)cb * ne + e];
+    }
+    (&sX[0][0][0][0][0])[cb * TE + t] = a;
+    if (JVP) (&sX[NS - 1][0][0][0][0])[cb * TE + t] = d;
+  }
+  __syncthreads();
+  // modal corrected gradient: Ghat_p = L0 U_e + L1 U_{e+p} + L2 U_{e-p}
+  for (int it = tid; it < DIM * NV * NB * TE; it += 256) {
+    int r = it;
+    const int t = r % TE;
+    r /= TE;
+    const int b = r % NB;
+    r /= NB;
+    const int c = r % NV;
+    const int p = r / NV;
+    const int64_t e = e0 + t;
+    double g = 0.0, gd = 0.0;
+    if (e < ne) {
+      const int64_t ep = m.nbr[(2 * p + 1) * ne + e], em = m.nbr[(2 * p) * ne + e];
+      const double* L0 = tb.vLift + (((size_t)p * 3 + 0) * NB + b) * NB;
+      const double* L1 = tb.vLift + (((size_t)p * 3 + 1) * NB + b) * NB;
+      const double* L2 = tb.vLift + (((size_t)p * 3 + 2) * NB + b) * NB;
+      for (int bp = 0; bp < NB; ++bp) {
+        const size_t i = (size_t)(c * NB + bp) * ne;
+        g += L0[bp] * sX[0][0][c][bp][t] + L1[bp] * U[i + ep] + L2[bp] * U[i + em];
+        if (JVP) gd += L0[bp] * sX[NS - 1][0][c][bp][t] + L1[bp] * V[i + ep] + L2[bp] * V[i + em];
+      }
+    }
+    sX[0][1 + p][c][b][t] = g;
+    if (JVP) sX[NS - 1][1 + p][c][b][t] = gd;
+  }
+  __syncthreads();
+
+  constexpr int NIT = NV * NB * TE;
+  constexpr int PER = (NIT + 255) / 256;
+  double acc[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) acc[k] = 0.0;
+
+  for (int q0 = 0; q0 < NQ; q0 += QC) {
+    for (int it = tid; it < QC * TE; it += 256) {
+      const int t = it % TE, ql = it / TE, q = q0 + ql;
+      if (q < NQ) {
+        const double* phq = tb.vPhi + (size_t)q * NB;
+        T u[NV], G[NV][DIM];
+        for (int c = 0; c < NV; ++c) {
+          u[c] = 0.0;
+          for (int j = 0; j < DIM; ++j) G[c][j] = 0.0;
+        }
+        for (int b = 0; b < NB; ++b) {
+          const double w = phq[b];
+          for (int c = 0; c < NV; ++c) {
+            if constexpr (JVP) {
+              u[c] += w * dual(sX[0][0][c][b][t], sX[1][0][c][b][t]);
+              for (int j = 0; j < DIM; ++j) G[c][j] += w * dual(sX[0][1 + j][c][b][t], sX[1][1 + j][c][b][t]);
+            } else {
+              u[c] += w * sX[0][0][c][b][t];
+              for (int j = 0; j < DIM; ++j) G[c][j] += w * sX[0][1 + j][c][b][t];
+            }
+          }
+        }
+        T rinv, vel[DIM], pr;
+        primitives<T, DIM>(u, ph.gamma, rinv, vel, pr);
+        ViscPrep<T, DIM> vp;
+        visc_prep<T, DIM>(u, G, ph.gamma, vp);
+        for (int j = 0; j < DIM; ++j) {
+          T Fc[NV], Fv[NV];
+          conv_flux_dir<T, DIM>(u, vel, pr, j, Fc);
+          visc_flux_dir<T, DIM>(vp, j, ph.mu, kap, Fv);
+          for (int c = 0; c < NV; ++c) sF[j][c][ql][t] = out_part(Fc[c] - Fv[c]);
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int it = tid + k * 256;
+      if (it < NIT) {
+        const int t = it % TE, cb = it / TE, b = cb % NB, c = cb / NB;
+        double a = acc[k];
+        for (int ql = 0; ql < QC; ++ql) {
+          const int q = q0 + ql;
+          if (q < NQ)
+            for (int j = 0; j < DIM; ++j) a -= tb.vWD[((size_t)j * NQ + q) * NB + b] * sF[j][c][ql][t];
+        }
+        acc[k] = a;
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int it = tid + k * 256;
+    if (it < NIT) {
+      const int t = it % TE, cb = it / TE, b = cb % NB, c = cb / NB;
+      const int64_t e = e0 + t;
+      if (e < ne) {
+        double a = acc[k];
+        for (int p = 0; p < DIM; ++p) {
+          const int64_t em = m.nbr[(2 * p) * ne + e];
+          const double* wP = tb.fWPhi + ((size_t)(p * 2 + 1) * NFQ) * NB + b;
+          const double* wM = tb.fWPhi + ((size_t)(p * 2 + 0) * NFQ) * NB + b;
+          for (int fq = 0; fq < NFQ; ++fq) {
+            const size_t hi = ((size_t)(p * NV + c) * NFQ + fq) * ne;
+            a += wP[fq * NB] * H[hi + e] - wM[fq * NB] * H[hi + em];
+          }
+        }
+        if (JVP) a += shift * V[(size_t)cb * ne + e];
+        out[(size_t)cb * ne + e] = a;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ small kernels
+template <int DIM, int NB, int NQ1>
+__global__ void k_project(const double* __restrict__ f, double* __restrict__ w, Tables tb, int64_t ne) {
+  constexpr int NV = DIM + 2, NQ = ipow(NQ1, DIM);
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)NV * NB * ne) return;
+  const int64_t e = i % ne;
+  const int cb = (int)(i / ne), c = cb / NB, b = cb % NB;
+  double a = 0.0;
+  for (int q = 0; q < NQ; ++q) a += tb.vWPhi[q * NB + b] * f[((size_t)c * NQ + q) * ne + e];
+  w[i] = a;
+}
+
+template <int DIM, int NB, int NQ1>
+__global__ void k_points(double* __restrict__ xyz, Tables tb, Mesh m) {
+  constexpr int NQ = ipow(NQ1, DIM);
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)NQ * m.ne) return;
+  const int64_t e = i % m.ne;
+  const int q = (int)(i / m.ne);
+  for (int j = 0; j < DIM; ++j)
+    xyz[((size_t)j * NQ + q) * m.ne + e] = m.x0[j * m.ne + e] + 0.5 * (tb.vXi[q * DIM + j] + 1.0) * m.h[j];
+}
+
+// per-block maxima of |u| + c over the volume points of a grid-stride set of elements
+template <int DIM, int NB, int NQ1>
+__global__ __launch_bounds__(256) void k_wave_speed(const double* __restrict__ w, double* __restrict__ partial,
+                                                     Tables tb, Mesh m, Phys ph) {
+  constexpr int NV = DIM + 2, NQ = ipow(NQ1, DIM);
+  __shared__ double red[256];
+  double mx = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < (int64_t)NQ * m.ne; i += (int64_t)gridDim.x * 256) {
+    const int64_t e = i % m.ne;
+    const int q = (int)(i / m.ne);
+    double u[NV];
+    for (int c = 0; c < NV; ++c) {
+      double a = 0.0;
+      for (int b = 0; b < NB; ++b) a += tb.vPhi[q * NB + b] * w[((size_t)c * NB + b) * m.ne + e];
+      u[c] = a;
+    }
+    double rinv, vel[DIM], p;
+    primitives<double, DIM>(u, ph.gamma, rinv, vel, p);
+    double s = 0.0;
+    for (int j = 0; j < DIM; ++j) s += vel[j] * vel[j];
+    const double a = sqrt(s) + sqrt(ph.gamma * p * rinv);
+    mx = (a > mx || a != a) ? a : mx;
+  }
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) {
+      const double o = red[threadIdx.x + st];
+      red[threadIdx.x] = (o > red[threadIdx.x] || o != o) ? o : red[threadIdx.x];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+// ------------------------------------------------------------------ dispatch
+// Compiled configurations (dim, nb, nq1d) and tile sizes of the volume kernel.
+#define DG_CONFIGS(X)   \
+  X(0, 2, 9, 4)         \
+  X(1, 2, 6, 4)         \
+  X(2, 3, 4, 2)         \
+  X(3, 3, 10, 3)        \
+  X(4, 3, 20, 4)        \
+  X(5, 3, 35, 5)
+
+int config_index(int dim, int nb, int nq1d) {
+#define X(id, d, nb_, nq_) \
+  if (dim == d && nb == nb_ && nq1d == nq_) return id;
+  DG_CONFIGS(X)
+#undef X
+  return -1;
+}
+
+template <int NB, bool JVP> struct VolTile {
+  static constexpr int TE = JVP ? 8 : 16;
+  static constexpr int QC = 256 / TE;
+};
+
+hipError_t launch_face(int cfg, bool jvp, const double* U, const double* V, double* H, const Tables& tb,
+                       const Mesh& m, const Phys& ph, hipStream_t s) {
+#define X(id, d, nb_, nq_)                                                                          \
+  case id: {                                                                                        \
+    dim3 grid((unsigned)((m.ne + 63) / 64), d);                                                     \
+    if (jvp)                                                                                        \
+      k_face<d, nb_, nq_, true><<<grid, 256, 0, s>>>(U, V, H, tb, m, ph);                           \
+    else                                                                                            \
+      k_face<d, nb_, nq_, false><<<grid, 256, 0, s>>>(U, V, H, tb, m, ph);                          \
+    return hipGetLastError();                                                                       \
+  }
+  switch (cfg) { DG_CONFIGS(X) }
+#undef X
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_volume(int cfg, bool jvp, const double* U, const double* V, const double* H, double* out,
+                         double shift, const Tables& tb, const Mesh& m, const Phys& ph, hipStream_t s) {
+#define X(id, d, nb_, nq_)                                                                                    \
+  case id: {                                                                                                  \
+    if (jvp) {                                                                                                \
+      using TL = VolTile<nb_, true>;                                                                          \
+      dim3 grid((unsigned)((m.ne + TL::TE - 1) / TL::TE));                                                    \
+      k_volume<d, nb_, nq_, true, TL::TE, TL::QC><<<grid, 256, 0, s>>>(U, V, H, out, shift, tb, m, ph);      \
+    } else {                                                                                                  \
+      using TL = VolTile<nb_, false>;                                                                         \
+      dim3 grid((unsigned)((m.ne + TL::TE - 1) / TL::TE));                                                    \
+      k_volume<d, nb_, nq_, false, TL::TE, TL::QC><<<grid, 256, 0, s>>>(U, V, H, out, shift, tb, m, ph);     \
+    }                                                                                                         \
+    return hipGetLastError();                                                                                 \
+  }
+  switch (cfg) { DG_CONFIGS(X) }
+#undef X
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_project(int cfg, const double* f, double* w, const Tables& tb, const Mesh& m, hipStream_t s) {
+#define X(id, d, nb_, nq_)                                                          \
+  case id: {                                                                        \
+    int64_t n = (int64_t)(d + 2) * nb_ * m.ne;                                      \
+    k_project<d, nb_, nq_><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(f, w, tb, m.ne); \
+    return hipGetLastError();                                                       \
+  }
+  switch (cfg) { DG_CONFIGS(X) }
+#undef X
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_points(int cfg, double* xyz, const Tables& tb, const Mesh& m, hipStream_t s) {
+#define X(id, d, nb_, nq_)                                                         \
+  case id: {                                                                       \
+    int64_t n = (int64_t)ipow(nq_, d) * m.ne;                                      \
+    k_points<d, nb_, nq_><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(xyz, tb, m); \
+    return hipGetLastError();                                                      \
+  }
+  switch (cfg) { DG_CONFIGS(X) }
+#undef X
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_wave_speed(int cfg, const double* w, double* partial, int nblocks, const Tables& tb,
+                             const Mesh& m, const Phys& ph, hipStream_t s) {
+#define X(id, d, nb_, nq_)                                                            \
+  case id: {                                                                          \
+    k_wave_speed<d, nb_, nq_><<<nblocks, 256, 0, s>>>(w, partial, tb, m, ph);         \
+    return hipGetLastError();                                                         \
+  }
+  switch (cfg) { DG_CONFIGS(X) }
+#undef X
+  return hipErrorInvalidValue;
+}
+
+}  // namespace dgk

@@ -1,0 +1,262 @@
+// Host-side construction of quadrature rules, the hierarchical modal basis
+// and the FP64 operator tables of a uniform affine lattice.
+//
+// Basis: psi_alpha(xi) = prod_i Lt_{alpha_i}(xi_i), Lt_n = sqrt((2n+1)/2) P_n.
+// Space P_k (total degree <= k, the paper's broken space, Sec. 2.1) or Q_k.
+// Ordering: ascending total degree, then descending alpha_1, then descending
+// alpha_2, so that the leading dim P_k' modes span P_k' (restriction to a
+// coarser p-level keeps leading modes, Sec. 2.4.1).
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <stdexcept>
+
+#include "dg_internal.h"
+
+namespace dgh {
+
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    // Newton iteration on P_n from the classical cosine guess.
+    double t = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = t;
+      if (n == 0) p1 = 1.0;
+      for (int k = 1; k < n; ++k) {
+        double p2 = ((2.0 * k + 1.0) * t * p1 - k * p0) / (k + 1.0);
+        p0 = p1;
+        p1 = p2;
+      }
+      // P_n'(t) = n (t P_n - P_{n-1}) / (t^2 - 1)
+      dp = n * (t * p1 - p0) / (t * t - 1.0);
+      double dt = p1 / dp;
+      t -= dt;
+      if (std::fabs(dt) < 1e-16) break;
+    }
+    {
+      double p0 = 1.0, p1 = t;
+      for (int k = 1; k < n; ++k) {
+        double p2 = ((2.0 * k + 1.0) * t * p1 - k * p0) / (k + 1.0);
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (t * p1 - p0) / (t * t - 1.0);
+    }
+    x[n - 1 - i] = t;  // ascending order
+    w[n - 1 - i] = 2.0 / ((1.0 - t * t) * dp * dp);
+  }
+  if (n == 1) {
+    x[0] = 0.0;
+    w[0] = 2.0;
+  }
+}
+
+void legendre_orthonormal(int kmax, double x, double* L, double* dL) {
+  // Bonnet recursion for P_n and P'_{n+1} = P'_{n-1} + (2n+1) P_n.
+  std::vector<double> P(kmax + 2, 0.0), dP(kmax + 2, 0.0);
+  P[0] = 1.0;
+  dP[0] = 0.0;
+  if (kmax >= 1) {
+    P[1] = x;
+    dP[1] = 1.0;
+  }
+  for (int n = 1; n < kmax; ++n) {
+    P[n + 1] = ((2.0 * n + 1.0) * x * P[n] - n * P[n - 1]) / (n + 1.0);
+    dP[n + 1] = dP[n - 1] + (2.0 * n + 1.0) * P[n];
+  }
+  for (int n = 0; n <= kmax; ++n) {
+    double s = std::sqrt((2.0 * n + 1.0) / 2.0);
+    L[n] = s * P[n];
+    dL[n] = s * dP[n];
+  }
+}
+
+std::vector<int> multi_indices(int k, int dim, int basis) {
+  std::vector<std::array<int, 3>> all;
+  int lim[3] = {k, dim > 1 ? k : 0, dim > 2 ? k : 0};
+  for (int a2 = 0; a2 <= lim[2]; ++a2)
+    for (int a1 = 0; a1 <= lim[1]; ++a1)
+      for (int a0 = 0; a0 <= lim[0]; ++a0) {
+        int s = a0 + a1 + a2;
+        bool ok = (basis == DG_BASIS_PK) ? (s <= k) : (std::max(a0, std::max(a1, a2)) <= k);
+        if (ok) all.push_back({a0, a1, a2});
+      }
+  std::sort(all.begin(), all.end(), [](const std::array<int, 3>& a, const std::array<int, 3>& b) {
+    int sa = a[0] + a[1] + a[2], sb = b[0] + b[1] + b[2];
+    if (sa != sb) return sa < sb;
+    if (a[0] != b[0]) return a[0] > b[0];
+    return a[1] > b[1];
+  });
+  std::vector<int> out;
+  for (auto& a : all)
+    for (int i = 0; i < dim; ++i) out.push_back(a[i]);
+  return out;
+}
+
+namespace {
+
+// psi_b and its reference gradient at a point xi[dim].
+void eval_psi(const std::vector<int>& alpha, int dim, int kmax, const double* xi, double* psi, double* dpsi) {
+  const int nb = (int)alpha.size() / dim;
+  std::vector<double> L(3 * (kmax + 1)), dL(3 * (kmax + 1));
+  for (int i = 0; i < dim; ++i) legendre_orthonormal(kmax, xi[i], &L[i * (kmax + 1)], &dL[i * (kmax + 1)]);
+  for (int b = 0; b < nb; ++b) {
+    double v = 1.0;
+    for (int i = 0; i < dim; ++i) v *= L[i * (kmax + 1) + alpha[b * dim + i]];
+    psi[b] = v;
+    for (int j = 0; j < dim; ++j) {
+      double g = 1.0;
+      for (int i = 0; i < dim; ++i) {
+        int a = alpha[b * dim + i];
+        g *= (i == j) ? dL[i * (kmax + 1) + a] : L[i * (kmax + 1) + a];
+      }
+      dpsi[j * nb + b] = g;
+    }
+  }
+}
+
+}  // namespace
+
+HostTables build_tables(int dim, int order, int basis, int nq1d, const double h[3]) {
+  if (dim < 2 || dim > 3) throw std::invalid_argument("dim must be 2 or 3");
+  HostTables T;
+  T.dim = dim;
+  T.alpha = multi_indices(order, dim, basis);
+  const int nb = (int)T.alpha.size() / dim;
+  T.nb = nb;
+  T.nq1 = nq1d;
+  int nq = 1, nfq = 1;
+  for (int i = 0; i < dim; ++i) nq *= nq1d;
+  for (int i = 0; i < dim - 1; ++i) nfq *= nq1d;
+  T.nq = nq;
+  T.nfq = nfq;
+  const int kmax = order;
+
+  std::vector<double> x1, w1;
+  gauss_legendre(nq1d, x1, w1);
+
+  double detJ = 1.0;
+  for (int i = 0; i < dim; ++i) detJ *= 0.5 * h[i];
+  const double s = 1.0 / std::sqrt(detJ);
+
+  // ---------------- volume tables
+  std::vector<double> vW(nq), vDphi((size_t)dim * nq * nb);
+  T.vPhi.assign((size_t)nq * nb, 0.0);
+  T.vXi.assign((size_t)nq * dim, 0.0);
+  std::vector<double> psi(nb), dpsi((size_t)dim * nb);
+  for (int q = 0; q < nq; ++q) {
+    int r = q;
+    double xi[3] = {0, 0, 0}, wq = 1.0;
+    for (int i = 0; i < dim; ++i) {
+      int k = r % nq1d;
+      r /= nq1d;
+      xi[i] = x1[k];
+      wq *= w1[k];
+    }
+    for (int i = 0; i < dim; ++i) T.vXi[q * dim + i] = xi[i];
+    vW[q] = wq * detJ;
+    eval_psi(T.alpha, dim, kmax, xi, psi.data(), dpsi.data());
+    for (int b = 0; b < nb; ++b) {
+      T.vPhi[q * nb + b] = s * psi[b];
+      for (int j = 0; j < dim; ++j) vDphi[((size_t)j * nq + q) * nb + b] = s * (2.0 / h[j]) * dpsi[j * nb + b];
+    }
+  }
+  T.vWD.assign((size_t)dim * nq * nb, 0.0);
+  T.vWPhi.assign((size_t)nq * nb, 0.0);
+  for (int q = 0; q < nq; ++q)
+    for (int b = 0; b < nb; ++b) {
+      T.vWPhi[q * nb + b] = vW[q] * T.vPhi[q * nb + b];
+      for (int j = 0; j < dim; ++j)
+        T.vWD[((size_t)j * nq + q) * nb + b] = vW[q] * vDphi[((size_t)j * nq + q) * nb + b];
+    }
+  // modal derivative D_j[a][b] = sum_q w|J| phi_a d_j phi_b (exact on affine elements)
+  std::vector<double> D((size_t)dim * nb * nb, 0.0);
+  for (int j = 0; j < dim; ++j)
+    for (int a = 0; a < nb; ++a)
+      for (int b = 0; b < nb; ++b) {
+        double acc = 0.0;
+        for (int q = 0; q < nq; ++q) acc += vW[q] * T.vPhi[q * nb + a] * vDphi[((size_t)j * nq + q) * nb + b];
+        D[((size_t)j * nb + a) * nb + b] = acc;
+      }
+
+  // ---------------- face tables
+  T.fPhi.assign((size_t)dim * 2 * nfq * nb, 0.0);
+  T.fDphi.assign((size_t)dim * 2 * dim * nfq * nb, 0.0);
+  T.fWPhi.assign((size_t)dim * 2 * nfq * nb, 0.0);
+  T.fLift.assign((size_t)dim * 2 * nfq * nb, 0.0);
+  T.vLift.assign((size_t)dim * 3 * nb * nb, 0.0);
+  std::vector<double> fW((size_t)dim * nfq);
+  for (int p = 0; p < dim; ++p) {
+    double detF = 1.0;
+    for (int i = 0; i < dim; ++i)
+      if (i != p) detF *= 0.5 * h[i];
+    for (int side = 0; side < 2; ++side) {
+      for (int fq = 0; fq < nfq; ++fq) {
+        double xi[3] = {0, 0, 0}, wf = 1.0;
+        int r = fq;
+        for (int i = 0; i < dim; ++i) {
+          if (i == p) {
+            xi[i] = side ? 1.0 : -1.0;
+            continue;
+          }
+          int k = r % nq1d;
+          r /= nq1d;
+          xi[i] = x1[k];
+          wf *= w1[k];
+        }
+        fW[p * nfq + fq] = wf * detF;
+        eval_psi(T.alpha, dim, kmax, xi, psi.data(), dpsi.data());
+        for (int b = 0; b < nb; ++b) {
+          size_t o = (((size_t)p * 2 + side) * nfq + fq) * nb + b;
+          T.fPhi[o] = s * psi[b];
+          T.fWPhi[o] = fW[p * nfq + fq] * s * psi[b];
+          for (int j = 0; j < dim; ++j)
+            T.fDphi[((((size_t)p * 2 + side) * dim + j) * nfq + fq) * nb + b] = s * (2.0 / h[j]) * dpsi[j * nb + b];
+        }
+      }
+    }
+    // face mass matrices M[st][b][b'] = sum_f w|J_f| phi^s_b phi^t_b'
+    auto fphi = [&](int side, int fq, int b) { return T.fPhi[(((size_t)p * 2 + side) * nfq + fq) * nb + b]; };
+    std::vector<double> M(4 * (size_t)nb * nb, 0.0);
+    for (int st = 0; st < 4; ++st) {
+      int sa = st >> 1, sb = st & 1;
+      for (int a = 0; a < nb; ++a)
+        for (int b = 0; b < nb; ++b) {
+          double acc = 0.0;
+          for (int fq = 0; fq < nfq; ++fq) acc += fW[p * nfq + fq] * fphi(sa, fq, a) * fphi(sb, fq, b);
+          M[((size_t)st * nb + a) * nb + b] = acc;
+        }
+    }
+    auto Mst = [&](int sa, int sb, int a, int b) { return M[((size_t)(sa * 2 + sb) * nb + a) * nb + b]; };
+    // Local lifting of face sigma (owner L on side +, neighbour R on side -),
+    // int r.tau = -int [[U]] {tau}.n, n = +e_p, [[U]] = U_L - U_R:
+    //   rhoL = -1/2 (M_++ U_L - M_+- U_R),  rhoR = -1/2 (M_-+ U_L - M_-- U_R)
+    // {r} at the face points = 1/2 (sum_b rhoL_b phi+_b + sum_b rhoR_b phi-_b).
+    for (int fq = 0; fq < nfq; ++fq)
+      for (int bp = 0; bp < nb; ++bp) {
+        double cl = 0.0, cr = 0.0;
+        for (int b = 0; b < nb; ++b) {
+          cl += fphi(1, fq, b) * (-0.5 * Mst(1, 1, b, bp)) + fphi(0, fq, b) * (-0.5 * Mst(0, 1, b, bp));
+          cr += fphi(1, fq, b) * (0.5 * Mst(1, 0, b, bp)) + fphi(0, fq, b) * (0.5 * Mst(0, 0, b, bp));
+        }
+        T.fLift[(((size_t)p * 2 + 0) * nfq + fq) * nb + bp] = 0.5 * cl;
+        T.fLift[(((size_t)p * 2 + 1) * nfq + fq) * nb + bp] = 0.5 * cr;
+      }
+    // Elemental lifting of element e in direction p: its +p face (e is L) and
+    // its -p face (e is R), plus the modal derivative D_p:
+    //   Ghat_p = (D_p - M_++/2 + M_--/2) U_e + (M_+-/2) U_{e+p} - (M_-+/2) U_{e-p}
+    for (int a = 0; a < nb; ++a)
+      for (int b = 0; b < nb; ++b) {
+        T.vLift[(((size_t)p * 3 + 0) * nb + a) * nb + b] =
+            D[((size_t)p * nb + a) * nb + b] - 0.5 * Mst(1, 1, a, b) + 0.5 * Mst(0, 0, a, b);
+        T.vLift[(((size_t)p * 3 + 1) * nb + a) * nb + b] = 0.5 * Mst(1, 0, a, b);
+        T.vLift[(((size_t)p * 3 + 2) * nb + a) * nb + b] = -0.5 * Mst(0, 1, a, b);
+      }
+  }
+  return T;
+}
+
+}  // namespace dgh

@@ -1,0 +1,76 @@
+"""CPU tests of the C ABI: the library loads, exports every declared symbol,
+and rejects invalid arguments on the host before touching the GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+from paper_1809_00866_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "dg.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(dg_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.load()
+    names = _declared()
+    assert len(names) >= 18
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(L.EXPORTED) == names
+
+
+def _create(prm, mesh):
+    lib = L.load()
+    xyz = np.ascontiguousarray(mesh["elem_xyz"], dtype=np.float64)
+    nbr = np.ascontiguousarray(mesh["elem_nbr"], dtype=np.int64)
+    m = L.DGMesh(xyz.shape[0], xyz.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                 nbr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    h = ctypes.c_void_p()
+    st = lib.dg_create(ctypes.byref(prm), ctypes.byref(m), ctypes.byref(h))
+    return st, lib.dg_last_error().decode()
+
+
+def _prm(dim=3, order=3, nq=4, basis=L.DG_BASIS_PK, flux=L.DG_FLUX_ROE):
+    return L.DGParams(dim, order, basis, nq, flux, 1.4, 0.72, 1e-3, 0.0, 0.0)
+
+
+@pytest.mark.parametrize("bad", [dict(dim=4), dict(order=-1), dict(nq=0), dict(basis=7), dict(flux=9)])
+def test_create_rejects_bad_params(bad):
+    kw = dict(dim=3, order=3, nq=4)
+    kw.update(bad)
+    st, msg = _create(_prm(**kw), synth.lattice_mesh((2, 2, 2)))
+    assert st == -1 and msg
+
+
+def test_create_rejects_non_uniform_mesh():
+    st, msg = _create(_prm(), synth.lattice_mesh((2, 2, 2), perturb=0.1, seed=1))
+    assert st == -1 and "axis-aligned" in msg
+
+
+def test_create_rejects_inconsistent_neighbours():
+    mesh = synth.lattice_mesh((3, 3, 3))
+    mesh["elem_nbr"] = mesh["elem_nbr"].copy()
+    mesh["elem_nbr"][4, 1] = 7
+    st, msg = _create(_prm(), mesh)
+    assert st == -1 and "neighbour" in msg
+
+
+def test_create_rejects_uncompiled_configuration():
+    st, msg = _create(_prm(order=6, nq=7), synth.lattice_mesh((2, 2, 2)))
+    assert st == -1 and "no kernel compiled" in msg
+
+
+def test_null_arguments():
+    lib = L.load()
+    assert lib.dg_create(None, None, None) == -1
+    assert lib.dg_residual(None, None, None, None) == -1
+    assert lib.dg_ndof(None) == -1

@@ -1,0 +1,199 @@
+"""GPU parity: the HIP library through the C ABI against the FP64 oracle.
+
+Tolerances (relative 2-norms): residual 1e-12 of max(|R|, |R_volume|), exact
+Jv 1e-12, FD Jv 1e-6 (the FD quotient amplifies round-off by 1/Delta),
+projection 1e-13, block apply 1e-11 (FP64) / 1e-4 (FP32 factors), solves
+checked on the true residual with the oracle operator.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import DGOracle, NavierStokes, block_solve
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def make_case(N, order, space, nq, flux="roe", mu=1e-2, seed=11, noise=1e-2):
+    from paper_1809_00866_amd import DG
+    mesh = synth.lattice_mesh(N, L=1.0)
+    d = len(N)
+    o = DGOracle(mesh, order, space, nq, NavierStokes(d, mu=mu, flux=flux))
+    g = DG(mesh, order, basis=space, nq1d=nq, flux=flux, mu=mu)
+    fld = synth.FreeStreamPlusModes(seed=seed) if d == 2 else synth.TaylorGreenStandIn(seed=seed, L=1.0)
+    U = o.project(fld)
+    rng = np.random.default_rng(seed)
+    U = U + noise * rng.standard_normal(U.shape) * np.abs(U[:, :, :1])
+    w = torch.tensor(o.to_flat(U), device="cuda")
+    return o, g, U, w
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+CASES = [
+    ((4, 4), 2, "Q", 4, "roe"),       # the 2D Q2 discretisation
+    ((3, 5), 2, "P", 4, "lf"),        # 2D P2, Lax-Friedrichs, odd sizes
+    ((2, 3, 5), 3, "P", 4, "roe"),    # 3D P3, ragged tiles
+    ((3, 2, 2), 4, "P", 5, "roe"),    # 3D P4
+    ((2, 2, 2), 1, "P", 2, "lf"),     # 3D P1
+    ((3, 3, 2), 2, "P", 3, "roe"),    # 3D P2
+    ((1, 1, 1), 3, "P", 4, "roe"),    # one periodic element: its own neighbour
+]
+IDS = [f"{len(c[0])}d-N{'x'.join(map(str, c[0]))}-{c[2]}{c[1]}-{c[4]}" for c in CASES]
+
+
+@pytest.mark.parametrize("N,k,sp,nq,flux", CASES, ids=IDS)
+def test_residual_parity(N, k, sp, nq, flux):
+    _say(f"residual parity {N} {sp}{k} {flux}")
+    o, g, U, w = make_case(N, k, sp, nq, flux)
+    R, Rv = o.residual(U, return_parts=True)
+    Rg = g.residual(w).cpu().numpy()
+    err = np.linalg.norm(Rg - o.to_flat(R)) / max(np.linalg.norm(R), np.linalg.norm(Rv))
+    assert err <= 1e-12, err
+
+
+@pytest.mark.parametrize("N,k,sp,nq,flux", CASES, ids=IDS)
+def test_jvp_exact_parity(N, k, sp, nq, flux):
+    _say(f"jvp parity {N} {sp}{k} {flux}")
+    o, g, U, w = make_case(N, k, sp, nq, flux)
+    V = np.random.default_rng(866).standard_normal(U.shape)
+    v = torch.tensor(o.to_flat(V), device="cuda")
+    Jv = o.jvp(U, V)
+    for shift in (0.0, 37.5):
+        out = g.jvp(w, v, shift=shift, mode="exact").cpu().numpy()
+        assert rel(out, o.to_flat(Jv + shift * V)) <= 1e-12
+
+
+@pytest.mark.parametrize("N,k,sp,nq,flux", [CASES[0], CASES[2]], ids=[IDS[0], IDS[2]])
+def test_jvp_fd_parity(N, k, sp, nq, flux):
+    _say(f"fd jvp parity {N}")
+    o, g, U, w = make_case(N, k, sp, nq, flux)
+    V = np.random.default_rng(3).standard_normal(U.shape)
+    v = torch.tensor(o.to_flat(V), device="cuda")
+    fd_o = o.to_flat(o.jvp_fd(U, V))
+    ex_o = o.to_flat(o.jvp(U, V))
+    fd_g = g.jvp(w, v, mode="fd").cpu().numpy()
+    assert rel(fd_g, fd_o) <= 1e-6
+    assert rel(fd_g, ex_o) <= 1e-5
+    r_w = g.residual(w)
+    fd_g2 = g.jvp(w, v, mode="fd", r_w=r_w).cpu().numpy()
+    assert np.array_equal(fd_g, fd_g2)
+    zero = torch.zeros_like(v)
+    assert torch.count_nonzero(g.jvp(w, zero, shift=2.0, mode="fd")) == 0
+
+
+def test_projection_and_points():
+    _say("projection parity")
+    o, g, U, w = make_case((3, 2, 4), 3, "P", 4)
+    xyz = g.volume_points().cpu().numpy()          # [dim, nq, ne]
+    et = o.elem_tables(np.arange(o.ne))
+    assert np.abs(np.moveaxis(xyz, 0, -1).transpose(1, 0, 2) - et["x"]).max() < 1e-14
+    fld = synth.TaylorGreenStandIn(seed=5, L=1.0)
+    wg = g.project_field(fld).cpu().numpy()
+    assert rel(wg, o.to_flat(o.project(fld))) <= 1e-13
+
+
+@pytest.mark.parametrize("N,k,sp,nq,flux", [CASES[0], CASES[2], CASES[3], CASES[6]],
+                         ids=[IDS[0], IDS[2], IDS[3], IDS[6]])
+def test_block_jacobi_parity(N, k, sp, nq, flux):
+    _say(f"block parity {N} {sp}{k}")
+    o, g, U, w = make_case(N, k, sp, nq, flux)
+    shift = 25.0
+    D = o.block_diagonal(U, shift=shift)
+    r = np.random.default_rng(4).standard_normal(U.shape)
+    z_o = block_solve(D, r.reshape(o.ne, -1)).reshape(U.shape)
+    rt = torch.tensor(o.to_flat(r), device="cuda")
+    g.block_setup(w, shift, storage="fp64")
+    z_g = g.block_apply(rt).cpu().numpy()
+    assert rel(z_g, o.to_flat(z_o)) <= 1e-11
+    if o.nb * o.nvar * o.nb * o.nvar * 4 <= 150 * 1024:
+        g.block_setup(w, shift, storage="fp32")
+        z_g32 = g.block_apply(rt).cpu().numpy()
+        assert rel(z_g32, o.to_flat(z_o)) <= 1e-4
+
+
+def test_block_apply_before_setup_is_state_error():
+    from paper_1809_00866_amd._lib import DGError
+    o, g, U, w = make_case((2, 2, 2), 1, "P", 2)
+    with pytest.raises(DGError) as ei:
+        g.block_apply(w)
+    assert ei.value.status == -4
+
+
+@pytest.mark.parametrize("precond", ["bj", "none"])
+def test_fgmres_true_residual_with_oracle_operator(precond):
+    _say(f"fgmres {precond}")
+    o, g, U, w = make_case((3, 3, 3), 2, "P", 3)
+    shift = 40.0
+    B = np.random.default_rng(5).standard_normal(U.shape)
+    b = torch.tensor(o.to_flat(B), device="cuda")
+    if precond == "bj":
+        g.block_setup(w, shift)
+    x, st = g.fgmres(w, shift, b, restart=30, rtol=1e-10, max_iter=2000, precond=precond)
+    assert st["converged"] == 1 and st["rel_res_true"] <= 1e-10
+    X = o.from_flat(x.cpu().numpy())
+    res = np.linalg.norm(o.to_flat(o.operator(U, X, shift)) - o.to_flat(B)) / np.linalg.norm(B)
+    assert res <= 1e-9
+
+
+def test_fgmres_edge_cases():
+    _say("fgmres edge cases")
+    o, g, U, w = make_case((2, 2, 2), 2, "P", 3)
+    b = torch.zeros(g.ndof, dtype=torch.float64, device="cuda")
+    x, st = g.fgmres(w, 10.0, b, x=torch.ones_like(b), precond="none")
+    assert st["converged"] == 1 and st["iters"] == 0 and torch.count_nonzero(x) == 0
+    b = torch.randn(g.ndof, dtype=torch.float64, device="cuda")
+    x, st = g.fgmres(w, 10.0, b, max_iter=1, rtol=1e-14, precond="none")
+    assert st["converged"] == 0 and st["iters"] == 1
+    from paper_1809_00866_amd._lib import DGError
+    bad = b.clone()
+    bad[3] = float("nan")
+    with pytest.raises(DGError) as ei:
+        g.fgmres(w, 10.0, bad, precond="none")
+    assert ei.value.status == -6
+
+
+def test_determinism():
+    o, g, U, w = make_case((2, 3, 5), 3, "P", 4)
+    v = torch.randn(g.ndof, dtype=torch.float64, device="cuda")
+    a, b2 = g.residual(w), g.residual(w)
+    assert torch.equal(a, b2)
+    assert torch.equal(g.jvp(w, v), g.jvp(w, v))
+
+
+@pytest.mark.parametrize("name", ["cfg1", "cfg2"])
+def test_full_size_sampled(name):
+    """Full-size workloads in the benchmark's launch configuration; the oracle
+    checks sampled elements (cfg1: all 256 elements)."""
+    from paper_1809_00866_amd import DG
+    _say(f"full-size sampled {name}")
+    cfg, mesh, fld = synth.preset(name)
+    d = cfg["dim"]
+    o = DGOracle(mesh, cfg["order"], cfg["space"], cfg["nq1d"], NavierStokes(d, mu=cfg["mu"], flux="roe"))
+    g = DG(mesh, cfg["order"], basis=cfg["space"], nq1d=cfg["nq1d"], flux="roe", mu=cfg["mu"])
+    U = o.project(fld)
+    w = torch.tensor(o.to_flat(U), device="cuda")
+    v = torch.tensor(synth.random_vector(g.ndof, cfg["v_seed"]), device="cuda")
+    V = o.from_flat(v.cpu().numpy())
+    Rg = o.from_flat(g.residual(w).cpu().numpy())
+    Jg = o.from_flat(g.jvp(w, v).cpu().numpy())
+    rng = np.random.default_rng(0)
+    sample = np.arange(o.ne) if o.ne <= 256 else np.unique(np.concatenate(
+        [[0, o.ne - 1], rng.choice(o.ne, 14, replace=False)]))
+    R, Rv = o.residual(U, elems=sample, return_parts=True)
+    scale = max(np.linalg.norm(R), np.linalg.norm(Rv))
+    assert np.linalg.norm(Rg[sample] - R) <= 1e-12 * scale
+    J = o.jvp(U, V, elems=sample)
+    assert np.linalg.norm(Jg[sample] - J) <= 1e-12 * np.linalg.norm(J)
