@@ -1,0 +1,199 @@
+#!/usr/bin/env python3
+"""Benchmark: DOFs/s of the matrix-free exact Jacobian-vector product of the
+3D compressible Navier-Stokes DG discretisation (P3, 32^3 periodic hexes,
+Taylor-Green-like synthetic field), plus wall time to a 1e-8 FGMRES solve of
+one backward-Euler system (P4, 24^3 hexes, CFL 100, block-Jacobi).
+
+One step = one Jv (face kernel + volume kernel) on data resident in HBM.
+Prints one JSON line (see the keys below).  --gpus > 1 is not supported:
+this build runs on a single GPU.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "DOFs/s for matrix-free DG Jv (p=3, 3D hex); wall time to 1e-8 FGMRES solve"
+PEAK_FP64 = 78.6  # TFLOP/s, MI355X dense FP64 (vector and matrix)
+PEAK_HBM = 8000.0  # GB/s
+
+
+def jv_kernel_flops(ne, nb, nq, nfq, d):
+    """Algorithmic contraction flops of the exact Jv per launch.
+
+    Per element: volume part 2*[2 Nq Nb n (1+3d)] (interpolation of U and
+    grad U, lifting at the volume points, projection; value and tangent);
+    face part 2*[d * 2 Nfq Nb n (2d+8)] (traces of both sides, local
+    liftings, face projection).  The face projection (2 of the 2d+8 units) is
+    done by the volume kernel here.
+    """
+    n = d + 2
+    vol = 2 * (2 * nq * nb * n * (1 + 3 * d))
+    face = 2 * (d * 2 * nfq * nb * n * (2 * d + 8))
+    face_proj = face * 2 / (2 * d + 8)
+    return {"vol_jvp": (vol + face_proj) * ne, "face_jvp": (face - face_proj) * ne}
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch from the committed rocprofv3 FETCH/WRITE summary, or
+    None when the kernel source changed since the counters were taken."""
+    import hashlib
+    prof = os.path.join(ROOT, "profiles", "jv_p3_32cube_hbm_counters.txt")
+    src = os.path.join(ROOT, "paper_1809_00866_amd", "csrc", "dg_kernels.hip")
+    try:
+        text = open(prof).read()
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    if f": {sha}" not in text:
+        return None
+    for line in text.splitlines():
+        parts = line.split()
+        if "traffic_bytes" in parts and parts[-2] == kernel:
+            return float(parts[-1].replace(",", ""))
+    return None
+
+
+def cpu_baseline(sample_elems=1024):
+    """Oracle Jv (complex step, FP64, numpy) on a bounded sample of the P3 32^3 workload."""
+    import synth
+    from oracle import DGOracle, NavierStokes
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except Exception:
+        cores = 1
+    cfg, mesh, fld = synth.preset("cfg2")
+    o = DGOracle(mesh, cfg["order"], cfg["space"], cfg["nq1d"], NavierStokes(3, mu=cfg["mu"], flux="roe"))
+    rng = np.random.default_rng(0)
+    sample = np.sort(rng.choice(o.ne, sample_elems, replace=False))
+    # the sample's rows need the sample and its face neighbours
+    need = np.unique(np.concatenate([sample, o.nbr[sample].reshape(-1)]))
+    U = np.zeros((o.ne, o.nvar, o.nb))
+    U[need] = o.project(fld, elems=need)
+    V = np.zeros_like(U)
+    V[need] = np.random.default_rng(866).standard_normal((len(need), o.nvar, o.nb))
+    t0 = time.perf_counter()
+    J = o.jvp(U, V, elems=sample)
+    t = time.perf_counter() - t0
+    dofs = sample_elems * o.nvar * o.nb
+    assert np.all(np.isfinite(J))
+    return {"value": dofs / t, "unit": "DOFs/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"exact Jv rows of {sample_elems} random elements of the P3 32^3 workload "
+                      f"({dofs} DOFs), complex-step numpy oracle, {t:.2f} s"}
+
+
+def time_to_tolerance(storage="fp64"):
+    """Backward-Euler system of the P4 24^3 workload solved by FGMRES(30) to 1e-8."""
+    import torch
+    import synth
+    from paper_1809_00866_amd import DG
+    cfg, mesh, fld = synth.preset("cfg3")
+    g = DG(mesh, cfg["order"], basis=cfg["space"], nq1d=cfg["nq1d"], flux="roe", mu=cfg["mu"])
+    w = g.project_field(fld)
+    smax = g.max_wave_speed(w)
+    h = float(np.min(mesh["h"]))
+    dt = cfg["cfl"] * h / ((2 * cfg["order"] + 1) * smax)
+    shift = 1.0 / dt
+    b = -g.residual(w)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.block_setup(w, shift, storage=storage)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    x, st = g.fgmres(w, shift, b, restart=cfg["restart"], max_iter=3000, rtol=cfg["rtol"], precond="bj")
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    g.close()
+    return {"workload": "backward Euler, P4 24^3 hexes, CFL 100, FGMRES(30), block Jacobi " + storage,
+            "seconds": t2 - t0, "setup_s": t1 - t0, "solve_s": t2 - t1, "iters": st["iters"],
+            "converged": bool(st["converged"]), "rel_res_true": st["rel_res_true"], "dt": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=8192)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a plain 256 MiB device copy (reference kernel for HBM counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: --gpus {args.gpus} is not supported; this build runs on one GPU "
+              "(the multi-GPU sharding is a design note in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    from paper_1809_00866_amd import DG
+
+    torch.cuda.set_device(0)
+    cfg, mesh, fld = synth.preset("cfg2")
+    g = DG(mesh, cfg["order"], basis=cfg["space"], nq1d=cfg["nq1d"], flux="roe", mu=cfg["mu"])
+    w = g.project_field(fld)
+    v = torch.tensor(synth.random_vector(g.ndof, cfg["v_seed"]), device="cuda")
+    out = g.empty()
+    for _ in range(args.warmup):
+        g.jvp(w, v, out=out)
+    torch.cuda.synchronize()
+    g.set_profiling(True)
+    for k in ("face_jvp", "vol_jvp"):
+        g.kernel_time(k)  # reset
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g.jvp(w, v, out=out)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    g.set_profiling(False)
+    kt = {k: g.kernel_time(k) for k in ("face_jvp", "vol_jvp")}
+    assert torch.isfinite(out).all()
+    ms_per_step = wall * 1e3 / args.steps
+    value = g.ndof / (wall / args.steps)
+
+    nfq = cfg["nq1d"] ** 2
+    flops = jv_kernel_flops(g.ne, g.nb, g.nq, nfq, 3)
+    avg = {k: kt[k][0] / max(kt[k][1], 1) for k in kt}
+    dom = max(avg, key=avg.get)
+    achieved = flops[dom] / (avg[dom] * 1e-3) / 1e12
+    roofline = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": PEAK_FP64, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP64, "traffic": measured_traffic(dom), "traffic_unit": "bytes/launch",
+                "kernel_ms": {k: round(avg[k], 4) for k in avg},
+                "flops_per_launch": {k: flops[k] for k in flops}}
+    g.close()
+    del w, v, out
+    if args.calib_copy:
+        a = torch.ones(1 << 25, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    torch.cuda.empty_cache()
+
+    res = {"metric": METRIC, "value": value, "unit": "DOFs/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "exact Jv, 3D compressible NS, P3 (Nb=20), 32^3 periodic hexes, 4^3/4^2 Gauss, "
+                                  "Roe + BR2, Taylor-Green-like field Mach 0.1 Re 1600",
+                      "n_elem": int(32 ** 3), "ndof": int(32 ** 3 * 100), "dofs_per_variable": int(32 ** 3 * 20)},
+           "roofline": roofline}
+    if not args.no_solve:
+        res["time_to_tol"] = time_to_tolerance("fp64")
+        res["time_to_tol_fp32_blocks"] = time_to_tolerance("fp32")
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(args.cpu_sample)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()
