@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <string>
@@ -42,6 +43,10 @@ struct dg_context {
   int dim = 0, nv = 0, nb = 0, nq1 = 0, nq = 0, nfq = 0, cfg = -1;
   int64_t ne = 0, ndof = 0;
   dgk::Tables tb{};
+  dgk::MTables mt{};
+  bool use_mfma = false;
+  double* d_mtab = nullptr;
+  int* d_midx = nullptr;
   dgk::Mesh mesh{};
   dgk::Phys ph{};
   double* d_tab = nullptr;
@@ -94,6 +99,17 @@ struct ProfScope {
 
 dg_status eval_residual(dg_context* c, bool jvp, const double* w, const double* v, double shift, double* out,
                         hipStream_t s) {
+  if (c->use_mfma) {
+    {
+      ProfScope ps(c, jvp ? "face_jvp" : "face_res", s);
+      HIPCHK(dgk::launch_face_mfma(c->cfg, jvp, w, v, c->d_H, c->mt, c->mesh, c->ph, s));
+    }
+    {
+      ProfScope ps(c, jvp ? "vol_jvp" : "vol_res", s);
+      HIPCHK(dgk::launch_volume_mfma(c->cfg, jvp, w, v, c->d_H, out, shift, c->mt, c->mesh, c->ph, s));
+    }
+    return DG_OK;
+  }
   {
     ProfScope ps(c, jvp ? "face_jvp" : "face_res", s);
     HIPCHK(dgk::launch_face(c->cfg, jvp, w, v, c->d_H, c->tb, c->mesh, c->ph, s));
@@ -249,6 +265,35 @@ dg_status dg_create(const dg_params* prm, const dg_mesh* mesh, dg_context** out)
   c->tb.fWPhi = c->d_tab + off[7];
   c->tb.vXi = c->d_tab + off[8];
 
+  // MFMA operand tables (3D configurations with MFMA kernels)
+  const char* variant = std::getenv("DG_KERNEL_VARIANT");
+  const bool want_mfma = !(variant && std::strcmp(variant, "reference") == 0);
+  if (want_mfma && dgk::has_mfma(cfg)) {
+    dgh::MfmaHost M = dgh::build_mfma_tables(T);
+    std::vector<const std::vector<double>*> mp = {&M.vA, &M.pA, &M.fA, &M.tA, &M.lCoef};
+    size_t mtot = 0;
+    for (auto* v : mp) mtot += v->size();
+    if ((st = dalloc(&c->d_mtab, mtot)) != DG_OK) return cleanup(st);
+    if ((st = dalloc(&c->d_midx, M.lIdx.size())) != DG_OK) return cleanup(st);
+    std::vector<double> mpk;
+    std::vector<size_t> moff;
+    for (auto* v : mp) {
+      moff.push_back(mpk.size());
+      mpk.insert(mpk.end(), v->begin(), v->end());
+    }
+    if (hipMemcpy(c->d_mtab, mpk.data(), mtot * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->d_midx, M.lIdx.data(), M.lIdx.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+      return cleanup(fail(DG_ERR_HIP, "MFMA table upload failed"));
+    c->mt.vA = c->d_mtab + moff[0];
+    c->mt.pA = c->d_mtab + moff[1];
+    c->mt.fA = c->d_mtab + moff[2];
+    c->mt.tA = c->d_mtab + moff[3];
+    c->mt.lCoef = c->d_mtab + moff[4];
+    c->mt.lIdx = c->d_midx;
+    c->mt.kl = M.kl;
+    c->use_mfma = true;
+  }
+
   // neighbours transposed to [2*dim][ne], low corners [dim][ne]
   std::vector<int64_t> nbrT((size_t)2 * dim * ne);
   std::vector<double> x0((size_t)dim * ne);
@@ -308,6 +353,8 @@ void dg_destroy(dg_context* c) {
       (void)hipEventDestroy(ab.second);
     }
   dfree(c->d_tab);
+  dfree(c->d_mtab);
+  dfree(c->d_midx);
   dfree(c->d_nbr);
   dfree(c->d_x0);
   dfree(c->d_H);

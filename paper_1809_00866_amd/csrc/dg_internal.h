@@ -32,6 +32,19 @@ struct Tables {
 // fLift[p][0] / [p][1] map the owner / neighbour modes to {r^sigma} at the
 // face points (normal component; the lattice normal is +e_p).
 
+// Operator tables pre-permuted into the operand order of the FP64 MFMA
+// 16x16x4 instruction (A[i][k] at lane i + 16k, B[k][j] at lane j + 16k,
+// D[i][j] at lane j + 16 (i % 4), register i / 4), 64 doubles per fragment.
+struct MTables {
+  const double* vA;     // [RBQ][KSB][64]            interpolation: phi(q, b)
+  const double* pA;     // [RBQ][MB][DIM*4][64]      projection: -w|J| d_j phi(q, b), k = (j, q)
+  const double* fA;     // [DIM][2][MB][KSF][64]     face projection: +/- w_f|J_f| phi(fq, b)
+  const double* tA;     // [DIM][RBF][6][2*KSB][64]  face traces (uL, uR, G_1..3 averaged, {r})
+  const int* lIdx;      // [DIM][3][NB][KL]          modal corrected gradient along tensor lines
+  const double* lCoef;  // [DIM][3][NB][KL]
+  int kl;
+};
+
 struct Phys {
   double gamma, prandtl, mu, eta, efix;
   int flux;  // DG_FLUX_LF / DG_FLUX_ROE
@@ -52,6 +65,12 @@ hipError_t launch_face(int cfg, bool jvp, const double* U, const double* V, doub
                        const Mesh& m, const Phys& ph, hipStream_t stream);
 hipError_t launch_volume(int cfg, bool jvp, const double* U, const double* V, const double* H, double* out,
                          double shift, const Tables& tb, const Mesh& m, const Phys& ph, hipStream_t stream);
+// MFMA kernels (3D); return hipErrorInvalidValue when the configuration has none.
+bool has_mfma(int cfg);
+hipError_t launch_face_mfma(int cfg, bool jvp, const double* U, const double* V, double* H, const MTables& mt,
+                            const Mesh& m, const Phys& ph, hipStream_t stream);
+hipError_t launch_volume_mfma(int cfg, bool jvp, const double* U, const double* V, const double* H, double* out,
+                              double shift, const MTables& mt, const Mesh& m, const Phys& ph, hipStream_t stream);
 hipError_t launch_project(int cfg, const double* f, double* w, const Tables& tb, const Mesh& m, hipStream_t s);
 hipError_t launch_points(int cfg, double* xyz, const Tables& tb, const Mesh& m, hipStream_t s);
 hipError_t launch_wave_speed(int cfg, const double* w, double* partial, int nblocks, const Tables& tb,
@@ -104,5 +123,12 @@ void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
 void legendre_orthonormal(int kmax, double x, double* L, double* dL);
 std::vector<int> multi_indices(int k, int dim, int basis);
 HostTables build_tables(int dim, int order, int basis, int nq1d, const double h[3]);
+
+struct MfmaHost {
+  std::vector<double> vA, pA, fA, tA, lCoef;
+  std::vector<int> lIdx;
+  int kl = 0;
+};
+MfmaHost build_mfma_tables(const HostTables& T);
 
 }  // namespace dgh

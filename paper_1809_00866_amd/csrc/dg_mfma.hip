@@ -1,0 +1,413 @@
+// FP64 MFMA kernels for the 3D residual and exact Jacobian-vector product
+// (gfx950, v_mfma_f64_16x16x4).  Same arithmetic as the reference kernels in
+// dg_kernels.hip (eq. NSdiscrRes with BR2 liftings, Sec. 2.1-2.2); the dense
+// contractions run as MFMA tiles of 16 elements (or faces) x 16 quadrature
+// points, the pointwise fluxes on the vector ALU.
+//
+// MFMA operand layout (FP64 16x16x4): A[i][k] in lane i + 16k, B[k][j] in
+// lane j + 16k, D[i][j] in lane j + 16 (i % 4), register i / 4.  With
+// g = lane / 16 and col = lane % 16 a lane therefore holds rows g, g+4, g+8,
+// g+12 of column col, which is exactly the B operand of a following MFMA
+// whose k-steps walk those rows in order.
+//
+// Volume kernel (one workgroup = 4 waves = 16 elements):
+//   1. modal fields per element (U and the corrected gradients G_p =
+//      d_p U + R^K_p, computed from the element and its +/-p neighbours with
+//      the line-sparse maps lIdx/lCoef) are formed directly in B-fragment
+//      order and kept in registers (each wave owns a quarter of the
+//      (value/tangent, field, variable) column blocks);
+//   2. per block of 16 quadrature points: MFMA interpolation -> LDS stage ->
+//      one thread per (point, element) evaluates the volume flux (dual numbers
+//      for Jv) -> LDS stage -> MFMA weighted-transpose projection into
+//      per-wave accumulators (rows = modes, columns = elements);
+//   3. the 2*dim face fluxes of every element are projected with MFMA
+//      (gathered from the face-flux buffer, no atomics) and the result is
+//      written once.
+// Face kernel (one workgroup = 4 waves = 16 faces of one direction): MFMA
+// traces of both sides (values, averaged gradients, averaged lifting) -> LDS
+// stage -> one thread per (face point, face) evaluates the numerical flux.
+#include "dg_device.h"
+
+namespace dgk {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+DEV f64x4 mfma4(double a, double b, f64x4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+
+// ------------------------------------------------------------------ volume
+template <int NB, int NQ1, int KL, bool JVP>
+__global__ __launch_bounds__(256) void k_volume_mfma(const double* __restrict__ U, const double* __restrict__ V,
+                                                     const double* __restrict__ H, double* __restrict__ out,
+                                                     double shift, MTables mt, Mesh m, Phys ph) {
+  using T = typename Scalar<JVP>::type;
+  constexpr int DIM = 3, NV = 5;
+  constexpr int NQ = ipow(NQ1, 3), NFQ = ipow(NQ1, 2);
+  constexpr int KSB = (NB + 3) / 4, MB = (NB + 15) / 16, RBQ = (NQ + 15) / 16;
+  constexpr int KSP = DIM * 4, KSF = (NFQ + 3) / 4;
+  constexpr int NS = JVP ? 2 : 1;
+  constexpr int NFC = (1 + DIM) * NV;        // (field, variable) pairs per value/tangent
+  constexpr int NCBW = NS * NFC / 4;          // column blocks per wave
+  constexpr int NPB = NV * MB;                // projection accumulator blocks (variable, mode block)
+  constexpr int NPBW = (NPB + 3) / 4;
+  static_assert(NFC % 4 == 0, "column blocks must split over 4 waves");
+  constexpr int STAGE_ROWS = (NFC * 256 > 3 * NV * NB * 16) ? NFC : (3 * NV * NB + 15) / 16;
+  __shared__ double stage[STAGE_ROWS][16][16];
+  __shared__ int sIdx[DIM * 3 * NB * KL];
+  __shared__ double sCoef[DIM * 3 * NB * KL];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int g = lane >> 4, col = lane & 15;
+  const int64_t ne = m.ne;
+  const int64_t e0 = (int64_t)blockIdx.x * 16;
+  const int64_t e = e0 + col;
+  const bool ev = e < ne;
+  const double kap = ph.mu * ph.gamma / (ph.prandtl * (ph.gamma - 1.0));
+
+  // ---- 1. modal fields in B-fragment order: Bf[i][ks] = X[b = g + 4 ks][e].
+  // The line-sparse corrected-gradient maps are applied from LDS copies of the
+  // element's and its +/-p neighbours' modes, one (value/tangent, p) round at a
+  // time, with the maps themselves held in LDS.
+  double Bf[NCBW][KSB];
+#pragma unroll
+  for (int i = 0; i < NCBW; ++i) {
+    const int s = i / (NFC / 4);
+    const int fc = wave + 4 * (i % (NFC / 4));
+    const int f = fc / NV, c = fc % NV;
+    const double* __restrict__ X = (s == 0) ? U : V;
+#pragma unroll
+    for (int ks = 0; ks < KSB; ++ks) {
+      const int b = g + 4 * ks;
+      Bf[i][ks] = (f == 0 && ev && b < NB) ? X[(size_t)(c * NB + b) * ne + e] : 0.0;
+    }
+  }
+  for (int it = tid; it < DIM * 3 * NB * KL; it += 256) {
+    sIdx[it] = mt.lIdx[it];
+    sCoef[it] = mt.lCoef[it];
+  }
+  double* sl = &stage[0][0][0];  // [src][c][b][16]
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const double* __restrict__ X = (s == 0) ? U : V;
+#pragma unroll
+    for (int p = 0; p < DIM; ++p) {
+      for (int it = tid; it < 3 * NV * NB * 16; it += 256) {
+        const int t = it & 15;
+        int r = it >> 4;
+        const int b = r % NB;
+        r /= NB;
+        const int c = r % NV, src = r / NV;
+        const int64_t et2 = e0 + t;
+        double val = 0.0;
+        if (et2 < ne) {
+          const int64_t es = (src == 0) ? et2 : m.nbr[(2 * p + (src == 1 ? 1 : 0)) * ne + et2];
+          val = X[(size_t)(c * NB + b) * ne + es];
+        }
+        sl[it] = val;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int i = s * (NFC / 4); i < (s + 1) * (NFC / 4); ++i) {
+        const int fc = wave + 4 * (i % (NFC / 4));
+        const int f = fc / NV, c = fc % NV;
+        if (f == p + 1) {
+#pragma unroll
+          for (int ks = 0; ks < KSB; ++ks) {
+            const int b = g + 4 * ks;
+            double val = 0.0;
+            if (b < NB) {
+#pragma unroll
+              for (int src = 0; src < 3; ++src) {
+                const int row = ((p * 3 + src) * NB + b) * KL;
+#pragma unroll
+                for (int k = 0; k < KL; ++k)
+                  val += sCoef[row + k] * sl[((src * NV + c) * NB + sIdx[row + k]) * 16 + col];
+              }
+            }
+            Bf[i][ks] = val;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+
+  f64x4 acc[NPBW];
+#pragma unroll
+  for (int i = 0; i < NPBW; ++i) acc[i] = f64x4{0.0, 0.0, 0.0, 0.0};
+
+  const int ql = tid >> 4, et = tid & 15;  // pointwise mapping: (point in block, element)
+  for (int rb = 0; rb < RBQ; ++rb) {
+    double st[NS][NFC];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      // ---- 2a. MFMA interpolation of this wave's column blocks
+#pragma unroll
+      for (int i = s * (NFC / 4); i < (s + 1) * (NFC / 4); ++i) {
+        const int fc = wave + 4 * (i % (NFC / 4));
+        f64x4 d = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int ks = 0; ks < KSB; ++ks) d = mfma4(mt.vA[((size_t)rb * KSB + ks) * 64 + lane], Bf[i][ks], d);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) stage[fc][g + 4 * r][col] = d[r];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int fc = 0; fc < NFC; ++fc) st[s][fc] = stage[fc][ql][et];
+      __syncthreads();
+    }
+    // ---- 2b. pointwise volume flux F = F^c - F^v (tangent for Jv)
+    const int q = 16 * rb + ql;
+    double Fo[DIM][NV];
+#pragma unroll
+    for (int j = 0; j < DIM; ++j)
+#pragma unroll
+      for (int c = 0; c < NV; ++c) Fo[j][c] = 0.0;
+    if (q < NQ && e0 + et < ne) {
+      T u[NV], G[NV][DIM];
+#pragma unroll
+      for (int c = 0; c < NV; ++c) {
+        if constexpr (JVP) {
+          u[c] = dual(st[0][c], st[NS - 1][c]);
+#pragma unroll
+          for (int j = 0; j < DIM; ++j) G[c][j] = dual(st[0][(1 + j) * NV + c], st[NS - 1][(1 + j) * NV + c]);
+        } else {
+          u[c] = st[0][c];
+#pragma unroll
+          for (int j = 0; j < DIM; ++j) G[c][j] = st[0][(1 + j) * NV + c];
+        }
+      }
+      T rinv, vel[DIM], pr;
+      primitives<T, DIM>(u, ph.gamma, rinv, vel, pr);
+      ViscPrep<T, DIM> vp;
+      visc_prep<T, DIM>(u, G, ph.gamma, vp);
+#pragma unroll
+      for (int j = 0; j < DIM; ++j) {
+        T Fc[NV], Fv[NV];
+        conv_flux_dir<T, DIM>(u, vel, pr, j, Fc);
+        visc_flux_dir<T, DIM>(vp, j, ph.mu, kap, Fv);
+#pragma unroll
+        for (int c = 0; c < NV; ++c) Fo[j][c] = out_part(Fc[c] - Fv[c]);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < DIM; ++j)
+#pragma unroll
+      for (int c = 0; c < NV; ++c) stage[j * NV + c][ql][et] = Fo[j][c];
+    __syncthreads();
+    // ---- 2c. MFMA projection: R[b][e] += -sum_{j,q} w|J| d_j phi(q,b) F_j(q,e)
+#pragma unroll
+    for (int i = 0; i < NPBW; ++i) {
+      const int pb = wave + 4 * i;
+      if (pb < NPB) {
+        const int c = pb / MB, mb = pb % MB;
+#pragma unroll
+        for (int ks = 0; ks < KSP; ++ks) {
+          const int k = g + 4 * ks;
+          acc[i] = mfma4(mt.pA[(((size_t)rb * MB + mb) * KSP + ks) * 64 + lane], stage[(k >> 4) * NV + c][k & 15][col],
+                         acc[i]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- 3. face contributions (+ on the element's own +p faces, - on its -p faces)
+#pragma unroll
+  for (int i = 0; i < NPBW; ++i) {
+    const int pb = wave + 4 * i;
+    if (pb < NPB) {
+      const int c = pb / MB, mb = pb % MB;
+#pragma unroll
+      for (int p = 0; p < DIM; ++p) {
+        const int64_t em = ev ? m.nbr[(2 * p) * ne + e] : 0;
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+          const int64_t es = side ? e : em;
+#pragma unroll
+          for (int ks = 0; ks < KSF; ++ks) {
+            const int fq = g + 4 * ks;
+            const double hb = (ev && fq < NFQ) ? H[((size_t)(p * NV + c) * NFQ + fq) * ne + es] : 0.0;
+            acc[i] = mfma4(mt.fA[((((size_t)p * 2 + side) * MB + mb) * KSF + ks) * 64 + lane], hb, acc[i]);
+          }
+        }
+      }
+      if (ev) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int b = 16 * mb + g + 4 * r;
+          if (b < NB) {
+            const size_t idx = (size_t)(c * NB + b) * ne + e;
+            double a = acc[i][r];
+            if (JVP) a += shift * V[idx];
+            out[idx] = a;
+          }
+        }
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ faces
+template <int NB, int NQ1, bool JVP, int P>
+DEV void face_mfma_body(const double* __restrict__ U, const double* __restrict__ V, double* __restrict__ H,
+                        const MTables& mt, const Mesh& m, const Phys& ph, double (*stage)[16][16]) {
+  using T = typename Scalar<JVP>::type;
+  constexpr int DIM = 3, NV = 5;
+  constexpr int NFQ = ipow(NQ1, 2);
+  constexpr int KSB = (NB + 3) / 4, RBF = (NFQ + 15) / 16;
+  constexpr int NS = JVP ? 2 : 1;
+  constexpr int NCB = NS * NV;               // (value/tangent, variable) column blocks
+  constexpr int NCBW = (NCB + 3) / 4;
+  constexpr int NCH = 6;                     // uL, uR, G_1..3 (averaged), {r}
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int g = lane >> 4, col = lane & 15;
+  const int64_t ne = m.ne;
+  const int64_t e0 = (int64_t)blockIdx.x * 16;
+  const int64_t e = e0 + col;
+  const bool ev = e < ne;
+  const int64_t er = ev ? m.nbr[(2 * P + 1) * ne + e] : 0;
+  const double kap = ph.mu * ph.gamma / (ph.prandtl * (ph.gamma - 1.0));
+
+  // B fragments: k-steps 0..KSB-1 from the owner, KSB..2KSB-1 from the +P neighbour
+  double Bf[NCBW][2 * KSB];
+#pragma unroll
+  for (int i = 0; i < NCBW; ++i) {
+    const int cb = wave + 4 * i;
+    const int s = cb / NV, c = cb % NV;
+    const double* __restrict__ X = (s == 0) ? U : V;
+#pragma unroll
+    for (int ks2 = 0; ks2 < 2 * KSB; ++ks2) {
+      const int b = g + 4 * (ks2 < KSB ? ks2 : ks2 - KSB);
+      const int64_t es = ks2 < KSB ? e : er;
+      Bf[i][ks2] = (cb < NCB && ev && b < NB) ? X[(size_t)(c * NB + b) * ne + es] : 0.0;
+    }
+  }
+
+  const int fql = tid >> 4, ft = tid & 15;
+  for (int rbf = 0; rbf < RBF; ++rbf) {
+    double st[NS][NCH * NV];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+#pragma unroll
+      for (int i = 0; i < NCBW; ++i) {
+        const int cb = wave + 4 * i;
+        if (cb < NCB && cb / NV == s) {
+          const int c = cb % NV;
+#pragma unroll
+          for (int ch = 0; ch < NCH; ++ch) {
+            const int k0 = (ch == 1) ? KSB : 0;
+            const int k1 = (ch == 0) ? KSB : 2 * KSB;
+            f64x4 d = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int ks2 = k0; ks2 < k1; ++ks2)
+              d = mfma4(mt.tA[((((size_t)P * RBF + rbf) * NCH + ch) * 2 * KSB + ks2) * 64 + lane], Bf[i][ks2], d);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) stage[ch * NV + c][g + 4 * r][col] = d[r];
+          }
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < NCH * NV; ++k) st[s][k] = stage[k][fql][ft];
+      __syncthreads();
+    }
+    const int fq = 16 * rbf + fql;
+    const int64_t ef = e0 + ft;
+    if (fq < NFQ && ef < ne) {
+      T uL[NV], uR[NV], Ga[NV][DIM];
+#pragma unroll
+      for (int c = 0; c < NV; ++c) {
+        if constexpr (JVP) {
+          uL[c] = dual(st[0][0 * NV + c], st[NS - 1][0 * NV + c]);
+          uR[c] = dual(st[0][1 * NV + c], st[NS - 1][1 * NV + c]);
+#pragma unroll
+          for (int j = 0; j < DIM; ++j) Ga[c][j] = dual(st[0][(2 + j) * NV + c], st[NS - 1][(2 + j) * NV + c]);
+          Ga[c][P] += ph.eta * dual(st[0][5 * NV + c], st[NS - 1][5 * NV + c]);
+        } else {
+          uL[c] = st[0][0 * NV + c];
+          uR[c] = st[0][1 * NV + c];
+#pragma unroll
+          for (int j = 0; j < DIM; ++j) Ga[c][j] = st[0][(2 + j) * NV + c];
+          Ga[c][P] += ph.eta * st[0][5 * NV + c];
+        }
+      }
+      T Hn[NV];
+      num_flux<T, DIM>(uL, uR, P, ph, Hn);
+      T ua[NV];
+#pragma unroll
+      for (int c = 0; c < NV; ++c) ua[c] = 0.5 * (uL[c] + uR[c]);
+      ViscPrep<T, DIM> vp;
+      visc_prep<T, DIM>(ua, Ga, ph.gamma, vp);
+      T Fv[NV];
+      visc_flux_dir<T, DIM>(vp, P, ph.mu, kap, Fv);
+#pragma unroll
+      for (int c = 0; c < NV; ++c) H[((size_t)(P * NV + c) * NFQ + fq) * ne + ef] = out_part(Hn[c] - Fv[c]);
+    }
+  }
+}
+
+template <int NB, int NQ1, bool JVP>
+__global__ __launch_bounds__(256) void k_face_mfma(const double* __restrict__ U, const double* __restrict__ V,
+                                                   double* __restrict__ H, MTables mt, Mesh m, Phys ph) {
+  __shared__ double stage[6 * 5][16][16];
+  switch (blockIdx.y) {
+    case 0: face_mfma_body<NB, NQ1, JVP, 0>(U, V, H, mt, m, ph, stage); break;
+    case 1: face_mfma_body<NB, NQ1, JVP, 1>(U, V, H, mt, m, ph, stage); break;
+    default: face_mfma_body<NB, NQ1, JVP, 2>(U, V, H, mt, m, ph, stage); break;
+  }
+}
+
+// ------------------------------------------------------------------ dispatch
+// (cfg id, nb, nq1d) of the 3D configurations with MFMA kernels; ids match
+// the configuration table of dg_kernels.hip.
+#define DG_MFMA_CONFIGS(X) \
+  X(3, 10, 3, 3)           \
+  X(4, 20, 4, 4)           \
+  X(5, 35, 5, 5)
+
+bool has_mfma(int cfg) {
+#define X(id, nb_, nq_, kl_) \
+  if (cfg == id) return true;
+  DG_MFMA_CONFIGS(X)
+#undef X
+  return false;
+}
+
+hipError_t launch_face_mfma(int cfg, bool jvp, const double* U, const double* V, double* H, const MTables& mt,
+                            const Mesh& m, const Phys& ph, hipStream_t s) {
+#define X(id, nb_, nq_, kl_)                                                         \
+  case id: {                                                                         \
+    dim3 grid((unsigned)((m.ne + 15) / 16), 3);                                      \
+    if (jvp)                                                                         \
+      k_face_mfma<nb_, nq_, true><<<grid, 256, 0, s>>>(U, V, H, mt, m, ph);          \
+    else                                                                             \
+      k_face_mfma<nb_, nq_, false><<<grid, 256, 0, s>>>(U, V, H, mt, m, ph);         \
+    return hipGetLastError();                                                        \
+  }
+  switch (cfg) { DG_MFMA_CONFIGS(X) }
+#undef X
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_volume_mfma(int cfg, bool jvp, const double* U, const double* V, const double* H, double* out,
+                              double shift, const MTables& mt, const Mesh& m, const Phys& ph, hipStream_t s) {
+#define X(id, nb_, nq_, kl_)                                                                     \
+  case id: {                                                                                     \
+    if (mt.kl != kl_) return hipErrorInvalidValue;                                               \
+    dim3 grid((unsigned)((m.ne + 15) / 16));                                                     \
+    if (jvp)                                                                                     \
+      k_volume_mfma<nb_, nq_, kl_, true><<<grid, 256, 0, s>>>(U, V, H, out, shift, mt, m, ph);   \
+    else                                                                                         \
+      k_volume_mfma<nb_, nq_, kl_, false><<<grid, 256, 0, s>>>(U, V, H, out, shift, mt, m, ph);  \
+    return hipGetLastError();                                                                    \
+  }
+  switch (cfg) { DG_MFMA_CONFIGS(X) }
+#undef X
+  return hipErrorInvalidValue;
+}
+
+}  // namespace dgk

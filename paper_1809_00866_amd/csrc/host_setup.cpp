@@ -259,4 +259,83 @@ HostTables build_tables(int dim, int order, int basis, int nq1d, const double h[
   return T;
 }
 
+MfmaHost build_mfma_tables(const HostTables& T) {
+  MfmaHost M;
+  const int dim = T.dim, nb = T.nb, nq = T.nq, nfq = T.nfq;
+  const int KSB = (nb + 3) / 4, MB = (nb + 15) / 16, RBQ = (nq + 15) / 16, KSP = dim * 4;
+  const int KSF = (nfq + 3) / 4, RBF = (nfq + 15) / 16;
+  M.vA.assign((size_t)RBQ * KSB * 64, 0.0);
+  for (int rb = 0; rb < RBQ; ++rb)
+    for (int ks = 0; ks < KSB; ++ks)
+      for (int l = 0; l < 64; ++l) {
+        const int q = 16 * rb + (l & 15), b = (l >> 4) + 4 * ks;
+        if (q < nq && b < nb) M.vA[((size_t)rb * KSB + ks) * 64 + l] = T.vPhi[(size_t)q * nb + b];
+      }
+  M.pA.assign((size_t)RBQ * MB * KSP * 64, 0.0);
+  for (int rb = 0; rb < RBQ; ++rb)
+    for (int mb = 0; mb < MB; ++mb)
+      for (int ks = 0; ks < KSP; ++ks)
+        for (int l = 0; l < 64; ++l) {
+          const int b = 16 * mb + (l & 15), k = (l >> 4) + 4 * ks, j = k >> 4, q = 16 * rb + (k & 15);
+          if (q < nq && b < nb)
+            M.pA[(((size_t)rb * MB + mb) * KSP + ks) * 64 + l] = -T.vWD[((size_t)j * nq + q) * nb + b];
+        }
+  M.fA.assign((size_t)dim * 2 * MB * KSF * 64, 0.0);
+  for (int p = 0; p < dim; ++p)
+    for (int side = 0; side < 2; ++side)
+      for (int mb = 0; mb < MB; ++mb)
+        for (int ks = 0; ks < KSF; ++ks)
+          for (int l = 0; l < 64; ++l) {
+            const int b = 16 * mb + (l & 15), fq = (l >> 4) + 4 * ks;
+            if (fq < nfq && b < nb)
+              M.fA[((((size_t)p * 2 + side) * MB + mb) * KSF + ks) * 64 + l] =
+                  (side ? 1.0 : -1.0) * T.fWPhi[(((size_t)p * 2 + side) * nfq + fq) * nb + b];
+          }
+  M.tA.assign((size_t)dim * RBF * 6 * 2 * KSB * 64, 0.0);
+  for (int p = 0; p < dim; ++p)
+    for (int rbf = 0; rbf < RBF; ++rbf)
+      for (int ch = 0; ch < 6; ++ch)
+        for (int ks2 = 0; ks2 < 2 * KSB; ++ks2)
+          for (int l = 0; l < 64; ++l) {
+            const int fq = 16 * rbf + (l & 15);
+            const bool left = ks2 < KSB;
+            const int b = (l >> 4) + 4 * (left ? ks2 : ks2 - KSB);
+            if (fq >= nfq || b >= nb) continue;
+            const int side = left ? 1 : 0;  // owner trace on xi_p = +1, neighbour on xi_p = -1
+            double v = 0.0;
+            if (ch == 0) v = left ? T.fPhi[(((size_t)p * 2 + 1) * nfq + fq) * nb + b] : 0.0;
+            else if (ch == 1) v = left ? 0.0 : T.fPhi[(((size_t)p * 2 + 0) * nfq + fq) * nb + b];
+            else if (ch < 5)
+              v = 0.5 * T.fDphi[((((size_t)p * 2 + side) * dim + (ch - 2)) * nfq + fq) * nb + b];
+            else
+              v = T.fLift[(((size_t)p * 2 + (left ? 0 : 1)) * nfq + fq) * nb + b];
+            M.tA[((((size_t)p * RBF + rbf) * 6 + ch) * 2 * KSB + ks2) * 64 + l] = v;
+          }
+  // sparse rows of the modal corrected-gradient maps (nonzeros lie on tensor lines)
+  double big = 0.0;
+  for (double v : T.vLift) big = std::max(big, std::fabs(v));
+  int kl = 0;
+  for (int r = 0; r < dim * 3 * nb; ++r) {
+    int cnt = 0;
+    for (int b = 0; b < nb; ++b)
+      if (std::fabs(T.vLift[(size_t)r * nb + b]) > 1e-14 * big) ++cnt;
+    kl = std::max(kl, cnt);
+  }
+  M.kl = kl;
+  M.lIdx.assign((size_t)dim * 3 * nb * kl, 0);
+  M.lCoef.assign((size_t)dim * 3 * nb * kl, 0.0);
+  for (int r = 0; r < dim * 3 * nb; ++r) {
+    int cnt = 0;
+    for (int b = 0; b < nb; ++b) {
+      const double v = T.vLift[(size_t)r * nb + b];
+      if (std::fabs(v) > 1e-14 * big) {
+        M.lIdx[(size_t)r * kl + cnt] = b;
+        M.lCoef[(size_t)r * kl + cnt] = v;
+        ++cnt;
+      }
+    }
+  }
+  return M;
+}
+
 }  // namespace dgh
