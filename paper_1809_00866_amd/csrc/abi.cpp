@@ -46,7 +46,6 @@ struct dg_context {
   dgk::MTables mt{};
   bool use_mfma = false;
   double* d_mtab = nullptr;
-  int* d_midx = nullptr;
   dgk::Mesh mesh{};
   dgk::Phys ph{};
   double* d_tab = nullptr;
@@ -270,26 +269,23 @@ dg_status dg_create(const dg_params* prm, const dg_mesh* mesh, dg_context** out)
   const bool want_mfma = !(variant && std::strcmp(variant, "reference") == 0);
   if (want_mfma && dgk::has_mfma(cfg)) {
     dgh::MfmaHost M = dgh::build_mfma_tables(T);
-    std::vector<const std::vector<double>*> mp = {&M.vA, &M.pA, &M.fA, &M.tA, &M.lCoef};
+    std::vector<const std::vector<double>*> mp = {&M.vA, &M.pA, &M.fA, &M.tA, &M.lA};
     size_t mtot = 0;
     for (auto* v : mp) mtot += v->size();
     if ((st = dalloc(&c->d_mtab, mtot)) != DG_OK) return cleanup(st);
-    if ((st = dalloc(&c->d_midx, M.lIdx.size())) != DG_OK) return cleanup(st);
     std::vector<double> mpk;
     std::vector<size_t> moff;
     for (auto* v : mp) {
       moff.push_back(mpk.size());
       mpk.insert(mpk.end(), v->begin(), v->end());
     }
-    if (hipMemcpy(c->d_mtab, mpk.data(), mtot * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(c->d_midx, M.lIdx.data(), M.lIdx.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+    if (hipMemcpy(c->d_mtab, mpk.data(), mtot * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
       return cleanup(fail(DG_ERR_HIP, "MFMA table upload failed"));
     c->mt.vA = c->d_mtab + moff[0];
     c->mt.pA = c->d_mtab + moff[1];
     c->mt.fA = c->d_mtab + moff[2];
     c->mt.tA = c->d_mtab + moff[3];
-    c->mt.lCoef = c->d_mtab + moff[4];
-    c->mt.lIdx = c->d_midx;
+    c->mt.lA = c->d_mtab + moff[4];
     c->mt.kl = M.kl;
     c->use_mfma = true;
   }
@@ -354,7 +350,6 @@ void dg_destroy(dg_context* c) {
     }
   dfree(c->d_tab);
   dfree(c->d_mtab);
-  dfree(c->d_midx);
   dfree(c->d_nbr);
   dfree(c->d_x0);
   dfree(c->d_H);

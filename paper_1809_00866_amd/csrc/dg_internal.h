@@ -40,9 +40,8 @@ struct MTables {
   const double* pA;     // [RBQ][MB][DIM*4][64]      projection: -w|J| d_j phi(q, b), k = (j, q)
   const double* fA;     // [DIM][2][MB][KSF][64]     face projection: +/- w_f|J_f| phi(fq, b)
   const double* tA;     // [DIM][RBF][6][2*KSB][64]  face traces (uL, uR, G_1..3 averaged, {r})
-  const int* lIdx;      // [DIM][3][NB][KL]          modal corrected gradient along tensor lines
-  const double* lCoef;  // [DIM][3][NB][KL]
-  int kl;
+  const double* lA;     // [DIM][MB][3*KSB][64]      modal corrected gradient [L0 | L1 | L2]
+  int kl;               // max nonzeros per row of the maps (p+1: they act along tensor lines)
 };
 
 struct Phys {
@@ -125,8 +124,7 @@ std::vector<int> multi_indices(int k, int dim, int basis);
 HostTables build_tables(int dim, int order, int basis, int nq1d, const double h[3]);
 
 struct MfmaHost {
-  std::vector<double> vA, pA, fA, tA, lCoef;
-  std::vector<int> lIdx;
+  std::vector<double> vA, pA, fA, tA, lA;
   int kl = 0;
 };
 MfmaHost build_mfma_tables(const HostTables& T);

@@ -12,9 +12,8 @@
 //
 // Volume kernel (one workgroup = 4 waves = 16 elements):
 //   1. modal fields per element (U and the corrected gradients G_p =
-//      d_p U + R^K_p, computed from the element and its +/-p neighbours with
-//      the line-sparse maps lIdx/lCoef) are formed directly in B-fragment
-//      order and kept in registers (each wave owns a quarter of the
+//      d_p U + R^K_p, computed by MFMA from the element and its +/-p
+//      neighbours) are formed directly in B-fragment order and kept in registers (each wave owns a quarter of the
 //      (value/tangent, field, variable) column blocks);
 //   2. per block of 16 quadrature points: MFMA interpolation -> LDS stage ->
 //      one thread per (point, element) evaluates the volume flux (dual numbers
@@ -36,7 +35,7 @@ DEV f64x4 mfma4(double a, double b, f64x4 c) { return __builtin_amdgcn_mfma_f64_
 
 // ------------------------------------------------------------------ volume
 template <int NB, int NQ1, int KL, bool JVP>
-__global__ __launch_bounds__(256) void k_volume_mfma(const double* __restrict__ U, const double* __restrict__ V,
+__global__ __launch_bounds__(256, 2) void k_volume_mfma(const double* __restrict__ U, const double* __restrict__ V,
                                                      const double* __restrict__ H, double* __restrict__ out,
                                                      double shift, MTables mt, Mesh m, Phys ph) {
   using T = typename Scalar<JVP>::type;
@@ -52,8 +51,6 @@ __global__ __launch_bounds__(256) void k_volume_mfma(const double* __restrict__ 
   static_assert(NFC % 4 == 0, "column blocks must split over 4 waves");
   constexpr int STAGE_ROWS = (NFC * 256 > 3 * NV * NB * 16) ? NFC : (3 * NV * NB + 15) / 16;
   __shared__ double stage[STAGE_ROWS][16][16];
-  __shared__ int sIdx[DIM * 3 * NB * KL];
-  __shared__ double sCoef[DIM * 3 * NB * KL];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -66,9 +63,9 @@ __global__ __launch_bounds__(256) void k_volume_mfma(const double* __restrict__ 
   const double kap = ph.mu * ph.gamma / (ph.prandtl * (ph.gamma - 1.0));
 
   // ---- 1. modal fields in B-fragment order: Bf[i][ks] = X[b = g + 4 ks][e].
-  // The line-sparse corrected-gradient maps are applied from LDS copies of the
+  // The corrected-gradient maps are applied with MFMA from LDS copies of the
   // element's and its +/-p neighbours' modes, one (value/tangent, p) round at a
-  // time, with the maps themselves held in LDS.
+  // time.
   double Bf[NCBW][KSB];
 #pragma unroll
   for (int i = 0; i < NCBW; ++i) {
@@ -81,10 +78,6 @@ __global__ __launch_bounds__(256) void k_volume_mfma(const double* __restrict__ 
       const int b = g + 4 * ks;
       Bf[i][ks] = (f == 0 && ev && b < NB) ? X[(size_t)(c * NB + b) * ne + e] : 0.0;
     }
-  }
-  for (int it = tid; it < DIM * 3 * NB * KL; it += 256) {
-    sIdx[it] = mt.lIdx[it];
-    sCoef[it] = mt.lCoef[it];
   }
   double* sl = &stage[0][0][0];  // [src][c][b][16]
 #pragma unroll
@@ -107,25 +100,25 @@ __global__ __launch_bounds__(256) void k_volume_mfma(const double* __restrict__ 
         sl[it] = val;
       }
       __syncthreads();
+      // G_p[b][e] = sum_{src, b'} L_src,p[b][b'] X_src[b'][e]: MFMA with rows = modes,
+      // k = (source, mode); the output rows g + 4r (+16 mb) are the B-fragment rows.
 #pragma unroll
       for (int i = s * (NFC / 4); i < (s + 1) * (NFC / 4); ++i) {
         const int fc = wave + 4 * (i % (NFC / 4));
         const int f = fc / NV, c = fc % NV;
         if (f == p + 1) {
 #pragma unroll
-          for (int ks = 0; ks < KSB; ++ks) {
-            const int b = g + 4 * ks;
-            double val = 0.0;
-            if (b < NB) {
+          for (int mb = 0; mb < MB; ++mb) {
+            f64x4 d = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-              for (int src = 0; src < 3; ++src) {
-                const int row = ((p * 3 + src) * NB + b) * KL;
-#pragma unroll
-                for (int k = 0; k < KL; ++k)
-                  val += sCoef[row + k] * sl[((src * NV + c) * NB + sIdx[row + k]) * 16 + col];
-              }
+            for (int ks3 = 0; ks3 < 3 * KSB; ++ks3) {
+              const int src = ks3 / KSB, bp = g + 4 * (ks3 % KSB);
+              const double bv = (bp < NB) ? sl[((src * NV + c) * NB + bp) * 16 + col] : 0.0;
+              d = mfma4(mt.lA[(((size_t)p * MB + mb) * 3 * KSB + ks3) * 64 + lane], bv, d);
             }
-            Bf[i][ks] = val;
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              if (4 * mb + r < KSB) Bf[i][4 * mb + r] = d[r];
           }
         }
       }
@@ -157,13 +150,9 @@ __global__ __launch_bounds__(256) void k_volume_mfma(const double* __restrict__ 
       for (int fc = 0; fc < NFC; ++fc) st[s][fc] = stage[fc][ql][et];
       __syncthreads();
     }
-    // ---- 2b. pointwise volume flux F = F^c - F^v (tangent for Jv)
+    // ---- 2b. pointwise volume flux F = F^c - F^v (tangent for Jv), written to
+    // the stage direction by direction (every read of the stage is complete).
     const int q = 16 * rb + ql;
-    double Fo[DIM][NV];
-#pragma unroll
-    for (int j = 0; j < DIM; ++j)
-#pragma unroll
-      for (int c = 0; c < NV; ++c) Fo[j][c] = 0.0;
     if (q < NQ && e0 + et < ne) {
       T u[NV], G[NV][DIM];
 #pragma unroll
@@ -188,13 +177,14 @@ __global__ __launch_bounds__(256) void k_volume_mfma(const double* __restrict__ 
         conv_flux_dir<T, DIM>(u, vel, pr, j, Fc);
         visc_flux_dir<T, DIM>(vp, j, ph.mu, kap, Fv);
 #pragma unroll
-        for (int c = 0; c < NV; ++c) Fo[j][c] = out_part(Fc[c] - Fv[c]);
+        for (int c = 0; c < NV; ++c) stage[j * NV + c][ql][et] = out_part(Fc[c] - Fv[c]);
       }
+    } else {
+#pragma unroll
+      for (int j = 0; j < DIM; ++j)
+#pragma unroll
+        for (int c = 0; c < NV; ++c) stage[j * NV + c][ql][et] = 0.0;
     }
-#pragma unroll
-    for (int j = 0; j < DIM; ++j)
-#pragma unroll
-      for (int c = 0; c < NV; ++c) stage[j * NV + c][ql][et] = Fo[j][c];
     __syncthreads();
     // ---- 2c. MFMA projection: R[b][e] += -sum_{j,q} w|J| d_j phi(q,b) F_j(q,e)
 #pragma unroll
@@ -351,7 +341,7 @@ DEV void face_mfma_body(const double* __restrict__ U, const double* __restrict__
 }
 
 template <int NB, int NQ1, bool JVP>
-__global__ __launch_bounds__(256) void k_face_mfma(const double* __restrict__ U, const double* __restrict__ V,
+__global__ __launch_bounds__(256, 2) void k_face_mfma(const double* __restrict__ U, const double* __restrict__ V,
                                                    double* __restrict__ H, MTables mt, Mesh m, Phys ph) {
   __shared__ double stage[6 * 5][16][16];
   switch (blockIdx.y) {

@@ -311,7 +311,18 @@ MfmaHost build_mfma_tables(const HostTables& T) {
               v = T.fLift[(((size_t)p * 2 + (left ? 0 : 1)) * nfq + fq) * nb + b];
             M.tA[((((size_t)p * RBF + rbf) * 6 + ch) * 2 * KSB + ks2) * 64 + l] = v;
           }
-  // sparse rows of the modal corrected-gradient maps (nonzeros lie on tensor lines)
+  // modal corrected-gradient maps in A-fragment order, k = (source, mode)
+  M.lA.assign((size_t)dim * MB * 3 * KSB * 64, 0.0);
+  for (int p = 0; p < dim; ++p)
+    for (int mb = 0; mb < MB; ++mb)
+      for (int ks3 = 0; ks3 < 3 * KSB; ++ks3)
+        for (int l = 0; l < 64; ++l) {
+          const int src = ks3 / KSB, b = 16 * mb + (l & 15), bp = (l >> 4) + 4 * (ks3 % KSB);
+          if (b < nb && bp < nb)
+            M.lA[(((size_t)p * MB + mb) * 3 * KSB + ks3) * 64 + l] =
+                T.vLift[(((size_t)p * 3 + src) * nb + b) * nb + bp];
+        }
+  // the maps act along tensor lines: at most p+1 nonzeros per row
   double big = 0.0;
   for (double v : T.vLift) big = std::max(big, std::fabs(v));
   int kl = 0;
@@ -322,19 +333,6 @@ MfmaHost build_mfma_tables(const HostTables& T) {
     kl = std::max(kl, cnt);
   }
   M.kl = kl;
-  M.lIdx.assign((size_t)dim * 3 * nb * kl, 0);
-  M.lCoef.assign((size_t)dim * 3 * nb * kl, 0.0);
-  for (int r = 0; r < dim * 3 * nb; ++r) {
-    int cnt = 0;
-    for (int b = 0; b < nb; ++b) {
-      const double v = T.vLift[(size_t)r * nb + b];
-      if (std::fabs(v) > 1e-14 * big) {
-        M.lIdx[(size_t)r * kl + cnt] = b;
-        M.lCoef[(size_t)r * kl + cnt] = v;
-        ++cnt;
-      }
-    }
-  }
   return M;
 }
 
