@@ -20,7 +20,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "DOFs/s for matrix-free DG Jv (p=3, 3D hex); wall time to 1e-8 FGMRES solve"
-PEAK_FP64 = 78.6  # TFLOP/s, MI355X dense FP64 (vector and matrix)
+PEAK_FP64 = 78.6  # TFLOP/s, MI355X dense FP64 matrix (MFMA) peak
 PEAK_HBM = 8000.0  # GB/s
 
 
@@ -40,15 +40,26 @@ def jv_kernel_flops(ne, nb, nq, nfq, d):
     return {"vol_jvp": (vol + face_proj) * ne, "face_jvp": (face - face_proj) * ne}
 
 
+KERNEL_SOURCES = ("dg_mfma.hip", "dg_device.h")
+
+
+def kernel_source_sha():
+    """sha256[:16] over the sources of the timed Jv kernels (concatenated)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1809_00866_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def measured_traffic(kernel):
     """HBM bytes per launch from the committed rocprofv3 FETCH/WRITE summary, or
-    None when the kernel source changed since the counters were taken."""
-    import hashlib
+    None when the kernel sources changed since the counters were taken."""
     prof = os.path.join(ROOT, "profiles", "jv_p3_32cube_hbm_counters.txt")
-    src = os.path.join(ROOT, "paper_1809_00866_amd", "csrc", "dg_kernels.hip")
     try:
         text = open(prof).read()
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        sha = kernel_source_sha()
     except OSError:
         return None
     if f": {sha}" not in text:
@@ -165,7 +176,7 @@ def main():
     avg = {k: kt[k][0] / max(kt[k][1], 1) for k in kt}
     dom = max(avg, key=avg.get)
     achieved = flops[dom] / (avg[dom] * 1e-3) / 1e12
-    roofline = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": PEAK_FP64, "unit": "TFLOP/s",
+    roofline = {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": PEAK_FP64, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP64, "traffic": measured_traffic(dom), "traffic_unit": "bytes/launch",
                 "kernel_ms": {k: round(avg[k], 4) for k in avg},
                 "flops_per_launch": {k: flops[k] for k in flops}}
@@ -190,6 +201,7 @@ def main():
     if not args.no_solve:
         res["time_to_tol"] = time_to_tolerance("fp64")
         res["time_to_tol_fp32_blocks"] = time_to_tolerance("fp32")
+        res["time_to_tol_bf16_blocks"] = time_to_tolerance("bf16")
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(args.cpu_sample)
     print(json.dumps(res), flush=True)

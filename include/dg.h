@@ -118,7 +118,10 @@ dg_status dg_jvp(dg_context* ctx, const double* w, const double* r_w, const doub
 
 /* EWBJ setup: D_K = shift*I + dR_K/dU_K for every element (exact, by
  * coloured probing with exact Jv), factored by Gauss-Jordan with partial
- * pivoting into explicit inverses, stored as `storage` (DG_FP64 or DG_FP32).
+ * pivoting into explicit inverses, stored as `storage`: DG_FP64 (FP64
+ * elimination), DG_FP32 (FP32 elimination) or DG_BF16 (FP32 elimination,
+ * inverse rounded to BF16; the apply accumulates in FP32).  Reduced precision
+ * only changes the preconditioner, never the FP64 operator of the solve.
  * Returns DG_ERR_SINGULAR_BLOCK if a pivot is exactly zero or non-finite
  * (synchronises the stream). */
 dg_status dg_block_precond_setup(dg_context* ctx, const double* w, double shift, int storage, void* stream);

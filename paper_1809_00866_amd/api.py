@@ -13,7 +13,7 @@ from . import _lib as L
 _FLUX = {"lf": L.DG_FLUX_LF, "roe": L.DG_FLUX_ROE}
 _BASIS = {"P": L.DG_BASIS_PK, "Q": L.DG_BASIS_QK}
 _MODE = {"exact": L.DG_JVP_EXACT, "fd": L.DG_JVP_FD}
-_STORAGE = {"fp64": L.DG_FP64, "fp32": L.DG_FP32}
+_STORAGE = {"fp64": L.DG_FP64, "fp32": L.DG_FP32, "bf16": L.DG_BF16}
 _PREC = {"none": L.DG_PREC_NONE, "bj": L.DG_PREC_BJ}
 
 

@@ -64,6 +64,7 @@ struct dg_context {
   double* d_D64 = nullptr;
   void* d_Dinv = nullptr;
   int blk_storage = -1;
+  size_t dinv_bytes = 0;  // size of a separate (FP32/BF16) inverse buffer
   bool blk_ready = false;
   double* d_V = nullptr;
   double* d_Z = nullptr;
@@ -402,26 +403,33 @@ dg_status dg_jvp(dg_context* c, const double* w, const double* r_w, const double
 
 dg_status dg_block_precond_setup(dg_context* c, const double* w, double shift, int storage, void* stream) {
   if (!c || !w) return fail(DG_ERR_ARG, "null argument");
-  if (storage != DG_FP64 && storage != DG_FP32) return fail(DG_ERR_ARG, "storage must be DG_FP64 or DG_FP32");
+  if (storage != DG_FP64 && storage != DG_FP32 && storage != DG_BF16)
+    return fail(DG_ERR_ARG, "storage must be DG_FP64, DG_FP32 or DG_BF16");
   hipStream_t s = (hipStream_t)stream;
   const int m = c->nv * c->nb;
   if (m > 256) return fail(DG_ERR_ARG, "block size above 256");
   dg_status st;
+  c->blk_ready = false;
   if ((st = dalloc(&c->d_D64, (size_t)c->ne * m * m)) != DG_OK) return st;
-  if (storage == DG_FP32) {
+  if (storage == DG_FP64) {
+    // FP64 inverses overwrite the probed blocks in place
+    if (c->d_Dinv && c->d_Dinv != c->d_D64) dfree(c->d_Dinv);
+    c->d_Dinv = c->d_D64;
+    c->dinv_bytes = 0;
+  } else {
+    const size_t need = (size_t)c->ne * m * m * (storage == DG_FP32 ? sizeof(float) : sizeof(uint16_t));
     if (c->d_Dinv == c->d_D64) c->d_Dinv = nullptr;
-    if (c->blk_storage != DG_FP32 && c->d_Dinv) {
+    if (c->d_Dinv && c->dinv_bytes != need) {
       dfree(c->d_Dinv);
       c->d_Dinv = nullptr;
     }
-    float* f = static_cast<float*>(c->d_Dinv);
-    if ((st = dalloc(&f, (size_t)c->ne * m * m)) != DG_OK) return st;
-    c->d_Dinv = f;
-  } else {
-    if (c->d_Dinv && c->d_Dinv != c->d_D64) dfree(c->d_Dinv);
-    c->d_Dinv = c->d_D64;
+    if (!c->d_Dinv) {
+      unsigned char* f = nullptr;
+      if ((st = dalloc(&f, need)) != DG_OK) return st;
+      c->d_Dinv = f;
+      c->dinv_bytes = need;
+    }
   }
-  c->blk_ready = false;
   {
     ProfScope ps(c, "block_probe", s);
     for (int col = 0; col < c->ncolor; ++col)

@@ -6,8 +6,9 @@
 // elements at a time (no two elements of a class are face neighbours, so the
 // product restricted to K only sees K's own perturbation).  Each block is then
 // inverted in place by Gauss-Jordan elimination with partial (row) pivoting
-// and stored explicitly (column-major, A[j*m + i] = entry (i, j)), in FP64 or
-// FP32, so the apply is a batched matrix-vector product bound by HBM.
+// and stored explicitly (column-major, A[j*m + i] = entry (i, j)), in FP64,
+// FP32 or BF16 (FP32 elimination rounded on store), so the apply is a batched
+// matrix-vector product bound by HBM (FP32 accumulation for FP32/BF16).
 #include "dg_internal.h"
 
 namespace dgk {
@@ -118,10 +119,29 @@ __global__ __launch_bounds__(256) void k_invert_global64(double* __restrict__ D,
   if (threadIdx.x == 0 && bad) info[0] = 1;
 }
 
-// LDS working copy of type S; result written to `out` (type S) or, for
-// FP64 in place, back into D.
-template <class S>
-__global__ __launch_bounds__(256) void k_invert_lds(const double* __restrict__ D, S* __restrict__ out, int m,
+// Storage conversions: FP64/FP32 pass through; BF16 = round-to-nearest-even
+// of the FP32 value (upper 16 bits), kept as raw bits.
+struct bf16_t {
+  unsigned short bits;
+};
+__device__ __forceinline__ void store_as(double& o, double v) { o = v; }
+__device__ __forceinline__ void store_as(float& o, float v) { o = v; }
+__device__ __forceinline__ void store_as(bf16_t& o, float v) {
+  unsigned int u = __float_as_uint(v);
+  if ((u & 0x7f800000u) == 0x7f800000u) {  // Inf / NaN: truncate, keep NaN quiet
+    o.bits = (unsigned short)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+    return;
+  }
+  u += 0x7fffu + ((u >> 16) & 1u);
+  o.bits = (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ double load_as(const double& v) { return v; }
+__device__ __forceinline__ float load_as(const float& v) { return v; }
+__device__ __forceinline__ float load_as(const bf16_t& v) { return __uint_as_float(((unsigned int)v.bits) << 16); }
+
+// LDS working copy of type S; result written to `out` (storage type O).
+template <class S, class O = S>
+__global__ __launch_bounds__(256) void k_invert_lds(const double* __restrict__ D, O* __restrict__ out, int m,
                                                     int* __restrict__ info) {
   extern __shared__ __align__(16) unsigned char smem[];
   S* A = reinterpret_cast<S*>(smem);
@@ -133,13 +153,14 @@ __global__ __launch_bounds__(256) void k_invert_lds(const double* __restrict__ D
   for (size_t i = threadIdx.x; i < (size_t)m * m; i += 256) A[i] = (S)Dg[i];
   __syncthreads();
   gauss_jordan<S>(A, m, colk, rowk, ipiv, rv, ri, &bad);
-  S* O = out + (size_t)blockIdx.x * m * m;
-  for (size_t i = threadIdx.x; i < (size_t)m * m; i += 256) O[i] = A[i];
+  O* Ob = out + (size_t)blockIdx.x * m * m;
+  for (size_t i = threadIdx.x; i < (size_t)m * m; i += 256) store_as(Ob[i], A[i]);
   if (threadIdx.x == 0 && bad) info[0] = 1;
 }
 
 // z_K = Dinv_K r_K; 64 lanes over rows, 4 waves over column quarters.
-template <class S>
+// ACC is the accumulation type (FP64 for FP64 factors, FP32 for FP32/BF16).
+template <class S, class ACC>
 __global__ __launch_bounds__(256) void k_apply(const S* __restrict__ Dinv, int m, int64_t ne,
                                                const double* __restrict__ r, double* __restrict__ z) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -152,10 +173,10 @@ __global__ __launch_bounds__(256) void k_apply(const S* __restrict__ Dinv, int m
   const S* A = Dinv + (size_t)e * m * m;
   for (int i0 = 0; i0 < m; i0 += 64) {
     const int i = i0 + lane;
-    double a = 0.0;
+    ACC a = 0;
     if (i < m)
-      for (int j = w; j < m; j += 4) a += (double)A[(size_t)j * m + i] * rk[j];
-    if (i < m) part[w * m + i] = a;
+      for (int j = w; j < m; j += 4) a += (ACC)load_as(A[(size_t)j * m + i]) * (ACC)rk[j];
+    if (i < m) part[w * m + i] = (double)a;
   }
   __syncthreads();
   for (int i = threadIdx.x; i < m; i += 256)
@@ -200,11 +221,18 @@ hipError_t launch_block_invert(int storage, double* D64, void* Dout, int m, int6
     }
     return hipGetLastError();
   }
-  if (storage == DG_FP32) {
+  if (storage == DG_FP32 || storage == DG_BF16) {
+    // FP32 Gauss-Jordan in LDS; BF16 storage rounds the FP32 inverse
     const size_t need = (size_t)m * m * sizeof(float);
     if (need + static_lds > kMaxLds) return hipErrorInvalidValue;
-    hipFuncSetAttribute((const void*)k_invert_lds<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)need);
-    k_invert_lds<float><<<(unsigned)ne, 256, need, s>>>(D64, static_cast<float*>(Dout), m, info);
+    if (storage == DG_FP32) {
+      hipFuncSetAttribute((const void*)k_invert_lds<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)need);
+      k_invert_lds<float><<<(unsigned)ne, 256, need, s>>>(D64, static_cast<float*>(Dout), m, info);
+    } else {
+      hipFuncSetAttribute((const void*)k_invert_lds<float, bf16_t>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)need);
+      k_invert_lds<float, bf16_t><<<(unsigned)ne, 256, need, s>>>(D64, static_cast<bf16_t*>(Dout), m, info);
+    }
     return hipGetLastError();
   }
   return hipErrorInvalidValue;
@@ -214,9 +242,11 @@ hipError_t launch_block_apply(int storage, const void* Dinv, int m, int64_t ne, 
                               hipStream_t s) {
   const size_t lds = (size_t)5 * m * sizeof(double);
   if (storage == DG_FP64)
-    k_apply<double><<<(unsigned)ne, 256, lds, s>>>(static_cast<const double*>(Dinv), m, ne, r, z);
+    k_apply<double, double><<<(unsigned)ne, 256, lds, s>>>(static_cast<const double*>(Dinv), m, ne, r, z);
   else if (storage == DG_FP32)
-    k_apply<float><<<(unsigned)ne, 256, lds, s>>>(static_cast<const float*>(Dinv), m, ne, r, z);
+    k_apply<float, float><<<(unsigned)ne, 256, lds, s>>>(static_cast<const float*>(Dinv), m, ne, r, z);
+  else if (storage == DG_BF16)
+    k_apply<bf16_t, float><<<(unsigned)ne, 256, lds, s>>>(static_cast<const bf16_t*>(Dinv), m, ne, r, z);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

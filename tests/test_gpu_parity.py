@@ -2,7 +2,8 @@
 
 Tolerances (relative 2-norms): residual 1e-12 of max(|R|, |R_volume|), exact
 Jv 1e-12, FD Jv 1e-6 (the FD quotient amplifies round-off by 1/Delta),
-projection 1e-13, block apply 1e-11 (FP64) / 1e-4 (FP32 factors), solves
+projection 1e-13, block apply 1e-11 (FP64) / 1e-4 (FP32 factors) / the
+entrywise BF16 rounding bound 2^-8 |D^-1||r| (BF16 factors), solves
 checked on the true residual with the oracle operator.
 """
 import sys
@@ -122,6 +123,15 @@ def test_block_jacobi_parity(N, k, sp, nq, flux):
         g.block_setup(w, shift, storage="fp32")
         z_g32 = g.block_apply(rt).cpu().numpy()
         assert rel(z_g32, o.to_flat(z_o)) <= 1e-4
+        # BF16 factors: every stored entry of D^-1 carries a relative rounding
+        # error <= 2^-9, so |z - z_exact| <= 2^-9 |D^-1| |r| entrywise, plus the
+        # FP32 elimination and accumulation error (well below 2^-9 here).
+        g.block_setup(w, shift, storage="bf16")
+        z_b = o.from_flat(g.block_apply(rt).cpu().numpy()).reshape(o.ne, -1)
+        Dinv = np.linalg.inv(D)
+        bound = np.einsum("eij,ej->ei", np.abs(Dinv), np.abs(r.reshape(o.ne, -1)))
+        err = np.abs(z_b - z_o.reshape(o.ne, -1))
+        assert np.all(err <= 2.0 ** -8 * bound + 1e-12), (err / bound).max()
 
 
 def test_block_apply_before_setup_is_state_error():
@@ -143,6 +153,26 @@ def test_fgmres_true_residual_with_oracle_operator(precond):
         g.block_setup(w, shift)
     x, st = g.fgmres(w, shift, b, restart=30, rtol=1e-10, max_iter=2000, precond=precond)
     assert st["converged"] == 1 and st["rel_res_true"] <= 1e-10
+    X = o.from_flat(x.cpu().numpy())
+    res = np.linalg.norm(o.to_flat(o.operator(U, X, shift)) - o.to_flat(B)) / np.linalg.norm(B)
+    assert res <= 1e-9
+
+
+@pytest.mark.parametrize("storage", ["fp32", "bf16"])
+def test_fgmres_reduced_precision_blocks_reach_fp64_tolerance(storage):
+    """Reduced-precision block factors change only the preconditioner: the FP64
+    flexible outer iteration still reaches 1e-10 on the true residual."""
+    _say(f"fgmres {storage} blocks")
+    o, g, U, w = make_case((3, 3, 3), 2, "P", 3)
+    shift = 40.0
+    B = np.random.default_rng(5).standard_normal(U.shape)
+    b = torch.tensor(o.to_flat(B), device="cuda")
+    g.block_setup(w, shift, storage="fp64")
+    _, st64 = g.fgmres(w, shift, b, restart=30, rtol=1e-10, max_iter=2000, precond="bj")
+    g.block_setup(w, shift, storage=storage)
+    x, st = g.fgmres(w, shift, b, restart=30, rtol=1e-10, max_iter=2000, precond="bj")
+    assert st["converged"] == 1 and st["rel_res_true"] <= 1e-10
+    assert st["iters"] <= st64["iters"] + 10
     X = o.from_flat(x.cpu().numpy())
     res = np.linalg.norm(o.to_flat(o.operator(U, X, shift)) - o.to_flat(B)) / np.linalg.norm(B)
     assert res <= 1e-9
