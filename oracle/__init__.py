@@ -19,7 +19,9 @@ The oracle follows the paper's statement of the discretisation:
   the finite-difference form of eqs. (matrix-free)/(epsdef) (Sec. 2.3);
 * the global operator G = M/(gamma*dt) + J of eq. (rosSysOp) with M = I;
 * element-wise block Jacobi = LU of the diagonal blocks (Sec. 2.3, EWBJ);
-* flexible GMRES with right preconditioning (Sec. 2.5).
+* flexible GMRES with right preconditioning (Sec. 2.5);
+* the p-multigrid V-cycle with inherited coarse operators and GMRES[EWBJ]
+  smoothers (Sec. 2.4, Alg. vcic, eq. GalProj) in ``oracle.pmg``.
 
 Compressible Navier-Stokes fluxes (perfect gas, Stokes stress as in the
 paper's viscous flux, Fourier heat flux, Lax-Friedrichs or Roe convective

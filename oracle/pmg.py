@@ -1,0 +1,148 @@
+"""p-multigrid V-cycle preconditioner (Sec. 2.4) -- FP64 oracle.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+Levels l = 0 (fine, degree k_0), 1, ..., L (coarsest), k_0 > k_1 > ... > k_L.
+With the hierarchical orthonormal modal basis of the fine discretisation
+(Sec. 2.4.1, 2.4.2):
+
+* restriction I_l^{l+1} (the L2 projection onto P^{k_{l+1}}) keeps the first
+  N_b(k_{l+1}) modes of every variable and discards the rest;
+* prolongation I_{l+1}^l (the injection) pads the missing modes with zeros;
+* the inherited coarse operator G_l = I_0^l G_0 I_l^0 (eq. GalProj; the
+  projection matrices are unit-diagonal rectangular) keeps the leading
+  sub-block of every diagonal and off-diagonal block of the fine operator;
+  it is formed here column by column from the fine operator itself;
+* SMOOTH(G_l, g, x0) is a fixed number of GMRES iterations (one cycle, no
+  restart), right-preconditioned by element-wise block Jacobi of G_l; the
+  coarsest-level SOLVE is the same smoother from x0 = 0 with its own count;
+* Alg. vcic: pre-smoothing, coarse-grid correction of the defect,
+  post-smoothing; called on the fine level with a zero initial guess, it is
+  the (nonlinear, hence flexible-GMRES) preconditioner of the outer solve.
+
+Arrays use the oracle layout X[e, c, b]; level l has N_b(k_l) modes.
+"""
+import numpy as np
+
+from .basis import basis_size
+from .solvers import block_solve
+
+
+def restrict(X, nb_coarse):
+    """Keep the first nb_coarse modes of every variable (L2 projection)."""
+    return np.ascontiguousarray(X[..., :nb_coarse])
+
+
+def prolong(Xc, nb_fine):
+    """Zero-pad the modes above Xc's degree (injection)."""
+    out = np.zeros(Xc.shape[:-1] + (nb_fine,), dtype=Xc.dtype)
+    out[..., :Xc.shape[-1]] = Xc
+    return out
+
+
+def inherited_matrix(o, U, shift, nb_coarse):
+    """Dense G_l = R G_0 P for the level with nb_coarse modes, in the flat
+    order of X[e, c, b].reshape(-1).  Column j is the fine operator applied to
+    the zero-padded j-th coarse unit vector, restricted to the coarse modes."""
+    mc = o.nvar * nb_coarse
+    n = o.ne * mc
+    A = np.zeros((n, n))
+    for col in range(n):
+        e, l = divmod(col, mc)
+        c, b = divmod(l, nb_coarse)
+        V = np.zeros(U.shape)
+        V[e, c, b] = 1.0
+        A[:, col] = restrict(o.operator(U, V, shift), nb_coarse).reshape(-1)
+    return A
+
+
+def diagonal_blocks(A, ne, m):
+    """Diagonal m x m blocks of a dense element-major matrix, [ne, m, m]."""
+    return np.stack([A[e * m:(e + 1) * m, e * m:(e + 1) * m] for e in range(ne)])
+
+
+def gmres_fixed(apply_A, apply_Minv, g, x0, iters, breakdown_tol=1e-14):
+    """x0 + M^-1 V_k y with y minimising ||g - A(x0 + M^-1 V_k y)||: k = iters
+    GMRES steps on A M^-1 (one cycle, no restart), Arnoldi by classical
+    Gram-Schmidt with one re-orthogonalisation.  Stops early only on a happy
+    breakdown (||w|| <= breakdown_tol ||A M^-1 v_j||).  Flat vectors."""
+    x0 = np.zeros_like(g) if x0 is None else x0
+    r = g - apply_A(x0) if np.any(x0) else g.copy()
+    beta = np.linalg.norm(r)
+    if beta == 0.0 or iters == 0:
+        return x0.copy()
+    V = [r / beta]
+    H = np.zeros((iters + 1, iters))
+    k = 0
+    for j in range(iters):
+        w = apply_A(apply_Minv(V[j]))
+        w0 = np.linalg.norm(w)
+        B = np.array(V)
+        h = B @ w
+        w = w - B.T @ h
+        h2 = B @ w
+        w = w - B.T @ h2
+        hn = np.linalg.norm(w)
+        H[:j + 1, j] = h + h2
+        H[j + 1, j] = hn
+        k = j + 1
+        if hn <= breakdown_tol * w0:
+            break
+        V.append(w / hn)
+    rhs = np.zeros(k + 1)
+    rhs[0] = beta
+    y = np.linalg.lstsq(H[:k + 1, :k], rhs, rcond=None)[0]
+    return x0 + apply_Minv(np.array(V[:k]).T @ y)
+
+
+class PMultigrid:
+    """Alg. vcic with inherited operators and GMRES[EWBJ] smoothers.
+
+    orders: degrees k_0 > ... > k_L (k_0 = o.order); iters: smoothing
+    iterations per level, the last one being the coarsest-level solve.
+    """
+
+    def __init__(self, o, U, shift, orders, iters):
+        assert orders[0] == o.order and all(a > b for a, b in zip(orders, orders[1:]))
+        assert len(iters) == len(orders)
+        self.o, self.U, self.shift = o, U, float(shift)
+        self.iters = list(iters)
+        self.nbs = [basis_size(k, o.d) for k in orders]
+        self.L = len(orders) - 1
+        self.A = [None] + [inherited_matrix(o, U, shift, nb) for nb in self.nbs[1:]]
+        self.D = [o.block_diagonal(U, shift)] + [
+            diagonal_blocks(self.A[l], o.ne, o.nvar * self.nbs[l]) for l in range(1, self.L + 1)]
+
+    # level operators on flat vectors of X[e, c, b] with N_b(k_l) modes
+    def _shape(self, l):
+        return (self.o.ne, self.o.nvar, self.nbs[l])
+
+    def apply_G(self, l, x):
+        if l == 0:
+            return self.o.operator(self.U, x.reshape(self._shape(0)), self.shift).reshape(-1)
+        return self.A[l] @ x
+
+    def apply_Minv(self, l, x):
+        return block_solve(self.D[l], x.reshape(self.o.ne, -1)).reshape(-1)
+
+    def smooth(self, l, g, x0):
+        return gmres_fixed(lambda v: self.apply_G(l, v), lambda v: self.apply_Minv(l, v), g, x0, self.iters[l])
+
+    def vcycle(self, l, g, trace=None):
+        """MG_V(l, g, 0) on flat level-l vectors.  `trace` (a dict, optional)
+        receives the level-l iterates after pre-smoothing and after the
+        coarse-grid correction."""
+        if l == self.L:
+            return self.smooth(l, g, None)
+        w = self.smooth(l, g, None)                                       # pre-smoothing
+        d = g - self.apply_G(l, w)                                        # defect
+        dc = restrict(d.reshape(self._shape(l)), self.nbs[l + 1]).reshape(-1)
+        e = self.vcycle(l + 1, dc)                                        # coarse-grid correction
+        w_hat = w + prolong(e.reshape(self._shape(l + 1)), self.nbs[l]).reshape(-1)
+        if trace is not None:
+            trace[l] = (w, w_hat)
+        return self.smooth(l, g, w_hat)                                   # post-smoothing
+
+    def apply(self, R):
+        """The preconditioner: Z = MG_V(0, R, 0) for R[e, c, b] on the fine level."""
+        return self.vcycle(0, np.asarray(R, dtype=np.float64).reshape(-1)).reshape(self._shape(0))

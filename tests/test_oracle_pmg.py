@@ -1,0 +1,172 @@
+"""Pins for the oracle's p-multigrid V-cycle (Sec. 2.4, Alg. vcic, eq. GalProj).
+
+Each pin checks the oracle against something other than itself: the coarse
+discretisation built independently at the lower degree, the colour-probed
+sparse Jacobian, dense linear algebra, and least squares over an explicitly
+built Krylov power basis.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import DGOracle, NavierStokes, block_solve
+from oracle.mms import sparse_jacobian
+from oracle.pmg import (PMultigrid, diagonal_blocks, gmres_fixed, inherited_matrix, prolong,
+                        restrict)
+
+
+def _state(N, order, nq, mu=1e-2, seed=4, coarse_nb=None):
+    mesh = synth.lattice_mesh(N, L=1.0)
+    o = DGOracle(mesh, order, "P", nq, NavierStokes(3, mu=mu))
+    U = o.project(synth.TaylorGreenStandIn(seed=seed, L=1.0))
+    U = U + 1e-2 * np.random.default_rng(seed).standard_normal(U.shape) * np.abs(U[:, :, :1])
+    if coarse_nb is not None:  # a state that lies in the coarse space
+        U = prolong(restrict(U, coarse_nb), o.nb)
+    return mesh, o, U
+
+
+def _dense(o, U, shift):
+    n = U.size
+    A = np.zeros((n, n))
+    for j in range(n):
+        V = np.zeros(n)
+        V[j] = 1.0
+        A[:, j] = o.operator(U, V.reshape(U.shape), shift).reshape(-1)
+    return A
+
+
+def test_restriction_is_l2_projection_and_prolongation_its_right_inverse():
+    """Keeping the low modes equals the L2 projection onto the coarse space built
+    from the degree-1 basis of its own discretisation; R P = I."""
+    mesh, o, U = _state((2, 2, 1), 3, 4)
+    oc = DGOracle(mesh, 1, "P", 4, NavierStokes(3))
+    et_f = o.elem_tables(np.arange(o.ne))
+    et_c = oc.elem_tables(np.arange(o.ne))
+    vals = np.einsum("eqb,ecb->eqc", et_f["phi"], U)            # the fine polynomial at the points
+    proj = np.einsum("eq,eqc,eqb->ecb", et_c["wdet"], vals, et_c["phi"])
+    assert np.abs(restrict(U, oc.nb) - proj).max() <= 1e-13 * np.abs(U).max()
+    Xc = np.random.default_rng(0).standard_normal((o.ne, o.nvar, oc.nb))
+    assert np.array_equal(restrict(prolong(Xc, o.nb), oc.nb), Xc)
+
+
+@pytest.mark.parametrize("mu,equal", [(0.0, True), (5e-2, False)], ids=["inviscid", "viscous"])
+def test_inherited_vs_rediscretised_coarse_operator(mu, equal):
+    """Inherited and non-inherited coarse Jacobians coincide for the inviscid part
+    and differ through the lifting operators for the viscous part (Sec. 2.4.2)."""
+    shift = 3.0
+    mesh, o, U = _state((1, 1, 2), 2, 3, mu=mu, coarse_nb=4)
+    A_inh = inherited_matrix(o, U, shift, 4)
+    oc = DGOracle(mesh, 1, "P", 3, NavierStokes(3, mu=mu))
+    A_re = _dense(oc, restrict(U, 4), shift)
+    diff = np.abs(A_inh - A_re).max() / np.abs(A_re).max()
+    if equal:
+        assert diff <= 1e-12, diff
+    else:
+        assert diff >= 1e-4, diff
+
+
+def test_inherited_operator_matches_colour_probed_jacobian_and_nests():
+    """G_1 = sub-matrix of the colour-probed assembled Jacobian; G_2 = leading
+    sub-blocks of G_1 (eq. GalProj applied recursively)."""
+    shift = 7.0
+    mesh, o, U = _state((1, 2, 2), 2, 3)
+    J = sparse_jacobian(o, U, shift).toarray()
+    m = o.nvar * o.nb
+
+    def idx(nbc):
+        return np.array([e * m + c * o.nb + b for e in range(o.ne) for c in range(o.nvar) for b in range(nbc)])
+
+    A1 = inherited_matrix(o, U, shift, 4)
+    i1 = idx(4)
+    assert np.abs(A1 - J[np.ix_(i1, i1)]).max() <= 1e-12 * np.abs(A1).max()
+    A0 = inherited_matrix(o, U, shift, 1)
+    m1 = o.nvar * 4
+    i01 = np.array([e * m1 + c * 4 for e in range(o.ne) for c in range(o.nvar)])
+    assert np.abs(A0 - A1[np.ix_(i01, i01)]).max() <= 1e-13 * np.abs(A0).max()
+    D = diagonal_blocks(A1, o.ne, m1)
+    for e in range(o.ne):
+        assert np.array_equal(D[e], A1[e * m1:(e + 1) * m1, e * m1:(e + 1) * m1])
+
+
+def test_fixed_gmres_is_the_minimal_residual_over_the_krylov_space():
+    """Compare with least squares over the explicit power basis of K_k(A M^-1, r0)."""
+    rng = np.random.default_rng(2)
+    n = 40
+    A = np.eye(n) * 4 + rng.standard_normal((n, n)) / np.sqrt(n)
+    Mi = np.diag(1.0 / np.diag(A))
+    g = rng.standard_normal(n)
+    x0 = rng.standard_normal(n)
+    for k in (1, 3, 5):
+        x = gmres_fixed(lambda v: A @ v, lambda v: Mi @ v, g, x0, k)
+        r0 = g - A @ x0
+        P = [r0]
+        for _ in range(k - 1):
+            P.append(A @ (Mi @ P[-1]))
+        P = np.array(P).T
+        y = np.linalg.lstsq(A @ Mi @ P, r0, rcond=None)[0]
+        xr = x0 + Mi @ P @ y
+        assert np.linalg.norm(x - xr) <= 1e-9 * np.linalg.norm(xr)
+    assert np.array_equal(gmres_fixed(lambda v: A @ v, lambda v: v, g, x0, 0), x0)
+
+
+def test_fixed_gmres_with_full_dimension_solves_exactly():
+    mesh, o, U = _state((1, 1, 1), 1, 2)
+    shift = 5.0
+    A = _dense(o, U, shift)
+    D = o.block_diagonal(U, shift)
+    g = np.random.default_rng(3).standard_normal(A.shape[0])
+    x = gmres_fixed(lambda v: A @ v, lambda v: block_solve(D, v.reshape(o.ne, -1)).reshape(-1), g, None,
+                    A.shape[0])
+    assert np.linalg.norm(x - np.linalg.solve(A, g)) <= 1e-9 * np.linalg.norm(x)
+
+
+def test_two_grid_without_smoothing_is_the_coarse_galerkin_solve():
+    """With no fine smoothing and an exact coarsest solve, Alg. vcic returns
+    P (R G P)^-1 R g, with R G P solved by dense LU."""
+    mesh, o, U = _state((1, 1, 2), 2, 3)
+    shift = 4.0
+    nc = o.ne * o.nvar * 4
+    mg = PMultigrid(o, U, shift, orders=(2, 1), iters=(0, nc))
+    R = np.random.default_rng(5).standard_normal(U.shape)
+    z = mg.apply(R)
+    A1 = inherited_matrix(o, U, shift, 4)
+    zc = np.linalg.solve(A1, restrict(R, 4).reshape(-1)).reshape(o.ne, o.nvar, 4)
+    assert np.linalg.norm(z - prolong(zc, o.nb)) <= 1e-9 * np.linalg.norm(zc)
+
+
+def test_coarse_correction_annihilates_the_restricted_defect():
+    """With an exact coarsest solve the Galerkin correction makes the restricted
+    defect vanish: R(g - G w_hat) = R d - (R G P) e = 0.  Pre-smoothing and
+    post-smoothing each reduce the residual (GMRES minimises it over a space
+    that contains the starting point; strictly, unless it stagnates)."""
+    mesh, o, U = _state((1, 1, 2), 2, 3)
+    shift = 4.0
+    nc = o.ne * o.nvar * 4
+    mg = PMultigrid(o, U, shift, orders=(2, 1), iters=(2, nc))
+    g = np.random.default_rng(8).standard_normal(U.size)
+    tr = {}
+    z = mg.vcycle(0, g, trace=tr)
+    w, w_hat = tr[0]
+    res = lambda x: g - mg.apply_G(0, x)
+    rd = restrict(res(w_hat).reshape(U.shape), 4)
+    assert np.linalg.norm(rd) <= 1e-10 * np.linalg.norm(g)
+    assert np.linalg.norm(res(w)) < np.linalg.norm(g)
+    assert np.linalg.norm(res(z)) < np.linalg.norm(res(w_hat))
+
+
+@pytest.mark.slow
+def test_mg_preconditioned_fgmres_beats_block_jacobi():
+    from oracle import fgmres
+    mesh, o, U = _state((3, 3, 2), 2, 3)
+    shift = 2.0
+    mg = PMultigrid(o, U, shift, orders=(2, 1, 0), iters=(4, 4, 20))
+    D = mg.D[0]
+    B = np.random.default_rng(6).standard_normal(U.shape).reshape(-1)
+    A = lambda v: o.operator(U, v.reshape(U.shape), shift).reshape(-1)
+    _, i_bj = fgmres(A, B, apply_M=lambda v: block_solve(D, v.reshape(o.ne, -1)).reshape(-1), rtol=1e-10,
+                     max_iter=600)
+    x, i_mg = fgmres(A, B, apply_M=lambda v: mg.apply(v.reshape(U.shape)).reshape(-1), rtol=1e-10,
+                     max_iter=600)
+    assert i_mg["converged"] and i_bj["converged"]
+    assert np.linalg.norm(A(x) - B) <= 1e-10 * np.linalg.norm(B) * 1.01
+    assert i_mg["iters"] < i_bj["iters"]
