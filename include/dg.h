@@ -14,6 +14,9 @@
  *   dg_block_precond_apply  LU of the diagonal blocks of G = shift*I + J
  *   dg_fgmres_solve         flexible GMRES (Sec. 2.5) on G dw = b,
  *                           eq. (rosSysOp) with M = I (orthonormal basis)
+ *   dg_mg_setup             p-multigrid V-cycle preconditioner (Sec. 2.4,
+ *   dg_mg_apply             Alg. vcic) with inherited coarse operators
+ *                           (eq. GalProj) and GMRES[EWBJ] smoothers
  *
  * Conventions (all entry points):
  *  - Every vector is FP64, device memory, caller-owned, contiguous, in the
@@ -55,7 +58,7 @@ enum { DG_BASIS_PK = 0, DG_BASIS_QK = 1 };          /* total degree / tensor deg
 enum { DG_FLUX_LF = 0, DG_FLUX_ROE = 1 };           /* convective numerical flux */
 enum { DG_JVP_EXACT = 0, DG_JVP_FD = 1 };           /* Jv mode */
 enum { DG_FP64 = 0, DG_FP32 = 1, DG_BF16 = 2 };     /* block-factor storage */
-enum { DG_PREC_NONE = 0, DG_PREC_BJ = 1 };          /* FGMRES preconditioner */
+enum { DG_PREC_NONE = 0, DG_PREC_BJ = 1, DG_PREC_MG = 2 };  /* FGMRES preconditioner */
 
 /* Discretisation parameters.
  *  dim 2 or 3; order k >= 0; basis DG_BASIS_PK (paper's total-degree space,
@@ -134,7 +137,8 @@ typedef struct {
   int restart;     /* Krylov subspace size m (default 30) */
   int max_iter;    /* total iteration cap */
   double rtol;     /* ||b - G x|| <= rtol*||b|| on the true residual */
-  int precond;     /* DG_PREC_NONE or DG_PREC_BJ (block setup must exist) */
+  int precond;     /* DG_PREC_NONE, DG_PREC_BJ (block setup must exist) or
+                      DG_PREC_MG (dg_mg_setup must exist, built with the same w, shift) */
   int jvp_mode;    /* DG_JVP_EXACT or DG_JVP_FD for G z */
 } dg_solve_opts;
 
@@ -152,13 +156,54 @@ typedef struct {
 dg_status dg_fgmres_solve(dg_context* ctx, const double* w, double shift, const double* b, double* x,
                           const dg_solve_opts* opts, dg_solve_stats* stats, void* stream);
 
+/* p-multigrid preconditioner (Sec. 2.4): levels l = 0..n_levels-1 of degrees
+ * orders[0] (= the context's order) > orders[1] > ...; level vectors use the
+ * DOF layout with N_b(orders[l]) modes.  Restriction keeps the first
+ * N_b(orders[l+1]) modes of every variable, prolongation pads with zeros
+ * (Sec. 2.4.1, hierarchical orthonormal basis).  Level 0 applies
+ * G_0 = shift*I + J(w) matrix-free; coarse levels apply the inherited
+ * operators G_l = R G_0 P (eq. GalProj), stored block-sparse (diagonal block
+ * plus one block per face neighbour, FP64) after probing G_0 with a
+ * distance-2 colouring of the elements.  Every level is smoothed by
+ * smooth_iters[l] right-preconditioned GMRES steps (one cycle, block Jacobi of
+ * the level operator, factors stored as `storage`); the last entry is the
+ * coarsest-level solve.  One apply is Alg. vcic from a zero initial guess. */
+typedef struct {
+  int n_levels;         /* 2 or 3, the fine level included */
+  int orders[3];        /* strictly decreasing, >= 0, orders[0] = context order */
+  int smooth_iters[3];  /* 0..60 each; the coarsest level needs >= 1 */
+  int storage;          /* block-factor storage on every level: DG_FP64/FP32/BF16 */
+  int use_graph;        /* nonzero: capture one V-cycle into a hipGraph at setup;
+                           every apply replays it on a library stream ordered
+                           against the caller's stream by events */
+} dg_mg_opts;
+
+/* Builds the hierarchy at state w (device, copied) and shift: runs the fine
+ * block-Jacobi setup (as dg_block_precond_setup with opts->storage, which
+ * replaces any earlier block setup), probes the first coarse level, truncates
+ * deeper ones, factors every level's diagonal blocks, autotunes the coarse
+ * operator kernels and optionally captures the graph.  Basis DG_BASIS_PK only.
+ * Synchronises the stream.  A later dg_block_precond_setup invalidates the
+ * hierarchy (apply then returns DG_ERR_STATE). */
+dg_status dg_mg_setup(dg_context* ctx, const double* w, double shift, const dg_mg_opts* opts, void* stream);
+
+/* z = MG_V(0, r, 0): one V-cycle on the fine level (r, z: device DOF vectors,
+ * no aliasing).  The cycle is nonlinear in r (GMRES smoothers), hence the
+ * flexible outer solver. */
+dg_status dg_mg_apply(dg_context* ctx, const double* r, double* z, void* stream);
+
+/* y = G_l x on level l (0 = fine, matrix-free; >= 1 = inherited block-sparse
+ * operator), vectors in level l's DOF layout. */
+dg_status dg_mg_level_apply(dg_context* ctx, int level, const double* x, double* y, void* stream);
+
 /* max over volume points of |u| + c, returned to host memory (synchronises). */
 dg_status dg_max_wave_speed(dg_context* ctx, const double* w, double* out, void* stream);
 
 /* Per-kernel timing: when enabled, the library records HIP events around
  * each launch on the launch stream; dg_kernel_time returns the accumulated
  * milliseconds and launch count of a named kernel ("face_jvp", "vol_jvp",
- * "face_res", "vol_res", "block_apply", ...) and resets it.  Synchronises. */
+ * "face_res", "vol_res", "block_probe", "block_invert", "block_apply",
+ * "arnoldi", "mg_probe", "mg_vcycle") and resets it.  Synchronises. */
 dg_status dg_set_profiling(dg_context* ctx, int on);
 dg_status dg_kernel_time(dg_context* ctx, const char* name, double* ms, int64_t* launches);
 

@@ -15,12 +15,12 @@ DG_BASIS_PK, DG_BASIS_QK = 0, 1
 DG_FLUX_LF, DG_FLUX_ROE = 0, 1
 DG_JVP_EXACT, DG_JVP_FD = 0, 1
 DG_FP64, DG_FP32, DG_BF16 = 0, 1, 2
-DG_PREC_NONE, DG_PREC_BJ = 0, 1
+DG_PREC_NONE, DG_PREC_BJ, DG_PREC_MG = 0, 1, 2
 
 EXPORTED = ["dg_create", "dg_destroy", "dg_ndof", "dg_nbasis", "dg_nvar", "dg_nq", "dg_volume_points",
             "dg_project", "dg_residual", "dg_jvp", "dg_block_precond_setup", "dg_block_precond_apply",
-            "dg_fgmres_solve", "dg_max_wave_speed", "dg_set_profiling", "dg_kernel_time", "dg_last_error",
-            "dg_sync"]
+            "dg_fgmres_solve", "dg_mg_setup", "dg_mg_apply", "dg_mg_level_apply", "dg_max_wave_speed",
+            "dg_set_profiling", "dg_kernel_time", "dg_last_error", "dg_sync"]
 
 
 class DGParams(ctypes.Structure):
@@ -37,6 +37,11 @@ class DGMesh(ctypes.Structure):
 class SolveOpts(ctypes.Structure):
     _fields_ = [("restart", ctypes.c_int), ("max_iter", ctypes.c_int), ("rtol", ctypes.c_double),
                 ("precond", ctypes.c_int), ("jvp_mode", ctypes.c_int)]
+
+
+class MgOpts(ctypes.Structure):
+    _fields_ = [("n_levels", ctypes.c_int), ("orders", ctypes.c_int * 3), ("smooth_iters", ctypes.c_int * 3),
+                ("storage", ctypes.c_int), ("use_graph", ctypes.c_int)]
 
 
 class SolveStats(ctypes.Structure):
@@ -72,6 +77,9 @@ def load():
         "dg_block_precond_setup": (i, [ctx, vp, d, i, vp]),
         "dg_block_precond_apply": (i, [ctx, vp, vp, vp]),
         "dg_fgmres_solve": (i, [ctx, vp, d, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats), vp]),
+        "dg_mg_setup": (i, [ctx, vp, d, ctypes.POINTER(MgOpts), vp]),
+        "dg_mg_apply": (i, [ctx, vp, vp, vp]),
+        "dg_mg_level_apply": (i, [ctx, i, vp, vp, vp]),
         "dg_max_wave_speed": (i, [ctx, vp, ctypes.POINTER(ctypes.c_double), vp]),
         "dg_set_profiling": (i, [ctx, i]),
         "dg_kernel_time": (i, [ctx, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),

@@ -4,6 +4,7 @@ Every numerical step runs in libdg.so; this module only checks tensor
 shapes/dtypes/devices and passes raw pointers plus the current HIP stream.
 """
 import ctypes
+import math
 
 import numpy as np
 import torch
@@ -14,7 +15,7 @@ _FLUX = {"lf": L.DG_FLUX_LF, "roe": L.DG_FLUX_ROE}
 _BASIS = {"P": L.DG_BASIS_PK, "Q": L.DG_BASIS_QK}
 _MODE = {"exact": L.DG_JVP_EXACT, "fd": L.DG_JVP_FD}
 _STORAGE = {"fp64": L.DG_FP64, "fp32": L.DG_FP32, "bf16": L.DG_BF16}
-_PREC = {"none": L.DG_PREC_NONE, "bj": L.DG_PREC_BJ}
+_PREC = {"none": L.DG_PREC_NONE, "bj": L.DG_PREC_BJ, "mg": L.DG_PREC_MG}
 
 
 def _stream():
@@ -23,6 +24,10 @@ def _stream():
 
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _nb(k, d):
+    return math.comb(k + d, d)
 
 
 class DG:
@@ -120,6 +125,33 @@ class DG:
         out = self.empty() if out is None else self._vec(out, "out")
         L.check(self.lib.dg_block_precond_apply(self.ctx, _ptr(r), _ptr(out), _stream()), "dg_block_precond_apply")
         return out
+
+    def mg_setup(self, w, shift, orders, smooth_iters, storage="fp64", use_graph=True):
+        """p-multigrid hierarchy at (w, shift); orders[0] must be the context's order."""
+        self._vec(w, "w")
+        orders, smooth_iters = list(orders), list(smooth_iters)
+        if not (2 <= len(orders) <= 3) or len(smooth_iters) != len(orders):
+            raise ValueError("need 2 or 3 levels and one smoothing count per level")
+        o = L.MgOpts(len(orders), (ctypes.c_int * 3)(*(orders + [0] * (3 - len(orders)))),
+                     (ctypes.c_int * 3)(*(smooth_iters + [0] * (3 - len(orders)))), _STORAGE[storage],
+                     int(bool(use_graph)))
+        self.mg_levels = [(self.ne * self.nv * _nb(k, self.dim)) for k in orders]
+        L.check(self.lib.dg_mg_setup(self.ctx, _ptr(w), float(shift), ctypes.byref(o), _stream()), "dg_mg_setup")
+
+    def mg_apply(self, r, out=None):
+        self._vec(r, "r")
+        out = self.empty() if out is None else self._vec(out, "out")
+        L.check(self.lib.dg_mg_apply(self.ctx, _ptr(r), _ptr(out), _stream()), "dg_mg_apply")
+        return out
+
+    def mg_level_apply(self, level, x):
+        n = self.mg_levels[level]
+        if not (isinstance(x, torch.Tensor) and x.dtype == torch.float64 and x.is_cuda and x.is_contiguous()
+                and x.numel() == n):
+            raise ValueError(f"x must be a contiguous float64 CUDA tensor with {n} entries")
+        y = torch.empty_like(x)
+        L.check(self.lib.dg_mg_level_apply(self.ctx, int(level), _ptr(x), _ptr(y), _stream()), "dg_mg_level_apply")
+        return y
 
     def fgmres(self, w, shift, b, x=None, restart=30, max_iter=1000, rtol=1e-8, precond="bj", jvp_mode="exact"):
         self._vec(w, "w")

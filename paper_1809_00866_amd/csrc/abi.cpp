@@ -13,9 +13,9 @@
 #include <string>
 #include <vector>
 
-#include "dg_internal.h"
+#include "context.h"
 
-namespace {
+namespace dgc {
 
 thread_local std::string g_err;
 
@@ -24,78 +24,9 @@ dg_status fail(dg_status s, const std::string& m) {
   return s;
 }
 
-#define HIPCHK(call)                                                                           \
-  do {                                                                                         \
-    hipError_t e_ = (call);                                                                    \
-    if (e_ != hipSuccess) return fail(DG_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
-  } while (0)
-
-struct Timer {
-  double ms = 0.0;
-  int64_t n = 0;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
-};
-
-}  // namespace
-
-struct dg_context {
-  dg_params prm{};
-  int dim = 0, nv = 0, nb = 0, nq1 = 0, nq = 0, nfq = 0, cfg = -1;
-  int64_t ne = 0, ndof = 0;
-  dgk::Tables tb{};
-  dgk::MTables mt{};
-  bool use_mfma = false;
-  double* d_mtab = nullptr;
-  dgk::Mesh mesh{};
-  dgk::Phys ph{};
-  double* d_tab = nullptr;
-  int64_t* d_nbr = nullptr;
-  double* d_x0 = nullptr;
-  double* d_H = nullptr;
-  double* d_t1 = nullptr;
-  double* d_t2 = nullptr;
-  double* d_t3 = nullptr;
-  double* d_rw = nullptr;
-  double* d_red = nullptr;
-  double* d_scal = nullptr;
-  int* d_flag = nullptr;
-  int* d_color = nullptr;
-  int ncolor = 0;
-  double* d_D64 = nullptr;
-  void* d_Dinv = nullptr;
-  int blk_storage = -1;
-  size_t dinv_bytes = 0;  // size of a separate (FP32/BF16) inverse buffer
-  bool blk_ready = false;
-  double* d_V = nullptr;
-  double* d_Z = nullptr;
-  int kry_m = 0;
-  double* h_pin = nullptr;
-  bool prof = false;
-  std::map<std::string, Timer> timers;
-};
-
-namespace {
-
-// Records HIP events around a launch on its stream when profiling is on.
-struct ProfScope {
-  dg_context* c;
-  const char* name;
-  hipStream_t s;
-  hipEvent_t a = nullptr, b = nullptr;
-  ProfScope(dg_context* ctx, const char* nm, hipStream_t st) : c(ctx), name(nm), s(st) {
-    if (c->prof) {
-      (void)hipEventCreate(&a);
-      (void)hipEventCreate(&b);
-      (void)hipEventRecord(a, s);
-    }
-  }
-  ~ProfScope() {
-    if (c->prof) {
-      (void)hipEventRecord(b, s);
-      c->timers[name].ev.push_back({a, b});
-    }
-  }
-};
+void dfree(void* p) {
+  if (p) (void)hipFree(p);
+}
 
 dg_status eval_residual(dg_context* c, bool jvp, const double* w, const double* v, double shift, double* out,
                         hipStream_t s) {
@@ -146,22 +77,9 @@ dg_status jvp_impl(dg_context* c, const double* w, const double* r_w, const doub
   return DG_OK;
 }
 
-template <class T>
-dg_status dalloc(T** p, size_t n) {
-  if (*p) return DG_OK;
-  if (hipMalloc((void**)p, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess) {
-    *p = nullptr;
-    (void)hipGetLastError();
-    return fail(DG_ERR_OOM, "hipMalloc of " + std::to_string(n * sizeof(T)) + " bytes failed");
-  }
-  return DG_OK;
-}
+}  // namespace dgc
 
-void dfree(void* p) {
-  if (p) (void)hipFree(p);
-}
-
-}  // namespace
+using namespace dgc;
 
 extern "C" {
 
@@ -366,6 +284,7 @@ void dg_destroy(dg_context* c) {
   if (c->d_Dinv != c->d_D64) dfree(c->d_Dinv);
   dfree(c->d_V);
   dfree(c->d_Z);
+  mg_destroy(c->mg);
   if (c->h_pin) (void)hipHostFree(c->h_pin);
   delete c;
 }
@@ -410,6 +329,7 @@ dg_status dg_block_precond_setup(dg_context* c, const double* w, double shift, i
   if (m > 256) return fail(DG_ERR_ARG, "block size above 256");
   dg_status st;
   c->blk_ready = false;
+  mg_invalidate(c->mg);
   if ((st = dalloc(&c->d_D64, (size_t)c->ne * m * m)) != DG_OK) return st;
   if (storage == DG_FP64) {
     // FP64 inverses overwrite the probed blocks in place
@@ -482,8 +402,10 @@ dg_status dg_fgmres_solve(dg_context* c, const double* w, double shift, const do
   if (x == b || x == w) return fail(DG_ERR_ARG, "x may not alias w or b");
   const int m = opts->restart > 0 ? opts->restart : 30;
   if (m > 60) return fail(DG_ERR_ARG, "restart above 60");
-  if (opts->precond != DG_PREC_NONE && opts->precond != DG_PREC_BJ) return fail(DG_ERR_ARG, "unknown precond");
+  if (opts->precond != DG_PREC_NONE && opts->precond != DG_PREC_BJ && opts->precond != DG_PREC_MG)
+    return fail(DG_ERR_ARG, "unknown precond");
   if (opts->precond == DG_PREC_BJ && !c->blk_ready) return fail(DG_ERR_STATE, "block preconditioner not set up");
+  if (opts->precond == DG_PREC_MG && !mg_ready(c->mg)) return fail(DG_ERR_STATE, "p-multigrid not set up");
   if (opts->jvp_mode != DG_JVP_EXACT && opts->jvp_mode != DG_JVP_FD) return fail(DG_ERR_ARG, "unknown jvp mode");
   const double rtol = opts->rtol > 0.0 ? opts->rtol : 1e-8;
   const int max_iter = opts->max_iter > 0 ? opts->max_iter : 1000;
@@ -508,6 +430,7 @@ dg_status dg_fgmres_solve(dg_context* c, const double* w, double shift, const do
   }
   auto applyG = [&](const double* z, double* outv) { return jvp_impl(c, w, rw, z, shift, opts->jvp_mode, outv, s); };
   auto applyM = [&](const double* v, double* z) -> dg_status {
+    if (opts->precond == DG_PREC_MG) return mg_apply(c, v, z, s);
     if (opts->precond == DG_PREC_BJ) {
       ProfScope ps(c, "block_apply", s);
       HIPCHK(dgk::launch_block_apply(c->blk_storage, c->d_Dinv, c->nv * c->nb, c->ne, v, z, s));

@@ -1,0 +1,126 @@
+// Library context shared by the entry-point translation units (internal
+// header; not part of the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "dg_internal.h"
+
+namespace dgc {
+
+// Sets the thread-local message returned by dg_last_error and returns s.
+dg_status fail(dg_status s, const std::string& m);
+
+#define HIPCHK(call)                                                                           \
+  do {                                                                                         \
+    hipError_t e_ = (call);                                                                    \
+    if (e_ != hipSuccess) return dgc::fail(DG_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+struct Timer {
+  double ms = 0.0;
+  int64_t n = 0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+};
+
+// Allocates n elements unless *p is already set.
+template <class T>
+dg_status dalloc(T** p, size_t n) {
+  if (*p) return DG_OK;
+  if (hipMalloc((void**)p, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return fail(DG_ERR_OOM, "hipMalloc of " + std::to_string(n * sizeof(T)) + " bytes failed");
+  }
+  return DG_OK;
+}
+
+
+void dfree(void* p);
+
+// p-multigrid preconditioner state (pmg.cpp)
+struct MgState;
+void mg_destroy(MgState* m);
+void mg_invalidate(MgState* m);  // the fine block factors changed
+bool mg_ready(const MgState* m);
+
+}  // namespace dgc
+
+struct dg_context {
+  dg_params prm{};
+  int dim = 0, nv = 0, nb = 0, nq1 = 0, nq = 0, nfq = 0, cfg = -1;
+  int64_t ne = 0, ndof = 0;
+  dgk::Tables tb{};
+  dgk::MTables mt{};
+  bool use_mfma = false;
+  double* d_mtab = nullptr;
+  dgk::Mesh mesh{};
+  dgk::Phys ph{};
+  double* d_tab = nullptr;
+  int64_t* d_nbr = nullptr;
+  double* d_x0 = nullptr;
+  double* d_H = nullptr;
+  double* d_t1 = nullptr;
+  double* d_t2 = nullptr;
+  double* d_t3 = nullptr;
+  double* d_rw = nullptr;
+  double* d_red = nullptr;
+  double* d_scal = nullptr;
+  int* d_flag = nullptr;
+  int* d_color = nullptr;
+  int ncolor = 0;
+  double* d_D64 = nullptr;
+  void* d_Dinv = nullptr;
+  int blk_storage = -1;
+  size_t dinv_bytes = 0;  // size of a separate (FP32/BF16) inverse buffer
+  bool blk_ready = false;
+  double* d_V = nullptr;
+  double* d_Z = nullptr;
+  int kry_m = 0;
+  double* h_pin = nullptr;
+  bool prof = false;
+  std::map<std::string, dgc::Timer> timers;
+  dgc::MgState* mg = nullptr;  // p-multigrid preconditioner (dg_mg_setup)
+};
+
+
+namespace dgc {
+
+// Records HIP events around a launch on its stream when profiling is on.
+struct ProfScope {
+  dg_context* c;
+  const char* name;
+  hipStream_t s;
+  hipEvent_t a = nullptr, b = nullptr;
+  ProfScope(dg_context* ctx, const char* nm, hipStream_t st) : c(ctx), name(nm), s(st) {
+    if (c->prof) {
+      (void)hipEventCreate(&a);
+      (void)hipEventCreate(&b);
+      (void)hipEventRecord(a, s);
+    }
+  }
+  ~ProfScope() {
+    if (c->prof) {
+      (void)hipEventRecord(b, s);
+      c->timers[name].ev.push_back({a, b});
+    }
+  }
+};
+
+// Residual (jvp = false) or exact Jv plus shift*v (jvp = true) on stream s.
+dg_status eval_residual(dg_context* c, bool jvp, const double* w, const double* v, double shift, double* out,
+                        hipStream_t s);
+// dout[0] = ||x||_2 over the context's DOF vector length.
+dg_status norm2(dg_context* c, const double* x, double* dout, hipStream_t s);
+// out = shift*v + J(w) v, exact or finite difference.
+dg_status jvp_impl(dg_context* c, const double* w, const double* r_w, const double* v, double shift, int mode,
+                   double* out, hipStream_t s);
+
+// z = MG_V(0, r, 0) with the context's p-multigrid state (must be ready).
+dg_status mg_apply(dg_context* c, const double* r, double* z, hipStream_t s);
+
+}  // namespace dgc

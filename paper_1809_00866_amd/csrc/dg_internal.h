@@ -107,6 +107,25 @@ hipError_t launch_block_invert(int storage, double* D64, void* Dout, int m, int6
 hipError_t launch_block_apply(int storage, const void* Dinv, int m, int64_t ne, const double* r, double* z,
                               hipStream_t s);
 
+// p-multigrid kernels (level transfer, inherited BSR operators, fixed-count
+// GMRES bookkeeping).  Device scalar block of one smoother, in doubles:
+constexpr int kMaxSmooth = 60;  // iterations per smoother call
+constexpr int kScBeta = 0, kScW0 = 1, kScHn = 2, kScInv = 3, kScFlag = 4;
+constexpr int kScH1 = 8, kScH2 = 72, kScCs = 136, kScSn = 200, kScG = 264, kScY = 336, kScR = 400;
+constexpr int kScSize = kScR + (kMaxSmooth + 1) * kMaxSmooth + 64;
+hipError_t launch_restrict(const double* f, int nbf, double* cv, int nbc, int nv, int64_t ne, hipStream_t s);
+hipError_t launch_prolong_add(const double* cv, int nbc, double* f, int nbf, int nv, int64_t ne, hipStream_t s);
+hipError_t launch_extract_bsr(const double* Jv, const int* color, int col, int l, const int64_t* nbr, int nf,
+                              int nbf, int nbc, int nv, int64_t ne, double* B, hipStream_t s);
+hipError_t launch_truncate_bsr(const double* B1, int nb1, double* B2, int nb2, int nv, int nslot, int64_t ne,
+                               hipStream_t s);
+hipError_t launch_bsr_apply(int bs, const double* B, const int64_t* nbr, int nf, int m, int64_t ne, const double* x,
+                            double* y, hipStream_t s);
+hipError_t launch_gmres_init(double* sc, int m, hipStream_t s);
+hipError_t launch_gmres_step(double* sc, int j, int m, hipStream_t s);
+hipError_t launch_gmres_backsolve(double* sc, int m, hipStream_t s);
+hipError_t launch_scale_by(int64_t n, double* x, const double* sc, hipStream_t s);
+
 }  // namespace dgk
 
 namespace dgh {

@@ -1,0 +1,437 @@
+// p-multigrid preconditioner (Sec. 2.4): Alg. vcic on levels k_0 > k_1 (> k_2)
+// with inherited coarse operators (eq. GalProj) and fixed-count GMRES smoothers
+// preconditioned by element-wise block Jacobi (EWBJ) on every level.
+//
+// * Level 0 applies the matrix-free operator G_0 = shift*I + J(w) (exact Jv).
+// * The first coarse level's operator is probed from G_0: for every colour of
+//   a distance-2 colouring (no two elements of a colour share a face
+//   neighbour, so every element sees at most one perturbed element among
+//   itself and its neighbours) and every coarse mode l, G_0 is applied to the
+//   zero-padded unit vectors of that colour; each element's restricted
+//   response is one column of the block that couples it to the perturbed
+//   element.  Deeper levels keep the leading sub-blocks (eq. GalProj with the
+//   unit-diagonal projection matrices of a hierarchical orthonormal basis).
+// * The smoothers run entirely on the device (Arnoldi by classical
+//   Gram-Schmidt with one re-orthogonalisation, Givens rotations and the
+//   triangular solve in one-thread kernels), so one V-cycle is a fixed
+//   sequence of kernel launches; setup captures it into a hipGraph that every
+//   apply replays on a library stream, ordered against the caller's stream
+//   by events.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "context.h"
+
+namespace dgc {
+
+struct MgLevel {
+  int order = 0, nb = 0, m = 0, iters = 0;
+  int64_t n = 0;               // level vector length ne*nv*nb
+  double* B = nullptr;         // coarse levels: BSR blocks [nslot][ne][m*m]
+  void* Dinv = nullptr;        // coarse levels: block-Jacobi inverses
+  double* g = nullptr;         // right-hand side
+  double* x = nullptr;         // iterate
+  double* t = nullptr;         // defect / work
+  double* z = nullptr;         // preconditioned vector
+  double* V = nullptr;         // Krylov basis [(iters+1)][n]
+  double* sc = nullptr;        // smoother scalars (kScSize)
+  int bs = 1024;               // BSR apply workgroup size (autotuned; same arithmetic for every size)
+};
+
+struct MgState {
+  int nlev = 0, nslot = 0, storage = DG_FP64;
+  double shift = 0.0;
+  bool use_graph = false, ready = false;
+  MgLevel lev[3];
+  double* w = nullptr;         // linearisation state (own copy)
+  double* red = nullptr;       // reduction partials [kMaxSmooth+4][kRedBlocks]
+  int* color2 = nullptr;
+  int ncolor2 = 0;
+  hipStream_t gs = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t ev_a = nullptr, ev_b = nullptr;
+};
+
+void mg_destroy(MgState* M) {
+  if (!M) return;
+  if (M->exec) (void)hipGraphExecDestroy(M->exec);
+  if (M->graph) (void)hipGraphDestroy(M->graph);
+  if (M->gs) (void)hipStreamDestroy(M->gs);
+  if (M->ev_a) (void)hipEventDestroy(M->ev_a);
+  if (M->ev_b) (void)hipEventDestroy(M->ev_b);
+  for (auto& L : M->lev) {
+    dfree(L.B);
+    dfree(L.Dinv);
+    dfree(L.g);
+    dfree(L.x);
+    dfree(L.t);
+    dfree(L.z);
+    dfree(L.V);
+    dfree(L.sc);
+  }
+  dfree(M->w);
+  dfree(M->red);
+  dfree(M->color2);
+  delete M;
+}
+
+void mg_invalidate(MgState* M) {
+  if (M) M->ready = false;
+}
+
+bool mg_ready(const MgState* M) { return M && M->ready; }
+
+namespace {
+
+int binom(int n, int k) {
+  long r = 1;
+  for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+  return (int)r;
+}
+
+// ---------------------------------------------------------------- level ops
+dg_status level_G(dg_context* c, MgState* M, int l, const double* x, double* y, hipStream_t s) {
+  if (l == 0) return eval_residual(c, true, M->w, x, M->shift, y, s);
+  const MgLevel& L = M->lev[l];
+  HIPCHK(dgk::launch_bsr_apply(L.bs, L.B, c->mesh.nbr, 2 * c->dim, L.m, c->ne, x, y, s));
+  return DG_OK;
+}
+
+dg_status level_Minv(dg_context* c, MgState* M, int l, const double* r, double* z, hipStream_t s) {
+  if (l == 0) {
+    HIPCHK(dgk::launch_block_apply(c->blk_storage, c->d_Dinv, c->nv * c->nb, c->ne, r, z, s));
+  } else {
+    const MgLevel& L = M->lev[l];
+    HIPCHK(dgk::launch_block_apply(M->storage, L.Dinv, L.m, c->ne, r, z, s));
+  }
+  return DG_OK;
+}
+
+dg_status lnorm(MgState* M, const double* x, int64_t n, double* dout, hipStream_t s) {
+  HIPCHK(dgk::launch_dot_partials(x, x, n, M->red, s));
+  HIPCHK(dgk::launch_sum_partials(M->red, dgk::kRedBlocks, dout, 1, s));
+  return DG_OK;
+}
+
+// x <- SMOOTH(G_l, g, x): `iters` right-preconditioned GMRES steps, one cycle.
+// zero_start: x0 = 0 (x is overwritten, its old content unused).
+dg_status smooth(dg_context* c, MgState* M, int l, bool zero_start, hipStream_t s) {
+  MgLevel& L = M->lev[l];
+  const int m = L.iters;
+  const int64_t n = L.n;
+  dg_status st;
+  if (m == 0) {
+    if (zero_start) HIPCHK(dgk::launch_fill(L.x, n, 0.0, s));
+    return DG_OK;
+  }
+  double* V0 = L.V;
+  if (zero_start) {
+    HIPCHK(dgk::launch_axpby(n, 1.0, L.g, 0.0, L.g, V0, s));
+  } else {
+    if ((st = level_G(c, M, l, L.x, L.t, s)) != DG_OK) return st;
+    HIPCHK(dgk::launch_axpby(n, 1.0, L.g, -1.0, L.t, V0, s));
+  }
+  if ((st = lnorm(M, V0, n, L.sc + dgk::kScBeta, s)) != DG_OK) return st;
+  HIPCHK(dgk::launch_gmres_init(L.sc, m, s));
+  HIPCHK(dgk::launch_scale_dev(n, V0, L.sc + dgk::kScBeta, V0, s));
+  for (int j = 0; j < m; ++j) {
+    double* Vj = L.V + (size_t)j * n;
+    double* Wn = L.V + (size_t)(j + 1) * n;
+    if ((st = level_Minv(c, M, l, Vj, L.z, s)) != DG_OK) return st;
+    if ((st = level_G(c, M, l, L.z, Wn, s)) != DG_OK) return st;
+    if ((st = lnorm(M, Wn, n, L.sc + dgk::kScW0, s)) != DG_OK) return st;
+    HIPCHK(dgk::launch_mdot(L.V, j + 1, n, Wn, M->red, s));
+    HIPCHK(dgk::launch_msum(M->red, j + 1, L.sc + dgk::kScH1, s));
+    HIPCHK(dgk::launch_mupdate(L.V, j + 1, n, L.sc + dgk::kScH1, Wn, s));
+    HIPCHK(dgk::launch_mdot(L.V, j + 1, n, Wn, M->red, s));
+    HIPCHK(dgk::launch_msum(M->red, j + 1, L.sc + dgk::kScH2, s));
+    HIPCHK(dgk::launch_mupdate(L.V, j + 1, n, L.sc + dgk::kScH2, Wn, s));
+    if ((st = lnorm(M, Wn, n, L.sc + dgk::kScHn, s)) != DG_OK) return st;
+    HIPCHK(dgk::launch_gmres_step(L.sc, j, m, s));
+    HIPCHK(dgk::launch_scale_by(n, Wn, L.sc + dgk::kScInv, s));
+  }
+  HIPCHK(dgk::launch_gmres_backsolve(L.sc, m, s));
+  HIPCHK(dgk::launch_fill(L.t, n, 0.0, s));
+  HIPCHK(dgk::launch_mupdate_add(L.V, m, n, L.sc + dgk::kScY, L.t, s));
+  if ((st = level_Minv(c, M, l, L.t, L.z, s)) != DG_OK) return st;
+  if (zero_start) {
+    HIPCHK(dgk::launch_axpby(n, 1.0, L.z, 0.0, L.z, L.x, s));
+  } else {
+    HIPCHK(dgk::launch_axpby(n, 1.0, L.x, 1.0, L.z, L.x, s));
+  }
+  return DG_OK;
+}
+
+// lev[l].x <- MG_V(l, lev[l].g, 0)  (Alg. vcic)
+dg_status vcycle(dg_context* c, MgState* M, int l, hipStream_t s) {
+  dg_status st;
+  MgLevel& L = M->lev[l];
+  if (l == M->nlev - 1) return smooth(c, M, l, true, s);  // coarsest-level solve
+  if ((st = smooth(c, M, l, true, s)) != DG_OK) return st;  // pre-smoothing
+  // coarse-grid correction of the defect d = g - G x
+  if ((st = level_G(c, M, l, L.x, L.t, s)) != DG_OK) return st;
+  HIPCHK(dgk::launch_axpby(L.n, 1.0, L.g, -1.0, L.t, L.t, s));
+  MgLevel& C = M->lev[l + 1];
+  HIPCHK(dgk::launch_restrict(L.t, L.nb, C.g, C.nb, c->nv, c->ne, s));
+  if ((st = vcycle(c, M, l + 1, s)) != DG_OK) return st;
+  HIPCHK(dgk::launch_prolong_add(C.x, C.nb, L.x, L.nb, c->nv, c->ne, s));
+  return smooth(c, M, l, false, s);  // post-smoothing
+}
+
+// ---------------------------------------------------------------- colouring
+// Distance-2 colouring: the lattice colouring (i + 2j + 3k) mod q (2D:
+// (i + 2j) mod q) for the smallest q that passes the check, else greedy.
+std::vector<int> distance2_colouring(const std::vector<int64_t>& nbrT, const std::vector<double>& x0, int dim,
+                                     int64_t ne, const double* h, int* ncolor) {
+  const int nf = 2 * dim;
+  auto elem = [&](int64_t K, int s) { return s == 0 ? K : nbrT[(size_t)(s - 1) * ne + K]; };
+  auto valid = [&](const std::vector<int>& col) {
+    // the closed neighbourhood of every element must carry distinct elements' distinct colours
+    for (int64_t K = 0; K < ne; ++K)
+      for (int a = 0; a <= nf; ++a)
+        for (int b = a + 1; b <= nf; ++b) {
+          const int64_t A = elem(K, a), Bv = elem(K, b);
+          if (A != Bv && col[A] == col[Bv]) return false;
+        }
+    return true;
+  };
+  std::vector<int> best;
+  // lattice indices from the low corners
+  double lo[3] = {0, 0, 0};
+  for (int i = 0; i < dim; ++i) {
+    lo[i] = x0[(size_t)i * ne];
+    for (int64_t e = 0; e < ne; ++e) lo[i] = std::min(lo[i], x0[(size_t)i * ne + e]);
+  }
+  for (int q = 2 * dim + 1; q <= 4 * dim && best.empty(); ++q) {
+    std::vector<int> col(ne);
+    for (int64_t e = 0; e < ne; ++e) {
+      long v = 0;
+      for (int i = 0; i < dim; ++i) v += (long)(i + 1) * std::lround((x0[(size_t)i * ne + e] - lo[i]) / h[i]);
+      col[e] = (int)(((v % q) + q) % q);
+    }
+    if (valid(col)) {
+      best = col;
+      *ncolor = q;
+    }
+  }
+  // greedy
+  std::vector<int> gcol(ne, -1);
+  int gn = 0;
+  for (int64_t e = 0; e < ne; ++e) {
+    std::vector<char> used(64 * 8, 0);
+    for (int a = 0; a <= nf; ++a) {
+      const int64_t A = elem(e, a);
+      for (int b = 0; b <= nf; ++b) {
+        const int64_t C = elem(A, b);
+        if (C != e && gcol[C] >= 0) used[gcol[C]] = 1;
+      }
+    }
+    int k = 0;
+    while (used[k]) ++k;
+    gcol[e] = k;
+    gn = std::max(gn, k + 1);
+  }
+  if (best.empty() || gn < *ncolor) {
+    *ncolor = gn;
+    return gcol;
+  }
+  return best;
+}
+
+}  // namespace
+
+dg_status mg_apply(dg_context* c, const double* r, double* z, hipStream_t s) {
+  MgState* M = c->mg;
+  MgLevel& L0 = M->lev[0];
+  ProfScope ps(c, "mg_vcycle", s);
+  HIPCHK(dgk::launch_axpby(L0.n, 1.0, r, 0.0, r, L0.g, s));
+  if (M->exec) {
+    HIPCHK(hipEventRecord(M->ev_a, s));
+    HIPCHK(hipStreamWaitEvent(M->gs, M->ev_a, 0));
+    HIPCHK(hipGraphLaunch(M->exec, M->gs));
+    HIPCHK(hipEventRecord(M->ev_b, M->gs));
+    HIPCHK(hipStreamWaitEvent(s, M->ev_b, 0));
+  } else {
+    dg_status st;
+    if ((st = vcycle(c, M, 0, s)) != DG_OK) return st;
+  }
+  HIPCHK(dgk::launch_axpby(L0.n, 1.0, L0.x, 0.0, L0.x, z, s));
+  return DG_OK;
+}
+
+}  // namespace dgc
+
+using namespace dgc;
+
+extern "C" {
+
+dg_status dg_mg_setup(dg_context* c, const double* w, double shift, const dg_mg_opts* o, void* stream) {
+  if (!c || !w || !o) return fail(DG_ERR_ARG, "null argument");
+  if (c->prm.basis != DG_BASIS_PK) return fail(DG_ERR_ARG, "p-multigrid needs the total-degree basis");
+  if (o->n_levels < 2 || o->n_levels > 3) return fail(DG_ERR_ARG, "n_levels must be 2 or 3");
+  if (o->orders[0] != c->prm.order) return fail(DG_ERR_ARG, "orders[0] must equal the context's order");
+  for (int l = 1; l < o->n_levels; ++l)
+    if (o->orders[l] < 0 || o->orders[l] >= o->orders[l - 1])
+      return fail(DG_ERR_ARG, "orders must be strictly decreasing and >= 0");
+  for (int l = 0; l < o->n_levels; ++l)
+    if (o->smooth_iters[l] < 0 || o->smooth_iters[l] > dgk::kMaxSmooth)
+      return fail(DG_ERR_ARG, "smooth_iters must lie in 0..60");
+  if (o->smooth_iters[o->n_levels - 1] < 1) return fail(DG_ERR_ARG, "the coarsest level needs >= 1 iteration");
+  if (o->storage != DG_FP64 && o->storage != DG_FP32 && o->storage != DG_BF16)
+    return fail(DG_ERR_ARG, "storage must be DG_FP64, DG_FP32 or DG_BF16");
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t ne = c->ne;
+  const int dim = c->dim, nv = c->nv, nf = 2 * dim;
+  dg_status st;
+
+  mg_destroy(c->mg);
+  c->mg = nullptr;
+  // fine-level block Jacobi (shared with DG_PREC_BJ)
+  if ((st = dg_block_precond_setup(c, w, shift, o->storage, stream)) != DG_OK) return st;
+
+  auto* M = new MgState();
+  c->mg = M;
+  auto bail = [&](dg_status e) {
+    mg_destroy(M);
+    c->mg = nullptr;
+    return e;
+  };
+  M->nlev = o->n_levels;
+  M->nslot = nf + 1;
+  M->storage = o->storage;
+  M->shift = shift;
+  M->use_graph = o->use_graph != 0;
+  for (int l = 0; l < M->nlev; ++l) {
+    MgLevel& L = M->lev[l];
+    L.order = o->orders[l];
+    L.nb = binom(L.order + dim, dim);
+    L.m = nv * L.nb;
+    L.iters = o->smooth_iters[l];
+    L.n = ne * L.m;
+    if ((st = dalloc(&L.g, (size_t)L.n)) != DG_OK) return bail(st);
+    if ((st = dalloc(&L.x, (size_t)L.n)) != DG_OK) return bail(st);
+    if ((st = dalloc(&L.t, (size_t)L.n)) != DG_OK) return bail(st);
+    if ((st = dalloc(&L.z, (size_t)L.n)) != DG_OK) return bail(st);
+    if ((st = dalloc(&L.V, (size_t)(L.iters + 1) * L.n)) != DG_OK) return bail(st);
+    if ((st = dalloc(&L.sc, (size_t)dgk::kScSize)) != DG_OK) return bail(st);
+    HIPCHK(dgk::launch_fill(L.sc, dgk::kScSize, 0.0, s));
+  }
+  if ((st = dalloc(&M->w, (size_t)c->ndof)) != DG_OK) return bail(st);
+  if ((st = dalloc(&M->red, (size_t)(dgk::kMaxSmooth + 4) * dgk::kRedBlocks)) != DG_OK) return bail(st);
+  HIPCHK(dgk::launch_axpby(c->ndof, 1.0, w, 0.0, w, M->w, s));
+
+  // distance-2 colouring (host)
+  std::vector<int64_t> nbrT((size_t)nf * ne);
+  std::vector<double> x0((size_t)dim * ne);
+  if (hipMemcpy(nbrT.data(), c->d_nbr, nbrT.size() * sizeof(int64_t), hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(x0.data(), c->d_x0, x0.size() * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+    return bail(fail(DG_ERR_HIP, "mesh download failed"));
+  std::vector<int> col2 = distance2_colouring(nbrT, x0, dim, ne, c->mesh.h, &M->ncolor2);
+  if ((st = dalloc(&M->color2, (size_t)ne)) != DG_OK) return bail(st);
+  if (hipMemcpy(M->color2, col2.data(), ne * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+    return bail(fail(DG_ERR_HIP, "colour upload failed"));
+
+  // first coarse level probed from G_0, deeper levels by truncation
+  {
+    MgLevel& C = M->lev[1];
+    const size_t nB = (size_t)M->nslot * ne * C.m * C.m;
+    if ((st = dalloc(&C.B, nB)) != DG_OK) return bail(st);
+    HIPCHK(dgk::launch_fill(C.B, (int64_t)nB, 0.0, s));
+    ProfScope ps(c, "mg_probe", s);
+    for (int col = 0; col < M->ncolor2; ++col)
+      for (int l = 0; l < C.m; ++l) {
+        const int lf = (l / C.nb) * c->nb + l % C.nb;
+        HIPCHK(dgk::launch_probe_vector(c->d_t1, M->color2, col, lf, c->nb, nv, ne, s));
+        if ((st = eval_residual(c, true, M->w, c->d_t1, shift, c->d_t2, s)) != DG_OK) return bail(st);
+        HIPCHK(dgk::launch_extract_bsr(c->d_t2, M->color2, col, l, c->mesh.nbr, nf, c->nb, C.nb, nv, ne, C.B, s));
+      }
+  }
+  for (int l = 2; l < M->nlev; ++l) {
+    MgLevel& P = M->lev[l - 1];
+    MgLevel& C = M->lev[l];
+    if ((st = dalloc(&C.B, (size_t)M->nslot * ne * C.m * C.m)) != DG_OK) return bail(st);
+    HIPCHK(dgk::launch_truncate_bsr(P.B, P.nb, C.B, C.nb, nv, M->nslot, ne, s));
+  }
+  // coarse block-Jacobi factors from the diagonal slot
+  for (int l = 1; l < M->nlev; ++l) {
+    MgLevel& C = M->lev[l];
+    const size_t esz = o->storage == DG_FP64 ? 8 : (o->storage == DG_FP32 ? 4 : 2);
+    unsigned char* p = nullptr;
+    if ((st = dalloc(&p, (size_t)ne * C.m * C.m * esz)) != DG_OK) return bail(st);
+    C.Dinv = p;
+    int zero = 0;
+    HIPCHK(hipMemcpyAsync(c->d_flag, &zero, sizeof(int), hipMemcpyHostToDevice, s));
+    HIPCHK(dgk::launch_block_invert(o->storage, C.B, C.Dinv, C.m, ne, c->d_flag, s));
+    int bad = 0;
+    HIPCHK(hipMemcpyAsync(&bad, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (bad) return bail(fail(DG_ERR_SINGULAR_BLOCK, "a coarse diagonal block has a zero or non-finite pivot"));
+  }
+  // autotune the BSR apply workgroup size per coarse level
+  {
+    hipEvent_t a, b;
+    HIPCHK(hipEventCreate(&a));
+    HIPCHK(hipEventCreate(&b));
+    for (int l = 1; l < M->nlev; ++l) {
+      MgLevel& C = M->lev[l];
+      HIPCHK(dgk::launch_fill(C.g, C.n, 0.5, s));
+      float best = 1e30f;
+      for (int bs : {256, 512, 1024}) {
+        if (bs < 4 * C.m) continue;
+        HIPCHK(dgk::launch_bsr_apply(bs, C.B, c->mesh.nbr, nf, C.m, ne, C.g, C.t, s));
+        HIPCHK(hipEventRecord(a, s));
+        for (int k = 0; k < 5; ++k) HIPCHK(dgk::launch_bsr_apply(bs, C.B, c->mesh.nbr, nf, C.m, ne, C.g, C.t, s));
+        HIPCHK(hipEventRecord(b, s));
+        HIPCHK(hipEventSynchronize(b));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, a, b));
+        if (ms < best) {
+          best = ms;
+          C.bs = bs;
+        }
+      }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+  }
+  HIPCHK(hipEventCreateWithFlags(&M->ev_a, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&M->ev_b, hipEventDisableTiming));
+  HIPCHK(hipStreamSynchronize(s));
+  if (M->use_graph) {
+    HIPCHK(hipStreamCreateWithFlags(&M->gs, hipStreamNonBlocking));
+    const bool prof = c->prof;
+    c->prof = false;  // no event records inside the captured graph
+    hipError_t e = hipStreamBeginCapture(M->gs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      st = vcycle(c, M, 0, M->gs);
+      e = hipStreamEndCapture(M->gs, &M->graph);
+    }
+    c->prof = prof;
+    if (e != hipSuccess) return bail(fail(DG_ERR_HIP, std::string("V-cycle capture: ") + hipGetErrorString(e)));
+    if (st != DG_OK) return bail(st);
+    HIPCHK(hipGraphInstantiate(&M->exec, M->graph, nullptr, nullptr, 0));
+  }
+  M->ready = true;
+  return DG_OK;
+}
+
+dg_status dg_mg_apply(dg_context* c, const double* r, double* z, void* stream) {
+  if (!c || !r || !z) return fail(DG_ERR_ARG, "null argument");
+  if (r == z) return fail(DG_ERR_ARG, "r and z may not alias");
+  if (!mg_ready(c->mg)) return fail(DG_ERR_STATE, "dg_mg_setup has not succeeded since the last block setup");
+  return mg_apply(c, r, z, (hipStream_t)stream);
+}
+
+dg_status dg_mg_level_apply(dg_context* c, int level, const double* x, double* y, void* stream) {
+  if (!c || !x || !y) return fail(DG_ERR_ARG, "null argument");
+  if (x == y) return fail(DG_ERR_ARG, "x and y may not alias");
+  if (!mg_ready(c->mg)) return fail(DG_ERR_STATE, "dg_mg_setup has not succeeded since the last block setup");
+  if (level < 0 || level >= c->mg->nlev) return fail(DG_ERR_ARG, "level out of range");
+  return level_G(c, c->mg, level, x, y, (hipStream_t)stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,262 @@
+// Kernels of the p-multigrid preconditioner (Sec. 2.4): mode truncation and
+// zero-padding between levels, the inherited coarse operators of eq. GalProj
+// stored block-sparse, and the device-side bookkeeping of the fixed-count
+// GMRES smoothers.
+//
+// Level vectors use the DOF layout of the library with the level's own mode
+// count: idx(e, c, b) = (c*Nb_l + b)*ne + e.  With the hierarchical
+// orthonormal basis the first Nb_l modes of the fine basis span the level's
+// space, so restriction keeps them and prolongation pads with zeros.
+//
+// Coarse operator storage (BSR, one block row per element): slot 0 holds the
+// diagonal block, slot 1 + f the coupling to the face neighbour f (order
+// -x,+x,-y,+y,-z,+z); blocks are m x m column-major, laid out [slot][e][m*m],
+// so slot 0 is the contiguous stack of diagonal blocks the block-Jacobi
+// inversion reads.
+#include "dg_internal.h"
+
+namespace dgk {
+
+namespace {
+
+__global__ void k_restrict(const double* __restrict__ f, int nbf, double* __restrict__ cv, int nbc, int nv,
+                           int64_t ne) {
+  const int64_t n = (int64_t)nv * nbc * ne;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = i % ne;
+    const int r = (int)(i / ne);
+    const int c = r / nbc, b = r % nbc;
+    cv[i] = f[((int64_t)c * nbf + b) * ne + e];
+  }
+}
+
+// f += pad(cv) on the modes the coarse level has
+__global__ void k_prolong_add(const double* __restrict__ cv, int nbc, double* __restrict__ f, int nbf, int nv,
+                              int64_t ne) {
+  const int64_t n = (int64_t)nv * nbc * ne;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = i % ne;
+    const int r = (int)(i / ne);
+    const int c = r / nbc, b = r % nbc;
+    f[((int64_t)c * nbf + b) * ne + e] += cv[i];
+  }
+}
+
+// Slot of element K whose element carries colour `col` (the first such slot;
+// later slots naming the same element keep zero blocks), or -1.
+__device__ __forceinline__ int colour_slot(const int* color, const int64_t* nbr, int nf, int64_t ne, int64_t K,
+                                           int col) {
+  if (color[K] == col) return 0;
+  for (int f = 0; f < nf; ++f) {
+    const int64_t J = nbr[(int64_t)f * ne + K];
+    if (color[J] != col) continue;
+    bool dup = (J == K);
+    for (int g = 0; g < f && !dup; ++g) dup = (nbr[(int64_t)g * ne + K] == J);
+    return dup ? -1 : 1 + f;
+  }
+  return -1;
+}
+
+// Column l (coarse local index c*nbc + b) of the block of row K in the slot of
+// the perturbed element: B[slot][K][l*m + r] = (G_0 P)_{K, r} for coarse rows r.
+__global__ void k_extract_bsr(const double* __restrict__ Jv, const int* __restrict__ color, int col, int l,
+                              const int64_t* __restrict__ nbr, int nf, int nbf, int nbc, int nv, int64_t ne,
+                              double* __restrict__ B) {
+  const int m = nv * nbc;
+  const int64_t n = (int64_t)m * ne;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t K = i % ne;
+    const int r = (int)(i / ne);
+    const int s = colour_slot(color, nbr, nf, ne, K, col);
+    if (s < 0) continue;
+    const int c = r / nbc, b = r % nbc;
+    B[((int64_t)s * ne + K) * m * m + (int64_t)l * m + r] = Jv[((int64_t)c * nbf + b) * ne + K];
+  }
+}
+
+// Leading sub-blocks: B2[s][K](r2, j2) = B1[s][K](r1, j1), r = c*nb + b with b < nb2.
+__global__ void k_truncate_bsr(const double* __restrict__ B1, int nb1, double* __restrict__ B2, int nb2, int nv,
+                               int nslot, int64_t ne) {
+  const int m1 = nv * nb1, m2 = nv * nb2;
+  const int64_t n = (int64_t)nslot * ne * m2 * m2;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t blk = i / ((int64_t)m2 * m2);
+    const int q = (int)(i % ((int64_t)m2 * m2));
+    const int j2 = q / m2, r2 = q % m2;
+    const int j1 = (j2 / nb2) * nb1 + j2 % nb2, r1 = (r2 / nb2) * nb1 + r2 % nb2;
+    B2[i] = B1[blk * m1 * m1 + (int64_t)j1 * m1 + r1];
+  }
+}
+
+// y_K = sum_s B[s][K] x_{elem(K, s)}.  A row of the level operator is
+// summed by 4 threads per matrix row (columns c, c+4, c+8, ... of the
+// (2d+1)*m gathered x values) and the 4 partial sums are added in a fixed
+// order, so the result does not depend on the workgroup size BS, which only
+// sets how many element rows (BS / 4m) share a workgroup.
+template <int BS>
+__global__ __launch_bounds__(BS) void k_bsr_apply(const double* __restrict__ B, const int64_t* __restrict__ nbr,
+                                                  int nf, int m, int64_t ne, const double* __restrict__ x,
+                                                  double* __restrict__ y) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int tpr = 4 * m;           // threads per element row
+  const int R = BS / tpr;          // element rows per workgroup
+  const int ncol = (nf + 1) * m;
+  double* xs = reinterpret_cast<double*>(smem);  // [R][ncol]
+  double* part = xs + R * ncol;                  // [BS]
+  const int64_t K0 = (int64_t)blockIdx.x * R;
+  for (int t = threadIdx.x; t < R * ncol; t += BS) {
+    const int rr = t / ncol, q = t - rr * ncol;
+    const int64_t K = K0 + rr;
+    if (K < ne) {
+      const int s = q / m, j = q - s * m;
+      const int64_t E = s == 0 ? K : nbr[(int64_t)(s - 1) * ne + K];
+      xs[t] = x[(int64_t)j * ne + E];
+    }
+  }
+  __syncthreads();
+  const int rr = threadIdx.x / tpr, q = threadIdx.x - rr * tpr;
+  const int cc = q / m, i = q - cc * m;
+  const int64_t K = K0 + rr;
+  double a = 0.0;
+  if (rr < R && K < ne) {
+    const double* xr = xs + rr * ncol;
+    for (int col = cc; col < ncol; col += 4) {
+      const int s = col / m, j = col - s * m;
+      a += B[((int64_t)s * ne + K) * m * m + (int64_t)j * m + i] * xr[col];
+    }
+  }
+  part[threadIdx.x] = a;
+  __syncthreads();
+  if ((int)threadIdx.x < R * m) {
+    const int r2 = threadIdx.x / m, i2 = threadIdx.x - r2 * m;
+    const int64_t K2 = K0 + r2;
+    const double* p = part + r2 * tpr + i2;
+    if (K2 < ne) y[(int64_t)i2 * ne + K2] = ((p[0] + p[m]) + p[2 * m]) + p[3 * m];
+  }
+}
+
+// --- fixed-count GMRES bookkeeping (one thread; column j of the Hessenberg
+// matrix, already orthogonalised, arrives in h1 + h2 with ||w|| in hn) ---
+
+__global__ void k_gmres_init(double* __restrict__ sc, int m) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double* gv = sc + kScG;
+  for (int i = 0; i <= m; ++i) gv[i] = 0.0;
+  gv[0] = sc[kScBeta];
+  sc[kScFlag] = 0.0;
+}
+
+__global__ void k_gmres_step(double* __restrict__ sc, int j, int m) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double* R = sc + kScR + (int64_t)j * (m + 1);  // column j, rows 0..j+1
+  double* cs = sc + kScCs;
+  double* sn = sc + kScSn;
+  double* gv = sc + kScG;
+  const double w0 = sc[kScW0], hn = sc[kScHn];
+  for (int i = 0; i <= j; ++i) R[i] = sc[kScH1 + i] + sc[kScH2 + i];
+  R[j + 1] = hn;
+  // happy breakdown (or a zero column after one): later Krylov vectors are 0
+  const bool brk = sc[kScFlag] != 0.0 || !(hn > 1e-14 * w0);
+  sc[kScFlag] = brk ? 1.0 : 0.0;
+  sc[kScInv] = brk ? 0.0 : 1.0 / hn;
+  for (int i = 0; i < j; ++i) {
+    const double t = cs[i] * R[i] + sn[i] * R[i + 1];
+    R[i + 1] = -sn[i] * R[i] + cs[i] * R[i + 1];
+    R[i] = t;
+  }
+  const double den = hypot(R[j], R[j + 1]);
+  cs[j] = den > 0.0 ? R[j] / den : 1.0;
+  sn[j] = den > 0.0 ? R[j + 1] / den : 0.0;
+  R[j] = den;
+  R[j + 1] = 0.0;
+  gv[j + 1] = -sn[j] * gv[j];
+  gv[j] = cs[j] * gv[j];
+}
+
+// y = R^-1 g (upper triangular, columns with a zero pivot give y = 0)
+__global__ void k_gmres_backsolve(double* __restrict__ sc, int m) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double* R = sc + kScR;
+  const double* gv = sc + kScG;
+  double* y = sc + kScY;
+  for (int i = m - 1; i >= 0; --i) {
+    double a = gv[i];
+    for (int l = i + 1; l < m; ++l) a -= R[(int64_t)l * (m + 1) + i] * y[l];
+    const double d = R[(int64_t)i * (m + 1) + i];
+    y[i] = d != 0.0 ? a / d : 0.0;
+  }
+}
+
+// x *= s[0]
+__global__ void k_scale_by(int64_t n, double* __restrict__ x, const double* __restrict__ s) {
+  const double a = s[0];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    x[i] *= a;
+}
+
+unsigned grid_for(int64_t n) {
+  const int64_t g = (n + 255) / 256;
+  return (unsigned)(g < 1 ? 1 : (g > 4096 ? 4096 : g));
+}
+
+}  // namespace
+
+hipError_t launch_restrict(const double* f, int nbf, double* cv, int nbc, int nv, int64_t ne, hipStream_t s) {
+  k_restrict<<<grid_for((int64_t)nv * nbc * ne), 256, 0, s>>>(f, nbf, cv, nbc, nv, ne);
+  return hipGetLastError();
+}
+
+hipError_t launch_prolong_add(const double* cv, int nbc, double* f, int nbf, int nv, int64_t ne, hipStream_t s) {
+  k_prolong_add<<<grid_for((int64_t)nv * nbc * ne), 256, 0, s>>>(cv, nbc, f, nbf, nv, ne);
+  return hipGetLastError();
+}
+
+hipError_t launch_extract_bsr(const double* Jv, const int* color, int col, int l, const int64_t* nbr, int nf,
+                              int nbf, int nbc, int nv, int64_t ne, double* B, hipStream_t s) {
+  k_extract_bsr<<<grid_for((int64_t)nv * nbc * ne), 256, 0, s>>>(Jv, color, col, l, nbr, nf, nbf, nbc, nv, ne, B);
+  return hipGetLastError();
+}
+
+hipError_t launch_truncate_bsr(const double* B1, int nb1, double* B2, int nb2, int nv, int nslot, int64_t ne,
+                               hipStream_t s) {
+  const int64_t m2 = (int64_t)nv * nb2;
+  k_truncate_bsr<<<grid_for((int64_t)nslot * ne * m2 * m2), 256, 0, s>>>(B1, nb1, B2, nb2, nv, nslot, ne);
+  return hipGetLastError();
+}
+
+hipError_t launch_bsr_apply(int bs, const double* B, const int64_t* nbr, int nf, int m, int64_t ne, const double* x,
+                            double* y, hipStream_t s) {
+  if (m < 1 || 4 * m > bs || ne < 1) return hipErrorInvalidValue;
+  const int R = bs / (4 * m);
+  const unsigned grid = (unsigned)((ne + R - 1) / R);
+  const size_t lds = ((size_t)R * (nf + 1) * m + bs) * sizeof(double);
+  switch (bs) {
+    case 256: k_bsr_apply<256><<<grid, 256, lds, s>>>(B, nbr, nf, m, ne, x, y); break;
+    case 512: k_bsr_apply<512><<<grid, 512, lds, s>>>(B, nbr, nf, m, ne, x, y); break;
+    case 1024: k_bsr_apply<1024><<<grid, 1024, lds, s>>>(B, nbr, nf, m, ne, x, y); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_gmres_init(double* sc, int m, hipStream_t s) {
+  k_gmres_init<<<1, 64, 0, s>>>(sc, m);
+  return hipGetLastError();
+}
+
+hipError_t launch_gmres_step(double* sc, int j, int m, hipStream_t s) {
+  k_gmres_step<<<1, 64, 0, s>>>(sc, j, m);
+  return hipGetLastError();
+}
+
+hipError_t launch_gmres_backsolve(double* sc, int m, hipStream_t s) {
+  k_gmres_backsolve<<<1, 64, 0, s>>>(sc, m);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_by(int64_t n, double* x, const double* sc, hipStream_t s) {
+  k_scale_by<<<grid_for(n), 256, 0, s>>>(n, x, sc);
+  return hipGetLastError();
+}
+
+}  // namespace dgk

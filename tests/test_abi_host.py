@@ -74,3 +74,6 @@ def test_null_arguments():
     assert lib.dg_create(None, None, None) == -1
     assert lib.dg_residual(None, None, None, None) == -1
     assert lib.dg_ndof(None) == -1
+    assert lib.dg_mg_setup(None, None, 0.0, None, None) == -1
+    assert lib.dg_mg_apply(None, None, None, None) == -1
+    assert lib.dg_mg_level_apply(None, 0, None, None, None) == -1
