@@ -100,8 +100,10 @@ def cpu_baseline(sample_elems=1024):
                       f"({dofs} DOFs), complex-step numpy oracle, {t:.2f} s"}
 
 
-def time_to_tolerance(storage="fp64"):
-    """Backward-Euler system of the P4 24^3 workload solved by FGMRES(30) to 1e-8."""
+def time_to_tolerance(storage="fp64", precond="bj"):
+    """Backward-Euler system of the P4 24^3 workload solved by FGMRES(30) to 1e-8,
+    preconditioned by block Jacobi or by the P4/P2/P1 p-multigrid V-cycle
+    (GMRES[EWBJ] smoothers 8/8/40, one captured graph per cycle)."""
     import torch
     import synth
     from paper_1809_00866_amd import DG
@@ -115,14 +117,19 @@ def time_to_tolerance(storage="fp64"):
     b = -g.residual(w)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    g.block_setup(w, shift, storage=storage)
+    if precond == "mg":
+        g.mg_setup(w, shift, cfg["mg_orders"], cfg["mg_smooth"], storage=storage, use_graph=True)
+    else:
+        g.block_setup(w, shift, storage=storage)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    x, st = g.fgmres(w, shift, b, restart=cfg["restart"], max_iter=3000, rtol=cfg["rtol"], precond="bj")
+    x, st = g.fgmres(w, shift, b, restart=cfg["restart"], max_iter=3000, rtol=cfg["rtol"], precond=precond)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     g.close()
-    return {"workload": "backward Euler, P4 24^3 hexes, CFL 100, FGMRES(30), block Jacobi " + storage,
+    name = ("p-multigrid V-cycle P4/P2/P1, GMRES[EWBJ] smoothers 8/8/40, " if precond == "mg"
+            else "block Jacobi ") + storage
+    return {"workload": "backward Euler, P4 24^3 hexes, CFL 100, FGMRES(30), " + name,
             "seconds": t2 - t0, "setup_s": t1 - t0, "solve_s": t2 - t1, "iters": st["iters"],
             "converged": bool(st["converged"]), "rel_res_true": st["rel_res_true"], "dt": dt}
 
@@ -202,6 +209,7 @@ def main():
         res["time_to_tol"] = time_to_tolerance("fp64")
         res["time_to_tol_fp32_blocks"] = time_to_tolerance("fp32")
         res["time_to_tol_bf16_blocks"] = time_to_tolerance("bf16")
+        res["time_to_tol_pmg"] = time_to_tolerance("fp64", precond="mg")
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(args.cpu_sample)
     print(json.dumps(res), flush=True)

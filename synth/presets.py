@@ -23,7 +23,7 @@ PRESETS = {
                  field="taylor_green", field_seed=1600, v_seed=866, perturb=0.0, mesh_seed=None),
     "cfg3": dict(dim=3, N=(24, 24, 24), L=2 * np.pi, space="P", order=4, nq1d=5, mu=1.0 / 1600.0,
                  field="taylor_green", field_seed=1600, v_seed=866, perturb=0.0, mesh_seed=None,
-                 cfl=100.0, restart=30, rtol=1e-8),
+                 cfl=100.0, mg_orders=(4, 2, 1), mg_smooth=(8, 8, 40), restart=30, rtol=1e-8),
     "cfg4": dict(dim=3, N=(24, 24, 24), L=2 * np.pi, space="P", order=4, nq1d=5, mu=1.0 / 1600.0,
                  field="taylor_green", field_seed=1600, v_seed=866, perturb=0.1, mesh_seed=2403,
                  cfl=100.0, mg_orders=(4, 2, 1), mg_smooth=(8, 8, 40), restart=30, rtol=1e-8),
