@@ -58,17 +58,6 @@ def n_params(n_in, n_out):
     return HIDDEN * n_in + HIDDEN + HIDDEN * HIDDEN + HIDDEN + n_out * HIDDEN + n_out
 
 
-def init_params(n_in, n_out, seed):
-    """He-uniform weights, zero biases (FP32 values)."""
-    rng = np.random.default_rng(seed)
-    parts = []
-    for fan_out, fan_in in [(HIDDEN, n_in), (HIDDEN, HIDDEN), (n_out, HIDDEN)]:
-        lim = np.sqrt(6.0 / fan_in)
-        parts.append(rng.uniform(-lim, lim, fan_out * fan_in))
-        parts.append(np.zeros(fan_out))
-    return np.concatenate(parts).astype(np.float32).astype(np.float64)
-
-
 def cell_means(o, U):
     """Cell means (1/|K|) int_K u_c of every element, [ne, nvar], by quadrature."""
     et = o.elem_tables(np.arange(o.ne))
@@ -100,21 +89,23 @@ def forward(theta, X, n_out, rounding=True):
 
 
 def loss_and_grad(theta, X, T, rounding=True):
-    """L = mean((Y - T)^2) over batch and outputs, and dL/dtheta (the rounding
-    to BF16 is passed through as the identity in the backward pass)."""
+    """L = mean((Y - T)^2) over batch and outputs, and dL/dtheta.  With
+    rounding, the output gradient and the back-propagated deltas are rounded
+    to BF16 like the activations (the device stores them so for its BF16
+    products); the rounding itself is differentiated as the identity."""
     n_out = T.shape[1]
     q = bf16_round if rounding else (lambda a: np.asarray(a, dtype=np.float64))
     W1, b1, W2, b2, W3, b3 = split(theta, X.shape[1], n_out)
     y, (x, a1, a2) = forward(theta, X, n_out, rounding)
     B = X.shape[0]
     L = np.mean((y - T) ** 2)
-    dy = 2.0 * (y - T) / (B * n_out)
+    dy = q(2.0 * (y - T) / (B * n_out))
     gW3 = dy.T @ a2
     gb3 = dy.sum(axis=0)
-    d2 = (dy @ q(W3)) * (a2 > 0)
+    d2 = q((dy @ q(W3)) * (a2 > 0))
     gW2 = d2.T @ a1
     gb2 = d2.sum(axis=0)
-    d1 = (d2 @ q(W2)) * (a1 > 0)
+    d1 = q((d2 @ q(W2)) * (a1 > 0))
     gW1 = d1.T @ x
     gb1 = d1.sum(axis=0)
     g = np.concatenate([gW1.ravel(), gb1, gW2.ravel(), gb2, gW3.ravel(), gb3])

@@ -9,7 +9,8 @@ flux, no projection.  It only builds
 * analytic initial fields, given as plain numpy functions of physical
   coordinates returning conserved variables (rho, rho*u_1..d, rho*E),
 * seeded random vectors (element-fastest flat layout),
-* the named workload presets (cfg1..cfg5) with their physical constants.
+* the named workload presets (cfg1..cfg5) with their physical constants,
+* seeded initial weights of the learned preconditioner's network.
 
 Each consumer (the oracle and the product library) projects the analytic
 fields onto its own basis with its own quadrature.
@@ -18,9 +19,10 @@ from .lattice import lattice_mesh, mesh_neighbors
 from .fields import (FreeStreamPlusModes, TaylorGreenStandIn, UniformState,
                      TrigSum, primitive_to_conserved)
 from .presets import PRESETS, preset, random_vector
+from .mlp_init import mlp_init_weights
 
 __all__ = [
     "lattice_mesh", "mesh_neighbors", "FreeStreamPlusModes", "TaylorGreenStandIn",
     "UniformState", "TrigSum", "primitive_to_conserved", "PRESETS", "preset",
-    "random_vector",
+    "random_vector", "mlp_init_weights",
 ]

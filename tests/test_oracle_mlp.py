@@ -7,8 +7,12 @@ import pytest
 
 import synth
 from oracle import DGOracle, NavierStokes
-from oracle.mlp import (adam_step, apply, bf16_round, cell_means, features, forward, init_params, loss_and_grad,
-                        n_params, sizes)
+from oracle.mlp import adam_step, apply, bf16_round, cell_means, features, forward, loss_and_grad, n_params, sizes
+from synth import mlp_init_weights
+
+
+def init_params(n_in, n_out, seed):
+    return mlp_init_weights(n_in, n_out, seed).astype(np.float64)
 
 
 def test_bf16_rounding_ties_to_even_and_matches_torch():
