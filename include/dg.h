@@ -17,6 +17,8 @@
  *   dg_mg_setup             p-multigrid V-cycle preconditioner (Sec. 2.4,
  *   dg_mg_apply             Alg. vcic) with inherited coarse operators
  *                           (eq. GalProj) and GMRES[EWBJ] smoothers
+ *   dg_mlp_*                learned element-local preconditioner, usable
+ *                           because the outer solver is flexible (Sec. 2.5)
  *
  * Conventions (all entry points):
  *  - Every vector is FP64, device memory, caller-owned, contiguous, in the
@@ -58,7 +60,7 @@ enum { DG_BASIS_PK = 0, DG_BASIS_QK = 1 };          /* total degree / tensor deg
 enum { DG_FLUX_LF = 0, DG_FLUX_ROE = 1 };           /* convective numerical flux */
 enum { DG_JVP_EXACT = 0, DG_JVP_FD = 1 };           /* Jv mode */
 enum { DG_FP64 = 0, DG_FP32 = 1, DG_BF16 = 2 };     /* block-factor storage */
-enum { DG_PREC_NONE = 0, DG_PREC_BJ = 1, DG_PREC_MG = 2 };  /* FGMRES preconditioner */
+enum { DG_PREC_NONE = 0, DG_PREC_BJ = 1, DG_PREC_MG = 2, DG_PREC_MLP = 3 };  /* FGMRES preconditioner */
 
 /* Discretisation parameters.
  *  dim 2 or 3; order k >= 0; basis DG_BASIS_PK (paper's total-degree space,
@@ -137,15 +139,22 @@ typedef struct {
   int restart;     /* Krylov subspace size m (default 30) */
   int max_iter;    /* total iteration cap */
   double rtol;     /* ||b - G x|| <= rtol*||b|| on the true residual */
-  int precond;     /* DG_PREC_NONE, DG_PREC_BJ (block setup must exist) or
-                      DG_PREC_MG (dg_mg_setup must exist, built with the same w, shift) */
+  int precond;     /* DG_PREC_NONE, DG_PREC_BJ (block setup must exist),
+                      DG_PREC_MG (dg_mg_setup must exist, built with the same w, shift)
+                      or DG_PREC_MLP (network weights set) */
   int jvp_mode;    /* DG_JVP_EXACT or DG_JVP_FD for G z */
+  double rho_ref;  /* DG_PREC_MLP only: if > 0 and a block setup exists, the
+                      solve switches to block Jacobi when the convergence
+                      factor (|g_j|/||r_0||)^(1/j) after judge_after
+                      iterations exceeds rho_ref (e.g. block Jacobi's) */
+  int judge_after; /* iterations before that check (<= 0 selects 5) */
 } dg_solve_opts;
 
 typedef struct {
   int iters, restarts, converged;
   double rel_res_est, rel_res_true, rho; /* rho: convergence factor */
   double ms_solve;
+  int fallbacks;   /* switches from DG_PREC_MLP to block Jacobi */
 } dg_solve_stats;
 
 /* Right-preconditioned flexible GMRES(m) for (shift*I + J(w)) x = b.
@@ -195,6 +204,40 @@ dg_status dg_mg_apply(dg_context* ctx, const double* r, double* z, void* stream)
 /* y = G_l x on level l (0 = fine, matrix-free; >= 1 = inherited block-sparse
  * operator), vectors in level l's DOF layout. */
 dg_status dg_mg_level_apply(dg_context* ctx, int level, const double* x, double* y, void* stream);
+
+/* Learned element-local preconditioner.  For element K with residual slice
+ * r_K (n*Nb values, local order c*Nb + b) and s_K = ||r_K||_2 + 1e-300 the
+ * features are x_K = [r_K / s_K, m(K_f)/m_ref for the 2d face neighbours K_f
+ * in the order -x,+x,-y,+y,-z,+z], with m the cell means of the n conserved
+ * variables of the state w and m_ref their RMS over the mesh
+ * (n_in = n*Nb + 2d*n).  Network n_in -> 256 -> 256 -> n*Nb with ReLU on the
+ * hidden layers; BF16 weights, activations and deltas, FP32 biases, MFMA
+ * products with FP32 accumulation; z_K = s_K * output.  Parameters: one
+ * flat FP32 vector W1 [256][n_in], b1 [256], W2 [256][256], b2 [256],
+ * W3 [n*Nb][256], b3 [n*Nb] (row-major), owned by the library (master copy,
+ * Adam moments, BF16 copies).  Training minimises the mean squared error
+ * over a batch of normalised pairs (x_K, z_K / s_K) with Adam (0.9, 0.999,
+ * 1e-8).  All arrays are device memory. */
+int64_t dg_mlp_nparams(dg_context* ctx);
+/* Copy the parameter vector in (resets the Adam state). */
+dg_status dg_mlp_set_weights(dg_context* ctx, const float* theta, void* stream);
+dg_status dg_mlp_get_weights(dg_context* ctx, float* theta, void* stream);
+/* Features X [n_elem][n_in] (FP32) for state w and residual r; optional
+ * normalised targets T [n_elem][n*Nb] = z_K / s_K (needs z) and scales
+ * s [n_elem] (FP64); T and s may be NULL. */
+dg_status dg_mlp_features(dg_context* ctx, const double* w, const double* r, const double* z, float* X, float* T,
+                          double* s, void* stream);
+/* Y [batch][n*Nb] = network(X [batch][n_in]) (normalised outputs). */
+dg_status dg_mlp_forward(dg_context* ctx, const float* X, int64_t batch, float* Y, void* stream);
+/* Gradient of the loss over rows[0..batch) of X / T (rows may be NULL for
+ * 0..batch-1) into grad (nparams FP32); loss (1 FP32) may be NULL. */
+dg_status dg_mlp_grad(dg_context* ctx, const float* X, const float* T, const int64_t* rows, int64_t batch,
+                      float* grad, float* loss, void* stream);
+/* One Adam step with learning rate lr on the same loss. */
+dg_status dg_mlp_train_step(dg_context* ctx, const float* X, const float* T, const int64_t* rows, int64_t batch,
+                            float lr, float* loss, void* stream);
+/* z = s_K * network(x_K(w, r)) for every element (DOF layout, FP64). */
+dg_status dg_mlp_apply(dg_context* ctx, const double* w, const double* r, double* z, void* stream);
 
 /* max over volume points of |u| + c, returned to host memory (synchronises). */
 dg_status dg_max_wave_speed(dg_context* ctx, const double* w, double* out, void* stream);

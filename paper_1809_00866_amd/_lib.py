@@ -15,11 +15,13 @@ DG_BASIS_PK, DG_BASIS_QK = 0, 1
 DG_FLUX_LF, DG_FLUX_ROE = 0, 1
 DG_JVP_EXACT, DG_JVP_FD = 0, 1
 DG_FP64, DG_FP32, DG_BF16 = 0, 1, 2
-DG_PREC_NONE, DG_PREC_BJ, DG_PREC_MG = 0, 1, 2
+DG_PREC_NONE, DG_PREC_BJ, DG_PREC_MG, DG_PREC_MLP = 0, 1, 2, 3
 
 EXPORTED = ["dg_create", "dg_destroy", "dg_ndof", "dg_nbasis", "dg_nvar", "dg_nq", "dg_volume_points",
             "dg_project", "dg_residual", "dg_jvp", "dg_block_precond_setup", "dg_block_precond_apply",
-            "dg_fgmres_solve", "dg_mg_setup", "dg_mg_apply", "dg_mg_level_apply", "dg_max_wave_speed",
+            "dg_fgmres_solve", "dg_mg_setup", "dg_mg_apply", "dg_mg_level_apply", "dg_mlp_nparams",
+            "dg_mlp_set_weights", "dg_mlp_get_weights", "dg_mlp_features", "dg_mlp_forward", "dg_mlp_grad",
+            "dg_mlp_train_step", "dg_mlp_apply", "dg_max_wave_speed",
             "dg_set_profiling", "dg_kernel_time", "dg_last_error", "dg_sync"]
 
 
@@ -36,7 +38,8 @@ class DGMesh(ctypes.Structure):
 
 class SolveOpts(ctypes.Structure):
     _fields_ = [("restart", ctypes.c_int), ("max_iter", ctypes.c_int), ("rtol", ctypes.c_double),
-                ("precond", ctypes.c_int), ("jvp_mode", ctypes.c_int)]
+                ("precond", ctypes.c_int), ("jvp_mode", ctypes.c_int), ("rho_ref", ctypes.c_double),
+                ("judge_after", ctypes.c_int)]
 
 
 class MgOpts(ctypes.Structure):
@@ -47,7 +50,7 @@ class MgOpts(ctypes.Structure):
 class SolveStats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("restarts", ctypes.c_int), ("converged", ctypes.c_int),
                 ("rel_res_est", ctypes.c_double), ("rel_res_true", ctypes.c_double), ("rho", ctypes.c_double),
-                ("ms_solve", ctypes.c_double)]
+                ("ms_solve", ctypes.c_double), ("fallbacks", ctypes.c_int)]
 
 
 _lib = None
@@ -80,6 +83,14 @@ def load():
         "dg_mg_setup": (i, [ctx, vp, d, ctypes.POINTER(MgOpts), vp]),
         "dg_mg_apply": (i, [ctx, vp, vp, vp]),
         "dg_mg_level_apply": (i, [ctx, i, vp, vp, vp]),
+        "dg_mlp_nparams": (i64, [ctx]),
+        "dg_mlp_set_weights": (i, [ctx, vp, vp]),
+        "dg_mlp_get_weights": (i, [ctx, vp, vp]),
+        "dg_mlp_features": (i, [ctx, vp, vp, vp, vp, vp, vp, vp]),
+        "dg_mlp_forward": (i, [ctx, vp, i64, vp, vp]),
+        "dg_mlp_grad": (i, [ctx, vp, vp, vp, i64, vp, vp, vp]),
+        "dg_mlp_train_step": (i, [ctx, vp, vp, vp, i64, ctypes.c_float, vp, vp]),
+        "dg_mlp_apply": (i, [ctx, vp, vp, vp, vp]),
         "dg_max_wave_speed": (i, [ctx, vp, ctypes.POINTER(ctypes.c_double), vp]),
         "dg_set_profiling": (i, [ctx, i]),
         "dg_kernel_time": (i, [ctx, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),

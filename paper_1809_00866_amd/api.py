@@ -15,7 +15,7 @@ _FLUX = {"lf": L.DG_FLUX_LF, "roe": L.DG_FLUX_ROE}
 _BASIS = {"P": L.DG_BASIS_PK, "Q": L.DG_BASIS_QK}
 _MODE = {"exact": L.DG_JVP_EXACT, "fd": L.DG_JVP_FD}
 _STORAGE = {"fp64": L.DG_FP64, "fp32": L.DG_FP32, "bf16": L.DG_BF16}
-_PREC = {"none": L.DG_PREC_NONE, "bj": L.DG_PREC_BJ, "mg": L.DG_PREC_MG}
+_PREC = {"none": L.DG_PREC_NONE, "bj": L.DG_PREC_BJ, "mg": L.DG_PREC_MG, "mlp": L.DG_PREC_MLP}
 
 
 def _stream():
@@ -153,11 +153,87 @@ class DG:
         L.check(self.lib.dg_mg_level_apply(self.ctx, int(level), _ptr(x), _ptr(y), _stream()), "dg_mg_level_apply")
         return y
 
-    def fgmres(self, w, shift, b, x=None, restart=30, max_iter=1000, rtol=1e-8, precond="bj", jvp_mode="exact"):
+    # ---------------------------------------------------------------- learned preconditioner
+    def _f32(self, t, name, n):
+        if not (isinstance(t, torch.Tensor) and t.dtype == torch.float32 and t.is_cuda and t.is_contiguous()
+                and t.numel() == n):
+            raise ValueError(f"{name} must be a contiguous float32 CUDA tensor with {n} entries")
+        return t
+
+    @property
+    def mlp_sizes(self):
+        n_out = self.nv * self.nb
+        return n_out + 2 * self.dim * self.nv, n_out
+
+    def mlp_nparams(self):
+        return int(self.lib.dg_mlp_nparams(self.ctx))
+
+    def mlp_set_weights(self, theta):
+        theta = torch.as_tensor(theta, dtype=torch.float32).to(self.device).contiguous()
+        self._f32(theta, "theta", self.mlp_nparams())
+        L.check(self.lib.dg_mlp_set_weights(self.ctx, _ptr(theta), _stream()), "dg_mlp_set_weights")
+
+    def mlp_get_weights(self):
+        out = torch.empty(self.mlp_nparams(), dtype=torch.float32, device=self.device)
+        L.check(self.lib.dg_mlp_get_weights(self.ctx, _ptr(out), _stream()), "dg_mlp_get_weights")
+        return out
+
+    def mlp_features(self, w, r, z=None):
+        """(X [ne, n_in], T [ne, n_out] or None, s [ne]) for state w, residual r, optional target z."""
+        self._vec(w, "w")
+        self._vec(r, "r")
+        n_in, n_out = self.mlp_sizes
+        X = torch.empty((self.ne, n_in), dtype=torch.float32, device=self.device)
+        T = None if z is None else torch.empty((self.ne, n_out), dtype=torch.float32, device=self.device)
+        s = torch.empty(self.ne, dtype=torch.float64, device=self.device)
+        if z is not None:
+            self._vec(z, "z")
+        L.check(self.lib.dg_mlp_features(self.ctx, _ptr(w), _ptr(r), _ptr(z), _ptr(X), _ptr(T), _ptr(s), _stream()),
+                "dg_mlp_features")
+        return X, T, s
+
+    def mlp_forward(self, X):
+        n_in, n_out = self.mlp_sizes
+        X = X.contiguous()
+        self._f32(X, "X", X.shape[0] * n_in)
+        Y = torch.empty((X.shape[0], n_out), dtype=torch.float32, device=self.device)
+        L.check(self.lib.dg_mlp_forward(self.ctx, _ptr(X), X.shape[0], _ptr(Y), _stream()), "dg_mlp_forward")
+        return Y
+
+    def _batch(self, X, T, rows):
+        n_in, n_out = self.mlp_sizes
+        self._f32(X, "X", X.shape[0] * n_in)
+        self._f32(T, "T", X.shape[0] * n_out)
+        if rows is not None and not (rows.dtype == torch.int64 and rows.is_cuda and rows.is_contiguous()):
+            raise ValueError("rows must be a contiguous int64 CUDA tensor")
+        return rows.numel() if rows is not None else X.shape[0]
+
+    def mlp_grad(self, X, T, rows=None):
+        B = self._batch(X, T, rows)
+        g = torch.empty(self.mlp_nparams(), dtype=torch.float32, device=self.device)
+        loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        L.check(self.lib.dg_mlp_grad(self.ctx, _ptr(X), _ptr(T), _ptr(rows), B, _ptr(g), _ptr(loss), _stream()),
+                "dg_mlp_grad")
+        return g, loss
+
+    def mlp_train_step(self, X, T, rows=None, lr=1e-3, loss=None):
+        B = self._batch(X, T, rows)
+        L.check(self.lib.dg_mlp_train_step(self.ctx, _ptr(X), _ptr(T), _ptr(rows), B, float(lr), _ptr(loss),
+                                           _stream()), "dg_mlp_train_step")
+
+    def mlp_apply(self, w, r, out=None):
+        self._vec(w, "w")
+        self._vec(r, "r")
+        out = self.empty() if out is None else self._vec(out, "out")
+        L.check(self.lib.dg_mlp_apply(self.ctx, _ptr(w), _ptr(r), _ptr(out), _stream()), "dg_mlp_apply")
+        return out
+
+    def fgmres(self, w, shift, b, x=None, restart=30, max_iter=1000, rtol=1e-8, precond="bj", jvp_mode="exact",
+               rho_ref=0.0, judge_after=5):
         self._vec(w, "w")
         self._vec(b, "b")
         x = torch.zeros_like(b) if x is None else self._vec(x, "x")
-        opts = L.SolveOpts(restart, max_iter, rtol, _PREC[precond], _MODE[jvp_mode])
+        opts = L.SolveOpts(restart, max_iter, rtol, _PREC[precond], _MODE[jvp_mode], float(rho_ref), int(judge_after))
         st = L.SolveStats()
         status = self.lib.dg_fgmres_solve(self.ctx, _ptr(w), float(shift), _ptr(b), _ptr(x), ctypes.byref(opts),
                                           ctypes.byref(st), _stream())

@@ -285,6 +285,7 @@ void dg_destroy(dg_context* c) {
   dfree(c->d_V);
   dfree(c->d_Z);
   mg_destroy(c->mg);
+  mlp_destroy(c->mlp);
   if (c->h_pin) (void)hipHostFree(c->h_pin);
   delete c;
 }
@@ -402,8 +403,10 @@ dg_status dg_fgmres_solve(dg_context* c, const double* w, double shift, const do
   if (x == b || x == w) return fail(DG_ERR_ARG, "x may not alias w or b");
   const int m = opts->restart > 0 ? opts->restart : 30;
   if (m > 60) return fail(DG_ERR_ARG, "restart above 60");
-  if (opts->precond != DG_PREC_NONE && opts->precond != DG_PREC_BJ && opts->precond != DG_PREC_MG)
+  if (opts->precond != DG_PREC_NONE && opts->precond != DG_PREC_BJ && opts->precond != DG_PREC_MG &&
+      opts->precond != DG_PREC_MLP)
     return fail(DG_ERR_ARG, "unknown precond");
+  if (opts->precond == DG_PREC_MLP && !mlp_ready(c->mlp)) return fail(DG_ERR_STATE, "network weights not set");
   if (opts->precond == DG_PREC_BJ && !c->blk_ready) return fail(DG_ERR_STATE, "block preconditioner not set up");
   if (opts->precond == DG_PREC_MG && !mg_ready(c->mg)) return fail(DG_ERR_STATE, "p-multigrid not set up");
   if (opts->jvp_mode != DG_JVP_EXACT && opts->jvp_mode != DG_JVP_FD) return fail(DG_ERR_ARG, "unknown jvp mode");
@@ -429,9 +432,13 @@ dg_status dg_fgmres_solve(dg_context* c, const double* w, double shift, const do
     rw = c->d_rw;
   }
   auto applyG = [&](const double* z, double* outv) { return jvp_impl(c, w, rw, z, shift, opts->jvp_mode, outv, s); };
+  int prec = opts->precond;  // the learned preconditioner may fall back to block Jacobi
+  const int judge_after = opts->judge_after > 0 ? opts->judge_after : 5;
+  int fallbacks = 0;
   auto applyM = [&](const double* v, double* z) -> dg_status {
-    if (opts->precond == DG_PREC_MG) return mg_apply(c, v, z, s);
-    if (opts->precond == DG_PREC_BJ) {
+    if (prec == DG_PREC_MG) return mg_apply(c, v, z, s);
+    if (prec == DG_PREC_MLP) return mlp_apply(c, w, v, z, s);
+    if (prec == DG_PREC_BJ) {
       ProfScope ps(c, "block_apply", s);
       HIPCHK(dgk::launch_block_apply(c->blk_storage, c->d_Dinv, c->nv * c->nb, c->ne, v, z, s));
       return DG_OK;
@@ -521,6 +528,16 @@ dg_status dg_fgmres_solve(dg_context* c, const double* w, double shift, const do
       k = j + 1;
       ++iters;
       est = std::fabs(g[j + 1]);
+      // judge of the learned preconditioner: a convergence factor above the
+      // reference one after judge_after iterations switches to block Jacobi
+      // (legal in flexible GMRES: every z_j is stored)
+      if (prec == DG_PREC_MLP && opts->rho_ref > 0.0 && iters == judge_after && c->blk_ready && d0 > 0.0) {
+        const double rho_now = std::exp(std::log(std::max(est, 1e-300) / d0) / iters);
+        if (rho_now > opts->rho_ref) {
+          prec = DG_PREC_BJ;
+          ++fallbacks;
+        }
+      }
       const bool brk = hn <= 1e-14 * w0;
       if (est <= rtol * bnorm || brk || iters >= max_iter) break;
       HIPCHK(dgk::launch_scale_dev(n, Wn, dS + 3, Wn, s));
@@ -543,6 +560,7 @@ dg_status dg_fgmres_solve(dg_context* c, const double* w, double shift, const do
     ++S.restarts;
   }
   S.iters = iters;
+  S.fallbacks = fallbacks;
   S.converged = converged ? 1 : 0;
   S.rel_res_est = est / bnorm;
   S.rel_res_true = beta / bnorm;

@@ -48,6 +48,11 @@ void mg_destroy(MgState* m);
 void mg_invalidate(MgState* m);  // the fine block factors changed
 bool mg_ready(const MgState* m);
 
+// learned preconditioner state (mlp.cpp)
+struct MlpState;
+void mlp_destroy(MlpState* m);
+bool mlp_ready(const MlpState* m);
+
 }  // namespace dgc
 
 struct dg_context {
@@ -84,7 +89,8 @@ struct dg_context {
   double* h_pin = nullptr;
   bool prof = false;
   std::map<std::string, dgc::Timer> timers;
-  dgc::MgState* mg = nullptr;  // p-multigrid preconditioner (dg_mg_setup)
+  dgc::MgState* mg = nullptr;    // p-multigrid preconditioner (dg_mg_setup)
+  dgc::MlpState* mlp = nullptr;  // learned preconditioner (dg_mlp_*)
 };
 
 
@@ -122,5 +128,7 @@ dg_status jvp_impl(dg_context* c, const double* w, const double* r_w, const doub
 
 // z = MG_V(0, r, 0) with the context's p-multigrid state (must be ready).
 dg_status mg_apply(dg_context* c, const double* r, double* z, hipStream_t s);
+// z = s_K MLP(x_K(w, r)) for every element (weights must be set).
+dg_status mlp_apply(dg_context* c, const double* w, const double* r, double* z, hipStream_t s);
 
 }  // namespace dgc

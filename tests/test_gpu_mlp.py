@@ -1,0 +1,152 @@
+"""GPU parity of the learned element-local preconditioner against the FP64 oracle
+(oracle/mlp.py), through the C ABI.
+
+Both sides take the same BF16-rounded inputs and weights; the device
+accumulates in FP32 and stores activations and deltas in BF16, the oracle
+accumulates in FP64 and rounds at the same places.  A rounding decision taken
+on an FP32 instead of an FP64 sum can differ by one BF16 unit (2^-8 relative)
+on isolated entries, so the bounds are norm-relative: 1e-3 for forward
+outputs, gradients and the preconditioned vector, 1e-6 for the FP32 features.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import DGOracle, NavierStokes
+from oracle import mlp as om
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    return np.linalg.norm(np.asarray(a, dtype=np.float64) - b) / max(np.linalg.norm(b), 1e-300)
+
+
+@pytest.fixture(scope="module")
+def setup():
+    from paper_1809_00866_amd import DG
+    mesh = synth.lattice_mesh((3, 2, 4), L=1.0)
+    o = DGOracle(mesh, 3, "P", 4, NavierStokes(3, mu=1e-2))
+    U = o.project(synth.TaylorGreenStandIn(seed=31, L=1.0))
+    g = DG(mesh, 3, nq1d=4, mu=1e-2)
+    w = torch.tensor(o.to_flat(U), device="cuda")
+    n_in, n_out = g.mlp_sizes
+    theta = synth.mlp_init_weights(n_in, n_out, seed=1809)
+    # non-zero biases so every term is exercised
+    k1 = 256 * n_in
+    theta[k1:k1 + 256] = 0.05 * np.random.default_rng(1).standard_normal(256).astype(np.float32)
+    theta[-n_out:] = 0.05 * np.random.default_rng(2).standard_normal(n_out).astype(np.float32)
+    g.mlp_set_weights(torch.from_numpy(theta))
+    yield dict(o=o, U=U, g=g, w=w, theta=theta.astype(np.float64), n_in=n_in, n_out=n_out)
+    g.close()
+
+
+def test_features_parity(setup):
+    o, U, g, w = setup["o"], setup["U"], setup["g"], setup["w"]
+    _say("mlp features parity")
+    R = np.random.default_rng(3).standard_normal(U.shape)
+    Z = np.random.default_rng(4).standard_normal(U.shape)
+    X, T, s = g.mlp_features(w, torch.tensor(o.to_flat(R), device="cuda"), torch.tensor(o.to_flat(Z), device="cuda"))
+    Xo, so = om.features(o, U, R)
+    assert rel(X.cpu().numpy(), Xo) <= 1e-6
+    assert rel(s.cpu().numpy(), so) <= 1e-13
+    assert rel(T.cpu().numpy(), Z.reshape(o.ne, -1) / so[:, None]) <= 1e-6
+
+
+def test_forward_and_gradient_parity(setup):
+    g, theta, n_in, n_out = setup["g"], setup["theta"], setup["n_in"], setup["n_out"]
+    _say("mlp forward/gradient parity")
+    rng = np.random.default_rng(5)
+    for B in (1, 37, 256):                                  # ragged batches against the 32-row k-step
+        X = rng.standard_normal((B, n_in)).astype(np.float32)
+        T = (0.1 * rng.standard_normal((B, n_out))).astype(np.float32)
+        Xd, Td = torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda()
+        Y = g.mlp_forward(Xd).cpu().numpy()
+        Yo, _ = om.forward(theta, X.astype(np.float64), n_out)
+        assert rel(Y, Yo) <= 1e-3, (B, rel(Y, Yo))
+        gd, loss = g.mlp_grad(Xd, Td)
+        Lo, go = om.loss_and_grad(theta, X.astype(np.float64), T.astype(np.float64))
+        assert abs(loss.item() - Lo) <= 1e-4 * Lo
+        gd = gd.cpu().numpy()
+        parts_o = om.split(go, n_in, n_out)
+        parts_g = om.split(gd.astype(np.float64), n_in, n_out)
+        for name, a, b in zip(("W1", "b1", "W2", "b2", "W3", "b3"), parts_g, parts_o):
+            assert rel(a, b) <= 1e-3, (B, name, rel(a, b))
+
+
+def test_row_selection_equals_the_gathered_batch(setup):
+    g, n_in, n_out = setup["g"], setup["n_in"], setup["n_out"]
+    rng = np.random.default_rng(6)
+    X = torch.from_numpy(rng.standard_normal((100, n_in)).astype(np.float32)).cuda()
+    T = torch.from_numpy(rng.standard_normal((100, n_out)).astype(np.float32)).cuda()
+    rows = torch.tensor([5, 99, 0, 42, 42, 7], dtype=torch.int64, device="cuda")
+    g1, l1 = g.mlp_grad(X, T, rows)
+    g2, l2 = g.mlp_grad(X[rows].contiguous(), T[rows].contiguous())
+    assert torch.equal(g1, g2) and torch.equal(l1, l2)
+
+
+def test_adam_steps_match_the_oracle_and_reduce_the_loss(setup):
+    from paper_1809_00866_amd import DG
+    o = setup["o"]
+    _say("mlp training steps")
+    g = DG(synth.lattice_mesh((3, 2, 4), L=1.0), 3, nq1d=4, mu=1e-2)
+    n_in, n_out = g.mlp_sizes
+    theta = synth.mlp_init_weights(n_in, n_out, seed=7).astype(np.float64)
+    g.mlp_set_weights(torch.from_numpy(theta.astype(np.float32)))
+    rng = np.random.default_rng(8)
+    X = rng.standard_normal((512, n_in)).astype(np.float32)
+    T = (0.3 * np.tanh(X[:, :n_out])).astype(np.float32)
+    Xd, Td = torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda()
+    lr = 1e-3
+    # first step: Adam moves every parameter by lr * g / (|g| + eps) -- compare where the
+    # gradient is well above its rounding noise
+    _, go = om.loss_and_grad(theta, X.astype(np.float64), T.astype(np.float64))
+    g.mlp_train_step(Xd, Td, lr=lr)
+    th1 = g.mlp_get_weights().cpu().numpy().astype(np.float64)
+    th_o, _, _ = om.adam_step(theta, go, np.zeros_like(theta), np.zeros_like(theta), 1, lr=lr)
+    big = np.abs(go) > 1e-2 * np.abs(go).max()
+    assert np.abs(th1 - th_o)[big].max() <= 1e-6
+    assert np.abs(th1 - th_o).max() <= 2 * lr + 1e-6
+    losses = []
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    for _ in range(100):
+        g.mlp_train_step(Xd, Td, lr=lr, loss=loss)
+        losses.append(loss.item())
+    assert losses[-1] < 0.5 * losses[0]
+    g.close()
+
+
+def test_apply_parity_and_homogeneity(setup):
+    o, U, g, w, theta = setup["o"], setup["U"], setup["g"], setup["w"], setup["theta"]
+    _say("mlp apply parity")
+    R = np.random.default_rng(9).standard_normal(U.shape)
+    r = torch.tensor(o.to_flat(R), device="cuda")
+    z = g.mlp_apply(w, r).cpu().numpy()
+    zo = o.to_flat(om.apply(o, theta, U, R))
+    assert rel(z, zo) <= 1e-3
+    z4 = g.mlp_apply(w, 4.0 * r).cpu().numpy()
+    assert np.array_equal(z4, 4.0 * z)
+
+
+def test_fgmres_with_the_network_and_its_judge(setup):
+    o, U, g, w = setup["o"], setup["U"], setup["g"], setup["w"]
+    _say("fgmres with the network")
+    shift = 20.0
+    b = torch.tensor(o.to_flat(np.random.default_rng(10).standard_normal(U.shape)), device="cuda")
+    g.block_setup(w, shift)
+    _, st_bj = g.fgmres(w, shift, b, rtol=1e-10, max_iter=2000, precond="bj")
+    # an untrained network is a poor preconditioner: the judge hands over to block Jacobi
+    x, st = g.fgmres(w, shift, b, rtol=1e-10, max_iter=2000, precond="mlp", rho_ref=st_bj["rho"], judge_after=5)
+    assert st["converged"] == 1 and st["rel_res_true"] <= 1e-10
+    assert st["fallbacks"] == 1
+    X = o.from_flat(x.cpu().numpy())
+    res = np.linalg.norm(o.to_flat(o.operator(U, X, shift)) - b.cpu().numpy()) / b.norm().item()
+    assert res <= 1e-9
