@@ -134,6 +134,75 @@ def time_to_tolerance(storage="fp64", precond="bj"):
             "converged": bool(st["converged"]), "rel_res_true": st["rel_res_true"], "dt": dt}
 
 
+def learned_preconditioner(train_steps=3000, max_iter=300):
+    """The learned element-local preconditioner on the P3 32^3 workload:
+    training pairs from backward-Euler snapshots 0, 2, 4 (CFL 100), 1e5 pairs
+    sampled, Adam with batch 1024; evaluation on the held-out snapshot 6
+    system against block Jacobi, no preconditioner, the untrained network and
+    the p-multigrid V-cycle."""
+    import torch
+    import synth
+    from paper_1809_00866_amd import DG
+    from paper_1809_00866_amd import learned as LR
+    cfg, mesh, fld = synth.preset("cfg5")
+    g = DG(mesh, cfg["order"], basis=cfg["space"], nq1d=cfg["nq1d"], flux="roe", mu=cfg["mu"])
+    h = float(np.min(mesh["h"]))
+    t0 = time.perf_counter()
+    states = LR.trajectory(g, g.project_field(fld), 6, cfg["cfl"], cfg["order"], h)
+    shifts = [LR.time_step(g, s, cfg["cfl"], cfg["order"], h) for s in states]
+    XT = [LR.pairs(g, states[k], shifts[k]) for k in (0, 2, 4)]
+    X = torch.cat([a for a, _ in XT])
+    T = torch.cat([b for _, b in XT])
+    Xv, Tv = LR.pairs(g, states[6], shifts[6])
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    n_in, n_out = g.mlp_sizes
+    theta0 = torch.from_numpy(synth.mlp_init_weights(n_in, n_out, seed=1809))
+    g.mlp_set_weights(theta0)
+    sub = torch.randperm(X.shape[0], generator=torch.Generator().manual_seed(0))[:100000].cuda()
+    Xt, Tt = X[sub].contiguous(), T[sub].contiguous()
+    val0 = LR.validation_loss(g, Xv, Tv)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    hist = LR.train(g, Xt, Tt, train_steps, batch=1024, lr=1e-3, seed=0)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    val1 = LR.validation_loss(g, Xv, Tv)
+    w6, sh6 = states[6], shifts[6]
+    b = -g.residual(w6)
+    g.block_setup(w6, sh6)
+    held = {}
+
+    def run(name, **kw):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        _, st = g.fgmres(w6, sh6, b, rtol=1e-8, max_iter=max_iter, **kw)
+        torch.cuda.synchronize()
+        held[name] = {"iters": st["iters"], "converged": bool(st["converged"]), "rel_res_true": st["rel_res_true"],
+                      "rho": st["rho"], "fallbacks": st["fallbacks"], "seconds": time.perf_counter() - a}
+
+    run("block_jacobi", precond="bj")
+    run("none", precond="none")
+    run("learned", precond="mlp")
+    run("learned_with_judge", precond="mlp", rho_ref=held["block_jacobi"]["rho"])
+    g.mlp_set_weights(theta0)
+    run("untrained", precond="mlp")
+    orders, its = LR.mg_levels(cfg["order"])
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    g.mg_setup(w6, sh6, orders, its)
+    torch.cuda.synchronize()
+    mg_setup_s = time.perf_counter() - a
+    run("p_multigrid", precond="mg")
+    held["p_multigrid"]["setup_s"] = mg_setup_s
+    g.close()
+    return {"workload": "P3 32^3, backward-Euler snapshots 0/2/4 (train) and 6 (held out), CFL 100",
+            "pairs_available": int(X.shape[0]), "pairs_train": int(Xt.shape[0]), "pairs_val": int(Xv.shape[0]),
+            "train_steps": train_steps, "batch": 1024, "data_s": t_data, "train_s": t_train,
+            "loss_first": float(hist[0]), "loss_last": float(hist[-1]), "val_loss_untrained": val0,
+            "val_loss_trained": val1, "held_out_solve_to_1e-8": held}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -142,6 +211,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=8192)
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner experiment")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -210,6 +280,8 @@ def main():
         res["time_to_tol_fp32_blocks"] = time_to_tolerance("fp32")
         res["time_to_tol_bf16_blocks"] = time_to_tolerance("bf16")
         res["time_to_tol_pmg"] = time_to_tolerance("fp64", precond="mg")
+    if not args.no_learned:
+        res["learned_precond"] = learned_preconditioner()
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(args.cpu_sample)
     print(json.dumps(res), flush=True)

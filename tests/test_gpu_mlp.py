@@ -150,3 +150,24 @@ def test_fgmres_with_the_network_and_its_judge(setup):
     X = o.from_flat(x.cpu().numpy())
     res = np.linalg.norm(o.to_flat(o.operator(U, X, shift)) - b.cpu().numpy()) / b.norm().item()
     assert res <= 1e-9
+
+
+def test_training_workflow_on_a_small_trajectory():
+    """Backward-Euler snapshots -> pairs -> Adam: the held-out loss drops."""
+    from paper_1809_00866_amd import DG
+    from paper_1809_00866_amd import learned as LR
+    _say("learned workflow")
+    cfg, mesh, fld = synth.preset("cfg5", N=(4, 4, 4), order=2, nq1d=3)
+    g = DG(mesh, 2, nq1d=3, mu=cfg["mu"])
+    h = float(np.min(mesh["h"]))
+    states = LR.trajectory(g, g.project_field(fld), 2, cfg["cfl"], 2, h)
+    X, T = LR.pairs(g, states[0], LR.time_step(g, states[0], cfg["cfl"], 2, h))
+    Xv, Tv = LR.pairs(g, states[2], LR.time_step(g, states[2], cfg["cfl"], 2, h))
+    assert X.shape == (3 * g.ne, g.mlp_sizes[0]) and torch.isfinite(X).all() and torch.isfinite(T).all()
+    n_in, n_out = g.mlp_sizes
+    g.mlp_set_weights(torch.from_numpy(synth.mlp_init_weights(n_in, n_out, seed=3)))
+    v0 = LR.validation_loss(g, Xv, Tv)
+    hist = LR.train(g, X, T, 300, batch=64, lr=1e-3, seed=1)
+    assert hist[-10:].mean() < 0.5 * hist[:10].mean()
+    assert LR.validation_loss(g, Xv, Tv) < v0
+    g.close()
