@@ -100,7 +100,7 @@ def cpu_baseline(sample_elems=1024):
                       f"({dofs} DOFs), complex-step numpy oracle, {t:.2f} s"}
 
 
-def time_to_tolerance(storage="fp64", precond="bj"):
+def time_to_tolerance(storage="fp64", precond="bj", fine_precision="fp64"):
     """Backward-Euler system of the P4 24^3 workload solved by FGMRES(30) to 1e-8,
     preconditioned by block Jacobi or by the P4/P2/P1 p-multigrid V-cycle
     (GMRES[EWBJ] smoothers 8/8/40, one captured graph per cycle)."""
@@ -118,7 +118,8 @@ def time_to_tolerance(storage="fp64", precond="bj"):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     if precond == "mg":
-        g.mg_setup(w, shift, cfg["mg_orders"], cfg["mg_smooth"], storage=storage, use_graph=True)
+        g.mg_setup(w, shift, cfg["mg_orders"], cfg["mg_smooth"], storage=storage, use_graph=True,
+                   fine_precision=fine_precision)
     else:
         g.block_setup(w, shift, storage=storage)
     torch.cuda.synchronize()
@@ -127,8 +128,8 @@ def time_to_tolerance(storage="fp64", precond="bj"):
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     g.close()
-    name = ("p-multigrid V-cycle P4/P2/P1, GMRES[EWBJ] smoothers 8/8/40, " if precond == "mg"
-            else "block Jacobi ") + storage
+    name = (f"p-multigrid V-cycle P4/P2/P1, GMRES[EWBJ] smoothers 8/8/40, {fine_precision} fine operator, "
+            if precond == "mg" else "block Jacobi ") + storage
     return {"workload": "backward Euler, P4 24^3 hexes, CFL 100, FGMRES(30), " + name,
             "seconds": t2 - t0, "setup_s": t1 - t0, "solve_s": t2 - t1, "iters": st["iters"],
             "converged": bool(st["converged"]), "rel_res_true": st["rel_res_true"], "dt": dt}
@@ -245,6 +246,20 @@ def main():
     g.set_profiling(False)
     kt = {k: g.kernel_time(k) for k in ("face_jvp", "vol_jvp")}
     assert torch.isfinite(out).all()
+    # the reduced-precision operator (FP32 contractions and fluxes) on the same
+    # workload, reported beside the FP64 metric (it serves preconditioners only)
+    out32 = g.empty()
+    for _ in range(args.warmup):
+        g.jvp(w, v, out=out32, mode="exact_fp32")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g.jvp(w, v, out=out32, mode="exact_fp32")
+    torch.cuda.synchronize()
+    wall32 = time.perf_counter() - t0
+    jv_fp32 = {"value": g.ndof / (wall32 / args.steps), "unit": "DOFs/s", "ms_per_step": wall32 * 1e3 / args.steps,
+               "rel_diff_vs_fp64": float((out32 - out).norm() / out.norm())}
+    del out32
     ms_per_step = wall * 1e3 / args.steps
     value = g.ndof / (wall / args.steps)
 
@@ -274,12 +289,13 @@ def main():
            "config": {"workload": "exact Jv, 3D compressible NS, P3 (Nb=20), 32^3 periodic hexes, 4^3/4^2 Gauss, "
                                   "Roe + BR2, Taylor-Green-like field Mach 0.1 Re 1600",
                       "n_elem": int(32 ** 3), "ndof": int(32 ** 3 * 100), "dofs_per_variable": int(32 ** 3 * 20)},
-           "roofline": roofline}
+           "roofline": roofline, "jv_fp32": jv_fp32}
     if not args.no_solve:
         res["time_to_tol"] = time_to_tolerance("fp64")
         res["time_to_tol_fp32_blocks"] = time_to_tolerance("fp32")
         res["time_to_tol_bf16_blocks"] = time_to_tolerance("bf16")
         res["time_to_tol_pmg"] = time_to_tolerance("fp64", precond="mg")
+        res["time_to_tol_pmg_fp32_smoothing"] = time_to_tolerance("fp32", precond="mg", fine_precision="fp32")
     if not args.no_learned:
         res["learned_precond"] = learned_preconditioner()
     if not args.no_cpu_baseline:

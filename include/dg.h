@@ -58,7 +58,7 @@ typedef enum {
 
 enum { DG_BASIS_PK = 0, DG_BASIS_QK = 1 };          /* total degree / tensor degree */
 enum { DG_FLUX_LF = 0, DG_FLUX_ROE = 1 };           /* convective numerical flux */
-enum { DG_JVP_EXACT = 0, DG_JVP_FD = 1 };           /* Jv mode */
+enum { DG_JVP_EXACT = 0, DG_JVP_FD = 1, DG_JVP_EXACT_FP32 = 2 };  /* Jv mode */
 enum { DG_FP64 = 0, DG_FP32 = 1, DG_BF16 = 2 };     /* block-factor storage */
 enum { DG_PREC_NONE = 0, DG_PREC_BJ = 1, DG_PREC_MG = 2, DG_PREC_MLP = 3 };  /* FGMRES preconditioner */
 
@@ -111,12 +111,20 @@ dg_status dg_project(dg_context* ctx, const double* f, double* w, void* stream);
  * the numerical flux against the jump of phi; BR2 corrected gradients. */
 dg_status dg_residual(dg_context* ctx, const double* w, double* r, void* stream);
 
+/* The same residual with FP32 contractions (MFMA, FP32 accumulation) and FP32
+ * pointwise fluxes; w and r stay FP64.  3D P2-P4 configurations only
+ * (DG_ERR_ARG otherwise).  A reduced-precision operator for preconditioners
+ * and smoothers; relative error of order 1e-6 against the FP64 residual. */
+dg_status dg_residual_fp32(dg_context* ctx, const double* w, double* r, void* stream);
+
 /* out = shift*v + J(w) v.
  *  mode DG_JVP_EXACT: exact directional derivative of the residual (the
  *  Jacobian forms j_h of Sec. 2.2 applied to v), FP64.
  *  mode DG_JVP_FD: (f_h(w + D v) - f_h(w))/D with D = 1e-9*sqrt(1+||w||)/||v||
  *  (eqs. matrix-free, epsdef; L2 norms = DOF 2-norms).  r_w may pass f_h(w)
  *  (device, nullable) to skip its evaluation.  ||v|| = 0 gives out = 0 + shift*v.
+ *  mode DG_JVP_EXACT_FP32: the exact tangent computed like dg_residual_fp32
+ *  (FP32 contractions and pointwise arithmetic; for preconditioners only).
  *  out may not alias w, v or r_w. */
 dg_status dg_jvp(dg_context* ctx, const double* w, const double* r_w, const double* v, double shift,
                  int mode, double* out, void* stream);
@@ -142,7 +150,7 @@ typedef struct {
   int precond;     /* DG_PREC_NONE, DG_PREC_BJ (block setup must exist),
                       DG_PREC_MG (dg_mg_setup must exist, built with the same w, shift)
                       or DG_PREC_MLP (network weights set) */
-  int jvp_mode;    /* DG_JVP_EXACT or DG_JVP_FD for G z */
+  int jvp_mode;    /* DG_JVP_EXACT or DG_JVP_FD for G z (the outer operator stays FP64) */
   double rho_ref;  /* DG_PREC_MLP only: if > 0 and a block setup exists, the
                       solve switches to block Jacobi when the convergence
                       factor (|g_j|/||r_0||)^(1/j) after judge_after
@@ -185,6 +193,10 @@ typedef struct {
   int use_graph;        /* nonzero: capture one V-cycle into a hipGraph at setup;
                            every apply replays it on a library stream ordered
                            against the caller's stream by events */
+  int fine_precision;   /* DG_FP64 or DG_FP32: the fine-level operator inside
+                           the cycle (smoother products and the defect) as the
+                           exact FP64 Jv or its FP32 variant; coarse operators,
+                           the probing and the outer solve stay FP64 */
 } dg_mg_opts;
 
 /* Builds the hierarchy at state w (device, copied) and shift: runs the fine
@@ -245,8 +257,9 @@ dg_status dg_max_wave_speed(dg_context* ctx, const double* w, double* out, void*
 /* Per-kernel timing: when enabled, the library records HIP events around
  * each launch on the launch stream; dg_kernel_time returns the accumulated
  * milliseconds and launch count of a named kernel ("face_jvp", "vol_jvp",
- * "face_res", "vol_res", "block_probe", "block_invert", "block_apply",
- * "arnoldi", "mg_probe", "mg_vcycle") and resets it.  Synchronises. */
+ * "face_res", "vol_res", "face_jvp_f32", "vol_jvp_f32", "block_probe",
+ * "block_invert", "block_apply", "arnoldi", "mg_probe", "mg_vcycle",
+ * "mlp_apply") and resets it.  Synchronises. */
 dg_status dg_set_profiling(dg_context* ctx, int on);
 dg_status dg_kernel_time(dg_context* ctx, const char* name, double* ms, int64_t* launches);
 

@@ -13,12 +13,12 @@ STATUS_NAMES = {0: "DG_OK", 1: "DG_NOT_CONVERGED", -1: "DG_ERR_ARG", -2: "DG_ERR
                 -4: "DG_ERR_STATE", -5: "DG_ERR_SINGULAR_BLOCK", -6: "DG_ERR_NONFINITE"}
 DG_BASIS_PK, DG_BASIS_QK = 0, 1
 DG_FLUX_LF, DG_FLUX_ROE = 0, 1
-DG_JVP_EXACT, DG_JVP_FD = 0, 1
+DG_JVP_EXACT, DG_JVP_FD, DG_JVP_EXACT_FP32 = 0, 1, 2
 DG_FP64, DG_FP32, DG_BF16 = 0, 1, 2
 DG_PREC_NONE, DG_PREC_BJ, DG_PREC_MG, DG_PREC_MLP = 0, 1, 2, 3
 
 EXPORTED = ["dg_create", "dg_destroy", "dg_ndof", "dg_nbasis", "dg_nvar", "dg_nq", "dg_volume_points",
-            "dg_project", "dg_residual", "dg_jvp", "dg_block_precond_setup", "dg_block_precond_apply",
+            "dg_project", "dg_residual", "dg_residual_fp32", "dg_jvp", "dg_block_precond_setup", "dg_block_precond_apply",
             "dg_fgmres_solve", "dg_mg_setup", "dg_mg_apply", "dg_mg_level_apply", "dg_mlp_nparams",
             "dg_mlp_set_weights", "dg_mlp_get_weights", "dg_mlp_features", "dg_mlp_forward", "dg_mlp_grad",
             "dg_mlp_train_step", "dg_mlp_apply", "dg_max_wave_speed",
@@ -44,7 +44,7 @@ class SolveOpts(ctypes.Structure):
 
 class MgOpts(ctypes.Structure):
     _fields_ = [("n_levels", ctypes.c_int), ("orders", ctypes.c_int * 3), ("smooth_iters", ctypes.c_int * 3),
-                ("storage", ctypes.c_int), ("use_graph", ctypes.c_int)]
+                ("storage", ctypes.c_int), ("use_graph", ctypes.c_int), ("fine_precision", ctypes.c_int)]
 
 
 class SolveStats(ctypes.Structure):
@@ -76,6 +76,7 @@ def load():
         "dg_volume_points": (i, [ctx, vp, vp]),
         "dg_project": (i, [ctx, vp, vp, vp]),
         "dg_residual": (i, [ctx, vp, vp, vp]),
+        "dg_residual_fp32": (i, [ctx, vp, vp, vp]),
         "dg_jvp": (i, [ctx, vp, vp, vp, d, i, vp, vp]),
         "dg_block_precond_setup": (i, [ctx, vp, d, i, vp]),
         "dg_block_precond_apply": (i, [ctx, vp, vp, vp]),

@@ -13,7 +13,7 @@ from . import _lib as L
 
 _FLUX = {"lf": L.DG_FLUX_LF, "roe": L.DG_FLUX_ROE}
 _BASIS = {"P": L.DG_BASIS_PK, "Q": L.DG_BASIS_QK}
-_MODE = {"exact": L.DG_JVP_EXACT, "fd": L.DG_JVP_FD}
+_MODE = {"exact": L.DG_JVP_EXACT, "fd": L.DG_JVP_FD, "exact_fp32": L.DG_JVP_EXACT_FP32}
 _STORAGE = {"fp64": L.DG_FP64, "fp32": L.DG_FP32, "bf16": L.DG_BF16}
 _PREC = {"none": L.DG_PREC_NONE, "bj": L.DG_PREC_BJ, "mg": L.DG_PREC_MG, "mlp": L.DG_PREC_MLP}
 
@@ -99,10 +99,13 @@ class DG:
         f = torch.from_numpy(np.ascontiguousarray(np.moveaxis(vals, -1, 0))).to(self.device)
         return self.project(f)
 
-    def residual(self, w, out=None):
+    def residual(self, w, out=None, precision="fp64"):
         self._vec(w, "w")
         out = self.empty() if out is None else self._vec(out, "out")
-        L.check(self.lib.dg_residual(self.ctx, _ptr(w), _ptr(out), _stream()), "dg_residual")
+        if precision == "fp32":
+            L.check(self.lib.dg_residual_fp32(self.ctx, _ptr(w), _ptr(out), _stream()), "dg_residual_fp32")
+        else:
+            L.check(self.lib.dg_residual(self.ctx, _ptr(w), _ptr(out), _stream()), "dg_residual")
         return out
 
     def jvp(self, w, v, shift=0.0, mode="exact", r_w=None, out=None):
@@ -126,7 +129,7 @@ class DG:
         L.check(self.lib.dg_block_precond_apply(self.ctx, _ptr(r), _ptr(out), _stream()), "dg_block_precond_apply")
         return out
 
-    def mg_setup(self, w, shift, orders, smooth_iters, storage="fp64", use_graph=True):
+    def mg_setup(self, w, shift, orders, smooth_iters, storage="fp64", use_graph=True, fine_precision="fp64"):
         """p-multigrid hierarchy at (w, shift); orders[0] must be the context's order."""
         self._vec(w, "w")
         orders, smooth_iters = list(orders), list(smooth_iters)
@@ -134,7 +137,7 @@ class DG:
             raise ValueError("need 2 or 3 levels and one smoothing count per level")
         o = L.MgOpts(len(orders), (ctypes.c_int * 3)(*(orders + [0] * (3 - len(orders)))),
                      (ctypes.c_int * 3)(*(smooth_iters + [0] * (3 - len(orders)))), _STORAGE[storage],
-                     int(bool(use_graph)))
+                     int(bool(use_graph)), _STORAGE[fine_precision])
         self.mg_levels = [(self.ne * self.nv * _nb(k, self.dim)) for k in orders]
         L.check(self.lib.dg_mg_setup(self.ctx, _ptr(w), float(shift), ctypes.byref(o), _stream()), "dg_mg_setup")
 

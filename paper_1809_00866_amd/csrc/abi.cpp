@@ -52,6 +52,21 @@ dg_status eval_residual(dg_context* c, bool jvp, const double* w, const double* 
   return DG_OK;
 }
 
+dg_status eval_residual_f32(dg_context* c, bool jvp, const double* w, const double* v, double shift, double* out,
+                            hipStream_t s) {
+  if (!c->use_mfma || !c->d_mtab_f || !c->d_Hf)
+    return fail(DG_ERR_ARG, "the reduced-precision operator needs a 3D P2-P4 configuration with MFMA kernels");
+  {
+    ProfScope ps(c, jvp ? "face_jvp_f32" : "face_res_f32", s);
+    HIPCHK(dgk::launch_face_mfma_f32(c->cfg, jvp, w, v, c->d_Hf, c->mtf, c->mesh, c->ph, s));
+  }
+  {
+    ProfScope ps(c, jvp ? "vol_jvp_f32" : "vol_res_f32", s);
+    HIPCHK(dgk::launch_volume_mfma_f32(c->cfg, jvp, w, v, c->d_Hf, out, shift, c->mtf, c->mesh, c->ph, s));
+  }
+  return DG_OK;
+}
+
 dg_status norm2(dg_context* c, const double* x, double* dout, hipStream_t s) {
   HIPCHK(dgk::launch_dot_partials(x, x, c->ndof, c->d_red, s));
   HIPCHK(dgk::launch_sum_partials(c->d_red, dgk::kRedBlocks, dout, 1, s));
@@ -61,6 +76,7 @@ dg_status norm2(dg_context* c, const double* x, double* dout, hipStream_t s) {
 dg_status jvp_impl(dg_context* c, const double* w, const double* r_w, const double* v, double shift, int mode,
                    double* out, hipStream_t s) {
   if (mode == DG_JVP_EXACT) return eval_residual(c, true, w, v, shift, out, s);
+  if (mode == DG_JVP_EXACT_FP32) return eval_residual_f32(c, true, w, v, shift, out, s);
   // finite difference of eqs. (matrix-free)/(epsdef)
   const double* r0 = r_w;
   dg_status st;
@@ -207,6 +223,28 @@ dg_status dg_create(const dg_params* prm, const dg_mesh* mesh, dg_context** out)
     c->mt.lA = c->d_mtab + moff[4];
     c->mt.kl = M.kl;
     c->use_mfma = true;
+    // FP32 copies (interpolation table in the FP32 fragment order)
+    std::vector<const std::vector<double>*> fp = {&M.vAf, &M.pA, &M.fA, &M.tA, &M.lA};
+    size_t ftot = 0;
+    for (auto* v : fp) ftot += v->size();
+    if ((st = dalloc(&c->d_mtab_f, ftot)) != DG_OK) return cleanup(st);
+    std::vector<float> fpk;
+    std::vector<size_t> foff;
+    fpk.reserve(ftot);
+    for (auto* v : fp) {
+      foff.push_back(fpk.size());
+      for (double x : *v) fpk.push_back((float)x);
+    }
+    if (hipMemcpy(c->d_mtab_f, fpk.data(), ftot * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
+      return cleanup(fail(DG_ERR_HIP, "FP32 MFMA table upload failed"));
+    c->mtf.vA = c->d_mtab_f + foff[0];
+    c->mtf.pA = c->d_mtab_f + foff[1];
+    c->mtf.fA = c->d_mtab_f + foff[2];
+    c->mtf.tA = c->d_mtab_f + foff[3];
+    c->mtf.lA = c->d_mtab_f + foff[4];
+    c->mtf.kl = M.kl;
+    // allocated here, not on first use: a captured V-cycle may call the FP32 operator
+    if ((st = dalloc(&c->d_Hf, (size_t)dim * c->nv * T.nfq * ne)) != DG_OK) return cleanup(st);
   }
 
   // neighbours transposed to [2*dim][ne], low corners [dim][ne]
@@ -269,6 +307,8 @@ void dg_destroy(dg_context* c) {
     }
   dfree(c->d_tab);
   dfree(c->d_mtab);
+  dfree(c->d_mtab_f);
+  dfree(c->d_Hf);
   dfree(c->d_nbr);
   dfree(c->d_x0);
   dfree(c->d_H);
@@ -313,11 +353,17 @@ dg_status dg_residual(dg_context* c, const double* w, double* r, void* stream) {
   return eval_residual(c, false, w, nullptr, 0.0, r, (hipStream_t)stream);
 }
 
+dg_status dg_residual_fp32(dg_context* c, const double* w, double* r, void* stream) {
+  if (!c || !w || !r) return fail(DG_ERR_ARG, "null argument");
+  if (w == r) return fail(DG_ERR_ARG, "w and r may not alias");
+  return eval_residual_f32(c, false, w, nullptr, 0.0, r, (hipStream_t)stream);
+}
+
 dg_status dg_jvp(dg_context* c, const double* w, const double* r_w, const double* v, double shift, int mode,
                  double* out, void* stream) {
   if (!c || !w || !v || !out) return fail(DG_ERR_ARG, "null argument");
   if (out == w || out == v || (r_w && out == r_w)) return fail(DG_ERR_ARG, "out may not alias w, v or r_w");
-  if (mode != DG_JVP_EXACT && mode != DG_JVP_FD) return fail(DG_ERR_ARG, "unknown jvp mode");
+  if (mode != DG_JVP_EXACT && mode != DG_JVP_FD && mode != DG_JVP_EXACT_FP32) return fail(DG_ERR_ARG, "unknown jvp mode");
   return jvp_impl(c, w, r_w, v, shift, mode, out, (hipStream_t)stream);
 }
 
@@ -409,7 +455,8 @@ dg_status dg_fgmres_solve(dg_context* c, const double* w, double shift, const do
   if (opts->precond == DG_PREC_MLP && !mlp_ready(c->mlp)) return fail(DG_ERR_STATE, "network weights not set");
   if (opts->precond == DG_PREC_BJ && !c->blk_ready) return fail(DG_ERR_STATE, "block preconditioner not set up");
   if (opts->precond == DG_PREC_MG && !mg_ready(c->mg)) return fail(DG_ERR_STATE, "p-multigrid not set up");
-  if (opts->jvp_mode != DG_JVP_EXACT && opts->jvp_mode != DG_JVP_FD) return fail(DG_ERR_ARG, "unknown jvp mode");
+  if (opts->jvp_mode != DG_JVP_EXACT && opts->jvp_mode != DG_JVP_FD)
+    return fail(DG_ERR_ARG, "the solve's operator is the exact FP64 or the finite-difference Jv");
   const double rtol = opts->rtol > 0.0 ? opts->rtol : 1e-8;
   const int max_iter = opts->max_iter > 0 ? opts->max_iter : 1000;
   hipStream_t s = (hipStream_t)stream;

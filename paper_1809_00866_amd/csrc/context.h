@@ -63,6 +63,9 @@ struct dg_context {
   dgk::MTables mt{};
   bool use_mfma = false;
   double* d_mtab = nullptr;
+  dgk::MTablesF mtf{};          // FP32 copies for the reduced-precision operator
+  float* d_mtab_f = nullptr;
+  float* d_Hf = nullptr;        // FP32 face-flux buffer
   dgk::Mesh mesh{};
   dgk::Phys ph{};
   double* d_tab = nullptr;
@@ -120,6 +123,10 @@ struct ProfScope {
 // Residual (jvp = false) or exact Jv plus shift*v (jvp = true) on stream s.
 dg_status eval_residual(dg_context* c, bool jvp, const double* w, const double* v, double shift, double* out,
                         hipStream_t s);
+// Same with FP32 contractions and FP32 pointwise arithmetic (inputs and
+// outputs FP64); 3D P2-P4 configurations only.
+dg_status eval_residual_f32(dg_context* c, bool jvp, const double* w, const double* v, double shift, double* out,
+                            hipStream_t s);
 // dout[0] = ||x||_2 over the context's DOF vector length.
 dg_status norm2(dg_context* c, const double* x, double* dout, hipStream_t s);
 // out = shift*v + J(w) v, exact or finite difference.

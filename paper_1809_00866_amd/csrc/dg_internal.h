@@ -35,14 +35,20 @@ struct Tables {
 // Operator tables pre-permuted into the operand order of the FP64 MFMA
 // 16x16x4 instruction (A[i][k] at lane i + 16k, B[k][j] at lane j + 16k,
 // D[i][j] at lane j + 16 (i % 4), register i / 4), 64 doubles per fragment.
-struct MTables {
-  const double* vA;     // [RBQ][KSB][64]            interpolation: phi(q, b)
-  const double* pA;     // [RBQ][MB][DIM*4][64]      projection: -w|J| d_j phi(q, b), k = (j, q)
-  const double* fA;     // [DIM][2][MB][KSF][64]     face projection: +/- w_f|J_f| phi(fq, b)
-  const double* tA;     // [DIM][RBF][6][2*KSB][64]  face traces (uL, uR, G_1..3 averaged, {r})
-  const double* lA;     // [DIM][MB][3*KSB][64]      modal corrected gradient [L0 | L1 | L2]
-  int kl;               // max nonzeros per row of the maps (p+1: they act along tensor lines)
+// MFMA operand tables in A-fragment order (lane l = row + 16 k of each 16x4
+// k-step), in the working precision R of the kernels that read them.
+template <class R>
+struct MTablesT {
+  const R* vA;     // [RBQ][KSV][64]            interpolation: phi(q, b); KSV = KSB (FP64) or 4 MB
+                   //                           with the FP32 fragment order of the modes
+  const R* pA;     // [RBQ][MB][DIM*4][64]      projection: -w|J| d_j phi(q, b), k = (j, q)
+  const R* fA;     // [DIM][2][MB][KSF][64]     face projection: +/- w_f|J_f| phi(fq, b)
+  const R* tA;     // [DIM][RBF][6][2*KSB][64]  face traces (uL, uR, G_1..3 averaged, {r})
+  const R* lA;     // [DIM][MB][3*KSB][64]      modal corrected gradient [L0 | L1 | L2]
+  int kl;          // max nonzeros per row of the maps (p+1: they act along tensor lines)
 };
+using MTables = MTablesT<double>;
+using MTablesF = MTablesT<float>;
 
 struct Phys {
   double gamma, prandtl, mu, eta, efix;
@@ -68,6 +74,12 @@ hipError_t launch_volume(int cfg, bool jvp, const double* U, const double* V, co
 bool has_mfma(int cfg);
 hipError_t launch_face_mfma(int cfg, bool jvp, const double* U, const double* V, double* H, const MTables& mt,
                             const Mesh& m, const Phys& ph, hipStream_t stream);
+// reduced precision variant: FP32 tables, FP32 face-flux buffer, FP32 MFMA and
+// pointwise arithmetic, FP64 inputs and outputs
+hipError_t launch_face_mfma_f32(int cfg, bool jvp, const double* U, const double* V, float* H, const MTablesF& mt,
+                                const Mesh& m, const Phys& ph, hipStream_t s);
+hipError_t launch_volume_mfma_f32(int cfg, bool jvp, const double* U, const double* V, const float* H, double* out,
+                                  double shift, const MTablesF& mt, const Mesh& m, const Phys& ph, hipStream_t s);
 hipError_t launch_volume_mfma(int cfg, bool jvp, const double* U, const double* V, const double* H, double* out,
                               double shift, const MTables& mt, const Mesh& m, const Phys& ph, hipStream_t stream);
 hipError_t launch_project(int cfg, const double* f, double* w, const Tables& tb, const Mesh& m, hipStream_t s);
@@ -144,6 +156,7 @@ HostTables build_tables(int dim, int order, int basis, int nq1d, const double h[
 
 struct MfmaHost {
   std::vector<double> vA, pA, fA, tA, lA;
+  std::vector<double> vAf;  // interpolation table in the FP32 fragment order (4 MB k-steps per point block)
   int kl = 0;
 };
 MfmaHost build_mfma_tables(const HostTables& T);

@@ -30,18 +30,43 @@
 namespace dgk {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-DEV f64x4 mfma4(double a, double b, f64x4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+// MFMA precision policy.  Both 16x16x4 instructions take A[i][k] from lane
+// i + 16k and B[k][j] from lane j + 16k; they differ in where the result
+// rows land: FP64 returns row g + 4r of column l%16 in register r of lane
+// group g = l/16, FP32 returns row 4g + r.  A result used directly as the next
+// B operand therefore carries, at fragment (k-step ks, lane group g), the
+// mode g + 4 ks (FP64) or 16 (ks/4) + 4 g + ks%4 (FP32); fields loaded from
+// memory into such fragments follow the same order, and the interpolation
+// table's columns are built to match (4 k-steps per 16 modes in FP32).
+template <class R> struct MP;
+template <> struct MP<double> {
+  using frag = f64x4;
+  static DEV frag mma(double a, double b, frag c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  static DEV int drow(int g, int r) { return g + 4 * r; }
+  static DEV int bmode(int g, int ks) { return g + 4 * ks; }
+  static constexpr int ksv(int nb) { return (nb + 3) / 4; }
+};
+template <> struct MP<float> {
+  using frag = f32x4;
+  static DEV frag mma(float a, float b, frag c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  static DEV int drow(int g, int r) { return 4 * g + r; }
+  static DEV int bmode(int g, int ks) { return 16 * (ks >> 2) + 4 * g + (ks & 3); }
+  static constexpr int ksv(int nb) { return 4 * ((nb + 15) / 16); }
+};
 
 // ------------------------------------------------------------------ volume
-template <int NB, int NQ1, int KL, bool JVP>
+template <class R, int NB, int NQ1, int KL, bool JVP>
 __global__ __launch_bounds__(256, 2) void k_volume_mfma(const double* __restrict__ U, const double* __restrict__ V,
-                                                     const double* __restrict__ H, double* __restrict__ out,
-                                                     double shift, MTables mt, Mesh m, Phys ph) {
-  using T = typename Scalar<JVP>::type;
+                                                     const R* __restrict__ H, double* __restrict__ out,
+                                                     double shift, MTablesT<R> mt, Mesh m, Phys ph) {
+  using T = typename Scalar<JVP, R>::type;
+  using F = typename MP<R>::frag;
   constexpr int DIM = 3, NV = 5;
   constexpr int NQ = ipow(NQ1, 3), NFQ = ipow(NQ1, 2);
   constexpr int KSB = (NB + 3) / 4, MB = (NB + 15) / 16, RBQ = (NQ + 15) / 16;
+  constexpr int KSV = MP<R>::ksv(NB);         // fragment k-steps of the modal fields
   constexpr int KSP = DIM * 4, KSF = (NFQ + 3) / 4;
   constexpr int NS = JVP ? 2 : 1;
   constexpr int NFC = (1 + DIM) * NV;        // (field, variable) pairs per value/tangent
@@ -50,7 +75,7 @@ __global__ __launch_bounds__(256, 2) void k_volume_mfma(const double* __restrict
   constexpr int NPBW = (NPB + 3) / 4;
   static_assert(NFC % 4 == 0, "column blocks must split over 4 waves");
   constexpr int STAGE_ROWS = (NFC * 256 > 3 * NV * NB * 16) ? NFC : (3 * NV * NB + 15) / 16;
-  __shared__ double stage[STAGE_ROWS][16][16];
+  __shared__ R stage[STAGE_ROWS][16][16];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -62,11 +87,11 @@ __global__ __launch_bounds__(256, 2) void k_volume_mfma(const double* __restrict
   const bool ev = e < ne;
   const double kap = ph.mu * ph.gamma / (ph.prandtl * (ph.gamma - 1.0));
 
-  // ---- 1. modal fields in B-fragment order: Bf[i][ks] = X[b = g + 4 ks][e].
+  // ---- 1. modal fields in B-fragment order: Bf[i][ks] = X[b = bmode(g, ks)][e].
   // The corrected-gradient maps are applied with MFMA from LDS copies of the
   // element's and its +/-p neighbours' modes, one (value/tangent, p) round at a
   // time.
-  double Bf[NCBW][KSB];
+  R Bf[NCBW][KSV];
 #pragma unroll
   for (int i = 0; i < NCBW; ++i) {
     const int s = i / (NFC / 4);
@@ -74,12 +99,12 @@ __global__ __launch_bounds__(256, 2) void k_volume_mfma(const double* __restrict
     const int f = fc / NV, c = fc % NV;
     const double* __restrict__ X = (s == 0) ? U : V;
 #pragma unroll
-    for (int ks = 0; ks < KSB; ++ks) {
-      const int b = g + 4 * ks;
-      Bf[i][ks] = (f == 0 && ev && b < NB) ? X[(size_t)(c * NB + b) * ne + e] : 0.0;
+    for (int ks = 0; ks < KSV; ++ks) {
+      const int b = MP<R>::bmode(g, ks);
+      Bf[i][ks] = (f == 0 && ev && b < NB) ? (R)X[(size_t)(c * NB + b) * ne + e] : R(0);
     }
   }
-  double* sl = &stage[0][0][0];  // [src][c][b][16]
+  R* sl = &stage[0][0][0];  // [src][c][b][16]
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     const double* __restrict__ X = (s == 0) ? U : V;
@@ -92,16 +117,16 @@ __global__ __launch_bounds__(256, 2) void k_volume_mfma(const double* __restrict
         r /= NB;
         const int c = r % NV, src = r / NV;
         const int64_t et2 = e0 + t;
-        double val = 0.0;
+        R val = R(0);
         if (et2 < ne) {
           const int64_t es = (src == 0) ? et2 : m.nbr[(2 * p + (src == 1 ? 1 : 0)) * ne + et2];
-          val = X[(size_t)(c * NB + b) * ne + es];
+          val = (R)X[(size_t)(c * NB + b) * ne + es];
         }
         sl[it] = val;
       }
       __syncthreads();
       // G_p[b][e] = sum_{src, b'} L_src,p[b][b'] X_src[b'][e]: MFMA with rows = modes,
-      // k = (source, mode); the output rows g + 4r (+16 mb) are the B-fragment rows.
+      // k = (source, mode); register r of the result is fragment k-step 4 mb + r.
 #pragma unroll
       for (int i = s * (NFC / 4); i < (s + 1) * (NFC / 4); ++i) {
         const int fc = wave + 4 * (i % (NFC / 4));
@@ -109,16 +134,16 @@ __global__ __launch_bounds__(256, 2) void k_volume_mfma(const double* __restrict
         if (f == p + 1) {
 #pragma unroll
           for (int mb = 0; mb < MB; ++mb) {
-            f64x4 d = {0.0, 0.0, 0.0, 0.0};
+            F d = {0, 0, 0, 0};
 #pragma unroll
             for (int ks3 = 0; ks3 < 3 * KSB; ++ks3) {
               const int src = ks3 / KSB, bp = g + 4 * (ks3 % KSB);
-              const double bv = (bp < NB) ? sl[((src * NV + c) * NB + bp) * 16 + col] : 0.0;
-              d = mfma4(mt.lA[(((size_t)p * MB + mb) * 3 * KSB + ks3) * 64 + lane], bv, d);
+              const R bv = (bp < NB) ? sl[((src * NV + c) * NB + bp) * 16 + col] : R(0);
+              d = MP<R>::mma(mt.lA[(((size_t)p * MB + mb) * 3 * KSB + ks3) * 64 + lane], bv, d);
             }
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-              if (4 * mb + r < KSB) Bf[i][4 * mb + r] = d[r];
+              if (4 * mb + r < KSV) Bf[i][4 * mb + r] = d[r];
           }
         }
       }
@@ -126,24 +151,24 @@ __global__ __launch_bounds__(256, 2) void k_volume_mfma(const double* __restrict
     }
   }
 
-  f64x4 acc[NPBW];
+  F acc[NPBW];
 #pragma unroll
-  for (int i = 0; i < NPBW; ++i) acc[i] = f64x4{0.0, 0.0, 0.0, 0.0};
+  for (int i = 0; i < NPBW; ++i) acc[i] = F{0, 0, 0, 0};
 
   const int ql = tid >> 4, et = tid & 15;  // pointwise mapping: (point in block, element)
   for (int rb = 0; rb < RBQ; ++rb) {
-    double st[NS][NFC];
+    R st[NS][NFC];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       // ---- 2a. MFMA interpolation of this wave's column blocks
 #pragma unroll
       for (int i = s * (NFC / 4); i < (s + 1) * (NFC / 4); ++i) {
         const int fc = wave + 4 * (i % (NFC / 4));
-        f64x4 d = {0.0, 0.0, 0.0, 0.0};
+        F d = {0, 0, 0, 0};
 #pragma unroll
-        for (int ks = 0; ks < KSB; ++ks) d = mfma4(mt.vA[((size_t)rb * KSB + ks) * 64 + lane], Bf[i][ks], d);
+        for (int ks = 0; ks < KSV; ++ks) d = MP<R>::mma(mt.vA[((size_t)rb * KSV + ks) * 64 + lane], Bf[i][ks], d);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) stage[fc][g + 4 * r][col] = d[r];
+        for (int r = 0; r < 4; ++r) stage[fc][MP<R>::drow(g, r)][col] = d[r];
       }
       __syncthreads();
 #pragma unroll
@@ -158,9 +183,9 @@ __global__ __launch_bounds__(256, 2) void k_volume_mfma(const double* __restrict
 #pragma unroll
       for (int c = 0; c < NV; ++c) {
         if constexpr (JVP) {
-          u[c] = dual(st[0][c], st[NS - 1][c]);
+          u[c] = T(st[0][c], st[NS - 1][c]);
 #pragma unroll
-          for (int j = 0; j < DIM; ++j) G[c][j] = dual(st[0][(1 + j) * NV + c], st[NS - 1][(1 + j) * NV + c]);
+          for (int j = 0; j < DIM; ++j) G[c][j] = T(st[0][(1 + j) * NV + c], st[NS - 1][(1 + j) * NV + c]);
         } else {
           u[c] = st[0][c];
 #pragma unroll
@@ -183,7 +208,7 @@ __global__ __launch_bounds__(256, 2) void k_volume_mfma(const double* __restrict
 #pragma unroll
       for (int j = 0; j < DIM; ++j)
 #pragma unroll
-        for (int c = 0; c < NV; ++c) stage[j * NV + c][ql][et] = 0.0;
+        for (int c = 0; c < NV; ++c) stage[j * NV + c][ql][et] = R(0);
     }
     __syncthreads();
     // ---- 2c. MFMA projection: R[b][e] += -sum_{j,q} w|J| d_j phi(q,b) F_j(q,e)
@@ -195,8 +220,8 @@ __global__ __launch_bounds__(256, 2) void k_volume_mfma(const double* __restrict
 #pragma unroll
         for (int ks = 0; ks < KSP; ++ks) {
           const int k = g + 4 * ks;
-          acc[i] = mfma4(mt.pA[(((size_t)rb * MB + mb) * KSP + ks) * 64 + lane], stage[(k >> 4) * NV + c][k & 15][col],
-                         acc[i]);
+          acc[i] = MP<R>::mma(mt.pA[(((size_t)rb * MB + mb) * KSP + ks) * 64 + lane],
+                              stage[(k >> 4) * NV + c][k & 15][col], acc[i]);
         }
       }
     }
@@ -218,18 +243,18 @@ __global__ __launch_bounds__(256, 2) void k_volume_mfma(const double* __restrict
 #pragma unroll
           for (int ks = 0; ks < KSF; ++ks) {
             const int fq = g + 4 * ks;
-            const double hb = (ev && fq < NFQ) ? H[((size_t)(p * NV + c) * NFQ + fq) * ne + es] : 0.0;
-            acc[i] = mfma4(mt.fA[((((size_t)p * 2 + side) * MB + mb) * KSF + ks) * 64 + lane], hb, acc[i]);
+            const R hb = (ev && fq < NFQ) ? H[((size_t)(p * NV + c) * NFQ + fq) * ne + es] : R(0);
+            acc[i] = MP<R>::mma(mt.fA[((((size_t)p * 2 + side) * MB + mb) * KSF + ks) * 64 + lane], hb, acc[i]);
           }
         }
       }
       if (ev) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int b = 16 * mb + g + 4 * r;
+          const int b = 16 * mb + MP<R>::drow(g, r);
           if (b < NB) {
             const size_t idx = (size_t)(c * NB + b) * ne + e;
-            double a = acc[i][r];
+            double a = (double)acc[i][r];
             if (JVP) a += shift * V[idx];
             out[idx] = a;
           }
@@ -240,10 +265,11 @@ __global__ __launch_bounds__(256, 2) void k_volume_mfma(const double* __restrict
 }
 
 // ------------------------------------------------------------------ faces
-template <int NB, int NQ1, bool JVP, int P>
-DEV void face_mfma_body(const double* __restrict__ U, const double* __restrict__ V, double* __restrict__ H,
-                        const MTables& mt, const Mesh& m, const Phys& ph, double (*stage)[16][16]) {
-  using T = typename Scalar<JVP>::type;
+template <class R, int NB, int NQ1, bool JVP, int P>
+DEV void face_mfma_body(const double* __restrict__ U, const double* __restrict__ V, R* __restrict__ H,
+                        const MTablesT<R>& mt, const Mesh& m, const Phys& ph, R (*stage)[16][16]) {
+  using T = typename Scalar<JVP, R>::type;
+  using F = typename MP<R>::frag;
   constexpr int DIM = 3, NV = 5;
   constexpr int NFQ = ipow(NQ1, 2);
   constexpr int KSB = (NB + 3) / 4, RBF = (NFQ + 15) / 16;
@@ -263,7 +289,7 @@ DEV void face_mfma_body(const double* __restrict__ U, const double* __restrict__
   const double kap = ph.mu * ph.gamma / (ph.prandtl * (ph.gamma - 1.0));
 
   // B fragments: k-steps 0..KSB-1 from the owner, KSB..2KSB-1 from the +P neighbour
-  double Bf[NCBW][2 * KSB];
+  R Bf[NCBW][2 * KSB];
 #pragma unroll
   for (int i = 0; i < NCBW; ++i) {
     const int cb = wave + 4 * i;
@@ -273,13 +299,13 @@ DEV void face_mfma_body(const double* __restrict__ U, const double* __restrict__
     for (int ks2 = 0; ks2 < 2 * KSB; ++ks2) {
       const int b = g + 4 * (ks2 < KSB ? ks2 : ks2 - KSB);
       const int64_t es = ks2 < KSB ? e : er;
-      Bf[i][ks2] = (cb < NCB && ev && b < NB) ? X[(size_t)(c * NB + b) * ne + es] : 0.0;
+      Bf[i][ks2] = (cb < NCB && ev && b < NB) ? (R)X[(size_t)(c * NB + b) * ne + es] : R(0);
     }
   }
 
   const int fql = tid >> 4, ft = tid & 15;
   for (int rbf = 0; rbf < RBF; ++rbf) {
-    double st[NS][NCH * NV];
+    R st[NS][NCH * NV];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
 #pragma unroll
@@ -291,12 +317,13 @@ DEV void face_mfma_body(const double* __restrict__ U, const double* __restrict__
           for (int ch = 0; ch < NCH; ++ch) {
             const int k0 = (ch == 1) ? KSB : 0;
             const int k1 = (ch == 0) ? KSB : 2 * KSB;
-            f64x4 d = {0.0, 0.0, 0.0, 0.0};
+            F d = {0, 0, 0, 0};
 #pragma unroll
             for (int ks2 = k0; ks2 < k1; ++ks2)
-              d = mfma4(mt.tA[((((size_t)P * RBF + rbf) * NCH + ch) * 2 * KSB + ks2) * 64 + lane], Bf[i][ks2], d);
+              d = MP<R>::mma(mt.tA[((((size_t)P * RBF + rbf) * NCH + ch) * 2 * KSB + ks2) * 64 + lane], Bf[i][ks2],
+                             d);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) stage[ch * NV + c][g + 4 * r][col] = d[r];
+            for (int r = 0; r < 4; ++r) stage[ch * NV + c][MP<R>::drow(g, r)][col] = d[r];
           }
         }
       }
@@ -312,24 +339,24 @@ DEV void face_mfma_body(const double* __restrict__ U, const double* __restrict__
 #pragma unroll
       for (int c = 0; c < NV; ++c) {
         if constexpr (JVP) {
-          uL[c] = dual(st[0][0 * NV + c], st[NS - 1][0 * NV + c]);
-          uR[c] = dual(st[0][1 * NV + c], st[NS - 1][1 * NV + c]);
+          uL[c] = T(st[0][0 * NV + c], st[NS - 1][0 * NV + c]);
+          uR[c] = T(st[0][1 * NV + c], st[NS - 1][1 * NV + c]);
 #pragma unroll
-          for (int j = 0; j < DIM; ++j) Ga[c][j] = dual(st[0][(2 + j) * NV + c], st[NS - 1][(2 + j) * NV + c]);
-          Ga[c][P] += ph.eta * dual(st[0][5 * NV + c], st[NS - 1][5 * NV + c]);
+          for (int j = 0; j < DIM; ++j) Ga[c][j] = T(st[0][(2 + j) * NV + c], st[NS - 1][(2 + j) * NV + c]);
+          Ga[c][P] += (R)ph.eta * T(st[0][5 * NV + c], st[NS - 1][5 * NV + c]);
         } else {
           uL[c] = st[0][0 * NV + c];
           uR[c] = st[0][1 * NV + c];
 #pragma unroll
           for (int j = 0; j < DIM; ++j) Ga[c][j] = st[0][(2 + j) * NV + c];
-          Ga[c][P] += ph.eta * st[0][5 * NV + c];
+          Ga[c][P] += (R)ph.eta * st[0][5 * NV + c];
         }
       }
       T Hn[NV];
       num_flux<T, DIM>(uL, uR, P, ph, Hn);
       T ua[NV];
 #pragma unroll
-      for (int c = 0; c < NV; ++c) ua[c] = 0.5 * (uL[c] + uR[c]);
+      for (int c = 0; c < NV; ++c) ua[c] = R(0.5) * (uL[c] + uR[c]);
       ViscPrep<T, DIM> vp;
       visc_prep<T, DIM>(ua, Ga, ph.gamma, vp);
       T Fv[NV];
@@ -340,14 +367,14 @@ DEV void face_mfma_body(const double* __restrict__ U, const double* __restrict__
   }
 }
 
-template <int NB, int NQ1, bool JVP>
+template <class R, int NB, int NQ1, bool JVP>
 __global__ __launch_bounds__(256, 2) void k_face_mfma(const double* __restrict__ U, const double* __restrict__ V,
-                                                   double* __restrict__ H, MTables mt, Mesh m, Phys ph) {
-  __shared__ double stage[6 * 5][16][16];
+                                                   R* __restrict__ H, MTablesT<R> mt, Mesh m, Phys ph) {
+  __shared__ R stage[6 * 5][16][16];
   switch (blockIdx.y) {
-    case 0: face_mfma_body<NB, NQ1, JVP, 0>(U, V, H, mt, m, ph, stage); break;
-    case 1: face_mfma_body<NB, NQ1, JVP, 1>(U, V, H, mt, m, ph, stage); break;
-    default: face_mfma_body<NB, NQ1, JVP, 2>(U, V, H, mt, m, ph, stage); break;
+    case 0: face_mfma_body<R, NB, NQ1, JVP, 0>(U, V, H, mt, m, ph, stage); break;
+    case 1: face_mfma_body<R, NB, NQ1, JVP, 1>(U, V, H, mt, m, ph, stage); break;
+    default: face_mfma_body<R, NB, NQ1, JVP, 2>(U, V, H, mt, m, ph, stage); break;
   }
 }
 
@@ -367,15 +394,16 @@ bool has_mfma(int cfg) {
   return false;
 }
 
-hipError_t launch_face_mfma(int cfg, bool jvp, const double* U, const double* V, double* H, const MTables& mt,
-                            const Mesh& m, const Phys& ph, hipStream_t s) {
+template <class R>
+hipError_t face_mfma_dispatch(int cfg, bool jvp, const double* U, const double* V, R* H, const MTablesT<R>& mt,
+                              const Mesh& m, const Phys& ph, hipStream_t s) {
 #define X(id, nb_, nq_, kl_)                                                         \
   case id: {                                                                         \
     dim3 grid((unsigned)((m.ne + 15) / 16), 3);                                      \
     if (jvp)                                                                         \
-      k_face_mfma<nb_, nq_, true><<<grid, 256, 0, s>>>(U, V, H, mt, m, ph);          \
+      k_face_mfma<R, nb_, nq_, true><<<grid, 256, 0, s>>>(U, V, H, mt, m, ph);       \
     else                                                                             \
-      k_face_mfma<nb_, nq_, false><<<grid, 256, 0, s>>>(U, V, H, mt, m, ph);         \
+      k_face_mfma<R, nb_, nq_, false><<<grid, 256, 0, s>>>(U, V, H, mt, m, ph);      \
     return hipGetLastError();                                                        \
   }
   switch (cfg) { DG_MFMA_CONFIGS(X) }
@@ -383,21 +411,42 @@ hipError_t launch_face_mfma(int cfg, bool jvp, const double* U, const double* V,
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_volume_mfma(int cfg, bool jvp, const double* U, const double* V, const double* H, double* out,
-                              double shift, const MTables& mt, const Mesh& m, const Phys& ph, hipStream_t s) {
-#define X(id, nb_, nq_, kl_)                                                                     \
-  case id: {                                                                                     \
-    if (mt.kl != kl_) return hipErrorInvalidValue;                                               \
-    dim3 grid((unsigned)((m.ne + 15) / 16));                                                     \
-    if (jvp)                                                                                     \
-      k_volume_mfma<nb_, nq_, kl_, true><<<grid, 256, 0, s>>>(U, V, H, out, shift, mt, m, ph);   \
-    else                                                                                         \
-      k_volume_mfma<nb_, nq_, kl_, false><<<grid, 256, 0, s>>>(U, V, H, out, shift, mt, m, ph);  \
-    return hipGetLastError();                                                                    \
+template <class R>
+hipError_t volume_mfma_dispatch(int cfg, bool jvp, const double* U, const double* V, const R* H, double* out,
+                                double shift, const MTablesT<R>& mt, const Mesh& m, const Phys& ph, hipStream_t s) {
+#define X(id, nb_, nq_, kl_)                                                                        \
+  case id: {                                                                                        \
+    if (mt.kl != kl_) return hipErrorInvalidValue;                                                  \
+    dim3 grid((unsigned)((m.ne + 15) / 16));                                                        \
+    if (jvp)                                                                                        \
+      k_volume_mfma<R, nb_, nq_, kl_, true><<<grid, 256, 0, s>>>(U, V, H, out, shift, mt, m, ph);   \
+    else                                                                                            \
+      k_volume_mfma<R, nb_, nq_, kl_, false><<<grid, 256, 0, s>>>(U, V, H, out, shift, mt, m, ph);  \
+    return hipGetLastError();                                                                       \
   }
   switch (cfg) { DG_MFMA_CONFIGS(X) }
 #undef X
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_face_mfma(int cfg, bool jvp, const double* U, const double* V, double* H, const MTables& mt,
+                            const Mesh& m, const Phys& ph, hipStream_t s) {
+  return face_mfma_dispatch<double>(cfg, jvp, U, V, H, mt, m, ph, s);
+}
+
+hipError_t launch_volume_mfma(int cfg, bool jvp, const double* U, const double* V, const double* H, double* out,
+                              double shift, const MTables& mt, const Mesh& m, const Phys& ph, hipStream_t s) {
+  return volume_mfma_dispatch<double>(cfg, jvp, U, V, H, out, shift, mt, m, ph, s);
+}
+
+hipError_t launch_face_mfma_f32(int cfg, bool jvp, const double* U, const double* V, float* H, const MTablesF& mt,
+                                const Mesh& m, const Phys& ph, hipStream_t s) {
+  return face_mfma_dispatch<float>(cfg, jvp, U, V, H, mt, m, ph, s);
+}
+
+hipError_t launch_volume_mfma_f32(int cfg, bool jvp, const double* U, const double* V, const float* H, double* out,
+                                  double shift, const MTablesF& mt, const Mesh& m, const Phys& ph, hipStream_t s) {
+  return volume_mfma_dispatch<float>(cfg, jvp, U, V, H, out, shift, mt, m, ph, s);
 }
 
 }  // namespace dgk

@@ -271,6 +271,17 @@ MfmaHost build_mfma_tables(const HostTables& T) {
         const int q = 16 * rb + (l & 15), b = (l >> 4) + 4 * ks;
         if (q < nq && b < nb) M.vA[((size_t)rb * KSB + ks) * 64 + l] = T.vPhi[(size_t)q * nb + b];
       }
+  // FP32 MFMA returns rows 4 (l/16) + r of its 16x16 result in register r of
+  // lane l; used unchanged as the B operand of the next MFMA, fragment k-step
+  // ks in lane group g then carries mode 16 (ks/4) + 4 g + ks%4, so the
+  // interpolation table's columns follow that order (4 k-steps per 16 modes).
+  M.vAf.assign((size_t)RBQ * 4 * MB * 64, 0.0);
+  for (int rb = 0; rb < RBQ; ++rb)
+    for (int ks = 0; ks < 4 * MB; ++ks)
+      for (int l = 0; l < 64; ++l) {
+        const int q = 16 * rb + (l & 15), b = 16 * (ks / 4) + 4 * (l >> 4) + ks % 4;
+        if (q < nq && b < nb) M.vAf[((size_t)rb * 4 * MB + ks) * 64 + l] = T.vPhi[(size_t)q * nb + b];
+      }
   M.pA.assign((size_t)RBQ * MB * KSP * 64, 0.0);
   for (int rb = 0; rb < RBQ; ++rb)
     for (int mb = 0; mb < MB; ++mb)

@@ -43,6 +43,7 @@ struct MgLevel {
 
 struct MgState {
   int nlev = 0, nslot = 0, storage = DG_FP64;
+  bool fine_f32 = false;  // FP32 fine-level operator inside the cycle
   double shift = 0.0;
   bool use_graph = false, ready = false;
   MgLevel lev[3];
@@ -95,7 +96,9 @@ int binom(int n, int k) {
 
 // ---------------------------------------------------------------- level ops
 dg_status level_G(dg_context* c, MgState* M, int l, const double* x, double* y, hipStream_t s) {
-  if (l == 0) return eval_residual(c, true, M->w, x, M->shift, y, s);
+  if (l == 0)
+    return M->fine_f32 ? eval_residual_f32(c, true, M->w, x, M->shift, y, s)
+                       : eval_residual(c, true, M->w, x, M->shift, y, s);
   const MgLevel& L = M->lev[l];
   HIPCHK(dgk::launch_bsr_apply(L.bs, L.B, c->mesh.nbr, 2 * c->dim, L.m, c->ne, x, y, s));
   return DG_OK;
@@ -283,6 +286,10 @@ dg_status dg_mg_setup(dg_context* c, const double* w, double shift, const dg_mg_
   if (o->smooth_iters[o->n_levels - 1] < 1) return fail(DG_ERR_ARG, "the coarsest level needs >= 1 iteration");
   if (o->storage != DG_FP64 && o->storage != DG_FP32 && o->storage != DG_BF16)
     return fail(DG_ERR_ARG, "storage must be DG_FP64, DG_FP32 or DG_BF16");
+  if (o->fine_precision != DG_FP64 && o->fine_precision != DG_FP32)
+    return fail(DG_ERR_ARG, "fine_precision must be DG_FP64 or DG_FP32");
+  if (o->fine_precision == DG_FP32 && !(c->use_mfma && c->d_mtab_f))
+    return fail(DG_ERR_ARG, "the FP32 fine operator needs a 3D P2-P4 configuration with MFMA kernels");
   hipStream_t s = (hipStream_t)stream;
   const int64_t ne = c->ne;
   const int dim = c->dim, nv = c->nv, nf = 2 * dim;
@@ -305,6 +312,7 @@ dg_status dg_mg_setup(dg_context* c, const double* w, double shift, const dg_mg_
   M->storage = o->storage;
   M->shift = shift;
   M->use_graph = o->use_graph != 0;
+  M->fine_f32 = o->fine_precision == DG_FP32;
   for (int l = 0; l < M->nlev; ++l) {
     MgLevel& L = M->lev[l];
     L.order = o->orders[l];

@@ -247,3 +247,31 @@ def test_mfma_and_reference_kernels_agree(N, k, nq, monkeypatch):
     assert (r0 - r1).norm() <= 1e-13 * r0.norm() * 1e2
     j0, j1 = gr.jvp(w, v, shift=1.5), gm.jvp(w, v, shift=1.5)
     assert (j0 - j1).norm() <= 1e-13 * j0.norm() * 1e2
+
+
+@pytest.mark.parametrize("N,k,sp,nq,flux", [CASES[2], CASES[3], CASES[5]], ids=[IDS[2], IDS[3], IDS[5]])
+def test_fp32_operator_error_against_the_oracle(N, k, sp, nq, flux):
+    """FP32 contractions and pointwise arithmetic: a reduced-precision operator
+    for preconditioners.  Its error against the FP64 oracle is bounded by 1e-5
+    (relative, residual normalised like the FP64 test) and is genuinely FP32
+    (above 1e-10)."""
+    _say(f"fp32 operator {N} {sp}{k}")
+    o, g, U, w = make_case(N, k, sp, nq, flux)
+    R, Rv = o.residual(U, return_parts=True)
+    r32 = g.residual(w, precision="fp32").cpu().numpy()
+    err_r = np.linalg.norm(r32 - o.to_flat(R)) / max(np.linalg.norm(R), np.linalg.norm(Rv))
+    V = np.random.default_rng(866).standard_normal(U.shape)
+    v = torch.tensor(o.to_flat(V), device="cuda")
+    ref = o.to_flat(o.jvp(U, V) + 3.0 * V)
+    j32 = g.jvp(w, v, shift=3.0, mode="exact_fp32").cpu().numpy()
+    err_j = rel(j32, ref)
+    _say(f"  fp32 residual error {err_r:.2e}, Jv error {err_j:.2e}")
+    assert 1e-10 < err_r <= 1e-5 and 1e-10 < err_j <= 1e-5
+
+
+def test_fp32_operator_rejects_configurations_without_mfma_kernels():
+    from paper_1809_00866_amd._lib import DGError
+    o, g, U, w = make_case((4, 4), 2, "Q", 4)
+    with pytest.raises(DGError) as ei:
+        g.residual(w, precision="fp32")
+    assert ei.value.status == -1

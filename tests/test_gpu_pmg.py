@@ -147,3 +147,23 @@ def test_state_errors_and_reduced_precision_smoothers():
     with pytest.raises(DGError) as ei:
         g.mg_apply(r)
     assert ei.value.status == -4
+
+
+def test_fp32_fine_operator_inside_the_cycle_keeps_the_fp64_solution(case):
+    """Reduced precision only inside the preconditioner: with the FP32 fine
+    operator in the smoothers the outer FP64 FGMRES still reaches 1e-10."""
+    o, U, g, w, shift = case["o"], case["U"], case["g"], case["w"], case["shift"]
+    if case["k"] < 2:
+        pytest.skip("the FP32 operator covers 3D P2-P4")
+    _say("p-MG with the FP32 fine operator")
+    from paper_1809_00866_amd import DG
+    g2 = DG(case["mesh"], case["k"], nq1d=case["nq"], mu=1e-2)
+    g2.mg_setup(w, shift, case["orders"], case["iters"], fine_precision="fp32")
+    B = np.random.default_rng(4).standard_normal(U.shape)
+    b = torch.tensor(o.to_flat(B), device="cuda")
+    x, st = g2.fgmres(w, shift, b, restart=30, rtol=1e-10, max_iter=500, precond="mg")
+    assert st["converged"] == 1 and st["rel_res_true"] <= 1e-10
+    X = o.from_flat(x.cpu().numpy())
+    res = np.linalg.norm(o.to_flat(o.operator(U, X, shift)) - o.to_flat(B)) / np.linalg.norm(B)
+    assert res <= 1e-9
+    g2.close()
