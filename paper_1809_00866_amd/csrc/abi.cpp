@@ -32,12 +32,16 @@ dg_status eval_residual(dg_context* c, bool jvp, const double* w, const double* 
                         hipStream_t s) {
   if (c->use_mfma) {
     {
+      ProfScope ps(c, jvp ? "grad_jvp" : "grad_res", s);
+      HIPCHK(dgk::launch_grad_mfma(c->cfg, jvp, w, v, c->d_G, c->mt, c->mesh, s));
+    }
+    {
       ProfScope ps(c, jvp ? "face_jvp" : "face_res", s);
       HIPCHK(dgk::launch_face_mfma(c->cfg, jvp, w, v, c->d_H, c->mt, c->mesh, c->ph, s));
     }
     {
       ProfScope ps(c, jvp ? "vol_jvp" : "vol_res", s);
-      HIPCHK(dgk::launch_volume_mfma(c->cfg, jvp, w, v, c->d_H, out, shift, c->mt, c->mesh, c->ph, s));
+      HIPCHK(dgk::launch_volume_mfma(c->cfg, jvp, w, v, c->d_G, c->d_H, out, shift, c->mt, c->mesh, c->ph, s));
     }
     return DG_OK;
   }
@@ -54,15 +58,19 @@ dg_status eval_residual(dg_context* c, bool jvp, const double* w, const double* 
 
 dg_status eval_residual_f32(dg_context* c, bool jvp, const double* w, const double* v, double shift, double* out,
                             hipStream_t s) {
-  if (!c->use_mfma || !c->d_mtab_f || !c->d_Hf)
+  if (!c->use_mfma || !c->d_mtab_f || !c->d_Hf || !c->d_Gf)
     return fail(DG_ERR_ARG, "the reduced-precision operator needs a 3D P2-P4 configuration with MFMA kernels");
+  {
+    ProfScope ps(c, jvp ? "grad_jvp_f32" : "grad_res_f32", s);
+    HIPCHK(dgk::launch_grad_mfma_f32(c->cfg, jvp, w, v, c->d_Gf, c->mtf, c->mesh, s));
+  }
   {
     ProfScope ps(c, jvp ? "face_jvp_f32" : "face_res_f32", s);
     HIPCHK(dgk::launch_face_mfma_f32(c->cfg, jvp, w, v, c->d_Hf, c->mtf, c->mesh, c->ph, s));
   }
   {
     ProfScope ps(c, jvp ? "vol_jvp_f32" : "vol_res_f32", s);
-    HIPCHK(dgk::launch_volume_mfma_f32(c->cfg, jvp, w, v, c->d_Hf, out, shift, c->mtf, c->mesh, c->ph, s));
+    HIPCHK(dgk::launch_volume_mfma_f32(c->cfg, jvp, w, v, c->d_Gf, c->d_Hf, out, shift, c->mtf, c->mesh, c->ph, s));
   }
   return DG_OK;
 }
@@ -243,8 +251,10 @@ dg_status dg_create(const dg_params* prm, const dg_mesh* mesh, dg_context** out)
     c->mtf.tA = c->d_mtab_f + foff[3];
     c->mtf.lA = c->d_mtab_f + foff[4];
     c->mtf.kl = M.kl;
-    // allocated here, not on first use: a captured V-cycle may call the FP32 operator
+    // allocated here, not on first use: a captured V-cycle may call either operator
     if ((st = dalloc(&c->d_Hf, (size_t)dim * c->nv * T.nfq * ne)) != DG_OK) return cleanup(st);
+    if ((st = dalloc(&c->d_G, (size_t)2 * dim * c->nv * T.nb * ne)) != DG_OK) return cleanup(st);
+    if ((st = dalloc(&c->d_Gf, (size_t)2 * dim * c->nv * T.nb * ne)) != DG_OK) return cleanup(st);
   }
 
   // neighbours transposed to [2*dim][ne], low corners [dim][ne]
@@ -309,6 +319,8 @@ void dg_destroy(dg_context* c) {
   dfree(c->d_mtab);
   dfree(c->d_mtab_f);
   dfree(c->d_Hf);
+  dfree(c->d_G);
+  dfree(c->d_Gf);
   dfree(c->d_nbr);
   dfree(c->d_x0);
   dfree(c->d_H);

@@ -66,6 +66,8 @@ struct dg_context {
   dgk::MTablesF mtf{};          // FP32 copies for the reduced-precision operator
   float* d_mtab_f = nullptr;
   float* d_Hf = nullptr;        // FP32 face-flux buffer
+  double* d_G = nullptr;        // modal corrected gradients [value/tangent][p][c][b][e]
+  float* d_Gf = nullptr;        // the same for the FP32 operator
   dgk::Mesh mesh{};
   dgk::Phys ph{};
   double* d_tab = nullptr;

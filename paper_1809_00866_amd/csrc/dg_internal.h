@@ -78,9 +78,16 @@ hipError_t launch_face_mfma(int cfg, bool jvp, const double* U, const double* V,
 // pointwise arithmetic, FP64 inputs and outputs
 hipError_t launch_face_mfma_f32(int cfg, bool jvp, const double* U, const double* V, float* H, const MTablesF& mt,
                                 const Mesh& m, const Phys& ph, hipStream_t s);
-hipError_t launch_volume_mfma_f32(int cfg, bool jvp, const double* U, const double* V, const float* H, double* out,
-                                  double shift, const MTablesF& mt, const Mesh& m, const Phys& ph, hipStream_t s);
-hipError_t launch_volume_mfma(int cfg, bool jvp, const double* U, const double* V, const double* H, double* out,
+hipError_t launch_volume_mfma_f32(int cfg, bool jvp, const double* U, const double* V, const float* Gm,
+                                  const float* H, double* out, double shift, const MTablesF& mt, const Mesh& m,
+                                  const Phys& ph, hipStream_t s);
+// modal corrected gradients Gm[s][p][c][b][e] (s = value, tangent)
+hipError_t launch_grad_mfma(int cfg, bool jvp, const double* U, const double* V, double* Gm, const MTables& mt,
+                            const Mesh& m, hipStream_t s);
+hipError_t launch_grad_mfma_f32(int cfg, bool jvp, const double* U, const double* V, float* Gm, const MTablesF& mt,
+                                const Mesh& m, hipStream_t s);
+hipError_t launch_volume_mfma(int cfg, bool jvp, const double* U, const double* V, const double* Gm, const double* H,
+                              double* out,
                               double shift, const MTables& mt, const Mesh& m, const Phys& ph, hipStream_t stream);
 hipError_t launch_project(int cfg, const double* f, double* w, const Tables& tb, const Mesh& m, hipStream_t s);
 hipError_t launch_points(int cfg, double* xyz, const Tables& tb, const Mesh& m, hipStream_t s);

@@ -10,10 +10,12 @@
 // g+12 of column col, which is exactly the B operand of a following MFMA
 // whose k-steps walk those rows in order.
 //
+// Gradient kernel (one wave per tile of 16 elements, direction and
+// value/tangent): the modal corrected gradients G_p = d_p U + R^K_p by MFMA
+// from the element and its +/-p neighbours, written to a global buffer.
 // Volume kernel (one workgroup = 4 waves = 16 elements):
-//   1. modal fields per element (U and the corrected gradients G_p =
-//      d_p U + R^K_p, computed by MFMA from the element and its +/-p
-//      neighbours) are formed directly in B-fragment order and kept in registers (each wave owns a quarter of the
+//   1. modal fields per element (U and the three G_p) are loaded in
+//      B-fragment order and kept in registers (each wave owns a quarter of the
 //      (value/tangent, field, variable) column blocks);
 //   2. per block of 16 quadrature points: MFMA interpolation -> LDS stage ->
 //      one thread per (point, element) evaluates the volume flux (dual numbers
@@ -56,11 +58,70 @@ template <> struct MP<float> {
   static constexpr int ksv(int nb) { return 4 * ((nb + 15) / 16); }
 };
 
+// Tile processed by this workgroup.  Workgroups are dispatched round-robin
+// over the 8 XCDs (each with its own L2); giving every XCD a contiguous range
+// of tiles keeps a tile's face neighbours (x: adjacent tiles, y: 2 tiles
+// away, z: 64 tiles away on a 32^3 lattice) in the same L2.
+DEV int64_t xcd_tile(int64_t bid, int64_t nblk) {
+  constexpr int64_t kXcd = 8;
+  const int64_t q = nblk / kXcd, r = nblk % kXcd, x = bid % kXcd;
+  return x * q + (x < r ? x : r) + bid / kXcd;
+}
+
+// ------------------------------------------------------------------ corrected gradients
+// Modal corrected gradients G_p = d_p U + R^K_p of every element (the modal
+// form of the BR2 consistent gradient on affine elements):
+//   G_p = L_{p,0} U_e + L_{p,1} U_{e+p} + L_{p,2} U_{e-p},
+// one wave per (tile of 16 elements, direction p, value/tangent s), all
+// variables; B fragments straight from global memory (no LDS, no barriers).
+// Output layout Gm[s][p][c][b][e].
+template <class R, int NB>
+__global__ __launch_bounds__(64) void k_grad_mfma(const double* __restrict__ U, const double* __restrict__ V,
+                                                  R* __restrict__ Gm, const R* __restrict__ lA, Mesh m) {
+  using F = typename MP<R>::frag;
+  constexpr int DIM = 3, NV = 5;
+  constexpr int KSB = (NB + 3) / 4, MB = (NB + 15) / 16;
+  const int lane = threadIdx.x;
+  const int g = lane >> 4, col = lane & 15;
+  const int64_t ne = m.ne;
+  const int64_t e = xcd_tile(blockIdx.x, gridDim.x) * 16 + col;
+  const bool ev = e < ne;
+  const int p = blockIdx.y, s = blockIdx.z;
+  const double* __restrict__ X = (s == 0) ? U : V;
+  int64_t es[3] = {e, e, e};  // sources: the element, its +p and its -p neighbour
+  if (ev) {
+    es[1] = m.nbr[(2 * p + 1) * ne + e];
+    es[2] = m.nbr[(2 * p) * ne + e];
+  }
+#pragma unroll 1
+  for (int c = 0; c < NV; ++c) {
+    R bf[3 * KSB];
+#pragma unroll
+    for (int ks3 = 0; ks3 < 3 * KSB; ++ks3) {
+      const int src = ks3 / KSB, bp = g + 4 * (ks3 % KSB);
+      bf[ks3] = (ev && bp < NB) ? (R)X[(size_t)(c * NB + bp) * ne + es[src]] : R(0);
+    }
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+      F d = {0, 0, 0, 0};
+#pragma unroll
+      for (int ks3 = 0; ks3 < 3 * KSB; ++ks3)
+        d = MP<R>::mma(lA[(((size_t)p * MB + mb) * 3 * KSB + ks3) * 64 + lane], bf[ks3], d);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int b = 16 * mb + MP<R>::drow(g, r);
+        if (ev && b < NB) Gm[((size_t)((s * DIM + p) * NV + c) * NB + b) * ne + e] = d[r];
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------------------ volume
 template <class R, int NB, int NQ1, int KL, bool JVP>
 __global__ __launch_bounds__(256, 2) void k_volume_mfma(const double* __restrict__ U, const double* __restrict__ V,
-                                                     const R* __restrict__ H, double* __restrict__ out,
-                                                     double shift, MTablesT<R> mt, Mesh m, Phys ph) {
+                                                     const R* __restrict__ Gm, const R* __restrict__ H,
+                                                     double* __restrict__ out, double shift, MTablesT<R> mt,
+                                                     Mesh m, Phys ph) {
   using T = typename Scalar<JVP, R>::type;
   using F = typename MP<R>::frag;
   constexpr int DIM = 3, NV = 5;
@@ -74,23 +135,20 @@ __global__ __launch_bounds__(256, 2) void k_volume_mfma(const double* __restrict
   constexpr int NPB = NV * MB;                // projection accumulator blocks (variable, mode block)
   constexpr int NPBW = (NPB + 3) / 4;
   static_assert(NFC % 4 == 0, "column blocks must split over 4 waves");
-  constexpr int STAGE_ROWS = (NFC * 256 > 3 * NV * NB * 16) ? NFC : (3 * NV * NB + 15) / 16;
-  __shared__ R stage[STAGE_ROWS][16][16];
+  __shared__ R stage[NFC][16][16];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int g = lane >> 4, col = lane & 15;
   const int64_t ne = m.ne;
-  const int64_t e0 = (int64_t)blockIdx.x * 16;
+  const int64_t e0 = xcd_tile(blockIdx.x, gridDim.x) * 16;
   const int64_t e = e0 + col;
   const bool ev = e < ne;
   const double kap = ph.mu * ph.gamma / (ph.prandtl * (ph.gamma - 1.0));
 
-  // ---- 1. modal fields in B-fragment order: Bf[i][ks] = X[b = bmode(g, ks)][e].
-  // The corrected-gradient maps are applied with MFMA from LDS copies of the
-  // element's and its +/-p neighbours' modes, one (value/tangent, p) round at a
-  // time.
+  // ---- 1. modal fields in B-fragment order: Bf[i][ks] = X[b = bmode(g, ks)][e],
+  // X = U (or V) for f = 0 and the corrected gradient G_f for f = 1..3.
   R Bf[NCBW][KSV];
 #pragma unroll
   for (int i = 0; i < NCBW; ++i) {
@@ -98,56 +156,13 @@ __global__ __launch_bounds__(256, 2) void k_volume_mfma(const double* __restrict
     const int fc = wave + 4 * (i % (NFC / 4));
     const int f = fc / NV, c = fc % NV;
     const double* __restrict__ X = (s == 0) ? U : V;
+    const R* __restrict__ Gf = Gm + (size_t)((s * DIM + (f > 0 ? f - 1 : 0)) * NV + c) * NB * ne;
 #pragma unroll
     for (int ks = 0; ks < KSV; ++ks) {
       const int b = MP<R>::bmode(g, ks);
-      Bf[i][ks] = (f == 0 && ev && b < NB) ? (R)X[(size_t)(c * NB + b) * ne + e] : R(0);
-    }
-  }
-  R* sl = &stage[0][0][0];  // [src][c][b][16]
-#pragma unroll
-  for (int s = 0; s < NS; ++s) {
-    const double* __restrict__ X = (s == 0) ? U : V;
-#pragma unroll
-    for (int p = 0; p < DIM; ++p) {
-      for (int it = tid; it < 3 * NV * NB * 16; it += 256) {
-        const int t = it & 15;
-        int r = it >> 4;
-        const int b = r % NB;
-        r /= NB;
-        const int c = r % NV, src = r / NV;
-        const int64_t et2 = e0 + t;
-        R val = R(0);
-        if (et2 < ne) {
-          const int64_t es = (src == 0) ? et2 : m.nbr[(2 * p + (src == 1 ? 1 : 0)) * ne + et2];
-          val = (R)X[(size_t)(c * NB + b) * ne + es];
-        }
-        sl[it] = val;
-      }
-      __syncthreads();
-      // G_p[b][e] = sum_{src, b'} L_src,p[b][b'] X_src[b'][e]: MFMA with rows = modes,
-      // k = (source, mode); register r of the result is fragment k-step 4 mb + r.
-#pragma unroll
-      for (int i = s * (NFC / 4); i < (s + 1) * (NFC / 4); ++i) {
-        const int fc = wave + 4 * (i % (NFC / 4));
-        const int f = fc / NV, c = fc % NV;
-        if (f == p + 1) {
-#pragma unroll
-          for (int mb = 0; mb < MB; ++mb) {
-            F d = {0, 0, 0, 0};
-#pragma unroll
-            for (int ks3 = 0; ks3 < 3 * KSB; ++ks3) {
-              const int src = ks3 / KSB, bp = g + 4 * (ks3 % KSB);
-              const R bv = (bp < NB) ? sl[((src * NV + c) * NB + bp) * 16 + col] : R(0);
-              d = MP<R>::mma(mt.lA[(((size_t)p * MB + mb) * 3 * KSB + ks3) * 64 + lane], bv, d);
-            }
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-              if (4 * mb + r < KSV) Bf[i][4 * mb + r] = d[r];
-          }
-        }
-      }
-      __syncthreads();
+      R x = R(0);
+      if (ev && b < NB) x = (f == 0) ? (R)X[(size_t)(c * NB + b) * ne + e] : Gf[(size_t)b * ne + e];
+      Bf[i][ks] = x;
     }
   }
 
@@ -282,7 +297,7 @@ DEV void face_mfma_body(const double* __restrict__ U, const double* __restrict__
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int g = lane >> 4, col = lane & 15;
   const int64_t ne = m.ne;
-  const int64_t e0 = (int64_t)blockIdx.x * 16;
+  const int64_t e0 = xcd_tile(blockIdx.x, gridDim.x) * 16;
   const int64_t e = e0 + col;
   const bool ev = e < ne;
   const int64_t er = ev ? m.nbr[(2 * P + 1) * ne + e] : 0;
@@ -412,17 +427,32 @@ hipError_t face_mfma_dispatch(int cfg, bool jvp, const double* U, const double* 
 }
 
 template <class R>
-hipError_t volume_mfma_dispatch(int cfg, bool jvp, const double* U, const double* V, const R* H, double* out,
-                                double shift, const MTablesT<R>& mt, const Mesh& m, const Phys& ph, hipStream_t s) {
-#define X(id, nb_, nq_, kl_)                                                                        \
-  case id: {                                                                                        \
-    if (mt.kl != kl_) return hipErrorInvalidValue;                                                  \
-    dim3 grid((unsigned)((m.ne + 15) / 16));                                                        \
-    if (jvp)                                                                                        \
-      k_volume_mfma<R, nb_, nq_, kl_, true><<<grid, 256, 0, s>>>(U, V, H, out, shift, mt, m, ph);   \
-    else                                                                                            \
-      k_volume_mfma<R, nb_, nq_, kl_, false><<<grid, 256, 0, s>>>(U, V, H, out, shift, mt, m, ph);  \
-    return hipGetLastError();                                                                       \
+hipError_t volume_mfma_dispatch(int cfg, bool jvp, const double* U, const double* V, const R* Gm, const R* H,
+                                double* out, double shift, const MTablesT<R>& mt, const Mesh& m, const Phys& ph,
+                                hipStream_t s) {
+#define X(id, nb_, nq_, kl_)                                                                             \
+  case id: {                                                                                             \
+    if (mt.kl != kl_) return hipErrorInvalidValue;                                                       \
+    dim3 grid((unsigned)((m.ne + 15) / 16));                                                             \
+    if (jvp)                                                                                             \
+      k_volume_mfma<R, nb_, nq_, kl_, true><<<grid, 256, 0, s>>>(U, V, Gm, H, out, shift, mt, m, ph);    \
+    else                                                                                                 \
+      k_volume_mfma<R, nb_, nq_, kl_, false><<<grid, 256, 0, s>>>(U, V, Gm, H, out, shift, mt, m, ph);   \
+    return hipGetLastError();                                                                            \
+  }
+  switch (cfg) { DG_MFMA_CONFIGS(X) }
+#undef X
+  return hipErrorInvalidValue;
+}
+
+template <class R>
+hipError_t grad_mfma_dispatch(int cfg, bool jvp, const double* U, const double* V, R* Gm, const MTablesT<R>& mt,
+                              const Mesh& m, hipStream_t s) {
+#define X(id, nb_, nq_, kl_)                                                                \
+  case id: {                                                                                \
+    dim3 grid((unsigned)((m.ne + 15) / 16), 3, jvp ? 2 : 1);                                \
+    k_grad_mfma<R, nb_><<<grid, 64, 0, s>>>(U, V, Gm, mt.lA, m);                            \
+    return hipGetLastError();                                                               \
   }
   switch (cfg) { DG_MFMA_CONFIGS(X) }
 #undef X
@@ -434,9 +464,20 @@ hipError_t launch_face_mfma(int cfg, bool jvp, const double* U, const double* V,
   return face_mfma_dispatch<double>(cfg, jvp, U, V, H, mt, m, ph, s);
 }
 
-hipError_t launch_volume_mfma(int cfg, bool jvp, const double* U, const double* V, const double* H, double* out,
-                              double shift, const MTables& mt, const Mesh& m, const Phys& ph, hipStream_t s) {
-  return volume_mfma_dispatch<double>(cfg, jvp, U, V, H, out, shift, mt, m, ph, s);
+hipError_t launch_volume_mfma(int cfg, bool jvp, const double* U, const double* V, const double* Gm, const double* H,
+                              double* out, double shift, const MTables& mt, const Mesh& m, const Phys& ph,
+                              hipStream_t s) {
+  return volume_mfma_dispatch<double>(cfg, jvp, U, V, Gm, H, out, shift, mt, m, ph, s);
+}
+
+hipError_t launch_grad_mfma(int cfg, bool jvp, const double* U, const double* V, double* Gm, const MTables& mt,
+                            const Mesh& m, hipStream_t s) {
+  return grad_mfma_dispatch<double>(cfg, jvp, U, V, Gm, mt, m, s);
+}
+
+hipError_t launch_grad_mfma_f32(int cfg, bool jvp, const double* U, const double* V, float* Gm, const MTablesF& mt,
+                                const Mesh& m, hipStream_t s) {
+  return grad_mfma_dispatch<float>(cfg, jvp, U, V, Gm, mt, m, s);
 }
 
 hipError_t launch_face_mfma_f32(int cfg, bool jvp, const double* U, const double* V, float* H, const MTablesF& mt,
@@ -444,9 +485,10 @@ hipError_t launch_face_mfma_f32(int cfg, bool jvp, const double* U, const double
   return face_mfma_dispatch<float>(cfg, jvp, U, V, H, mt, m, ph, s);
 }
 
-hipError_t launch_volume_mfma_f32(int cfg, bool jvp, const double* U, const double* V, const float* H, double* out,
-                                  double shift, const MTablesF& mt, const Mesh& m, const Phys& ph, hipStream_t s) {
-  return volume_mfma_dispatch<float>(cfg, jvp, U, V, H, out, shift, mt, m, ph, s);
+hipError_t launch_volume_mfma_f32(int cfg, bool jvp, const double* U, const double* V, const float* Gm,
+                                  const float* H, double* out, double shift, const MTablesF& mt, const Mesh& m,
+                                  const Phys& ph, hipStream_t s) {
+  return volume_mfma_dispatch<float>(cfg, jvp, U, V, Gm, H, out, shift, mt, m, ph, s);
 }
 
 }  // namespace dgk
