@@ -4,7 +4,7 @@
 Taylor-Green-like synthetic field), plus wall time to a 1e-8 FGMRES solve of
 one backward-Euler system (P4, 24^3 hexes, CFL 100, block-Jacobi).
 
-One step = one Jv (face kernel + volume kernel) on data resident in HBM.
+One step = one Jv (gradient, face and volume kernels) on data resident in HBM.
 Prints one JSON line (see the keys below).  --gpus > 1 is not supported:
 this build runs on a single GPU.
 """
@@ -30,17 +30,20 @@ def jv_kernel_flops(ne, nb, nq, nfq, d):
     Per element: volume part 2*[2 Nq Nb n (1+3d)] (interpolation of U and
     grad U, lifting at the volume points, projection; value and tangent);
     face part 2*[d * 2 Nfq Nb n (2d+8)] (traces of both sides, local
-    liftings, face projection).  The face projection (2 of the 2d+8 units) is
-    done by the volume kernel here.
+    liftings, face projection).  Placement in this build: the d lifting units
+    are the gradient kernel's (modal corrected gradients), the face
+    projection (2 of the 2d+8 face units) is done by the volume kernel.
     """
     n = d + 2
-    vol = 2 * (2 * nq * nb * n * (1 + 3 * d))
+    unit = 2 * (2 * nq * nb * n)
     face = 2 * (d * 2 * nfq * nb * n * (2 * d + 8))
     face_proj = face * 2 / (2 * d + 8)
-    return {"vol_jvp": (vol + face_proj) * ne, "face_jvp": (face - face_proj) * ne}
+    return {"vol_jvp": (unit * (1 + 2 * d) + face_proj) * ne, "grad_jvp": unit * d * ne,
+            "face_jvp": (face - face_proj) * ne}
 
 
 KERNEL_SOURCES = ("dg_mfma.hip", "dg_device.h")
+KERNELS = ("grad_jvp", "face_jvp", "vol_jvp")
 
 
 def kernel_source_sha():
@@ -235,7 +238,7 @@ def main():
         g.jvp(w, v, out=out)
     torch.cuda.synchronize()
     g.set_profiling(True)
-    for k in ("face_jvp", "vol_jvp"):
+    for k in KERNELS:
         g.kernel_time(k)  # reset
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -244,7 +247,7 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     g.set_profiling(False)
-    kt = {k: g.kernel_time(k) for k in ("face_jvp", "vol_jvp")}
+    kt = {k: g.kernel_time(k) for k in KERNELS}
     assert torch.isfinite(out).all()
     # the reduced-precision operator (FP32 contractions and fluxes) on the same
     # workload, reported beside the FP64 metric (it serves preconditioners only)

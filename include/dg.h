@@ -133,8 +133,10 @@ dg_status dg_jvp(dg_context* ctx, const double* w, const double* r_w, const doub
  * coloured probing with exact Jv), factored by Gauss-Jordan with partial
  * pivoting into explicit inverses, stored as `storage`: DG_FP64 (FP64
  * elimination), DG_FP32 (FP32 elimination) or DG_BF16 (FP32 elimination,
- * inverse rounded to BF16; the apply accumulates in FP32).  Reduced precision
- * only changes the preconditioner, never the FP64 operator of the solve.
+ * inverse rounded to BF16; the apply accumulates in FP32).  With DG_FP32 or
+ * DG_BF16 the blocks are also probed with the FP32 operator (dg_residual_fp32)
+ * where the configuration has it.  Reduced precision only changes the
+ * preconditioner, never the FP64 operator of the solve.
  * Returns DG_ERR_SINGULAR_BLOCK if a pivot is exactly zero or non-finite
  * (synchronises the stream). */
 dg_status dg_block_precond_setup(dg_context* ctx, const double* w, double shift, int storage, void* stream);
@@ -194,9 +196,9 @@ typedef struct {
                            every apply replays it on a library stream ordered
                            against the caller's stream by events */
   int fine_precision;   /* DG_FP64 or DG_FP32: the fine-level operator inside
-                           the cycle (smoother products and the defect) as the
-                           exact FP64 Jv or its FP32 variant; coarse operators,
-                           the probing and the outer solve stay FP64 */
+                           the cycle (smoother products and the defect) and the
+                           probing of the coarse operators as the exact FP64 Jv
+                           or its FP32 variant; the outer solve stays FP64 */
 } dg_mg_opts;
 
 /* Builds the hierarchy at state w (device, copied) and shift: runs the fine

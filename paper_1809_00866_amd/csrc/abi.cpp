@@ -409,12 +409,16 @@ dg_status dg_block_precond_setup(dg_context* c, const double* w, double shift, i
       c->dinv_bytes = need;
     }
   }
+  // reduced-precision factors are probed with the FP32 operator where it exists
+  const bool probe_f32 = storage != DG_FP64 && c->use_mfma && c->d_mtab_f;
   {
     ProfScope ps(c, "block_probe", s);
     for (int col = 0; col < c->ncolor; ++col)
       for (int l = 0; l < m; ++l) {
         HIPCHK(dgk::launch_probe_vector(c->d_t1, c->d_color, col, l, c->nb, c->nv, c->ne, s));
-        if ((st = eval_residual(c, true, w, c->d_t1, shift, c->d_t2, s)) != DG_OK) return st;
+        if ((st = probe_f32 ? eval_residual_f32(c, true, w, c->d_t1, shift, c->d_t2, s)
+                            : eval_residual(c, true, w, c->d_t1, shift, c->d_t2, s)) != DG_OK)
+          return st;
         HIPCHK(dgk::launch_extract_column(c->d_t2, c->d_color, col, l, m, c->ne, shift, c->d_D64, s));
       }
   }

@@ -354,7 +354,9 @@ dg_status dg_mg_setup(dg_context* c, const double* w, double shift, const dg_mg_
       for (int l = 0; l < C.m; ++l) {
         const int lf = (l / C.nb) * c->nb + l % C.nb;
         HIPCHK(dgk::launch_probe_vector(c->d_t1, M->color2, col, lf, c->nb, nv, ne, s));
-        if ((st = eval_residual(c, true, M->w, c->d_t1, shift, c->d_t2, s)) != DG_OK) return bail(st);
+        if ((st = M->fine_f32 ? eval_residual_f32(c, true, M->w, c->d_t1, shift, c->d_t2, s)
+                              : eval_residual(c, true, M->w, c->d_t1, shift, c->d_t2, s)) != DG_OK)
+          return bail(st);
         HIPCHK(dgk::launch_extract_bsr(c->d_t2, M->color2, col, l, c->mesh.nbr, nf, c->nb, C.nb, nv, ne, C.B, s));
       }
   }
