@@ -389,14 +389,15 @@ dg_status dg_block_precond_setup(dg_context* c, const double* w, double shift, i
   dg_status st;
   c->blk_ready = false;
   mg_invalidate(c->mg);
-  if ((st = dalloc(&c->d_D64, (size_t)c->ne * m * m)) != DG_OK) return st;
+  const int ld = dgk::block_ld(m);
+  if ((st = dalloc(&c->d_D64, (size_t)c->ne * m * ld)) != DG_OK) return st;
   if (storage == DG_FP64) {
     // FP64 inverses overwrite the probed blocks in place
     if (c->d_Dinv && c->d_Dinv != c->d_D64) dfree(c->d_Dinv);
     c->d_Dinv = c->d_D64;
     c->dinv_bytes = 0;
   } else {
-    const size_t need = (size_t)c->ne * m * m * (storage == DG_FP32 ? sizeof(float) : sizeof(uint16_t));
+    const size_t need = (size_t)c->ne * m * ld * (storage == DG_FP32 ? sizeof(float) : sizeof(uint16_t));
     if (c->d_Dinv == c->d_D64) c->d_Dinv = nullptr;
     if (c->d_Dinv && c->dinv_bytes != need) {
       dfree(c->d_Dinv);
@@ -426,7 +427,7 @@ dg_status dg_block_precond_setup(dg_context* c, const double* w, double shift, i
   HIPCHK(hipMemcpyAsync(c->d_flag, &zero, sizeof(int), hipMemcpyHostToDevice, s));
   {
     ProfScope ps(c, "block_invert", s);
-    HIPCHK(dgk::launch_block_invert(storage, c->d_D64, c->d_Dinv, m, c->ne, c->d_flag, s));
+    HIPCHK(dgk::launch_block_invert(storage, c->d_D64, ld, c->d_Dinv, m, c->ne, c->d_flag, s));
   }
   int bad = 0;
   HIPCHK(hipMemcpyAsync(&bad, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));

@@ -122,7 +122,12 @@ hipError_t launch_probe_vector(double* P, const int* color, int col, int l, int 
                                hipStream_t s);
 hipError_t launch_extract_column(const double* Jv, const int* color, int col, int l, int m, int64_t ne,
                                  double shift, double* D, hipStream_t s);
-hipError_t launch_block_invert(int storage, double* D64, void* Dout, int m, int64_t ne, int* info, hipStream_t s);
+// Stored block inverses use the column stride block_ld(m) (16-byte aligned
+// columns for every storage type); D64 holds probed blocks with column
+// stride ldd (block_ld(m) for the fine blocks).
+constexpr int block_ld(int m) { return (m + 7) / 8 * 8; }
+hipError_t launch_block_invert(int storage, double* D64, int ldd, void* Dout, int m, int64_t ne, int* info,
+                               hipStream_t s);
 hipError_t launch_block_apply(int storage, const void* Dinv, int m, int64_t ne, const double* r, double* z,
                               hipStream_t s);
 

@@ -371,11 +371,11 @@ dg_status dg_mg_setup(dg_context* c, const double* w, double shift, const dg_mg_
     MgLevel& C = M->lev[l];
     const size_t esz = o->storage == DG_FP64 ? 8 : (o->storage == DG_FP32 ? 4 : 2);
     unsigned char* p = nullptr;
-    if ((st = dalloc(&p, (size_t)ne * C.m * C.m * esz)) != DG_OK) return bail(st);
+    if ((st = dalloc(&p, (size_t)ne * C.m * dgk::block_ld(C.m) * esz)) != DG_OK) return bail(st);
     C.Dinv = p;
     int zero = 0;
     HIPCHK(hipMemcpyAsync(c->d_flag, &zero, sizeof(int), hipMemcpyHostToDevice, s));
-    HIPCHK(dgk::launch_block_invert(o->storage, C.B, C.Dinv, C.m, ne, c->d_flag, s));
+    HIPCHK(dgk::launch_block_invert(o->storage, C.B, C.m, C.Dinv, C.m, ne, c->d_flag, s));
     int bad = 0;
     HIPCHK(hipMemcpyAsync(&bad, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
