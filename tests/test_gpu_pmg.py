@@ -38,6 +38,7 @@ CASES = {
     # name: mesh, fine order, nq1d, orders, smoothing iterations, shift
     "P2-P1": ((2, 3, 2), 2, 3, (2, 1), (3, 10), 6.0),
     "P4-P2-P1": ((1, 2, 2), 4, 5, (4, 2, 1), (2, 2, 6), 6.0),
+    "2d-P2-P1-P0": ((3, 4), 2, 4, (2, 1, 0), (3, 3, 12), 6.0),
 }
 
 
@@ -47,8 +48,10 @@ def case(request):
     N, k, nq, orders, iters, shift = CASES[request.param]
     _say(f"p-MG case {request.param}: oracle set-up")
     mesh = synth.lattice_mesh(N, L=1.0)
-    o = DGOracle(mesh, k, "P", nq, NavierStokes(3, mu=1e-2))
-    U = o.project(synth.TaylorGreenStandIn(seed=21, L=1.0))
+    d = len(N)
+    o = DGOracle(mesh, k, "P", nq, NavierStokes(d, mu=1e-2))
+    fld = synth.TaylorGreenStandIn(seed=21, L=1.0) if d == 3 else synth.FreeStreamPlusModes(seed=21)
+    U = o.project(fld)
     U = U + 1e-2 * np.random.default_rng(21).standard_normal(U.shape) * np.abs(U[:, :, :1])
     mg = PMultigrid(o, U, shift, orders, iters)
     g = DG(mesh, k, nq1d=nq, mu=1e-2)
@@ -153,7 +156,7 @@ def test_fp32_fine_operator_inside_the_cycle_keeps_the_fp64_solution(case):
     """Reduced precision only inside the preconditioner: with the FP32 fine
     operator in the smoothers the outer FP64 FGMRES still reaches 1e-10."""
     o, U, g, w, shift = case["o"], case["U"], case["g"], case["w"], case["shift"]
-    if case["k"] < 2:
+    if case["k"] < 2 or len(case["mesh"]["N"]) != 3:
         pytest.skip("the FP32 operator covers 3D P2-P4")
     _say("p-MG with the FP32 fine operator")
     from paper_1809_00866_amd import DG
