@@ -18,7 +18,13 @@ With the hierarchical orthonormal modal basis of the fine discretisation
   coarsest-level SOLVE is the same smoother from x0 = 0 with its own count;
 * Alg. vcic: pre-smoothing, coarse-grid correction of the defect,
   post-smoothing; called on the fine level with a zero initial guess, it is
-  the (nonlinear, hence flexible-GMRES) preconditioner of the outer solve.
+  the (nonlinear, hence flexible-GMRES) preconditioner of the outer solve;
+* Alg. fullvcic (the full cycle): the right-hand side is restricted to the
+  next level, solved there by the full cycle, prolonged as the initial
+  iterate, and corrected by one V-cycle on the defect.  The full cycle runs as
+  the algorithm lists it: its V-cycle correction smooths the level twice (the
+  text's count of one fine smoothing per full cycle is not what the listing
+  does).
 
 Arrays use the oracle layout X[e, c, b]; level l has N_b(k_l) modes.
 """
@@ -102,10 +108,10 @@ class PMultigrid:
     iterations per level, the last one being the coarsest-level solve.
     """
 
-    def __init__(self, o, U, shift, orders, iters):
+    def __init__(self, o, U, shift, orders, iters, cycle="V"):
         assert orders[0] == o.order and all(a > b for a, b in zip(orders, orders[1:]))
-        assert len(iters) == len(orders)
-        self.o, self.U, self.shift = o, U, float(shift)
+        assert len(iters) == len(orders) and cycle in ("V", "full")
+        self.o, self.U, self.shift, self.cycle = o, U, float(shift), cycle
         self.iters = list(iters)
         self.nbs = [basis_size(k, o.d) for k in orders]
         self.L = len(orders) - 1
@@ -143,6 +149,18 @@ class PMultigrid:
             trace[l] = (w, w_hat)
         return self.smooth(l, g, w_hat)                                   # post-smoothing
 
+    def full(self, l, g):
+        """MG_full(l, g, 0) on flat level-l vectors (Alg. fullvcic)."""
+        if l == self.L:
+            return self.smooth(l, g, None)
+        gc = restrict(g.reshape(self._shape(l)), self.nbs[l + 1]).reshape(-1)
+        w_hat = prolong(self.full(l + 1, gc).reshape(self._shape(l + 1)), self.nbs[l]).reshape(-1)
+        d = g - self.apply_G(l, w_hat)                                    # defect of the prolonged solution
+        return w_hat + self.vcycle(l, d)                                  # V-cycle correction
+
     def apply(self, R):
-        """The preconditioner: Z = MG_V(0, R, 0) for R[e, c, b] on the fine level."""
-        return self.vcycle(0, np.asarray(R, dtype=np.float64).reshape(-1)).reshape(self._shape(0))
+        """The preconditioner on the fine level, R[e, c, b] -> Z: MG_V(0, R, 0),
+        or MG_full(0, R, 0) for the full cycle."""
+        g = np.asarray(R, dtype=np.float64).reshape(-1)
+        z = self.vcycle(0, g) if self.cycle == "V" else self.full(0, g)
+        return z.reshape(self._shape(0))

@@ -1,4 +1,4 @@
-"""Pins for the oracle's p-multigrid V-cycle (Sec. 2.4, Alg. vcic, eq. GalProj).
+"""Pins for the oracle's p-multigrid cycles (Sec. 2.4, Algs. vcic and fullvcic, eq. GalProj).
 
 Each pin checks the oracle against something other than itself: the coarse
 discretisation built independently at the lower degree, the colour-probed
@@ -152,6 +152,37 @@ def test_coarse_correction_annihilates_the_restricted_defect():
     assert np.linalg.norm(rd) <= 1e-10 * np.linalg.norm(g)
     assert np.linalg.norm(res(w)) < np.linalg.norm(g)
     assert np.linalg.norm(res(z)) < np.linalg.norm(res(w_hat))
+
+
+def test_full_cycle_two_grid_is_the_galerkin_solve_and_its_correction_vanishes():
+    """Alg. fullvcic on two levels with no fine smoothing and an exact coarsest
+    solve: the prolonged coarse solution w_hat = P (R G P)^-1 R g has a defect
+    whose restriction is zero, so the V-cycle correction adds nothing and the
+    cycle returns w_hat (a wrong sign of the defect would double it)."""
+    mesh, o, U = _state((1, 1, 2), 2, 3)
+    shift = 4.0
+    nc = o.ne * o.nvar * 4
+    mg = PMultigrid(o, U, shift, orders=(2, 1), iters=(0, nc), cycle="full")
+    R = np.random.default_rng(11).standard_normal(U.shape)
+    z = mg.apply(R)
+    A1 = inherited_matrix(o, U, shift, 4)
+    zc = np.linalg.solve(A1, restrict(R, 4).reshape(-1)).reshape(o.ne, o.nvar, 4)
+    assert np.linalg.norm(z - prolong(zc, o.nb)) <= 1e-9 * np.linalg.norm(zc)
+
+
+def test_full_cycle_three_levels_with_exact_middle_smoothing():
+    """Three levels (P2/P1/P0), exact GMRES on the two coarse levels and no fine
+    smoothing: the level-1 full cycle ends with an exact post-smoothing, so the
+    result is again P (R G P)^-1 R g with the level-1 inherited operator."""
+    mesh, o, U = _state((1, 1, 2), 2, 3)
+    shift = 4.0
+    n1, n2 = o.ne * o.nvar * 4, o.ne * o.nvar
+    R = np.random.default_rng(12).standard_normal(U.shape)
+    A1 = inherited_matrix(o, U, shift, 4)
+    zc = np.linalg.solve(A1, restrict(R, 4).reshape(-1)).reshape(o.ne, o.nvar, 4)
+    mg = PMultigrid(o, U, shift, orders=(2, 1, 0), iters=(0, n1, n2), cycle="full")
+    z = mg.apply(R)
+    assert np.linalg.norm(z - prolong(zc, o.nb)) <= 1e-9 * np.linalg.norm(zc)
 
 
 @pytest.mark.slow
