@@ -136,6 +136,7 @@ __global__ __launch_bounds__(256, 2) void k_volume_mfma(const double* __restrict
   constexpr int NPBW = (NPB + 3) / 4;
   static_assert(NFC % 4 == 0, "column blocks must split over 4 waves");
   __shared__ R stage[NFC][16][16];
+  __shared__ R ptab[MB * KSP * 64];  // projection table of the current point block (A operands of every wave)
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -172,6 +173,10 @@ __global__ __launch_bounds__(256, 2) void k_volume_mfma(const double* __restrict
 
   const int ql = tid >> 4, et = tid & 15;  // pointwise mapping: (point in block, element)
   for (int rb = 0; rb < RBQ; ++rb) {
+    // stage this block's projection table (read after the barriers below;
+    // the previous block's projection ended with a barrier)
+    for (int idx = tid; idx < MB * KSP * 64; idx += 256) ptab[idx] = mt.pA[(size_t)rb * MB * KSP * 64 + idx];
+    __syncthreads();
     R st[NS][NFC];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
@@ -235,23 +240,27 @@ __global__ __launch_bounds__(256, 2) void k_volume_mfma(const double* __restrict
 #pragma unroll
         for (int ks = 0; ks < KSP; ++ks) {
           const int k = g + 4 * ks;
-          acc[i] = MP<R>::mma(mt.pA[(((size_t)rb * MB + mb) * KSP + ks) * 64 + lane],
-                              stage[(k >> 4) * NV + c][k & 15][col], acc[i]);
+          acc[i] = MP<R>::mma(ptab[(mb * KSP + ks) * 64 + lane], stage[(k >> 4) * NV + c][k & 15][col], acc[i]);
         }
       }
     }
     __syncthreads();
   }
 
-  // ---- 3. face contributions (+ on the element's own +p faces, - on its -p faces)
+  // ---- 3. face contributions (+ on the element's own +p faces, - on its -p faces);
+  // the face projection table of direction p is staged in the idle stage buffer
+  static_assert(2 * MB * KSF * 64 <= NFC * 256, "face table slice must fit the stage buffer");
+  R* ftab = &stage[0][0][0];
 #pragma unroll
-  for (int i = 0; i < NPBW; ++i) {
-    const int pb = wave + 4 * i;
-    if (pb < NPB) {
-      const int c = pb / MB, mb = pb % MB;
+  for (int p = 0; p < DIM; ++p) {
+    for (int idx = tid; idx < 2 * MB * KSF * 64; idx += 256) ftab[idx] = mt.fA[(size_t)p * 2 * MB * KSF * 64 + idx];
+    __syncthreads();
+    const int64_t em = ev ? m.nbr[(2 * p) * ne + e] : 0;
 #pragma unroll
-      for (int p = 0; p < DIM; ++p) {
-        const int64_t em = ev ? m.nbr[(2 * p) * ne + e] : 0;
+    for (int i = 0; i < NPBW; ++i) {
+      const int pb = wave + 4 * i;
+      if (pb < NPB) {
+        const int c = pb / MB, mb = pb % MB;
 #pragma unroll
         for (int side = 0; side < 2; ++side) {
           const int64_t es = side ? e : em;
@@ -259,10 +268,18 @@ __global__ __launch_bounds__(256, 2) void k_volume_mfma(const double* __restrict
           for (int ks = 0; ks < KSF; ++ks) {
             const int fq = g + 4 * ks;
             const R hb = (ev && fq < NFQ) ? H[((size_t)(p * NV + c) * NFQ + fq) * ne + es] : R(0);
-            acc[i] = MP<R>::mma(mt.fA[((((size_t)p * 2 + side) * MB + mb) * KSF + ks) * 64 + lane], hb, acc[i]);
+            acc[i] = MP<R>::mma(ftab[((side * MB + mb) * KSF + ks) * 64 + lane], hb, acc[i]);
           }
         }
       }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < NPBW; ++i) {
+    const int pb = wave + 4 * i;
+    if (pb < NPB) {
+      const int c = pb / MB, mb = pb % MB;
       if (ev) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
