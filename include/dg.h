@@ -61,6 +61,7 @@ enum { DG_FLUX_LF = 0, DG_FLUX_ROE = 1 };           /* convective numerical flux
 enum { DG_JVP_EXACT = 0, DG_JVP_FD = 1, DG_JVP_EXACT_FP32 = 2 };  /* Jv mode */
 enum { DG_FP64 = 0, DG_FP32 = 1, DG_BF16 = 2 };     /* block-factor storage */
 enum { DG_PREC_NONE = 0, DG_PREC_BJ = 1, DG_PREC_MG = 2, DG_PREC_MLP = 3 };  /* FGMRES preconditioner */
+enum { DG_MG_V = 0, DG_MG_FULL = 1 };               /* p-multigrid cycle (Algs. vcic, fullvcic) */
 
 /* Discretisation parameters.
  *  dim 2 or 3; order k >= 0; basis DG_BASIS_PK (paper's total-degree space,
@@ -186,19 +187,23 @@ dg_status dg_fgmres_solve(dg_context* ctx, const double* w, double shift, const 
  * distance-2 colouring of the elements.  Every level is smoothed by
  * smooth_iters[l] right-preconditioned GMRES steps (one cycle, block Jacobi of
  * the level operator, factors stored as `storage`); the last entry is the
- * coarsest-level solve.  One apply is Alg. vcic from a zero initial guess. */
+ * coarsest-level solve.  One apply is Alg. vcic (cycle DG_MG_V) or Alg.
+ * fullvcic (DG_MG_FULL: restrict the right-hand side level by level, solve
+ * on the coarsest, then on each finer level prolong the coarser result and
+ * correct it by one V-cycle on its defect) from a zero initial guess. */
 typedef struct {
   int n_levels;         /* 2 or 3, the fine level included */
   int orders[3];        /* strictly decreasing, >= 0, orders[0] = context order */
   int smooth_iters[3];  /* 0..60 each; the coarsest level needs >= 1 */
   int storage;          /* block-factor storage on every level: DG_FP64/FP32/BF16 */
-  int use_graph;        /* nonzero: capture one V-cycle into a hipGraph at setup;
+  int use_graph;        /* nonzero: capture one cycle into a hipGraph at setup;
                            every apply replays it on a library stream ordered
                            against the caller's stream by events */
   int fine_precision;   /* DG_FP64 or DG_FP32: the fine-level operator inside
                            the cycle (smoother products and the defect) and the
                            probing of the coarse operators as the exact FP64 Jv
                            or its FP32 variant; the outer solve stays FP64 */
+  int cycle;            /* DG_MG_V or DG_MG_FULL */
 } dg_mg_opts;
 
 /* Builds the hierarchy at state w (device, copied) and shift: runs the fine

@@ -16,6 +16,7 @@ DG_FLUX_LF, DG_FLUX_ROE = 0, 1
 DG_JVP_EXACT, DG_JVP_FD, DG_JVP_EXACT_FP32 = 0, 1, 2
 DG_FP64, DG_FP32, DG_BF16 = 0, 1, 2
 DG_PREC_NONE, DG_PREC_BJ, DG_PREC_MG, DG_PREC_MLP = 0, 1, 2, 3
+DG_MG_V, DG_MG_FULL = 0, 1
 
 EXPORTED = ["dg_create", "dg_destroy", "dg_ndof", "dg_nbasis", "dg_nvar", "dg_nq", "dg_volume_points",
             "dg_project", "dg_residual", "dg_residual_fp32", "dg_jvp", "dg_block_precond_setup", "dg_block_precond_apply",
@@ -44,7 +45,8 @@ class SolveOpts(ctypes.Structure):
 
 class MgOpts(ctypes.Structure):
     _fields_ = [("n_levels", ctypes.c_int), ("orders", ctypes.c_int * 3), ("smooth_iters", ctypes.c_int * 3),
-                ("storage", ctypes.c_int), ("use_graph", ctypes.c_int), ("fine_precision", ctypes.c_int)]
+                ("storage", ctypes.c_int), ("use_graph", ctypes.c_int), ("fine_precision", ctypes.c_int),
+                ("cycle", ctypes.c_int)]
 
 
 class SolveStats(ctypes.Structure):

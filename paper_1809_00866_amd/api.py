@@ -129,15 +129,19 @@ class DG:
         L.check(self.lib.dg_block_precond_apply(self.ctx, _ptr(r), _ptr(out), _stream()), "dg_block_precond_apply")
         return out
 
-    def mg_setup(self, w, shift, orders, smooth_iters, storage="fp64", use_graph=True, fine_precision="fp64"):
-        """p-multigrid hierarchy at (w, shift); orders[0] must be the context's order."""
+    def mg_setup(self, w, shift, orders, smooth_iters, storage="fp64", use_graph=True, fine_precision="fp64",
+                 cycle="v"):
+        """p-multigrid hierarchy at (w, shift); orders[0] must be the context's order;
+        cycle "v" (Alg. vcic) or "full" (Alg. fullvcic)."""
+        if cycle not in ("v", "full"):
+            raise ValueError("cycle must be 'v' or 'full'")
         self._vec(w, "w")
         orders, smooth_iters = list(orders), list(smooth_iters)
         if not (2 <= len(orders) <= 3) or len(smooth_iters) != len(orders):
             raise ValueError("need 2 or 3 levels and one smoothing count per level")
         o = L.MgOpts(len(orders), (ctypes.c_int * 3)(*(orders + [0] * (3 - len(orders)))),
                      (ctypes.c_int * 3)(*(smooth_iters + [0] * (3 - len(orders)))), _STORAGE[storage],
-                     int(bool(use_graph)), _STORAGE[fine_precision])
+                     int(bool(use_graph)), _STORAGE[fine_precision], L.DG_MG_FULL if cycle == "full" else L.DG_MG_V)
         self.mg_levels = [(self.ne * self.nv * _nb(k, self.dim)) for k in orders]
         L.check(self.lib.dg_mg_setup(self.ctx, _ptr(w), float(shift), ctypes.byref(o), _stream()), "dg_mg_setup")
 

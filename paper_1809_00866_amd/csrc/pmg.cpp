@@ -1,6 +1,7 @@
-// p-multigrid preconditioner (Sec. 2.4): Alg. vcic on levels k_0 > k_1 (> k_2)
-// with inherited coarse operators (eq. GalProj) and fixed-count GMRES smoothers
-// preconditioned by element-wise block Jacobi (EWBJ) on every level.
+// p-multigrid preconditioner (Sec. 2.4): Alg. vcic or Alg. fullvcic on levels
+// k_0 > k_1 (> k_2) with inherited coarse operators (eq. GalProj) and
+// fixed-count GMRES smoothers preconditioned by element-wise block Jacobi
+// (EWBJ) on every level.
 //
 // * Level 0 applies the matrix-free operator G_0 = shift*I + J(w) (exact Jv).
 // * The first coarse level's operator is probed from G_0: for every colour of
@@ -36,6 +37,7 @@ struct MgLevel {
   double* x = nullptr;         // iterate
   double* t = nullptr;         // defect / work
   double* z = nullptr;         // preconditioned vector
+  double* h = nullptr;         // full cycle: prolonged coarser solution
   double* V = nullptr;         // Krylov basis [(iters+1)][n]
   double* sc = nullptr;        // smoother scalars (kScSize)
   int bs = 1024;               // BSR apply workgroup size (autotuned; same arithmetic for every size)
@@ -44,6 +46,7 @@ struct MgLevel {
 struct MgState {
   int nlev = 0, nslot = 0, storage = DG_FP64;
   bool fine_f32 = false;  // FP32 fine-level operator inside the cycle
+  bool full = false;      // Alg. fullvcic instead of Alg. vcic
   double shift = 0.0;
   bool use_graph = false, ready = false;
   MgLevel lev[3];
@@ -71,6 +74,7 @@ void mg_destroy(MgState* M) {
     dfree(L.x);
     dfree(L.t);
     dfree(L.z);
+    dfree(L.h);
     dfree(L.V);
     dfree(L.sc);
   }
@@ -185,6 +189,29 @@ dg_status vcycle(dg_context* c, MgState* M, int l, hipStream_t s) {
   return smooth(c, M, l, false, s);  // post-smoothing
 }
 
+// lev[l].x <- MG_full(l, lev[l].g, 0)  (Alg. fullvcic); lev[l].g is consumed
+// (it ends as the defect that the V-cycle correction solved for)
+dg_status fullcycle(dg_context* c, MgState* M, int l, hipStream_t s) {
+  dg_status st;
+  MgLevel& L = M->lev[l];
+  if (l == M->nlev - 1) return smooth(c, M, l, true, s);  // coarsest-level solve
+  MgLevel& C = M->lev[l + 1];
+  HIPCHK(dgk::launch_restrict(L.g, L.nb, C.g, C.nb, c->nv, c->ne, s));
+  if ((st = fullcycle(c, M, l + 1, s)) != DG_OK) return st;
+  // initial iterate: the prolonged coarser solution, then its defect
+  HIPCHK(dgk::launch_fill(L.h, L.n, 0.0, s));
+  HIPCHK(dgk::launch_prolong_add(C.x, C.nb, L.h, L.nb, c->nv, c->ne, s));
+  if ((st = level_G(c, M, l, L.h, L.t, s)) != DG_OK) return st;
+  HIPCHK(dgk::launch_axpby(L.n, 1.0, L.g, -1.0, L.t, L.g, s));
+  if ((st = vcycle(c, M, l, s)) != DG_OK) return st;  // V-cycle correction
+  HIPCHK(dgk::launch_axpby(L.n, 1.0, L.x, 1.0, L.h, L.x, s));
+  return DG_OK;
+}
+
+dg_status cycle(dg_context* c, MgState* M, hipStream_t s) {
+  return M->full ? fullcycle(c, M, 0, s) : vcycle(c, M, 0, s);
+}
+
 // ---------------------------------------------------------------- colouring
 // Distance-2 colouring: the lattice colouring (i + 2j + 3k) mod q (2D:
 // (i + 2j) mod q) for the smallest q that passes the check, else greedy.
@@ -260,7 +287,7 @@ dg_status mg_apply(dg_context* c, const double* r, double* z, hipStream_t s) {
     HIPCHK(hipStreamWaitEvent(s, M->ev_b, 0));
   } else {
     dg_status st;
-    if ((st = vcycle(c, M, 0, s)) != DG_OK) return st;
+    if ((st = cycle(c, M, s)) != DG_OK) return st;
   }
   HIPCHK(dgk::launch_axpby(L0.n, 1.0, L0.x, 0.0, L0.x, z, s));
   return DG_OK;
@@ -288,6 +315,7 @@ dg_status dg_mg_setup(dg_context* c, const double* w, double shift, const dg_mg_
     return fail(DG_ERR_ARG, "storage must be DG_FP64, DG_FP32 or DG_BF16");
   if (o->fine_precision != DG_FP64 && o->fine_precision != DG_FP32)
     return fail(DG_ERR_ARG, "fine_precision must be DG_FP64 or DG_FP32");
+  if (o->cycle != DG_MG_V && o->cycle != DG_MG_FULL) return fail(DG_ERR_ARG, "cycle must be DG_MG_V or DG_MG_FULL");
   if (o->fine_precision == DG_FP32 && !(c->use_mfma && c->d_mtab_f))
     return fail(DG_ERR_ARG, "the FP32 fine operator needs a 3D P2-P4 configuration with MFMA kernels");
   hipStream_t s = (hipStream_t)stream;
@@ -313,6 +341,7 @@ dg_status dg_mg_setup(dg_context* c, const double* w, double shift, const dg_mg_
   M->shift = shift;
   M->use_graph = o->use_graph != 0;
   M->fine_f32 = o->fine_precision == DG_FP32;
+  M->full = o->cycle == DG_MG_FULL;
   for (int l = 0; l < M->nlev; ++l) {
     MgLevel& L = M->lev[l];
     L.order = o->orders[l];
@@ -324,6 +353,7 @@ dg_status dg_mg_setup(dg_context* c, const double* w, double shift, const dg_mg_
     if ((st = dalloc(&L.x, (size_t)L.n)) != DG_OK) return bail(st);
     if ((st = dalloc(&L.t, (size_t)L.n)) != DG_OK) return bail(st);
     if ((st = dalloc(&L.z, (size_t)L.n)) != DG_OK) return bail(st);
+    if (M->full && l < M->nlev - 1 && (st = dalloc(&L.h, (size_t)L.n)) != DG_OK) return bail(st);
     if ((st = dalloc(&L.V, (size_t)(L.iters + 1) * L.n)) != DG_OK) return bail(st);
     if ((st = dalloc(&L.sc, (size_t)dgk::kScSize)) != DG_OK) return bail(st);
     HIPCHK(dgk::launch_fill(L.sc, dgk::kScSize, 0.0, s));
@@ -417,11 +447,11 @@ dg_status dg_mg_setup(dg_context* c, const double* w, double shift, const dg_mg_
     c->prof = false;  // no event records inside the captured graph
     hipError_t e = hipStreamBeginCapture(M->gs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-      st = vcycle(c, M, 0, M->gs);
+      st = cycle(c, M, M->gs);
       e = hipStreamEndCapture(M->gs, &M->graph);
     }
     c->prof = prof;
-    if (e != hipSuccess) return bail(fail(DG_ERR_HIP, std::string("V-cycle capture: ") + hipGetErrorString(e)));
+    if (e != hipSuccess) return bail(fail(DG_ERR_HIP, std::string("cycle capture: ") + hipGetErrorString(e)));
     if (st != DG_OK) return bail(st);
     HIPCHK(hipGraphInstantiate(&M->exec, M->graph, nullptr, nullptr, 0));
   }

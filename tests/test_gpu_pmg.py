@@ -1,4 +1,4 @@
-"""GPU parity of the p-multigrid preconditioner (Sec. 2.4, Alg. vcic, eq. GalProj)
+"""GPU parity of the p-multigrid preconditioner (Sec. 2.4, Algs. vcic and fullvcic, eq. GalProj)
 against the FP64 oracle, through the C ABI.
 
 Tolerances: coarse operators (probed from exact Jv) 1e-12 relative; one
@@ -120,6 +120,36 @@ def test_fgmres_with_mg_reaches_tolerance_in_fewer_iterations(case):
     # BJ alone (the fine factors of the hierarchy are the same block setup)
     _, st_bj = g.fgmres(w, shift, b, restart=30, rtol=1e-10, max_iter=2000, precond="bj")
     assert st["iters"] < st_bj["iters"], (st["iters"], st_bj["iters"])
+
+
+def test_full_cycle_matches_the_oracle_and_its_graph_replays_the_eager_cycle(case):
+    """Alg. fullvcic: parity with the oracle's full cycle (same bound as the
+    V-cycle), graph replays equal to the eager full cycle bit for bit, and
+    FGMRES preconditioned by it reaches the tolerance."""
+    from paper_1809_00866_amd import DG
+    o, mg, U, w, shift = case["o"], case["mg"], case["U"], case["w"], case["shift"]
+    _say("full cycle parity")
+    R = np.random.default_rng(7).standard_normal(U.shape)
+    z_o = o.to_flat(mg.full(0, R.reshape(-1)).reshape(U.shape))
+    r = torch.tensor(o.to_flat(R), device="cuda")
+    gf = DG(case["mesh"], case["k"], nq1d=case["nq"], mu=1e-2)
+    gf.mg_setup(w, shift, case["orders"], case["iters"], storage="fp64", use_graph=True, cycle="full")
+    ge = DG(case["mesh"], case["k"], nq1d=case["nq"], mu=1e-2)
+    ge.mg_setup(w, shift, case["orders"], case["iters"], storage="fp64", use_graph=False, cycle="full")
+    z_e = ge.mg_apply(r)
+    z_g = z_e.cpu().numpy()
+    assert np.linalg.norm(z_g - z_o) <= 1e-9 * np.linalg.norm(z_o), np.linalg.norm(z_g - z_o) / np.linalg.norm(z_o)
+    for rep in range(3):
+        z = gf.mg_apply(r)
+        torch.cuda.synchronize()
+        _ = gf.residual(w)
+        torch.cuda.synchronize()
+        assert torch.equal(z, z_e), rep
+    b = torch.tensor(o.to_flat(np.random.default_rng(8).standard_normal(U.shape)), device="cuda")
+    x, st = gf.fgmres(w, shift, b, restart=30, rtol=1e-10, max_iter=500, precond="mg")
+    assert st["converged"] == 1 and st["rel_res_true"] <= 1e-10
+    gf.close()
+    ge.close()
 
 
 def test_state_errors_and_reduced_precision_smoothers():
