@@ -119,6 +119,15 @@ class PMultigrid:
         self.D = [o.block_diagonal(U, shift)] + [
             diagonal_blocks(self.A[l], o.ne, o.nvar * self.nbs[l]) for l in range(1, self.L + 1)]
 
+    def update_fine(self, U, shift, refresh_blocks=True):
+        """Preconditioner lagging (Sec. 4, time-step study): the fine level's
+        operator (and, with refresh_blocks, its block-Jacobi blocks) follows the
+        new state and shift; the coarse operators and their blocks stay those of
+        the state the hierarchy was built at."""
+        self.U, self.shift = U, float(shift)
+        if refresh_blocks:
+            self.D[0] = self.o.block_diagonal(U, shift)
+
     # level operators on flat vectors of X[e, c, b] with N_b(k_l) modes
     def _shape(self, l):
         return (self.o.ne, self.o.nvar, self.nbs[l])

@@ -185,6 +185,29 @@ def test_full_cycle_three_levels_with_exact_middle_smoothing():
     assert np.linalg.norm(z - prolong(zc, o.nb)) <= 1e-9 * np.linalg.norm(zc)
 
 
+def test_lagged_hierarchy_keeps_the_coarse_solve_and_follows_the_fine_operator():
+    """Preconditioner lagging: built at state U1, updated to (U2, shift2).
+    Without fine smoothing and with an exact coarse solve the cycle is still
+    P (R G(U1) P)^-1 R g (the coarse level is frozen); with a fine smoothing
+    count equal to the fine dimension the post-smoothing is an exact solve with
+    the new operator G(U2), so the cycle returns G(U2)^-1 g (dense LU)."""
+    mesh, o, U1 = _state((1, 1, 2), 2, 3, seed=4)
+    _, _, U2 = _state((1, 1, 2), 2, 3, seed=9)
+    s1, s2 = 4.0, 6.0
+    nc, nf = o.ne * o.nvar * 4, U1.size
+    g = np.random.default_rng(13).standard_normal(U1.shape)
+    mg = PMultigrid(o, U1, s1, orders=(2, 1), iters=(0, nc))
+    mg.update_fine(U2, s2)
+    A1 = inherited_matrix(o, U1, s1, 4)
+    zc = np.linalg.solve(A1, restrict(g, 4).reshape(-1)).reshape(o.ne, o.nvar, 4)
+    assert np.linalg.norm(mg.apply(g) - prolong(zc, o.nb)) <= 1e-9 * np.linalg.norm(zc)
+    mg = PMultigrid(o, U1, s1, orders=(2, 1), iters=(nf, nc))
+    mg.update_fine(U2, s2)
+    z = mg.apply(g).reshape(-1)
+    z_ex = np.linalg.solve(_dense(o, U2, s2), g.reshape(-1))
+    assert np.linalg.norm(z - z_ex) <= 1e-8 * np.linalg.norm(z_ex)
+
+
 @pytest.mark.slow
 def test_mg_preconditioned_fgmres_beats_block_jacobi():
     from oracle import fgmres
