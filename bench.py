@@ -138,6 +138,51 @@ def time_to_tolerance(storage="fp64", precond="bj", fine_precision="fp64"):
             "converged": bool(st["converged"]), "rel_res_true": st["rel_res_true"], "dt": dt}
 
 
+def mg_trajectory(n_steps=4, lag=1, cycle="v"):
+    """Backward-Euler steps of the P4 24^3 workload (CFL 100), each solved by
+    FGMRES(30) to 1e-8 with the P4/P2/P1 p-multigrid preconditioner (FP32 fine
+    smoothing and factors).  lag > 1: the hierarchy is built every lag steps and
+    in between only its fine level follows the current state and time step
+    (coarse operators frozen, fine block Jacobi refreshed)."""
+    import torch
+    import synth
+    from paper_1809_00866_amd import DG
+    cfg, mesh, fld = synth.preset("cfg3")
+    g = DG(mesh, cfg["order"], basis=cfg["space"], nq1d=cfg["nq1d"], flux="roe", mu=cfg["mu"])
+    w = g.project_field(fld)
+    h = float(np.min(mesh["h"]))
+    iters, t_setup, t_solve = [], 0.0, 0.0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(n_steps):
+        shift = (2 * cfg["order"] + 1) * g.max_wave_speed(w) / (cfg["cfl"] * h)
+        b = -g.residual(w)
+        ta = time.perf_counter()
+        if k % lag == 0:
+            g.mg_setup(w, shift, cfg["mg_orders"], cfg["mg_smooth"], storage="fp32", use_graph=True,
+                       fine_precision="fp32", cycle=cycle)
+        else:
+            g.mg_update_fine(w, shift, refresh_blocks=True)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        dw, st = g.fgmres(w, shift, b, restart=cfg["restart"], max_iter=600, rtol=cfg["rtol"], precond="mg")
+        torch.cuda.synchronize()
+        tc = time.perf_counter()
+        t_setup += tb - ta
+        t_solve += tc - tb
+        if not st["converged"]:
+            raise RuntimeError(f"step {k} did not converge: {st}")
+        iters.append(st["iters"])
+        w = w + dw
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    g.close()
+    return {"workload": f"{n_steps} backward-Euler steps, P4 24^3 hexes, CFL 100, FGMRES(30) to 1e-8, p-multigrid "
+                        f"{'full' if cycle == 'full' else 'V'} cycle P4/P2/P1 8/8/40, fp32 smoothing, "
+                        f"hierarchy rebuilt every {lag} step(s)",
+            "seconds": total, "setup_s": t_setup, "solve_s": t_solve, "iters_per_step": iters}
+
+
 def learned_preconditioner(train_steps=3000, max_iter=300):
     """The learned element-local preconditioner on the P3 32^3 workload:
     training pairs from backward-Euler snapshots 0, 2, 4 (CFL 100), 1e5 pairs
@@ -299,6 +344,9 @@ def main():
         res["time_to_tol_bf16_blocks"] = time_to_tolerance("bf16")
         res["time_to_tol_pmg"] = time_to_tolerance("fp64", precond="mg")
         res["time_to_tol_pmg_fp32_smoothing"] = time_to_tolerance("fp32", precond="mg", fine_precision="fp32")
+        res["trajectory_pmg"] = mg_trajectory(4, lag=1)
+        res["trajectory_pmg_lag3"] = mg_trajectory(4, lag=3)
+        res["trajectory_pmg_full_cycle"] = mg_trajectory(4, lag=1, cycle="full")
     if not args.no_learned:
         res["learned_precond"] = learned_preconditioner()
     if not args.no_cpu_baseline:

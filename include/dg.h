@@ -215,6 +215,19 @@ typedef struct {
  * hierarchy (apply then returns DG_ERR_STATE). */
 dg_status dg_mg_setup(dg_context* ctx, const double* w, double shift, const dg_mg_opts* opts, void* stream);
 
+/* Preconditioner lagging (the time-step study of Sec. 4: the coarse operators
+ * are frozen for several steps while the matrix-free fine level follows the
+ * current state).  Replaces the state (device, copied) and shift of the
+ * fine-level operator inside the cycle (smoother products and defect) and
+ * keeps the probed coarse operators and their factors from the last
+ * dg_mg_setup.  refresh_blocks != 0 also rebuilds the fine block-Jacobi
+ * factors at (w, shift) with the hierarchy's storage (as
+ * dg_block_precond_setup, which alone would invalidate the hierarchy);
+ * refresh_blocks = 0 keeps them and is refused (DG_ERR_STATE) once another
+ * block setup has replaced them.  Re-captures the graph.  Synchronises the
+ * stream. */
+dg_status dg_mg_update_fine(dg_context* ctx, const double* w, double shift, int refresh_blocks, void* stream);
+
 /* z = MG_V(0, r, 0): one V-cycle on the fine level (r, z: device DOF vectors,
  * no aliasing).  The cycle is nonlinear in r (GMRES smoothers), hence the
  * flexible outer solver. */

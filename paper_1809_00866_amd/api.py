@@ -145,6 +145,13 @@ class DG:
         self.mg_levels = [(self.ne * self.nv * _nb(k, self.dim)) for k in orders]
         L.check(self.lib.dg_mg_setup(self.ctx, _ptr(w), float(shift), ctypes.byref(o), _stream()), "dg_mg_setup")
 
+    def mg_update_fine(self, w, shift, refresh_blocks=True):
+        """Lag the hierarchy: the fine-level operator follows (w, shift), the coarse
+        operators stay those of the last mg_setup."""
+        self._vec(w, "w")
+        L.check(self.lib.dg_mg_update_fine(self.ctx, _ptr(w), float(shift), int(bool(refresh_blocks)), _stream()),
+                "dg_mg_update_fine")
+
     def mg_apply(self, r, out=None):
         self._vec(r, "r")
         out = self.empty() if out is None else self._vec(out, "out")

@@ -212,6 +212,27 @@ dg_status cycle(dg_context* c, MgState* M, hipStream_t s) {
   return M->full ? fullcycle(c, M, 0, s) : vcycle(c, M, 0, s);
 }
 
+// (Re)captures one cycle into M->graph / M->exec on the library stream.
+dg_status capture(dg_context* c, MgState* M) {
+  if (M->exec) (void)hipGraphExecDestroy(M->exec);
+  if (M->graph) (void)hipGraphDestroy(M->graph);
+  M->exec = nullptr;
+  M->graph = nullptr;
+  dg_status st = DG_OK;
+  const bool prof = c->prof;
+  c->prof = false;  // no event records inside the captured graph
+  hipError_t e = hipStreamBeginCapture(M->gs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    st = cycle(c, M, M->gs);
+    e = hipStreamEndCapture(M->gs, &M->graph);
+  }
+  c->prof = prof;
+  if (e != hipSuccess) return fail(DG_ERR_HIP, std::string("cycle capture: ") + hipGetErrorString(e));
+  if (st != DG_OK) return st;
+  HIPCHK(hipGraphInstantiate(&M->exec, M->graph, nullptr, nullptr, 0));
+  return DG_OK;
+}
+
 // ---------------------------------------------------------------- colouring
 // Distance-2 colouring: the lattice colouring (i + 2j + 3k) mod q (2D:
 // (i + 2j) mod q) for the smallest q that passes the check, else greedy.
@@ -443,18 +464,26 @@ dg_status dg_mg_setup(dg_context* c, const double* w, double shift, const dg_mg_
   HIPCHK(hipStreamSynchronize(s));
   if (M->use_graph) {
     HIPCHK(hipStreamCreateWithFlags(&M->gs, hipStreamNonBlocking));
-    const bool prof = c->prof;
-    c->prof = false;  // no event records inside the captured graph
-    hipError_t e = hipStreamBeginCapture(M->gs, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) {
-      st = cycle(c, M, M->gs);
-      e = hipStreamEndCapture(M->gs, &M->graph);
-    }
-    c->prof = prof;
-    if (e != hipSuccess) return bail(fail(DG_ERR_HIP, std::string("cycle capture: ") + hipGetErrorString(e)));
-    if (st != DG_OK) return bail(st);
-    HIPCHK(hipGraphInstantiate(&M->exec, M->graph, nullptr, nullptr, 0));
+    if ((st = capture(c, M)) != DG_OK) return bail(st);
   }
+  M->ready = true;
+  return DG_OK;
+}
+
+dg_status dg_mg_update_fine(dg_context* c, const double* w, double shift, int refresh_blocks, void* stream) {
+  if (!c || !w) return fail(DG_ERR_ARG, "null argument");
+  MgState* M = c->mg;
+  if (!M) return fail(DG_ERR_STATE, "dg_mg_setup has not succeeded");
+  if (!M->ready && !refresh_blocks)
+    return fail(DG_ERR_STATE, "the fine block factors were replaced since dg_mg_setup: pass refresh_blocks");
+  hipStream_t s = (hipStream_t)stream;
+  dg_status st;
+  M->ready = false;
+  if (refresh_blocks && (st = dg_block_precond_setup(c, w, shift, M->storage, stream)) != DG_OK) return st;
+  HIPCHK(dgk::launch_axpby(c->ndof, 1.0, w, 0.0, w, M->w, s));
+  M->shift = shift;
+  HIPCHK(hipStreamSynchronize(s));
+  if (M->use_graph && (st = capture(c, M)) != DG_OK) return st;  // the shift is a kernel argument
   M->ready = true;
   return DG_OK;
 }

@@ -152,6 +152,48 @@ def test_full_cycle_matches_the_oracle_and_its_graph_replays_the_eager_cycle(cas
     ge.close()
 
 
+def test_lagged_hierarchy_matches_the_oracle(case):
+    """Preconditioner lagging: hierarchy built at U, fine level moved to a second
+    state and shift (coarse operators kept); parity with the oracle's lagged
+    hierarchy, graph replays equal to the eager cycle, and the refusal to keep
+    fine factors that a later block setup replaced."""
+    import copy
+    from paper_1809_00866_amd import DG
+    from paper_1809_00866_amd._lib import DGError
+    o, mg, U, w, shift = case["o"], case["mg"], case["U"], case["w"], case["shift"]
+    _say("lagged hierarchy parity")
+    U2 = U * (1.0 + 0.02 * np.random.default_rng(17).standard_normal(U.shape))
+    s2 = 1.5 * shift
+    mg2 = copy.copy(mg)
+    mg2.D = list(mg.D)
+    mg2.update_fine(U2, s2)
+    R = np.random.default_rng(18).standard_normal(U.shape)
+    z_o = o.to_flat(mg2.apply(R))
+    r = torch.tensor(o.to_flat(R), device="cuda")
+    w2 = torch.tensor(o.to_flat(U2), device="cuda")
+    gl = DG(case["mesh"], case["k"], nq1d=case["nq"], mu=1e-2)
+    gl.mg_setup(w, shift, case["orders"], case["iters"], storage="fp64", use_graph=True)
+    gl.mg_update_fine(w2, s2)
+    z = gl.mg_apply(r)
+    z_g = z.cpu().numpy()
+    assert np.linalg.norm(z_g - z_o) <= 1e-9 * np.linalg.norm(z_o), np.linalg.norm(z_g - z_o) / np.linalg.norm(z_o)
+    ge = DG(case["mesh"], case["k"], nq1d=case["nq"], mu=1e-2)
+    ge.mg_setup(w, shift, case["orders"], case["iters"], storage="fp64", use_graph=False)
+    ge.mg_update_fine(w2, s2)
+    assert torch.equal(ge.mg_apply(r), z)
+    for rep in range(2):
+        torch.cuda.synchronize()
+        assert torch.equal(gl.mg_apply(r), z), rep
+    gl.block_setup(w2, s2)                      # replaces the fine factors: the hierarchy is stale
+    with pytest.raises(DGError) as ei:
+        gl.mg_update_fine(w2, s2, refresh_blocks=False)
+    assert ei.value.status == -4
+    gl.mg_update_fine(w2, s2, refresh_blocks=True)
+    assert torch.equal(gl.mg_apply(r), z)
+    gl.close()
+    ge.close()
+
+
 def test_state_errors_and_reduced_precision_smoothers():
     from paper_1809_00866_amd import DG
     from paper_1809_00866_amd._lib import DGError
