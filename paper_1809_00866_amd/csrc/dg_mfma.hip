@@ -306,9 +306,8 @@ DEV void face_mfma_body(const double* __restrict__ U, const double* __restrict__
   constexpr int NFQ = ipow(NQ1, 2);
   constexpr int KSB = (NB + 3) / 4, RBF = (NFQ + 15) / 16;
   constexpr int NS = JVP ? 2 : 1;
-  constexpr int NCB = NS * NV;               // (value/tangent, variable) column blocks
-  constexpr int NCBW = (NCB + 3) / 4;
   constexpr int NCH = 6;                     // uL, uR, G_1..3 (averaged), {r}
+  static_assert(NV == 5, "balanced split: 4 waves own variables 0..3, variable 4 is shared");
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -320,18 +319,46 @@ DEV void face_mfma_body(const double* __restrict__ U, const double* __restrict__
   const int64_t er = ev ? m.nbr[(2 * P + 1) * ne + e] : 0;
   const double kap = ph.mu * ph.gamma / (ph.prandtl * (ph.gamma - 1.0));
 
-  // B fragments: k-steps 0..KSB-1 from the owner, KSB..2KSB-1 from the +P neighbour
-  R Bf[NCBW][2 * KSB];
-#pragma unroll
-  for (int i = 0; i < NCBW; ++i) {
-    const int cb = wave + 4 * i;
-    const int s = cb / NV, c = cb % NV;
+  // B fragments of (value/tangent s, variable c): k-steps 0..KSB-1 from the
+  // owner, KSB..2KSB-1 from the +P neighbour
+  auto load_b = [&](int s, int c, R* bf) {
     const double* __restrict__ X = (s == 0) ? U : V;
 #pragma unroll
     for (int ks2 = 0; ks2 < 2 * KSB; ++ks2) {
       const int b = g + 4 * (ks2 < KSB ? ks2 : ks2 - KSB);
       const int64_t es = ks2 < KSB ? e : er;
-      Bf[i][ks2] = (cb < NCB && ev && b < NB) ? (R)X[(size_t)(c * NB + b) * ne + es] : R(0);
+      bf[ks2] = (ev && b < NB) ? (R)X[(size_t)(c * NB + b) * ne + es] : R(0);
+    }
+  };
+  // trace channel ch of one column block into the stage
+  auto trace = [&](int rbf, int ch, int c, const R* bf) {
+    const int k0 = (ch == 1) ? KSB : 0;
+    const int k1 = (ch == 0) ? KSB : 2 * KSB;
+    F d = {0, 0, 0, 0};
+#pragma unroll
+    for (int ks2 = k0; ks2 < k1; ++ks2)
+      d = MP<R>::mma(mt.tA[((((size_t)P * RBF + rbf) * NCH + ch) * 2 * KSB + ks2) * 64 + lane], bf[ks2], d);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) stage[ch * NV + c][MP<R>::drow(g, r)][col] = d[r];
+  };
+  // Work split.  Balanced (FP64, one face-point block): wave w traces all
+  // channels of variable w; the channels of variable 4 are shared out as
+  // {uL, G_1}, {uR, G_2}, {G_3}, {r}, so each wave issues about a quarter of
+  // the MFMAs of a phase.  Otherwise (FP32, several point blocks) column block
+  // cb = w + 4i goes to wave w whole: fewer live fragments at the cost of an
+  // uneven split (measured faster there).
+  constexpr bool kBalanced = std::is_same<R, double>::value && RBF == 1;
+  constexpr int NCB = NS * NV;               // (value/tangent, variable) column blocks
+  constexpr int NCBW = kBalanced ? NS : (NCB + 3) / 4;
+  R Bf[NCBW][2 * KSB];
+#pragma unroll
+  for (int i = 0; i < NCBW; ++i) {
+    const int cb = kBalanced ? i * NV + wave : wave + 4 * i;
+    if (cb < NCB) {
+      load_b(cb / NV, cb % NV, Bf[i]);
+    } else {
+#pragma unroll
+      for (int ks2 = 0; ks2 < 2 * KSB; ++ks2) Bf[i][ks2] = R(0);
     }
   }
 
@@ -340,22 +367,23 @@ DEV void face_mfma_body(const double* __restrict__ U, const double* __restrict__
     R st[NS][NCH * NV];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
+      if constexpr (kBalanced) {
+        R Bs[2 * KSB];
+        load_b(s, 4, Bs);
 #pragma unroll
-      for (int i = 0; i < NCBW; ++i) {
-        const int cb = wave + 4 * i;
-        if (cb < NCB && cb / NV == s) {
-          const int c = cb % NV;
+        for (int ch = 0; ch < NCH; ++ch) {
+          const int owner = ch < 4 ? (ch & 1) : ch - 2;
+          if (owner == wave) trace(rbf, ch, 4, Bs);
+        }
 #pragma unroll
-          for (int ch = 0; ch < NCH; ++ch) {
-            const int k0 = (ch == 1) ? KSB : 0;
-            const int k1 = (ch == 0) ? KSB : 2 * KSB;
-            F d = {0, 0, 0, 0};
+        for (int ch = 0; ch < NCH; ++ch) trace(rbf, ch, wave, Bf[s]);
+      } else {
 #pragma unroll
-            for (int ks2 = k0; ks2 < k1; ++ks2)
-              d = MP<R>::mma(mt.tA[((((size_t)P * RBF + rbf) * NCH + ch) * 2 * KSB + ks2) * 64 + lane], Bf[i][ks2],
-                             d);
+        for (int i = 0; i < NCBW; ++i) {
+          const int cb = wave + 4 * i;
+          if (cb < NCB && cb / NV == s) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) stage[ch * NV + c][MP<R>::drow(g, r)][col] = d[r];
+            for (int ch = 0; ch < NCH; ++ch) trace(rbf, ch, cb % NV, Bf[i]);
           }
         }
       }
