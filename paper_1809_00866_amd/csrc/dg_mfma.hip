@@ -117,8 +117,10 @@ __global__ __launch_bounds__(64) void k_grad_mfma(const double* __restrict__ U, 
 }
 
 // ------------------------------------------------------------------ volume
+// FP64 P4 runs at one wave per SIMD (no register spills; measured faster than
+// occupancy 2 with spills)
 template <class R, int NB, int NQ1, int KL, bool JVP>
-__global__ __launch_bounds__(256, 2) void k_volume_mfma(const double* __restrict__ U, const double* __restrict__ V,
+__global__ __launch_bounds__(256, (NB > 20 && sizeof(R) == 8) ? 1 : 2) void k_volume_mfma(const double* __restrict__ U, const double* __restrict__ V,
                                                      const R* __restrict__ Gm, const R* __restrict__ H,
                                                      double* __restrict__ out, double shift, MTablesT<R> mt,
                                                      Mesh m, Phys ph) {
@@ -297,9 +299,21 @@ __global__ __launch_bounds__(256, 2) void k_volume_mfma(const double* __restrict
 }
 
 // ------------------------------------------------------------------ faces
+// P4 (35 modes, two face-point blocks): the trace table of the current point
+// block is staged in LDS next to the stage buffer (reading the A operands from
+// L2 left the MFMA chains waiting); in FP64 the kernel also runs at one wave
+// per SIMD, which makes room for the table and removes the register spills of
+// the dual-number flux.  The smaller configurations read the table from L2 at
+// occupancy 2 or more (staging it measured slower there).
+template <class R, int NB>
+struct FaceTab {
+  static constexpr bool lds = NB > 20;
+  static constexpr int occupancy = (lds && sizeof(R) == 8) ? 1 : 2;
+};
+
 template <class R, int NB, int NQ1, bool JVP, int P>
 DEV void face_mfma_body(const double* __restrict__ U, const double* __restrict__ V, R* __restrict__ H,
-                        const MTablesT<R>& mt, const Mesh& m, const Phys& ph, R (*stage)[16][16]) {
+                        const MTablesT<R>& mt, const Mesh& m, const Phys& ph, R (*stage)[16][16], R* ttab) {
   using T = typename Scalar<JVP, R>::type;
   using F = typename MP<R>::frag;
   constexpr int DIM = 3, NV = 5;
@@ -330,14 +344,19 @@ DEV void face_mfma_body(const double* __restrict__ U, const double* __restrict__
       bf[ks2] = (ev && b < NB) ? (R)X[(size_t)(c * NB + b) * ne + es] : R(0);
     }
   };
-  // trace channel ch of one column block into the stage
+  // trace channel ch of one column block into the stage; the trace table of
+  // the current point block is read from LDS when the kernel stages it there
+  constexpr bool kTabLds = FaceTab<R, NB>::lds;
   auto trace = [&](int rbf, int ch, int c, const R* bf) {
     const int k0 = (ch == 1) ? KSB : 0;
     const int k1 = (ch == 0) ? KSB : 2 * KSB;
     F d = {0, 0, 0, 0};
 #pragma unroll
-    for (int ks2 = k0; ks2 < k1; ++ks2)
-      d = MP<R>::mma(mt.tA[((((size_t)P * RBF + rbf) * NCH + ch) * 2 * KSB + ks2) * 64 + lane], bf[ks2], d);
+    for (int ks2 = k0; ks2 < k1; ++ks2) {
+      const R a = kTabLds ? ttab[(ch * 2 * KSB + ks2) * 64 + lane]
+                          : mt.tA[((((size_t)P * RBF + rbf) * NCH + ch) * 2 * KSB + ks2) * 64 + lane];
+      d = MP<R>::mma(a, bf[ks2], d);
+    }
 #pragma unroll
     for (int r = 0; r < 4; ++r) stage[ch * NV + c][MP<R>::drow(g, r)][col] = d[r];
   };
@@ -364,6 +383,12 @@ DEV void face_mfma_body(const double* __restrict__ U, const double* __restrict__
 
   const int fql = tid >> 4, ft = tid & 15;
   for (int rbf = 0; rbf < RBF; ++rbf) {
+    if constexpr (kTabLds) {
+      // the previous point block's last table reads precede its final barrier
+      const R* __restrict__ src = mt.tA + ((size_t)P * RBF + rbf) * NCH * 2 * KSB * 64;
+      for (int idx = tid; idx < NCH * 2 * KSB * 64; idx += 256) ttab[idx] = src[idx];
+      __syncthreads();
+    }
     R st[NS][NCH * NV];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
@@ -428,13 +453,14 @@ DEV void face_mfma_body(const double* __restrict__ U, const double* __restrict__
 }
 
 template <class R, int NB, int NQ1, bool JVP>
-__global__ __launch_bounds__(256, 2) void k_face_mfma(const double* __restrict__ U, const double* __restrict__ V,
-                                                   R* __restrict__ H, MTablesT<R> mt, Mesh m, Phys ph) {
+__global__ __launch_bounds__(256, (FaceTab<R, NB>::occupancy)) void k_face_mfma(
+    const double* __restrict__ U, const double* __restrict__ V, R* __restrict__ H, MTablesT<R> mt, Mesh m, Phys ph) {
   __shared__ R stage[6 * 5][16][16];
+  __shared__ R ttab[FaceTab<R, NB>::lds ? 6 * 2 * ((NB + 3) / 4) * 64 : 1];
   switch (blockIdx.y) {
-    case 0: face_mfma_body<R, NB, NQ1, JVP, 0>(U, V, H, mt, m, ph, stage); break;
-    case 1: face_mfma_body<R, NB, NQ1, JVP, 1>(U, V, H, mt, m, ph, stage); break;
-    default: face_mfma_body<R, NB, NQ1, JVP, 2>(U, V, H, mt, m, ph, stage); break;
+    case 0: face_mfma_body<R, NB, NQ1, JVP, 0>(U, V, H, mt, m, ph, stage, ttab); break;
+    case 1: face_mfma_body<R, NB, NQ1, JVP, 1>(U, V, H, mt, m, ph, stage, ttab); break;
+    default: face_mfma_body<R, NB, NQ1, JVP, 2>(U, V, H, mt, m, ph, stage, ttab); break;
   }
 }
 
