@@ -88,20 +88,23 @@ __global__ __launch_bounds__(64) void k_grad_mfma(const double* __restrict__ U, 
   const bool ev = e < ne;
   const int p = blockIdx.y, s = blockIdx.z;
   const double* __restrict__ X = (s == 0) ? U : V;
-  int64_t es[3] = {e, e, e};  // sources: the element, its +p and its -p neighbour
-  if (ev) {
-    es[1] = m.nbr[(2 * p + 1) * ne + e];
-    es[2] = m.nbr[(2 * p) * ne + e];
-  }
+  // Loads use clamped, always valid addresses and a select instead of a branch
+  // (a branch per load keeps the scheduler from batching them).
+  const int64_t ec = ev ? e : ne - 1;
+  const int64_t es[3] = {ec, m.nbr[(2 * p + 1) * ne + ec], m.nbr[(2 * p) * ne + ec]};  // element, +p, -p
 #pragma unroll 1
   for (int c = 0; c < NV; ++c) {
     R bf[3 * KSB];
 #pragma unroll
     for (int ks3 = 0; ks3 < 3 * KSB; ++ks3) {
       const int src = ks3 / KSB, bp = g + 4 * (ks3 % KSB);
-      bf[ks3] = (ev && bp < NB) ? (R)X[(size_t)(c * NB + bp) * ne + es[src]] : R(0);
+      const R x = (R)X[(size_t)(c * NB + (bp < NB ? bp : NB - 1)) * ne + es[src]];
+      bf[ks3] = (ev && bp < NB) ? x : R(0);
     }
-#pragma unroll
+    // FP64 P4: one mode block at a time (all three unrolled hold their A
+    // operands in flight and leave one wave per SIMD)
+    constexpr int kMbUnroll = (sizeof(R) == 8 && MB > 2) ? 1 : MB;
+#pragma unroll kMbUnroll
     for (int mb = 0; mb < MB; ++mb) {
       F d = {0, 0, 0, 0};
 #pragma unroll
@@ -148,6 +151,7 @@ __global__ __launch_bounds__(256, (NB > 20 && sizeof(R) == 8) ? 1 : 2) void k_vo
   const int64_t e0 = xcd_tile(blockIdx.x, gridDim.x) * 16;
   const int64_t e = e0 + col;
   const bool ev = e < ne;
+  const int64_t ec = ev ? e : ne - 1;  // clamped element: loads stay branch-free
   const double kap = ph.mu * ph.gamma / (ph.prandtl * (ph.gamma - 1.0));
 
   // ---- 1. modal fields in B-fragment order: Bf[i][ks] = X[b = bmode(g, ks)][e],
@@ -158,14 +162,22 @@ __global__ __launch_bounds__(256, (NB > 20 && sizeof(R) == 8) ? 1 : 2) void k_vo
     const int s = i / (NFC / 4);
     const int fc = wave + 4 * (i % (NFC / 4));
     const int f = fc / NV, c = fc % NV;
-    const double* __restrict__ X = (s == 0) ? U : V;
+    const double* __restrict__ X = ((s == 0) ? U : V) + (size_t)c * NB * ne;
     const R* __restrict__ Gf = Gm + (size_t)((s * DIM + (f > 0 ? f - 1 : 0)) * NV + c) * NB * ne;
+    if (f == 0) {
 #pragma unroll
-    for (int ks = 0; ks < KSV; ++ks) {
-      const int b = MP<R>::bmode(g, ks);
-      R x = R(0);
-      if (ev && b < NB) x = (f == 0) ? (R)X[(size_t)(c * NB + b) * ne + e] : Gf[(size_t)b * ne + e];
-      Bf[i][ks] = x;
+      for (int ks = 0; ks < KSV; ++ks) {
+        const int b = MP<R>::bmode(g, ks);
+        const R x = (R)X[(size_t)(b < NB ? b : NB - 1) * ne + ec];
+        Bf[i][ks] = (ev && b < NB) ? x : R(0);
+      }
+    } else {
+#pragma unroll
+      for (int ks = 0; ks < KSV; ++ks) {
+        const int b = MP<R>::bmode(g, ks);
+        const R x = Gf[(size_t)(b < NB ? b : NB - 1) * ne + ec];
+        Bf[i][ks] = (ev && b < NB) ? x : R(0);
+      }
     }
   }
 
@@ -257,7 +269,7 @@ __global__ __launch_bounds__(256, (NB > 20 && sizeof(R) == 8) ? 1 : 2) void k_vo
   for (int p = 0; p < DIM; ++p) {
     for (int idx = tid; idx < 2 * MB * KSF * 64; idx += 256) ftab[idx] = mt.fA[(size_t)p * 2 * MB * KSF * 64 + idx];
     __syncthreads();
-    const int64_t em = ev ? m.nbr[(2 * p) * ne + e] : 0;
+    const int64_t em = m.nbr[(2 * p) * ne + ec];
 #pragma unroll
     for (int i = 0; i < NPBW; ++i) {
       const int pb = wave + 4 * i;
@@ -265,11 +277,12 @@ __global__ __launch_bounds__(256, (NB > 20 && sizeof(R) == 8) ? 1 : 2) void k_vo
         const int c = pb / MB, mb = pb % MB;
 #pragma unroll
         for (int side = 0; side < 2; ++side) {
-          const int64_t es = side ? e : em;
+          const int64_t es = side ? ec : em;
 #pragma unroll
           for (int ks = 0; ks < KSF; ++ks) {
             const int fq = g + 4 * ks;
-            const R hb = (ev && fq < NFQ) ? H[((size_t)(p * NV + c) * NFQ + fq) * ne + es] : R(0);
+            const R h = H[((size_t)(p * NV + c) * NFQ + (fq < NFQ ? fq : NFQ - 1)) * ne + es];
+            const R hb = (ev && fq < NFQ) ? h : R(0);
             acc[i] = MP<R>::mma(ftab[((side * MB + mb) * KSF + ks) * 64 + lane], hb, acc[i]);
           }
         }
@@ -330,7 +343,8 @@ DEV void face_mfma_body(const double* __restrict__ U, const double* __restrict__
   const int64_t e0 = xcd_tile(blockIdx.x, gridDim.x) * 16;
   const int64_t e = e0 + col;
   const bool ev = e < ne;
-  const int64_t er = ev ? m.nbr[(2 * P + 1) * ne + e] : 0;
+  const int64_t ec = ev ? e : ne - 1;  // clamped element: loads stay branch-free
+  const int64_t er = m.nbr[(2 * P + 1) * ne + ec];
   const double kap = ph.mu * ph.gamma / (ph.prandtl * (ph.gamma - 1.0));
 
   // B fragments of (value/tangent s, variable c): k-steps 0..KSB-1 from the
@@ -340,8 +354,9 @@ DEV void face_mfma_body(const double* __restrict__ U, const double* __restrict__
 #pragma unroll
     for (int ks2 = 0; ks2 < 2 * KSB; ++ks2) {
       const int b = g + 4 * (ks2 < KSB ? ks2 : ks2 - KSB);
-      const int64_t es = ks2 < KSB ? e : er;
-      bf[ks2] = (ev && b < NB) ? (R)X[(size_t)(c * NB + b) * ne + es] : R(0);
+      const int64_t es = ks2 < KSB ? ec : er;
+      const R x = (R)X[(size_t)(c * NB + (b < NB ? b : NB - 1)) * ne + es];
+      bf[ks2] = (ev && b < NB) ? x : R(0);
     }
   };
   // trace channel ch of one column block into the stage; the trace table of
