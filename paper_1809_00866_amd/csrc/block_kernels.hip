@@ -42,91 +42,6 @@ __global__ void k_extract(const double* __restrict__ Jv, const int* __restrict__
   }
 }
 
-// In-place Gauss-Jordan inversion with row pivoting of one m x m column-major
-// block per workgroup.  S is the arithmetic/storage type of the working copy
-// A (LDS when it fits, else the block's own global storage).
-template <class S>
-__device__ void gauss_jordan(S* A, int m, int lda, S* colk, S* rowk, int* ipiv, double* rv, int* ri, int* bad) {
-  const int tid = threadIdx.x;
-  for (int k = 0; k < m; ++k) {
-    // pivot: max |A[i][k]|, i >= k; ties keep the smallest row index
-    double best = -1.0;
-    int bi = k;
-    for (int i = k + tid; i < m; i += 256) {
-      const double a = fabs((double)A[(size_t)k * lda + i]);
-      if (a > best || (a != a)) {
-        best = (a != a) ? 1e308 : a;
-        bi = i;
-      }
-    }
-    rv[tid] = best;
-    ri[tid] = bi;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-      if (tid < s) {
-        const double o = rv[tid + s];
-        const int oi = ri[tid + s];
-        if (o > rv[tid] || (o == rv[tid] && oi < ri[tid])) {
-          rv[tid] = o;
-          ri[tid] = oi;
-        }
-      }
-      __syncthreads();
-    }
-    const int piv = ri[0];
-    if (tid == 0) ipiv[k] = piv;
-    // swap rows k and piv
-    if (piv != k)
-      for (int j = tid; j < m; j += 256) {
-        const S t = A[(size_t)j * lda + k];
-        A[(size_t)j * lda + k] = A[(size_t)j * lda + piv];
-        A[(size_t)j * lda + piv] = t;
-      }
-    __syncthreads();
-    const S pv = A[(size_t)k * lda + k];
-    if (tid == 0 && !(pv != (S)0 && (double)pv - (double)pv == 0.0)) *bad = 1;
-    const S pinv = (pv != (S)0) ? (S)1 / pv : (S)0;
-    // scaled pivot row (entry k becomes pinv) and the old column k
-    for (int j = tid; j < m; j += 256) rowk[j] = (j == k) ? pinv : A[(size_t)j * lda + k] * pinv;
-    for (int i = tid; i < m; i += 256) colk[i] = A[(size_t)k * lda + i];
-    __syncthreads();
-    for (size_t idx = tid; idx < (size_t)m * m; idx += 256) {
-      const int i = (int)(idx % m), j = (int)(idx / m);
-      S* a = &A[(size_t)j * lda + i];
-      if (i == k) {
-        *a = rowk[j];
-      } else {
-        const S base = (j == k) ? (S)0 : *a;
-        *a = base - colk[i] * rowk[j];
-      }
-    }
-    __syncthreads();
-  }
-  // undo the row interchanges as column interchanges, last first
-  for (int k = m - 1; k >= 0; --k) {
-    const int p = ipiv[k];
-    if (p != k)
-      for (int i = tid; i < m; i += 256) {
-        const S t = A[(size_t)k * lda + i];
-        A[(size_t)k * lda + i] = A[(size_t)p * lda + i];
-        A[(size_t)p * lda + i] = t;
-      }
-    __syncthreads();
-  }
-}
-
-// FP64 working copy in global memory (in place, column stride ld).
-__global__ __launch_bounds__(256) void k_invert_global64(double* __restrict__ D, int m, int ld,
-                                                         int* __restrict__ info) {
-  __shared__ double colk[256], rowk[256], rv[256];
-  __shared__ int ipiv[256], ri[256], bad;
-  if (threadIdx.x == 0) bad = 0;
-  __syncthreads();
-  double* A = D + (size_t)blockIdx.x * m * ld;
-  gauss_jordan<double>(A, m, ld, colk, rowk, ipiv, rv, ri, &bad);
-  if (threadIdx.x == 0 && bad) info[0] = 1;
-}
-
 // Storage conversions: FP64/FP32 pass through; BF16 = round-to-nearest-even
 // of the FP32 value (upper 16 bits), kept as raw bits.
 struct bf16_t {
@@ -147,28 +62,184 @@ __device__ __forceinline__ double load_as(const double& v) { return v; }
 __device__ __forceinline__ float load_as(const float& v) { return v; }
 __device__ __forceinline__ float load_as(const bf16_t& v) { return __uint_as_float(((unsigned int)v.bits) << 16); }
 
-// LDS working copy of type S (compact, stride m); input blocks of column
-// stride ldd, result written to `out` (storage type O, column stride ldo,
-// padding rows zero).
-template <class S, class O = S>
-__global__ __launch_bounds__(256) void k_invert_lds(const double* __restrict__ D, int ldd, O* __restrict__ out,
-                                                    int ldo, int m, int* __restrict__ info) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  S* A = reinterpret_cast<S*>(smem);
-  __shared__ S colk[256], rowk[256];
-  __shared__ double rv[256];
-  __shared__ int ipiv[256], ri[256], bad;
-  if (threadIdx.x == 0) bad = 0;
-  const double* Dg = D + (size_t)blockIdx.x * m * ldd;
-  for (size_t i = threadIdx.x; i < (size_t)m * m; i += 256) A[i] = (S)Dg[(i / m) * ldd + i % m];
-  __syncthreads();
-  gauss_jordan<S>(A, m, m, colk, rowk, ipiv, rv, ri, &bad);
-  O* Ob = out + (size_t)blockIdx.x * m * ldo;
-  for (size_t i = threadIdx.x; i < (size_t)m * ldo; i += 256) {
-    const int r = (int)(i % ldo), j = (int)(i / ldo);
-    store_as(Ob[i], r < m ? A[(size_t)j * m + r] : S(0));
+// Gauss-Jordan inversion with partial (row) pivoting, one m x m block per
+// workgroup (m <= 256), thread i owning row i.  Columns j < nl of row i are
+// at A[j*lda + i] in LDS, columns nl <= j < nl + NREG in the thread's
+// registers rr.  Per
+// pivot step: a wave-level max reduction of |A[i][k]| over i >= k (ties: the
+// smallest row), the scaled pivot row and the old row k through LDS (double
+// buffered, so two barriers per step), and a rank-1 update of each thread's
+// own row.  The row interchanges are undone at the end as column
+// interchanges within each row.
+DEVI double fma_s(double a, double b, double c) { return fma(a, b, c); }
+DEVI float fma_s(float a, float b, float c) { return fmaf(a, b, c); }
+
+template <class S, int NREG>
+DEVI S gj_get(const S* Ai, int lda, int nl, const S (&rr)[NREG > 0 ? NREG : 1], int j) {
+  if (j < nl) return Ai[(size_t)j * lda];
+  S v = S(0);
+#pragma unroll
+  for (int jj = 0; jj < NREG; ++jj) v = (jj == j - nl) ? rr[jj] : v;
+  return v;
+}
+template <class S, int NREG>
+DEVI void gj_set(S* Ai, int lda, int nl, S (&rr)[NREG > 0 ? NREG : 1], int j, S v) {
+  if (j < nl) {
+    Ai[(size_t)j * lda] = v;
+    return;
   }
-  if (threadIdx.x == 0 && bad) info[0] = 1;
+#pragma unroll
+  for (int jj = 0; jj < NREG; ++jj) rr[jj] = (jj == j - nl) ? v : rr[jj];
+}
+
+template <class S, int NREG>
+DEVI void gauss_jordan_rows(S* A, int m, int lda, int nl, S (&rr)[NREG > 0 ? NREG : 1], S (*rk2)[256],
+                            S (*ro2)[256], double (*wv)[4], int (*wi)[4], S (*wp)[4], int* ipiv, int* bad) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const bool own = tid < m;
+  S* Ai = A + tid;
+  for (int k = 0; k < m; ++k) {
+    const int par = k & 1;
+    // pivot: max |A[i][k]| over i >= k (ties: the smallest i), with its value
+    double best = -1.0;
+    int bi = 0x7fffffff;
+    S pv = S(0);
+    if (own && tid >= k) {
+      pv = gj_get<S, NREG>(Ai, lda, nl, rr, k);
+      const double a = fabs((double)pv);
+      best = (a != a) ? 1e308 : a;
+      bi = tid;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ob = __shfl_xor(best, off);
+      const int oi = __shfl_xor(bi, off);
+      const S op = __shfl_xor(pv, off);
+      if (ob > best || (ob == best && oi < bi)) {
+        best = ob;
+        bi = oi;
+        pv = op;
+      }
+    }
+    if (lane == 0) {
+      wv[par][wave] = best;
+      wi[par][wave] = bi;
+      wp[par][wave] = pv;
+    }
+    __syncthreads();
+    best = wv[par][0];
+    bi = wi[par][0];
+    pv = wp[par][0];
+#pragma unroll
+    for (int w = 1; w < 4; ++w) {
+      const double ob = wv[par][w];
+      const int oi = wi[par][w];
+      if (ob > best || (ob == best && oi < bi)) {
+        best = ob;
+        bi = oi;
+        pv = wp[par][w];
+      }
+    }
+    const int piv = bi;
+    if (tid == 0) {
+      ipiv[k] = piv;
+      if (!(pv != S(0) && (double)pv - (double)pv == 0.0)) *bad = 1;
+    }
+    const S pinv = (pv != S(0)) ? S(1) / pv : S(0);
+    S* rk = rk2[par];
+    S* ro = ro2[par];
+    // Row interchange and scaled pivot row, one column per thread: rk = row
+    // piv * pinv (entry k: pinv); row piv <- row k.  Register columns go
+    // through rk / ro from the threads that own rows piv and k.
+    if (tid < nl) {
+      const S apv = A[(size_t)tid * lda + piv];
+      const S ak = A[(size_t)tid * lda + k];
+      rk[tid] = (tid == k) ? pinv : apv * pinv;
+      A[(size_t)tid * lda + piv] = ak;
+    }
+    if (NREG > 0 && tid == piv) {
+#pragma unroll
+      for (int jj = 0; jj < NREG; ++jj) rk[nl + jj] = (nl + jj == k) ? pinv : rr[jj] * pinv;
+    }
+    if (NREG > 0 && tid == k) {
+#pragma unroll
+      for (int jj = 0; jj < NREG; ++jj) ro[nl + jj] = rr[jj];
+    }
+    __syncthreads();
+    if (own) {
+      if (NREG > 0 && tid == piv && piv != k) {
+#pragma unroll
+        for (int jj = 0; jj < NREG; ++jj) rr[jj] = ro[nl + jj];
+      }
+      // row k becomes the scaled pivot row (zero row, multiplier -1); every
+      // other row i: A[i][j] -= A[i][k] rk[j], then A[i][k] = -A[i][k] pinv.
+      // A multiplier rather than a select keeps the loads unconditional.
+      const bool rowk = (tid == k);
+      const S c = rowk ? S(-1) : gj_get<S, NREG>(Ai, lda, nl, rr, k);
+      const S keep = rowk ? S(0) : S(1);
+      int j = 0;
+      for (; j + 8 <= nl; j += 8) {  // 8 loads issued before the 8 stores
+        S a[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] = Ai[(size_t)(j + u) * lda];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) Ai[(size_t)(j + u) * lda] = fma_s(-c, rk[j + u], a[u] * keep);
+      }
+      for (; j < nl; ++j) Ai[(size_t)j * lda] = fma_s(-c, rk[j], Ai[(size_t)j * lda] * keep);
+#pragma unroll
+      for (int jj = 0; jj < NREG; ++jj) rr[jj] = fma_s(-c, rk[nl + jj], rr[jj] * keep);
+      gj_set<S, NREG>(Ai, lda, nl, rr, k, -c * rk[k]);
+    }
+  }
+  __syncthreads();  // ipiv complete
+  if (own)
+    for (int k = m - 1; k >= 0; --k) {
+      const int p = ipiv[k];
+      if (p != k) {
+        const S a = gj_get<S, NREG>(Ai, lda, nl, rr, k);
+        const S b = gj_get<S, NREG>(Ai, lda, nl, rr, p);
+        gj_set<S, NREG>(Ai, lda, nl, rr, k, b);
+        gj_set<S, NREG>(Ai, lda, nl, rr, p, a);
+      }
+    }
+}
+
+// One block per workgroup.  Input blocks D (FP64, column stride ldd, block
+// stride m*ldd); columns j < nl are copied to LDS as type S (stride m), the
+// remaining m - nl <= NREG columns to registers, and the inverse is written to
+// `out` (storage O, column stride ldo, block stride m*ldo, padding rows zero).
+// Each thread reads and writes only its own row, so out may be D itself when
+// ldo = ldd.
+template <class S, class O, int NREG>
+__global__ __launch_bounds__(256, 1) void k_invert(const double* __restrict__ D, int ldd, O* __restrict__ out,
+                                                   int ldo, int m, int nl, int* __restrict__ info) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ S rk2[2][256], ro2[2][256];
+  __shared__ double wv[2][4];
+  __shared__ int wi[2][4], ipiv[256], bad;
+  __shared__ S wp[2][4];
+  const int tid = threadIdx.x;
+  if (tid == 0) bad = 0;
+  const double* Dg = D + (size_t)blockIdx.x * m * ldd;
+  S* A = reinterpret_cast<S*>(smem);
+  const int lda = m;
+  if (tid < m)
+    for (int j = 0; j < nl; ++j) A[(size_t)j * lda + tid] = (S)Dg[(size_t)j * ldd + tid];
+  S rr[NREG > 0 ? NREG : 1];
+#pragma unroll
+  for (int jj = 0; jj < (NREG > 0 ? NREG : 1); ++jj)
+    rr[jj] = (NREG > 0 && tid < m && nl + jj < m) ? (S)Dg[(size_t)(nl + jj) * ldd + tid] : S(0);
+  __syncthreads();
+  gauss_jordan_rows<S, NREG>(A, m, lda, nl, rr, rk2, ro2, wv, wi, wp, ipiv, &bad);
+  O* Ob = out + (size_t)blockIdx.x * m * ldo;
+  if (tid < ldo) {
+    for (int j = 0; j < nl; ++j) store_as(Ob[(size_t)j * ldo + tid], tid < m ? A[(size_t)j * lda + tid] : S(0));
+#pragma unroll
+    for (int jj = 0; jj < NREG; ++jj)
+      if (nl + jj < m) store_as(Ob[(size_t)(nl + jj) * ldo + tid], tid < m ? rr[jj] : S(0));
+  }
+  __syncthreads();
+  if (tid == 0 && bad) info[0] = 1;
 }
 
 // z_K = Dinv_K r_K.  16-byte loads along the (padded) columns: a thread owns
@@ -262,32 +333,40 @@ static constexpr size_t kMaxLds = 160 * 1024;
 
 hipError_t launch_block_invert(int storage, double* D64, int ldd, void* Dout, int m, int64_t ne, int* info,
                               hipStream_t s) {
-  if (m > 256) return hipErrorInvalidValue;
+  if (m < 1 || m > 256) return hipErrorInvalidValue;
   const int ldo = block_ld(m);
-  // static LDS of the kernels: pivot row/column, reduction scratch
-  const size_t static_lds = 2 * 256 * sizeof(double) + 256 * sizeof(double) + 2 * 256 * sizeof(int) + 64;
+  constexpr int kRegCols = 72;  // FP64 columns kept in registers when the block does not fit LDS
+  // static LDS: pivot rows (2 x 2 x 256 entries), reductions, pivots
+  auto fixed = [](size_t es) { return (4 * 256 + 8) * es + 2 * 4 * (sizeof(double) + sizeof(int)) + 257 * sizeof(int) + 64; };
   if (storage == DG_FP64) {
-    const size_t need = (size_t)m * m * sizeof(double);
-    if (need + static_lds <= kMaxLds) {
-      hipFuncSetAttribute((const void*)k_invert_lds<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)need);
-      k_invert_lds<double><<<(unsigned)ne, 256, need, s>>>(D64, ldd, static_cast<double*>(Dout), ldo, m, info);
+    double* O = static_cast<double*>(Dout);
+    const size_t all = (size_t)m * m * sizeof(double);
+    if (all + fixed(8) <= kMaxLds) {
+      hipFuncSetAttribute((const void*)k_invert<double, double, 0>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)all);
+      k_invert<double, double, 0><<<(unsigned)ne, 256, all, s>>>(D64, ldd, O, ldo, m, m, info);
+    } else if (m > kRegCols && (size_t)(m - kRegCols) * m * sizeof(double) + fixed(8) <= kMaxLds) {
+      const size_t part = (size_t)(m - kRegCols) * m * sizeof(double);
+      hipFuncSetAttribute((const void*)k_invert<double, double, kRegCols>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)part);
+      k_invert<double, double, kRegCols><<<(unsigned)ne, 256, part, s>>>(D64, ldd, O, ldo, m, m - kRegCols, info);
     } else {
-      if (Dout != D64 || ldd != ldo) return hipErrorInvalidValue;
-      k_invert_global64<<<(unsigned)ne, 256, 0, s>>>(D64, m, ldd, info);
+      return hipErrorInvalidValue;  // FP64 blocks above m = 189 do not fit LDS + registers
     }
     return hipGetLastError();
   }
   if (storage == DG_FP32 || storage == DG_BF16) {
     // FP32 Gauss-Jordan in LDS; BF16 storage rounds the FP32 inverse
-    const size_t need = (size_t)m * m * sizeof(float);
-    if (need + static_lds > kMaxLds) return hipErrorInvalidValue;
+    const size_t all = (size_t)m * m * sizeof(float);
+    if (all + fixed(4) > kMaxLds) return hipErrorInvalidValue;
     if (storage == DG_FP32) {
-      hipFuncSetAttribute((const void*)k_invert_lds<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)need);
-      k_invert_lds<float><<<(unsigned)ne, 256, need, s>>>(D64, ldd, static_cast<float*>(Dout), ldo, m, info);
+      hipFuncSetAttribute((const void*)k_invert<float, float, 0>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)all);
+      k_invert<float, float, 0><<<(unsigned)ne, 256, all, s>>>(D64, ldd, static_cast<float*>(Dout), ldo, m, m, info);
     } else {
-      hipFuncSetAttribute((const void*)k_invert_lds<float, bf16_t>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)need);
-      k_invert_lds<float, bf16_t><<<(unsigned)ne, 256, need, s>>>(D64, ldd, static_cast<bf16_t*>(Dout), ldo, m, info);
+      hipFuncSetAttribute((const void*)k_invert<float, bf16_t, 0>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)all);
+      k_invert<float, bf16_t, 0><<<(unsigned)ne, 256, all, s>>>(D64, ldd, static_cast<bf16_t*>(Dout), ldo, m, m, info);
     }
     return hipGetLastError();
   }
