@@ -138,12 +138,14 @@ def time_to_tolerance(storage="fp64", precond="bj", fine_precision="fp64"):
             "converged": bool(st["converged"]), "rel_res_true": st["rel_res_true"], "dt": dt}
 
 
-def mg_trajectory(n_steps=4, lag=1, cycle="v"):
+def mg_trajectory(n_steps=4, lag=1, cycle="v", scheme="be"):
     """Backward-Euler steps of the P4 24^3 workload (CFL 100), each solved by
     FGMRES(30) to 1e-8 with the P4/P2/P1 p-multigrid preconditioner (FP32 fine
     smoothing and factors).  lag > 1: the hierarchy is built every lag steps and
     in between only its fine level follows the current state and time step
-    (coarse operators frozen, fine block Jacobi refreshed)."""
+    (coarse operators frozen, fine block Jacobi refreshed).  scheme "ros2": each
+    step is a two-stage ROS2 Rosenbrock step (Alg. ros), one solve per stage
+    with the hierarchy of the step's initial state."""
     import torch
     import synth
     from paper_1809_00866_amd import DG
@@ -154,9 +156,10 @@ def mg_trajectory(n_steps=4, lag=1, cycle="v"):
     iters, t_setup, t_solve = [], 0.0, 0.0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    from paper_1809_00866_amd import schemes
     for k in range(n_steps):
-        shift = (2 * cfg["order"] + 1) * g.max_wave_speed(w) / (cfg["cfl"] * h)
-        b = -g.residual(w)
+        dt = cfg["cfl"] * h / ((2 * cfg["order"] + 1) * g.max_wave_speed(w))
+        shift = 1.0 / dt if scheme == "be" else 1.0 / (schemes.ROS2["gamma"] * dt)
         ta = time.perf_counter()
         if k % lag == 0:
             g.mg_setup(w, shift, cfg["mg_orders"], cfg["mg_smooth"], storage="fp32", use_graph=True,
@@ -165,7 +168,13 @@ def mg_trajectory(n_steps=4, lag=1, cycle="v"):
             g.mg_update_fine(w, shift, refresh_blocks=True)
         torch.cuda.synchronize()
         tb = time.perf_counter()
-        dw, st = g.fgmres(w, shift, b, restart=cfg["restart"], max_iter=600, rtol=cfg["rtol"], precond="mg")
+        if scheme == "be":
+            dw, st = g.fgmres(w, shift, -g.residual(w), restart=cfg["restart"], max_iter=600, rtol=cfg["rtol"],
+                              precond="mg")
+            w_next = w + dw
+        else:
+            w_next, st = g.rosenbrock_step(w, dt, schemes.ROS2, restart=cfg["restart"], max_iter=600,
+                                           rtol=cfg["rtol"], precond="mg")
         torch.cuda.synchronize()
         tc = time.perf_counter()
         t_setup += tb - ta
@@ -173,11 +182,12 @@ def mg_trajectory(n_steps=4, lag=1, cycle="v"):
         if not st["converged"]:
             raise RuntimeError(f"step {k} did not converge: {st}")
         iters.append(st["iters"])
-        w = w + dw
+        w = w_next
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
     g.close()
-    return {"workload": f"{n_steps} backward-Euler steps, P4 24^3 hexes, CFL 100, FGMRES(30) to 1e-8, p-multigrid "
+    kind = "backward-Euler steps" if scheme == "be" else "ROS2 Rosenbrock steps (2 solves each)"
+    return {"workload": f"{n_steps} {kind}, P4 24^3 hexes, CFL 100, FGMRES(30) to 1e-8, p-multigrid "
                         f"{'full' if cycle == 'full' else 'V'} cycle P4/P2/P1 8/8/40, fp32 smoothing, "
                         f"hierarchy rebuilt every {lag} step(s)",
             "seconds": total, "setup_s": t_setup, "solve_s": t_solve, "iters_per_step": iters}
@@ -347,6 +357,7 @@ def main():
         res["trajectory_pmg"] = mg_trajectory(4, lag=1)
         res["trajectory_pmg_lag3"] = mg_trajectory(4, lag=3)
         res["trajectory_pmg_full_cycle"] = mg_trajectory(4, lag=1, cycle="full")
+        res["trajectory_pmg_ros2"] = mg_trajectory(4, lag=1, scheme="ros2")
     if not args.no_learned:
         res["learned_precond"] = learned_preconditioner()
     if not args.no_cpu_baseline:

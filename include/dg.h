@@ -176,6 +176,34 @@ typedef struct {
 dg_status dg_fgmres_solve(dg_context* ctx, const double* w, double shift, const double* b, double* x,
                           const dg_solve_opts* opts, dg_solve_stats* stats, void* stream);
 
+/* Rosenbrock (linearly implicit Runge-Kutta) step (Sec. 2.2, Alg. ros) for
+ * M dw/dt + R(w) = 0 with M = I (orthonormal basis):
+ *   for s = 1..n_stages:
+ *     dp = sum_{o<s} a[s][o] dw_o,  dq = sum_{o<s} c[s][o] dw_o   (0-based s, o)
+ *     (I/(gamma dt) + J(w)) dw_s = -R(w + dp) - dq/dt      (FGMRES with *opts)
+ *   w_next = w + sum_s m[s] dw_s
+ * The Jacobian is that of w for every stage, and the preconditioner named by
+ * opts->precond must have been set up by the caller at (w, 1/(gamma dt))
+ * (dg_block_precond_setup or dg_mg_setup; once per step).  Coefficients are
+ * the caller's (the scheme of the paper, ROSI2PW, is cited there without
+ * them); n_stages = 1, gamma = 1, m[0] = 1 is the linearised backward Euler
+ * step.  w and w_next: device, ndof entries, may not alias.  Stage vectors
+ * live in a library buffer grown on demand.  stats (host, nullable): iters
+ * and restarts summed over the stages, converged = all stages converged,
+ * rel_res_est / rel_res_true / rho = the largest over the stages, ms_solve
+ * summed.  Returns DG_NOT_CONVERGED (w_next still written) if a stage did
+ * not converge.  Synchronises the stream (once per FGMRES iteration). */
+enum { DG_ROS_MAX_STAGES = 6 };
+typedef struct {
+  int n_stages;                                  /* 1..DG_ROS_MAX_STAGES */
+  double gamma;                                  /* > 0 */
+  double a[DG_ROS_MAX_STAGES][DG_ROS_MAX_STAGES]; /* a[s][o], o < s used */
+  double c[DG_ROS_MAX_STAGES][DG_ROS_MAX_STAGES]; /* c[s][o], o < s used */
+  double m[DG_ROS_MAX_STAGES];
+} dg_rosenbrock;
+dg_status dg_rosenbrock_step(dg_context* ctx, const double* w, double dt, const dg_rosenbrock* coeffs,
+                             const dg_solve_opts* opts, double* w_next, dg_solve_stats* stats, void* stream);
+
 /* p-multigrid preconditioner (Sec. 2.4): levels l = 0..n_levels-1 of degrees
  * orders[0] (= the context's order) > orders[1] > ...; level vectors use the
  * DOF layout with N_b(orders[l]) modes.  Restriction keeps the first

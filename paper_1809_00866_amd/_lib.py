@@ -20,7 +20,7 @@ DG_MG_V, DG_MG_FULL = 0, 1
 
 EXPORTED = ["dg_create", "dg_destroy", "dg_ndof", "dg_nbasis", "dg_nvar", "dg_nq", "dg_volume_points",
             "dg_project", "dg_residual", "dg_residual_fp32", "dg_jvp", "dg_block_precond_setup", "dg_block_precond_apply",
-            "dg_fgmres_solve", "dg_mg_setup", "dg_mg_update_fine", "dg_mg_apply", "dg_mg_level_apply", "dg_mlp_nparams",
+            "dg_fgmres_solve", "dg_rosenbrock_step", "dg_mg_setup", "dg_mg_update_fine", "dg_mg_apply", "dg_mg_level_apply", "dg_mlp_nparams",
             "dg_mlp_set_weights", "dg_mlp_get_weights", "dg_mlp_features", "dg_mlp_forward", "dg_mlp_grad",
             "dg_mlp_train_step", "dg_mlp_apply", "dg_max_wave_speed",
             "dg_set_profiling", "dg_kernel_time", "dg_last_error", "dg_sync"]
@@ -41,6 +41,15 @@ class SolveOpts(ctypes.Structure):
     _fields_ = [("restart", ctypes.c_int), ("max_iter", ctypes.c_int), ("rtol", ctypes.c_double),
                 ("precond", ctypes.c_int), ("jvp_mode", ctypes.c_int), ("rho_ref", ctypes.c_double),
                 ("judge_after", ctypes.c_int)]
+
+
+ROS_MAX_STAGES = 6
+
+
+class RosCoeffs(ctypes.Structure):
+    _fields_ = [("n_stages", ctypes.c_int), ("gamma", ctypes.c_double),
+                ("a", (ctypes.c_double * ROS_MAX_STAGES) * ROS_MAX_STAGES),
+                ("c", (ctypes.c_double * ROS_MAX_STAGES) * ROS_MAX_STAGES), ("m", ctypes.c_double * ROS_MAX_STAGES)]
 
 
 class MgOpts(ctypes.Structure):
@@ -83,6 +92,8 @@ def load():
         "dg_block_precond_setup": (i, [ctx, vp, d, i, vp]),
         "dg_block_precond_apply": (i, [ctx, vp, vp, vp]),
         "dg_fgmres_solve": (i, [ctx, vp, d, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats), vp]),
+        "dg_rosenbrock_step": (i, [ctx, vp, d, ctypes.POINTER(RosCoeffs), ctypes.POINTER(SolveOpts), vp,
+                                   ctypes.POINTER(SolveStats), vp]),
         "dg_mg_setup": (i, [ctx, vp, d, ctypes.POINTER(MgOpts), vp]),
         "dg_mg_update_fine": (i, [ctx, vp, d, i, vp]),
         "dg_mg_apply": (i, [ctx, vp, vp, vp]),

@@ -255,6 +255,29 @@ class DG:
         stats = {k: getattr(st, k) for k, _ in L.SolveStats._fields_}
         return x, stats
 
+    def rosenbrock_step(self, w, dt, coeffs, out=None, restart=30, max_iter=1000, rtol=1e-8, precond="bj",
+                        jvp_mode="exact"):
+        """One step of Alg. ros; coeffs = dict(gamma, a, c, m) (a, c: n_s x n_s, m: n_s).
+        The preconditioner must be set up at (w, 1/(gamma dt))."""
+        self._vec(w, "w")
+        out = self.empty() if out is None else self._vec(out, "out")
+        ns = len(coeffs["m"])
+        if not 1 <= ns <= L.ROS_MAX_STAGES:
+            raise ValueError("1..6 stages")
+        k = L.RosCoeffs()
+        k.n_stages, k.gamma = ns, float(coeffs["gamma"])
+        for s in range(ns):
+            k.m[s] = float(coeffs["m"][s])
+            for o in range(s):
+                k.a[s][o] = float(coeffs["a"][s][o])
+                k.c[s][o] = float(coeffs["c"][s][o])
+        opts = L.SolveOpts(restart, max_iter, rtol, _PREC[precond], _MODE[jvp_mode], 0.0, 0)
+        st = L.SolveStats()
+        status = self.lib.dg_rosenbrock_step(self.ctx, _ptr(w), float(dt), ctypes.byref(k), ctypes.byref(opts),
+                                             _ptr(out), ctypes.byref(st), _stream())
+        L.check(status, "dg_rosenbrock_step", allow_not_converged=True)
+        return out, {f: getattr(st, f) for f, _ in L.SolveStats._fields_}
+
     def max_wave_speed(self, w):
         self._vec(w, "w")
         out = ctypes.c_double()

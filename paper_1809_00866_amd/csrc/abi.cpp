@@ -333,6 +333,7 @@ void dg_destroy(dg_context* c) {
   dfree(c->d_flag);
   dfree(c->d_color);
   dfree(c->d_D64);
+  dfree(c->d_ros);
   if (c->d_Dinv != c->d_D64) dfree(c->d_Dinv);
   dfree(c->d_V);
   dfree(c->d_Z);

@@ -94,6 +94,8 @@ struct dg_context {
   double* h_pin = nullptr;
   bool prof = false;
   std::map<std::string, dgc::Timer> timers;
+  double* d_ros = nullptr;       // Rosenbrock step: stage vectors, stage state, right-hand side
+  int64_t ros_len = 0;           // entries of d_ros
   dgc::MgState* mg = nullptr;    // p-multigrid preconditioner (dg_mg_setup)
   dgc::MlpState* mlp = nullptr;  // learned preconditioner (dg_mlp_*)
 };

@@ -78,3 +78,4 @@ def test_null_arguments():
     assert lib.dg_mg_apply(None, None, None, None) == -1
     assert lib.dg_mg_level_apply(None, 0, None, None, None) == -1
     assert lib.dg_mg_update_fine(None, None, 0.0, 1, None) == -1
+    assert lib.dg_rosenbrock_step(None, None, 0.1, None, None, None, None, None) == -1
