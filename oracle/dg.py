@@ -173,8 +173,10 @@ class DGOracle:
         fp, fo = self._faces_of(el)
         return el, fp, fo, self.face_tables(fp, fo), self.elem_tables(el)
 
-    def residual(self, U, elems=None, return_parts=False):
-        """R[E, c, b] for the elements `elems` (all elements if None)."""
+    def residual(self, U, elems=None, return_parts=False, U_lift=None):
+        """R[E, c, b] for the elements `elems` (all elements if None).
+        U_lift (optional): state whose jumps feed the face lifting term eta {r}
+        of the face viscous flux (only there; the elemental lifting R^K keeps U)."""
         el, fp, fo, ft, et = self._setup(elems)
         fn = ft["fn"]
         phys = self.phys
@@ -194,8 +196,13 @@ class DGOracle:
         # local lifting coefficients on each side
         rhoL = -0.5 * _ein("fq,fqp,fqc,fqb->fbcp", W, n, jump, ft["phiL"])
         rhoR = -0.5 * _ein("fq,fqp,fqc,fqb->fbcp", W, n, jump, ft["phiR"])
-        rL = _ein("fqb,fbcp->fqcp", ft["phiL"], rhoL)
-        rR = _ein("fqb,fbcp->fqcp", ft["phiR"], rhoR)
+        if U_lift is None:
+            rL = _ein("fqb,fbcp->fqcp", ft["phiL"], rhoL)
+            rR = _ein("fqb,fbcp->fqcp", ft["phiR"], rhoR)
+        else:
+            jl = _ein("fqb,fcb->fqc", ft["phiL"], U_lift[fo]) - _ein("fqb,fcb->fqc", ft["phiR"], U_lift[fn])
+            rL = _ein("fqb,fbcp->fqcp", ft["phiL"], -0.5 * _ein("fq,fqp,fqc,fqb->fbcp", W, n, jl, ft["phiL"]))
+            rR = _ein("fqb,fbcp->fqcp", ft["phiR"], -0.5 * _ein("fq,fqp,fqc,fqb->fbcp", W, n, jl, ft["phiR"]))
         gface = 0.5 * (gL + gR) + s * phys.eta * 0.5 * (rL + rR)
         uavg = 0.5 * (uL + uR)
         Hn = phys.conv_numflux(uL, uR, n) - _ein("fqpc,fqp->fqc", phys.visc_flux(uavg, gface), n)
@@ -235,6 +242,13 @@ class DGOracle:
         """
         Uc = U.astype(np.complex128) + 1j * h * V
         return np.imag(self.residual(Uc, elems)) / h
+
+    def stab_jvp(self, U, V, elems=None, h=1e-100):
+        """The BR2 stabilisation part of J(U) V (the last term of eq.
+        jacTrilFNURef): the derivative of the residual through the face lifting
+        argument eta {r} of the face viscous flux only, by complex step."""
+        Uc = U.astype(np.complex128)
+        return np.imag(self.residual(Uc, elems, U_lift=U + 1j * h * V)) / h
 
     def jvp_fd(self, U, V, R0=None, eps=1e-9, elems=None):
         """Finite-difference Jv of eqs. (matrix-free), (epsdef): one-sided,

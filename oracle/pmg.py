@@ -62,6 +62,33 @@ def inherited_matrix(o, U, shift, nb_coarse):
     return A
 
 
+def stab_matrix(o, U, nb_coarse):
+    """Dense R STB_0 P for the level with nb_coarse modes (STB_0: the BR2
+    stabilisation part of the fine Jacobian, DGOracle.stab_jvp)."""
+    mc = o.nvar * nb_coarse
+    n = o.ne * mc
+    A = np.zeros((n, n))
+    for col in range(n):
+        e, l = divmod(col, mc)
+        c, b = divmod(l, nb_coarse)
+        V = np.zeros(U.shape)
+        V[e, c, b] = 1.0
+        A[:, col] = restrict(o.stab_jvp(U, V), nb_coarse).reshape(-1)
+    return A
+
+
+def truncate_matrix(A, ne, nv, nb_from, nb_to):
+    """Keep the rows and columns of the first nb_to modes of every variable
+    (the Galerkin projection between two coarse levels)."""
+    keep = (np.arange(ne * nv * nb_from).reshape(ne, nv, nb_from)[:, :, :nb_to]).reshape(-1)
+    return A[np.ix_(keep, keep)]
+
+
+def stab_scale(k_from, k_to, d):
+    """S = k_to (k_to + d) / (k_from (k_from + d)) (App. A)."""
+    return k_to * (k_to + d) / (k_from * (k_from + d))
+
+
 def diagonal_blocks(A, ne, m):
     """Diagonal m x m blocks of a dense element-major matrix, [ne, m, m]."""
     return np.stack([A[e * m:(e + 1) * m, e * m:(e + 1) * m] for e in range(ne)])
@@ -102,20 +129,36 @@ def gmres_fixed(apply_A, apply_Minv, g, x0, iters, breakdown_tol=1e-14):
 
 
 class PMultigrid:
-    """Alg. vcic with inherited operators and GMRES[EWBJ] smoothers.
+    """Alg. vcic (or fullvcic) with inherited (optionally rescaled-inherited,
+    App. A) operators and GMRES[EWBJ] smoothers.
 
     orders: degrees k_0 > ... > k_L (k_0 = o.order); iters: smoothing
     iterations per level, the last one being the coarsest-level solve.
     """
 
-    def __init__(self, o, U, shift, orders, iters, cycle="V"):
+    def __init__(self, o, U, shift, orders, iters, cycle="V", rescale=False):
         assert orders[0] == o.order and all(a > b for a, b in zip(orders, orders[1:]))
         assert len(iters) == len(orders) and cycle in ("V", "full")
         self.o, self.U, self.shift, self.cycle = o, U, float(shift), cycle
         self.iters = list(iters)
         self.nbs = [basis_size(k, o.d) for k in orders]
         self.L = len(orders) - 1
-        self.A = [None] + [inherited_matrix(o, U, shift, nb) for nb in self.nbs[1:]]
+        if not rescale:
+            self.A = [None] + [inherited_matrix(o, U, shift, nb) for nb in self.nbs[1:]]
+        else:
+            # eq. GalProjResc: G_{l+1} = R (G_l - STB_l) P + S_l^{l+1} R STB_l P,
+            # STB_{l+1} = S_l^{l+1} R STB_l P, starting from the fine operator
+            self.A = [None]
+            G = inherited_matrix(o, U, shift, self.nbs[1])
+            S = stab_matrix(o, U, self.nbs[1])
+            for l in range(1, self.L + 1):
+                if l > 1:
+                    G = truncate_matrix(G, o.ne, o.nvar, self.nbs[l - 1], self.nbs[l])
+                    S = truncate_matrix(S, o.ne, o.nvar, self.nbs[l - 1], self.nbs[l])
+                sc = stab_scale(orders[l - 1], orders[l], o.d)
+                G = G - (1.0 - sc) * S
+                S = sc * S
+                self.A.append(G)
         self.D = [o.block_diagonal(U, shift)] + [
             diagonal_blocks(self.A[l], o.ne, o.nvar * self.nbs[l]) for l in range(1, self.L + 1)]
 
