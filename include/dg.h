@@ -58,7 +58,7 @@ typedef enum {
 
 enum { DG_BASIS_PK = 0, DG_BASIS_QK = 1 };          /* total degree / tensor degree */
 enum { DG_FLUX_LF = 0, DG_FLUX_ROE = 1 };           /* convective numerical flux */
-enum { DG_JVP_EXACT = 0, DG_JVP_FD = 1, DG_JVP_EXACT_FP32 = 2 };  /* Jv mode */
+enum { DG_JVP_EXACT = 0, DG_JVP_FD = 1, DG_JVP_EXACT_FP32 = 2, DG_JVP_STAB = 3 };  /* Jv mode */
 enum { DG_FP64 = 0, DG_FP32 = 1, DG_BF16 = 2 };     /* block-factor storage */
 enum { DG_PREC_NONE = 0, DG_PREC_BJ = 1, DG_PREC_MG = 2, DG_PREC_MLP = 3 };  /* FGMRES preconditioner */
 enum { DG_MG_V = 0, DG_MG_FULL = 1 };               /* p-multigrid cycle (Algs. vcic, fullvcic) */
@@ -126,6 +126,9 @@ dg_status dg_residual_fp32(dg_context* ctx, const double* w, double* r, void* st
  *  (device, nullable) to skip its evaluation.  ||v|| = 0 gives out = 0 + shift*v.
  *  mode DG_JVP_EXACT_FP32: the exact tangent computed like dg_residual_fp32
  *  (FP32 contractions and pointwise arithmetic; for preconditioners only).
+ *  mode DG_JVP_STAB: J replaced by its BR2 stabilisation part (the last term
+ *  of eq. jacTrilFNURef: the tangent through the face lifting argument
+ *  eta {r} of the face viscous flux only), FP64; not a solver mode.
  *  out may not alias w, v or r_w. */
 dg_status dg_jvp(dg_context* ctx, const double* w, const double* r_w, const double* v, double shift,
                  int mode, double* out, void* stream);
@@ -232,6 +235,11 @@ typedef struct {
                            probing of the coarse operators as the exact FP64 Jv
                            or its FP32 variant; the outer solve stays FP64 */
   int cycle;            /* DG_MG_V or DG_MG_FULL */
+  int rescale;          /* 1: rescaled-inherited coarse operators (App. A, eq.
+                           GalProjResc): the BR2 stabilisation part of each
+                           inherited operator is scaled by
+                           S = k_{l+1}(k_{l+1}+d) / (k_l(k_l+d)) per level
+                           (probing costs one more product per column) */
 } dg_mg_opts;
 
 /* Builds the hierarchy at state w (device, copied) and shift: runs the fine

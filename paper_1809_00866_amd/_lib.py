@@ -13,7 +13,7 @@ STATUS_NAMES = {0: "DG_OK", 1: "DG_NOT_CONVERGED", -1: "DG_ERR_ARG", -2: "DG_ERR
                 -4: "DG_ERR_STATE", -5: "DG_ERR_SINGULAR_BLOCK", -6: "DG_ERR_NONFINITE"}
 DG_BASIS_PK, DG_BASIS_QK = 0, 1
 DG_FLUX_LF, DG_FLUX_ROE = 0, 1
-DG_JVP_EXACT, DG_JVP_FD, DG_JVP_EXACT_FP32 = 0, 1, 2
+DG_JVP_EXACT, DG_JVP_FD, DG_JVP_EXACT_FP32, DG_JVP_STAB = 0, 1, 2, 3
 DG_FP64, DG_FP32, DG_BF16 = 0, 1, 2
 DG_PREC_NONE, DG_PREC_BJ, DG_PREC_MG, DG_PREC_MLP = 0, 1, 2, 3
 DG_MG_V, DG_MG_FULL = 0, 1
@@ -55,7 +55,7 @@ class RosCoeffs(ctypes.Structure):
 class MgOpts(ctypes.Structure):
     _fields_ = [("n_levels", ctypes.c_int), ("orders", ctypes.c_int * 3), ("smooth_iters", ctypes.c_int * 3),
                 ("storage", ctypes.c_int), ("use_graph", ctypes.c_int), ("fine_precision", ctypes.c_int),
-                ("cycle", ctypes.c_int)]
+                ("cycle", ctypes.c_int), ("rescale", ctypes.c_int)]
 
 
 class SolveStats(ctypes.Structure):

@@ -13,7 +13,7 @@ from . import _lib as L
 
 _FLUX = {"lf": L.DG_FLUX_LF, "roe": L.DG_FLUX_ROE}
 _BASIS = {"P": L.DG_BASIS_PK, "Q": L.DG_BASIS_QK}
-_MODE = {"exact": L.DG_JVP_EXACT, "fd": L.DG_JVP_FD, "exact_fp32": L.DG_JVP_EXACT_FP32}
+_MODE = {"exact": L.DG_JVP_EXACT, "fd": L.DG_JVP_FD, "exact_fp32": L.DG_JVP_EXACT_FP32, "stab": L.DG_JVP_STAB}
 _STORAGE = {"fp64": L.DG_FP64, "fp32": L.DG_FP32, "bf16": L.DG_BF16}
 _PREC = {"none": L.DG_PREC_NONE, "bj": L.DG_PREC_BJ, "mg": L.DG_PREC_MG, "mlp": L.DG_PREC_MLP}
 
@@ -130,7 +130,7 @@ class DG:
         return out
 
     def mg_setup(self, w, shift, orders, smooth_iters, storage="fp64", use_graph=True, fine_precision="fp64",
-                 cycle="v"):
+                 cycle="v", rescale=False):
         """p-multigrid hierarchy at (w, shift); orders[0] must be the context's order;
         cycle "v" (Alg. vcic) or "full" (Alg. fullvcic)."""
         if cycle not in ("v", "full"):
@@ -141,7 +141,8 @@ class DG:
             raise ValueError("need 2 or 3 levels and one smoothing count per level")
         o = L.MgOpts(len(orders), (ctypes.c_int * 3)(*(orders + [0] * (3 - len(orders)))),
                      (ctypes.c_int * 3)(*(smooth_iters + [0] * (3 - len(orders)))), _STORAGE[storage],
-                     int(bool(use_graph)), _STORAGE[fine_precision], L.DG_MG_FULL if cycle == "full" else L.DG_MG_V)
+                     int(bool(use_graph)), _STORAGE[fine_precision], L.DG_MG_FULL if cycle == "full" else L.DG_MG_V,
+                     int(bool(rescale)))
         self.mg_levels = [(self.ne * self.nv * _nb(k, self.dim)) for k in orders]
         L.check(self.lib.dg_mg_setup(self.ctx, _ptr(w), float(shift), ctypes.byref(o), _stream()), "dg_mg_setup")
 

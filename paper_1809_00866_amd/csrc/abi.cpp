@@ -75,6 +75,34 @@ dg_status eval_residual_f32(dg_context* c, bool jvp, const double* w, const doub
   return DG_OK;
 }
 
+dg_status eval_stab(dg_context* c, bool f32, const double* w, const double* v, double* out, hipStream_t s) {
+  if (!c->d_zero) {
+    dg_status st;
+    if ((st = dalloc(&c->d_zero, (size_t)c->ndof)) != DG_OK) return st;
+    HIPCHK(dgk::launch_fill(c->d_zero, c->ndof, 0.0, s));
+  }
+  dgk::Phys ph = c->ph;
+  ph.stab_only = 1;
+  const double* z = c->d_zero;  // no tangent in the volume terms and the gradients
+  if (f32) {
+    if (!c->use_mfma || !c->d_mtab_f || !c->d_Hf || !c->d_Gf)
+      return fail(DG_ERR_ARG, "the reduced-precision operator needs a 3D P2-P4 configuration with MFMA kernels");
+    HIPCHK(dgk::launch_grad_mfma_f32(c->cfg, true, w, z, c->d_Gf, c->mtf, c->mesh, s));
+    HIPCHK(dgk::launch_face_mfma_f32(c->cfg, true, w, v, c->d_Hf, c->mtf, c->mesh, ph, s));
+    HIPCHK(dgk::launch_volume_mfma_f32(c->cfg, true, w, z, c->d_Gf, c->d_Hf, out, 0.0, c->mtf, c->mesh, c->ph, s));
+    return DG_OK;
+  }
+  if (c->use_mfma) {
+    HIPCHK(dgk::launch_grad_mfma(c->cfg, true, w, z, c->d_G, c->mt, c->mesh, s));
+    HIPCHK(dgk::launch_face_mfma(c->cfg, true, w, v, c->d_H, c->mt, c->mesh, ph, s));
+    HIPCHK(dgk::launch_volume_mfma(c->cfg, true, w, z, c->d_G, c->d_H, out, 0.0, c->mt, c->mesh, c->ph, s));
+    return DG_OK;
+  }
+  HIPCHK(dgk::launch_face(c->cfg, true, w, v, c->d_H, c->tb, c->mesh, ph, s));
+  HIPCHK(dgk::launch_volume(c->cfg, true, w, z, c->d_H, out, 0.0, c->tb, c->mesh, c->ph, s));
+  return DG_OK;
+}
+
 dg_status norm2(dg_context* c, const double* x, double* dout, hipStream_t s) {
   HIPCHK(dgk::launch_dot_partials(x, x, c->ndof, c->d_red, s));
   HIPCHK(dgk::launch_sum_partials(c->d_red, dgk::kRedBlocks, dout, 1, s));
@@ -85,6 +113,12 @@ dg_status jvp_impl(dg_context* c, const double* w, const double* r_w, const doub
                    double* out, hipStream_t s) {
   if (mode == DG_JVP_EXACT) return eval_residual(c, true, w, v, shift, out, s);
   if (mode == DG_JVP_EXACT_FP32) return eval_residual_f32(c, true, w, v, shift, out, s);
+  if (mode == DG_JVP_STAB) {
+    dg_status st;
+    if ((st = eval_stab(c, false, w, v, out, s)) != DG_OK) return st;
+    if (shift != 0.0) HIPCHK(dgk::launch_axpby(c->ndof, 1.0, out, shift, v, out, s));
+    return DG_OK;
+  }
   // finite difference of eqs. (matrix-free)/(epsdef)
   const double* r0 = r_w;
   dg_status st;
@@ -334,6 +368,7 @@ void dg_destroy(dg_context* c) {
   dfree(c->d_color);
   dfree(c->d_D64);
   dfree(c->d_ros);
+  dfree(c->d_zero);
   if (c->d_Dinv != c->d_D64) dfree(c->d_Dinv);
   dfree(c->d_V);
   dfree(c->d_Z);
@@ -376,7 +411,8 @@ dg_status dg_jvp(dg_context* c, const double* w, const double* r_w, const double
                  double* out, void* stream) {
   if (!c || !w || !v || !out) return fail(DG_ERR_ARG, "null argument");
   if (out == w || out == v || (r_w && out == r_w)) return fail(DG_ERR_ARG, "out may not alias w, v or r_w");
-  if (mode != DG_JVP_EXACT && mode != DG_JVP_FD && mode != DG_JVP_EXACT_FP32) return fail(DG_ERR_ARG, "unknown jvp mode");
+  if (mode != DG_JVP_EXACT && mode != DG_JVP_FD && mode != DG_JVP_EXACT_FP32 && mode != DG_JVP_STAB)
+    return fail(DG_ERR_ARG, "unknown jvp mode");
   return jvp_impl(c, w, r_w, v, shift, mode, out, (hipStream_t)stream);
 }
 

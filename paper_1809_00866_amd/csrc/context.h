@@ -94,6 +94,7 @@ struct dg_context {
   double* h_pin = nullptr;
   bool prof = false;
   std::map<std::string, dgc::Timer> timers;
+  double* d_zero = nullptr;      // ndof zeros (stabilisation-only Jv)
   double* d_ros = nullptr;       // Rosenbrock step: stage vectors, stage state, right-hand side
   int64_t ros_len = 0;           // entries of d_ros
   dgc::MgState* mg = nullptr;    // p-multigrid preconditioner (dg_mg_setup)
@@ -131,6 +132,10 @@ dg_status eval_residual(dg_context* c, bool jvp, const double* w, const double* 
 // outputs FP64); 3D P2-P4 configurations only.
 dg_status eval_residual_f32(dg_context* c, bool jvp, const double* w, const double* v, double shift, double* out,
                             hipStream_t s);
+// out = STB(w) v: the BR2 stabilisation part of the Jacobian (the tangent of
+// the face lifting term eta {r} of the face viscous flux only; no shift),
+// FP64 or the FP32 operator.
+dg_status eval_stab(dg_context* c, bool f32, const double* w, const double* v, double* out, hipStream_t s);
 // dout[0] = ||x||_2 over the context's DOF vector length.
 dg_status norm2(dg_context* c, const double* x, double* dout, hipStream_t s);
 // out = shift*v + J(w) v, exact or finite difference.

@@ -52,7 +52,9 @@ using MTablesF = MTablesT<float>;
 
 struct Phys {
   double gamma, prandtl, mu, eta, efix;
-  int flux;  // DG_FLUX_LF / DG_FLUX_ROE
+  int flux;           // DG_FLUX_LF / DG_FLUX_ROE
+  int stab_only = 0;  // Jv face kernels: keep only the tangent of the face lifting
+                      // term eta {r} (the BR2 stabilisation part of the Jacobian)
 };
 
 struct Mesh {

@@ -70,6 +70,18 @@ DEV void face_body(const double* __restrict__ U, const double* __restrict__ V, d
         }
       }
     }
+    if constexpr (JVP) {
+      if (ph.stab_only) {  // tangent through the face lifting term only
+        for (int c = 0; c < NV; ++c) {
+          uL[c].d = 0.0;
+          uR[c].d = 0.0;
+          for (int j = 0; j < DIM; ++j) {
+            gL[c][j].d = 0.0;
+            gR[c][j].d = 0.0;
+          }
+        }
+      }
+    }
     T Hn[NV];
     num_flux<T, DIM>(uL, uR, p, ph, Hn);
     T ua[NV], Ga[NV][DIM];

@@ -432,6 +432,12 @@ DEV void face_mfma_body(const double* __restrict__ U, const double* __restrict__
       for (int k = 0; k < NCH * NV; ++k) st[s][k] = stage[k][fql][ft];
       __syncthreads();
     }
+    if constexpr (JVP) {
+      if (ph.stab_only) {  // tangent through the face lifting channel {r} only
+#pragma unroll
+        for (int k = 0; k < 5 * NV; ++k) st[NS - 1][k] = R(0);
+      }
+    }
     const int fq = 16 * rbf + fql;
     const int64_t ef = e0 + ft;
     if (fq < NFQ && ef < ne) {

@@ -32,6 +32,7 @@ struct MgLevel {
   int order = 0, nb = 0, m = 0, iters = 0;
   int64_t n = 0;               // level vector length ne*nv*nb
   double* B = nullptr;         // coarse levels: BSR blocks [nslot][ne][m*m]
+  double* Bs = nullptr;        // rescaled hierarchy, level 1: its stabilisation part (same layout)
   void* Dinv = nullptr;        // coarse levels: block-Jacobi inverses
   double* g = nullptr;         // right-hand side
   double* x = nullptr;         // iterate
@@ -47,6 +48,7 @@ struct MgState {
   int nlev = 0, nslot = 0, storage = DG_FP64;
   bool fine_f32 = false;  // FP32 fine-level operator inside the cycle
   bool full = false;      // Alg. fullvcic instead of Alg. vcic
+  bool rescale = false;   // rescaled-inherited coarse operators (App. A)
   double shift = 0.0;
   bool use_graph = false, ready = false;
   MgLevel lev[3];
@@ -69,6 +71,7 @@ void mg_destroy(MgState* M) {
   if (M->ev_b) (void)hipEventDestroy(M->ev_b);
   for (auto& L : M->lev) {
     dfree(L.B);
+    dfree(L.Bs);
     dfree(L.Dinv);
     dfree(L.g);
     dfree(L.x);
@@ -337,6 +340,7 @@ dg_status dg_mg_setup(dg_context* c, const double* w, double shift, const dg_mg_
   if (o->fine_precision != DG_FP64 && o->fine_precision != DG_FP32)
     return fail(DG_ERR_ARG, "fine_precision must be DG_FP64 or DG_FP32");
   if (o->cycle != DG_MG_V && o->cycle != DG_MG_FULL) return fail(DG_ERR_ARG, "cycle must be DG_MG_V or DG_MG_FULL");
+  if (o->rescale != 0 && o->rescale != 1) return fail(DG_ERR_ARG, "rescale must be 0 or 1");
   if (o->fine_precision == DG_FP32 && !(c->use_mfma && c->d_mtab_f))
     return fail(DG_ERR_ARG, "the FP32 fine operator needs a 3D P2-P4 configuration with MFMA kernels");
   hipStream_t s = (hipStream_t)stream;
@@ -363,6 +367,7 @@ dg_status dg_mg_setup(dg_context* c, const double* w, double shift, const dg_mg_
   M->use_graph = o->use_graph != 0;
   M->fine_f32 = o->fine_precision == DG_FP32;
   M->full = o->cycle == DG_MG_FULL;
+  M->rescale = o->rescale != 0;
   for (int l = 0; l < M->nlev; ++l) {
     MgLevel& L = M->lev[l];
     L.order = o->orders[l];
@@ -394,12 +399,25 @@ dg_status dg_mg_setup(dg_context* c, const double* w, double shift, const dg_mg_
   if (hipMemcpy(M->color2, col2.data(), ne * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
     return bail(fail(DG_ERR_HIP, "colour upload failed"));
 
-  // first coarse level probed from G_0, deeper levels by truncation
+  // first coarse level probed from G_0, deeper levels by truncation.  Rescaled
+  // hierarchy (App. A, eq. GalProjResc): with STB_0 the BR2 stabilisation part
+  // of the fine Jacobian, G_1 = R (G_0 - (1 - S_0^1) STB_0) P and
+  // STB_1 = S_0^1 R STB_0 P; G_2 = R (G_1 - (1 - S_1^2) STB_1) P, where
+  // S_l^{l+1} = k_{l+1} (k_{l+1} + d) / (k_l (k_l + d)).
+  auto scale = [&](int l) {
+    const double a = M->lev[l].order, b = M->lev[l + 1].order;
+    return b * (b + dim) / (a * (a + dim));
+  };
   {
     MgLevel& C = M->lev[1];
     const size_t nB = (size_t)M->nslot * ne * C.m * C.m;
     if ((st = dalloc(&C.B, nB)) != DG_OK) return bail(st);
     HIPCHK(dgk::launch_fill(C.B, (int64_t)nB, 0.0, s));
+    if (M->rescale) {
+      if ((st = dalloc(&C.Bs, nB)) != DG_OK) return bail(st);
+      HIPCHK(dgk::launch_fill(C.Bs, (int64_t)nB, 0.0, s));
+    }
+    const double s01 = scale(0);
     ProfScope ps(c, "mg_probe", s);
     for (int col = 0; col < M->ncolor2; ++col)
       for (int l = 0; l < C.m; ++l) {
@@ -408,14 +426,33 @@ dg_status dg_mg_setup(dg_context* c, const double* w, double shift, const dg_mg_
         if ((st = M->fine_f32 ? eval_residual_f32(c, true, M->w, c->d_t1, shift, c->d_t2, s)
                               : eval_residual(c, true, M->w, c->d_t1, shift, c->d_t2, s)) != DG_OK)
           return bail(st);
+        if (M->rescale) {
+          if ((st = eval_stab(c, M->fine_f32, M->w, c->d_t1, c->d_t3, s)) != DG_OK) return bail(st);
+          HIPCHK(dgk::launch_axpby(c->ndof, 1.0, c->d_t2, -(1.0 - s01), c->d_t3, c->d_t2, s));
+          HIPCHK(dgk::launch_axpby(c->ndof, s01, c->d_t3, 0.0, c->d_t3, c->d_t3, s));
+          HIPCHK(dgk::launch_extract_bsr(c->d_t3, M->color2, col, l, c->mesh.nbr, nf, c->nb, C.nb, nv, ne, C.Bs, s));
+        }
         HIPCHK(dgk::launch_extract_bsr(c->d_t2, M->color2, col, l, c->mesh.nbr, nf, c->nb, C.nb, nv, ne, C.B, s));
       }
   }
   for (int l = 2; l < M->nlev; ++l) {
     MgLevel& P = M->lev[l - 1];
     MgLevel& C = M->lev[l];
+    const int64_t nP = (int64_t)M->nslot * ne * P.m * P.m;
     if ((st = dalloc(&C.B, (size_t)M->nslot * ne * C.m * C.m)) != DG_OK) return bail(st);
-    HIPCHK(dgk::launch_truncate_bsr(P.B, P.nb, C.B, C.nb, nv, M->nslot, ne, s));
+    if (M->rescale) {
+      // P.Bs <- G_{l-1} - (1 - S) STB_{l-1}, truncated into G_l (STB_l is not
+      // needed: three levels at most)
+      HIPCHK(dgk::launch_axpby(nP, 1.0, P.B, -(1.0 - scale(l - 1)), P.Bs, P.Bs, s));
+      HIPCHK(dgk::launch_truncate_bsr(P.Bs, P.nb, C.B, C.nb, nv, M->nslot, ne, s));
+    } else {
+      HIPCHK(dgk::launch_truncate_bsr(P.B, P.nb, C.B, C.nb, nv, M->nslot, ne, s));
+    }
+  }
+  if (M->rescale) {
+    HIPCHK(hipStreamSynchronize(s));
+    dfree(M->lev[1].Bs);
+    M->lev[1].Bs = nullptr;
   }
   // coarse block-Jacobi factors from the diagonal slot
   for (int l = 1; l < M->nlev; ++l) {

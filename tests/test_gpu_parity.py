@@ -229,6 +229,22 @@ def test_full_size_sampled(name):
     assert np.linalg.norm(Jg[sample] - J) <= 1e-12 * np.linalg.norm(J)
 
 
+@pytest.mark.parametrize("N,k,sp,nq,flux", [CASES[0], CASES[2], CASES[3], CASES[4]],
+                         ids=[IDS[0], IDS[2], IDS[3], IDS[4]])
+def test_stabilisation_jvp_parity(N, k, sp, nq, flux):
+    """The BR2 stabilisation part of the Jacobian (jvp mode "stab") against the
+    oracle's complex-step derivative through the face lifting term, 1e-12."""
+    _say(f"stabilisation jvp {N} {sp}{k}")
+    o, g, U, w = make_case(N, k, sp, nq, flux)
+    V = np.random.default_rng(44).standard_normal(U.shape)
+    v = torch.tensor(o.to_flat(V), device="cuda")
+    ref = o.to_flat(o.stab_jvp(U, V))
+    out = g.jvp(w, v, mode="stab").cpu().numpy()
+    assert rel(out, ref) <= 1e-12, rel(out, ref)
+    out2 = g.jvp(w, v, shift=2.5, mode="stab").cpu().numpy()
+    assert rel(out2, ref + 2.5 * o.to_flat(V)) <= 1e-12
+
+
 @pytest.mark.parametrize("N,k,nq", [((2, 3, 5), 3, 4), ((3, 2, 3), 4, 5), ((3, 3, 2), 2, 3)],
                          ids=["P3", "P4", "P2"])
 def test_mfma_and_reference_kernels_agree(N, k, nq, monkeypatch):

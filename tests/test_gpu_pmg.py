@@ -194,6 +194,36 @@ def test_lagged_hierarchy_matches_the_oracle(case):
     ge.close()
 
 
+@pytest.mark.parametrize("name", ["P2-P1", "2d-P2-P1-P0"])
+def test_rescaled_inherited_hierarchy_matches_the_oracle(name):
+    """App. A: coarse operators with the BR2 stabilisation part rescaled level by
+    level (1e-12), and the V-cycle built on them (1e-9)."""
+    from paper_1809_00866_amd import DG
+    N, k, nq, orders, iters, shift = CASES[name]
+    _say(f"rescaled hierarchy {name}")
+    mesh = synth.lattice_mesh(N, L=1.0)
+    d = len(N)
+    o = DGOracle(mesh, k, "P", nq, NavierStokes(d, mu=5e-2))
+    fld = synth.TaylorGreenStandIn(seed=23, L=1.0) if d == 3 else synth.FreeStreamPlusModes(seed=23)
+    U = o.project(fld)
+    mg = PMultigrid(o, U, shift, orders, iters, rescale=True)
+    g = DG(mesh, k, nq1d=nq, mu=5e-2)
+    w = torch.tensor(o.to_flat(U), device="cuda")
+    g.mg_setup(w, shift, orders, iters, storage="fp64", use_graph=True, rescale=True)
+    rng = np.random.default_rng(24)
+    for l in range(1, mg.L + 1):
+        X = rng.standard_normal((o.ne, o.nvar, mg.nbs[l]))
+        y_o = (mg.A[l] @ X.reshape(-1)).reshape(X.shape)
+        y_g = _unflat(g.mg_level_apply(l, torch.tensor(_flat(X), device="cuda")).cpu().numpy(), o.ne, o.nvar,
+                      mg.nbs[l])
+        assert np.linalg.norm(y_g - y_o) <= 1e-12 * np.linalg.norm(y_o), (l, np.linalg.norm(y_g - y_o))
+    R = rng.standard_normal(U.shape)
+    z_o = o.to_flat(mg.apply(R))
+    z_g = g.mg_apply(torch.tensor(o.to_flat(R), device="cuda")).cpu().numpy()
+    assert np.linalg.norm(z_g - z_o) <= 1e-9 * np.linalg.norm(z_o)
+    g.close()
+
+
 def test_state_errors_and_reduced_precision_smoothers():
     from paper_1809_00866_amd import DG
     from paper_1809_00866_amd._lib import DGError
