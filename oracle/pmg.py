@@ -89,6 +89,88 @@ def stab_scale(k_from, k_to, d):
     return k_to * (k_to + d) / (k_from * (k_from + d))
 
 
+def greedy_colouring(nbr):
+    """Colour of every element: the smallest colour not used by an earlier
+    face neighbour (elements in index order, self-neighbours ignored)."""
+    ne = nbr.shape[0]
+    col = -np.ones(ne, dtype=np.int64)
+    for e in range(ne):
+        used = {int(col[n]) for n in nbr[e] if n != e and col[n] >= 0}
+        c = 0
+        while c in used:
+            c += 1
+        col[e] = c
+    return col
+
+
+class BlockILU0:
+    """Block ILU(0) of a level operator (dense, element-major blocks of size m)
+    in the multicolour order of the face-neighbour graph (colour, then element
+    index): the textbook elimination restricted to the block pattern of the
+    operator (element K couples to itself and to its face neighbours), fill
+    outside the pattern dropped.  Stands in for the ILU-based coarse smoother
+    preconditioner of the paper (ASM(1,ILU(0)) over subdomains)."""
+
+    def __init__(self, A, ne, m, nbr, colour):
+        order = np.lexsort((np.arange(ne), colour))           # colour-major
+        pos = np.empty(ne, dtype=np.int64)
+        pos[order] = np.arange(ne)
+        pat = np.zeros((ne, ne), dtype=bool)
+        for e in range(ne):
+            pat[e, e] = True
+            pat[e, nbr[e]] = True
+        blk = lambda X, i, j: X[i * m:(i + 1) * m, j * m:(j + 1) * m]
+        LU = A.copy()
+        for kk in range(ne):
+            k = order[kk]
+            Dk_inv = np.linalg.inv(blk(LU, k, k))
+            for ii in range(kk + 1, ne):
+                i = order[ii]
+                if not pat[i, k]:
+                    continue
+                Lik = blk(LU, i, k) @ Dk_inv
+                LU[i * m:(i + 1) * m, k * m:(k + 1) * m] = Lik
+                for jj in range(kk + 1, ne):
+                    j = order[jj]
+                    if pat[k, j] and pat[i, j]:
+                        LU[i * m:(i + 1) * m, j * m:(j + 1) * m] -= Lik @ blk(LU, k, j)
+        self.LU, self.order, self.pos, self.pat, self.ne, self.m = LU, order, pos, pat, ne, m
+
+    def factors(self):
+        """(L, U) as dense matrices in the element ordering: L unit block lower,
+        U block upper, with respect to the multicolour order."""
+        ne, m = self.ne, self.m
+        L = np.eye(ne * m)
+        U = np.zeros((ne * m, ne * m))
+        for i in range(ne):
+            for j in range(ne):
+                if not self.pat[i, j]:
+                    continue
+                B = self.LU[i * m:(i + 1) * m, j * m:(j + 1) * m]
+                if self.pos[j] < self.pos[i]:
+                    L[i * m:(i + 1) * m, j * m:(j + 1) * m] = B
+                else:
+                    U[i * m:(i + 1) * m, j * m:(j + 1) * m] = B
+        return L, U
+
+    def solve(self, r):
+        """(L U)^-1 r by block forward and backward substitution."""
+        ne, m = self.ne, self.m
+        blk = lambda i, j: self.LU[i * m:(i + 1) * m, j * m:(j + 1) * m]
+        y = np.array(r, dtype=np.float64).reshape(ne, m)
+        for k in self.order:                                   # forward, unit lower
+            for j in range(ne):
+                if self.pat[k, j] and self.pos[j] < self.pos[k]:
+                    y[k] -= blk(k, j) @ y[j]
+        z = y.copy()
+        for k in self.order[::-1]:                             # backward, upper
+            for j in range(ne):
+                if self.pat[k, j] and self.pos[j] > self.pos[k]:
+                    z[k] -= blk(k, j) @ z[j]
+            z[k] = np.linalg.solve(blk(k, k), z[k])
+        return z.reshape(-1)
+
+
 def diagonal_blocks(A, ne, m):
     """Diagonal m x m blocks of a dense element-major matrix, [ne, m, m]."""
     return np.stack([A[e * m:(e + 1) * m, e * m:(e + 1) * m] for e in range(ne)])
@@ -136,7 +218,7 @@ class PMultigrid:
     iterations per level, the last one being the coarsest-level solve.
     """
 
-    def __init__(self, o, U, shift, orders, iters, cycle="V", rescale=False):
+    def __init__(self, o, U, shift, orders, iters, cycle="V", rescale=False, coarse_ilu=False):
         assert orders[0] == o.order and all(a > b for a, b in zip(orders, orders[1:]))
         assert len(iters) == len(orders) and cycle in ("V", "full")
         self.o, self.U, self.shift, self.cycle = o, U, float(shift), cycle
@@ -161,6 +243,9 @@ class PMultigrid:
                 self.A.append(G)
         self.D = [o.block_diagonal(U, shift)] + [
             diagonal_blocks(self.A[l], o.ne, o.nvar * self.nbs[l]) for l in range(1, self.L + 1)]
+        # optional block ILU(0) preconditioner of the coarsest level's smoother
+        self.ilu = (BlockILU0(self.A[self.L], o.ne, o.nvar * self.nbs[self.L], o.nbr,
+                              greedy_colouring(o.nbr)) if coarse_ilu else None)
 
     def update_fine(self, U, shift, refresh_blocks=True):
         """Preconditioner lagging (Sec. 4, time-step study): the fine level's
@@ -181,6 +266,8 @@ class PMultigrid:
         return self.A[l] @ x
 
     def apply_Minv(self, l, x):
+        if l == self.L and self.ilu is not None:
+            return self.ilu.solve(x)
         return block_solve(self.D[l], x.reshape(self.o.ne, -1)).reshape(-1)
 
     def smooth(self, l, g, x0):

@@ -208,6 +208,38 @@ def test_lagged_hierarchy_keeps_the_coarse_solve_and_follows_the_fine_operator()
     assert np.linalg.norm(z - z_ex) <= 1e-8 * np.linalg.norm(z_ex)
 
 
+def test_block_ilu0_reproduces_the_operator_on_its_pattern():
+    """ILU(0): L U agrees with A on every block of the pattern (element and
+    face neighbours) and differs only by the dropped fill; on two elements the
+    pattern is closed under elimination, so the factorisation is exact."""
+    from oracle.pmg import BlockILU0, greedy_colouring
+    mesh, o, U = _state((3, 3, 2), 1, 2)
+    shift = 4.0
+    A = inherited_matrix(o, U, shift, 1)                        # P0 level: m = 5
+    m = o.nvar
+    ilu = BlockILU0(A, o.ne, m, o.nbr, greedy_colouring(o.nbr))
+    L, Uf = ilu.factors()
+    M = L @ Uf
+    mask = np.kron(ilu.pat, np.ones((m, m), dtype=bool))
+    assert np.abs((M - A)[mask]).max() <= 1e-12 * np.abs(A).max()
+    assert np.abs((M - A)[~mask]).max() > 1e-8 * np.abs(A).max()      # fill was dropped
+    r = np.random.default_rng(9).standard_normal(A.shape[0])
+    assert np.allclose(M @ ilu.solve(r), r, rtol=0, atol=1e-10 * np.abs(r).max())
+    mesh2, o2, U2 = _state((2, 1, 1), 1, 2)
+    A2 = inherited_matrix(o2, U2, shift, 4)
+    ilu2 = BlockILU0(A2, o2.ne, o2.nvar * 4, o2.nbr, greedy_colouring(o2.nbr))
+    r2 = np.random.default_rng(10).standard_normal(A2.shape[0])
+    assert np.allclose(ilu2.solve(r2), np.linalg.solve(A2, r2), rtol=1e-10, atol=1e-12)
+
+
+def test_greedy_colouring_is_proper():
+    from oracle.pmg import greedy_colouring
+    mesh, o, U = _state((3, 4, 2), 1, 2)
+    col = greedy_colouring(o.nbr)
+    for e in range(o.ne):
+        assert all(col[n] != col[e] for n in o.nbr[e] if n != e)
+
+
 @pytest.mark.slow
 def test_mg_preconditioned_fgmres_beats_block_jacobi():
     from oracle import fgmres
