@@ -103,7 +103,7 @@ def cpu_baseline(sample_elems=1024):
                       f"({dofs} DOFs), complex-step numpy oracle, {t:.2f} s"}
 
 
-def time_to_tolerance(storage="fp64", precond="bj", fine_precision="fp64", rescale=False):
+def time_to_tolerance(storage="fp64", precond="bj", fine_precision="fp64", rescale=False, coarse_ilu=False):
     """Backward-Euler system of the P4 24^3 workload solved by FGMRES(30) to 1e-8,
     preconditioned by block Jacobi or by the P4/P2/P1 p-multigrid V-cycle
     (GMRES[EWBJ] smoothers 8/8/40, one captured graph per cycle)."""
@@ -122,7 +122,7 @@ def time_to_tolerance(storage="fp64", precond="bj", fine_precision="fp64", resca
     t0 = time.perf_counter()
     if precond == "mg":
         g.mg_setup(w, shift, cfg["mg_orders"], cfg["mg_smooth"], storage=storage, use_graph=True,
-                   fine_precision=fine_precision, rescale=rescale)
+                   fine_precision=fine_precision, rescale=rescale, coarse_ilu=coarse_ilu)
     else:
         g.block_setup(w, shift, storage=storage)
     torch.cuda.synchronize()
@@ -132,7 +132,8 @@ def time_to_tolerance(storage="fp64", precond="bj", fine_precision="fp64", resca
     t2 = time.perf_counter()
     g.close()
     name = (f"p-multigrid V-cycle P4/P2/P1{' rescaled-inherited' if rescale else ''}, GMRES[EWBJ] smoothers "
-            f"8/8/40, {fine_precision} fine operator, " if precond == "mg" else "block Jacobi ") + storage
+            f"8/8/40{' (coarsest: GMRES[block ILU(0)])' if coarse_ilu else ''}, {fine_precision} fine operator, "
+            if precond == "mg" else "block Jacobi ") + storage
     return {"workload": "backward Euler, P4 24^3 hexes, CFL 100, FGMRES(30), " + name,
             "seconds": t2 - t0, "setup_s": t1 - t0, "solve_s": t2 - t1, "iters": st["iters"],
             "converged": bool(st["converged"]), "rel_res_true": st["rel_res_true"], "dt": dt}
@@ -356,6 +357,8 @@ def main():
         res["time_to_tol_pmg_fp32_smoothing"] = time_to_tolerance("fp32", precond="mg", fine_precision="fp32")
         res["time_to_tol_pmg_fp32_rescaled"] = time_to_tolerance("fp32", precond="mg", fine_precision="fp32",
                                                                  rescale=True)
+        res["time_to_tol_pmg_fp32_coarse_ilu"] = time_to_tolerance("fp32", precond="mg", fine_precision="fp32",
+                                                                   coarse_ilu=True)
         res["trajectory_pmg"] = mg_trajectory(4, lag=1)
         res["trajectory_pmg_lag3"] = mg_trajectory(4, lag=3)
         res["trajectory_pmg_full_cycle"] = mg_trajectory(4, lag=1, cycle="full")

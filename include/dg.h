@@ -240,6 +240,15 @@ typedef struct {
                            inherited operator is scaled by
                            S = k_{l+1}(k_{l+1}+d) / (k_l(k_l+d)) per level
                            (probing costs one more product per column) */
+  int coarse_ilu;       /* 1: the coarsest level's smoother is preconditioned by
+                           a block ILU(0) of its operator in the multicolour
+                           order of the face-neighbour graph (FP64; blocks of
+                           at most 64 rows) instead of block Jacobi; stands in
+                           for the paper's ASM(1,ILU(0)) coarse smoother.  The
+                           elimination updates only diagonal blocks, exact for
+                           face-neighbour graphs without triangles; a mesh with
+                           a periodic direction of three elements is refused
+                           (DG_ERR_ARG) */
 } dg_mg_opts;
 
 /* Builds the hierarchy at state w (device, copied) and shift: runs the fine

@@ -55,7 +55,7 @@ class RosCoeffs(ctypes.Structure):
 class MgOpts(ctypes.Structure):
     _fields_ = [("n_levels", ctypes.c_int), ("orders", ctypes.c_int * 3), ("smooth_iters", ctypes.c_int * 3),
                 ("storage", ctypes.c_int), ("use_graph", ctypes.c_int), ("fine_precision", ctypes.c_int),
-                ("cycle", ctypes.c_int), ("rescale", ctypes.c_int)]
+                ("cycle", ctypes.c_int), ("rescale", ctypes.c_int), ("coarse_ilu", ctypes.c_int)]
 
 
 class SolveStats(ctypes.Structure):

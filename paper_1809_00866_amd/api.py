@@ -130,7 +130,7 @@ class DG:
         return out
 
     def mg_setup(self, w, shift, orders, smooth_iters, storage="fp64", use_graph=True, fine_precision="fp64",
-                 cycle="v", rescale=False):
+                 cycle="v", rescale=False, coarse_ilu=False):
         """p-multigrid hierarchy at (w, shift); orders[0] must be the context's order;
         cycle "v" (Alg. vcic) or "full" (Alg. fullvcic)."""
         if cycle not in ("v", "full"):
@@ -142,7 +142,7 @@ class DG:
         o = L.MgOpts(len(orders), (ctypes.c_int * 3)(*(orders + [0] * (3 - len(orders)))),
                      (ctypes.c_int * 3)(*(smooth_iters + [0] * (3 - len(orders)))), _STORAGE[storage],
                      int(bool(use_graph)), _STORAGE[fine_precision], L.DG_MG_FULL if cycle == "full" else L.DG_MG_V,
-                     int(bool(rescale)))
+                     int(bool(rescale)), int(bool(coarse_ilu)))
         self.mg_levels = [(self.ne * self.nv * _nb(k, self.dim)) for k in orders]
         L.check(self.lib.dg_mg_setup(self.ctx, _ptr(w), float(shift), ctypes.byref(o), _stream()), "dg_mg_setup")
 

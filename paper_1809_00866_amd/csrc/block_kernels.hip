@@ -315,6 +315,116 @@ unsigned grid_for(int64_t n) {
   return (unsigned)g;
 }
 
+// ---------------------------------------------------------------- block ILU(0)
+// Block ILU(0) of a level operator stored block-sparse (B[s][K], s = 0 the
+// element's own block, s = 1..nf its face neighbours, column-major m x m),
+// in the multicolour order of the face-neighbour graph: colours in order, and
+// within a colour no two elements couple.  On a lattice no two neighbours of
+// an element are neighbours of each other, so the only entries that the
+// elimination changes inside the pattern are the diagonal blocks:
+//   D'_K = D_K - sum_{J ~ K, colour(J) < colour(K)} A_KJ D'_J^{-1} A_JK,
+// with A_KJ the sum of K's blocks that point to J (a face neighbour reached
+// through two faces, or the element itself through a periodic face of a
+// one-element direction, are summed; self couplings belong to D_K).
+// One workgroup per element of colour q; D'_K^{-1} (FP64) is written to Dinv.
+__global__ __launch_bounds__(256, 1) void k_ilu_factor(const double* __restrict__ B, const int64_t* __restrict__ nbr,
+                                                       const int* __restrict__ color, int q, int nf, int m,
+                                                       int64_t ne, double* __restrict__ Dinv, int* __restrict__ info) {
+  const int64_t K = blockIdx.x;
+  if (color[K] != q) return;  // uniform in the workgroup
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* Dp = reinterpret_cast<double*>(smem);
+  double* T1 = Dp + m * m;  // A_JK
+  double* T2 = T1 + m * m;  // A_KJ
+  double* X = T2 + m * m;   // D'_J^{-1} A_JK
+  __shared__ double rk2[2][256], ro2[2][256];
+  __shared__ double wv[2][4], wp[2][4];
+  __shared__ int wi[2][4], ipiv[256], bad;
+  const int tid = threadIdx.x;
+  const int mm = m * m;
+  if (tid == 0) bad = 0;
+  for (int i = tid; i < mm; i += 256) {
+    double v = B[(size_t)K * mm + i];
+    for (int t = 1; t <= nf; ++t)
+      if (nbr[(size_t)(t - 1) * ne + K] == K) v += B[((size_t)t * ne + K) * mm + i];
+    Dp[i] = v;
+  }
+  for (int t = 1; t <= nf; ++t) {
+    const int64_t J = nbr[(size_t)(t - 1) * ne + K];
+    if (J == K || color[J] >= q) continue;
+    bool dup = false;
+    for (int t0 = 1; t0 < t; ++t0) dup = dup || nbr[(size_t)(t0 - 1) * ne + K] == J;
+    if (dup) continue;
+    __syncthreads();  // previous products done with T1, T2, X
+    for (int i = tid; i < mm; i += 256) {
+      double a = 0.0, b = 0.0;
+      for (int u = 1; u <= nf; ++u) {
+        if (nbr[(size_t)(u - 1) * ne + J] == K) a += B[((size_t)u * ne + J) * mm + i];
+        if (nbr[(size_t)(u - 1) * ne + K] == J) b += B[((size_t)u * ne + K) * mm + i];
+      }
+      T1[i] = a;
+      T2[i] = b;
+    }
+    __syncthreads();
+    const double* DJ = Dinv + (size_t)J * mm;
+    for (int i = tid; i < mm; i += 256) {  // X(r, c) = sum_k D'_J^{-1}(r, k) A_JK(k, c)
+      const int r = i % m, cc = i / m;
+      double s = 0.0;
+      for (int k = 0; k < m; ++k) s = fma(DJ[(size_t)k * m + r], T1[cc * m + k], s);
+      X[i] = s;
+    }
+    __syncthreads();
+    for (int i = tid; i < mm; i += 256) {  // D' -= A_KJ X
+      const int r = i % m, cc = i / m;
+      double s = 0.0;
+      for (int k = 0; k < m; ++k) s = fma(T2[k * m + r], X[cc * m + k], s);
+      Dp[i] -= s;
+    }
+  }
+  __syncthreads();
+  double rr[1] = {0.0};
+  gauss_jordan_rows<double, 0>(Dp, m, m, m, rr, rk2, ro2, wv, wi, wp, ipiv, &bad);
+  __syncthreads();
+  for (int i = tid; i < mm; i += 256) Dinv[(size_t)K * mm + i] = Dp[i];
+  if (tid == 0 && bad) info[0] = 1;
+}
+
+// One sweep over the elements of colour q (one wave per element, thread =
+// row).  Forward: z_K = D'_K^{-1} (r_K - sum_{earlier colours} A_K,t z_J);
+// backward: z_K -= D'_K^{-1} sum_{later colours} A_K,t z_J.
+__global__ __launch_bounds__(64) void k_ilu_sweep(const double* __restrict__ B, const int64_t* __restrict__ nbr,
+                                                  const int* __restrict__ color, int q, int forward, int nf, int m,
+                                                  int64_t ne, const double* __restrict__ Dinv,
+                                                  const double* __restrict__ r, double* __restrict__ z) {
+  const int64_t K = blockIdx.x;
+  if (color[K] != q) return;
+  __shared__ double y[64];
+  const int row = threadIdx.x;
+  const int mm = m * m;
+  double acc = (forward && row < m) ? r[(size_t)row * ne + K] : 0.0;
+  for (int t = 1; t <= nf; ++t) {
+    const int64_t J = nbr[(size_t)(t - 1) * ne + K];
+    if (J == K) continue;
+    const int cj = color[J];
+    if (forward ? cj >= q : cj <= q) continue;
+    if (row < m) {
+      const double* BK = B + ((size_t)t * ne + K) * mm;
+      for (int j = 0; j < m; ++j) acc = fma(-BK[(size_t)j * m + row], z[(size_t)j * ne + J], acc);
+    }
+  }
+  y[row] = acc;
+  __syncthreads();
+  if (row < m) {
+    const double* DK = Dinv + (size_t)K * mm;
+    double s = 0.0;
+    for (int j = 0; j < m; ++j) s = fma(DK[(size_t)j * m + row], y[j], s);
+    if (forward)
+      z[(size_t)row * ne + K] = s;
+    else
+      z[(size_t)row * ne + K] += s;
+  }
+}
+
 }  // namespace
 
 hipError_t launch_probe_vector(double* P, const int* color, int col, int l, int nb, int nv, int64_t ne,
@@ -371,6 +481,26 @@ hipError_t launch_block_invert(int storage, double* D64, int ldd, void* Dout, in
     return hipGetLastError();
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_ilu_factor(const double* B, const int64_t* nbr, const int* color, int ncolor, int nf, int m,
+                             int64_t ne, double* Dinv, int* info, hipStream_t s) {
+  if (m < 1 || m > 64 || ncolor < 1 || ne < 1) return hipErrorInvalidValue;
+  const size_t lds = (size_t)4 * m * m * sizeof(double);
+  hipFuncSetAttribute((const void*)k_ilu_factor, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  for (int q = 0; q < ncolor; ++q)
+    k_ilu_factor<<<(unsigned)ne, 256, lds, s>>>(B, nbr, color, q, nf, m, ne, Dinv, info);
+  return hipGetLastError();
+}
+
+hipError_t launch_ilu_apply(const double* B, const int64_t* nbr, const int* color, int ncolor, int nf, int m,
+                            int64_t ne, const double* Dinv, const double* r, double* z, hipStream_t s) {
+  if (m < 1 || m > 64 || ncolor < 1 || ne < 1 || r == z) return hipErrorInvalidValue;
+  for (int q = 0; q < ncolor; ++q)
+    k_ilu_sweep<<<(unsigned)ne, 64, 0, s>>>(B, nbr, color, q, 1, nf, m, ne, Dinv, r, z);
+  for (int q = ncolor - 1; q >= 0; --q)
+    k_ilu_sweep<<<(unsigned)ne, 64, 0, s>>>(B, nbr, color, q, 0, nf, m, ne, Dinv, r, z);
+  return hipGetLastError();
 }
 
 hipError_t launch_block_apply(int storage, const void* Dinv, int m, int64_t ne, const double* r, double* z,

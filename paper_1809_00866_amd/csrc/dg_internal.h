@@ -130,6 +130,12 @@ hipError_t launch_extract_column(const double* Jv, const int* color, int col, in
 constexpr int block_ld(int m) { return (m + 7) / 8 * 8; }
 hipError_t launch_block_invert(int storage, double* D64, int ldd, void* Dout, int m, int64_t ne, int* info,
                                hipStream_t s);
+// Multicolour block ILU(0) of a block-sparse level operator (m <= 64): factor
+// (one launch per colour; D'^{-1} FP64, [ne][m*m]) and apply z = (L U)^{-1} r.
+hipError_t launch_ilu_factor(const double* B, const int64_t* nbr, const int* color, int ncolor, int nf, int m,
+                             int64_t ne, double* Dinv, int* info, hipStream_t s);
+hipError_t launch_ilu_apply(const double* B, const int64_t* nbr, const int* color, int ncolor, int nf, int m,
+                            int64_t ne, const double* Dinv, const double* r, double* z, hipStream_t s);
 hipError_t launch_block_apply(int storage, const void* Dinv, int m, int64_t ne, const double* r, double* z,
                               hipStream_t s);
 

@@ -33,6 +33,7 @@ struct MgLevel {
   int64_t n = 0;               // level vector length ne*nv*nb
   double* B = nullptr;         // coarse levels: BSR blocks [nslot][ne][m*m]
   double* Bs = nullptr;        // rescaled hierarchy, level 1: its stabilisation part (same layout)
+  double* Ilu = nullptr;       // coarsest level with block ILU(0): D'^{-1} [ne][m*m] (FP64)
   void* Dinv = nullptr;        // coarse levels: block-Jacobi inverses
   double* g = nullptr;         // right-hand side
   double* x = nullptr;         // iterate
@@ -49,6 +50,7 @@ struct MgState {
   bool fine_f32 = false;  // FP32 fine-level operator inside the cycle
   bool full = false;      // Alg. fullvcic instead of Alg. vcic
   bool rescale = false;   // rescaled-inherited coarse operators (App. A)
+  bool coarse_ilu = false;  // block ILU(0) preconditions the coarsest smoother
   double shift = 0.0;
   bool use_graph = false, ready = false;
   MgLevel lev[3];
@@ -72,6 +74,7 @@ void mg_destroy(MgState* M) {
   for (auto& L : M->lev) {
     dfree(L.B);
     dfree(L.Bs);
+    dfree(L.Ilu);
     dfree(L.Dinv);
     dfree(L.g);
     dfree(L.x);
@@ -114,6 +117,9 @@ dg_status level_G(dg_context* c, MgState* M, int l, const double* x, double* y, 
 dg_status level_Minv(dg_context* c, MgState* M, int l, const double* r, double* z, hipStream_t s) {
   if (l == 0) {
     HIPCHK(dgk::launch_block_apply(c->blk_storage, c->d_Dinv, c->nv * c->nb, c->ne, r, z, s));
+  } else if (l == M->nlev - 1 && M->coarse_ilu) {
+    const MgLevel& L = M->lev[l];
+    HIPCHK(dgk::launch_ilu_apply(L.B, c->mesh.nbr, c->d_color, c->ncolor, 2 * c->dim, L.m, c->ne, L.Ilu, r, z, s));
   } else {
     const MgLevel& L = M->lev[l];
     HIPCHK(dgk::launch_block_apply(M->storage, L.Dinv, L.m, c->ne, r, z, s));
@@ -341,6 +347,9 @@ dg_status dg_mg_setup(dg_context* c, const double* w, double shift, const dg_mg_
     return fail(DG_ERR_ARG, "fine_precision must be DG_FP64 or DG_FP32");
   if (o->cycle != DG_MG_V && o->cycle != DG_MG_FULL) return fail(DG_ERR_ARG, "cycle must be DG_MG_V or DG_MG_FULL");
   if (o->rescale != 0 && o->rescale != 1) return fail(DG_ERR_ARG, "rescale must be 0 or 1");
+  if (o->coarse_ilu != 0 && o->coarse_ilu != 1) return fail(DG_ERR_ARG, "coarse_ilu must be 0 or 1");
+  if (o->coarse_ilu && c->nv * binom(o->orders[o->n_levels - 1] + c->dim, c->dim) > 64)
+    return fail(DG_ERR_ARG, "block ILU(0) needs coarsest blocks of at most 64 rows");
   if (o->fine_precision == DG_FP32 && !(c->use_mfma && c->d_mtab_f))
     return fail(DG_ERR_ARG, "the FP32 fine operator needs a 3D P2-P4 configuration with MFMA kernels");
   hipStream_t s = (hipStream_t)stream;
@@ -368,6 +377,7 @@ dg_status dg_mg_setup(dg_context* c, const double* w, double shift, const dg_mg_
   M->fine_f32 = o->fine_precision == DG_FP32;
   M->full = o->cycle == DG_MG_FULL;
   M->rescale = o->rescale != 0;
+  M->coarse_ilu = o->coarse_ilu != 0;
   for (int l = 0; l < M->nlev; ++l) {
     MgLevel& L = M->lev[l];
     L.order = o->orders[l];
@@ -394,6 +404,21 @@ dg_status dg_mg_setup(dg_context* c, const double* w, double shift, const dg_mg_
   if (hipMemcpy(nbrT.data(), c->d_nbr, nbrT.size() * sizeof(int64_t), hipMemcpyDeviceToHost) != hipSuccess ||
       hipMemcpy(x0.data(), c->d_x0, x0.size() * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
     return bail(fail(DG_ERR_HIP, "mesh download failed"));
+  if (M->coarse_ilu) {
+    // the diagonal-only elimination of the block ILU(0) is exact on graphs
+    // without triangles (two neighbours of an element that are neighbours
+    // of each other: a periodic direction of three elements)
+    for (int64_t K = 0; K < ne; ++K)
+      for (int a = 0; a < nf; ++a)
+        for (int b = 0; b < nf; ++b) {
+          const int64_t J = nbrT[(size_t)a * ne + K], L = nbrT[(size_t)b * ne + K];
+          if (J == K || L == K || J == L) continue;
+          for (int t = 0; t < nf; ++t)
+            if (nbrT[(size_t)t * ne + J] == L)
+              return bail(fail(DG_ERR_ARG, "block ILU(0) needs a face-neighbour graph without triangles "
+                                           "(no periodic direction of exactly three elements)"));
+        }
+  }
   std::vector<int> col2 = distance2_colouring(nbrT, x0, dim, ne, c->mesh.h, &M->ncolor2);
   if ((st = dalloc(&M->color2, (size_t)ne)) != DG_OK) return bail(st);
   if (hipMemcpy(M->color2, col2.data(), ne * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
@@ -468,6 +493,18 @@ dg_status dg_mg_setup(dg_context* c, const double* w, double shift, const dg_mg_
     HIPCHK(hipMemcpyAsync(&bad, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (bad) return bail(fail(DG_ERR_SINGULAR_BLOCK, "a coarse diagonal block has a zero or non-finite pivot"));
+  }
+  // block ILU(0) of the coarsest level (colour by colour)
+  if (M->coarse_ilu) {
+    MgLevel& C = M->lev[M->nlev - 1];
+    if ((st = dalloc(&C.Ilu, (size_t)ne * C.m * C.m)) != DG_OK) return bail(st);
+    int zero = 0;
+    HIPCHK(hipMemcpyAsync(c->d_flag, &zero, sizeof(int), hipMemcpyHostToDevice, s));
+    HIPCHK(dgk::launch_ilu_factor(C.B, c->mesh.nbr, c->d_color, c->ncolor, nf, C.m, ne, C.Ilu, c->d_flag, s));
+    int bad = 0;
+    HIPCHK(hipMemcpyAsync(&bad, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (bad) return bail(fail(DG_ERR_SINGULAR_BLOCK, "a block ILU(0) pivot block is singular"));
   }
   // autotune the BSR apply workgroup size per coarse level
   {
