@@ -12,7 +12,7 @@ import numpy as np
 
 
 def fgmres(apply_A, b, apply_M=None, x0=None, restart=30, rtol=1e-8, max_iter=1000,
-           breakdown_tol=1e-14):
+           breakdown_tol=1e-14, orth="cgs2"):
     b = np.asarray(b, dtype=np.float64)
     n = b.size
     x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64)
@@ -46,11 +46,17 @@ def fgmres(apply_A, b, apply_M=None, x0=None, restart=30, rtol=1e-8, max_iter=10
             Z[j] = M(V[j])
             w = apply_A(Z[j])
             w0 = np.linalg.norm(w)
-            h = V[:j + 1] @ w
-            w = w - V[:j + 1].T @ h
-            h2 = V[:j + 1] @ w
-            w = w - V[:j + 1].T @ h2
-            h = h + h2
+            if orth == "mgs":                 # modified Gram-Schmidt: one vector at a time
+                h = np.zeros(j + 1)
+                for i in range(j + 1):
+                    h[i] = V[i] @ w
+                    w = w - h[i] * V[i]
+            else:                             # classical Gram-Schmidt, one re-orthogonalisation
+                h = V[:j + 1] @ w
+                w = w - V[:j + 1].T @ h
+                h2 = V[:j + 1] @ w
+                w = w - V[:j + 1].T @ h2
+                h = h + h2
             hn = np.linalg.norm(w)
             H[:j + 1, j] = h
             H[j + 1, j] = hn

@@ -29,6 +29,21 @@ def test_fgmres_matches_dense_solve_and_is_monotone():
     assert np.all(np.diff(h) <= 1e-12 * h[0])
 
 
+def test_fgmres_modified_gram_schmidt_matches_the_dense_solve_and_cgs2():
+    """Both orthogonalisations span the same Krylov spaces: the same iteration
+    count and solution (to the tolerance), and the dense solution."""
+    o, U, A = _dense_G()
+    b = np.random.default_rng(2).standard_normal(A.shape[0])
+    x1, i1 = fgmres(lambda v: A @ v, b, restart=20, rtol=1e-10, max_iter=2000, orth="mgs")
+    x2, i2 = fgmres(lambda v: A @ v, b, restart=20, rtol=1e-10, max_iter=2000, orth="cgs2")
+    assert i1["converged"] and i2["converged"] and abs(i1["iters"] - i2["iters"]) <= 1
+    assert np.linalg.norm(b - A @ x1) <= 1e-10 * np.linalg.norm(b)
+    xd = np.linalg.solve(A, b)
+    assert np.linalg.norm(x1 - xd) <= 1e-8 * np.linalg.norm(xd) * np.linalg.cond(A) ** 0.5
+    h1, h2 = np.array(i1["history"][:20]), np.array(i2["history"][:20])
+    assert np.allclose(h1, h2, rtol=1e-8, atol=1e-12 * h1[0])
+
+
 def test_fgmres_exact_preconditioner_one_iteration():
     _, _, A = _dense_G()
     Ainv = np.linalg.inv(A)
