@@ -61,6 +61,7 @@ enum { DG_FLUX_LF = 0, DG_FLUX_ROE = 1 };           /* convective numerical flux
 enum { DG_JVP_EXACT = 0, DG_JVP_FD = 1, DG_JVP_EXACT_FP32 = 2, DG_JVP_STAB = 3 };  /* Jv mode */
 enum { DG_FP64 = 0, DG_FP32 = 1, DG_BF16 = 2 };     /* block-factor storage */
 enum { DG_PREC_NONE = 0, DG_PREC_BJ = 1, DG_PREC_MG = 2, DG_PREC_MLP = 3 };  /* FGMRES preconditioner */
+enum { DG_ORTH_CGS2 = 0, DG_ORTH_MGS = 1 };         /* FGMRES orthogonalisation */
 enum { DG_MG_V = 0, DG_MG_FULL = 1 };               /* p-multigrid cycle (Algs. vcic, fullvcic) */
 
 /* Discretisation parameters.
@@ -162,6 +163,9 @@ typedef struct {
                       factor (|g_j|/||r_0||)^(1/j) after judge_after
                       iterations exceeds rho_ref (e.g. block Jacobi's) */
   int judge_after; /* iterations before that check (<= 0 selects 5) */
+  int orth;        /* Arnoldi: DG_ORTH_CGS2 (classical Gram-Schmidt with one
+                      re-orthogonalisation, two fused passes over the basis) or
+                      DG_ORTH_MGS (modified Gram-Schmidt, one vector at a time) */
 } dg_solve_opts;
 
 typedef struct {

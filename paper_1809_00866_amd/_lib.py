@@ -17,6 +17,7 @@ DG_JVP_EXACT, DG_JVP_FD, DG_JVP_EXACT_FP32, DG_JVP_STAB = 0, 1, 2, 3
 DG_FP64, DG_FP32, DG_BF16 = 0, 1, 2
 DG_PREC_NONE, DG_PREC_BJ, DG_PREC_MG, DG_PREC_MLP = 0, 1, 2, 3
 DG_MG_V, DG_MG_FULL = 0, 1
+DG_ORTH_CGS2, DG_ORTH_MGS = 0, 1
 
 EXPORTED = ["dg_create", "dg_destroy", "dg_ndof", "dg_nbasis", "dg_nvar", "dg_nq", "dg_volume_points",
             "dg_project", "dg_residual", "dg_residual_fp32", "dg_jvp", "dg_block_precond_setup", "dg_block_precond_apply",
@@ -40,7 +41,7 @@ class DGMesh(ctypes.Structure):
 class SolveOpts(ctypes.Structure):
     _fields_ = [("restart", ctypes.c_int), ("max_iter", ctypes.c_int), ("rtol", ctypes.c_double),
                 ("precond", ctypes.c_int), ("jvp_mode", ctypes.c_int), ("rho_ref", ctypes.c_double),
-                ("judge_after", ctypes.c_int)]
+                ("judge_after", ctypes.c_int), ("orth", ctypes.c_int)]
 
 
 ROS_MAX_STAGES = 6

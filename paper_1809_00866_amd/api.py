@@ -16,6 +16,7 @@ _BASIS = {"P": L.DG_BASIS_PK, "Q": L.DG_BASIS_QK}
 _MODE = {"exact": L.DG_JVP_EXACT, "fd": L.DG_JVP_FD, "exact_fp32": L.DG_JVP_EXACT_FP32, "stab": L.DG_JVP_STAB}
 _STORAGE = {"fp64": L.DG_FP64, "fp32": L.DG_FP32, "bf16": L.DG_BF16}
 _PREC = {"none": L.DG_PREC_NONE, "bj": L.DG_PREC_BJ, "mg": L.DG_PREC_MG, "mlp": L.DG_PREC_MLP}
+_ORTH = {"cgs2": L.DG_ORTH_CGS2, "mgs": L.DG_ORTH_MGS}
 
 
 def _stream():
@@ -244,11 +245,12 @@ class DG:
         return out
 
     def fgmres(self, w, shift, b, x=None, restart=30, max_iter=1000, rtol=1e-8, precond="bj", jvp_mode="exact",
-               rho_ref=0.0, judge_after=5):
+               rho_ref=0.0, judge_after=5, orth="cgs2"):
         self._vec(w, "w")
         self._vec(b, "b")
         x = torch.zeros_like(b) if x is None else self._vec(x, "x")
-        opts = L.SolveOpts(restart, max_iter, rtol, _PREC[precond], _MODE[jvp_mode], float(rho_ref), int(judge_after))
+        opts = L.SolveOpts(restart, max_iter, rtol, _PREC[precond], _MODE[jvp_mode], float(rho_ref), int(judge_after),
+                           _ORTH[orth])
         st = L.SolveStats()
         status = self.lib.dg_fgmres_solve(self.ctx, _ptr(w), float(shift), _ptr(b), _ptr(x), ctypes.byref(opts),
                                           ctypes.byref(st), _stream())
@@ -272,7 +274,7 @@ class DG:
             for o in range(s):
                 k.a[s][o] = float(coeffs["a"][s][o])
                 k.c[s][o] = float(coeffs["c"][s][o])
-        opts = L.SolveOpts(restart, max_iter, rtol, _PREC[precond], _MODE[jvp_mode], 0.0, 0)
+        opts = L.SolveOpts(restart, max_iter, rtol, _PREC[precond], _MODE[jvp_mode], 0.0, 0, L.DG_ORTH_CGS2)
         st = L.SolveStats()
         status = self.lib.dg_rosenbrock_step(self.ctx, _ptr(w), float(dt), ctypes.byref(k), ctypes.byref(opts),
                                              _ptr(out), ctypes.byref(st), _stream())

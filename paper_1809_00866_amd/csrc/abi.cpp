@@ -511,6 +511,8 @@ dg_status dg_fgmres_solve(dg_context* c, const double* w, double shift, const do
   if (opts->precond == DG_PREC_MG && !mg_ready(c->mg)) return fail(DG_ERR_STATE, "p-multigrid not set up");
   if (opts->jvp_mode != DG_JVP_EXACT && opts->jvp_mode != DG_JVP_FD)
     return fail(DG_ERR_ARG, "the solve's operator is the exact FP64 or the finite-difference Jv");
+  if (opts->orth != DG_ORTH_CGS2 && opts->orth != DG_ORTH_MGS) return fail(DG_ERR_ARG, "unknown orthogonalisation");
+  const bool mgs = opts->orth == DG_ORTH_MGS;
   const double rtol = opts->rtol > 0.0 ? opts->rtol : 1e-8;
   const int max_iter = opts->max_iter > 0 ? opts->max_iter : 1000;
   hipStream_t s = (hipStream_t)stream;
@@ -599,12 +601,20 @@ dg_status dg_fgmres_solve(dg_context* c, const double* w, double shift, const do
       if ((st = norm2(c, Wn, dS + 2, s)) != DG_OK) return st;
       {
         ProfScope ps(c, "arnoldi", s);
-        HIPCHK(dgk::launch_mdot(V, j + 1, n, Wn, c->d_red, s));
-        HIPCHK(dgk::launch_msum(c->d_red, j + 1, dS + 16, s));
-        HIPCHK(dgk::launch_mupdate(V, j + 1, n, dS + 16, Wn, s));
-        HIPCHK(dgk::launch_mdot(V, j + 1, n, Wn, c->d_red, s));
-        HIPCHK(dgk::launch_msum(c->d_red, j + 1, dS + 80, s));
-        HIPCHK(dgk::launch_mupdate(V, j + 1, n, dS + 80, Wn, s));
+        if (mgs) {  // modified Gram-Schmidt: one basis vector at a time
+          for (int i = 0; i <= j; ++i) {
+            HIPCHK(dgk::launch_mdot(V + (size_t)i * n, 1, n, Wn, c->d_red, s));
+            HIPCHK(dgk::launch_msum(c->d_red, 1, dS + 16 + i, s));
+            HIPCHK(dgk::launch_mupdate(V + (size_t)i * n, 1, n, dS + 16 + i, Wn, s));
+          }
+        } else {  // classical Gram-Schmidt with one re-orthogonalisation
+          HIPCHK(dgk::launch_mdot(V, j + 1, n, Wn, c->d_red, s));
+          HIPCHK(dgk::launch_msum(c->d_red, j + 1, dS + 16, s));
+          HIPCHK(dgk::launch_mupdate(V, j + 1, n, dS + 16, Wn, s));
+          HIPCHK(dgk::launch_mdot(V, j + 1, n, Wn, c->d_red, s));
+          HIPCHK(dgk::launch_msum(c->d_red, j + 1, dS + 80, s));
+          HIPCHK(dgk::launch_mupdate(V, j + 1, n, dS + 80, Wn, s));
+        }
       }
       if ((st = norm2(c, Wn, dS + 3, s)) != DG_OK) return st;
       if ((st = readback(dS, 144)) != DG_OK) return st;
@@ -612,7 +622,7 @@ dg_status dg_fgmres_solve(dg_context* c, const double* w, double shift, const do
       const double w0 = hp[2], hn = hp[3];
       if (!std::isfinite(hn)) return fail(DG_ERR_NONFINITE, "Arnoldi vector is not finite");
       double* Hc = &H[(size_t)j * (m + 1)];  // column j, rows 0..j+1
-      for (int i = 0; i <= j; ++i) Hc[i] = hp[16 + i] + hp[80 + i];
+      for (int i = 0; i <= j; ++i) Hc[i] = mgs ? hp[16 + i] : hp[16 + i] + hp[80 + i];
       Hc[j + 1] = hn;
       for (int i = 0; i < j; ++i) {
         const double t = cs[i] * Hc[i] + sn[i] * Hc[i + 1];

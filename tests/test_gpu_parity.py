@@ -158,6 +158,24 @@ def test_fgmres_true_residual_with_oracle_operator(precond):
     assert res <= 1e-9
 
 
+def test_fgmres_modified_gram_schmidt():
+    """orth="mgs": the same Krylov spaces as CGS2 (iteration counts within one),
+    the true residual checked with the oracle operator."""
+    _say("fgmres mgs")
+    o, g, U, w = make_case((3, 3, 3), 2, "P", 3)
+    shift = 40.0
+    B = np.random.default_rng(7).standard_normal(U.shape)
+    b = torch.tensor(o.to_flat(B), device="cuda")
+    g.block_setup(w, shift)
+    x1, s1 = g.fgmres(w, shift, b, restart=20, rtol=1e-10, max_iter=2000, precond="bj", orth="mgs")
+    x2, s2 = g.fgmres(w, shift, b, restart=20, rtol=1e-10, max_iter=2000, precond="bj", orth="cgs2")
+    assert s1["converged"] == 1 and abs(s1["iters"] - s2["iters"]) <= 1
+    X = o.from_flat(x1.cpu().numpy())
+    res = np.linalg.norm(o.to_flat(o.operator(U, X, shift)) - o.to_flat(B)) / np.linalg.norm(B)
+    assert res <= 1e-9
+    assert rel(x1.cpu().numpy(), x2.cpu().numpy()) <= 1e-8
+
+
 @pytest.mark.parametrize("storage", ["fp32", "bf16"])
 def test_fgmres_reduced_precision_blocks_reach_fp64_tolerance(storage):
     """Reduced-precision block factors change only the preconditioner: the FP64
