@@ -103,22 +103,32 @@ def cpu_baseline(sample_elems=1024):
                       f"({dofs} DOFs), complex-step numpy oracle, {t:.2f} s"}
 
 
-def time_to_tolerance(storage="fp64", precond="bj", fine_precision="fp64", rescale=False, coarse_ilu=False):
+def time_to_tolerance(storage="fp64", precond="bj", fine_precision="fp64", rescale=False, coarse_ilu=False,
+                      preset="cfg3"):
     """Backward-Euler system of the P4 24^3 workload solved by FGMRES(30) to 1e-8,
     preconditioned by block Jacobi or by the P4/P2/P1 p-multigrid V-cycle
     (GMRES[EWBJ] smoothers 8/8/40, one captured graph per cycle)."""
     import torch
     import synth
     from paper_1809_00866_amd import DG
-    cfg, mesh, fld = synth.preset("cfg3")
+    cfg, mesh, fld = synth.preset(preset)
+    tc = time.perf_counter()
     g = DG(mesh, cfg["order"], basis=cfg["space"], nq1d=cfg["nq1d"], flux="roe", mu=cfg["mu"])
+    t_create = time.perf_counter() - tc
     w = g.project_field(fld)
     smax = g.max_wave_speed(w)
     h = float(np.min(mesh["h"]))
     dt = cfg["cfl"] * h / ((2 * cfg["order"] + 1) * smax)
     shift = 1.0 / dt
     b = -g.residual(w)
+    for _ in range(3):
+        g.jvp(w, b, shift=shift)
     torch.cuda.synchronize()
+    tj = time.perf_counter()
+    for _ in range(10):
+        g.jvp(w, b, shift=shift)
+    torch.cuda.synchronize()
+    jv_ms = (time.perf_counter() - tj) * 100.0
     t0 = time.perf_counter()
     if precond == "mg":
         g.mg_setup(w, shift, cfg["mg_orders"], cfg["mg_smooth"], storage=storage, use_graph=True,
@@ -134,7 +144,9 @@ def time_to_tolerance(storage="fp64", precond="bj", fine_precision="fp64", resca
     name = (f"p-multigrid V-cycle P4/P2/P1{' rescaled-inherited' if rescale else ''}, GMRES[EWBJ] smoothers "
             f"8/8/40{' (coarsest: GMRES[block ILU(0)])' if coarse_ilu else ''}, {fine_precision} fine operator, "
             if precond == "mg" else "block Jacobi ") + storage
-    return {"workload": "backward Euler, P4 24^3 hexes, CFL 100, FGMRES(30), " + name,
+    mesh_name = "P4 24^3 hexes" if preset == "cfg3" else "P4 24^3 curved hexes (vertices moved by +-0.1h)"
+    return {"workload": f"backward Euler, {mesh_name}, CFL 100, FGMRES(30), " + name, "create_s": t_create,
+            "jv_ms": jv_ms,
             "seconds": t2 - t0, "setup_s": t1 - t0, "solve_s": t2 - t1, "iters": st["iters"],
             "converged": bool(st["converged"]), "rel_res_true": st["rel_res_true"], "dt": dt}
 
@@ -359,6 +371,8 @@ def main():
                                                                  rescale=True)
         res["time_to_tol_pmg_fp32_coarse_ilu"] = time_to_tolerance("fp32", precond="mg", fine_precision="fp32",
                                                                    coarse_ilu=True)
+        res["time_to_tol_pmg_curved"] = time_to_tolerance("fp32", precond="mg", fine_precision="fp64", preset="cfg4")
+        res["time_to_tol_bj_curved"] = time_to_tolerance("fp32", preset="cfg4")
         res["trajectory_pmg"] = mg_trajectory(4, lag=1)
         res["trajectory_pmg_lag3"] = mg_trajectory(4, lag=3)
         res["trajectory_pmg_full_cycle"] = mg_trajectory(4, lag=1, cycle="full")

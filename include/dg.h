@@ -82,9 +82,16 @@ typedef struct {
  *  (v = v0 + 2*v1 + 4*v2, v_i = 0/1 low/high end along axis i), unwrapped
  *  across periodic boundaries.  elem_nbr [n_elem][2*dim]: face neighbours in
  *  the order -x,+x,-y,+y,-z,+z; the +p neighbour's -p neighbour must be the
- *  element itself.  This version requires every element to be the same
- *  axis-aligned box (uniform periodic lattice); other meshes return
- *  DG_ERR_ARG. */
+ *  element itself.  Faces must be conforming: the +p face of an element and
+ *  the -p face of its neighbour have the same corners (up to a periodic
+ *  shift).  Elements are multilinear (Sec. 2.1): when every element is the
+ *  same axis-aligned box (uniform periodic lattice) the affine kernels run;
+ *  otherwise each element carries its own orthonormal basis (Cholesky
+ *  factor of its mass matrix in the reference basis) and the curved FP64
+ *  kernels run.  An element with a non-positive Jacobian determinant at a
+ *  quadrature point returns DG_ERR_ARG.  On curved meshes the FP32
+ *  operator (reduced-precision smoothing) and the learned preconditioner
+ *  are unavailable (DG_ERR_STATE). */
 typedef struct {
   int64_t n_elem;
   const double* elem_xyz;

@@ -30,6 +30,17 @@ void dfree(void* p) {
 
 dg_status eval_residual(dg_context* c, bool jvp, const double* w, const double* v, double shift, double* out,
                         hipStream_t s) {
+  if (c->curved) {
+    {
+      ProfScope ps(c, jvp ? "face_jvp" : "face_res", s);
+      HIPCHK(dgk::launch_face_curved(c->cfg, jvp, w, v, c->ct, c->mesh, c->ph, s));
+    }
+    {
+      ProfScope ps(c, jvp ? "vol_jvp" : "vol_res", s);
+      HIPCHK(dgk::launch_volume_curved(c->cfg, jvp, w, v, c->ct, out, shift, c->mesh, c->ph, s));
+    }
+    return DG_OK;
+  }
   if (c->use_mfma) {
     {
       ProfScope ps(c, jvp ? "grad_jvp" : "grad_res", s);
@@ -84,6 +95,12 @@ dg_status eval_stab(dg_context* c, bool f32, const double* w, const double* v, d
   dgk::Phys ph = c->ph;
   ph.stab_only = 1;
   const double* z = c->d_zero;  // no tangent in the volume terms and the gradients
+  if (c->curved) {
+    if (f32) return fail(DG_ERR_ARG, "the reduced-precision operator needs a 3D P2-P4 lattice configuration");
+    HIPCHK(dgk::launch_face_curved(c->cfg, true, w, v, c->ct, c->mesh, ph, s));
+    HIPCHK(dgk::launch_volume_curved(c->cfg, true, w, z, c->ct, out, 0.0, c->mesh, c->ph, s));
+    return DG_OK;
+  }
   if (f32) {
     if (!c->use_mfma || !c->d_mtab_f || !c->d_Hf || !c->d_Gf)
       return fail(DG_ERR_ARG, "the reduced-precision operator needs a 3D P2-P4 configuration with MFMA kernels");
@@ -162,15 +179,15 @@ dg_status dg_create(const dg_params* prm, const dg_mesh* mesh, dg_context** out)
   for (int i = 0; i < dim; ++i) h[i] = mesh->elem_xyz[(size_t)(1 << i) * dim + i] - mesh->elem_xyz[i];
   for (int i = 0; i < dim; ++i)
     if (!(h[i] > 0.0)) return fail(DG_ERR_ARG, "element 0 is not an axis-aligned box with positive edges");
-  for (int64_t e = 0; e < ne; ++e) {
+  // a uniform axis-aligned lattice takes the affine (MFMA / table) kernels;
+  // any other mesh of multilinear elements takes the curved-element kernels
+  bool lattice = true;
+  for (int64_t e = 0; e < ne && lattice; ++e) {
     const double* X = mesh->elem_xyz + (size_t)e * nvtx * dim;
-    for (int v = 0; v < nvtx; ++v)
+    for (int v = 0; v < nvtx && lattice; ++v)
       for (int i = 0; i < dim; ++i) {
         const double expect = X[i] + (((v >> i) & 1) ? h[i] : 0.0);
-        if (std::fabs(X[(size_t)v * dim + i] - expect) > 1e-10 * h[i])
-          return fail(DG_ERR_ARG, "element " + std::to_string(e) +
-                                      " is not the same axis-aligned box as element 0 (only uniform lattices "
-                                      "are supported)");
+        if (std::fabs(X[(size_t)v * dim + i] - expect) > 1e-10 * h[i]) lattice = false;
       }
   }
   for (int64_t e = 0; e < ne; ++e)
@@ -186,6 +203,14 @@ dg_status dg_create(const dg_params* prm, const dg_mesh* mesh, dg_context** out)
     T = dgh::build_tables(dim, prm->order, prm->basis, prm->nq1d, h);
   } catch (const std::exception& ex) {
     return fail(DG_ERR_ARG, ex.what());
+  }
+  dgh::CurvedHost CH;  // curved (non-lattice) meshes: built before any device work
+  if (!lattice) {
+    try {
+      CH = dgh::build_curved_tables(T, prm->order, mesh->elem_xyz, mesh->elem_nbr, ne);
+    } catch (const std::exception& ex) {
+      return fail(DG_ERR_ARG, ex.what());
+    }
   }
   const int cfg = dgk::config_index(dim, T.nb, prm->nq1d);
   if (cfg < 0)
@@ -241,9 +266,40 @@ dg_status dg_create(const dg_params* prm, const dg_mesh* mesh, dg_context** out)
   c->tb.fWPhi = c->d_tab + off[7];
   c->tb.vXi = c->d_tab + off[8];
 
+  // curved elements: per-element and per-face tables, face outputs
+  if (!lattice) {
+    std::vector<const std::vector<double>*> cp = {&CH.vPhi, &CH.vGPhi, &CH.vW, &CH.vX, &CH.fPhiL, &CH.fPhiR,
+                                                  &CH.fGPhiL, &CH.fGPhiR, &CH.fN, &CH.fW};
+    size_t ctot = 0;
+    for (auto* v : cp) ctot += v->size();
+    if ((st = dalloc(&c->d_curved, ctot)) != DG_OK) return cleanup(st);
+    size_t o = 0;
+    std::vector<double*> dst;
+    for (auto* v : cp) {
+      dst.push_back(c->d_curved + o);
+      if (hipMemcpy(c->d_curved + o, v->data(), v->size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+        return cleanup(fail(DG_ERR_HIP, "curved table upload failed"));
+      o += v->size();
+    }
+    c->ct.vPhi = dst[0];
+    c->ct.vGPhi = dst[1];
+    c->ct.vW = dst[2];
+    c->d_cvX = dst[3];
+    c->ct.fPhiL = dst[4];
+    c->ct.fPhiR = dst[5];
+    c->ct.fGPhiL = dst[6];
+    c->ct.fGPhiR = dst[7];
+    c->ct.fN = dst[8];
+    c->ct.fW = dst[9];
+    const size_t nrho = (size_t)dim * ne * 2 * 2 * c->nv * dim * T.nb, nproj = (size_t)dim * ne * 2 * c->nv * T.nb;
+    if ((st = dalloc(&c->ct.fRho, nrho)) != DG_OK) return cleanup(st);
+    if ((st = dalloc(&c->ct.fProj, nproj)) != DG_OK) return cleanup(st);
+    c->curved = true;
+  }
+
   // MFMA operand tables (3D configurations with MFMA kernels)
   const char* variant = std::getenv("DG_KERNEL_VARIANT");
-  const bool want_mfma = !(variant && std::strcmp(variant, "reference") == 0);
+  const bool want_mfma = lattice && !(variant && std::strcmp(variant, "reference") == 0);
   if (want_mfma && dgk::has_mfma(cfg)) {
     dgh::MfmaHost M = dgh::build_mfma_tables(T);
     std::vector<const std::vector<double>*> mp = {&M.vA, &M.pA, &M.fA, &M.tA, &M.lA};
@@ -369,6 +425,9 @@ void dg_destroy(dg_context* c) {
   dfree(c->d_D64);
   dfree(c->d_ros);
   dfree(c->d_zero);
+  dfree(c->d_curved);
+  dfree(c->ct.fRho);
+  dfree(c->ct.fProj);
   if (c->d_Dinv != c->d_D64) dfree(c->d_Dinv);
   dfree(c->d_V);
   dfree(c->d_Z);
@@ -385,12 +444,21 @@ int dg_nq(const dg_context* c) { return c ? c->nq : -1; }
 
 dg_status dg_volume_points(dg_context* c, double* xyz, void* stream) {
   if (!c || !xyz) return fail(DG_ERR_ARG, "null argument");
+  if (c->curved) {
+    HIPCHK(hipMemcpyAsync(xyz, c->d_cvX, (size_t)c->dim * c->nq * c->ne * sizeof(double), hipMemcpyDeviceToDevice,
+                          (hipStream_t)stream));
+    return DG_OK;
+  }
   HIPCHK(dgk::launch_points(c->cfg, xyz, c->tb, c->mesh, (hipStream_t)stream));
   return DG_OK;
 }
 
 dg_status dg_project(dg_context* c, const double* f, double* w, void* stream) {
   if (!c || !f || !w) return fail(DG_ERR_ARG, "null argument");
+  if (c->curved) {
+    HIPCHK(dgk::launch_project_curved(c->cfg, f, w, c->ct, c->ne, (hipStream_t)stream));
+    return DG_OK;
+  }
   HIPCHK(dgk::launch_project(c->cfg, f, w, c->tb, c->mesh, (hipStream_t)stream));
   return DG_OK;
 }
@@ -489,7 +557,10 @@ dg_status dg_max_wave_speed(dg_context* c, const double* w, double* out, void* s
   if (!c || !w || !out) return fail(DG_ERR_ARG, "null argument");
   hipStream_t s = (hipStream_t)stream;
   const int nblk = 1024;
-  HIPCHK(dgk::launch_wave_speed(c->cfg, w, c->d_red, nblk, c->tb, c->mesh, c->ph, s));
+  if (c->curved)
+    HIPCHK(dgk::launch_wave_speed_curved(c->cfg, w, c->d_red, nblk, c->ct, c->mesh, c->ph, s));
+  else
+    HIPCHK(dgk::launch_wave_speed(c->cfg, w, c->d_red, nblk, c->tb, c->mesh, c->ph, s));
   HIPCHK(dgk::launch_max_partials(c->d_red, nblk, c->d_scal + 200, s));
   HIPCHK(hipMemcpyAsync(c->h_pin, c->d_scal + 200, sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));

@@ -62,6 +62,10 @@ struct dg_context {
   dgk::Tables tb{};
   dgk::MTables mt{};
   bool use_mfma = false;
+  bool curved = false;           // multilinear (non-lattice) mesh: curved-element kernels
+  dgk::CurvedTables ct{};
+  double* d_curved = nullptr;    // packed curved tables
+  double* d_cvX = nullptr;       // curved volume points [dim][nq][ne] (inside d_curved)
   double* d_mtab = nullptr;
   dgk::MTablesF mtf{};          // FP32 copies for the reduced-precision operator
   float* d_mtab_f = nullptr;

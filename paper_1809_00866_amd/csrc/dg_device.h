@@ -164,6 +164,74 @@ DEV void num_flux(const T* UL, const T* UR, int P, const Phys& ph, T* H) {
   H[DIM + 1] -= R(0.5) * de;
 }
 
+// Numerical convective flux across a face of unit normal n (any direction),
+// L -> R: the same Lax-Friedrichs / Roe construction as num_flux with the
+// normal velocity u.n and the tangential velocity jump du - (du.n) n.
+template <class T, int DIM>
+DEV void num_flux_n(const T* UL, const T* UR, const double* n, const Phys& ph, T* H) {
+  using R = typename RealOf<T>::type;
+  constexpr int NV = DIM + 2;
+  const R g = (R)ph.gamma;
+  T rinvL, uL[DIM], pL, rinvR, uR[DIM], pR;
+  primitives<T, DIM>(UL, g, rinvL, uL, pL);
+  primitives<T, DIM>(UR, g, rinvR, uR, pR);
+  T unL = R(0), unR = R(0);
+  for (int j = 0; j < DIM; ++j) {
+    unL += uL[j] * (R)n[j];
+    unR += uR[j] * (R)n[j];
+  }
+  H[0] = R(0.5) * (UL[0] * unL + UR[0] * unR);
+  for (int j = 0; j < DIM; ++j) H[1 + j] = R(0.5) * (UL[1 + j] * unL + UR[1 + j] * unR + (pL + pR) * (R)n[j]);
+  H[DIM + 1] = R(0.5) * (unL * (UL[DIM + 1] + pL) + unR * (UR[DIM + 1] + pR));
+  if (ph.flux == DG_FLUX_LF) {
+    T cL = dsqrt(g * pL * rinvL), cR = dsqrt(g * pR * rinvR);
+    T lam = rmax(rabs(unL) + cL, rabs(unR) + cR);
+    for (int c = 0; c < NV; ++c) H[c] -= R(0.5) * lam * (UR[c] - UL[c]);
+    return;
+  }
+  T sL = dsqrt(UL[0]), sR = dsqrt(UR[0]);
+  T HL = (UL[DIM + 1] + pL) * rinvL, HR = (UR[DIM + 1] + pR) * rinvR;
+  T iw = R(1) / (sL + sR);
+  T ut[DIM], q2 = R(0), unt = R(0);
+  for (int j = 0; j < DIM; ++j) {
+    ut[j] = (sL * uL[j] + sR * uR[j]) * iw;
+    q2 += ut[j] * ut[j];
+    unt += ut[j] * (R)n[j];
+  }
+  T Ht = (sL * HL + sR * HR) * iw;
+  T ct2 = (g - R(1)) * (Ht - R(0.5) * q2);
+  T ct = dsqrt(ct2);
+  T ict2 = R(1) / ct2;
+  T rhot = sL * sR;
+  T dr = UR[0] - UL[0];
+  T dp = pR - pL;
+  T du[DIM], dun = R(0);
+  for (int j = 0; j < DIM; ++j) {
+    du[j] = uR[j] - uL[j];
+    dun += du[j] * (R)n[j];
+  }
+  T a1 = (dp - rhot * ct * dun) * (R(0.5) * ict2);
+  T a5 = (dp + rhot * ct * dun) * (R(0.5) * ict2);
+  T a2 = dr - dp * ict2;
+  T delta = (R)ph.efix * (rabs(unt) + ct);
+  auto fix = [&](T lam) {
+    T al = rabs(lam);
+    return val(al) < val(delta) ? (lam * lam + delta * delta) / (R(2) * delta) : al;
+  };
+  T l1 = fix(unt - ct), l2 = fix(unt), l5 = fix(unt + ct);
+  T w1 = l1 * a1, w5 = l5 * a5, w2 = l2 * a2;
+  T sh = R(0);  // u~ . du_t
+  H[0] -= R(0.5) * (w1 + w2 + w5);
+  for (int j = 0; j < DIM; ++j) {
+    T dut = du[j] - dun * (R)n[j];
+    sh += ut[j] * dut;
+    T dj = (w1 + w2 + w5) * ut[j] + l2 * rhot * dut + (w5 - w1) * ct * (R)n[j];
+    H[1 + j] -= R(0.5) * dj;
+  }
+  T de = w1 * (Ht - ct * unt) + w2 * (R(0.5) * q2) + l2 * rhot * sh + w5 * (Ht + ct * unt);
+  H[DIM + 1] -= R(0.5) * de;
+}
+
 // Velocity and p/rho gradients from the corrected conservative gradient G[c][j].
 template <class T, int DIM>
 struct ViscPrep {

@@ -32,6 +32,14 @@ struct Tables {
 // fLift[p][0] / [p][1] map the owner / neighbour modes to {r^sigma} at the
 // face points (normal component; the lattice normal is +e_p).
 
+// Curved (multilinear) elements: device tables (layouts as in CurvedHost) and
+// the face kernel's outputs read by the volume kernel.
+struct CurvedTables {
+  const double *vPhi, *vGPhi, *vW, *fPhiL, *fPhiR, *fGPhiL, *fGPhiR, *fN, *fW;
+  double* fRho;   // [dim*ne][value/tangent][side][nv][dim][nb]  local lifting coefficients
+  double* fProj;  // [dim*ne][side][nv][nb]                       w_f|J_f| Hn projected on each side
+};
+
 // Operator tables pre-permuted into the operand order of the FP64 MFMA
 // 16x16x4 instruction (A[i][k] at lane i + 16k, B[k][j] at lane j + 16k,
 // D[i][j] at lane j + 16 (i % 4), register i / 4), 64 doubles per fragment.
@@ -158,6 +166,17 @@ hipError_t launch_gmres_step(double* sc, int j, int m, hipStream_t s);
 hipError_t launch_gmres_backsolve(double* sc, int m, hipStream_t s);
 hipError_t launch_scale_by(int64_t n, double* x, const double* sc, hipStream_t s);
 
+// Curved (multilinear) elements: residual / Jv in two passes (faces, then
+// volume and gather), L2 projection and maximal wave speed.
+hipError_t launch_face_curved(int cfg, bool jvp, const double* U, const double* V, const CurvedTables& ct,
+                              const Mesh& m, const Phys& ph, hipStream_t s);
+hipError_t launch_volume_curved(int cfg, bool jvp, const double* U, const double* V, const CurvedTables& ct,
+                                double* out, double shift, const Mesh& m, const Phys& ph, hipStream_t s);
+hipError_t launch_project_curved(int cfg, const double* f, double* w, const CurvedTables& ct, int64_t ne,
+                                 hipStream_t s);
+hipError_t launch_wave_speed_curved(int cfg, const double* w, double* partial, int nblocks, const CurvedTables& ct,
+                                    const Mesh& m, const Phys& ph, hipStream_t s);
+
 }  // namespace dgk
 
 namespace dgh {
@@ -173,6 +192,19 @@ void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
 void legendre_orthonormal(int kmax, double x, double* L, double* dL);
 std::vector<int> multi_indices(int k, int dim, int basis);
 HostTables build_tables(int dim, int order, int basis, int nq1d, const double h[3]);
+
+// Curved (multilinear) elements: per-element and per-face tables.
+struct CurvedHost {
+  std::vector<double> vPhi;    // [ne][nq][nb]
+  std::vector<double> vGPhi;   // [ne][nq][dim][nb]      physical gradients
+  std::vector<double> vW;      // [ne][nq]               w_q |J_q|
+  std::vector<double> vX;      // [dim][nq][ne]          physical volume points
+  std::vector<double> fPhiL, fPhiR;    // [dim*ne][nfq][nb]       owner / neighbour traces
+  std::vector<double> fGPhiL, fGPhiR;  // [dim*ne][nfq][dim][nb]
+  std::vector<double> fN;      // [dim*ne][nfq][dim]     unit normal, owner to neighbour
+  std::vector<double> fW;      // [dim*ne][nfq]          w_f |J_f|
+};
+CurvedHost build_curved_tables(const HostTables& T, int order, const double* xyz, const int64_t* nbr, int64_t ne);
 
 struct MfmaHost {
   std::vector<double> vA, pA, fA, tA, lA;

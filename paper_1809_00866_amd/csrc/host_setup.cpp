@@ -259,6 +259,225 @@ HostTables build_tables(int dim, int order, int basis, int nq1d, const double h[
   return T;
 }
 
+// ---------------------------------------------------------------- curved elements
+// Every element is the multilinear image of [-1,1]^dim through its 2^dim
+// corners (corner v at xi_i = +1 where bit i of v is set).  Its basis is
+// phi_K = L_K^{-1} psi with L_K L_K^T = sum_q w_q |J_q| psi psi^T (Cholesky of
+// the discrete reference mass matrix): orthonormal in the discrete L2(K)
+// product and hierarchical (L_K lower triangular); physical gradients
+// J^{-T} grad_xi.  Face (p, e) is the +p face of e; its neighbour er is
+// reached through e's +p face and sees the face at xi_p = -1 with the same
+// tangential reference coordinates.  Normal and area follow Nanson's formula
+// from the owner: n dA = |J| J^{-T} e_p dA_ref.
+namespace {
+
+void multilinear(int dim, const double* X, const double* xi, double* x, double* J) {
+  const int nv = 1 << dim;
+  for (int i = 0; i < dim; ++i) {
+    x[i] = 0.0;
+    for (int j = 0; j < dim; ++j) J[i * 3 + j] = 0.0;
+  }
+  for (int v = 0; v < nv; ++v) {
+    double f[3], df[3];
+    for (int i = 0; i < dim; ++i) {
+      const int bit = (v >> i) & 1;
+      f[i] = bit ? 0.5 * (1.0 + xi[i]) : 0.5 * (1.0 - xi[i]);
+      df[i] = bit ? 0.5 : -0.5;
+    }
+    double N = 1.0;
+    for (int i = 0; i < dim; ++i) N *= f[i];
+    for (int i = 0; i < dim; ++i) x[i] += N * X[v * dim + i];
+    for (int j = 0; j < dim; ++j) {
+      double dN = 1.0;
+      for (int i = 0; i < dim; ++i) dN *= (i == j) ? df[i] : f[i];
+      for (int i = 0; i < dim; ++i) J[i * 3 + j] += dN * X[v * dim + i];
+    }
+  }
+}
+
+// determinant and inverse of the leading dim x dim block of a 3x3 row-major matrix
+double det_inv(int dim, const double* J, double* Ji) {
+  if (dim == 2) {
+    const double d = J[0] * J[4] - J[1] * J[3];
+    Ji[0] = J[4] / d;
+    Ji[1] = -J[1] / d;
+    Ji[3] = -J[3] / d;
+    Ji[4] = J[0] / d;
+    return d;
+  }
+  const double a = J[0], b = J[1], c = J[2], d = J[3], e = J[4], f = J[5], g = J[6], h = J[7], k = J[8];
+  const double A = e * k - f * h, B = -(d * k - f * g), C = d * h - e * g;
+  const double det = a * A + b * B + c * C;
+  Ji[0] = A / det;
+  Ji[3] = B / det;
+  Ji[6] = C / det;
+  Ji[1] = -(b * k - c * h) / det;
+  Ji[4] = (a * k - c * g) / det;
+  Ji[7] = -(a * h - b * g) / det;
+  Ji[2] = (b * f - c * e) / det;
+  Ji[5] = -(a * f - c * d) / det;
+  Ji[8] = (a * e - b * d) / det;
+  return det;
+}
+
+}  // namespace
+
+CurvedHost build_curved_tables(const HostTables& T, int order, const double* xyz, const int64_t* nbr, int64_t ne) {
+  const int dim = T.dim, nb = T.nb, nq = T.nq, nfq = T.nfq, nq1 = T.nq1;
+  const int nvtx = 1 << dim;
+  CurvedHost C;
+  std::vector<double> x1, w1;
+  gauss_legendre(nq1, x1, w1);
+  // reference points and weights: volume (first coordinate fastest) and face rules
+  std::vector<double> vxi((size_t)nq * dim), vw(nq), fxi((size_t)nfq * (dim - 1)), fw(nfq);
+  for (int q = 0; q < nq; ++q) {
+    int r = q;
+    double w = 1.0;
+    for (int i = 0; i < dim; ++i) {
+      const int k = r % nq1;
+      r /= nq1;
+      vxi[(size_t)q * dim + i] = x1[k];
+      w *= w1[k];
+    }
+    vw[q] = w;
+  }
+  for (int f = 0; f < nfq; ++f) {
+    int r = f;
+    double w = 1.0;
+    for (int i = 0; i < dim - 1; ++i) {
+      const int k = r % nq1;
+      r /= nq1;
+      fxi[(size_t)f * (dim - 1) + i] = x1[k];
+      w *= w1[k];
+    }
+    fw[f] = w;
+  }
+  std::vector<double> psi(nb), dpsi((size_t)dim * nb);
+  std::vector<double> vpsi((size_t)nq * nb), vdpsi((size_t)nq * dim * nb);
+  for (int q = 0; q < nq; ++q) {
+    eval_psi(T.alpha, dim, order, &vxi[(size_t)q * dim], psi.data(), dpsi.data());
+    for (int b = 0; b < nb; ++b) {
+      vpsi[(size_t)q * nb + b] = psi[b];
+      for (int j = 0; j < dim; ++j) vdpsi[((size_t)q * dim + j) * nb + b] = dpsi[(size_t)j * nb + b];
+    }
+  }
+  // per element: L_K^{-1} (lower triangular), volume tables
+  std::vector<double> Linv((size_t)ne * nb * nb, 0.0);
+  C.vPhi.assign((size_t)ne * nq * nb, 0.0);
+  C.vGPhi.assign((size_t)ne * nq * dim * nb, 0.0);
+  C.vW.assign((size_t)ne * nq, 0.0);
+  C.vX.assign((size_t)dim * nq * ne, 0.0);
+  std::vector<double> det(nq), Jinv((size_t)nq * 9), M((size_t)nb * nb), L((size_t)nb * nb);
+  for (int64_t e = 0; e < ne; ++e) {
+    const double* X = xyz + (size_t)e * nvtx * dim;
+    for (int q = 0; q < nq; ++q) {
+      double x[3], J[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+      multilinear(dim, X, &vxi[(size_t)q * dim], x, J);
+      det[q] = det_inv(dim, J, &Jinv[(size_t)q * 9]);
+      if (!(det[q] > 0.0)) throw std::invalid_argument("element " + std::to_string(e) + " has a non-positive Jacobian");
+      for (int i = 0; i < dim; ++i) C.vX[((size_t)i * nq + q) * ne + e] = x[i];
+      C.vW[(size_t)e * nq + q] = vw[q] * det[q];
+    }
+    for (int a = 0; a < nb; ++a)
+      for (int b = 0; b < nb; ++b) {
+        double s = 0.0;
+        for (int q = 0; q < nq; ++q) s += vw[q] * det[q] * vpsi[(size_t)q * nb + a] * vpsi[(size_t)q * nb + b];
+        M[(size_t)a * nb + b] = s;
+      }
+    std::fill(L.begin(), L.end(), 0.0);  // Cholesky M = L L^T
+    for (int j = 0; j < nb; ++j) {
+      double s = M[(size_t)j * nb + j];
+      for (int k = 0; k < j; ++k) s -= L[(size_t)j * nb + k] * L[(size_t)j * nb + k];
+      if (!(s > 0.0)) throw std::invalid_argument("element mass matrix not positive definite");
+      const double d = std::sqrt(s);
+      L[(size_t)j * nb + j] = d;
+      for (int i = j + 1; i < nb; ++i) {
+        double t = M[(size_t)i * nb + j];
+        for (int k = 0; k < j; ++k) t -= L[(size_t)i * nb + k] * L[(size_t)j * nb + k];
+        L[(size_t)i * nb + j] = t / d;
+      }
+    }
+    double* Li = &Linv[(size_t)e * nb * nb];  // L^{-1} by forward substitution, column by column
+    for (int c = 0; c < nb; ++c)
+      for (int i = c; i < nb; ++i) {
+        double s = (i == c) ? 1.0 : 0.0;
+        for (int k = c; k < i; ++k) s -= L[(size_t)i * nb + k] * Li[(size_t)k * nb + c];
+        Li[(size_t)i * nb + c] = s / L[(size_t)i * nb + i];
+      }
+    for (int q = 0; q < nq; ++q) {
+      const double* Jq = &Jinv[(size_t)q * 9];
+      for (int a = 0; a < nb; ++a) {
+        double v = 0.0, g[3] = {0, 0, 0};
+        for (int b = 0; b <= a; ++b) {
+          const double l = Li[(size_t)a * nb + b];
+          v += l * vpsi[(size_t)q * nb + b];
+          for (int i = 0; i < dim; ++i) {
+            double gr = 0.0;  // (J^{-T} grad_xi psi_b)_i = sum_j Jinv[j][i] dpsi_j
+            for (int j = 0; j < dim; ++j) gr += Jq[j * 3 + i] * vdpsi[((size_t)q * dim + j) * nb + b];
+            g[i] += l * gr;
+          }
+        }
+        C.vPhi[((size_t)e * nq + q) * nb + a] = v;
+        for (int i = 0; i < dim; ++i) C.vGPhi[(((size_t)e * nq + q) * dim + i) * nb + a] = g[i];
+      }
+    }
+  }
+  // faces f = p*ne + e
+  const size_t nfc = (size_t)dim * ne;
+  C.fPhiL.assign(nfc * nfq * nb, 0.0);
+  C.fPhiR.assign(nfc * nfq * nb, 0.0);
+  C.fGPhiL.assign(nfc * nfq * dim * nb, 0.0);
+  C.fGPhiR.assign(nfc * nfq * dim * nb, 0.0);
+  C.fN.assign(nfc * nfq * dim, 0.0);
+  C.fW.assign(nfc * nfq, 0.0);
+  for (int p = 0; p < dim; ++p)
+    for (int64_t e = 0; e < ne; ++e) {
+      const size_t f = (size_t)p * ne + e;
+      const int64_t er = nbr[(size_t)e * 2 * dim + 2 * p + 1];
+      for (int side = 0; side < 2; ++side) {
+        const int64_t K = side == 0 ? e : er;
+        const double* X = xyz + (size_t)K * nvtx * dim;
+        const double* Li = &Linv[(size_t)K * nb * nb];
+        double* phi = side == 0 ? C.fPhiL.data() : C.fPhiR.data();
+        double* gphi = side == 0 ? C.fGPhiL.data() : C.fGPhiR.data();
+        for (int fq = 0; fq < nfq; ++fq) {
+          double xi[3] = {0, 0, 0};
+          for (int i = 0, k = 0; i < dim; ++i) xi[i] = (i == p) ? (side == 0 ? 1.0 : -1.0) : fxi[(size_t)fq * (dim - 1) + k++];
+          double x[3], J[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, Ji[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+          multilinear(dim, X, xi, x, J);
+          const double dt = det_inv(dim, J, Ji);
+          if (!(dt > 0.0)) throw std::invalid_argument("element " + std::to_string(K) + " has a non-positive Jacobian");
+          eval_psi(T.alpha, dim, order, xi, psi.data(), dpsi.data());
+          for (int a = 0; a < nb; ++a) {
+            double v = 0.0, g[3] = {0, 0, 0};
+            for (int b = 0; b <= a; ++b) {
+              const double l = Li[(size_t)a * nb + b];
+              v += l * psi[b];
+              for (int i = 0; i < dim; ++i) {
+                double gr = 0.0;
+                for (int j = 0; j < dim; ++j) gr += Ji[j * 3 + i] * dpsi[(size_t)j * nb + b];
+                g[i] += l * gr;
+              }
+            }
+            phi[(f * nfq + fq) * nb + a] = v;
+            for (int i = 0; i < dim; ++i) gphi[((f * nfq + fq) * dim + i) * nb + a] = g[i];
+          }
+          if (side == 0) {
+            double av[3], area2 = 0.0;
+            for (int i = 0; i < dim; ++i) {
+              av[i] = dt * Ji[p * 3 + i];
+              area2 += av[i] * av[i];
+            }
+            const double area = std::sqrt(area2);
+            for (int i = 0; i < dim; ++i) C.fN[(f * nfq + fq) * dim + i] = av[i] / area;
+            C.fW[f * nfq + fq] = fw[fq] * area;
+          }
+        }
+      }
+    }
+  return C;
+}
+
 MfmaHost build_mfma_tables(const HostTables& T) {
   MfmaHost M;
   const int dim = T.dim, nb = T.nb, nq = T.nq, nfq = T.nfq;

@@ -198,6 +198,7 @@ dg_status grad_impl(MlpState* M, const float* X, const float* T, const int64_t* 
 // X rows (ldx) of features for every element at state w, residual r
 dg_status features_impl(dg_context* c, MlpState* M, const double* w, const double* r, const double* z, float* X,
                         int ldx, float* T, double* sK, hipStream_t s) {
+  if (c->curved) return fail(DG_ERR_ARG, "the learned preconditioner's features need a uniform lattice");
   double vol = 1.0;
   for (int i = 0; i < c->dim; ++i) vol *= c->mesh.h[i];
   for (int v = 0; v < c->nv; ++v) {

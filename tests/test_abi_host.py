@@ -51,9 +51,17 @@ def test_create_rejects_bad_params(bad):
     assert st == -1 and msg
 
 
-def test_create_rejects_non_uniform_mesh():
+def test_create_accepts_curved_meshes_and_rejects_inverted_elements():
+    """A perturbed lattice is a valid curved mesh (no argument error; without
+    a GPU the create then fails on device memory); an element whose corners
+    are mirrored has a negative Jacobian and is refused before device work."""
     st, msg = _create(_prm(), synth.lattice_mesh((2, 2, 2), perturb=0.1, seed=1))
-    assert st == -1 and "axis-aligned" in msg
+    assert st != -1, msg
+    mesh = synth.lattice_mesh((2, 2, 2), perturb=0.1, seed=1)
+    xyz = np.array(mesh["elem_xyz"])
+    xyz[3] = xyz[3][[1, 0, 3, 2, 5, 4, 7, 6]]            # mirror element 3 in x
+    st, msg = _create(_prm(), dict(mesh, elem_xyz=xyz))
+    assert st == -1 and "Jacobian" in msg
 
 
 def test_create_rejects_inconsistent_neighbours():
