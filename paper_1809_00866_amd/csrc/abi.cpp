@@ -32,12 +32,16 @@ dg_status eval_residual(dg_context* c, bool jvp, const double* w, const double* 
                         hipStream_t s) {
   if (c->curved) {
     {
+      ProfScope ps(c, jvp ? "grad_jvp" : "grad_res", s);
+      HIPCHK(dgk::launch_modal_curved(c->cfg, jvp, w, v, c->ct, c->ne, s));
+    }
+    {
       ProfScope ps(c, jvp ? "face_jvp" : "face_res", s);
-      HIPCHK(dgk::launch_face_curved(c->cfg, jvp, w, v, c->ct, c->mesh, c->ph, s));
+      HIPCHK(dgk::launch_face_curved(c->cfg, jvp, c->ct, c->mesh, c->ph, s));
     }
     {
       ProfScope ps(c, jvp ? "vol_jvp" : "vol_res", s);
-      HIPCHK(dgk::launch_volume_curved(c->cfg, jvp, w, v, c->ct, out, shift, c->mesh, c->ph, s));
+      HIPCHK(dgk::launch_volume_curved(c->cfg, jvp, v, c->ct, out, shift, c->mesh, c->ph, s));
     }
     return DG_OK;
   }
@@ -97,8 +101,9 @@ dg_status eval_stab(dg_context* c, bool f32, const double* w, const double* v, d
   const double* z = c->d_zero;  // no tangent in the volume terms and the gradients
   if (c->curved) {
     if (f32) return fail(DG_ERR_ARG, "the reduced-precision operator needs a 3D P2-P4 lattice configuration");
-    HIPCHK(dgk::launch_face_curved(c->cfg, true, w, v, c->ct, c->mesh, ph, s));
-    HIPCHK(dgk::launch_volume_curved(c->cfg, true, w, z, c->ct, out, 0.0, c->mesh, c->ph, s));
+    HIPCHK(dgk::launch_modal_curved(c->cfg, true, w, v, c->ct, c->ne, s));
+    HIPCHK(dgk::launch_face_curved(c->cfg, true, c->ct, c->mesh, ph, s));
+    HIPCHK(dgk::launch_volume_curved(c->cfg, true, z, c->ct, out, 0.0, c->mesh, ph, s));
     return DG_OK;
   }
   if (f32) {
@@ -268,8 +273,9 @@ dg_status dg_create(const dg_params* prm, const dg_mesh* mesh, dg_context** out)
 
   // curved elements: per-element and per-face tables, face outputs
   if (!lattice) {
-    std::vector<const std::vector<double>*> cp = {&CH.vPhi, &CH.vGPhi, &CH.vW, &CH.vX, &CH.fPhiL, &CH.fPhiR,
-                                                  &CH.fGPhiL, &CH.fGPhiR, &CH.fN, &CH.fW};
+    std::vector<const std::vector<double>*> cp = {&CH.rPsiT, &CH.rDPsiT, &CH.rDPsi, &CH.rFPsiT, &CH.rFDPsiT,
+                                                  &CH.rFPsi,  &CH.Linv,   &CH.vGeo,  &CH.fGeo,   &CH.fP,
+                                                  &CH.vX};
     size_t ctot = 0;
     for (auto* v : cp) ctot += v->size();
     if ((st = dalloc(&c->d_curved, ctot)) != DG_OK) return cleanup(st);
@@ -281,19 +287,24 @@ dg_status dg_create(const dg_params* prm, const dg_mesh* mesh, dg_context** out)
         return cleanup(fail(DG_ERR_HIP, "curved table upload failed"));
       o += v->size();
     }
-    c->ct.vPhi = dst[0];
-    c->ct.vGPhi = dst[1];
-    c->ct.vW = dst[2];
-    c->d_cvX = dst[3];
-    c->ct.fPhiL = dst[4];
-    c->ct.fPhiR = dst[5];
-    c->ct.fGPhiL = dst[6];
-    c->ct.fGPhiR = dst[7];
-    c->ct.fN = dst[8];
-    c->ct.fW = dst[9];
-    const size_t nrho = (size_t)dim * ne * 2 * 2 * c->nv * dim * T.nb, nproj = (size_t)dim * ne * 2 * c->nv * T.nb;
-    if ((st = dalloc(&c->ct.fRho, nrho)) != DG_OK) return cleanup(st);
-    if ((st = dalloc(&c->ct.fProj, nproj)) != DG_OK) return cleanup(st);
+    c->ct.rPsiT = dst[0];
+    c->ct.rDPsiT = dst[1];
+    c->ct.rDPsi = dst[2];
+    c->ct.rFPsiT = dst[3];
+    c->ct.rFDPsiT = dst[4];
+    c->ct.rFPsi = dst[5];
+    c->ct.Linv = dst[6];
+    c->ct.vGeo = dst[7];
+    c->ct.fGeo = dst[8];
+    c->ct.fP = dst[9];
+    c->d_cvX = dst[10];
+    // work buffers: Ut, Vt, face jumps (value, tangent), face fluxes
+    const size_t nx = (size_t)ne * c->nv * T.nb, nfp = (size_t)dim * ne * c->nv * T.nfq;
+    if ((st = dalloc(&c->d_cwork, 2 * nx + 3 * nfp)) != DG_OK) return cleanup(st);
+    c->ct.Ut = c->d_cwork;
+    c->ct.Vt = c->d_cwork + nx;
+    c->ct.fJmp = c->d_cwork + 2 * nx;
+    c->ct.fHn = c->d_cwork + 2 * nx + 2 * nfp;
     c->curved = true;
   }
 
@@ -426,8 +437,7 @@ void dg_destroy(dg_context* c) {
   dfree(c->d_ros);
   dfree(c->d_zero);
   dfree(c->d_curved);
-  dfree(c->ct.fRho);
-  dfree(c->ct.fProj);
+  dfree(c->d_cwork);
   if (c->d_Dinv != c->d_D64) dfree(c->d_Dinv);
   dfree(c->d_V);
   dfree(c->d_Z);

@@ -66,6 +66,7 @@ struct dg_context {
   dgk::CurvedTables ct{};
   double* d_curved = nullptr;    // packed curved tables
   double* d_cvX = nullptr;       // curved volume points [dim][nq][ne] (inside d_curved)
+  double* d_cwork = nullptr;     // curved work buffers (Ut, Vt, face jumps and fluxes)
   double* d_mtab = nullptr;
   dgk::MTablesF mtf{};          // FP32 copies for the reduced-precision operator
   float* d_mtab_f = nullptr;

@@ -1,291 +1,452 @@
 // DG residual and exact Jv on curved (multilinear) elements (Sec. 2.1-2.2,
-// eq. NSdiscrRes): per-element and per-face basis tables (each element's own
-// orthonormalised basis, physical gradients, Nanson normals and area
-// weights) read from memory, pointwise fluxes on the vector ALU in FP64
-// (dual numbers for Jv).
+// eq. NSdiscrRes), FP64 on the vector ALU (dual numbers for Jv).
 //
-// Pass 1, one workgroup per face (p, e) (owner e, neighbour across its +p
-// face): traces of both sides, the local BR2 lifting coefficients of both
-// sides, rho^{S}_{c,j,b} = -1/2 sum_f w_f|J_f| [[U_c]] n_j phi^S_b, the face
-// flux Hn = H^c(U_L, U_R, n) - F^v({U}, {grad U} + eta {r}) . n, and its
-// projection w_f|J_f| Hn phi^S_b on each side.
-// Pass 2, one workgroup per element: the elemental lifting R^K (sum of the
-// local liftings of its 2d faces), the volume flux at the volume points with
-// G = grad U + R^K, its projection on the physical gradients of the basis,
-// plus the gathered face projections (+ on the owner side, - on the
-// neighbour side).
+// Element K's orthonormal basis is phi = L^{-1} psi, with L L^T the mass
+// matrix of the reference basis psi on K.  Every contraction therefore runs
+// against the shared reference tables of psi (read through the caches by all
+// elements) on coefficients transformed by the element's L^{-1}:
+//   u(x) = sum_a psi_a(xi) Ut_a,             Ut = L^{-T} U,
+//   grad_x u = K grad_xi u,                  K = J^{-T} at the point,
+//   R_b = sum_{a<=b} L^{-1}_{ba} Yt_a,       Yt = the projection on psi.
+// Only L^{-1} (packed) and the point geometry are stored per element and
+// face.
+//
+// Pass 1 (k_modal_curved), one workgroup per element: Ut and Vt.
+// Pass 2 (k_face_curved), one workgroup per face (p, e) (owner e, neighbour
+// across its +p face), one lane per (side, face point): traces of both sides,
+// the jump [[U]] = U_owner - U_neighbour (stored for pass 3), the averaged
+// lifting {r} at the face points through the face's point-to-point matrix
+// P_fg = sum_sides phi(x_f).phi(x_g):
+//   {r}_cj(x_f) = -1/4 sum_g P_fg w_g n_j(x_g) [[U_c]](x_g),
+// and w_f|J_f| times the normal flux H^c(U_L, U_R, n) - F^v({U}, {G}).n.
+// Pass 3 (k_volume_curved), one workgroup per element: the elemental lifting
+// R^K = sum over its 2d faces of the local liftings, in the reference basis
+// Rt = L^{-T} L^{-1} rho_t with rho_t_{a,c,j} = -1/2 sum_f psi_a w n_j [[U_c]];
+// the volume flux with G = grad U + R^K at the volume points, mapped to
+// reference directions (w|J| K^T F); its projection on grad_xi psi and the
+// face fluxes gathered on psi of each face (+ owner, - neighbour side); and
+// finally L^{-1}.
 #include "dg_device.h"
 
 namespace dgk {
 
 namespace {
 
-template <int DIM, int NB, int NQ1, bool JVP>
-__global__ __launch_bounds__(64) void k_face_curved(const double* __restrict__ U, const double* __restrict__ V,
-                                                    CurvedTables ct, Mesh m, Phys ph) {
-  using T = typename Scalar<JVP>::type;
-  constexpr int NV = DIM + 2, NFQ = ipow(NQ1, DIM - 1), NS = JVP ? 2 : 1;
-  static_assert(NFQ <= 64, "one thread per face point");
-  __shared__ double sU[NS][2][NV][NB];
-  __shared__ double sJ[NS][NFQ][NV];
-  __shared__ double sRho[NS][2][NV][DIM][NB];
-  __shared__ double sH[NFQ][NV];
+template <bool JVP>
+DEV typename Scalar<JVP>::type mk(double v, double t);
+template <>
+DEV double mk<false>(double v, double) {
+  return v;
+}
+template <>
+DEV dual mk<true>(double v, double t) {
+  return dual(v, t);
+}
+
+// value (and tangent) stored adjacently: one 16-byte LDS read per dual
+template <bool JVP>
+DEV typename Scalar<JVP>::type ld2(const double* p);
+template <>
+DEV double ld2<false>(const double* p) {
+  return p[0];
+}
+template <>
+DEV dual ld2<true>(const double* p) {
+  const double2 v = *reinterpret_cast<const double2*>(p);
+  return dual(v.x, v.y);
+}
+
+template <int DIM, int NB, bool JVP>
+__global__ __launch_bounds__(64) void k_modal_curved(const double* __restrict__ U, const double* __restrict__ V,
+                                                     CurvedTables ct, int64_t ne) {
+  constexpr int NV = DIM + 2, NBT = NB * (NB + 1) / 2, NS = JVP ? 2 : 1, NX = NV * NB;
+  __shared__ double sL[NBT];
+  __shared__ double sX[NS * NX];
   const int tid = threadIdx.x;
+  const int64_t e = blockIdx.x;
+  for (int i = tid; i < NBT; i += 64) sL[i] = ct.Linv[(size_t)e * NBT + i];
+  for (int i = tid; i < NS * NX; i += 64) sX[i] = (i < NX ? U : V)[(size_t)(i % NX) * ne + e];
+  __syncthreads();
+  for (int i = tid; i < NS * NX; i += 64) {
+    const int a = i % NB, row = i - a;  // row = (s, c) * NB
+    double acc = 0.0;
+    for (int b = a; b < NB; ++b) acc += sL[b * (b + 1) / 2 + a] * sX[row + b];
+    (i < NX ? ct.Ut : ct.Vt)[(size_t)e * NX + (i % NX)] = acc;
+  }
+}
+
+template <int DIM, int NB, int NQ1, bool JVP>
+__global__ __launch_bounds__(64) void k_face_curved(CurvedTables ct, Mesh m, Phys ph) {
+  using T = typename Scalar<JVP>::type;
+  constexpr int NV = DIM + 2, NFQ = ipow(NQ1, DIM - 1), NS = JVP ? 2 : 1, NC = NV * DIM, NX = NV * NB;
+  constexpr int GF = DIM + 1 + 2 * DIM * DIM, NTR = NV * (1 + DIM);
+  static_assert(NFQ <= 32, "one lane per (side, face point)");
+  constexpr int NW = 2 * NS * NX > 2 * NS * NC * NFQ ? 2 * NS * NX : 2 * NS * NC * NFQ;
+  __shared__ __align__(16) double sW[NW];     // coefficients of both sides, then sX and sR
+  __shared__ double sT[2][NS][NTR][NFQ];      // traces of both sides: values, physical gradients
+  __shared__ double sH[2][NV][NFQ];           // convective and viscous parts of the normal flux
+  double* sU = sW;                                               // [side][c][a][value/tangent]
+  auto sX = reinterpret_cast<double(*)[NC][NFQ]>(sW);            // [s][c*DIM+j][fq]: w n_j [[U_c]]
+  auto sR = reinterpret_cast<double(*)[NC][NFQ]>(sW + NS * NC * NFQ);  // {r}_cj at the face points
+  const int tid = threadIdx.x, side = tid >> 5, fq = tid & 31;
   const int P = blockIdx.y;
   const int64_t ne = m.ne;
   const int64_t e = blockIdx.x;
   const int64_t er = m.nbr[(size_t)(2 * P + 1) * ne + e];
   const size_t f = (size_t)P * ne + e;
-  const double kap = ph.mu * ph.gamma / (ph.prandtl * (ph.gamma - 1.0));
+  const double* geo = ct.fGeo + f * GF * NFQ;
+  const bool act = fq < NFQ;
 
-  for (int i = tid; i < NS * 2 * NV * NB; i += 64) {
-    const int b = i % NB, c = (i / NB) % NV, side = (i / (NB * NV)) % 2, s = i / (2 * NV * NB);
-    const double* X = s == 0 ? U : V;
-    sU[s][side][c][b] = X[(size_t)(c * NB + b) * ne + (side == 0 ? e : er)];
+  for (int i = tid; i < 2 * NS * NX; i += 64) {  // [side][c][a][value/tangent]
+    const int sd = i / (NS * NX), s = (i / NX) % NS;
+    sU[(sd * NX + i % NX) * NS + s] = (s ? ct.Vt : ct.Ut)[(size_t)(sd ? er : e) * NX + (i % NX)];
   }
   __syncthreads();
 
-  // traces at face point fq = tid
-  T uL[NV], uR[NV], gL[NV][DIM], gR[NV][DIM];
-  if (tid < NFQ) {
-    const double* phL = ct.fPhiL + (f * NFQ + tid) * NB;
-    const double* phR = ct.fPhiR + (f * NFQ + tid) * NB;
-    const double* gpL = ct.fGPhiL + (f * NFQ + tid) * DIM * NB;
-    const double* gpR = ct.fGPhiR + (f * NFQ + tid) * DIM * NB;
+  // traces of this lane's side at face point fq
+  if (act) {
+    const int ls = side == 0 ? 2 * P + 1 : 2 * P;  // local face: owner at xi_P = +1, neighbour at -1
+    const double* ps = ct.rFPsiT + (size_t)ls * NB * NFQ + fq;
+    const double* dps = ct.rFDPsiT + (size_t)ls * DIM * NB * NFQ + fq;
+    const double* xs = sU + side * NS * NX;
+    T u[NV], g[NV][DIM];
     for (int c = 0; c < NV; ++c) {
-      T a = 0.0, r = 0.0, ga[DIM], gr[DIM];
-      for (int j = 0; j < DIM; ++j) {
-        ga[j] = 0.0;
-        gr[j] = 0.0;
-      }
-#pragma unroll 1
-      for (int b = 0; b < NB; ++b) {
-        T xl, xr;
-        if constexpr (JVP) {
-          xl = T(sU[0][0][c][b], sU[NS - 1][0][c][b]);
-          xr = T(sU[0][1][c][b], sU[NS - 1][1][c][b]);
-        } else {
-          xl = sU[0][0][c][b];
-          xr = sU[0][1][c][b];
-        }
-        a += phL[b] * xl;
-        r += phR[b] * xr;
-        for (int j = 0; j < DIM; ++j) {
-          ga[j] += gpL[j * NB + b] * xl;
-          gr[j] += gpR[j * NB + b] * xr;
-        }
-      }
-      uL[c] = a;
-      uR[c] = r;
-      for (int j = 0; j < DIM; ++j) {
-        gL[c][j] = ga[j];
-        gR[c][j] = gr[j];
-      }
-      const T jmp = a - r;
-      sJ[0][tid][c] = val(jmp);
-      if constexpr (JVP) sJ[NS - 1][tid][c] = out_part(jmp);
+      u[c] = 0.0;
+      for (int r = 0; r < DIM; ++r) g[c][r] = 0.0;
     }
-    if constexpr (JVP) {
-      if (ph.stab_only) {  // tangent through the face lifting term only
-        for (int c = 0; c < NV; ++c) {
-          uL[c].d = 0.0;
-          uR[c].d = 0.0;
-          for (int j = 0; j < DIM; ++j) {
-            gL[c][j].d = 0.0;
-            gR[c][j].d = 0.0;
-          }
-        }
+#pragma unroll 2
+    for (int b = 0; b < NB; ++b) {  // each table entry read once for all variables
+      const double pb = ps[b * NFQ];
+      double db[DIM];
+      for (int r = 0; r < DIM; ++r) db[r] = dps[(r * NB + b) * NFQ];
+      for (int c = 0; c < NV; ++c) {
+        const T x = ld2<JVP>(xs + (c * NB + b) * NS);
+        u[c] += pb * x;
+        for (int r = 0; r < DIM; ++r) g[c][r] += db[r] * x;
       }
     }
-  }
-  __syncthreads();
-
-  // local lifting coefficients of both sides
-  for (int i = tid; i < 2 * NV * DIM * NB; i += 64) {
-    const int b = i % NB, j = (i / NB) % DIM, c = (i / (NB * DIM)) % NV, side = i / (NB * DIM * NV);
-    const double* tb = side == 0 ? ct.fPhiL : ct.fPhiR;
-    double sv = 0.0, st = 0.0;
-    for (int fq = 0; fq < NFQ; ++fq) {
-      const double wn = ct.fW[f * NFQ + fq] * ct.fN[(f * NFQ + fq) * DIM + j] * tb[(f * NFQ + fq) * NB + b];
-      sv += wn * sJ[0][fq][c];
-      if (JVP) st += wn * sJ[NS - 1][fq][c];
-    }
-    sRho[0][side][c][j][b] = -0.5 * sv;
-    if (JVP) sRho[NS - 1][side][c][j][b] = -0.5 * st;
-    double* out = ct.fRho + (f * 2 * 2 + 0 * 2 + side) * NV * DIM * NB;
-    out[(c * DIM + j) * NB + b] = -0.5 * sv;
-    double* outt = ct.fRho + (f * 2 * 2 + 1 * 2 + side) * NV * DIM * NB;
-    outt[(c * DIM + j) * NB + b] = (JVP && !ph.stab_only) ? -0.5 * st : 0.0;
-  }
-  __syncthreads();
-
-  // face flux at face point fq = tid
-  if (tid < NFQ) {
-    const double* phL = ct.fPhiL + (f * NFQ + tid) * NB;
-    const double* phR = ct.fPhiR + (f * NFQ + tid) * NB;
-    const double* n = ct.fN + (f * NFQ + tid) * DIM;
-    T ua[NV], Ga[NV][DIM];
+    double K[DIM][DIM];
+    for (int i = 0; i < DIM; ++i)
+      for (int r = 0; r < DIM; ++r) K[i][r] = geo[(size_t)(DIM + 1 + side * DIM * DIM + i * DIM + r) * NFQ + fq];
     for (int c = 0; c < NV; ++c) {
-      ua[c] = 0.5 * (uL[c] + uR[c]);
-      for (int j = 0; j < DIM; ++j) {
-        T rl = 0.0, rr = 0.0;
-#pragma unroll 1
-        for (int b = 0; b < NB; ++b) {
-          if constexpr (JVP) {
-            rl += phL[b] * T(sRho[0][0][c][j][b], sRho[NS - 1][0][c][j][b]);
-            rr += phR[b] * T(sRho[0][1][c][j][b], sRho[NS - 1][1][c][j][b]);
-          } else {
-            rl += phL[b] * sRho[0][0][c][j][b];
-            rr += phR[b] * sRho[0][1][c][j][b];
-          }
-        }
-        Ga[c][j] = 0.5 * (gL[c][j] + gR[c][j]) + ph.eta * (0.5 * (rl + rr));
+      sT[side][0][c][fq] = val(u[c]);
+      if constexpr (JVP) sT[side][NS - 1][c][fq] = out_part(u[c]);
+      for (int i = 0; i < DIM; ++i) {  // reference to physical gradient
+        T t = 0.0;
+        for (int r = 0; r < DIM; ++r) t += K[i][r] * g[c][r];
+        sT[side][0][NV + c * DIM + i][fq] = val(t);
+        if constexpr (JVP) sT[side][NS - 1][NV + c * DIM + i][fq] = out_part(t);
       }
     }
-    T Hn[NV];
-    num_flux_n<T, DIM>(uL, uR, n, ph, Hn);
-    ViscPrep<T, DIM> vp;
-    visc_prep<T, DIM>(ua, Ga, ph.gamma, vp);
-    for (int j = 0; j < DIM; ++j) {
-      T Fv[NV];
-      visc_flux_dir<T, DIM>(vp, j, ph.mu, kap, Fv);
-      for (int c = 0; c < NV; ++c) Hn[c] -= n[j] * Fv[c];
-    }
-    const double w = ct.fW[f * NFQ + tid];
-    for (int c = 0; c < NV; ++c) sH[tid][c] = w * out_part(Hn[c]);
   }
   __syncthreads();
 
-  // projection on both sides
-  for (int i = tid; i < 2 * NV * NB; i += 64) {
-    const int b = i % NB, c = (i / NB) % NV, side = i / (NB * NV);
-    const double* tb = side == 0 ? ct.fPhiL : ct.fPhiR;
-    double s = 0.0;
-    for (int fq = 0; fq < NFQ; ++fq) s += sH[fq][c] * tb[(f * NFQ + fq) * NB + b];
-    ct.fProj[((f * 2 + side) * NV + c) * NB + b] = s;
+  // jumps (kept for the elemental liftings) and w n [[U]]
+  double n[DIM];
+  for (int j = 0; j < DIM; ++j) n[j] = act ? geo[(size_t)j * NFQ + fq] : 0.0;
+  const double W = act ? geo[(size_t)DIM * NFQ + fq] : 0.0;
+  if (side == 0 && act) {
+    for (int c = 0; c < NV; ++c) {
+      const double jv = sT[0][0][c][fq] - sT[1][0][c][fq];
+      const double jt = JVP ? sT[0][NS - 1][c][fq] - sT[1][NS - 1][c][fq] : 0.0;
+      ct.fJmp[((f * 2 + 0) * NV + c) * NFQ + fq] = jv;
+      ct.fJmp[((f * 2 + 1) * NV + c) * NFQ + fq] = (JVP && !ph.stab_only) ? jt : 0.0;
+      for (int j = 0; j < DIM; ++j) {
+        sX[0][c * DIM + j][fq] = W * n[j] * jv;
+        if constexpr (JVP) sX[NS - 1][c * DIM + j][fq] = W * n[j] * jt;
+      }
+    }
+  }
+  __syncthreads();
+
+  // {r} = -1/4 P X, the (c, j) columns shared between the two halves
+  if (act) {
+    const double* Pf = ct.fP + f * NFQ * NFQ + fq;  // P is symmetric: row fq read along g
+    for (int k = side; k < NC; k += 2) {
+      double rv = 0.0, rt = 0.0;
+      for (int gq = 0; gq < NFQ; ++gq) {
+        const double pv = Pf[gq * NFQ];
+        rv += pv * sX[0][k][gq];
+        if constexpr (JVP) rt += pv * sX[NS - 1][k][gq];
+      }
+      sR[0][k][fq] = -0.25 * rv;
+      if constexpr (JVP) sR[NS - 1][k][fq] = -0.25 * rt;
+    }
+  }
+  __syncthreads();
+
+  // normal flux: convective part on the owner-side lanes, viscous part on the
+  // neighbour-side lanes (in the stabilisation-only tangent, only the face
+  // lifting term eta {r} carries a tangent)
+  const bool tr = JVP && !ph.stab_only;
+  if (act) {
+    T Hp[NV];
+    if (side == 0) {
+      T uL[NV], uR[NV];
+      for (int c = 0; c < NV; ++c) {
+        uL[c] = mk<JVP>(sT[0][0][c][fq], tr ? sT[0][NS - 1][c][fq] : 0.0);
+        uR[c] = mk<JVP>(sT[1][0][c][fq], tr ? sT[1][NS - 1][c][fq] : 0.0);
+      }
+      num_flux_n<T, DIM>(uL, uR, n, ph, Hp);
+    } else {
+      const double kap = ph.mu * ph.gamma / (ph.prandtl * (ph.gamma - 1.0));
+      T ua[NV], Ga[NV][DIM];
+      for (int c = 0; c < NV; ++c) {
+        ua[c] = 0.5 * mk<JVP>(sT[0][0][c][fq] + sT[1][0][c][fq],
+                              tr ? sT[0][NS - 1][c][fq] + sT[1][NS - 1][c][fq] : 0.0);
+        for (int i = 0; i < DIM; ++i) {
+          const int k = NV + c * DIM + i;
+          Ga[c][i] = 0.5 * mk<JVP>(sT[0][0][k][fq] + sT[1][0][k][fq], tr ? sT[0][NS - 1][k][fq] + sT[1][NS - 1][k][fq] : 0.0) +
+                     ph.eta * mk<JVP>(sR[0][c * DIM + i][fq], sR[NS - 1][c * DIM + i][fq]);
+        }
+      }
+      ViscPrep<T, DIM> vp;
+      visc_prep<T, DIM>(ua, Ga, ph.gamma, vp);
+      for (int c = 0; c < NV; ++c) Hp[c] = 0.0;
+      for (int j = 0; j < DIM; ++j) {
+        T Fv[NV];
+        visc_flux_dir<T, DIM>(vp, j, ph.mu, kap, Fv);
+        for (int c = 0; c < NV; ++c) Hp[c] -= n[j] * Fv[c];
+      }
+    }
+    for (int c = 0; c < NV; ++c) sH[side][c][fq] = out_part(Hp[c]);
+  }
+  __syncthreads();
+  for (int i = tid; i < NV * NFQ; i += 64) {
+    const int gq = i % NFQ, c = i / NFQ;
+    ct.fHn[f * NV * NFQ + i] = geo[(size_t)DIM * NFQ + gq] * (sH[0][c][gq] + sH[1][c][gq]);
   }
 }
 
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+
 template <int DIM, int NB, int NQ1, bool JVP>
-__global__ __launch_bounds__(128) void k_volume_curved(const double* __restrict__ U, const double* __restrict__ V,
-                                                      CurvedTables ct, double* __restrict__ out, double shift,
-                                                      Mesh m, Phys ph) {
+__global__ __launch_bounds__(128) void k_volume_curved(const double* __restrict__ V, CurvedTables ct,
+                                                      double* __restrict__ out, double shift, Mesh m, Phys ph) {
   using T = typename Scalar<JVP>::type;
-  constexpr int NV = DIM + 2, NQ = ipow(NQ1, DIM), NS = JVP ? 2 : 1;
+  constexpr int NV = DIM + 2, NQ = ipow(NQ1, DIM), NFQ = ipow(NQ1, DIM - 1), NS = JVP ? 2 : 1;
+  constexpr int NBT = NB * (NB + 1) / 2, NC = NV * DIM, NX = NV * NB, GV = DIM * DIM + 1;
+  constexpr int GF = DIM + 1 + 2 * DIM * DIM;
+  constexpr int NA = NS * NC * NB, NF = NQ * DIM * NV;
+  constexpr int NR = NS * NC + NV, RG = 5, NRG = (NR + RG - 1) / RG, NAG = (NB + 1) / 2;
+  constexpr int NSTG = NR * NFQ + NFQ * NB;  // one face: w n [[U]], w Hn, psi
+  static_assert(NRG * NAG <= 128, "one thread per 2-mode x RG-row block of a face product");
   static_assert(NQ <= 128, "one thread per volume point");
-  __shared__ double sU[NS][NV][NB];
-  __shared__ double sR[NS][NV][DIM][NB];
-  __shared__ double sF[NQ][DIM][NV];
+  static_assert(DIM * NB <= 128, "one thread per (reference direction, mode) in the projection");
+  static_assert(DIM * NV * NB <= NA, "projection partials fit the lifting buffer");
+  __shared__ __align__(16) double sU[NS * NX];      // Ut, Vt interleaved
+  __shared__ double sL[NBT];                        // L^{-1}, packed rows
+  __shared__ __align__(16) double sA[NA];           // rho_t, Rt (interleaved), projection partials
+  __shared__ double sB[cmax(NA, cmax(NF, NSTG))];  // face staging, L^{-1} rho_t, then w|J| K^T F
+  __shared__ double sY[NX];                         // projection on psi
   const int tid = threadIdx.x;
   const int64_t ne = m.ne;
   const int64_t e = blockIdx.x;
-  const double kap = ph.mu * ph.gamma / (ph.prandtl * (ph.gamma - 1.0));
+  const bool vt = JVP && !ph.stab_only;  // tangent of the volume terms
 
-  for (int i = tid; i < NS * NV * NB; i += 128) {
-    const int b = i % NB, c = (i / NB) % NV, s = i / (NB * NV);
-    sU[s][c][b] = (s == 0 ? U : V)[(size_t)(c * NB + b) * ne + e];
-  }
-  // elemental lifting: owner side of the +p faces, neighbour side of the -p faces
-  for (int i = tid; i < NS * NV * DIM * NB; i += 128) {
-    const int b = i % NB, j = (i / NB) % DIM, c = (i / (NB * DIM)) % NV, s = i / (NB * DIM * NV);
-    double a = 0.0;
-    for (int p = 0; p < DIM; ++p) {
-      const size_t fo = (size_t)p * ne + e;
-      const size_t fm = (size_t)p * ne + m.nbr[(size_t)(2 * p) * ne + e];
-      a += ct.fRho[((fo * 2 + s) * 2 + 0) * NV * DIM * NB + (c * DIM + j) * NB + b];
-      a += ct.fRho[((fm * 2 + s) * 2 + 1) * NV * DIM * NB + (c * DIM + j) * NB + b];
+  for (int i = tid; i < NBT; i += 128) sL[i] = ct.Linv[(size_t)e * NBT + i];
+  for (int i = tid; i < NS * NX; i += 128)  // value and tangent interleaved: [c][a][s]
+    sU[(i % NX) * NS + i / NX] = i < NX ? ct.Ut[(size_t)e * NX + i] : (vt ? ct.Vt[(size_t)e * NX + i - NX] : 0.0);
+
+  // the 2d faces one at a time: +p faces (owner side, xi_p = +1) and -p faces
+  // (neighbour side, xi_p = -1).  Rows of the staged face matrix: w n_j [[U_c]]
+  // (value, tangent) then w Hn; each thread accumulates a 2-mode x RG-row
+  // block of their products with psi of the face: the local liftings rho_t
+  // and the face part of the projection.
+  double acc[RG][2];
+  for (int r = 0; r < RG; ++r) acc[r][0] = acc[r][1] = 0.0;
+  const int ag = tid % NAG, rg = tid / NAG;
+  const int a0 = 2 * ag, a1 = a0 + 1 < NB ? a0 + 1 : a0;
+  double* sXs = sB;                  // [NR][NFQ]
+  double* sPs = sB + NR * NFQ;       // [NFQ][NB]
+  for (int hf = 0; hf < 2 * DIM; ++hf) {
+    const int p = hf >> 1, h = hf & 1;
+    const size_t f = (size_t)p * ne + (h ? m.nbr[(size_t)(2 * p) * ne + e] : e);
+    const int ls = h ? 2 * p : 2 * p + 1;
+    const double* geo = ct.fGeo + f * GF * NFQ;
+    __syncthreads();
+    for (int i = tid; i < NS * NC * NFQ; i += 128) {
+      const int gq = i % NFQ, k = (i / NFQ) % NC, s = i / (NC * NFQ), c = k / DIM, j = k % DIM;
+      sXs[i] = geo[(size_t)DIM * NFQ + gq] * geo[(size_t)j * NFQ + gq] * ct.fJmp[((f * 2 + s) * NV + c) * NFQ + gq];
     }
-    sR[s][c][j][b] = a;
+    for (int i = tid; i < NV * NFQ; i += 128) sXs[NS * NC * NFQ + i] = ct.fHn[f * NV * NFQ + i] * (h ? -1.0 : 1.0);
+    for (int i = tid; i < NFQ * NB; i += 128) sPs[i] = ct.rFPsi[(size_t)ls * NFQ * NB + i];
+    __syncthreads();
+    if (rg < NRG) {
+#pragma unroll 5
+      for (int gq = 0; gq < NFQ; ++gq) {
+        const double p0 = sPs[gq * NB + a0], p1 = sPs[gq * NB + a1];
+#pragma unroll
+        for (int r = 0; r < RG; ++r) {
+          const int row = rg * RG + r < NR ? rg * RG + r : NR - 1;
+          const double x = sXs[row * NFQ + gq];
+          acc[r][0] += p0 * x;
+          acc[r][1] += p1 * x;
+        }
+      }
+    }
+  }
+  if (rg < NRG) {
+#pragma unroll
+    for (int r = 0; r < RG; ++r) {
+      const int row = rg * RG + r;
+      for (int t = 0; t < 2; ++t) {
+        const int a = t ? a1 : a0;
+        if (row >= NR || (t && a1 == a0)) continue;
+        if (row < NS * NC)
+          sA[row * NB + a] = -0.5 * acc[r][t];
+        else
+          sY[(row - NS * NC) * NB + a] = acc[r][t];
+      }
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < NA; i += 128) {  // L^{-1} rho_t
+    const int b = i % NB, col = i - b;
+    double acc = 0.0;
+    for (int a = 0; a <= b; ++a) acc += sL[b * (b + 1) / 2 + a] * sA[col + a];
+    sB[i] = acc;
+  }
+  __syncthreads();
+  for (int i = tid; i < NA; i += 128) {  // Rt = L^{-T} L^{-1} rho_t, value and tangent interleaved
+    const int a = i % NB, col = i - a;
+    double acc = 0.0;
+    for (int b = a; b < NB; ++b) acc += sL[b * (b + 1) / 2 + a] * sB[col + b];
+    sA[(i % (NC * NB)) * NS + i / (NC * NB)] = acc;
   }
   __syncthreads();
 
   if (tid < NQ) {
-    const double* phi = ct.vPhi + ((size_t)e * NQ + tid) * NB;
-    const double* gphi = ct.vGPhi + ((size_t)e * NQ + tid) * DIM * NB;
+    const double kap = ph.mu * ph.gamma / (ph.prandtl * (ph.gamma - 1.0));
+    const double* geo = ct.vGeo + (size_t)e * GV * NQ + tid;
+    double K[DIM][DIM];
+    for (int i = 0; i < DIM; ++i)
+      for (int r = 0; r < DIM; ++r) K[i][r] = geo[(size_t)(i * DIM + r) * NQ];
+    const double wd = geo[(size_t)(DIM * DIM) * NQ];
+    const double* ps = ct.rPsiT + tid;
+    const double* dps = ct.rDPsiT + tid;
     T u[NV], G[NV][DIM];
-    for (int c = 0; c < NV; ++c) {
-      T a = 0.0, g[DIM];
-      for (int j = 0; j < DIM; ++j) g[j] = 0.0;
-#pragma unroll 1
-      for (int b = 0; b < NB; ++b) {
-        T x;
-        if constexpr (JVP)
-          x = T(sU[0][c][b], sU[NS - 1][c][b]);
-        else
-          x = sU[0][c][b];
-        a += phi[b] * x;
-        for (int j = 0; j < DIM; ++j) {
-          T rk;
-          if constexpr (JVP)
-            rk = T(sR[0][c][j][b], sR[NS - 1][c][j][b]);
-          else
-            rk = sR[0][c][j][b];
-          g[j] += gphi[j * NB + b] * x + phi[b] * rk;
+    {
+      T gx[NV][DIM];
+      for (int c = 0; c < NV; ++c) {
+        u[c] = 0.0;
+        for (int r = 0; r < DIM; ++r) gx[c][r] = 0.0;
+      }
+#pragma unroll 2
+      for (int b = 0; b < NB; ++b) {  // each table entry read once for all variables
+        const double pb = ps[b * NQ];
+        double db[DIM];
+        for (int r = 0; r < DIM; ++r) db[r] = dps[(r * NB + b) * NQ];
+        for (int c = 0; c < NV; ++c) {
+          const T x = ld2<JVP>(sU + (c * NB + b) * NS);
+          u[c] += pb * x;
+          for (int r = 0; r < DIM; ++r) gx[c][r] += db[r] * x;
         }
       }
-      u[c] = a;
-      for (int j = 0; j < DIM; ++j) G[c][j] = g[j];
+      for (int c = 0; c < NV; ++c)
+        for (int i = 0; i < DIM; ++i) {
+          T t = 0.0;
+          for (int r = 0; r < DIM; ++r) t += K[i][r] * gx[c][r];
+          G[c][i] = t;
+        }
+    }
+#pragma unroll 2
+    for (int b = 0; b < NB; ++b) {  // + R^K
+      const double pb = ps[b * NQ];
+      for (int c = 0; c < NV; ++c)
+        for (int r = 0; r < DIM; ++r)
+          G[c][r] += pb * ld2<JVP>(sA + ((c * DIM + r) * NB + b) * NS);
     }
     T rinv, vel[DIM], pr;
     primitives<T, DIM>(u, ph.gamma, rinv, vel, pr);
     ViscPrep<T, DIM> vp;
     visc_prep<T, DIM>(u, G, ph.gamma, vp);
-    const double w = ct.vW[(size_t)e * NQ + tid];
-    for (int j = 0; j < DIM; ++j) {
+    double Ft[DIM][NV];
+    for (int r = 0; r < DIM; ++r)
+      for (int c = 0; c < NV; ++c) Ft[r][c] = 0.0;
+    for (int p = 0; p < DIM; ++p) {
       T Fc[NV], Fv[NV];
-      conv_flux_dir<T, DIM>(u, vel, pr, j, Fc);
-      visc_flux_dir<T, DIM>(vp, j, ph.mu, kap, Fv);
-      for (int c = 0; c < NV; ++c) sF[tid][j][c] = w * out_part(Fc[c] - Fv[c]);
+      conv_flux_dir<T, DIM>(u, vel, pr, p, Fc);
+      visc_flux_dir<T, DIM>(vp, p, ph.mu, kap, Fv);
+      for (int c = 0; c < NV; ++c) {
+        const double fp = out_part(Fc[c] - Fv[c]);
+        for (int r = 0; r < DIM; ++r) Ft[r][c] += K[p][r] * fp;
+      }
     }
+    for (int r = 0; r < DIM; ++r)
+      for (int c = 0; c < NV; ++c) sB[(tid * DIM + r) * NV + c] = wd * Ft[r][c];
   }
   __syncthreads();
 
-  for (int i = tid; i < NV * NB; i += 128) {
-    const int b = i % NB, c = i / NB;
-    double a = 0.0;
+  if (tid < DIM * NB) {  // volume projection on d psi_a / d xi_r, one thread per (r, a)
+    const int a = tid % NB, r = tid / NB;
+    double acc[NV];
+    for (int c = 0; c < NV; ++c) acc[c] = 0.0;
+    const double* dp = ct.rDPsi + r * NB + a;
+#pragma unroll 4
     for (int q = 0; q < NQ; ++q) {
-      const double* gphi = ct.vGPhi + ((size_t)e * NQ + q) * DIM * NB;
-      for (int j = 0; j < DIM; ++j) a -= sF[q][j][c] * gphi[j * NB + b];
+      const double d = dp[q * DIM * NB];
+      for (int c = 0; c < NV; ++c) acc[c] += d * sB[(q * DIM + r) * NV + c];
     }
-    for (int p = 0; p < DIM; ++p) {
-      const size_t fo = (size_t)p * ne + e;
-      const size_t fm = (size_t)p * ne + m.nbr[(size_t)(2 * p) * ne + e];
-      a += ct.fProj[((fo * 2 + 0) * NV + c) * NB + b];
-      a -= ct.fProj[((fm * 2 + 1) * NV + c) * NB + b];
-    }
+    for (int c = 0; c < NV; ++c) sA[(r * NV + c) * NB + a] = acc[c];
+  }
+  __syncthreads();
+  for (int i = tid; i < NX; i += 128) {
+    const int a = i % NB, c = i / NB;
+    double y = sY[i];
+    for (int r = 0; r < DIM; ++r) y -= sA[(r * NV + c) * NB + a];
+    sY[i] = y;
+  }
+  __syncthreads();
+  for (int i = tid; i < NX; i += 128) {
+    const int b = i % NB, c = i / NB;
+    double acc = 0.0;
+    for (int a = 0; a <= b; ++a) acc += sL[b * (b + 1) / 2 + a] * sY[c * NB + a];
     const size_t idx = (size_t)(c * NB + b) * ne + e;
-    if (JVP) a += shift * V[idx];
-    out[idx] = a;
+    if (JVP) acc += shift * V[idx];
+    out[idx] = acc;
   }
 }
 
+// w = L^{-1} sum_q w_q|J_q| psi(xi_q) f_q
 template <int DIM, int NB, int NQ1>
-__global__ void k_project_curved(const double* __restrict__ f, double* __restrict__ w, CurvedTables ct, int64_t ne) {
-  constexpr int NV = DIM + 2, NQ = ipow(NQ1, DIM);
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (int64_t)NV * NB * ne) return;
-  const int64_t e = i % ne;
-  const int cb = (int)(i / ne), c = cb / NB, b = cb % NB;
-  double a = 0.0;
-  for (int q = 0; q < NQ; ++q)
-    a += ct.vW[(size_t)e * NQ + q] * ct.vPhi[((size_t)e * NQ + q) * NB + b] * f[((size_t)c * NQ + q) * ne + e];
-  w[i] = a;
+__global__ __launch_bounds__(64) void k_project_curved(const double* __restrict__ f, double* __restrict__ w,
+                                                       CurvedTables ct, int64_t ne) {
+  constexpr int NV = DIM + 2, NQ = ipow(NQ1, DIM), NBT = NB * (NB + 1) / 2, GV = DIM * DIM + 1;
+  __shared__ double sT[NV * NB];
+  const int64_t e = blockIdx.x;
+  const double* wd = ct.vGeo + ((size_t)e * GV + DIM * DIM) * NQ;
+  for (int i = threadIdx.x; i < NV * NB; i += 64) {
+    const int a = i % NB, c = i / NB;
+    double acc = 0.0;
+    for (int q = 0; q < NQ; ++q) acc += wd[q] * ct.rPsiT[a * NQ + q] * f[((size_t)c * NQ + q) * ne + e];
+    sT[i] = acc;
+  }
+  __syncthreads();
+  const double* Li = ct.Linv + (size_t)e * NBT;
+  for (int i = threadIdx.x; i < NV * NB; i += 64) {
+    const int b = i % NB, c = i / NB;
+    double acc = 0.0;
+    for (int a = 0; a <= b; ++a) acc += Li[b * (b + 1) / 2 + a] * sT[c * NB + a];
+    w[(size_t)(c * NB + b) * ne + e] = acc;
+  }
 }
 
+// max |u| + c over the volume points; reads Ut (the modal pass on w runs first)
 template <int DIM, int NB, int NQ1>
-__global__ __launch_bounds__(256) void k_wave_speed_curved(const double* __restrict__ w, double* __restrict__ partial,
-                                                           CurvedTables ct, Mesh m, Phys ph) {
+__global__ __launch_bounds__(256) void k_wave_speed_curved(double* __restrict__ partial, CurvedTables ct, Mesh m,
+                                                           Phys ph) {
   constexpr int NV = DIM + 2, NQ = ipow(NQ1, DIM);
   __shared__ double red[256];
   double mx = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < (int64_t)NQ * m.ne; i += (int64_t)gridDim.x * 256) {
     const int64_t e = i % m.ne;
     const int q = (int)(i / m.ne);
-    const double* phi = ct.vPhi + ((size_t)e * NQ + q) * NB;
+    const double* ut = ct.Ut + (size_t)e * NV * NB;
     double u[NV];
     for (int c = 0; c < NV; ++c) {
       double a = 0.0;
-      for (int b = 0; b < NB; ++b) a += phi[b] * w[((size_t)c * NB + b) * m.ne + e];
+      for (int b = 0; b < NB; ++b) a += ct.rPsiT[b * NQ + q] * ut[c * NB + b];
       u[c] = a;
     }
     double rinv, vel[DIM], p;
@@ -318,15 +479,14 @@ __global__ __launch_bounds__(256) void k_wave_speed_curved(const double* __restr
   X(4, 3, 20, 4)             \
   X(5, 3, 35, 5)
 
-hipError_t launch_face_curved(int cfg, bool jvp, const double* U, const double* V, const CurvedTables& ct,
-                              const Mesh& m, const Phys& ph, hipStream_t s) {
+hipError_t launch_modal_curved(int cfg, bool jvp, const double* U, const double* V, const CurvedTables& ct,
+                               int64_t ne, hipStream_t s) {
 #define X(id, d, nb_, nq_)                                                          \
   case id: {                                                                        \
-    dim3 grid((unsigned)m.ne, d);                                                   \
     if (jvp)                                                                        \
-      k_face_curved<d, nb_, nq_, true><<<grid, 64, 0, s>>>(U, V, ct, m, ph);        \
+      k_modal_curved<d, nb_, true><<<(unsigned)ne, 64, 0, s>>>(U, V, ct, ne);       \
     else                                                                            \
-      k_face_curved<d, nb_, nq_, false><<<grid, 64, 0, s>>>(U, V, ct, m, ph);       \
+      k_modal_curved<d, nb_, false><<<(unsigned)ne, 64, 0, s>>>(U, V, ct, ne);      \
     return hipGetLastError();                                                       \
   }
   switch (cfg) { DG_CURVED_CONFIGS(X) }
@@ -334,15 +494,31 @@ hipError_t launch_face_curved(int cfg, bool jvp, const double* U, const double* 
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_volume_curved(int cfg, bool jvp, const double* U, const double* V, const CurvedTables& ct,
-                                double* out, double shift, const Mesh& m, const Phys& ph, hipStream_t s) {
-#define X(id, d, nb_, nq_)                                                                           \
-  case id: {                                                                                         \
-    if (jvp)                                                                                         \
-      k_volume_curved<d, nb_, nq_, true><<<(unsigned)m.ne, 128, 0, s>>>(U, V, ct, out, shift, m, ph);  \
-    else                                                                                             \
-      k_volume_curved<d, nb_, nq_, false><<<(unsigned)m.ne, 128, 0, s>>>(U, V, ct, out, shift, m, ph); \
-    return hipGetLastError();                                                                        \
+hipError_t launch_face_curved(int cfg, bool jvp, const CurvedTables& ct, const Mesh& m, const Phys& ph,
+                              hipStream_t s) {
+#define X(id, d, nb_, nq_)                                                          \
+  case id: {                                                                        \
+    dim3 grid((unsigned)m.ne, d);                                                   \
+    if (jvp)                                                                        \
+      k_face_curved<d, nb_, nq_, true><<<grid, 64, 0, s>>>(ct, m, ph);              \
+    else                                                                            \
+      k_face_curved<d, nb_, nq_, false><<<grid, 64, 0, s>>>(ct, m, ph);             \
+    return hipGetLastError();                                                       \
+  }
+  switch (cfg) { DG_CURVED_CONFIGS(X) }
+#undef X
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_volume_curved(int cfg, bool jvp, const double* V, const CurvedTables& ct, double* out,
+                                double shift, const Mesh& m, const Phys& ph, hipStream_t s) {
+#define X(id, d, nb_, nq_)                                                                     \
+  case id: {                                                                                   \
+    if (jvp)                                                                                   \
+      k_volume_curved<d, nb_, nq_, true><<<(unsigned)m.ne, 128, 0, s>>>(V, ct, out, shift, m, ph);  \
+    else                                                                                       \
+      k_volume_curved<d, nb_, nq_, false><<<(unsigned)m.ne, 128, 0, s>>>(V, ct, out, shift, m, ph); \
+    return hipGetLastError();                                                                  \
   }
   switch (cfg) { DG_CURVED_CONFIGS(X) }
 #undef X
@@ -351,11 +527,10 @@ hipError_t launch_volume_curved(int cfg, bool jvp, const double* U, const double
 
 hipError_t launch_project_curved(int cfg, const double* f, double* w, const CurvedTables& ct, int64_t ne,
                                  hipStream_t s) {
-#define X(id, d, nb_, nq_)                                                                             \
-  case id: {                                                                                           \
-    const int64_t n = (int64_t)(d + 2) * nb_ * ne;                                                     \
-    k_project_curved<d, nb_, nq_><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(f, w, ct, ne);           \
-    return hipGetLastError();                                                                          \
+#define X(id, d, nb_, nq_)                                                         \
+  case id: {                                                                       \
+    k_project_curved<d, nb_, nq_><<<(unsigned)ne, 64, 0, s>>>(f, w, ct, ne);       \
+    return hipGetLastError();                                                      \
   }
   switch (cfg) { DG_CURVED_CONFIGS(X) }
 #undef X
@@ -364,10 +539,11 @@ hipError_t launch_project_curved(int cfg, const double* f, double* w, const Curv
 
 hipError_t launch_wave_speed_curved(int cfg, const double* w, double* partial, int nblocks, const CurvedTables& ct,
                                     const Mesh& m, const Phys& ph, hipStream_t s) {
-#define X(id, d, nb_, nq_)                                                                    \
-  case id: {                                                                                  \
-    k_wave_speed_curved<d, nb_, nq_><<<nblocks, 256, 0, s>>>(w, partial, ct, m, ph);          \
-    return hipGetLastError();                                                                 \
+#define X(id, d, nb_, nq_)                                                                  \
+  case id: {                                                                                \
+    k_modal_curved<d, nb_, false><<<(unsigned)m.ne, 64, 0, s>>>(w, w, ct, m.ne);            \
+    k_wave_speed_curved<d, nb_, nq_><<<nblocks, 256, 0, s>>>(partial, ct, m, ph);           \
+    return hipGetLastError();                                                               \
   }
   switch (cfg) { DG_CURVED_CONFIGS(X) }
 #undef X

@@ -35,9 +35,12 @@ struct Tables {
 // Curved (multilinear) elements: device tables (layouts as in CurvedHost) and
 // the face kernel's outputs read by the volume kernel.
 struct CurvedTables {
-  const double *vPhi, *vGPhi, *vW, *fPhiL, *fPhiR, *fGPhiL, *fGPhiR, *fN, *fW;
-  double* fRho;   // [dim*ne][value/tangent][side][nv][dim][nb]  local lifting coefficients
-  double* fProj;  // [dim*ne][side][nv][nb]                       w_f|J_f| Hn projected on each side
+  // shared reference tables (see CurvedHost) and per-element / per-face data
+  const double *rPsiT, *rDPsiT, *rDPsi, *rFPsiT, *rFDPsiT, *rFPsi;
+  const double *Linv, *vGeo, *fGeo, *fP;
+  double *Ut, *Vt;  // [ne][nv][nb]          L^{-T} U and L^{-T} V
+  double* fJmp;     // [dim*ne][2][nv][nfq]  [[U]] at the face points (value, tangent)
+  double* fHn;      // [dim*ne][nv][nfq]     w_f|J_f| times the normal flux (or its tangent)
 };
 
 // Operator tables pre-permuted into the operand order of the FP64 MFMA
@@ -168,10 +171,12 @@ hipError_t launch_scale_by(int64_t n, double* x, const double* sc, hipStream_t s
 
 // Curved (multilinear) elements: residual / Jv in two passes (faces, then
 // volume and gather), L2 projection and maximal wave speed.
-hipError_t launch_face_curved(int cfg, bool jvp, const double* U, const double* V, const CurvedTables& ct,
-                              const Mesh& m, const Phys& ph, hipStream_t s);
-hipError_t launch_volume_curved(int cfg, bool jvp, const double* U, const double* V, const CurvedTables& ct,
-                                double* out, double shift, const Mesh& m, const Phys& ph, hipStream_t s);
+hipError_t launch_modal_curved(int cfg, bool jvp, const double* U, const double* V, const CurvedTables& ct,
+                               int64_t ne, hipStream_t s);
+hipError_t launch_face_curved(int cfg, bool jvp, const CurvedTables& ct, const Mesh& m, const Phys& ph,
+                              hipStream_t s);
+hipError_t launch_volume_curved(int cfg, bool jvp, const double* V, const CurvedTables& ct, double* out,
+                                double shift, const Mesh& m, const Phys& ph, hipStream_t s);
 hipError_t launch_project_curved(int cfg, const double* f, double* w, const CurvedTables& ct, int64_t ne,
                                  hipStream_t s);
 hipError_t launch_wave_speed_curved(int cfg, const double* w, double* partial, int nblocks, const CurvedTables& ct,
@@ -193,16 +198,23 @@ void legendre_orthonormal(int kmax, double x, double* L, double* dL);
 std::vector<int> multi_indices(int k, int dim, int basis);
 HostTables build_tables(int dim, int order, int basis, int nq1d, const double h[3]);
 
-// Curved (multilinear) elements: per-element and per-face tables.
+// Curved (multilinear) elements.  Each element's orthonormal basis is
+// phi = L_K^{-1} psi (M_K = L_K L_K^T, the mass matrix of the reference basis
+// psi on K), so every contraction runs against the shared reference tables
+// of psi on coefficients transformed by L_K^{-1}; per element and per face
+// only L_K^{-1} and the point geometry are stored.
 struct CurvedHost {
-  std::vector<double> vPhi;    // [ne][nq][nb]
-  std::vector<double> vGPhi;   // [ne][nq][dim][nb]      physical gradients
-  std::vector<double> vW;      // [ne][nq]               w_q |J_q|
-  std::vector<double> vX;      // [dim][nq][ne]          physical volume points
-  std::vector<double> fPhiL, fPhiR;    // [dim*ne][nfq][nb]       owner / neighbour traces
-  std::vector<double> fGPhiL, fGPhiR;  // [dim*ne][nfq][dim][nb]
-  std::vector<double> fN;      // [dim*ne][nfq][dim]     unit normal, owner to neighbour
-  std::vector<double> fW;      // [dim*ne][nfq]          w_f |J_f|
+  std::vector<double> rPsiT;    // [nb][nq]             psi_a(xi_q)
+  std::vector<double> rDPsiT;   // [dim][nb][nq]        d psi_a / d xi_r
+  std::vector<double> rDPsi;    // [nq][dim][nb]
+  std::vector<double> rFPsiT;   // [2dim][nb][nfq]      psi_a on local face s (2p: xi_p=-1, 2p+1: +1)
+  std::vector<double> rFDPsiT;  // [2dim][dim][nb][nfq]
+  std::vector<double> rFPsi;    // [2dim][nfq][nb]
+  std::vector<double> Linv;     // [ne][nb(nb+1)/2]     L_K^{-1}, packed lower rows
+  std::vector<double> vGeo;     // [ne][dim*dim+1][nq]  K = J^{-T} (grad_x = K grad_xi), w_q|J_q|
+  std::vector<double> vX;       // [dim][nq][ne]        physical volume points
+  std::vector<double> fGeo;     // [dim*ne][dim+1+2dim^2][nfq]  n (owner to neighbour), w_f|J_f|, K owner, K neighbour
+  std::vector<double> fP;       // [dim*ne][nfq][nfq]   sum over both sides of phi(x_f).phi(x_g)
 };
 CurvedHost build_curved_tables(const HostTables& T, int order, const double* xyz, const int64_t* nbr, int64_t ne);
 

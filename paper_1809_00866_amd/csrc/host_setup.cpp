@@ -9,7 +9,10 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <exception>
 #include <stdexcept>
+#include <string>
+#include <thread>
 
 #include "dg_internal.h"
 
@@ -322,9 +325,34 @@ double det_inv(int dim, const double* J, double* Ji) {
 
 }  // namespace
 
+namespace {
+
+// Runs f(i0, i1) over [0, n) in chunks on the host's cores; the first
+// exception thrown by any chunk is rethrown after every thread has joined.
+template <class F>
+void parallel_chunks(int64_t n, F f) {
+  const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  const int64_t nt = std::max<int64_t>(1, std::min<int64_t>(hw, n / 64));
+  std::vector<std::thread> th;
+  std::vector<std::exception_ptr> err(nt);
+  for (int64_t t = 0; t < nt; ++t)
+    th.emplace_back([&, t] {
+      try {
+        f(n * t / nt, n * (t + 1) / nt);
+      } catch (...) {
+        err[t] = std::current_exception();
+      }
+    });
+  for (auto& x : th) x.join();
+  for (auto& e : err)
+    if (e) std::rethrow_exception(e);
+}
+
+}  // namespace
+
 CurvedHost build_curved_tables(const HostTables& T, int order, const double* xyz, const int64_t* nbr, int64_t ne) {
   const int dim = T.dim, nb = T.nb, nq = T.nq, nfq = T.nfq, nq1 = T.nq1;
-  const int nvtx = 1 << dim;
+  const int nvtx = 1 << dim, nbt = nb * (nb + 1) / 2, gv = dim * dim + 1, gf = dim + 1 + 2 * dim * dim;
   CurvedHost C;
   std::vector<double> x1, w1;
   gauss_legendre(nq1, x1, w1);
@@ -352,129 +380,149 @@ CurvedHost build_curved_tables(const HostTables& T, int order, const double* xyz
     }
     fw[f] = w;
   }
+  // reference point of face point fq on local face s (s = 2p: xi_p = -1, s = 2p+1: xi_p = +1)
+  auto face_xi = [&](int s, int fq, double* xi) {
+    const int p = s / 2;
+    for (int i = 0, k = 0; i < dim; ++i) xi[i] = (i == p) ? (s % 2 ? 1.0 : -1.0) : fxi[(size_t)fq * (dim - 1) + k++];
+  };
+
+  // shared reference tables
   std::vector<double> psi(nb), dpsi((size_t)dim * nb);
-  std::vector<double> vpsi((size_t)nq * nb), vdpsi((size_t)nq * dim * nb);
+  std::vector<double> vpsi((size_t)nq * nb);
+  C.rPsiT.assign((size_t)nb * nq, 0.0);
+  C.rDPsiT.assign((size_t)dim * nb * nq, 0.0);
+  C.rDPsi.assign((size_t)nq * dim * nb, 0.0);
   for (int q = 0; q < nq; ++q) {
     eval_psi(T.alpha, dim, order, &vxi[(size_t)q * dim], psi.data(), dpsi.data());
-    for (int b = 0; b < nb; ++b) {
-      vpsi[(size_t)q * nb + b] = psi[b];
-      for (int j = 0; j < dim; ++j) vdpsi[((size_t)q * dim + j) * nb + b] = dpsi[(size_t)j * nb + b];
+    for (int a = 0; a < nb; ++a) {
+      vpsi[(size_t)q * nb + a] = psi[a];
+      C.rPsiT[(size_t)a * nq + q] = psi[a];
+      for (int r = 0; r < dim; ++r) {
+        C.rDPsiT[((size_t)r * nb + a) * nq + q] = dpsi[(size_t)r * nb + a];
+        C.rDPsi[((size_t)q * dim + r) * nb + a] = dpsi[(size_t)r * nb + a];
+      }
     }
   }
-  // per element: L_K^{-1} (lower triangular), volume tables
-  std::vector<double> Linv((size_t)ne * nb * nb, 0.0);
-  C.vPhi.assign((size_t)ne * nq * nb, 0.0);
-  C.vGPhi.assign((size_t)ne * nq * dim * nb, 0.0);
-  C.vW.assign((size_t)ne * nq, 0.0);
-  C.vX.assign((size_t)dim * nq * ne, 0.0);
-  std::vector<double> det(nq), Jinv((size_t)nq * 9), M((size_t)nb * nb), L((size_t)nb * nb);
-  for (int64_t e = 0; e < ne; ++e) {
-    const double* X = xyz + (size_t)e * nvtx * dim;
-    for (int q = 0; q < nq; ++q) {
-      double x[3], J[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-      multilinear(dim, X, &vxi[(size_t)q * dim], x, J);
-      det[q] = det_inv(dim, J, &Jinv[(size_t)q * 9]);
-      if (!(det[q] > 0.0)) throw std::invalid_argument("element " + std::to_string(e) + " has a non-positive Jacobian");
-      for (int i = 0; i < dim; ++i) C.vX[((size_t)i * nq + q) * ne + e] = x[i];
-      C.vW[(size_t)e * nq + q] = vw[q] * det[q];
-    }
-    for (int a = 0; a < nb; ++a)
-      for (int b = 0; b < nb; ++b) {
-        double s = 0.0;
-        for (int q = 0; q < nq; ++q) s += vw[q] * det[q] * vpsi[(size_t)q * nb + a] * vpsi[(size_t)q * nb + b];
-        M[(size_t)a * nb + b] = s;
-      }
-    std::fill(L.begin(), L.end(), 0.0);  // Cholesky M = L L^T
-    for (int j = 0; j < nb; ++j) {
-      double s = M[(size_t)j * nb + j];
-      for (int k = 0; k < j; ++k) s -= L[(size_t)j * nb + k] * L[(size_t)j * nb + k];
-      if (!(s > 0.0)) throw std::invalid_argument("element mass matrix not positive definite");
-      const double d = std::sqrt(s);
-      L[(size_t)j * nb + j] = d;
-      for (int i = j + 1; i < nb; ++i) {
-        double t = M[(size_t)i * nb + j];
-        for (int k = 0; k < j; ++k) t -= L[(size_t)i * nb + k] * L[(size_t)j * nb + k];
-        L[(size_t)i * nb + j] = t / d;
-      }
-    }
-    double* Li = &Linv[(size_t)e * nb * nb];  // L^{-1} by forward substitution, column by column
-    for (int c = 0; c < nb; ++c)
-      for (int i = c; i < nb; ++i) {
-        double s = (i == c) ? 1.0 : 0.0;
-        for (int k = c; k < i; ++k) s -= L[(size_t)i * nb + k] * Li[(size_t)k * nb + c];
-        Li[(size_t)i * nb + c] = s / L[(size_t)i * nb + i];
-      }
-    for (int q = 0; q < nq; ++q) {
-      const double* Jq = &Jinv[(size_t)q * 9];
+  const int nfs = 2 * dim;
+  std::vector<double> fpsi((size_t)nfs * nfq * nb);  // [s][fq][a]
+  C.rFPsiT.assign((size_t)nfs * nb * nfq, 0.0);
+  C.rFDPsiT.assign((size_t)nfs * dim * nb * nfq, 0.0);
+  for (int s = 0; s < nfs; ++s)
+    for (int fq = 0; fq < nfq; ++fq) {
+      double xi[3];
+      face_xi(s, fq, xi);
+      eval_psi(T.alpha, dim, order, xi, psi.data(), dpsi.data());
       for (int a = 0; a < nb; ++a) {
-        double v = 0.0, g[3] = {0, 0, 0};
-        for (int b = 0; b <= a; ++b) {
-          const double l = Li[(size_t)a * nb + b];
-          v += l * vpsi[(size_t)q * nb + b];
-          for (int i = 0; i < dim; ++i) {
-            double gr = 0.0;  // (J^{-T} grad_xi psi_b)_i = sum_j Jinv[j][i] dpsi_j
-            for (int j = 0; j < dim; ++j) gr += Jq[j * 3 + i] * vdpsi[((size_t)q * dim + j) * nb + b];
-            g[i] += l * gr;
-          }
-        }
-        C.vPhi[((size_t)e * nq + q) * nb + a] = v;
-        for (int i = 0; i < dim; ++i) C.vGPhi[(((size_t)e * nq + q) * dim + i) * nb + a] = g[i];
+        fpsi[((size_t)s * nfq + fq) * nb + a] = psi[a];
+        C.rFPsiT[((size_t)s * nb + a) * nfq + fq] = psi[a];
+        for (int r = 0; r < dim; ++r)
+          C.rFDPsiT[(((size_t)s * dim + r) * nb + a) * nfq + fq] = dpsi[(size_t)r * nb + a];
       }
     }
-  }
-  // faces f = p*ne + e
-  const size_t nfc = (size_t)dim * ne;
-  C.fPhiL.assign(nfc * nfq * nb, 0.0);
-  C.fPhiR.assign(nfc * nfq * nb, 0.0);
-  C.fGPhiL.assign(nfc * nfq * dim * nb, 0.0);
-  C.fGPhiR.assign(nfc * nfq * dim * nb, 0.0);
-  C.fN.assign(nfc * nfq * dim, 0.0);
-  C.fW.assign(nfc * nfq, 0.0);
-  for (int p = 0; p < dim; ++p)
-    for (int64_t e = 0; e < ne; ++e) {
-      const size_t f = (size_t)p * ne + e;
+  C.rFPsi = fpsi;
+
+  // per element: geometry at the volume points, L_K^{-1} (packed rows)
+  C.Linv.assign((size_t)ne * nbt, 0.0);
+  C.vGeo.assign((size_t)ne * gv * nq, 0.0);
+  C.vX.assign((size_t)dim * nq * ne, 0.0);
+  parallel_chunks(ne, [&](int64_t e0, int64_t e1) {
+    std::vector<double> wd(nq), M((size_t)nb * nb), L((size_t)nb * nb);
+    for (int64_t e = e0; e < e1; ++e) {
+      const double* X = xyz + (size_t)e * nvtx * dim;
+      for (int q = 0; q < nq; ++q) {
+        double x[3], J[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, Ji[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        multilinear(dim, X, &vxi[(size_t)q * dim], x, J);
+        const double dt = det_inv(dim, J, Ji);
+        if (!(dt > 0.0)) throw std::invalid_argument("element " + std::to_string(e) + " has a non-positive Jacobian");
+        for (int i = 0; i < dim; ++i) C.vX[((size_t)i * nq + q) * ne + e] = x[i];
+        double* g = &C.vGeo[(size_t)e * gv * nq];
+        for (int i = 0; i < dim; ++i)  // K[i][r] = d xi_r / d x_i: grad_x = K grad_xi
+          for (int r = 0; r < dim; ++r) g[(size_t)(i * dim + r) * nq + q] = Ji[r * 3 + i];
+        wd[q] = vw[q] * dt;
+        g[(size_t)(dim * dim) * nq + q] = wd[q];
+      }
+      for (int a = 0; a < nb; ++a)
+        for (int b = 0; b <= a; ++b) {
+          double s = 0.0;
+          for (int q = 0; q < nq; ++q) s += wd[q] * vpsi[(size_t)q * nb + a] * vpsi[(size_t)q * nb + b];
+          M[(size_t)a * nb + b] = s;
+        }
+      std::fill(L.begin(), L.end(), 0.0);  // Cholesky M = L L^T
+      for (int j = 0; j < nb; ++j) {
+        double s = M[(size_t)j * nb + j];
+        for (int k = 0; k < j; ++k) s -= L[(size_t)j * nb + k] * L[(size_t)j * nb + k];
+        if (!(s > 0.0)) throw std::invalid_argument("element mass matrix not positive definite");
+        const double d = std::sqrt(s);
+        L[(size_t)j * nb + j] = d;
+        for (int i = j + 1; i < nb; ++i) {
+          double t = M[(size_t)i * nb + j];
+          for (int k = 0; k < j; ++k) t -= L[(size_t)i * nb + k] * L[(size_t)j * nb + k];
+          L[(size_t)i * nb + j] = t / d;
+        }
+      }
+      double* Li = &C.Linv[(size_t)e * nbt];  // L^{-1} by forward substitution, column by column
+      for (int c = 0; c < nb; ++c)
+        for (int i = c; i < nb; ++i) {
+          double s = (i == c) ? 1.0 : 0.0;
+          for (int k = c; k < i; ++k) s -= L[(size_t)i * nb + k] * Li[(size_t)k * (k + 1) / 2 + c];
+          Li[(size_t)i * (i + 1) / 2 + c] = s / L[(size_t)i * nb + i];
+        }
+    }
+  });
+
+  // faces f = p*ne + e (owner e, neighbour across its +p face): normals,
+  // area weights, both sides' K, and P = sum over sides of phi(x_f).phi(x_g)
+  const int64_t nfc = (int64_t)dim * ne;
+  C.fGeo.assign((size_t)nfc * gf * nfq, 0.0);
+  C.fP.assign((size_t)nfc * nfq * nfq, 0.0);
+  parallel_chunks(nfc, [&](int64_t f0, int64_t f1) {
+    std::vector<double> ph((size_t)nfq * nb);
+    for (int64_t f = f0; f < f1; ++f) {
+      const int p = (int)(f / ne);
+      const int64_t e = f % ne;
       const int64_t er = nbr[(size_t)e * 2 * dim + 2 * p + 1];
+      double* g = &C.fGeo[(size_t)f * gf * nfq];
+      double* P = &C.fP[(size_t)f * nfq * nfq];
       for (int side = 0; side < 2; ++side) {
         const int64_t K = side == 0 ? e : er;
+        const int s = side == 0 ? 2 * p + 1 : 2 * p;
         const double* X = xyz + (size_t)K * nvtx * dim;
-        const double* Li = &Linv[(size_t)K * nb * nb];
-        double* phi = side == 0 ? C.fPhiL.data() : C.fPhiR.data();
-        double* gphi = side == 0 ? C.fGPhiL.data() : C.fGPhiR.data();
+        const double* Li = &C.Linv[(size_t)K * nbt];
         for (int fq = 0; fq < nfq; ++fq) {
-          double xi[3] = {0, 0, 0};
-          for (int i = 0, k = 0; i < dim; ++i) xi[i] = (i == p) ? (side == 0 ? 1.0 : -1.0) : fxi[(size_t)fq * (dim - 1) + k++];
-          double x[3], J[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, Ji[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+          double xi[3], x[3], J[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, Ji[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+          face_xi(s, fq, xi);
           multilinear(dim, X, xi, x, J);
           const double dt = det_inv(dim, J, Ji);
           if (!(dt > 0.0)) throw std::invalid_argument("element " + std::to_string(K) + " has a non-positive Jacobian");
-          eval_psi(T.alpha, dim, order, xi, psi.data(), dpsi.data());
-          for (int a = 0; a < nb; ++a) {
-            double v = 0.0, g[3] = {0, 0, 0};
-            for (int b = 0; b <= a; ++b) {
-              const double l = Li[(size_t)a * nb + b];
-              v += l * psi[b];
-              for (int i = 0; i < dim; ++i) {
-                double gr = 0.0;
-                for (int j = 0; j < dim; ++j) gr += Ji[j * 3 + i] * dpsi[(size_t)j * nb + b];
-                g[i] += l * gr;
-              }
-            }
-            phi[(f * nfq + fq) * nb + a] = v;
-            for (int i = 0; i < dim; ++i) gphi[((f * nfq + fq) * dim + i) * nb + a] = g[i];
-          }
-          if (side == 0) {
+          for (int i = 0; i < dim; ++i)
+            for (int r = 0; r < dim; ++r)
+              g[(size_t)(dim + 1 + side * dim * dim + i * dim + r) * nfq + fq] = Ji[r * 3 + i];
+          if (side == 0) {  // Nanson: |J| J^{-T} e_p is the area-weighted normal
             double av[3], area2 = 0.0;
             for (int i = 0; i < dim; ++i) {
               av[i] = dt * Ji[p * 3 + i];
               area2 += av[i] * av[i];
             }
             const double area = std::sqrt(area2);
-            for (int i = 0; i < dim; ++i) C.fN[(f * nfq + fq) * dim + i] = av[i] / area;
-            C.fW[f * nfq + fq] = fw[fq] * area;
+            for (int i = 0; i < dim; ++i) g[(size_t)i * nfq + fq] = av[i] / area;
+            g[(size_t)dim * nfq + fq] = fw[fq] * area;
+          }
+          const double* ps = &fpsi[((size_t)s * nfq + fq) * nb];
+          for (int b = 0; b < nb; ++b) {  // phi_b(x_fq) = sum_{a<=b} L^{-1}[b][a] psi_a
+            double v = 0.0;
+            for (int a = 0; a <= b; ++a) v += Li[(size_t)b * (b + 1) / 2 + a] * ps[a];
+            ph[(size_t)fq * nb + b] = v;
           }
         }
+        for (int f1q = 0; f1q < nfq; ++f1q)
+          for (int f2q = 0; f2q < nfq; ++f2q) {
+            double v = 0.0;
+            for (int b = 0; b < nb; ++b) v += ph[(size_t)f1q * nb + b] * ph[(size_t)f2q * nb + b];
+            P[(size_t)f1q * nfq + f2q] += v;
+          }
       }
     }
+  });
   return C;
 }
 
