@@ -18,6 +18,8 @@
 //   sequence of kernel launches; setup captures it into a hipGraph that every
 //   apply replays on a library stream, ordered against the caller's stream
 //   by events.
+#include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -245,8 +247,7 @@ dg_status capture(dg_context* c, MgState* M) {
 // ---------------------------------------------------------------- colouring
 // Distance-2 colouring: the lattice colouring (i + 2j + 3k) mod q (2D:
 // (i + 2j) mod q) for the smallest q that passes the check, else greedy.
-std::vector<int> distance2_colouring(const std::vector<int64_t>& nbrT, const std::vector<double>& x0, int dim,
-                                     int64_t ne, const double* h, int* ncolor) {
+std::vector<int> distance2_colouring(const std::vector<int64_t>& nbrT, int dim, int64_t ne, int* ncolor) {
   const int nf = 2 * dim;
   auto elem = [&](int64_t K, int s) { return s == 0 ? K : nbrT[(size_t)(s - 1) * ne + K]; };
   auto valid = [&](const std::vector<int>& col) {
@@ -260,17 +261,36 @@ std::vector<int> distance2_colouring(const std::vector<int64_t>& nbrT, const std
     return true;
   };
   std::vector<int> best;
-  // lattice indices from the low corners
-  double lo[3] = {0, 0, 0};
-  for (int i = 0; i < dim; ++i) {
-    lo[i] = x0[(size_t)i * ne];
-    for (int64_t e = 0; e < ne; ++e) lo[i] = std::min(lo[i], x0[(size_t)i * ne + e]);
+  // lattice indices from the face-neighbour topology: a breadth-first walk
+  // from element 0, one step along +-axis i per face crossed (the check
+  // below rejects colourings that do not survive the periodic wrap)
+  std::vector<std::array<long, 3>> ijk(ne, std::array<long, 3>{0, 0, 0});
+  {
+    std::vector<char> seen(ne, 0);
+    std::vector<int64_t> queue;
+    queue.reserve(ne);
+    for (int64_t root = 0; root < ne; ++root) {
+      if (seen[root]) continue;
+      seen[root] = 1;
+      queue.push_back(root);
+      for (size_t qh = queue.size() - 1; qh < queue.size(); ++qh) {
+        const int64_t K = queue[qh];
+        for (int fc = 0; fc < nf; ++fc) {
+          const int64_t J = nbrT[(size_t)fc * ne + K];
+          if (J < 0 || J >= ne || seen[J]) continue;
+          seen[J] = 1;
+          ijk[J] = ijk[K];
+          ijk[J][fc / 2] += (fc % 2) ? 1 : -1;
+          queue.push_back(J);
+        }
+      }
+    }
   }
   for (int q = 2 * dim + 1; q <= 4 * dim && best.empty(); ++q) {
     std::vector<int> col(ne);
     for (int64_t e = 0; e < ne; ++e) {
       long v = 0;
-      for (int i = 0; i < dim; ++i) v += (long)(i + 1) * std::lround((x0[(size_t)i * ne + e] - lo[i]) / h[i]);
+      for (int i = 0; i < dim; ++i) v += (long)(i + 1) * ijk[e][i];
       col[e] = (int)(((v % q) + q) % q);
     }
     if (valid(col)) {
@@ -400,9 +420,7 @@ dg_status dg_mg_setup(dg_context* c, const double* w, double shift, const dg_mg_
 
   // distance-2 colouring (host)
   std::vector<int64_t> nbrT((size_t)nf * ne);
-  std::vector<double> x0((size_t)dim * ne);
-  if (hipMemcpy(nbrT.data(), c->d_nbr, nbrT.size() * sizeof(int64_t), hipMemcpyDeviceToHost) != hipSuccess ||
-      hipMemcpy(x0.data(), c->d_x0, x0.size() * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+  if (hipMemcpy(nbrT.data(), c->d_nbr, nbrT.size() * sizeof(int64_t), hipMemcpyDeviceToHost) != hipSuccess)
     return bail(fail(DG_ERR_HIP, "mesh download failed"));
   if (M->coarse_ilu) {
     // the diagonal-only elimination of the block ILU(0) is exact on graphs
@@ -419,7 +437,7 @@ dg_status dg_mg_setup(dg_context* c, const double* w, double shift, const dg_mg_
                                            "(no periodic direction of exactly three elements)"));
         }
   }
-  std::vector<int> col2 = distance2_colouring(nbrT, x0, dim, ne, c->mesh.h, &M->ncolor2);
+  std::vector<int> col2 = distance2_colouring(nbrT, dim, ne, &M->ncolor2);
   if ((st = dalloc(&M->color2, (size_t)ne)) != DG_OK) return bail(st);
   if (hipMemcpy(M->color2, col2.data(), ne * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
     return bail(fail(DG_ERR_HIP, "colour upload failed"));
