@@ -70,7 +70,10 @@ __global__ __launch_bounds__(64) void k_modal_curved(const double* __restrict__ 
   for (int i = tid; i < NS * NX; i += 64) {
     const int a = i % NB, row = i - a;  // row = (s, c) * NB
     double acc = 0.0;
-    for (int b = a; b < NB; ++b) acc += sL[b * (b + 1) / 2 + a] * sX[row + b];
+    for (int b = 0; b < NB; ++b) {  // same b in every lane: consecutive a read consecutive words
+      const double l = sL[b * (b + 1) / 2 + a];
+      acc += (b >= a ? l : 0.0) * sX[row + b];
+    }
     (i < NX ? ct.Ut : ct.Vt)[(size_t)e * NX + (i % NX)] = acc;
   }
 }
@@ -236,6 +239,7 @@ __global__ __launch_bounds__(128) void k_volume_curved(const double* __restrict_
   static_assert(DIM * NV * NB <= NA, "projection partials fit the lifting buffer");
   __shared__ __align__(16) double sU[NS * NX];      // Ut, Vt interleaved
   __shared__ double sL[NBT];                        // L^{-1}, packed rows
+  __shared__ double sLc[NBT];                       // L^{-1}, packed columns
   __shared__ __align__(16) double sA[NA];           // rho_t, Rt (interleaved), projection partials
   __shared__ double sB[cmax(NA, cmax(NF, NSTG))];  // face staging, L^{-1} rho_t, then w|J| K^T F
   __shared__ double sY[NX];                         // projection on psi
@@ -244,7 +248,14 @@ __global__ __launch_bounds__(128) void k_volume_curved(const double* __restrict_
   const int64_t e = blockIdx.x;
   const bool vt = JVP && !ph.stab_only;  // tangent of the volume terms
 
-  for (int i = tid; i < NBT; i += 128) sL[i] = ct.Linv[(size_t)e * NBT + i];
+  for (int i = tid; i < NB * NB; i += 128) {
+    const int b = i / NB, a = i % NB;
+    if (a <= b) {
+      const double l = ct.Linv[(size_t)e * NBT + b * (b + 1) / 2 + a];
+      sL[b * (b + 1) / 2 + a] = l;
+      sLc[a * NB - a * (a - 1) / 2 + b - a] = l;
+    }
+  }
   for (int i = tid; i < NS * NX; i += 128)  // value and tangent interleaved: [c][a][s]
     sU[(i % NX) * NS + i / NX] = i < NX ? ct.Ut[(size_t)e * NX + i] : (vt ? ct.Vt[(size_t)e * NX + i - NX] : 0.0);
 
@@ -301,17 +312,26 @@ __global__ __launch_bounds__(128) void k_volume_curved(const double* __restrict_
     }
   }
   __syncthreads();
+  // the triangular products run uniform loops (one index for every lane) over
+  // the row- or column-packed copy that makes neighbouring lanes read
+  // neighbouring words
   for (int i = tid; i < NA; i += 128) {  // L^{-1} rho_t
     const int b = i % NB, col = i - b;
     double acc = 0.0;
-    for (int a = 0; a <= b; ++a) acc += sL[b * (b + 1) / 2 + a] * sA[col + a];
+    for (int a = 0; a < NB; ++a) {
+      const double l = sLc[a * NB - a * (a - 1) / 2 + b - a];
+      acc += (a <= b ? l : 0.0) * sA[col + a];
+    }
     sB[i] = acc;
   }
   __syncthreads();
   for (int i = tid; i < NA; i += 128) {  // Rt = L^{-T} L^{-1} rho_t, value and tangent interleaved
     const int a = i % NB, col = i - a;
     double acc = 0.0;
-    for (int b = a; b < NB; ++b) acc += sL[b * (b + 1) / 2 + a] * sB[col + b];
+    for (int b = 0; b < NB; ++b) {
+      const double l = sL[b * (b + 1) / 2 + a];
+      acc += (b >= a ? l : 0.0) * sB[col + b];
+    }
     sA[(i % (NC * NB)) * NS + i / (NC * NB)] = acc;
   }
   __syncthreads();
@@ -401,7 +421,10 @@ __global__ __launch_bounds__(128) void k_volume_curved(const double* __restrict_
   for (int i = tid; i < NX; i += 128) {
     const int b = i % NB, c = i / NB;
     double acc = 0.0;
-    for (int a = 0; a <= b; ++a) acc += sL[b * (b + 1) / 2 + a] * sY[c * NB + a];
+    for (int a = 0; a < NB; ++a) {
+      const double l = sLc[a * NB - a * (a - 1) / 2 + b - a];
+      acc += (a <= b ? l : 0.0) * sY[c * NB + a];
+    }
     const size_t idx = (size_t)(c * NB + b) * ne + e;
     if (JVP) acc += shift * V[idx];
     out[idx] = acc;
