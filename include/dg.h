@@ -89,9 +89,9 @@ typedef struct {
  *  otherwise each element carries its own orthonormal basis (Cholesky
  *  factor of its mass matrix in the reference basis) and the curved FP64
  *  kernels run.  An element with a non-positive Jacobian determinant at a
- *  quadrature point returns DG_ERR_ARG.  On curved meshes the FP32
- *  operator (reduced-precision smoothing) and the learned preconditioner
- *  are unavailable (DG_ERR_STATE). */
+ *  quadrature point returns DG_ERR_ARG.  On curved meshes the learned
+ *  preconditioner is unavailable (DG_ERR_ARG: its features assume a uniform
+ *  lattice). */
 typedef struct {
   int64_t n_elem;
   const double* elem_xyz;
@@ -121,8 +121,8 @@ dg_status dg_project(dg_context* ctx, const double* f, double* w, void* stream);
 dg_status dg_residual(dg_context* ctx, const double* w, double* r, void* stream);
 
 /* The same residual with FP32 contractions (MFMA, FP32 accumulation) and FP32
- * pointwise fluxes; w and r stay FP64.  3D P2-P4 configurations only
- * (DG_ERR_ARG otherwise).  A reduced-precision operator for preconditioners
+ * pointwise fluxes; w and r stay FP64.  Curved meshes (FP32 tables and
+ * vector-ALU kernels) and 3D P2-P4 lattices only (DG_ERR_ARG otherwise).  A reduced-precision operator for preconditioners
  * and smoothers; relative error of order 1e-6 against the FP64 residual. */
 dg_status dg_residual_fp32(dg_context* ctx, const double* w, double* r, void* stream);
 

@@ -73,8 +73,23 @@ dg_status eval_residual(dg_context* c, bool jvp, const double* w, const double* 
 
 dg_status eval_residual_f32(dg_context* c, bool jvp, const double* w, const double* v, double shift, double* out,
                             hipStream_t s) {
-  if (!c->use_mfma || !c->d_mtab_f || !c->d_Hf || !c->d_Gf)
-    return fail(DG_ERR_ARG, "the reduced-precision operator needs a 3D P2-P4 configuration with MFMA kernels");
+  if (!has_f32(c))
+    return fail(DG_ERR_ARG, "the reduced-precision operator needs a curved mesh or a 3D P2-P4 lattice configuration");
+  if (c->curved) {
+    {
+      ProfScope ps(c, jvp ? "grad_jvp_f32" : "grad_res_f32", s);
+      HIPCHK(dgk::launch_modal_curved_f32(c->cfg, jvp, w, v, c->ctf, c->ne, s));
+    }
+    {
+      ProfScope ps(c, jvp ? "face_jvp_f32" : "face_res_f32", s);
+      HIPCHK(dgk::launch_face_curved_f32(c->cfg, jvp, c->ctf, c->mesh, c->ph, s));
+    }
+    {
+      ProfScope ps(c, jvp ? "vol_jvp_f32" : "vol_res_f32", s);
+      HIPCHK(dgk::launch_volume_curved_f32(c->cfg, jvp, v, c->ctf, out, shift, c->mesh, c->ph, s));
+    }
+    return DG_OK;
+  }
   {
     ProfScope ps(c, jvp ? "grad_jvp_f32" : "grad_res_f32", s);
     HIPCHK(dgk::launch_grad_mfma_f32(c->cfg, jvp, w, v, c->d_Gf, c->mtf, c->mesh, s));
@@ -100,7 +115,14 @@ dg_status eval_stab(dg_context* c, bool f32, const double* w, const double* v, d
   ph.stab_only = 1;
   const double* z = c->d_zero;  // no tangent in the volume terms and the gradients
   if (c->curved) {
-    if (f32) return fail(DG_ERR_ARG, "the reduced-precision operator needs a 3D P2-P4 lattice configuration");
+    if (f32) {
+      if (!has_f32(c))
+        return fail(DG_ERR_ARG, "the reduced-precision operator needs a curved mesh or a 3D P2-P4 lattice configuration");
+      HIPCHK(dgk::launch_modal_curved_f32(c->cfg, true, w, v, c->ctf, c->ne, s));
+      HIPCHK(dgk::launch_face_curved_f32(c->cfg, true, c->ctf, c->mesh, ph, s));
+      HIPCHK(dgk::launch_volume_curved_f32(c->cfg, true, z, c->ctf, out, 0.0, c->mesh, ph, s));
+      return DG_OK;
+    }
     HIPCHK(dgk::launch_modal_curved(c->cfg, true, w, v, c->ct, c->ne, s));
     HIPCHK(dgk::launch_face_curved(c->cfg, true, c->ct, c->mesh, ph, s));
     HIPCHK(dgk::launch_volume_curved(c->cfg, true, z, c->ct, out, 0.0, c->mesh, ph, s));
@@ -305,6 +327,37 @@ dg_status dg_create(const dg_params* prm, const dg_mesh* mesh, dg_context** out)
     c->ct.Vt = c->d_cwork + nx;
     c->ct.fJmp = c->d_cwork + 2 * nx;
     c->ct.fHn = c->d_cwork + 2 * nx + 2 * nfp;
+    {  // FP32 copies of the tables and FP32 work buffers: the reduced-precision operator
+      const size_t ftot = ctot - CH.vX.size();
+      std::vector<float> fl(ftot);
+      size_t q = 0;
+      for (size_t k = 0; k + 1 < cp.size(); ++k)
+        for (double x : *cp[k]) fl[q++] = (float)x;
+      if ((st = dalloc(&c->d_curved_f, ftot)) != DG_OK) return cleanup(st);
+      if (hipMemcpy(c->d_curved_f, fl.data(), ftot * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
+        return cleanup(fail(DG_ERR_HIP, "curved table upload failed"));
+      const float* fp[10];
+      size_t of = 0;
+      for (int k = 0; k < 10; ++k) {
+        fp[k] = c->d_curved_f + of;
+        of += cp[k]->size();
+      }
+      c->ctf.rPsiT = fp[0];
+      c->ctf.rDPsiT = fp[1];
+      c->ctf.rDPsi = fp[2];
+      c->ctf.rFPsiT = fp[3];
+      c->ctf.rFDPsiT = fp[4];
+      c->ctf.rFPsi = fp[5];
+      c->ctf.Linv = fp[6];
+      c->ctf.vGeo = fp[7];
+      c->ctf.fGeo = fp[8];
+      c->ctf.fP = fp[9];
+      if ((st = dalloc(&c->d_cwork_f, 2 * nx + 3 * nfp)) != DG_OK) return cleanup(st);
+      c->ctf.Ut = c->d_cwork_f;
+      c->ctf.Vt = c->d_cwork_f + nx;
+      c->ctf.fJmp = c->d_cwork_f + 2 * nx;
+      c->ctf.fHn = c->d_cwork_f + 2 * nx + 2 * nfp;
+    }
     c->curved = true;
   }
 
@@ -438,6 +491,8 @@ void dg_destroy(dg_context* c) {
   dfree(c->d_zero);
   dfree(c->d_curved);
   dfree(c->d_cwork);
+  dfree(c->d_curved_f);
+  dfree(c->d_cwork_f);
   if (c->d_Dinv != c->d_D64) dfree(c->d_Dinv);
   dfree(c->d_V);
   dfree(c->d_Z);
@@ -526,7 +581,7 @@ dg_status dg_block_precond_setup(dg_context* c, const double* w, double shift, i
     }
   }
   // reduced-precision factors are probed with the FP32 operator where it exists
-  const bool probe_f32 = storage != DG_FP64 && c->use_mfma && c->d_mtab_f;
+  const bool probe_f32 = storage != DG_FP64 && has_f32(c);
   {
     ProfScope ps(c, "block_probe", s);
     for (int col = 0; col < c->ncolor; ++col)

@@ -67,6 +67,9 @@ struct dg_context {
   double* d_curved = nullptr;    // packed curved tables
   double* d_cvX = nullptr;       // curved volume points [dim][nq][ne] (inside d_curved)
   double* d_cwork = nullptr;     // curved work buffers (Ut, Vt, face jumps and fluxes)
+  dgk::CurvedTablesF ctf{};      // FP32 copies for the reduced-precision curved operator
+  float* d_curved_f = nullptr;
+  float* d_cwork_f = nullptr;
   double* d_mtab = nullptr;
   dgk::MTablesF mtf{};          // FP32 copies for the reduced-precision operator
   float* d_mtab_f = nullptr;
@@ -129,6 +132,12 @@ struct ProfScope {
     }
   }
 };
+
+// True when the reduced-precision (FP32) operator exists for this context:
+// the 3D P2-P4 MFMA kernels on lattices, the curved kernels on curved meshes.
+inline bool has_f32(const dg_context* c) {
+  return (c->use_mfma && c->d_mtab_f && c->d_Hf && c->d_Gf) || (c->curved && c->d_curved_f && c->d_cwork_f);
+}
 
 // Residual (jvp = false) or exact Jv plus shift*v (jvp = true) on stream s.
 dg_status eval_residual(dg_context* c, bool jvp, const double* w, const double* v, double shift, double* out,

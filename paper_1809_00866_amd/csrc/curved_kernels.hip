@@ -32,36 +32,33 @@ namespace dgk {
 
 namespace {
 
-template <bool JVP>
-DEV typename Scalar<JVP>::type mk(double v, double t);
-template <>
-DEV double mk<false>(double v, double) {
-  return v;
-}
-template <>
-DEV dual mk<true>(double v, double t) {
-  return dual(v, t);
+template <bool JVP, class R>
+DEV typename Scalar<JVP, R>::type mk(R v, R t) {
+  if constexpr (JVP)
+    return dualT<R>(v, t);
+  else
+    return v;
 }
 
-// value (and tangent) stored adjacently: one 16-byte LDS read per dual
-template <bool JVP>
-DEV typename Scalar<JVP>::type ld2(const double* p);
-template <>
-DEV double ld2<false>(const double* p) {
-  return p[0];
-}
-template <>
-DEV dual ld2<true>(const double* p) {
-  const double2 v = *reinterpret_cast<const double2*>(p);
-  return dual(v.x, v.y);
+// value (and tangent) stored adjacently: one 16-byte (FP64) or 8-byte (FP32)
+// LDS read per dual
+template <bool JVP, class R>
+DEV typename Scalar<JVP, R>::type ld2(const R* p) {
+  if constexpr (JVP) {
+    using V2 = typename std::conditional<sizeof(R) == 8, double2, float2>::type;
+    const V2 v = *reinterpret_cast<const V2*>(p);
+    return dualT<R>(v.x, v.y);
+  } else {
+    return p[0];
+  }
 }
 
-template <int DIM, int NB, bool JVP>
+template <class R, int DIM, int NB, bool JVP>
 __global__ __launch_bounds__(64) void k_modal_curved(const double* __restrict__ U, const double* __restrict__ V,
-                                                     CurvedTables ct, int64_t ne) {
+                                                     CurvedTablesT<R> ct, int64_t ne) {
   constexpr int NV = DIM + 2, NBT = NB * (NB + 1) / 2, NS = JVP ? 2 : 1, NX = NV * NB;
-  __shared__ double sL[NBT];
-  __shared__ double sX[NS * NX];
+  __shared__ R sL[NBT];
+  __shared__ R sX[NS * NX];
   const int tid = threadIdx.x;
   const int64_t e = blockIdx.x;
   for (int i = tid; i < NBT; i += 64) sL[i] = ct.Linv[(size_t)e * NBT + i];
@@ -69,35 +66,35 @@ __global__ __launch_bounds__(64) void k_modal_curved(const double* __restrict__ 
   __syncthreads();
   for (int i = tid; i < NS * NX; i += 64) {
     const int a = i % NB, row = i - a;  // row = (s, c) * NB
-    double acc = 0.0;
+    R acc = 0.0;
     for (int b = 0; b < NB; ++b) {  // same b in every lane: consecutive a read consecutive words
-      const double l = sL[b * (b + 1) / 2 + a];
-      acc += (b >= a ? l : 0.0) * sX[row + b];
+      const R l = sL[b * (b + 1) / 2 + a];
+      acc += (b >= a ? l : R(0)) * sX[row + b];
     }
     (i < NX ? ct.Ut : ct.Vt)[(size_t)e * NX + (i % NX)] = acc;
   }
 }
 
-template <int DIM, int NB, int NQ1, bool JVP>
-__global__ __launch_bounds__(64) void k_face_curved(CurvedTables ct, Mesh m, Phys ph) {
-  using T = typename Scalar<JVP>::type;
+template <class R, int DIM, int NB, int NQ1, bool JVP>
+__global__ __launch_bounds__(64) void k_face_curved(CurvedTablesT<R> ct, Mesh m, Phys ph) {
+  using T = typename Scalar<JVP, R>::type;
   constexpr int NV = DIM + 2, NFQ = ipow(NQ1, DIM - 1), NS = JVP ? 2 : 1, NC = NV * DIM, NX = NV * NB;
   constexpr int GF = DIM + 1 + 2 * DIM * DIM, NTR = NV * (1 + DIM);
   static_assert(NFQ <= 32, "one lane per (side, face point)");
   constexpr int NW = 2 * NS * NX > 2 * NS * NC * NFQ ? 2 * NS * NX : 2 * NS * NC * NFQ;
-  __shared__ __align__(16) double sW[NW];     // coefficients of both sides, then sX and sR
-  __shared__ double sT[2][NS][NTR][NFQ];      // traces of both sides: values, physical gradients
-  __shared__ double sH[2][NV][NFQ];           // convective and viscous parts of the normal flux
-  double* sU = sW;                                               // [side][c][a][value/tangent]
-  auto sX = reinterpret_cast<double(*)[NC][NFQ]>(sW);            // [s][c*DIM+j][fq]: w n_j [[U_c]]
-  auto sR = reinterpret_cast<double(*)[NC][NFQ]>(sW + NS * NC * NFQ);  // {r}_cj at the face points
+  __shared__ __align__(16) R sW[NW];     // coefficients of both sides, then sX and sR
+  __shared__ R sT[2][NS][NTR][NFQ];      // traces of both sides: values, physical gradients
+  __shared__ R sH[2][NV][NFQ];           // convective and viscous parts of the normal flux
+  R* sU = sW;                                               // [side][c][a][value/tangent]
+  auto sX = reinterpret_cast<R(*)[NC][NFQ]>(sW);            // [s][c*DIM+j][fq]: w n_j [[U_c]]
+  auto sR = reinterpret_cast<R(*)[NC][NFQ]>(sW + NS * NC * NFQ);  // {r}_cj at the face points
   const int tid = threadIdx.x, side = tid >> 5, fq = tid & 31;
   const int P = blockIdx.y;
   const int64_t ne = m.ne;
   const int64_t e = blockIdx.x;
   const int64_t er = m.nbr[(size_t)(2 * P + 1) * ne + e];
   const size_t f = (size_t)P * ne + e;
-  const double* geo = ct.fGeo + f * GF * NFQ;
+  const R* geo = ct.fGeo + f * GF * NFQ;
   const bool act = fq < NFQ;
 
   for (int i = tid; i < 2 * NS * NX; i += 64) {  // [side][c][a][value/tangent]
@@ -109,9 +106,9 @@ __global__ __launch_bounds__(64) void k_face_curved(CurvedTables ct, Mesh m, Phy
   // traces of this lane's side at face point fq
   if (act) {
     const int ls = side == 0 ? 2 * P + 1 : 2 * P;  // local face: owner at xi_P = +1, neighbour at -1
-    const double* ps = ct.rFPsiT + (size_t)ls * NB * NFQ + fq;
-    const double* dps = ct.rFDPsiT + (size_t)ls * DIM * NB * NFQ + fq;
-    const double* xs = sU + side * NS * NX;
+    const R* ps = ct.rFPsiT + (size_t)ls * NB * NFQ + fq;
+    const R* dps = ct.rFDPsiT + (size_t)ls * DIM * NB * NFQ + fq;
+    const R* xs = sU + side * NS * NX;
     T u[NV], g[NV][DIM];
     for (int c = 0; c < NV; ++c) {
       u[c] = 0.0;
@@ -119,16 +116,16 @@ __global__ __launch_bounds__(64) void k_face_curved(CurvedTables ct, Mesh m, Phy
     }
 #pragma unroll 2
     for (int b = 0; b < NB; ++b) {  // each table entry read once for all variables
-      const double pb = ps[b * NFQ];
-      double db[DIM];
+      const R pb = ps[b * NFQ];
+      R db[DIM];
       for (int r = 0; r < DIM; ++r) db[r] = dps[(r * NB + b) * NFQ];
       for (int c = 0; c < NV; ++c) {
-        const T x = ld2<JVP>(xs + (c * NB + b) * NS);
+        const T x = ld2<JVP, R>(xs + (c * NB + b) * NS);
         u[c] += pb * x;
         for (int r = 0; r < DIM; ++r) g[c][r] += db[r] * x;
       }
     }
-    double K[DIM][DIM];
+    R K[DIM][DIM];
     for (int i = 0; i < DIM; ++i)
       for (int r = 0; r < DIM; ++r) K[i][r] = geo[(size_t)(DIM + 1 + side * DIM * DIM + i * DIM + r) * NFQ + fq];
     for (int c = 0; c < NV; ++c) {
@@ -145,13 +142,13 @@ __global__ __launch_bounds__(64) void k_face_curved(CurvedTables ct, Mesh m, Phy
   __syncthreads();
 
   // jumps (kept for the elemental liftings) and w n [[U]]
-  double n[DIM];
+  double n[DIM];  // the numerical flux takes an FP64 normal
   for (int j = 0; j < DIM; ++j) n[j] = act ? geo[(size_t)j * NFQ + fq] : 0.0;
-  const double W = act ? geo[(size_t)DIM * NFQ + fq] : 0.0;
+  const R W = act ? geo[(size_t)DIM * NFQ + fq] : R(0);
   if (side == 0 && act) {
     for (int c = 0; c < NV; ++c) {
-      const double jv = sT[0][0][c][fq] - sT[1][0][c][fq];
-      const double jt = JVP ? sT[0][NS - 1][c][fq] - sT[1][NS - 1][c][fq] : 0.0;
+      const R jv = sT[0][0][c][fq] - sT[1][0][c][fq];
+      const R jt = JVP ? sT[0][NS - 1][c][fq] - sT[1][NS - 1][c][fq] : 0.0;
       ct.fJmp[((f * 2 + 0) * NV + c) * NFQ + fq] = jv;
       ct.fJmp[((f * 2 + 1) * NV + c) * NFQ + fq] = (JVP && !ph.stab_only) ? jt : 0.0;
       for (int j = 0; j < DIM; ++j) {
@@ -164,11 +161,11 @@ __global__ __launch_bounds__(64) void k_face_curved(CurvedTables ct, Mesh m, Phy
 
   // {r} = -1/4 P X, the (c, j) columns shared between the two halves
   if (act) {
-    const double* Pf = ct.fP + f * NFQ * NFQ + fq;  // P is symmetric: row fq read along g
+    const R* Pf = ct.fP + f * NFQ * NFQ + fq;  // P is symmetric: row fq read along g
     for (int k = side; k < NC; k += 2) {
-      double rv = 0.0, rt = 0.0;
+      R rv = 0.0, rt = 0.0;
       for (int gq = 0; gq < NFQ; ++gq) {
-        const double pv = Pf[gq * NFQ];
+        const R pv = Pf[gq * NFQ];
         rv += pv * sX[0][k][gq];
         if constexpr (JVP) rt += pv * sX[NS - 1][k][gq];
       }
@@ -187,20 +184,21 @@ __global__ __launch_bounds__(64) void k_face_curved(CurvedTables ct, Mesh m, Phy
     if (side == 0) {
       T uL[NV], uR[NV];
       for (int c = 0; c < NV; ++c) {
-        uL[c] = mk<JVP>(sT[0][0][c][fq], tr ? sT[0][NS - 1][c][fq] : 0.0);
-        uR[c] = mk<JVP>(sT[1][0][c][fq], tr ? sT[1][NS - 1][c][fq] : 0.0);
+        uL[c] = mk<JVP, R>(sT[0][0][c][fq], tr ? sT[0][NS - 1][c][fq] : R(0));
+        uR[c] = mk<JVP, R>(sT[1][0][c][fq], tr ? sT[1][NS - 1][c][fq] : R(0));
       }
       num_flux_n<T, DIM>(uL, uR, n, ph, Hp);
     } else {
       const double kap = ph.mu * ph.gamma / (ph.prandtl * (ph.gamma - 1.0));
       T ua[NV], Ga[NV][DIM];
       for (int c = 0; c < NV; ++c) {
-        ua[c] = 0.5 * mk<JVP>(sT[0][0][c][fq] + sT[1][0][c][fq],
-                              tr ? sT[0][NS - 1][c][fq] + sT[1][NS - 1][c][fq] : 0.0);
+        ua[c] = R(0.5) * mk<JVP, R>(sT[0][0][c][fq] + sT[1][0][c][fq],
+                                    tr ? sT[0][NS - 1][c][fq] + sT[1][NS - 1][c][fq] : R(0));
         for (int i = 0; i < DIM; ++i) {
           const int k = NV + c * DIM + i;
-          Ga[c][i] = 0.5 * mk<JVP>(sT[0][0][k][fq] + sT[1][0][k][fq], tr ? sT[0][NS - 1][k][fq] + sT[1][NS - 1][k][fq] : 0.0) +
-                     ph.eta * mk<JVP>(sR[0][c * DIM + i][fq], sR[NS - 1][c * DIM + i][fq]);
+          Ga[c][i] = R(0.5) * mk<JVP, R>(sT[0][0][k][fq] + sT[1][0][k][fq],
+                                         tr ? sT[0][NS - 1][k][fq] + sT[1][NS - 1][k][fq] : R(0)) +
+                     (R)ph.eta * mk<JVP, R>(sR[0][c * DIM + i][fq], sR[NS - 1][c * DIM + i][fq]);
         }
       }
       ViscPrep<T, DIM> vp;
@@ -209,7 +207,7 @@ __global__ __launch_bounds__(64) void k_face_curved(CurvedTables ct, Mesh m, Phy
       for (int j = 0; j < DIM; ++j) {
         T Fv[NV];
         visc_flux_dir<T, DIM>(vp, j, ph.mu, kap, Fv);
-        for (int c = 0; c < NV; ++c) Hp[c] -= n[j] * Fv[c];
+        for (int c = 0; c < NV; ++c) Hp[c] -= (R)n[j] * Fv[c];
       }
     }
     for (int c = 0; c < NV; ++c) sH[side][c][fq] = out_part(Hp[c]);
@@ -223,10 +221,10 @@ __global__ __launch_bounds__(64) void k_face_curved(CurvedTables ct, Mesh m, Phy
 
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 
-template <int DIM, int NB, int NQ1, bool JVP>
-__global__ __launch_bounds__(128) void k_volume_curved(const double* __restrict__ V, CurvedTables ct,
+template <class R, int DIM, int NB, int NQ1, bool JVP>
+__global__ __launch_bounds__(128) void k_volume_curved(const double* __restrict__ V, CurvedTablesT<R> ct,
                                                       double* __restrict__ out, double shift, Mesh m, Phys ph) {
-  using T = typename Scalar<JVP>::type;
+  using T = typename Scalar<JVP, R>::type;
   constexpr int NV = DIM + 2, NQ = ipow(NQ1, DIM), NFQ = ipow(NQ1, DIM - 1), NS = JVP ? 2 : 1;
   constexpr int NBT = NB * (NB + 1) / 2, NC = NV * DIM, NX = NV * NB, GV = DIM * DIM + 1;
   constexpr int GF = DIM + 1 + 2 * DIM * DIM;
@@ -237,12 +235,12 @@ __global__ __launch_bounds__(128) void k_volume_curved(const double* __restrict_
   static_assert(NQ <= 128, "one thread per volume point");
   static_assert(DIM * NB <= 128, "one thread per (reference direction, mode) in the projection");
   static_assert(DIM * NV * NB <= NA, "projection partials fit the lifting buffer");
-  __shared__ __align__(16) double sU[NS * NX];      // Ut, Vt interleaved
-  __shared__ double sL[NBT];                        // L^{-1}, packed rows
-  __shared__ double sLc[NBT];                       // L^{-1}, packed columns
-  __shared__ __align__(16) double sA[NA];           // rho_t, Rt (interleaved), projection partials
-  __shared__ double sB[cmax(NA, cmax(NF, NSTG))];  // face staging, L^{-1} rho_t, then w|J| K^T F
-  __shared__ double sY[NX];                         // projection on psi
+  __shared__ __align__(16) R sU[NS * NX];      // Ut, Vt interleaved
+  __shared__ R sL[NBT];                        // L^{-1}, packed rows
+  __shared__ R sLc[NBT];                       // L^{-1}, packed columns
+  __shared__ __align__(16) R sA[NA];           // rho_t, Rt (interleaved), projection partials
+  __shared__ R sB[cmax(NA, cmax(NF, NSTG))];  // face staging, L^{-1} rho_t, then w|J| K^T F
+  __shared__ R sY[NX];                         // projection on psi
   const int tid = threadIdx.x;
   const int64_t ne = m.ne;
   const int64_t e = blockIdx.x;
@@ -251,7 +249,7 @@ __global__ __launch_bounds__(128) void k_volume_curved(const double* __restrict_
   for (int i = tid; i < NB * NB; i += 128) {
     const int b = i / NB, a = i % NB;
     if (a <= b) {
-      const double l = ct.Linv[(size_t)e * NBT + b * (b + 1) / 2 + a];
+      const R l = ct.Linv[(size_t)e * NBT + b * (b + 1) / 2 + a];
       sL[b * (b + 1) / 2 + a] = l;
       sLc[a * NB - a * (a - 1) / 2 + b - a] = l;
     }
@@ -264,17 +262,17 @@ __global__ __launch_bounds__(128) void k_volume_curved(const double* __restrict_
   // (value, tangent) then w Hn; each thread accumulates a 2-mode x RG-row
   // block of their products with psi of the face: the local liftings rho_t
   // and the face part of the projection.
-  double acc[RG][2];
+  R acc[RG][2];
   for (int r = 0; r < RG; ++r) acc[r][0] = acc[r][1] = 0.0;
   const int ag = tid % NAG, rg = tid / NAG;
   const int a0 = 2 * ag, a1 = a0 + 1 < NB ? a0 + 1 : a0;
-  double* sXs = sB;                  // [NR][NFQ]
-  double* sPs = sB + NR * NFQ;       // [NFQ][NB]
+  R* sXs = sB;                  // [NR][NFQ]
+  R* sPs = sB + NR * NFQ;       // [NFQ][NB]
   for (int hf = 0; hf < 2 * DIM; ++hf) {
     const int p = hf >> 1, h = hf & 1;
     const size_t f = (size_t)p * ne + (h ? m.nbr[(size_t)(2 * p) * ne + e] : e);
     const int ls = h ? 2 * p : 2 * p + 1;
-    const double* geo = ct.fGeo + f * GF * NFQ;
+    const R* geo = ct.fGeo + f * GF * NFQ;
     __syncthreads();
     for (int i = tid; i < NS * NC * NFQ; i += 128) {
       const int gq = i % NFQ, k = (i / NFQ) % NC, s = i / (NC * NFQ), c = k / DIM, j = k % DIM;
@@ -286,11 +284,11 @@ __global__ __launch_bounds__(128) void k_volume_curved(const double* __restrict_
     if (rg < NRG) {
 #pragma unroll 5
       for (int gq = 0; gq < NFQ; ++gq) {
-        const double p0 = sPs[gq * NB + a0], p1 = sPs[gq * NB + a1];
+        const R p0 = sPs[gq * NB + a0], p1 = sPs[gq * NB + a1];
 #pragma unroll
         for (int r = 0; r < RG; ++r) {
           const int row = rg * RG + r < NR ? rg * RG + r : NR - 1;
-          const double x = sXs[row * NFQ + gq];
+          const R x = sXs[row * NFQ + gq];
           acc[r][0] += p0 * x;
           acc[r][1] += p1 * x;
         }
@@ -317,20 +315,20 @@ __global__ __launch_bounds__(128) void k_volume_curved(const double* __restrict_
   // neighbouring words
   for (int i = tid; i < NA; i += 128) {  // L^{-1} rho_t
     const int b = i % NB, col = i - b;
-    double acc = 0.0;
+    R acc = 0.0;
     for (int a = 0; a < NB; ++a) {
-      const double l = sLc[a * NB - a * (a - 1) / 2 + b - a];
-      acc += (a <= b ? l : 0.0) * sA[col + a];
+      const R l = sLc[a * NB - a * (a - 1) / 2 + b - a];
+      acc += (a <= b ? l : R(0)) * sA[col + a];
     }
     sB[i] = acc;
   }
   __syncthreads();
   for (int i = tid; i < NA; i += 128) {  // Rt = L^{-T} L^{-1} rho_t, value and tangent interleaved
     const int a = i % NB, col = i - a;
-    double acc = 0.0;
+    R acc = 0.0;
     for (int b = 0; b < NB; ++b) {
-      const double l = sL[b * (b + 1) / 2 + a];
-      acc += (b >= a ? l : 0.0) * sB[col + b];
+      const R l = sL[b * (b + 1) / 2 + a];
+      acc += (b >= a ? l : R(0)) * sB[col + b];
     }
     sA[(i % (NC * NB)) * NS + i / (NC * NB)] = acc;
   }
@@ -338,13 +336,13 @@ __global__ __launch_bounds__(128) void k_volume_curved(const double* __restrict_
 
   if (tid < NQ) {
     const double kap = ph.mu * ph.gamma / (ph.prandtl * (ph.gamma - 1.0));
-    const double* geo = ct.vGeo + (size_t)e * GV * NQ + tid;
-    double K[DIM][DIM];
+    const R* geo = ct.vGeo + (size_t)e * GV * NQ + tid;
+    R K[DIM][DIM];
     for (int i = 0; i < DIM; ++i)
       for (int r = 0; r < DIM; ++r) K[i][r] = geo[(size_t)(i * DIM + r) * NQ];
-    const double wd = geo[(size_t)(DIM * DIM) * NQ];
-    const double* ps = ct.rPsiT + tid;
-    const double* dps = ct.rDPsiT + tid;
+    const R wd = geo[(size_t)(DIM * DIM) * NQ];
+    const R* ps = ct.rPsiT + tid;
+    const R* dps = ct.rDPsiT + tid;
     T u[NV], G[NV][DIM];
     {
       T gx[NV][DIM];
@@ -354,11 +352,11 @@ __global__ __launch_bounds__(128) void k_volume_curved(const double* __restrict_
       }
 #pragma unroll 2
       for (int b = 0; b < NB; ++b) {  // each table entry read once for all variables
-        const double pb = ps[b * NQ];
-        double db[DIM];
+        const R pb = ps[b * NQ];
+        R db[DIM];
         for (int r = 0; r < DIM; ++r) db[r] = dps[(r * NB + b) * NQ];
         for (int c = 0; c < NV; ++c) {
-          const T x = ld2<JVP>(sU + (c * NB + b) * NS);
+          const T x = ld2<JVP, R>(sU + (c * NB + b) * NS);
           u[c] += pb * x;
           for (int r = 0; r < DIM; ++r) gx[c][r] += db[r] * x;
         }
@@ -372,16 +370,16 @@ __global__ __launch_bounds__(128) void k_volume_curved(const double* __restrict_
     }
 #pragma unroll 2
     for (int b = 0; b < NB; ++b) {  // + R^K
-      const double pb = ps[b * NQ];
+      const R pb = ps[b * NQ];
       for (int c = 0; c < NV; ++c)
         for (int r = 0; r < DIM; ++r)
-          G[c][r] += pb * ld2<JVP>(sA + ((c * DIM + r) * NB + b) * NS);
+          G[c][r] += pb * ld2<JVP, R>(sA + ((c * DIM + r) * NB + b) * NS);
     }
     T rinv, vel[DIM], pr;
     primitives<T, DIM>(u, ph.gamma, rinv, vel, pr);
     ViscPrep<T, DIM> vp;
     visc_prep<T, DIM>(u, G, ph.gamma, vp);
-    double Ft[DIM][NV];
+    R Ft[DIM][NV];
     for (int r = 0; r < DIM; ++r)
       for (int c = 0; c < NV; ++c) Ft[r][c] = 0.0;
     for (int p = 0; p < DIM; ++p) {
@@ -389,7 +387,7 @@ __global__ __launch_bounds__(128) void k_volume_curved(const double* __restrict_
       conv_flux_dir<T, DIM>(u, vel, pr, p, Fc);
       visc_flux_dir<T, DIM>(vp, p, ph.mu, kap, Fv);
       for (int c = 0; c < NV; ++c) {
-        const double fp = out_part(Fc[c] - Fv[c]);
+        const R fp = out_part(Fc[c] - Fv[c]);
         for (int r = 0; r < DIM; ++r) Ft[r][c] += K[p][r] * fp;
       }
     }
@@ -400,12 +398,12 @@ __global__ __launch_bounds__(128) void k_volume_curved(const double* __restrict_
 
   if (tid < DIM * NB) {  // volume projection on d psi_a / d xi_r, one thread per (r, a)
     const int a = tid % NB, r = tid / NB;
-    double acc[NV];
+    R acc[NV];
     for (int c = 0; c < NV; ++c) acc[c] = 0.0;
-    const double* dp = ct.rDPsi + r * NB + a;
+    const R* dp = ct.rDPsi + r * NB + a;
 #pragma unroll 4
     for (int q = 0; q < NQ; ++q) {
-      const double d = dp[q * DIM * NB];
+      const R d = dp[q * DIM * NB];
       for (int c = 0; c < NV; ++c) acc[c] += d * sB[(q * DIM + r) * NV + c];
     }
     for (int c = 0; c < NV; ++c) sA[(r * NV + c) * NB + a] = acc[c];
@@ -413,21 +411,22 @@ __global__ __launch_bounds__(128) void k_volume_curved(const double* __restrict_
   __syncthreads();
   for (int i = tid; i < NX; i += 128) {
     const int a = i % NB, c = i / NB;
-    double y = sY[i];
+    R y = sY[i];
     for (int r = 0; r < DIM; ++r) y -= sA[(r * NV + c) * NB + a];
     sY[i] = y;
   }
   __syncthreads();
   for (int i = tid; i < NX; i += 128) {
     const int b = i % NB, c = i / NB;
-    double acc = 0.0;
+    R acc = 0.0;
     for (int a = 0; a < NB; ++a) {
-      const double l = sLc[a * NB - a * (a - 1) / 2 + b - a];
-      acc += (a <= b ? l : 0.0) * sY[c * NB + a];
+      const R l = sLc[a * NB - a * (a - 1) / 2 + b - a];
+      acc += (a <= b ? l : R(0)) * sY[c * NB + a];
     }
     const size_t idx = (size_t)(c * NB + b) * ne + e;
-    if (JVP) acc += shift * V[idx];
-    out[idx] = acc;
+    double o = acc;
+    if (JVP) o += shift * V[idx];
+    out[idx] = o;
   }
 }
 
@@ -502,14 +501,17 @@ __global__ __launch_bounds__(256) void k_wave_speed_curved(double* __restrict__ 
   X(4, 3, 20, 4)             \
   X(5, 3, 35, 5)
 
-hipError_t launch_modal_curved(int cfg, bool jvp, const double* U, const double* V, const CurvedTables& ct,
-                               int64_t ne, hipStream_t s) {
+namespace {
+
+template <class R>
+hipError_t modal_curved(int cfg, bool jvp, const double* U, const double* V, const CurvedTablesT<R>& ct, int64_t ne,
+                        hipStream_t s) {
 #define X(id, d, nb_, nq_)                                                          \
   case id: {                                                                        \
     if (jvp)                                                                        \
-      k_modal_curved<d, nb_, true><<<(unsigned)ne, 64, 0, s>>>(U, V, ct, ne);       \
+      k_modal_curved<R, d, nb_, true><<<(unsigned)ne, 64, 0, s>>>(U, V, ct, ne);    \
     else                                                                            \
-      k_modal_curved<d, nb_, false><<<(unsigned)ne, 64, 0, s>>>(U, V, ct, ne);      \
+      k_modal_curved<R, d, nb_, false><<<(unsigned)ne, 64, 0, s>>>(U, V, ct, ne);   \
     return hipGetLastError();                                                       \
   }
   switch (cfg) { DG_CURVED_CONFIGS(X) }
@@ -517,15 +519,15 @@ hipError_t launch_modal_curved(int cfg, bool jvp, const double* U, const double*
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_face_curved(int cfg, bool jvp, const CurvedTables& ct, const Mesh& m, const Phys& ph,
-                              hipStream_t s) {
+template <class R>
+hipError_t face_curved(int cfg, bool jvp, const CurvedTablesT<R>& ct, const Mesh& m, const Phys& ph, hipStream_t s) {
 #define X(id, d, nb_, nq_)                                                          \
   case id: {                                                                        \
     dim3 grid((unsigned)m.ne, d);                                                   \
     if (jvp)                                                                        \
-      k_face_curved<d, nb_, nq_, true><<<grid, 64, 0, s>>>(ct, m, ph);              \
+      k_face_curved<R, d, nb_, nq_, true><<<grid, 64, 0, s>>>(ct, m, ph);           \
     else                                                                            \
-      k_face_curved<d, nb_, nq_, false><<<grid, 64, 0, s>>>(ct, m, ph);             \
+      k_face_curved<R, d, nb_, nq_, false><<<grid, 64, 0, s>>>(ct, m, ph);          \
     return hipGetLastError();                                                       \
   }
   switch (cfg) { DG_CURVED_CONFIGS(X) }
@@ -533,19 +535,47 @@ hipError_t launch_face_curved(int cfg, bool jvp, const CurvedTables& ct, const M
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_volume_curved(int cfg, bool jvp, const double* V, const CurvedTables& ct, double* out,
-                                double shift, const Mesh& m, const Phys& ph, hipStream_t s) {
-#define X(id, d, nb_, nq_)                                                                     \
-  case id: {                                                                                   \
-    if (jvp)                                                                                   \
-      k_volume_curved<d, nb_, nq_, true><<<(unsigned)m.ne, 128, 0, s>>>(V, ct, out, shift, m, ph);  \
-    else                                                                                       \
-      k_volume_curved<d, nb_, nq_, false><<<(unsigned)m.ne, 128, 0, s>>>(V, ct, out, shift, m, ph); \
-    return hipGetLastError();                                                                  \
+template <class R>
+hipError_t volume_curved(int cfg, bool jvp, const double* V, const CurvedTablesT<R>& ct, double* out, double shift,
+                         const Mesh& m, const Phys& ph, hipStream_t s) {
+#define X(id, d, nb_, nq_)                                                                          \
+  case id: {                                                                                        \
+    if (jvp)                                                                                        \
+      k_volume_curved<R, d, nb_, nq_, true><<<(unsigned)m.ne, 128, 0, s>>>(V, ct, out, shift, m, ph);  \
+    else                                                                                            \
+      k_volume_curved<R, d, nb_, nq_, false><<<(unsigned)m.ne, 128, 0, s>>>(V, ct, out, shift, m, ph); \
+    return hipGetLastError();                                                                       \
   }
   switch (cfg) { DG_CURVED_CONFIGS(X) }
 #undef X
   return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t launch_modal_curved(int cfg, bool jvp, const double* U, const double* V, const CurvedTables& ct,
+                               int64_t ne, hipStream_t s) {
+  return modal_curved<double>(cfg, jvp, U, V, ct, ne, s);
+}
+hipError_t launch_face_curved(int cfg, bool jvp, const CurvedTables& ct, const Mesh& m, const Phys& ph,
+                              hipStream_t s) {
+  return face_curved<double>(cfg, jvp, ct, m, ph, s);
+}
+hipError_t launch_volume_curved(int cfg, bool jvp, const double* V, const CurvedTables& ct, double* out,
+                                double shift, const Mesh& m, const Phys& ph, hipStream_t s) {
+  return volume_curved<double>(cfg, jvp, V, ct, out, shift, m, ph, s);
+}
+hipError_t launch_modal_curved_f32(int cfg, bool jvp, const double* U, const double* V, const CurvedTablesF& ct,
+                                   int64_t ne, hipStream_t s) {
+  return modal_curved<float>(cfg, jvp, U, V, ct, ne, s);
+}
+hipError_t launch_face_curved_f32(int cfg, bool jvp, const CurvedTablesF& ct, const Mesh& m, const Phys& ph,
+                                  hipStream_t s) {
+  return face_curved<float>(cfg, jvp, ct, m, ph, s);
+}
+hipError_t launch_volume_curved_f32(int cfg, bool jvp, const double* V, const CurvedTablesF& ct, double* out,
+                                    double shift, const Mesh& m, const Phys& ph, hipStream_t s) {
+  return volume_curved<float>(cfg, jvp, V, ct, out, shift, m, ph, s);
 }
 
 hipError_t launch_project_curved(int cfg, const double* f, double* w, const CurvedTables& ct, int64_t ne,
@@ -564,7 +594,7 @@ hipError_t launch_wave_speed_curved(int cfg, const double* w, double* partial, i
                                     const Mesh& m, const Phys& ph, hipStream_t s) {
 #define X(id, d, nb_, nq_)                                                                  \
   case id: {                                                                                \
-    k_modal_curved<d, nb_, false><<<(unsigned)m.ne, 64, 0, s>>>(w, w, ct, m.ne);            \
+    k_modal_curved<double, d, nb_, false><<<(unsigned)m.ne, 64, 0, s>>>(w, w, ct, m.ne);            \
     k_wave_speed_curved<d, nb_, nq_><<<nblocks, 256, 0, s>>>(partial, ct, m, ph);           \
     return hipGetLastError();                                                               \
   }

@@ -34,14 +34,17 @@ struct Tables {
 
 // Curved (multilinear) elements: device tables (layouts as in CurvedHost) and
 // the face kernel's outputs read by the volume kernel.
-struct CurvedTables {
+template <class R>
+struct CurvedTablesT {
   // shared reference tables (see CurvedHost) and per-element / per-face data
-  const double *rPsiT, *rDPsiT, *rDPsi, *rFPsiT, *rFDPsiT, *rFPsi;
-  const double *Linv, *vGeo, *fGeo, *fP;
-  double *Ut, *Vt;  // [ne][nv][nb]          L^{-T} U and L^{-T} V
-  double* fJmp;     // [dim*ne][2][nv][nfq]  [[U]] at the face points (value, tangent)
-  double* fHn;      // [dim*ne][nv][nfq]     w_f|J_f| times the normal flux (or its tangent)
+  const R *rPsiT, *rDPsiT, *rDPsi, *rFPsiT, *rFDPsiT, *rFPsi;
+  const R *Linv, *vGeo, *fGeo, *fP;
+  R *Ut, *Vt;  // [ne][nv][nb]          L^{-T} U and L^{-T} V
+  R* fJmp;     // [dim*ne][2][nv][nfq]  [[U]] at the face points (value, tangent)
+  R* fHn;      // [dim*ne][nv][nfq]     w_f|J_f| times the normal flux (or its tangent)
 };
+using CurvedTables = CurvedTablesT<double>;
+using CurvedTablesF = CurvedTablesT<float>;  // the reduced-precision curved operator
 
 // Operator tables pre-permuted into the operand order of the FP64 MFMA
 // 16x16x4 instruction (A[i][k] at lane i + 16k, B[k][j] at lane j + 16k,
@@ -177,6 +180,12 @@ hipError_t launch_face_curved(int cfg, bool jvp, const CurvedTables& ct, const M
                               hipStream_t s);
 hipError_t launch_volume_curved(int cfg, bool jvp, const double* V, const CurvedTables& ct, double* out,
                                 double shift, const Mesh& m, const Phys& ph, hipStream_t s);
+hipError_t launch_modal_curved_f32(int cfg, bool jvp, const double* U, const double* V, const CurvedTablesF& ct,
+                                   int64_t ne, hipStream_t s);
+hipError_t launch_face_curved_f32(int cfg, bool jvp, const CurvedTablesF& ct, const Mesh& m, const Phys& ph,
+                                  hipStream_t s);
+hipError_t launch_volume_curved_f32(int cfg, bool jvp, const double* V, const CurvedTablesF& ct, double* out,
+                                    double shift, const Mesh& m, const Phys& ph, hipStream_t s);
 hipError_t launch_project_curved(int cfg, const double* f, double* w, const CurvedTables& ct, int64_t ne,
                                  hipStream_t s);
 hipError_t launch_wave_speed_curved(int cfg, const double* w, double* partial, int nblocks, const CurvedTables& ct,

@@ -370,8 +370,8 @@ dg_status dg_mg_setup(dg_context* c, const double* w, double shift, const dg_mg_
   if (o->coarse_ilu != 0 && o->coarse_ilu != 1) return fail(DG_ERR_ARG, "coarse_ilu must be 0 or 1");
   if (o->coarse_ilu && c->nv * binom(o->orders[o->n_levels - 1] + c->dim, c->dim) > 64)
     return fail(DG_ERR_ARG, "block ILU(0) needs coarsest blocks of at most 64 rows");
-  if (o->fine_precision == DG_FP32 && !(c->use_mfma && c->d_mtab_f))
-    return fail(DG_ERR_ARG, "the FP32 fine operator needs a 3D P2-P4 configuration with MFMA kernels");
+  if (o->fine_precision == DG_FP32 && !has_f32(c))
+    return fail(DG_ERR_ARG, "the FP32 fine operator needs a curved mesh or a 3D P2-P4 lattice configuration");
   hipStream_t s = (hipStream_t)stream;
   const int64_t ne = c->ne;
   const int dim = c->dim, nv = c->nv, nf = 2 * dim;

@@ -5,7 +5,8 @@ own orthonormalised basis, Nanson normals and area weights.
 
 Bounds as on the affine lattices: residual and exact Jv 1e-12 relative
 (the residual normalised by the larger of its total and volume parts), block
-Jacobi 1e-11, one V-cycle 1e-9.
+Jacobi 1e-11, one V-cycle 1e-9; the FP32 operator 1e-5 (and above 1e-10),
+FP32 block factors 1e-4.
 """
 import sys
 
@@ -105,4 +106,47 @@ def test_curved_block_jacobi_and_vcycle():
     X = o.from_flat(x.cpu().numpy())
     res = np.linalg.norm(o.to_flat(o.operator(U, X, shift)) - b.cpu().numpy()) / b.norm().item()
     assert res <= 1e-9
+    g.close()
+
+
+@pytest.mark.parametrize("N,k,sp,nq,flux", [CASES[0], CASES[3], CASES[5]], ids=[IDS[0], IDS[3], IDS[5]])
+def test_curved_fp32_operator_error_against_the_oracle(N, k, sp, nq, flux):
+    """The curved kernels in FP32 (tables, contractions, pointwise fluxes;
+    FP64 inputs and outputs): a reduced-precision operator for the
+    preconditioners, within 1e-5 of the FP64 oracle and genuinely FP32."""
+    _say(f"curved fp32 operator {N} {sp}{k} {flux}")
+    mesh, o, g, U, w, fld = make_curved(N, k, sp, nq, flux)
+    R, Rv = o.residual(U, return_parts=True)
+    r32 = g.residual(w, precision="fp32").cpu().numpy()
+    err_r = np.linalg.norm(r32 - o.to_flat(R)) / max(np.linalg.norm(R), np.linalg.norm(Rv))
+    V = np.random.default_rng(866).standard_normal(U.shape)
+    v = torch.tensor(o.to_flat(V), device="cuda")
+    err_j = rel(g.jvp(w, v, shift=3.0, mode="exact_fp32").cpu().numpy(), o.to_flat(o.jvp(U, V) + 3.0 * V))
+    _say(f"  fp32 residual error {err_r:.2e}, Jv error {err_j:.2e}")
+    assert 1e-10 < err_r <= 1e-5 and 1e-10 < err_j <= 1e-5
+    g.close()
+
+
+def test_curved_fp32_probing_and_smoothing():
+    """Block Jacobi probed with the FP32 curved operator (FP32 factors) and
+    the V-cycle with FP32 fine-level smoothing: both precondition an FGMRES
+    solve whose FP64 true residual reaches the tolerance."""
+    _say("curved fp32 probing and smoothing")
+    mesh, o, g, U, w, fld = make_curved((2, 2, 2), 2, "P", 3)
+    shift = 8.0
+    r = np.random.default_rng(5).standard_normal(U.shape)
+    rt = torch.tensor(o.to_flat(r), device="cuda")
+    D = o.block_diagonal(U, shift=shift)
+    g.block_setup(w, shift, storage="fp32")
+    z = g.block_apply(rt).cpu().numpy()
+    assert rel(z, o.to_flat(block_solve(D, r.reshape(o.ne, -1)).reshape(U.shape))) <= 1e-4
+    b = torch.tensor(o.to_flat(np.random.default_rng(6).standard_normal(U.shape)), device="cuda")
+    for precond in ("bj", "mg"):
+        if precond == "mg":
+            g.mg_setup(w, shift, (2, 1), (3, 10), storage="fp32", use_graph=True, fine_precision="fp32")
+        x, st = g.fgmres(w, shift, b, rtol=1e-10, max_iter=500, precond=precond)
+        assert st["converged"] == 1, precond
+        X = o.from_flat(x.cpu().numpy())
+        res = np.linalg.norm(o.to_flat(o.operator(U, X, shift)) - b.cpu().numpy()) / b.norm().item()
+        assert res <= 1e-9, (precond, res)
     g.close()
