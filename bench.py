@@ -6,7 +6,7 @@ one backward-Euler system (P4, 24^3 hexes, CFL 100, block-Jacobi).
 
 One step = one Jv (gradient, face and volume kernels) on data resident in HBM.
 Prints one JSON line (see the keys below).  --gpus > 1 is not supported:
-this build runs on a single GPU.
+the library runs on a single GPU.
 """
 import argparse
 import json
@@ -22,15 +22,16 @@ sys.path.insert(0, ROOT)
 METRIC = "DOFs/s for matrix-free DG Jv (p=3, 3D hex); wall time to 1e-8 FGMRES solve"
 PEAK_FP64 = 78.6  # TFLOP/s, MI355X dense FP64 matrix (MFMA) peak
 PEAK_HBM = 8000.0  # GB/s
+PEAK_FP32 = 157.3  # TFLOP/s, MI355X dense FP32 matrix peak
 
 
 def jv_kernel_flops(ne, nb, nq, nfq, d):
-    """Algorithmic contraction flops of the exact Jv per launch (see DESIGN.md).
+    """Algorithmic contraction flops of the exact Jv per launch.
 
     Per element: volume part 2*[2 Nq Nb n (1+3d)] (interpolation of U and
     grad U, lifting at the volume points, projection; value and tangent);
     face part 2*[d * 2 Nfq Nb n (2d+8)] (traces of both sides, local
-    liftings, face projection).  Placement in this build: the d lifting units
+    liftings, face projection).  Placement in these kernels: the d lifting units
     are the gradient kernel's (modal corrected gradients), the face
     projection (2 of the 2d+8 face units) is done by the volume kernel.
     """
@@ -103,6 +104,49 @@ def cpu_baseline(sample_elems=1024):
                       f"({dofs} DOFs), complex-step numpy oracle, {t:.2f} s"}
 
 
+PHASES = ("grad_jvp", "face_jvp", "vol_jvp", "grad_jvp_f32", "face_jvp_f32", "vol_jvp_f32", "block_probe",
+          "block_invert", "block_apply", "arnoldi", "mg_vcycle")
+STORAGE_BYTES = {"fp64": 8, "fp32": 4, "bf16": 2}
+
+
+def solve_phases(g, w, shift, b, cfg, precond, storage, curved):
+    """Per-phase breakdown of one solve: the block setup (block Jacobi) and
+    the solve again with HIP events around each phase (the timed run above
+    carries no events).  Each phase: total ms, calls, ms per call; the Jv
+    phases with their contraction flops against the FP64 (or FP32) matrix
+    peak on affine meshes, the block apply with its bytes against HBM."""
+    import torch
+    g.set_profiling(True)
+    for k in PHASES:
+        g.kernel_time(k)  # reset
+    if precond != "mg":
+        g.block_setup(w, shift, storage=storage)
+    g.fgmres(w, shift, b, restart=cfg["restart"], max_iter=3000, rtol=cfg["rtol"], precond=precond)
+    torch.cuda.synchronize()
+    g.set_profiling(False)
+    out = {}
+    for k in PHASES:
+        ms, n = g.kernel_time(k)
+        if n:
+            out[k] = {"ms_total": round(ms, 3), "calls": n, "ms_per_call": round(ms / n, 4)}
+    nfq = cfg["nq1d"] ** 2
+    fl = jv_kernel_flops(g.ne, g.nb, g.nq, nfq, 3)
+    for suf, peak in (("", PEAK_FP64), ("_f32", PEAK_FP32)):
+        ks = [k + suf for k in KERNELS]
+        if curved or not all(k in out for k in ks):
+            continue
+        ms = sum(out[k]["ms_per_call"] for k in ks)
+        tf = sum(fl.values()) / (ms * 1e-3) / 1e12
+        out["jv" + suf] = {"ms_per_call": round(ms, 4), "achieved_tflops": round(tf, 2), "peak": peak,
+                           "frac": round(tf / peak, 3)}
+    if "block_apply" in out:
+        m = g.nv * g.nb
+        by = g.ne * m * m * STORAGE_BYTES[storage] + 2 * g.ndof * 8
+        gbs = by / (out["block_apply"]["ms_per_call"] * 1e-3) / 1e9
+        out["block_apply"].update({"bytes_per_call": by, "achieved_gbs": round(gbs, 1), "frac_hbm": round(gbs / PEAK_HBM, 3)})
+    return out
+
+
 def time_to_tolerance(storage="fp64", precond="bj", fine_precision="fp64", rescale=False, coarse_ilu=False,
                       preset="cfg3"):
     """Backward-Euler system of the P4 24^3 workload solved by FGMRES(30) to 1e-8,
@@ -140,7 +184,7 @@ def time_to_tolerance(storage="fp64", precond="bj", fine_precision="fp64", resca
     x, st = g.fgmres(w, shift, b, restart=cfg["restart"], max_iter=3000, rtol=cfg["rtol"], precond=precond)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    extra = {}
+    extra = {"phases": solve_phases(g, w, shift, b, cfg, precond, storage, curved=preset != "cfg3")}
     if precond == "mg":  # one preconditioner application (the captured V-cycle), outside the solve
         z = g.empty()
         g.mg_apply(b, out=z)
@@ -299,8 +343,8 @@ def main():
                     help="also run a plain 256 MiB device copy (reference kernel for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: --gpus {args.gpus} is not supported; this build runs on one GPU "
-              "(the multi-GPU sharding is a design note in DESIGN.md)", file=sys.stderr)
+        print(f"bench.py: --gpus {args.gpus} is not supported: the library runs on one GPU "
+              "(elements would shard into slabs with one halo exchange per Jv; not built)", file=sys.stderr)
         sys.exit(2)
 
     import torch

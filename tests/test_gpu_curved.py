@@ -150,3 +150,25 @@ def test_curved_fp32_probing_and_smoothing():
         res = np.linalg.norm(o.to_flat(o.operator(U, X, shift)) - b.cpu().numpy()) / b.norm().item()
         assert res <= 1e-9, (precond, res)
     g.close()
+
+
+def test_curved_rescaled_inherited_hierarchy():
+    """App. A on curved elements: the stabilisation part of every inherited
+    coarse operator rescaled level by level (1e-12 per level) and the
+    V-cycle on them (1e-9), against the oracle."""
+    _say("curved rescaled hierarchy")
+    mesh, o, g, U, w, fld = make_curved((2, 2, 2), 2, "P", 3, mu=5e-2)
+    shift, orders, iters = 8.0, (2, 1), (3, 10)
+    mg = PMultigrid(o, U, shift, orders, iters, rescale=True)
+    g.mg_setup(w, shift, orders, iters, storage="fp64", use_graph=True, rescale=True)
+    rng = np.random.default_rng(24)
+    for l in range(1, mg.L + 1):
+        X = rng.standard_normal((o.ne, o.nvar, mg.nbs[l]))
+        y_o = (mg.A[l] @ X.reshape(-1)).reshape(X.shape)
+        xg = torch.tensor(np.ascontiguousarray(X.transpose(1, 2, 0)).reshape(-1), device="cuda")
+        y_g = g.mg_level_apply(l, xg).cpu().numpy().reshape(o.nvar, mg.nbs[l], o.ne).transpose(2, 0, 1)
+        assert np.linalg.norm(y_g - y_o) <= 1e-12 * np.linalg.norm(y_o), (l, np.linalg.norm(y_g - y_o))
+    R = rng.standard_normal(U.shape)
+    z_o = o.to_flat(mg.apply(R))
+    assert rel(g.mg_apply(torch.tensor(o.to_flat(R), device="cuda")).cpu().numpy(), z_o) <= 1e-9
+    g.close()
