@@ -476,13 +476,14 @@ CurvedHost build_curved_tables(const HostTables& T, int order, const double* xyz
   C.fGeo.assign((size_t)nfc * gf * nfq, 0.0);
   C.fP.assign((size_t)nfc * nfq * nfq, 0.0);
   parallel_chunks(nfc, [&](int64_t f0, int64_t f1) {
-    std::vector<double> ph((size_t)nfq * nb);
+    std::vector<double> ph((size_t)nfq * nb), xf((size_t)nfq * 3);
     for (int64_t f = f0; f < f1; ++f) {
       const int p = (int)(f / ne);
       const int64_t e = f % ne;
       const int64_t er = nbr[(size_t)e * 2 * dim + 2 * p + 1];
       double* g = &C.fGeo[(size_t)f * gf * nfq];
       double* P = &C.fP[(size_t)f * nfq * nfq];
+      double shift[3] = {0.0, 0.0, 0.0};
       for (int side = 0; side < 2; ++side) {
         const int64_t K = side == 0 ? e : er;
         const int s = side == 0 ? 2 * p + 1 : 2 * p;
@@ -494,6 +495,23 @@ CurvedHost build_curved_tables(const HostTables& T, int order, const double* xyz
           multilinear(dim, X, xi, x, J);
           const double dt = det_inv(dim, J, Ji);
           if (!(dt > 0.0)) throw std::invalid_argument("element " + std::to_string(K) + " has a non-positive Jacobian");
+          // conforming faces: both sides map face point fq to the same
+          // physical point, up to one periodic shift per face
+          if (side == 0) {
+            for (int i = 0; i < dim; ++i) xf[(size_t)fq * 3 + i] = x[i];
+          } else {
+            double dev = 0.0, scale = 0.0;
+            for (int i = 0; i < dim; ++i) {
+              const double d = xf[(size_t)fq * 3 + i] - x[i];
+              if (fq == 0) shift[i] = d;
+              dev = std::max(dev, std::fabs(d - shift[i]));
+              for (int r = 0; r < dim; ++r) scale = std::max(scale, std::fabs(J[i * 3 + r]));
+            }
+            if (dev > 1e-9 * scale)
+              throw std::invalid_argument("face " + std::to_string(p) + " of element " + std::to_string(e) +
+                                          " is not conforming: element " + std::to_string(K) +
+                                          " sees it with other corners or another orientation");
+          }
           for (int i = 0; i < dim; ++i)
             for (int r = 0; r < dim; ++r)
               g[(size_t)(dim + 1 + side * dim * dim + i * dim + r) * nfq + fq] = Ji[r * 3 + i];

@@ -64,6 +64,21 @@ def test_create_accepts_curved_meshes_and_rejects_inverted_elements():
     assert st == -1 and "Jacobian" in msg
 
 
+def test_create_rejects_nonconforming_curved_faces():
+    """Rotating one element's local frame by 90 degrees about z keeps its
+    Jacobian positive but makes its +-x faces disagree with the neighbour
+    list: the face points seen from both sides no longer coincide."""
+    mesh = synth.lattice_mesh((2, 2, 2), perturb=0.1, seed=1)
+    xyz = np.array(mesh["elem_xyz"])
+    old = xyz[3].copy()
+    for i in range(2):
+        for j in range(2):
+            for k in range(2):
+                xyz[3][i + 2 * j + 4 * k] = old[(1 - j) + 2 * i + 4 * k]
+    st, msg = _create(_prm(), dict(mesh, elem_xyz=xyz))
+    assert st == -1 and "not conforming" in msg
+
+
 def test_create_rejects_inconsistent_neighbours():
     mesh = synth.lattice_mesh((3, 3, 3))
     mesh["elem_nbr"] = mesh["elem_nbr"].copy()
