@@ -53,6 +53,25 @@ DEV typename Scalar<JVP, R>::type ld2(const R* p) {
   }
 }
 
+// 16x16x4 matrix-core step: lane l supplies A[l%16][l/16] and B[l/16][l%16];
+// D[i][j] lands in lane j + 16 g, register r with i = drow(g, r).
+typedef double cv_f64x4 __attribute__((ext_vector_type(4)));
+typedef float cv_f32x4 __attribute__((ext_vector_type(4)));
+template <class R>
+struct CMma;
+template <>
+struct CMma<double> {
+  using frag = cv_f64x4;
+  static DEV frag mma(double a, double b, frag c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  static DEV int drow(int g, int r) { return g + 4 * r; }
+};
+template <>
+struct CMma<float> {
+  using frag = cv_f32x4;
+  static DEV frag mma(float a, float b, frag c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  static DEV int drow(int g, int r) { return 4 * g + r; }
+};
+
 template <class R, int DIM, int NB, bool JVP>
 __global__ __launch_bounds__(64) void k_modal_curved(const double* __restrict__ U, const double* __restrict__ V,
                                                      CurvedTablesT<R> ct, int64_t ne) {
@@ -229,9 +248,9 @@ __global__ __launch_bounds__(128) void k_volume_curved(const double* __restrict_
   constexpr int NBT = NB * (NB + 1) / 2, NC = NV * DIM, NX = NV * NB, GV = DIM * DIM + 1;
   constexpr int GF = DIM + 1 + 2 * DIM * DIM;
   constexpr int NA = NS * NC * NB, NF = NQ * DIM * NV;
-  constexpr int NR = NS * NC + NV, RG = 5, NRG = (NR + RG - 1) / RG, NAG = (NB + 1) / 2;
+  constexpr int NR = NS * NC + NV, MT = (NR + 15) / 16, NT = (NB + 15) / 16, NTW = (MT * NT + 1) / 2;
+  constexpr int KSF = (NFQ + 3) / 4;
   constexpr int NSTG = NR * NFQ + NFQ * NB;  // one face: w n [[U]], w Hn, psi
-  static_assert(NRG * NAG <= 128, "one thread per 2-mode x RG-row block of a face product");
   static_assert(NQ <= 128, "one thread per volume point");
   static_assert(DIM * NB <= 128, "one thread per (reference direction, mode) in the projection");
   static_assert(DIM * NV * NB <= NA, "projection partials fit the lifting buffer");
@@ -262,10 +281,14 @@ __global__ __launch_bounds__(128) void k_volume_curved(const double* __restrict_
   // (value, tangent) then w Hn; each thread accumulates a 2-mode x RG-row
   // block of their products with psi of the face: the local liftings rho_t
   // and the face part of the projection.
-  R acc[RG][2];
-  for (int r = 0; r < RG; ++r) acc[r][0] = acc[r][1] = 0.0;
-  const int ag = tid % NAG, rg = tid / NAG;
-  const int a0 = 2 * ag, a1 = a0 + 1 < NB ? a0 + 1 : a0;
+  // Each of the two waves accumulates its share of the 16x16 tiles of the
+  // (row x mode) product over the 2d faces on the matrix cores; K runs over
+  // the face points (zero-padded to a multiple of 4).
+  using MM = CMma<R>;
+  typename MM::frag acc[NTW];
+  for (int t = 0; t < NTW; ++t)
+    for (int r = 0; r < 4; ++r) acc[t][r] = R(0);
+  const int wv = tid >> 6, ln = tid & 63, li = ln & 15, lg = ln >> 4;
   R* sXs = sB;                  // [NR][NFQ]
   R* sPs = sB + NR * NFQ;       // [NFQ][NB]
   for (int hf = 0; hf < 2 * DIM; ++hf) {
@@ -281,31 +304,34 @@ __global__ __launch_bounds__(128) void k_volume_curved(const double* __restrict_
     for (int i = tid; i < NV * NFQ; i += 128) sXs[NS * NC * NFQ + i] = ct.fHn[f * NV * NFQ + i] * (h ? -1.0 : 1.0);
     for (int i = tid; i < NFQ * NB; i += 128) sPs[i] = ct.rFPsi[(size_t)ls * NFQ * NB + i];
     __syncthreads();
-    if (rg < NRG) {
-#pragma unroll 5
-      for (int gq = 0; gq < NFQ; ++gq) {
-        const R p0 = sPs[gq * NB + a0], p1 = sPs[gq * NB + a1];
 #pragma unroll
-        for (int r = 0; r < RG; ++r) {
-          const int row = rg * RG + r < NR ? rg * RG + r : NR - 1;
-          const R x = sXs[row * NFQ + gq];
-          acc[r][0] += p0 * x;
-          acc[r][1] += p1 * x;
+    for (int t = 0; t < NTW; ++t) {
+      const int tile = wv + 2 * t;
+      if (tile < MT * NT) {  // uniform per wave
+        const int row = (tile / NT) * 16 + li, mode = (tile % NT) * 16 + li;
+        const int rowc = row < NR ? row : NR - 1, modec = mode < NB ? mode : NB - 1;
+#pragma unroll
+        for (int ks = 0; ks < KSF; ++ks) {
+          const int k = 4 * ks + lg, kc = k < NFQ ? k : NFQ - 1;
+          const R av = sXs[rowc * NFQ + kc], bv = sPs[kc * NB + modec];
+          acc[t] = MM::mma((row < NR && k < NFQ) ? av : R(0), (mode < NB && k < NFQ) ? bv : R(0), acc[t]);
         }
       }
     }
   }
-  if (rg < NRG) {
 #pragma unroll
-    for (int r = 0; r < RG; ++r) {
-      const int row = rg * RG + r;
-      for (int t = 0; t < 2; ++t) {
-        const int a = t ? a1 : a0;
-        if (row >= NR || (t && a1 == a0)) continue;
-        if (row < NS * NC)
-          sA[row * NB + a] = -0.5 * acc[r][t];
-        else
-          sY[(row - NS * NC) * NB + a] = acc[r][t];
+  for (int t = 0; t < NTW; ++t) {
+    const int tile = wv + 2 * t;
+    if (tile < MT * NT) {
+      const int mode = (tile % NT) * 16 + li;
+      for (int r = 0; r < 4; ++r) {
+        const int row = (tile / NT) * 16 + MM::drow(lg, r);
+        if (row < NR && mode < NB) {
+          if (row < NS * NC)
+            sA[row * NB + mode] = R(-0.5) * acc[t][r];
+          else
+            sY[(row - NS * NC) * NB + mode] = acc[t][r];
+        }
       }
     }
   }
@@ -401,7 +427,7 @@ __global__ __launch_bounds__(128) void k_volume_curved(const double* __restrict_
     R acc[NV];
     for (int c = 0; c < NV; ++c) acc[c] = 0.0;
     const R* dp = ct.rDPsi + r * NB + a;
-#pragma unroll 4
+#pragma unroll 8
     for (int q = 0; q < NQ; ++q) {
       const R d = dp[q * DIM * NB];
       for (int c = 0; c < NV; ++c) acc[c] += d * sB[(q * DIM + r) * NV + c];
