@@ -454,7 +454,7 @@ dg_status dg_create(const dg_params* prm, const dg_mesh* mesh, dg_context** out)
   if ((st = dalloc(&c->d_red, (size_t)64 * dgk::kRedBlocks)) != DG_OK) return cleanup(st);
   if ((st = dalloc(&c->d_scal, (size_t)256)) != DG_OK) return cleanup(st);
   if ((st = dalloc(&c->d_flag, (size_t)16)) != DG_OK) return cleanup(st);
-  if (hipHostMalloc((void**)&c->h_pin, 256 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+  if (hipHostMalloc((void**)&c->h_pin, 512 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
     c->h_pin = nullptr;
     return cleanup(fail(DG_ERR_OOM, "pinned host allocation failed"));
   }
@@ -499,6 +499,8 @@ void dg_destroy(dg_context* c) {
   mg_destroy(c->mg);
   mlp_destroy(c->mlp);
   if (c->h_pin) (void)hipHostFree(c->h_pin);
+  for (int i = 0; i < 2; ++i)
+    if (c->ev_rb[i]) (void)hipEventDestroy(c->ev_rb[i]);
   delete c;
 }
 
@@ -664,6 +666,8 @@ dg_status dg_fgmres_solve(dg_context* c, const double* w, double shift, const do
     if ((st = dalloc(&c->d_Z, (size_t)m * n)) != DG_OK) return st;
     c->kry_m = m;
   }
+  for (int i = 0; i < 2; ++i)
+    if (!c->ev_rb[i]) HIPCHK(hipEventCreateWithFlags(&c->ev_rb[i], hipEventDisableTiming));
   const double* rw = nullptr;
   if (opts->jvp_mode == DG_JVP_FD) {
     if ((st = dalloc(&c->d_rw, (size_t)n)) != DG_OK) return st;
@@ -727,8 +731,52 @@ dg_status dg_fgmres_solve(dg_context* c, const double* w, double shift, const do
     std::fill(H.begin(), H.end(), 0.0);
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
-    int k = 0;
-    for (int j = 0; j < m; ++j) {
+    // The Hessenberg column of iteration j travels to the host asynchronously
+    // (pinned slot j % 2, event ev_rb[j % 2]); the host applies its Givens
+    // rotation and tests convergence while iteration j + 1 runs on the GPU.
+    // An iteration enqueued past the stopping point is discarded (with the
+    // V-cycle as preconditioner every column is processed before the next
+    // iteration is enqueued).
+    int k = 0, pend = -1;
+    bool stop = false;
+    auto process = [&](int jj) -> dg_status {
+      HIPCHK(hipEventSynchronize(c->ev_rb[jj & 1]));
+      const double* hp = c->h_pin + 256 * (jj & 1);
+      const double w0 = hp[2], hn = hp[3];
+      if (!std::isfinite(hn)) return fail(DG_ERR_NONFINITE, "Arnoldi vector is not finite");
+      double* Hc = &H[(size_t)jj * (m + 1)];  // column jj, rows 0..jj+1
+      for (int i = 0; i <= jj; ++i) Hc[i] = mgs ? hp[16 + i] : hp[16 + i] + hp[80 + i];
+      Hc[jj + 1] = hn;
+      for (int i = 0; i < jj; ++i) {
+        const double t = cs[i] * Hc[i] + sn[i] * Hc[i + 1];
+        Hc[i + 1] = -sn[i] * Hc[i] + cs[i] * Hc[i + 1];
+        Hc[i] = t;
+      }
+      const double den = std::hypot(Hc[jj], Hc[jj + 1]);
+      cs[jj] = den > 0.0 ? Hc[jj] / den : 1.0;
+      sn[jj] = den > 0.0 ? Hc[jj + 1] / den : 0.0;
+      Hc[jj] = den;
+      Hc[jj + 1] = 0.0;
+      g[jj + 1] = -sn[jj] * g[jj];
+      g[jj] = cs[jj] * g[jj];
+      k = jj + 1;
+      ++iters;
+      est = std::fabs(g[jj + 1]);
+      // judge of the learned preconditioner: a convergence factor above the
+      // reference one after judge_after iterations switches to block Jacobi
+      // (legal in flexible GMRES: every z_j is stored)
+      if (prec == DG_PREC_MLP && opts->rho_ref > 0.0 && iters == judge_after && c->blk_ready && d0 > 0.0) {
+        const double rho_now = std::exp(std::log(std::max(est, 1e-300) / d0) / iters);
+        if (rho_now > opts->rho_ref) {
+          prec = DG_PREC_BJ;
+          ++fallbacks;
+        }
+      }
+      const bool brk = hn <= 1e-14 * w0;
+      stop = est <= rtol * bnorm || brk || iters >= max_iter;
+      return DG_OK;
+    };
+    for (int j = 0; j < m && !stop; ++j) {
       double* Vj = V + (size_t)j * n;
       double* Zj = Z + (size_t)j * n;
       double* Wn = V + (size_t)(j + 1) * n;
@@ -753,42 +801,17 @@ dg_status dg_fgmres_solve(dg_context* c, const double* w, double shift, const do
         }
       }
       if ((st = norm2(c, Wn, dS + 3, s)) != DG_OK) return st;
-      if ((st = readback(dS, 144)) != DG_OK) return st;
-      const double* hp = c->h_pin;
-      const double w0 = hp[2], hn = hp[3];
-      if (!std::isfinite(hn)) return fail(DG_ERR_NONFINITE, "Arnoldi vector is not finite");
-      double* Hc = &H[(size_t)j * (m + 1)];  // column j, rows 0..j+1
-      for (int i = 0; i <= j; ++i) Hc[i] = mgs ? hp[16 + i] : hp[16 + i] + hp[80 + i];
-      Hc[j + 1] = hn;
-      for (int i = 0; i < j; ++i) {
-        const double t = cs[i] * Hc[i] + sn[i] * Hc[i + 1];
-        Hc[i + 1] = -sn[i] * Hc[i] + cs[i] * Hc[i + 1];
-        Hc[i] = t;
-      }
-      const double den = std::hypot(Hc[j], Hc[j + 1]);
-      cs[j] = den > 0.0 ? Hc[j] / den : 1.0;
-      sn[j] = den > 0.0 ? Hc[j + 1] / den : 0.0;
-      Hc[j] = den;
-      Hc[j + 1] = 0.0;
-      g[j + 1] = -sn[j] * g[j];
-      g[j] = cs[j] * g[j];
-      k = j + 1;
-      ++iters;
-      est = std::fabs(g[j + 1]);
-      // judge of the learned preconditioner: a convergence factor above the
-      // reference one after judge_after iterations switches to block Jacobi
-      // (legal in flexible GMRES: every z_j is stored)
-      if (prec == DG_PREC_MLP && opts->rho_ref > 0.0 && iters == judge_after && c->blk_ready && d0 > 0.0) {
-        const double rho_now = std::exp(std::log(std::max(est, 1e-300) / d0) / iters);
-        if (rho_now > opts->rho_ref) {
-          prec = DG_PREC_BJ;
-          ++fallbacks;
-        }
-      }
-      const bool brk = hn <= 1e-14 * w0;
-      if (est <= rtol * bnorm || brk || iters >= max_iter) break;
+      HIPCHK(hipMemcpyAsync(c->h_pin + 256 * (j & 1), dS, 144 * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipEventRecord(c->ev_rb[j & 1], s));
       HIPCHK(dgk::launch_scale_dev(n, Wn, dS + 3, Wn, s));
+      if (prec == DG_PREC_MG) {  // a V-cycle per iteration: no speculative iteration past the stop
+        if ((st = process(j)) != DG_OK) return st;
+      } else {
+        if (pend >= 0 && (st = process(pend)) != DG_OK) return st;
+        pend = j;
+      }
     }
+    if (!stop && pend >= 0 && (st = process(pend)) != DG_OK) return st;
     // y = H_k^{-1} g (upper triangular back substitution)
     for (int i = k - 1; i >= 0; --i) {
       double a = g[i];
@@ -796,8 +819,8 @@ dg_status dg_fgmres_solve(dg_context* c, const double* w, double shift, const do
       const double d = H[(size_t)i * (m + 1) + i];
       y[i] = d != 0.0 ? a / d : 0.0;
     }
-    for (int i = 0; i < k; ++i) c->h_pin[144 + i] = y[i];
-    HIPCHK(hipMemcpyAsync(dS + 144, c->h_pin + 144, k * sizeof(double), hipMemcpyHostToDevice, s));
+    for (int i = 0; i < k; ++i) c->h_pin[400 + i] = y[i];
+    HIPCHK(hipMemcpyAsync(dS + 144, c->h_pin + 400, k * sizeof(double), hipMemcpyHostToDevice, s));
     HIPCHK(dgk::launch_mupdate_add(Z, k, n, dS + 144, x, s));
     if ((st = applyG(x, c->d_t1)) != DG_OK) return st;
     HIPCHK(dgk::launch_axpby(n, 1.0, b, -1.0, c->d_t1, V, s));

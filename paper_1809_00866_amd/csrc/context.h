@@ -100,6 +100,7 @@ struct dg_context {
   double* d_Z = nullptr;
   int kry_m = 0;
   double* h_pin = nullptr;
+  hipEvent_t ev_rb[2] = {nullptr, nullptr};  // FGMRES: Hessenberg columns copied to h_pin
   bool prof = false;
   std::map<std::string, dgc::Timer> timers;
   double* d_zero = nullptr;      // ndof zeros (stabilisation-only Jv)
