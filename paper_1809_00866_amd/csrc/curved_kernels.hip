@@ -100,13 +100,14 @@ __global__ __launch_bounds__(64) void k_face_curved(CurvedTablesT<R> ct, Mesh m,
   constexpr int NV = DIM + 2, NFQ = ipow(NQ1, DIM - 1), NS = JVP ? 2 : 1, NC = NV * DIM, NX = NV * NB;
   constexpr int GF = DIM + 1 + 2 * DIM * DIM, NTR = NV * (1 + DIM);
   static_assert(NFQ <= 32, "one lane per (side, face point)");
-  constexpr int NW = 2 * NS * NX > 2 * NS * NC * NFQ ? 2 * NS * NX : 2 * NS * NC * NFQ;
-  __shared__ __align__(16) R sW[NW];     // coefficients of both sides, then sX and sR
+  constexpr int NW = 2 * NS * NX > NS * NC * NFQ ? 2 * NS * NX : NS * NC * NFQ;
+  constexpr int NKL = (NC + 1) / 2;  // {r} columns per lane half
+  __shared__ __align__(16) R sW[NW];     // coefficients of both sides, then sX, then sR
   __shared__ R sT[2][NS][NTR][NFQ];      // traces of both sides: values, physical gradients
   __shared__ R sH[2][NV][NFQ];           // convective and viscous parts of the normal flux
   R* sU = sW;                                               // [side][c][a][value/tangent]
   auto sX = reinterpret_cast<R(*)[NC][NFQ]>(sW);            // [s][c*DIM+j][fq]: w n_j [[U_c]]
-  auto sR = reinterpret_cast<R(*)[NC][NFQ]>(sW + NS * NC * NFQ);  // {r}_cj at the face points
+  auto sR = reinterpret_cast<R(*)[NC][NFQ]>(sW);            // {r}_cj at the face points (over sX)
   const int tid = threadIdx.x, side = tid >> 5, fq = tid & 31;
   const int P = blockIdx.y;
   const int64_t ne = m.ne;
@@ -178,18 +179,33 @@ __global__ __launch_bounds__(64) void k_face_curved(CurvedTablesT<R> ct, Mesh m,
   }
   __syncthreads();
 
-  // {r} = -1/4 P X, the (c, j) columns shared between the two halves
+  // {r} = -1/4 P X, the (c, j) columns shared between the two halves; held
+  // in registers until every lane has read X, then written over it
+  R rv[NKL], rt[NKL];
+  for (int q = 0; q < NKL; ++q) rv[q] = rt[q] = R(0);
   if (act) {
     const R* Pf = ct.fP + f * NFQ * NFQ + fq;  // P is symmetric: row fq read along g
-    for (int k = side; k < NC; k += 2) {
-      R rv = 0.0, rt = 0.0;
-      for (int gq = 0; gq < NFQ; ++gq) {
-        const R pv = Pf[gq * NFQ];
-        rv += pv * sX[0][k][gq];
-        if constexpr (JVP) rt += pv * sX[NS - 1][k][gq];
+#pragma unroll
+    for (int q = 0; q < NKL; ++q) {
+      const int k = side + 2 * q;
+      if (k < NC) {
+        for (int gq = 0; gq < NFQ; ++gq) {
+          const R pv = Pf[gq * NFQ];
+          rv[q] += pv * sX[0][k][gq];
+          if constexpr (JVP) rt[q] += pv * sX[NS - 1][k][gq];
+        }
       }
-      sR[0][k][fq] = -0.25 * rv;
-      if constexpr (JVP) sR[NS - 1][k][fq] = -0.25 * rt;
+    }
+  }
+  __syncthreads();
+  if (act) {
+#pragma unroll
+    for (int q = 0; q < NKL; ++q) {
+      const int k = side + 2 * q;
+      if (k < NC) {
+        sR[0][k][fq] = R(-0.25) * rv[q];
+        if constexpr (JVP) sR[NS - 1][k][fq] = R(-0.25) * rt[q];
+      }
     }
   }
   __syncthreads();
