@@ -14,11 +14,21 @@
  *   dg_block_precond_apply  LU of the diagonal blocks of G = shift*I + J
  *   dg_fgmres_solve         flexible GMRES (Sec. 2.5) on G dw = b,
  *                           eq. (rosSysOp) with M = I (orthonormal basis)
- *   dg_mg_setup             p-multigrid V-cycle preconditioner (Sec. 2.4,
- *   dg_mg_apply             Alg. vcic) with inherited coarse operators
- *                           (eq. GalProj) and GMRES[EWBJ] smoothers
+ *   dg_rosenbrock_step      one linearly implicit stage loop (Alg. ros)
+ *                           with caller-supplied coefficients
+ *   dg_mg_setup             p-multigrid V-cycle or full cycle (Sec. 2.4,
+ *   dg_mg_apply             Alg. vcic / fullvcic) with inherited or
+ *                           rescaled-inherited coarse operators (eq. GalProj,
+ *                           App. A) and GMRES[EWBJ] smoothers
+ *   dg_mg_update_fine       preconditioner lagging: new fine state, coarse
+ *                           levels kept (Sec. 4)
  *   dg_mlp_*                learned element-local preconditioner, usable
  *                           because the outer solver is flexible (Sec. 2.5)
+ *
+ * Meshes: periodic, conforming, multilinear elements (Sec. 2.1).  Uniform
+ * axis-aligned lattices run MFMA kernels (3D P2-P4); any other such mesh
+ * runs the curved-element kernels, each element with its own orthonormal
+ * basis.
  *
  * Conventions (all entry points):
  *  - Every vector is FP64, device memory, caller-owned, contiguous, in the
