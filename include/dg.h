@@ -247,7 +247,9 @@ typedef struct {
   int n_levels;         /* 2 or 3, the fine level included */
   int orders[3];        /* strictly decreasing, >= 0, orders[0] = context order */
   int smooth_iters[3];  /* 0..60 each; the coarsest level needs >= 1 */
-  int storage;          /* block-factor storage on every level: DG_FP64/FP32/BF16 */
+  int storage;          /* block-factor storage on every level: DG_FP64/FP32/BF16;
+                           with FP32 or BF16 the cycle also applies FP32
+                           copies of the coarse operators (FP64 sums) */
   int use_graph;        /* nonzero: capture one cycle into a hipGraph at setup;
                            every apply replays it on a library stream ordered
                            against the caller's stream by events */

@@ -167,6 +167,10 @@ hipError_t launch_truncate_bsr(const double* B1, int nb1, double* B2, int nb2, i
                                hipStream_t s);
 hipError_t launch_bsr_apply(int bs, const double* B, const int64_t* nbr, int nf, int m, int64_t ne, const double* x,
                             double* y, hipStream_t s);
+// The same with FP32 blocks (FP64 sums); FP64 -> FP32 copy of n entries.
+hipError_t launch_bsr_apply_f32(int bs, const float* B, const int64_t* nbr, int nf, int m, int64_t ne,
+                                const double* x, double* y, hipStream_t s);
+hipError_t launch_to_f32(const double* x, float* y, int64_t n, hipStream_t s);
 hipError_t launch_gmres_init(double* sc, int m, hipStream_t s);
 hipError_t launch_gmres_step(double* sc, int j, int m, hipStream_t s);
 hipError_t launch_gmres_backsolve(double* sc, int m, hipStream_t s);

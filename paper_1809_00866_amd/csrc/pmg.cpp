@@ -35,6 +35,7 @@ struct MgLevel {
   int64_t n = 0;               // level vector length ne*nv*nb
   double* B = nullptr;         // coarse levels: BSR blocks [nslot][ne][m*m]
   double* Bs = nullptr;        // rescaled hierarchy, level 1: its stabilisation part (same layout)
+  float* B32 = nullptr;        // FP32 copy of B applied inside the cycle (FP32/BF16 storage)
   double* Ilu = nullptr;       // coarsest level with block ILU(0): D'^{-1} [ne][m*m] (FP64)
   void* Dinv = nullptr;        // coarse levels: block-Jacobi inverses
   double* g = nullptr;         // right-hand side
@@ -76,6 +77,7 @@ void mg_destroy(MgState* M) {
   for (auto& L : M->lev) {
     dfree(L.B);
     dfree(L.Bs);
+    dfree(L.B32);
     dfree(L.Ilu);
     dfree(L.Dinv);
     dfree(L.g);
@@ -107,12 +109,16 @@ int binom(int n, int k) {
 }
 
 // ---------------------------------------------------------------- level ops
-dg_status level_G(dg_context* c, MgState* M, int l, const double* x, double* y, hipStream_t s) {
+// exact: the FP64 level operator even where the cycle applies an FP32 copy
+dg_status level_G(dg_context* c, MgState* M, int l, const double* x, double* y, hipStream_t s, bool exact = false) {
   if (l == 0)
-    return M->fine_f32 ? eval_residual_f32(c, true, M->w, x, M->shift, y, s)
-                       : eval_residual(c, true, M->w, x, M->shift, y, s);
+    return M->fine_f32 && !exact ? eval_residual_f32(c, true, M->w, x, M->shift, y, s)
+                                 : eval_residual(c, true, M->w, x, M->shift, y, s);
   const MgLevel& L = M->lev[l];
-  HIPCHK(dgk::launch_bsr_apply(L.bs, L.B, c->mesh.nbr, 2 * c->dim, L.m, c->ne, x, y, s));
+  if (L.B32 && !exact)
+    HIPCHK(dgk::launch_bsr_apply_f32(L.bs, L.B32, c->mesh.nbr, 2 * c->dim, L.m, c->ne, x, y, s));
+  else
+    HIPCHK(dgk::launch_bsr_apply(L.bs, L.B, c->mesh.nbr, 2 * c->dim, L.m, c->ne, x, y, s));
   return DG_OK;
 }
 
@@ -524,6 +530,15 @@ dg_status dg_mg_setup(dg_context* c, const double* w, double shift, const dg_mg_
     HIPCHK(hipStreamSynchronize(s));
     if (bad) return bail(fail(DG_ERR_SINGULAR_BLOCK, "a block ILU(0) pivot block is singular"));
   }
+  // reduced-precision storage: the cycle applies FP32 copies of the coarse
+  // operators (the preconditioner only; the level operators stay FP64)
+  if (M->storage != DG_FP64)
+    for (int l = 1; l < M->nlev; ++l) {
+      MgLevel& C = M->lev[l];
+      const int64_t nB = (int64_t)M->nslot * ne * C.m * C.m;
+      if ((st = dalloc(&C.B32, (size_t)nB)) != DG_OK) return bail(st);
+      HIPCHK(dgk::launch_to_f32(C.B, C.B32, nB, s));
+    }
   // autotune the BSR apply workgroup size per coarse level
   {
     hipEvent_t a, b;
@@ -535,9 +550,13 @@ dg_status dg_mg_setup(dg_context* c, const double* w, double shift, const dg_mg_
       float best = 1e30f;
       for (int bs : {256, 512, 1024}) {
         if (bs < 4 * C.m) continue;
-        HIPCHK(dgk::launch_bsr_apply(bs, C.B, c->mesh.nbr, nf, C.m, ne, C.g, C.t, s));
+        auto apply = [&]() {
+          return C.B32 ? dgk::launch_bsr_apply_f32(bs, C.B32, c->mesh.nbr, nf, C.m, ne, C.g, C.t, s)
+                       : dgk::launch_bsr_apply(bs, C.B, c->mesh.nbr, nf, C.m, ne, C.g, C.t, s);
+        };
+        HIPCHK(apply());
         HIPCHK(hipEventRecord(a, s));
-        for (int k = 0; k < 5; ++k) HIPCHK(dgk::launch_bsr_apply(bs, C.B, c->mesh.nbr, nf, C.m, ne, C.g, C.t, s));
+        for (int k = 0; k < 5; ++k) HIPCHK(apply());
         HIPCHK(hipEventRecord(b, s));
         HIPCHK(hipEventSynchronize(b));
         float ms = 0.f;
@@ -592,7 +611,7 @@ dg_status dg_mg_level_apply(dg_context* c, int level, const double* x, double* y
   if (x == y) return fail(DG_ERR_ARG, "x and y may not alias");
   if (!mg_ready(c->mg)) return fail(DG_ERR_STATE, "dg_mg_setup has not succeeded since the last block setup");
   if (level < 0 || level >= c->mg->nlev) return fail(DG_ERR_ARG, "level out of range");
-  return level_G(c, c->mg, level, x, y, (hipStream_t)stream);
+  return level_G(c, c->mg, level, x, y, (hipStream_t)stream, true);
 }
 
 }  // extern "C"

@@ -92,9 +92,11 @@ __global__ void k_truncate_bsr(const double* __restrict__ B1, int nb1, double* _
 // summed by 4 threads per matrix row (columns c, c+4, c+8, ... of the
 // (2d+1)*m gathered x values) and the 4 partial sums are added in a fixed
 // order, so the result does not depend on the workgroup size BS, which only
-// sets how many element rows (BS / 4m) share a workgroup.
-template <int BS>
-__global__ __launch_bounds__(BS) void k_bsr_apply(const double* __restrict__ B, const int64_t* __restrict__ nbr,
+// sets how many element rows (BS / 4m) share a workgroup.  The blocks are
+// stored in S (FP64, or an FP32 copy for the reduced-precision smoothers);
+// the sums are FP64.
+template <int BS, class S>
+__global__ __launch_bounds__(BS) void k_bsr_apply(const S* __restrict__ B, const int64_t* __restrict__ nbr,
                                                   int nf, int m, int64_t ne, const double* __restrict__ x,
                                                   double* __restrict__ y) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -122,7 +124,7 @@ __global__ __launch_bounds__(BS) void k_bsr_apply(const double* __restrict__ B, 
     const double* xr = xs + rr * ncol;
     for (int col = cc; col < ncol; col += 4) {
       const int s = col / m, j = col - s * m;
-      a += B[((int64_t)s * ne + K) * m * m + (int64_t)j * m + i] * xr[col];
+      a += (double)B[((int64_t)s * ne + K) * m * m + (int64_t)j * m + i] * xr[col];
     }
   }
   part[threadIdx.x] = a;
@@ -224,18 +226,43 @@ hipError_t launch_truncate_bsr(const double* B1, int nb1, double* B2, int nb2, i
   return hipGetLastError();
 }
 
-hipError_t launch_bsr_apply(int bs, const double* B, const int64_t* nbr, int nf, int m, int64_t ne, const double* x,
-                            double* y, hipStream_t s) {
+namespace {
+
+template <class S>
+hipError_t bsr_apply(int bs, const S* B, const int64_t* nbr, int nf, int m, int64_t ne, const double* x, double* y,
+                     hipStream_t s) {
   if (m < 1 || 4 * m > bs || ne < 1) return hipErrorInvalidValue;
   const int R = bs / (4 * m);
   const unsigned grid = (unsigned)((ne + R - 1) / R);
   const size_t lds = ((size_t)R * (nf + 1) * m + bs) * sizeof(double);
   switch (bs) {
-    case 256: k_bsr_apply<256><<<grid, 256, lds, s>>>(B, nbr, nf, m, ne, x, y); break;
-    case 512: k_bsr_apply<512><<<grid, 512, lds, s>>>(B, nbr, nf, m, ne, x, y); break;
-    case 1024: k_bsr_apply<1024><<<grid, 1024, lds, s>>>(B, nbr, nf, m, ne, x, y); break;
+    case 256: k_bsr_apply<256, S><<<grid, 256, lds, s>>>(B, nbr, nf, m, ne, x, y); break;
+    case 512: k_bsr_apply<512, S><<<grid, 512, lds, s>>>(B, nbr, nf, m, ne, x, y); break;
+    case 1024: k_bsr_apply<1024, S><<<grid, 1024, lds, s>>>(B, nbr, nf, m, ne, x, y); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+__global__ void k_to_f32(const double* __restrict__ x, float* __restrict__ y, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = (float)x[i];
+}
+
+}  // namespace
+
+hipError_t launch_bsr_apply(int bs, const double* B, const int64_t* nbr, int nf, int m, int64_t ne, const double* x,
+                            double* y, hipStream_t s) {
+  return bsr_apply<double>(bs, B, nbr, nf, m, ne, x, y, s);
+}
+
+hipError_t launch_bsr_apply_f32(int bs, const float* B, const int64_t* nbr, int nf, int m, int64_t ne,
+                                const double* x, double* y, hipStream_t s) {
+  return bsr_apply<float>(bs, B, nbr, nf, m, ne, x, y, s);
+}
+
+hipError_t launch_to_f32(const double* x, float* y, int64_t n, hipStream_t s) {
+  k_to_f32<<<grid_for(n), 256, 0, s>>>(x, y, n);
   return hipGetLastError();
 }
 
