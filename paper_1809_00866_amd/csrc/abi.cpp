@@ -551,16 +551,14 @@ dg_status dg_jvp(dg_context* c, const double* w, const double* r_w, const double
   return jvp_impl(c, w, r_w, v, shift, mode, out, (hipStream_t)stream);
 }
 
-dg_status dg_block_precond_setup(dg_context* c, const double* w, double shift, int storage, void* stream) {
-  if (!c || !w) return fail(DG_ERR_ARG, "null argument");
-  if (storage != DG_FP64 && storage != DG_FP32 && storage != DG_BF16)
-    return fail(DG_ERR_ARG, "storage must be DG_FP64, DG_FP32 or DG_BF16");
-  hipStream_t s = (hipStream_t)stream;
+}  // extern "C"
+
+namespace dgc {
+
+dg_status block_alloc(dg_context* c, int storage) {
   const int m = c->nv * c->nb;
-  if (m > 256) return fail(DG_ERR_ARG, "block size above 256");
   dg_status st;
   c->blk_ready = false;
-  mg_invalidate(c->mg);
   const int ld = dgk::block_ld(m);
   if ((st = dalloc(&c->d_D64, (size_t)c->ne * m * ld)) != DG_OK) return st;
   if (storage == DG_FP64) {
@@ -582,12 +580,20 @@ dg_status dg_block_precond_setup(dg_context* c, const double* w, double shift, i
       c->dinv_bytes = need;
     }
   }
+  return DG_OK;
+}
+
+dg_status block_probe_invert(dg_context* c, const double* w, double shift, int storage, int skip_modes,
+                             hipStream_t s) {
+  const int m = c->nv * c->nb, ld = dgk::block_ld(m);
+  dg_status st;
   // reduced-precision factors are probed with the FP32 operator where it exists
   const bool probe_f32 = storage != DG_FP64 && has_f32(c);
   {
     ProfScope ps(c, "block_probe", s);
     for (int col = 0; col < c->ncolor; ++col)
       for (int l = 0; l < m; ++l) {
+        if (l % c->nb < skip_modes) continue;  // column already in d_D64
         HIPCHK(dgk::launch_probe_vector(c->d_t1, c->d_color, col, l, c->nb, c->nv, c->ne, s));
         if ((st = probe_f32 ? eval_residual_f32(c, true, w, c->d_t1, shift, c->d_t2, s)
                             : eval_residual(c, true, w, c->d_t1, shift, c->d_t2, s)) != DG_OK)
@@ -608,6 +614,21 @@ dg_status dg_block_precond_setup(dg_context* c, const double* w, double shift, i
   c->blk_storage = storage;
   c->blk_ready = true;
   return DG_OK;
+}
+
+}  // namespace dgc
+
+extern "C" {
+
+dg_status dg_block_precond_setup(dg_context* c, const double* w, double shift, int storage, void* stream) {
+  if (!c || !w) return fail(DG_ERR_ARG, "null argument");
+  if (storage != DG_FP64 && storage != DG_FP32 && storage != DG_BF16)
+    return fail(DG_ERR_ARG, "storage must be DG_FP64, DG_FP32 or DG_BF16");
+  if (c->nv * c->nb > 256) return fail(DG_ERR_ARG, "block size above 256");
+  mg_invalidate(c->mg);
+  dg_status st;
+  if ((st = block_alloc(c, storage)) != DG_OK) return st;
+  return block_probe_invert(c, w, shift, storage, 0, (hipStream_t)stream);
 }
 
 dg_status dg_block_precond_apply(dg_context* c, const double* r, double* z, void* stream) {

@@ -151,6 +151,12 @@ dg_status eval_residual_f32(dg_context* c, bool jvp, const double* w, const doub
 // the face lifting term eta {r} of the face viscous flux only; no shift),
 // FP64 or the FP32 operator.
 dg_status eval_stab(dg_context* c, bool f32, const double* w, const double* v, double* out, hipStream_t s);
+// Element-block Jacobi setup in two steps: storage for the blocks, then the
+// coloured probing of every column whose mode index is at least skip_modes
+// (the caller has written the others into d_D64) and the inversion.
+dg_status block_alloc(dg_context* c, int storage);
+dg_status block_probe_invert(dg_context* c, const double* w, double shift, int storage, int skip_modes,
+                             hipStream_t s);
 // dout[0] = ||x||_2 over the context's DOF vector length.
 dg_status norm2(dg_context* c, const double* x, double* dout, hipStream_t s);
 // out = shift*v + J(w) v, exact or finite difference.

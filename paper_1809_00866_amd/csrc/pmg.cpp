@@ -385,8 +385,13 @@ dg_status dg_mg_setup(dg_context* c, const double* w, double shift, const dg_mg_
 
   mg_destroy(c->mg);
   c->mg = nullptr;
-  // fine-level block Jacobi (shared with DG_PREC_BJ)
-  if ((st = dg_block_precond_setup(c, w, shift, o->storage, stream)) != DG_OK) return st;
+  // fine-level block Jacobi (shared with DG_PREC_BJ): the columns of the
+  // coarse modes come from the distance-2 probing below, the rest from the
+  // face-neighbour colouring
+  if (o->storage != DG_FP64 && o->storage != DG_FP32 && o->storage != DG_BF16)
+    return fail(DG_ERR_ARG, "storage must be DG_FP64, DG_FP32 or DG_BF16");
+  if (nv * c->nb > 256) return fail(DG_ERR_ARG, "block size above 256");
+  if ((st = block_alloc(c, o->storage)) != DG_OK) return st;
 
   auto* M = new MgState();
   c->mg = M;
@@ -475,6 +480,8 @@ dg_status dg_mg_setup(dg_context* c, const double* w, double shift, const dg_mg_
         if ((st = M->fine_f32 ? eval_residual_f32(c, true, M->w, c->d_t1, shift, c->d_t2, s)
                               : eval_residual(c, true, M->w, c->d_t1, shift, c->d_t2, s)) != DG_OK)
           return bail(st);
+        // the element's own rows: column lf of its fine diagonal block
+        HIPCHK(dgk::launch_extract_column(c->d_t2, M->color2, col, lf, nv * c->nb, ne, shift, c->d_D64, s));
         if (M->rescale) {
           if ((st = eval_stab(c, M->fine_f32, M->w, c->d_t1, c->d_t3, s)) != DG_OK) return bail(st);
           HIPCHK(dgk::launch_axpby(c->ndof, 1.0, c->d_t2, -(1.0 - s01), c->d_t3, c->d_t2, s));
@@ -483,6 +490,7 @@ dg_status dg_mg_setup(dg_context* c, const double* w, double shift, const dg_mg_
         }
         HIPCHK(dgk::launch_extract_bsr(c->d_t2, M->color2, col, l, c->mesh.nbr, nf, c->nb, C.nb, nv, ne, C.B, s));
       }
+    if ((st = block_probe_invert(c, w, shift, o->storage, C.nb, s)) != DG_OK) return bail(st);
   }
   for (int l = 2; l < M->nlev; ++l) {
     MgLevel& P = M->lev[l - 1];
