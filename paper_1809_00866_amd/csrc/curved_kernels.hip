@@ -185,15 +185,14 @@ __global__ __launch_bounds__(64) void k_face_curved(CurvedTablesT<R> ct, Mesh m,
   for (int q = 0; q < NKL; ++q) rv[q] = rt[q] = R(0);
   if (act) {
     const R* Pf = ct.fP + f * NFQ * NFQ + fq;  // P is symmetric: row fq read along g
+#pragma unroll 5
+    for (int gq = 0; gq < NFQ; ++gq) {  // each entry of P read once for all columns
+      const R pv = Pf[gq * NFQ];
 #pragma unroll
-    for (int q = 0; q < NKL; ++q) {
-      const int k = side + 2 * q;
-      if (k < NC) {
-        for (int gq = 0; gq < NFQ; ++gq) {
-          const R pv = Pf[gq * NFQ];
-          rv[q] += pv * sX[0][k][gq];
-          if constexpr (JVP) rt[q] += pv * sX[NS - 1][k][gq];
-        }
+      for (int q = 0; q < NKL; ++q) {
+        const int k = side + 2 * q < NC ? side + 2 * q : NC - 1;
+        rv[q] += pv * sX[0][k][gq];
+        if constexpr (JVP) rt[q] += pv * sX[NS - 1][k][gq];
       }
     }
   }
