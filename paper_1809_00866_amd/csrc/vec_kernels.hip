@@ -74,22 +74,55 @@ __global__ void k_scale_dev(int64_t n, const double* __restrict__ x, const doubl
 constexpr int kMaxK = 64;
 
 // partial[j][blk] = sum over the block's range of V_j[i] * w[i], j < k
+// Partial dot products of w with V_j0 .. V_j0+G-1 per pass: every w value is
+// read once per G basis vectors; VEC loads two consecutive entries at a time
+// (n even).  The per-block sums go through wave shuffles and one LDS step.
+template <int G, bool VEC>
 __global__ __launch_bounds__(256) void k_mdot(const double* __restrict__ V, int k, int64_t n,
                                                const double* __restrict__ w, double* __restrict__ partial) {
-  __shared__ double sh[256];
-  for (int j0 = 0; j0 < k; j0 += 8) {
-    double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    const int jn = min(8, k - j0);
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-      const double wi = w[i];
+  __shared__ double sh[4][G];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int j0 = 0; j0 < k; j0 += G) {
+    double a[G];
 #pragma unroll
-      for (int jj = 0; jj < 8; ++jj)
-        if (jj < jn) a[jj] += V[(size_t)(j0 + jj) * n + i] * wi;
+    for (int jj = 0; jj < G; ++jj) a[jj] = 0.0;
+    const int jn = min(G, k - j0);
+    if constexpr (VEC) {
+      const int64_t n2 = n / 2;
+      const double2* w2 = reinterpret_cast<const double2*>(w);
+      for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n2; i += stride) {
+        const double2 wi = w2[i];
+#pragma unroll
+        for (int jj = 0; jj < G; ++jj)
+          if (jj < jn) {
+            const double2 v = reinterpret_cast<const double2*>(V + (size_t)(j0 + jj) * n)[i];
+            a[jj] += v.x * wi.x + v.y * wi.y;
+          }
+      }
+    } else {
+      for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
+        const double wi = w[i];
+#pragma unroll
+        for (int jj = 0; jj < G; ++jj)
+          if (jj < jn) a[jj] += V[(size_t)(j0 + jj) * n + i] * wi;
+      }
     }
-    for (int jj = 0; jj < jn; ++jj) {
-      double s = block_sum256(a[jj], sh);
-      if (threadIdx.x == 0) partial[(size_t)(j0 + jj) * gridDim.x + blockIdx.x] = s;
+#pragma unroll
+    for (int jj = 0; jj < G; ++jj) {
+      double v = a[jj];
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+      a[jj] = v;
     }
+    if (lane == 0)
+#pragma unroll
+      for (int jj = 0; jj < G; ++jj) sh[wv][jj] = a[jj];
+    __syncthreads();
+    if ((int)threadIdx.x < jn) {
+      const int t = threadIdx.x;
+      partial[(size_t)(j0 + t) * gridDim.x + blockIdx.x] = (sh[0][t] + sh[1][t]) + (sh[2][t] + sh[3][t]);
+    }
+    __syncthreads();
   }
 }
 
@@ -196,7 +229,10 @@ hipError_t launch_scale_dev(int64_t n, const double* x, const double* dnorm, dou
 }
 hipError_t launch_mdot(const double* V, int k, int64_t n, const double* w, double* partial, hipStream_t s) {
   if (k > kMaxK) return hipErrorInvalidValue;
-  k_mdot<<<kRedBlocks, 256, 0, s>>>(V, k, n, w, partial);
+  if (n % 2 == 0)
+    k_mdot<16, true><<<kRedBlocks, 256, 0, s>>>(V, k, n, w, partial);
+  else
+    k_mdot<16, false><<<kRedBlocks, 256, 0, s>>>(V, k, n, w, partial);
   return hipGetLastError();
 }
 hipError_t launch_msum(const double* partial, int k, double* h, hipStream_t s) {
