@@ -122,6 +122,7 @@ __global__ __launch_bounds__(BS) void k_bsr_apply(const S* __restrict__ B, const
   double a = 0.0;
   if (rr < R && K < ne) {
     const double* xr = xs + rr * ncol;
+#pragma unroll 8
     for (int col = cc; col < ncol; col += 4) {
       const int s = col / m, j = col - s * m;
       a += (double)B[((int64_t)s * ne + K) * m * m + (int64_t)j * m + i] * xr[col];
