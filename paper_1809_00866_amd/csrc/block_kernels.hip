@@ -308,6 +308,26 @@ __global__ __launch_bounds__(kApplyThreads) void k_apply(const S* __restrict__ D
   }
 }
 
+// Small blocks (m <= 64): one wave per element (four per workgroup), lane i
+// owns row i and walks the columns (column-major storage: consecutive lanes
+// read consecutive entries); r_K sits in the wave's slice of LDS.
+template <class S, class ACC>
+__global__ __launch_bounds__(256) void k_apply_small(const S* __restrict__ Dinv, int m, int ld, int64_t ne,
+                                                     const double* __restrict__ r, double* __restrict__ z) {
+  __shared__ double rs[4][64];
+  const int wv = threadIdx.x >> 6, i = threadIdx.x & 63;
+  const int64_t e = (int64_t)blockIdx.x * 4 + wv;
+  const bool live = e < ne && i < m;
+  if (live) rs[wv][i] = r[(size_t)i * ne + e];
+  __syncthreads();
+  if (!live) return;
+  const S* A = Dinv + (size_t)e * m * ld + i;
+  ACC acc = 0;
+#pragma unroll 8
+  for (int j = 0; j < m; ++j) acc += (ACC)load_as(A[(size_t)j * ld]) * (ACC)rs[wv][j];
+  z[(size_t)i * ne + e] = (double)acc;
+}
+
 unsigned grid_for(int64_t n) {
   int64_t g = (n + 255) / 256;
   if (g > 8192) g = 8192;
@@ -507,6 +527,18 @@ hipError_t launch_block_apply(int storage, const void* Dinv, int m, int64_t ne, 
                               hipStream_t s) {
   if (m < 1 || m > 256) return hipErrorInvalidValue;
   const int ld = block_ld(m);
+  if (m <= 64) {
+    const unsigned grid = (unsigned)((ne + 3) / 4);
+    if (storage == DG_FP64)
+      k_apply_small<double, double><<<grid, 256, 0, s>>>(static_cast<const double*>(Dinv), m, ld, ne, r, z);
+    else if (storage == DG_FP32)
+      k_apply_small<float, float><<<grid, 256, 0, s>>>(static_cast<const float*>(Dinv), m, ld, ne, r, z);
+    else if (storage == DG_BF16)
+      k_apply_small<bf16_t, float><<<grid, 256, 0, s>>>(static_cast<const bf16_t*>(Dinv), m, ld, ne, r, z);
+    else
+      return hipErrorInvalidValue;
+    return hipGetLastError();
+  }
   constexpr int T = kApplyThreads;
   auto lds = [&](int vec) { return (size_t)(m + (T / (ld / vec)) * ld) * sizeof(double); };
   if (storage == DG_FP64)
