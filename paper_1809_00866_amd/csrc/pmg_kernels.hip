@@ -13,6 +13,8 @@
 // -x,+x,-y,+y,-z,+z); blocks are m x m column-major, laid out [slot][e][m*m],
 // so slot 0 is the contiguous stack of diagonal blocks the block-Jacobi
 // inversion reads.
+#include <algorithm>
+
 #include "dg_internal.h"
 
 namespace dgk {
@@ -95,16 +97,56 @@ __global__ void k_truncate_bsr(const double* __restrict__ B1, int nb1, double* _
 // sets how many element rows (BS / 4m) share a workgroup.  The blocks are
 // stored in S (FP64, or an FP32 copy for the reduced-precision smoothers);
 // the sums are FP64.
-template <int BS, class S>
+template <class S, int RPT>
+struct RowVec;  // RPT consecutive entries of a column, one load
+template <>
+struct RowVec<double, 1> {
+  static __device__ __forceinline__ void ld(const double* p, double* o) { o[0] = p[0]; }
+};
+template <>
+struct RowVec<double, 2> {
+  static __device__ __forceinline__ void ld(const double* p, double* o) {
+    const double2 v = *reinterpret_cast<const double2*>(p);
+    o[0] = v.x;
+    o[1] = v.y;
+  }
+};
+template <>
+struct RowVec<float, 1> {
+  static __device__ __forceinline__ void ld(const float* p, double* o) { o[0] = p[0]; }
+};
+template <>
+struct RowVec<float, 2> {
+  static __device__ __forceinline__ void ld(const float* p, double* o) {
+    const float2 v = *reinterpret_cast<const float2*>(p);
+    o[0] = v.x;
+    o[1] = v.y;
+  }
+};
+template <>
+struct RowVec<float, 4> {
+  static __device__ __forceinline__ void ld(const float* p, double* o) {
+    const float4 v = *reinterpret_cast<const float4*>(p);
+    o[0] = v.x;
+    o[1] = v.y;
+    o[2] = v.z;
+    o[3] = v.w;
+  }
+};
+
+// Each thread owns RPT consecutive rows (one vector load per column; m is a
+// multiple of RPT) and one of 4 column slices; partial sums land in
+// part[element][slice][row].
+template <int BS, class S, int RPT>
 __global__ __launch_bounds__(BS) void k_bsr_apply(const S* __restrict__ B, const int64_t* __restrict__ nbr,
-                                                  int nf, int m, int64_t ne, const double* __restrict__ x,
+                                                  int nf, int m, int R, int64_t ne, const double* __restrict__ x,
                                                   double* __restrict__ y) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int tpr = 4 * m;           // threads per element row
-  const int R = BS / tpr;          // element rows per workgroup
+  const int mr = m / RPT;          // row groups
+  const int tpr = 4 * mr;          // threads per element row; R element rows per workgroup
   const int ncol = (nf + 1) * m;
   double* xs = reinterpret_cast<double*>(smem);  // [R][ncol]
-  double* part = xs + R * ncol;                  // [BS]
+  double* part = xs + R * ncol;                  // [R][4][m]
   const int64_t K0 = (int64_t)blockIdx.x * R;
   for (int t = threadIdx.x; t < R * ncol; t += BS) {
     const int rr = t / ncol, q = t - rr * ncol;
@@ -117,23 +159,31 @@ __global__ __launch_bounds__(BS) void k_bsr_apply(const S* __restrict__ B, const
   }
   __syncthreads();
   const int rr = threadIdx.x / tpr, q = threadIdx.x - rr * tpr;
-  const int cc = q / m, i = q - cc * m;
+  const int cc = q / mr, ig = q - cc * mr;
   const int64_t K = K0 + rr;
-  double a = 0.0;
+  double a[RPT];
+#pragma unroll
+  for (int u = 0; u < RPT; ++u) a[u] = 0.0;
   if (rr < R && K < ne) {
     const double* xr = xs + rr * ncol;
 #pragma unroll 8
     for (int col = cc; col < ncol; col += 4) {
       const int s = col / m, j = col - s * m;
-      a += (double)B[((int64_t)s * ne + K) * m * m + (int64_t)j * m + i] * xr[col];
+      double v[RPT];
+      RowVec<S, RPT>::ld(B + ((int64_t)s * ne + K) * m * m + (int64_t)j * m + ig * RPT, v);
+      const double xc = xr[col];
+#pragma unroll
+      for (int u = 0; u < RPT; ++u) a[u] += v[u] * xc;
     }
   }
-  part[threadIdx.x] = a;
+  if (rr < R)
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) part[(rr * 4 + cc) * m + ig * RPT + u] = a[u];
   __syncthreads();
   if ((int)threadIdx.x < R * m) {
     const int r2 = threadIdx.x / m, i2 = threadIdx.x - r2 * m;
     const int64_t K2 = K0 + r2;
-    const double* p = part + r2 * tpr + i2;
+    const double* p = part + r2 * 4 * m + i2;
     if (K2 < ne) y[(int64_t)i2 * ne + K2] = ((p[0] + p[m]) + p[2 * m]) + p[3 * m];
   }
 }
@@ -229,20 +279,31 @@ hipError_t launch_truncate_bsr(const double* B1, int nb1, double* B2, int nb2, i
 
 namespace {
 
+template <class S, int RPT>
+hipError_t bsr_apply_rpt(int bs, const S* B, const int64_t* nbr, int nf, int m, int64_t ne, const double* x,
+                         double* y, hipStream_t s) {
+  // element rows per workgroup: as many as the threads allow, within 64 KB of LDS
+  const size_t per = ((size_t)(nf + 1) * m + (size_t)4 * m) * sizeof(double);
+  const int R = std::min<int>(bs / (4 * (m / RPT)), (int)(65536 / per));
+  if (R < 1) return hipErrorInvalidValue;
+  const unsigned grid = (unsigned)((ne + R - 1) / R);
+  const size_t lds = (size_t)R * per;
+  switch (bs) {
+    case 256: k_bsr_apply<256, S, RPT><<<grid, 256, lds, s>>>(B, nbr, nf, m, R, ne, x, y); break;
+    case 512: k_bsr_apply<512, S, RPT><<<grid, 512, lds, s>>>(B, nbr, nf, m, R, ne, x, y); break;
+    case 1024: k_bsr_apply<1024, S, RPT><<<grid, 1024, lds, s>>>(B, nbr, nf, m, R, ne, x, y); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 template <class S>
 hipError_t bsr_apply(int bs, const S* B, const int64_t* nbr, int nf, int m, int64_t ne, const double* x, double* y,
                      hipStream_t s) {
   if (m < 1 || 4 * m > bs || ne < 1) return hipErrorInvalidValue;
-  const int R = bs / (4 * m);
-  const unsigned grid = (unsigned)((ne + R - 1) / R);
-  const size_t lds = ((size_t)R * (nf + 1) * m + bs) * sizeof(double);
-  switch (bs) {
-    case 256: k_bsr_apply<256, S><<<grid, 256, lds, s>>>(B, nbr, nf, m, ne, x, y); break;
-    case 512: k_bsr_apply<512, S><<<grid, 512, lds, s>>>(B, nbr, nf, m, ne, x, y); break;
-    case 1024: k_bsr_apply<1024, S><<<grid, 1024, lds, s>>>(B, nbr, nf, m, ne, x, y); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
+  if (sizeof(S) == 4 && m % 4 == 0) return bsr_apply_rpt<S, sizeof(S) == 4 ? 4 : 2>(bs, B, nbr, nf, m, ne, x, y, s);
+  if (m % 2 == 0) return bsr_apply_rpt<S, 2>(bs, B, nbr, nf, m, ne, x, y, s);
+  return bsr_apply_rpt<S, 1>(bs, B, nbr, nf, m, ne, x, y, s);
 }
 
 __global__ void k_to_f32(const double* __restrict__ x, float* __restrict__ y, int64_t n) {
