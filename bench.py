@@ -431,6 +431,7 @@ def main():
         res["time_to_tol_bf16_blocks"] = time_to_tolerance("bf16")
         res["time_to_tol_pmg"] = time_to_tolerance("fp64", precond="mg")
         res["time_to_tol_pmg_fp32_smoothing"] = time_to_tolerance("fp32", precond="mg", fine_precision="fp32")
+        res["time_to_tol_pmg_bf16_factors"] = time_to_tolerance("bf16", precond="mg", fine_precision="fp32")
         res["time_to_tol_pmg_fp32_rescaled"] = time_to_tolerance("fp32", precond="mg", fine_precision="fp32",
                                                                  rescale=True)
         res["time_to_tol_pmg_fp32_coarse_ilu"] = time_to_tolerance("fp32", precond="mg", fine_precision="fp32",
@@ -438,6 +439,8 @@ def main():
         res["time_to_tol_pmg_curved"] = time_to_tolerance("fp32", precond="mg", fine_precision="fp64", preset="cfg4")
         res["time_to_tol_pmg_curved_fp32_smoothing"] = time_to_tolerance("fp32", precond="mg", fine_precision="fp32",
                                                                          preset="cfg4")
+        res["time_to_tol_pmg_curved_bf16_factors"] = time_to_tolerance("bf16", precond="mg", fine_precision="fp32",
+                                                                       preset="cfg4")
         res["time_to_tol_bj_curved"] = time_to_tolerance("fp32", preset="cfg4")
         res["trajectory_pmg"] = mg_trajectory(4, lag=1)
         res["trajectory_pmg_lag3"] = mg_trajectory(4, lag=3)
