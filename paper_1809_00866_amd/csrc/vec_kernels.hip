@@ -9,14 +9,13 @@ namespace dgk {
 
 namespace {
 
+// Sum over a 256-thread workgroup: wave shuffles, then the four wave sums
+// through LDS (sh needs 4 entries); every thread gets the result.
 __device__ __forceinline__ double block_sum256(double v, double* sh) {
-  sh[threadIdx.x] = v;
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
-    __syncthreads();
-  }
-  double r = sh[0];
+  const double r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
   __syncthreads();
   return r;
 }
