@@ -715,7 +715,8 @@ dg_status dg_fgmres_solve(dg_context* c, const double* w, double shift, const do
     HIPCHK(hipStreamSynchronize(s));
     return DG_OK;
   };
-  // device scalars: [0] |b|, [1] beta, [2] |w0|, [3] h_{j+1,j}; [16..] h pass 1; [80..] h pass 2; [144..] y
+  // device scalars: [0] |b|, [1] beta, [2] |w| before orthogonalisation (MGS; CGS2: |w|^2 at
+  // [16 + j + 1]), [3] h_{j+1,j}; [16..] h pass 1; [80..] h pass 2; [144..] y
   double* dS = c->d_scal;
   if ((st = norm2(c, b, dS + 0, s)) != DG_OK) return st;
   if ((st = readback(dS + 0, 1)) != DG_OK) return st;
@@ -763,7 +764,7 @@ dg_status dg_fgmres_solve(dg_context* c, const double* w, double shift, const do
     auto process = [&](int jj) -> dg_status {
       HIPCHK(hipEventSynchronize(c->ev_rb[jj & 1]));
       const double* hp = c->h_pin + 256 * (jj & 1);
-      const double w0 = hp[2], hn = hp[3];
+      const double w0 = mgs ? hp[2] : std::sqrt(hp[16 + jj + 1]), hn = hp[3];
       if (!std::isfinite(hn)) return fail(DG_ERR_NONFINITE, "Arnoldi vector is not finite");
       double* Hc = &H[(size_t)jj * (m + 1)];  // column jj, rows 0..jj+1
       for (int i = 0; i <= jj; ++i) Hc[i] = mgs ? hp[16 + i] : hp[16 + i] + hp[80 + i];
@@ -803,7 +804,7 @@ dg_status dg_fgmres_solve(dg_context* c, const double* w, double shift, const do
       double* Wn = V + (size_t)(j + 1) * n;
       if ((st = applyM(Vj, Zj)) != DG_OK) return st;
       if ((st = applyG(Zj, Wn)) != DG_OK) return st;
-      if ((st = norm2(c, Wn, dS + 2, s)) != DG_OK) return st;
+      if (mgs && (st = norm2(c, Wn, dS + 2, s)) != DG_OK) return st;
       {
         ProfScope ps(c, "arnoldi", s);
         if (mgs) {  // modified Gram-Schmidt: one basis vector at a time
@@ -812,9 +813,10 @@ dg_status dg_fgmres_solve(dg_context* c, const double* w, double shift, const do
             HIPCHK(dgk::launch_msum(c->d_red, 1, dS + 16 + i, s));
             HIPCHK(dgk::launch_mupdate(V + (size_t)i * n, 1, n, dS + 16 + i, Wn, s));
           }
-        } else {  // classical Gram-Schmidt with one re-orthogonalisation
-          HIPCHK(dgk::launch_mdot(V, j + 1, n, Wn, c->d_red, s));
-          HIPCHK(dgk::launch_msum(c->d_red, j + 1, dS + 16, s));
+        } else {  // classical Gram-Schmidt with one re-orthogonalisation; the first
+                  // pass also gives |Wn|^2 (Wn is V_{j+1}) as entry j + 1
+          HIPCHK(dgk::launch_mdot(V, j + 2, n, Wn, c->d_red, s));
+          HIPCHK(dgk::launch_msum(c->d_red, j + 2, dS + 16, s));
           HIPCHK(dgk::launch_mupdate(V, j + 1, n, dS + 16, Wn, s));
           HIPCHK(dgk::launch_mdot(V, j + 1, n, Wn, c->d_red, s));
           HIPCHK(dgk::launch_msum(c->d_red, j + 1, dS + 80, s));

@@ -156,7 +156,7 @@ hipError_t launch_block_apply(int storage, const void* Dinv, int m, int64_t ne, 
 // p-multigrid kernels (level transfer, inherited BSR operators, fixed-count
 // GMRES bookkeeping).  Device scalar block of one smoother, in doubles:
 constexpr int kMaxSmooth = 60;  // iterations per smoother call
-constexpr int kScBeta = 0, kScW0 = 1, kScHn = 2, kScInv = 3, kScFlag = 4;
+constexpr int kScBeta = 0, kScHn = 2, kScInv = 3, kScFlag = 4;  // |w|^2 before orthogonalisation: kScH1 + j + 1
 constexpr int kScH1 = 8, kScH2 = 72, kScCs = 136, kScSn = 200, kScG = 264, kScY = 336, kScR = 400;
 constexpr int kScSize = kScR + (kMaxSmooth + 1) * kMaxSmooth + 64;
 hipError_t launch_restrict(const double* f, int nbf, double* cv, int nbc, int nv, int64_t ne, hipStream_t s);

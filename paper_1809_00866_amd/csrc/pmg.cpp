@@ -167,9 +167,9 @@ dg_status smooth(dg_context* c, MgState* M, int l, bool zero_start, hipStream_t 
     double* Wn = L.V + (size_t)(j + 1) * n;
     if ((st = level_Minv(c, M, l, Vj, L.z, s)) != DG_OK) return st;
     if ((st = level_G(c, M, l, L.z, Wn, s)) != DG_OK) return st;
-    if ((st = lnorm(M, Wn, n, L.sc + dgk::kScW0, s)) != DG_OK) return st;
-    HIPCHK(dgk::launch_mdot(L.V, j + 1, n, Wn, M->red, s));
-    HIPCHK(dgk::launch_msum(M->red, j + 1, L.sc + dgk::kScH1, s));
+    // first pass: dots with V_0..V_j and, as entry j + 1 (Wn is V_{j+1}), |Wn|^2
+    HIPCHK(dgk::launch_mdot(L.V, j + 2, n, Wn, M->red, s));
+    HIPCHK(dgk::launch_msum(M->red, j + 2, L.sc + dgk::kScH1, s));
     HIPCHK(dgk::launch_mupdate(L.V, j + 1, n, L.sc + dgk::kScH1, Wn, s));
     HIPCHK(dgk::launch_mdot(L.V, j + 1, n, Wn, M->red, s));
     HIPCHK(dgk::launch_msum(M->red, j + 1, L.sc + dgk::kScH2, s));

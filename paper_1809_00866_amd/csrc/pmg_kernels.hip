@@ -205,7 +205,7 @@ __global__ void k_gmres_step(double* __restrict__ sc, int j, int m) {
   double* cs = sc + kScCs;
   double* sn = sc + kScSn;
   double* gv = sc + kScG;
-  const double w0 = sc[kScW0], hn = sc[kScHn];
+  const double w0 = sqrt(sc[kScH1 + j + 1]), hn = sc[kScHn];  // |w| before orthogonalisation
   for (int i = 0; i <= j; ++i) R[i] = sc[kScH1 + i] + sc[kScH2 + i];
   R[j + 1] = hn;
   // happy breakdown (or a zero column after one): later Krylov vectors are 0
