@@ -99,9 +99,20 @@ def cpu_baseline(sample_elems=1024):
     t = time.perf_counter() - t0
     dofs = sample_elems * o.nvar * o.nb
     assert np.all(np.isfinite(J))
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), model)
+    except OSError:
+        pass
+    try:
+        visible = len(os.sched_getaffinity(0))
+    except AttributeError:
+        visible = os.cpu_count()
     return {"value": dofs / t, "unit": "DOFs/s", "cores": int(cores), "kind": "oracle",
             "sample": f"exact Jv rows of {sample_elems} random elements of the P3 32^3 workload "
-                      f"({dofs} DOFs), complex-step numpy oracle, {t:.2f} s"}
+                      f"({dofs} DOFs), complex-step numpy oracle, {t:.2f} s",
+            "host": {"cpu_model": model, "cpus_visible": visible}}
 
 
 PHASES = ("grad_jvp", "face_jvp", "vol_jvp", "grad_jvp_f32", "face_jvp_f32", "vol_jvp_f32", "block_probe",
