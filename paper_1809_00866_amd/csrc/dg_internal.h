@@ -172,7 +172,8 @@ hipError_t launch_bsr_apply_f32(int bs, const float* B, const int64_t* nbr, int 
                                 const double* x, double* y, hipStream_t s);
 hipError_t launch_to_f32(const double* x, float* y, int64_t n, hipStream_t s);
 hipError_t launch_gmres_init(double* sc, int m, hipStream_t s);
-hipError_t launch_gmres_step(double* sc, int j, int m, hipStream_t s);
+// ||w|| = sqrt(sum of the partials) into kScHn, then the Givens update of column j
+hipError_t launch_norm_gmres_step(const double* partial, int np, double* sc, int j, int m, hipStream_t s);
 hipError_t launch_gmres_backsolve(double* sc, int m, hipStream_t s);
 hipError_t launch_scale_by(int64_t n, double* x, const double* sc, hipStream_t s);
 

@@ -174,8 +174,8 @@ dg_status smooth(dg_context* c, MgState* M, int l, bool zero_start, hipStream_t 
     HIPCHK(dgk::launch_mdot(L.V, j + 1, n, Wn, M->red, s));
     HIPCHK(dgk::launch_msum(M->red, j + 1, L.sc + dgk::kScH2, s));
     HIPCHK(dgk::launch_mupdate(L.V, j + 1, n, L.sc + dgk::kScH2, Wn, s));
-    if ((st = lnorm(M, Wn, n, L.sc + dgk::kScHn, s)) != DG_OK) return st;
-    HIPCHK(dgk::launch_gmres_step(L.sc, j, m, s));
+    HIPCHK(dgk::launch_dot_partials(Wn, Wn, n, M->red, s));
+    HIPCHK(dgk::launch_norm_gmres_step(M->red, dgk::kRedBlocks, L.sc, j, m, s));
     HIPCHK(dgk::launch_scale_by(n, Wn, L.sc + dgk::kScInv, s));
   }
   HIPCHK(dgk::launch_gmres_backsolve(L.sc, m, s));

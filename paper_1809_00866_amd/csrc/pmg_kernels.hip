@@ -189,7 +189,7 @@ __global__ __launch_bounds__(BS) void k_bsr_apply(const S* __restrict__ B, const
 }
 
 // --- fixed-count GMRES bookkeeping (one thread; column j of the Hessenberg
-// matrix, already orthogonalised, arrives in h1 + h2 with ||w|| in hn) ---
+// matrix, already orthogonalised, arrives in h1 + h2; ||w|| from partials) ---
 
 __global__ void k_gmres_init(double* __restrict__ sc, int m) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -199,8 +199,18 @@ __global__ void k_gmres_init(double* __restrict__ sc, int m) {
   sc[kScFlag] = 0.0;
 }
 
-__global__ void k_gmres_step(double* __restrict__ sc, int j, int m) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// ||w|| after orthogonalisation from the partial sums of w.w (one workgroup
+// of 256 threads), then the Givens update of column j (thread 0).
+__global__ __launch_bounds__(256) void k_norm_gmres_step(const double* __restrict__ partial, int np,
+                                                         double* __restrict__ sc, int j, int m) {
+  __shared__ double wsum[4];
+  double a = 0.0;
+  for (int i = threadIdx.x; i < np; i += 256) a += partial[i];
+  for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = a;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  sc[kScHn] = sqrt((wsum[0] + wsum[1]) + (wsum[2] + wsum[3]));
   double* R = sc + kScR + (int64_t)j * (m + 1);  // column j, rows 0..j+1
   double* cs = sc + kScCs;
   double* sn = sc + kScSn;
@@ -333,8 +343,8 @@ hipError_t launch_gmres_init(double* sc, int m, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_gmres_step(double* sc, int j, int m, hipStream_t s) {
-  k_gmres_step<<<1, 64, 0, s>>>(sc, j, m);
+hipError_t launch_norm_gmres_step(const double* partial, int np, double* sc, int j, int m, hipStream_t s) {
+  k_norm_gmres_step<<<1, 256, 0, s>>>(partial, np, sc, j, m);
   return hipGetLastError();
 }
 
