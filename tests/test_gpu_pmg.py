@@ -79,6 +79,24 @@ def test_coarse_operators_match_the_inherited_oracle_operators(case):
     assert np.linalg.norm(y0 - ref) <= 1e-12 * np.linalg.norm(ref)
 
 
+def test_level_operators_stay_fp64_with_reduced_precision_storage(case):
+    """With BF16 factors the cycle applies FP32 copies of the coarse operators;
+    the level operators reported through the ABI stay the FP64 ones (1e-12)."""
+    from paper_1809_00866_amd import DG
+    o, mg = case["o"], case["mg"]
+    _say("level operators with bf16 storage")
+    g2 = DG(case["mesh"], case["k"], nq1d=case["nq"], mu=1e-2)
+    g2.mg_setup(case["w"], case["shift"], case["orders"], case["iters"], storage="bf16", use_graph=True)
+    rng = np.random.default_rng(11)
+    for l in range(1, mg.L + 1):
+        X = rng.standard_normal((o.ne, o.nvar, mg.nbs[l]))
+        y_o = (mg.A[l] @ X.reshape(-1)).reshape(X.shape)
+        y_g = _unflat(g2.mg_level_apply(l, torch.tensor(_flat(X), device="cuda")).cpu().numpy(), o.ne, o.nvar,
+                      mg.nbs[l])
+        assert np.linalg.norm(y_g - y_o) <= 1e-12 * np.linalg.norm(y_o)
+    g2.close()
+
+
 def test_vcycle_matches_the_oracle(case):
     o, mg, g = case["o"], case["mg"], case["g"]
     _say("V-cycle parity")
