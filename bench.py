@@ -99,6 +99,16 @@ def cpu_baseline(sample_elems=1024):
     t = time.perf_counter() - t0
     dofs = sample_elems * o.nvar * o.nb
     assert np.all(np.isfinite(J))
+    single = None
+    try:  # the same oracle restricted to one thread, on an eighth of the sample
+        from threadpoolctl import threadpool_limits
+        sub = sample[: max(1, sample_elems // 8)]
+        with threadpool_limits(1):
+            t1 = time.perf_counter()
+            o.jvp(U, V, elems=sub)
+            single = len(sub) * o.nvar * o.nb / (time.perf_counter() - t1)
+    except Exception:
+        pass
     model = "unknown"
     try:
         with open("/proc/cpuinfo") as fh:
@@ -111,8 +121,9 @@ def cpu_baseline(sample_elems=1024):
         visible = os.cpu_count()
     return {"value": dofs / t, "unit": "DOFs/s", "cores": int(cores), "kind": "oracle",
             "sample": f"exact Jv rows of {sample_elems} random elements of the P3 32^3 workload "
-                      f"({dofs} DOFs), complex-step numpy oracle, {t:.2f} s",
-            "host": {"cpu_model": model, "cpus_visible": visible}}
+                      f"({dofs} DOFs), complex-step numpy oracle, {t:.2f} s; single_thread_value: the first eighth of "
+                      f"those elements with the BLAS/OpenMP pools limited to one thread",
+            "host": {"cpu_model": model, "cpus_visible": visible}, "single_thread_value": single}
 
 
 PHASES = ("grad_jvp", "face_jvp", "vol_jvp", "grad_jvp_f32", "face_jvp_f32", "vol_jvp_f32", "block_probe",
@@ -417,6 +428,12 @@ def main():
                 "frac": achieved / PEAK_FP64, "traffic": measured_traffic(dom), "traffic_unit": "bytes/launch",
                 "kernel_ms": {k: round(avg[k], 4) for k in avg},
                 "ms_per_step_with_kernel_events": wall_prof * 1e3 / args.steps,
+                # the whole Jv against an algorithmic count that also includes the
+                # pointwise tangent flops (an estimate: 6.2 kflop/DOF at P3), i.e. the
+                # DOFs/s ideal of 1.27e10 at the FP64 peak
+                "whole_jv_estimate": {"flop_per_dof": 6200.0, "achieved": value * 6200.0 / 1e12,
+                                      "peak": PEAK_FP64, "unit": "TFLOP/s",
+                                      "frac": value * 6200.0 / 1e12 / PEAK_FP64},
                 "flops_per_launch": {k: flops[k] for k in flops}}
     g.close()
     del w, v, out
