@@ -94,9 +94,12 @@ def cpu_baseline(sample_elems=1024):
     U[need] = o.project(fld, elems=need)
     V = np.zeros_like(U)
     V[need] = np.random.default_rng(866).standard_normal((len(need), o.nvar, o.nb))
+    c0 = time.process_time()
     t0 = time.perf_counter()
     J = o.jvp(U, V, elems=sample)
     t = time.perf_counter() - t0
+    # threads the oracle actually kept busy: process CPU time over wall time
+    busy = (time.process_time() - c0) / t
     dofs = sample_elems * o.nvar * o.nb
     assert np.all(np.isfinite(J))
     single = None
@@ -119,7 +122,8 @@ def cpu_baseline(sample_elems=1024):
         visible = len(os.sched_getaffinity(0))
     except AttributeError:
         visible = os.cpu_count()
-    return {"value": dofs / t, "unit": "DOFs/s", "cores": int(cores), "kind": "oracle",
+    return {"value": dofs / t, "unit": "DOFs/s", "cores": max(1, int(round(busy))), "kind": "oracle",
+            "threads_available": int(cores), "cpu_busy_threads": round(busy, 2),
             "sample": f"exact Jv rows of {sample_elems} random elements of the P3 32^3 workload "
                       f"({dofs} DOFs), complex-step numpy oracle, {t:.2f} s; single_thread_value: the first eighth of "
                       f"those elements with the BLAS/OpenMP pools limited to one thread",
