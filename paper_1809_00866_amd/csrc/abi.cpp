@@ -366,7 +366,7 @@ dg_status dg_create(const dg_params* prm, const dg_mesh* mesh, dg_context** out)
   const bool want_mfma = lattice && !(variant && std::strcmp(variant, "reference") == 0);
   if (want_mfma && dgk::has_mfma(cfg)) {
     dgh::MfmaHost M = dgh::build_mfma_tables(T);
-    std::vector<const std::vector<double>*> mp = {&M.vA, &M.pA, &M.fA, &M.tA, &M.lA};
+    std::vector<const std::vector<double>*> mp = {&M.vA, &M.pA, &M.fA, &M.tA, &M.lA, &M.dA};
     size_t mtot = 0;
     for (auto* v : mp) mtot += v->size();
     if ((st = dalloc(&c->d_mtab, mtot)) != DG_OK) return cleanup(st);
@@ -383,10 +383,11 @@ dg_status dg_create(const dg_params* prm, const dg_mesh* mesh, dg_context** out)
     c->mt.fA = c->d_mtab + moff[2];
     c->mt.tA = c->d_mtab + moff[3];
     c->mt.lA = c->d_mtab + moff[4];
+    c->mt.dA = c->d_mtab + moff[5];
     c->mt.kl = M.kl;
     c->use_mfma = true;
     // FP32 copies (interpolation table in the FP32 fragment order)
-    std::vector<const std::vector<double>*> fp = {&M.vAf, &M.pA, &M.fA, &M.tA, &M.lA};
+    std::vector<const std::vector<double>*> fp = {&M.vAf, &M.pA, &M.fA, &M.tA, &M.lA, &M.dAf};
     size_t ftot = 0;
     for (auto* v : fp) ftot += v->size();
     if ((st = dalloc(&c->d_mtab_f, ftot)) != DG_OK) return cleanup(st);
@@ -404,6 +405,7 @@ dg_status dg_create(const dg_params* prm, const dg_mesh* mesh, dg_context** out)
     c->mtf.fA = c->d_mtab_f + foff[2];
     c->mtf.tA = c->d_mtab_f + foff[3];
     c->mtf.lA = c->d_mtab_f + foff[4];
+    c->mtf.dA = c->d_mtab_f + foff[5];
     c->mtf.kl = M.kl;
     // allocated here, not on first use: a captured V-cycle may call either operator
     if ((st = dalloc(&c->d_Hf, (size_t)dim * c->nv * T.nfq * ne)) != DG_OK) return cleanup(st);

@@ -59,6 +59,10 @@ struct MTablesT {
   const R* fA;     // [DIM][2][MB][KSF][64]     face projection: +/- w_f|J_f| phi(fq, b)
   const R* tA;     // [DIM][RBF][6][2*KSB][64]  face traces (uL, uR, G_1..3 averaged, {r})
   const R* lA;     // [DIM][MB][3*KSB][64]      modal corrected gradient [L0 | L1 | L2]
+  const R* dA;     // [DIM][3][4][64]           maps between the points of one face: d/dx_t
+                   //                           (t: the two tangential directions) and the
+                   //                           averaged lifting from the jump; k = face point in
+                   //                           the row order of this precision's MFMA result
   int kl;          // max nonzeros per row of the maps (p+1: they act along tensor lines)
 };
 using MTables = MTablesT<double>;
@@ -204,6 +208,8 @@ namespace dgh {
 struct HostTables {
   int dim = 0, nb = 0, nq1 = 0, nq = 0, nfq = 0;
   std::vector<double> vPhi, vWD, vWPhi, vLift, fPhi, fDphi, fLift, fWPhi, vXi;
+  std::vector<double> x1;       // 1D Gauss points (reference coordinate)
+  double h[3] = {0, 0, 0};      // lattice spacing per direction
   std::vector<int> alpha;  // [nb][dim]
 };
 
@@ -235,6 +241,7 @@ CurvedHost build_curved_tables(const HostTables& T, int order, const double* xyz
 struct MfmaHost {
   std::vector<double> vA, pA, fA, tA, lA;
   std::vector<double> vAf;  // interpolation table in the FP32 fragment order (4 MB k-steps per point block)
+  std::vector<double> dA, dAf;  // face point-to-point maps, FP64 / FP32 result-row order
   int kl = 0;
 };
 MfmaHost build_mfma_tables(const HostTables& T);

@@ -362,7 +362,11 @@ DEV void face_mfma_body(const double* __restrict__ U, const double* __restrict__
   // trace channel ch of one column block into the stage; the trace table of
   // the current point block is read from LDS when the kernel stages it there
   constexpr bool kTabLds = FaceTab<R, NB>::lds;
-  auto trace = [&](int rbf, int ch, int c, const R* bf) {
+  auto put = [&](int ch, int c, const F& d) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) stage[ch * NV + c][MP<R>::drow(g, r)][col] = d[r];
+  };
+  auto trace_d = [&](int rbf, int ch, const R* bf) {
     const int k0 = (ch == 1) ? KSB : 0;
     const int k1 = (ch == 0) ? KSB : 2 * KSB;
     F d = {0, 0, 0, 0};
@@ -372,15 +376,54 @@ DEV void face_mfma_body(const double* __restrict__ U, const double* __restrict__
                           : mt.tA[((((size_t)P * RBF + rbf) * NCH + ch) * 2 * KSB + ks2) * 64 + lane];
       d = MP<R>::mma(a, bf[ks2], d);
     }
+    return d;
+  };
+  auto trace = [&](int rbf, int ch, int c, const R* bf) { put(ch, c, trace_d(rbf, ch, bf)); };
+  // One point block: the tangential components of the averaged gradient are
+  // d/dx_t of the averaged trace {U} = (uL + uR)/2 on the face points (exact:
+  // the points resolve the trace polynomial), and the averaged lifting is a map
+  // of the jump uL - uR on the same points (the quadrature that defines it):
+  // 16-point contractions instead of ones over the modes of both sides.  The
+  // trace results, held as MFMA result rows, are the B operand of these
+  // products as they stand.
+  constexpr bool kPts = RBF == 1;
+  constexpr int KT = std::is_same<R, double>::value ? (NFQ + 3) / 4 : 4;
+  auto point_channels = [&](int c, const R* bf) {
+    const F dL = trace_d(0, 0, bf), dR = trace_d(0, 1, bf);
+    put(0, c, dL);
+    put(1, c, dR);
+    R avg[4], jmp[4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) stage[ch * NV + c][MP<R>::drow(g, r)][col] = d[r];
+    for (int r = 0; r < 4; ++r) {
+      avg[r] = R(0.5) * (dL[r] + dR[r]);
+      jmp[r] = dL[r] - dR[r];
+    }
+#pragma unroll
+    for (int jt = 0; jt < 3; ++jt) {
+      F d = {0, 0, 0, 0};
+#pragma unroll
+      for (int ks = 0; ks < KT; ++ks)
+        d = MP<R>::mma(mt.dA[((P * 3 + jt) * 4 + ks) * 64 + lane], jt < 2 ? avg[ks] : jmp[ks], d);
+      const int ch = jt == 2 ? 5 : 2 + ((jt == 0) ? (P == 0 ? 1 : 0) : (P == 2 ? 1 : 2));
+      put(ch, c, d);
+    }
+  };
+  // all six channels of variable c from its B fragments
+  auto channels = [&](int rbf, int c, const R* bf) {
+    if constexpr (kPts) {
+      point_channels(c, bf);
+      trace(rbf, 2 + P, c, bf);
+    } else {
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch) trace(rbf, ch, c, bf);
+    }
   };
   // Work split.  Balanced (FP64, one face-point block): wave w traces all
   // channels of variable w; the channels of variable 4 are shared out as
-  // {uL, G_1}, {uR, G_2}, {G_3}, {r}, so each wave issues about a quarter of
-  // the MFMAs of a phase.  Otherwise (FP32, several point blocks) column block
-  // cb = w + 4i goes to wave w whole: fewer live fragments at the cost of an
-  // uneven split (measured faster there).
+  // {uL, uR, tangential G, {r}}, {normal G}, {}, {} (the point products need
+  // both traces in their own registers).  Otherwise (FP32, several point blocks)
+  // column block cb = w + 4i goes to wave w whole: fewer live fragments at the
+  // cost of an uneven split (measured faster there).
   constexpr bool kBalanced = std::is_same<R, double>::value && RBF == 1;
   constexpr int NCB = NS * NV;               // (value/tangent, variable) column blocks
   constexpr int NCBW = kBalanced ? NS : (NCB + 3) / 4;
@@ -410,21 +453,14 @@ DEV void face_mfma_body(const double* __restrict__ U, const double* __restrict__
       if constexpr (kBalanced) {
         R Bs[2 * KSB];
         load_b(s, 4, Bs);
-#pragma unroll
-        for (int ch = 0; ch < NCH; ++ch) {
-          const int owner = ch < 4 ? (ch & 1) : ch - 2;
-          if (owner == wave) trace(rbf, ch, 4, Bs);
-        }
-#pragma unroll
-        for (int ch = 0; ch < NCH; ++ch) trace(rbf, ch, wave, Bf[s]);
+        if (wave == 3) point_channels(4, Bs);
+        else if (wave == 0) trace(rbf, 2 + P, 4, Bs);
+        channels(rbf, wave, Bf[s]);
       } else {
 #pragma unroll
         for (int i = 0; i < NCBW; ++i) {
           const int cb = wave + 4 * i;
-          if (cb < NCB && cb / NV == s) {
-#pragma unroll
-            for (int ch = 0; ch < NCH; ++ch) trace(rbf, ch, cb % NV, Bf[i]);
-          }
+          if (cb < NCB && cb / NV == s) channels(rbf, cb % NV, Bf[i]);
         }
       }
       __syncthreads();

@@ -140,6 +140,8 @@ HostTables build_tables(int dim, int order, int basis, int nq1d, const double h[
 
   std::vector<double> x1, w1;
   gauss_legendre(nq1d, x1, w1);
+  T.x1 = x1;
+  for (int i = 0; i < dim; ++i) T.h[i] = h[i];
 
   double detJ = 1.0;
   for (int i = 0; i < dim; ++i) detJ *= 0.5 * h[i];
@@ -607,6 +609,67 @@ MfmaHost build_mfma_tables(const HostTables& T) {
               v = T.fLift[(((size_t)p * 2 + (left ? 0 : 1)) * nfq + fq) * nb + b];
             M.tA[((((size_t)p * RBF + rbf) * 6 + ch) * 2 * KSB + ks2) * 64 + l] = v;
           }
+  // Point-to-point maps on one face's points (one 16-point block), slots 0-1:
+  // tangential derivatives.  The face
+  // points are the tensor Gauss grid of the two tangential directions t0 < t1
+  // (t0 fastest), so d/dx_t of the interpolating tensor polynomial is the 1D
+  // Lagrange derivative along that grid line, scaled by 2/h_t.  Exact on face
+  // traces: a trace has degree <= order <= nq1 - 1 in each tangential variable.
+  // A[i][k] = D_t[i][k] with k the point in result-row order drow(g, ks), so the
+  // 16x16 result of a trace MFMA is directly the B operand of this product.
+  if (dim == 3 && nfq <= 16) {
+    const int n1 = T.nq1;
+    int maxdeg = 0;
+    for (int v : T.alpha) maxdeg = std::max(maxdeg, v);
+    if (maxdeg > n1 - 1) throw std::logic_error("face points do not resolve the trace degree");
+    std::vector<double> Dl((size_t)n1 * n1, 0.0);  // Dl[k][m] = l_m'(x_k)
+    std::vector<double> bw(n1, 1.0);
+    for (int m = 0; m < n1; ++m)
+      for (int n = 0; n < n1; ++n)
+        if (n != m) bw[m] /= (T.x1[m] - T.x1[n]);
+    for (int k = 0; k < n1; ++k) {
+      double diag = 0.0;
+      for (int m = 0; m < n1; ++m)
+        if (m != k) {
+          Dl[k * n1 + m] = (bw[m] / bw[k]) / (T.x1[k] - T.x1[m]);
+          diag -= Dl[k * n1 + m];
+        }
+      Dl[k * n1 + k] = diag;
+    }
+    auto dt = [&](int p, int jt, int i, int k) {  // D_t[i][k] on face p, tangential index jt
+      const int t = (jt == 0) ? (p == 0 ? 1 : 0) : (p == 2 ? 1 : 2);
+      const int i0 = i % n1, i1 = i / n1, k0 = k % n1, k1 = k / n1;
+      if (jt == 0) return i1 == k1 ? (2.0 / T.h[t]) * Dl[i0 * n1 + k0] : 0.0;
+      return i0 == k0 ? (2.0 / T.h[t]) * Dl[i1 * n1 + k1] : 0.0;
+    };
+    // Slot 2: the averaged lifting from the jump at the face points.  With the
+    // face mass matrices written out, {r}(x_f) = -1/4 sum_g P_fg w_g (uL - uR)(x_g),
+    // P_fg = sum_b phi+_b(x_f) phi+_b(x_g) + phi-_b(x_f) phi-_b(x_g): the same
+    // quadrature as the modal lifting map, so equal to it up to rounding.
+    auto lift = [&](int p, int i, int k) {
+      double acc = 0.0;
+      for (int b = 0; b < nb; ++b)
+        for (int side = 0; side < 2; ++side)
+          acc += T.fPhi[(((size_t)p * 2 + side) * nfq + i) * nb + b] * T.fWPhi[(((size_t)p * 2 + side) * nfq + k) * nb + b];
+      return -0.25 * acc;
+    };
+    M.dA.assign((size_t)dim * 3 * 4 * 64, 0.0);
+    M.dAf.assign((size_t)dim * 3 * 4 * 64, 0.0);
+    for (int p = 0; p < dim; ++p)
+      for (int jt = 0; jt < 3; ++jt)
+        for (int ks = 0; ks < 4; ++ks)
+          for (int l = 0; l < 64; ++l) {
+            const int i = l & 15, g = l >> 4;
+            const size_t o = (((size_t)p * 3 + jt) * 4 + ks) * 64 + l;
+            const int k64 = g + 4 * ks, k32 = 4 * g + ks;
+            auto val = [&](int k) { return jt < 2 ? dt(p, jt, i, k) : lift(p, i, k); };
+            if (i < nfq && k64 < nfq) M.dA[o] = val(k64);
+            if (i < nfq && k32 < nfq) M.dAf[o] = val(k32);
+          }
+  } else {
+    M.dA.assign(64, 0.0);
+    M.dAf.assign(64, 0.0);
+  }
   // modal corrected-gradient maps in A-fragment order, k = (source, mode)
   M.lA.assign((size_t)dim * MB * 3 * KSB * 64, 0.0);
   for (int p = 0; p < dim; ++p)
