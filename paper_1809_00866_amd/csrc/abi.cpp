@@ -365,7 +365,12 @@ dg_status dg_create(const dg_params* prm, const dg_mesh* mesh, dg_context** out)
   const char* variant = std::getenv("DG_KERNEL_VARIANT");
   const bool want_mfma = lattice && !(variant && std::strcmp(variant, "reference") == 0);
   if (want_mfma && dgk::has_mfma(cfg)) {
-    dgh::MfmaHost M = dgh::build_mfma_tables(T);
+    dgh::MfmaHost M;
+    try {
+      M = dgh::build_mfma_tables(T);
+    } catch (const std::exception& ex) {
+      return cleanup(fail(DG_ERR_ARG, ex.what()));
+    }
     std::vector<const std::vector<double>*> mp = {&M.vA, &M.pA, &M.fA, &M.tA, &M.lA, &M.dA};
     size_t mtot = 0;
     for (auto* v : mp) mtot += v->size();
