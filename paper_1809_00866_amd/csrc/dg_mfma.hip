@@ -419,9 +419,11 @@ DEV void face_mfma_body(const double* __restrict__ U, const double* __restrict__
     }
   };
   // Work split.  Balanced (FP64, one face-point block): wave w traces all
-  // channels of variable w; the channels of variable 4 are shared out as
-  // {uL, uR, tangential G, {r}}, {normal G}, {}, {} (the point products need
-  // both traces in their own registers).  Otherwise (FP32, several point blocks)
+  // channels of variable w, except that wave 3 keeps only the trace and point
+  // products (uL, uR, tangential G, {r}) of variables 3 and 4 (the point
+  // products need both traces in its own registers) and the normal-gradient
+  // chains of variables 3 and 4 go to waves 1 and 2: 32/42/42/44 MFMA k-steps
+  // per wave and value/tangent pass at P3.  Otherwise (FP32, several point blocks)
   // column block cb = w + 4i goes to wave w whole: fewer live fragments at the
   // cost of an uneven split (measured faster there).
   constexpr bool kBalanced = std::is_same<R, double>::value && RBF == 1;
@@ -452,10 +454,14 @@ DEV void face_mfma_body(const double* __restrict__ U, const double* __restrict__
     for (int s = 0; s < NS; ++s) {
       if constexpr (kBalanced) {
         R Bs[2 * KSB];
-        load_b(s, 4, Bs);
-        if (wave == 3) point_channels(4, Bs);
-        else if (wave == 0) trace(rbf, 2 + P, 4, Bs);
-        channels(rbf, wave, Bf[s]);
+        if (wave != 0) load_b(s, wave == 1 ? 3 : 4, Bs);
+        if (wave == 3) {
+          point_channels(3, Bf[s]);
+          point_channels(4, Bs);
+        } else {
+          if (wave != 0) trace(rbf, 2 + P, wave == 1 ? 3 : 4, Bs);
+          channels(rbf, wave, Bf[s]);
+        }
       } else {
 #pragma unroll
         for (int i = 0; i < NCBW; ++i) {
