@@ -48,12 +48,17 @@ KERNELS = ("grad_jvp", "face_jvp", "vol_jvp")
 
 
 def kernel_source_sha():
-    """sha256[:16] over the sources of the timed Jv kernels (concatenated)."""
+    """sha256[:16] over the code of the timed Jv kernels' sources (concatenated;
+    line comments, indentation and blank lines left out, so an edit of a comment
+    does not orphan counters taken on the same code)."""
     import hashlib
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_1809_00866_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1809_00866_amd", "csrc", f), encoding="utf-8") as fh:
+            for line in fh:
+                code = line.split("//", 1)[0].strip()
+                if code:
+                    h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

@@ -27,6 +27,9 @@
 // Face kernel (one workgroup = 4 waves = 16 faces of one direction): MFMA
 // traces of both sides (values, averaged gradients, averaged lifting) -> LDS
 // stage -> one thread per (face point, face) evaluates the numerical flux.
+// With one 16-point block (P2, P3) only the two value traces and the normal
+// averaged gradient contract over modes; the tangential averaged gradients
+// and the averaged lifting are point-to-point products of those traces.
 #include "dg_device.h"
 
 namespace dgk {
