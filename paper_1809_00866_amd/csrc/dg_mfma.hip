@@ -421,15 +421,18 @@ DEV void face_mfma_body(const double* __restrict__ U, const double* __restrict__
       for (int ch = 0; ch < NCH; ++ch) trace(rbf, ch, c, bf);
     }
   };
-  // Work split.  Balanced (FP64, one face-point block): wave w traces all
-  // channels of variable w, except that wave 3 keeps only the trace and point
-  // products (uL, uR, tangential G, {r}) of variables 3 and 4 (the point
-  // products need both traces in its own registers) and the normal-gradient
-  // chains of variables 3 and 4 go to waves 1 and 2: 32/42/42/44 MFMA k-steps
-  // per wave and value/tangent pass at P3.  Otherwise (FP32, several point blocks)
-  // column block cb = w + 4i goes to wave w whole: fewer live fragments at the
-  // cost of an uneven split (measured faster there).
-  constexpr bool kBalanced = std::is_same<R, double>::value && RBF == 1;
+  // Work split.  Balanced (FP64 with one face-point block, and P4): wave w
+  // traces the channels of variable w.  With one point block wave 3 keeps only
+  // the trace and point products (uL, uR, tangential G, {r}) of variables 3
+  // and 4 (the point products need both traces in its own registers) and the
+  // normal-gradient chains of variables 3 and 4 go to waves 1 and 2: 32/42/42/44
+  // MFMA k-steps per wave and value/tangent pass at P3.  At P4 (all channels
+  // modal) the channels of variable 4 are shared out as {uL, G_1}, {uR, G_2},
+  // {G_3}, {r}: at most 117 k-steps per wave and pass instead of the 180 of
+  // whole column blocks (P4 face Jv 0.402 -> 0.336 ms FP64, 0.186 -> 0.177 ms
+  // FP32).  Otherwise (FP32 with one point block) column block cb = w + 4i goes
+  // to wave w whole: fewer live fragments at the cost of an uneven split.
+  constexpr bool kBalanced = (std::is_same<R, double>::value && RBF == 1) || RBF == 2;
   constexpr int NCB = NS * NV;               // (value/tangent, variable) column blocks
   constexpr int NCBW = kBalanced ? NS : (NCB + 3) / 4;
   R Bf[NCBW][2 * KSB];
@@ -457,13 +460,24 @@ DEV void face_mfma_body(const double* __restrict__ U, const double* __restrict__
     for (int s = 0; s < NS; ++s) {
       if constexpr (kBalanced) {
         R Bs[2 * KSB];
-        if (wave != 0) load_b(s, wave == 1 ? 3 : 4, Bs);
-        if (wave == 3) {
-          point_channels(3, Bf[s]);
-          point_channels(4, Bs);
+        if constexpr (kPts) {
+          if (wave != 0) load_b(s, wave == 1 ? 3 : 4, Bs);
+          if (wave == 3) {
+            point_channels(3, Bf[s]);
+            point_channels(4, Bs);
+          } else {
+            if (wave != 0) trace(rbf, 2 + P, wave == 1 ? 3 : 4, Bs);
+            channels(rbf, wave, Bf[s]);
+          }
         } else {
-          if (wave != 0) trace(rbf, 2 + P, wave == 1 ? 3 : 4, Bs);
-          channels(rbf, wave, Bf[s]);
+          load_b(s, 4, Bs);
+#pragma unroll
+          for (int ch = 0; ch < NCH; ++ch) {
+            const int owner = ch < 4 ? (ch & 1) : ch - 2;
+            if (owner == wave) trace(rbf, ch, 4, Bs);
+          }
+#pragma unroll
+          for (int ch = 0; ch < NCH; ++ch) trace(rbf, ch, wave, Bf[s]);
         }
       } else {
 #pragma unroll
