@@ -421,8 +421,8 @@ DEV void face_mfma_body(const double* __restrict__ U, const double* __restrict__
       for (int ch = 0; ch < NCH; ++ch) trace(rbf, ch, c, bf);
     }
   };
-  // Work split.  Balanced (FP64 with one face-point block, and P4): wave w
-  // traces the channels of variable w.  With one point block wave 3 keeps only
+  // Work split.  Balanced (one or two face-point blocks, i.e. every compiled
+  // configuration): wave w traces the channels of variable w.  With one point block wave 3 keeps only
   // the trace and point products (uL, uR, tangential G, {r}) of variables 3
   // and 4 (the point products need both traces in its own registers) and the
   // normal-gradient chains of variables 3 and 4 go to waves 1 and 2: 32/42/42/44
@@ -430,9 +430,9 @@ DEV void face_mfma_body(const double* __restrict__ U, const double* __restrict__
   // modal) the channels of variable 4 are shared out as {uL, G_1}, {uR, G_2},
   // {G_3}, {r}: at most 117 k-steps per wave and pass instead of the 180 of
   // whole column blocks (P4 face Jv 0.402 -> 0.336 ms FP64, 0.186 -> 0.177 ms
-  // FP32).  Otherwise (FP32 with one point block) column block cb = w + 4i goes
-  // to wave w whole: fewer live fragments at the cost of an uneven split.
-  constexpr bool kBalanced = (std::is_same<R, double>::value && RBF == 1) || RBF == 2;
+  // FP32; P3 FP32 0.110 -> 0.096 ms).  Otherwise (more point blocks) column
+  // block cb = w + 4i goes to wave w whole.
+  constexpr bool kBalanced = RBF <= 2;
   constexpr int NCB = NS * NV;               // (value/tangent, variable) column blocks
   constexpr int NCBW = kBalanced ? NS : (NCB + 3) / 4;
   R Bf[NCBW][2 * KSB];
