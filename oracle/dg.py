@@ -250,11 +250,17 @@ class DGOracle:
         Uc = U.astype(np.complex128)
         return np.imag(self.residual(Uc, elems, U_lift=U + 1j * h * V)) / h
 
+    @staticmethod
+    def fd_step(U, V, eps=1e-9):
+        """Step of the finite-difference Jv, eq. (epsdef) as printed:
+        Delta = eps*sqrt(1 + ||U||)/||V||, with L2 norms, which equal the DOF
+        2-norms for an orthonormal basis."""
+        return eps * np.sqrt(1.0 + np.linalg.norm(U)) / np.linalg.norm(V)
+
     def jvp_fd(self, U, V, R0=None, eps=1e-9, elems=None):
         """Finite-difference Jv of eqs. (matrix-free), (epsdef): one-sided,
-        Delta = eps*sqrt(1 + ||U||)/||V|| with L2 norms (= DOF 2-norms for an
-        orthonormal basis)."""
-        delta = eps * np.sqrt(1.0 + np.linalg.norm(U)) / np.linalg.norm(V)
+        (R(U + Delta V) - R(U))/Delta with Delta from fd_step."""
+        delta = self.fd_step(U, V, eps)
         if R0 is None:
             R0 = self.residual(U, elems)
         return (self.residual(U + delta * V, elems) - R0) / delta

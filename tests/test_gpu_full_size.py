@@ -1,0 +1,118 @@
+"""Full-size parity at P4: the 24^3 lattice (affine) and the perturbed 24^3
+lattice (trilinear elements with their own Jacobians), residual and exact Jv
+(eq. NSdiscrRes and its linearisation, Sec. 2.2), in the launch configuration
+the benchmark times, against the FP64 oracle on sampled elements.
+
+The sample holds the first and last tile of 16 elements, both sides of every
+tile boundary among the first tiles, both sides of every boundary between the
+contiguous element ranges that the kernels hand to the 8 XCDs, and random
+elements.  Each check is element-wise (max abs error over the sampled DOFs) as
+well as a 2-norm over the sample:
+
+* FP64 operator: both <= 1e-12 of the scale max(|R|, |R_volume|) (residual)
+  or |Jv| (Jacobian-vector product);
+* FP32 operator (contractions and pointwise fluxes in FP32): <= 1e-5 of the
+  same scales, and above 1e-10 (genuinely reduced precision); the measured
+  errors are printed.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import DGOracle, NavierStokes
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu, pytest.mark.timeout(400)]  # the oracle projects 13,824 elements
+
+TILE = 16
+N_XCD = 8
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def boundary_sample(ne, seed=0, n_random=12):
+    """Elements at the first and last tile, tile boundaries and XCD range boundaries."""
+    nblk = (ne + TILE - 1) // TILE
+    q, r = divmod(nblk, N_XCD)
+    s = {0, 1, TILE - 1, ne - 1, ne - 2, (nblk - 1) * TILE}
+    for t in range(1, 4):                              # boundaries of the first tiles
+        s.update({t * TILE - 1, t * TILE})
+    for x in range(1, N_XCD):                          # first tile of each XCD range
+        t0 = x * q + min(x, r)
+        s.update({t0 * TILE - 1, t0 * TILE})
+    rng = np.random.default_rng(seed)
+    s.update(rng.choice(ne, n_random, replace=False).tolist())
+    return np.array(sorted(e for e in s if 0 <= e < ne), dtype=np.int64)
+
+
+@pytest.fixture(scope="module", params=["cfg3", "cfg4"], ids=["P4-24cube-affine", "P4-24cube-curved"])
+def workload(request):
+    from paper_1809_00866_amd import DG
+    name = request.param
+    _say(f"full-size {name}: oracle projection")
+    cfg, mesh, fld = synth.preset(name)
+    o = DGOracle(mesh, cfg["order"], cfg["space"], cfg["nq1d"], NavierStokes(3, mu=cfg["mu"], flux="roe"))
+    U = o.project(fld)
+    _say(f"full-size {name}: GPU context")
+    g = DG(mesh, cfg["order"], basis=cfg["space"], nq1d=cfg["nq1d"], flux="roe", mu=cfg["mu"])
+    w = torch.tensor(o.to_flat(U), device="cuda")
+    v = torch.tensor(synth.random_vector(g.ndof, cfg["v_seed"]), device="cuda")
+    V = o.from_flat(v.cpu().numpy())
+    sample = boundary_sample(o.ne)
+    _say(f"full-size {name}: oracle on {len(sample)} sampled elements")
+    R, Rv = o.residual(U, elems=sample, return_parts=True)
+    J = o.jvp(U, V, elems=sample)
+    yield dict(name=name, o=o, g=g, w=w, v=v, V=V, sample=sample, R=R, Rv=Rv, J=J)
+    g.close()
+
+
+def _errors(got, ref, scale):
+    d = got - ref
+    return np.abs(d).max() / scale[0], np.linalg.norm(d) / scale[1]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_full_size_p4_residual(workload, precision):
+    o, g, s = workload["o"], workload["g"], workload["sample"]
+    R, Rv = workload["R"], workload["Rv"]
+    _say(f"full-size {workload['name']} residual {precision}")
+    Rg = o.from_flat(g.residual(workload["w"], precision=precision).cpu().numpy())[s]
+    scale = (max(np.abs(R).max(), np.abs(Rv).max()), max(np.linalg.norm(R), np.linalg.norm(Rv)))
+    e_max, e_2 = _errors(Rg, R, scale)
+    _say(f"  residual {precision}: max-entry error {e_max:.2e}, 2-norm error {e_2:.2e}")
+    if precision == "fp64":
+        assert e_max <= 1e-12 and e_2 <= 1e-12
+    else:
+        assert 1e-10 < e_2 and e_max <= 1e-5 and e_2 <= 1e-5
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_full_size_p4_jvp(workload, precision):
+    o, g, s, J, V = workload["o"], workload["g"], workload["sample"], workload["J"], workload["V"]
+    _say(f"full-size {workload['name']} jvp {precision}")
+    shift = 2.5
+    mode = "exact" if precision == "fp64" else "exact_fp32"
+    Jg = o.from_flat(g.jvp(workload["w"], workload["v"], shift=shift, mode=mode).cpu().numpy())[s]
+    ref = J + shift * V[s]
+    scale = (np.abs(ref).max(), np.linalg.norm(ref))
+    e_max, e_2 = _errors(Jg, ref, scale)
+    _say(f"  jvp {precision}: max-entry error {e_max:.2e}, 2-norm error {e_2:.2e}")
+    if precision == "fp64":
+        assert e_max <= 1e-12 and e_2 <= 1e-12
+    else:
+        assert 1e-10 < e_2 and e_max <= 1e-5 and e_2 <= 1e-5
+
+
+def test_boundary_sample_covers_tiles_and_xcd_ranges():
+    """Host check of the sample itself (24^3: 864 tiles, 108 per XCD)."""
+    s = boundary_sample(13824)
+    for x in range(N_XCD):
+        assert x * 1728 in s
+        if x:
+            assert x * 1728 - 1 in s
+    assert {0, 15, 16, 13808, 13823} <= set(s.tolist())
