@@ -47,6 +47,7 @@
 #ifndef DG_H
 #define DG_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -150,6 +151,23 @@ dg_status dg_residual_fp32(dg_context* ctx, const double* w, double* r, void* st
  *  out may not alias w, v or r_w. */
 dg_status dg_jvp(dg_context* ctx, const double* w, const double* r_w, const double* v, double shift,
                  int mode, double* out, void* stream);
+
+/* Allocation-free variant of dg_jvp in mode DG_JVP_EXACT, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): out = shift*v + J(w) v computed by
+ * the same kernels, bit for bit the result of dg_jvp, with the intermediate
+ * arrays (modal corrected gradients and face fluxes, or on curved meshes the
+ * transformed coefficients, face jumps and face fluxes) in a static device
+ * array of dg_jvp_noalloc_scratch_bytes() = 256 MiB that every GPU running the
+ * library holds until the process ends.  Calls no allocating routine.
+ * Returns DG_ERR_ARG when the context's arrays exceed that size (affine P3:
+ * 6,720 B per element, i.e. up to 39,945 elements; affine P4: 11,400 B per
+ * element, up to 23,546).  All calls on one GPU share the array, whatever the
+ * context or stream: calls that overlap on one GPU race, the caller
+ * serialises them.  w, v, out: device, ndof entries; out may not alias w or v. */
+dg_status dg_jvp_noalloc(dg_context* ctx, const double* w, const double* v, double shift, double* out,
+                         void* stream);
+size_t dg_jvp_noalloc_scratch_bytes(void);
 
 /* EWBJ setup: D_K = shift*I + dR_K/dU_K for every element (exact, by
  * coloured probing with exact Jv), factored by Gauss-Jordan with partial

@@ -20,7 +20,8 @@ DG_MG_V, DG_MG_FULL = 0, 1
 DG_ORTH_CGS2, DG_ORTH_MGS = 0, 1
 
 EXPORTED = ["dg_create", "dg_destroy", "dg_ndof", "dg_nbasis", "dg_nvar", "dg_nq", "dg_volume_points",
-            "dg_project", "dg_residual", "dg_residual_fp32", "dg_jvp", "dg_block_precond_setup", "dg_block_precond_apply",
+            "dg_project", "dg_residual", "dg_residual_fp32", "dg_jvp", "dg_jvp_noalloc", "dg_jvp_noalloc_scratch_bytes",
+            "dg_block_precond_setup", "dg_block_precond_apply",
             "dg_fgmres_solve", "dg_rosenbrock_step", "dg_mg_setup", "dg_mg_update_fine", "dg_mg_apply", "dg_mg_level_apply", "dg_mlp_nparams",
             "dg_mlp_set_weights", "dg_mlp_get_weights", "dg_mlp_features", "dg_mlp_forward", "dg_mlp_grad",
             "dg_mlp_train_step", "dg_mlp_apply", "dg_max_wave_speed",
@@ -90,6 +91,8 @@ def load():
         "dg_residual": (i, [ctx, vp, vp, vp]),
         "dg_residual_fp32": (i, [ctx, vp, vp, vp]),
         "dg_jvp": (i, [ctx, vp, vp, vp, d, i, vp, vp]),
+        "dg_jvp_noalloc": (i, [ctx, vp, vp, d, vp, vp]),
+        "dg_jvp_noalloc_scratch_bytes": (ctypes.c_size_t, []),
         "dg_block_precond_setup": (i, [ctx, vp, d, i, vp]),
         "dg_block_precond_apply": (i, [ctx, vp, vp, vp]),
         "dg_fgmres_solve": (i, [ctx, vp, d, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats), vp]),

@@ -119,6 +119,20 @@ class DG:
                                 _stream()), "dg_jvp")
         return out
 
+    @staticmethod
+    def noalloc_scratch_bytes():
+        """Size of the static device scratch that dg_jvp_noalloc uses."""
+        return int(L.load().dg_jvp_noalloc_scratch_bytes())
+
+    def jvp_noalloc(self, w, v, shift=0.0, out=None):
+        """shift*v + J(w) v through dg_jvp_noalloc (exact mode, static scratch)."""
+        self._vec(w, "w")
+        self._vec(v, "v")
+        out = self.empty() if out is None else self._vec(out, "out")
+        L.check(self.lib.dg_jvp_noalloc(self.ctx, _ptr(w), _ptr(v), float(shift), _ptr(out), _stream()),
+                "dg_jvp_noalloc")
+        return out
+
     def block_setup(self, w, shift, storage="fp64"):
         self._vec(w, "w")
         L.check(self.lib.dg_block_precond_setup(self.ctx, _ptr(w), float(shift), _STORAGE[storage], _stream()),

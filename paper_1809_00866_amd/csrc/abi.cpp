@@ -465,6 +465,7 @@ dg_status dg_create(const dg_params* prm, const dg_mesh* mesh, dg_context** out)
     c->h_pin = nullptr;
     return cleanup(fail(DG_ERR_OOM, "pinned host allocation failed"));
   }
+  if ((st = noalloc_scratch_address(&c->d_scratch)) != DG_OK) return cleanup(st);
   *out = c;
   return DG_OK;
 }

@@ -42,6 +42,10 @@ dg_status dalloc(T** p, size_t n) {
 
 void dfree(void* p);
 
+// Device address of the static scratch array of dg_jvp_noalloc on the current
+// device (looked up once per device; noalloc.hip).
+dg_status noalloc_scratch_address(void** out);
+
 // p-multigrid preconditioner state (pmg.cpp)
 struct MgState;
 void mg_destroy(MgState* m);
@@ -108,6 +112,7 @@ struct dg_context {
   int64_t ros_len = 0;           // entries of d_ros
   dgc::MgState* mg = nullptr;    // p-multigrid preconditioner (dg_mg_setup)
   dgc::MlpState* mlp = nullptr;  // learned preconditioner (dg_mlp_*)
+  void* d_scratch = nullptr;     // device address of the static scratch array on this device (dg_jvp_noalloc)
 };
 
 
