@@ -152,8 +152,9 @@ def cpu_baseline(sample_elems=1024):
             "host": {"cpu_model": model, "cpus_visible": visible}, "single_thread_value": single}
 
 
-PHASES = ("grad_jvp", "face_jvp", "vol_jvp", "grad_jvp_f32", "face_jvp_f32", "vol_jvp_f32", "block_probe",
-          "block_invert", "block_apply", "arnoldi", "mg_vcycle")
+PHASES = ("grad_jvp", "face_jvp", "vol_jvp", "grad_jvp_f32", "face_jvp_f32", "vol_jvp_f32", "grad_jvp_bf16",
+          "face_jvp_bf16", "vol_jvp_bf16", "block_probe", "block_invert", "block_apply", "arnoldi", "mg_vcycle",
+          "mlp_apply")
 STORAGE_BYTES = {"fp64": 8, "fp32": 4, "bf16": 2}
 
 
@@ -179,7 +180,7 @@ def solve_phases(g, w, shift, b, cfg, precond, storage, curved):
             out[k] = {"ms_total": round(ms, 3), "calls": n, "ms_per_call": round(ms / n, 4)}
     nfq = cfg["nq1d"] ** 2
     fl = jv_kernel_flops(g.ne, g.nb, g.nq, nfq, 3)
-    for suf, peak in (("", PEAK_FP64), ("_f32", PEAK_FP32)):
+    for suf, peak in (("", PEAK_FP64), ("_f32", PEAK_FP32), ("_bf16", PEAK_FP32)):
         ks = [k + suf for k in KERNELS]
         if curved or not all(k in out for k in ks):
             continue
@@ -309,12 +310,15 @@ def mg_trajectory(n_steps=4, lag=1, cycle="v", scheme="be"):
             "seconds": total, "setup_s": t_setup, "solve_s": t_solve, "iters_per_step": iters}
 
 
-def learned_preconditioner(train_steps=3000, max_iter=300):
-    """The learned element-local preconditioner on the P3 32^3 workload:
-    training pairs from backward-Euler snapshots 0, 2, 4 (CFL 100), 1e5 pairs
-    sampled, Adam with batch 1024; evaluation on the held-out snapshot 6
-    system against block Jacobi, no preconditioner, the untrained network and
-    the p-multigrid V-cycle."""
+def learned_preconditioner(train_steps=3000, max_iter=1000):
+    """The learned element-local preconditioner on the P3 32^3 workload, as a
+    correction to block Jacobi (z_K = D_K^-1 r_K + s_K MLP(x_K); a zero last
+    layer is block Jacobi exactly): pairs from backward-Euler snapshots 0, 2, 4
+    (inputs r = R(w) and three terms of the block-Jacobi-preconditioned Krylov
+    sequence, targets the solutions of G z = r to 1e-6), 1e5 pairs sampled,
+    Adam with batch 1024; the held-out snapshot 6 system solved to 1e-8 with
+    block Jacobi, the trained correction (with and without its judge), the
+    untrained correction, no preconditioner and the p-multigrid V-cycle."""
     import torch
     import synth
     from paper_1809_00866_amd import DG
@@ -325,14 +329,17 @@ def learned_preconditioner(train_steps=3000, max_iter=300):
     t0 = time.perf_counter()
     states = LR.trajectory(g, g.project_field(fld), 6, cfg["cfl"], cfg["order"], h)
     shifts = [LR.time_step(g, s, cfg["cfl"], cfg["order"], h) for s in states]
-    XT = [LR.pairs(g, states[k], shifts[k]) for k in (0, 2, 4)]
+    g.mlp_set_mode("correct_bj")
+    XT = [LR.pairs(g, states[k], shifts[k], n_krylov=3) for k in (0, 2, 4)]
     X = torch.cat([a for a, _ in XT])
     T = torch.cat([b for _, b in XT])
-    Xv, Tv = LR.pairs(g, states[6], shifts[6])
+    Xv, Tv = LR.pairs(g, states[6], shifts[6], n_krylov=3)
     torch.cuda.synchronize()
     t_data = time.perf_counter() - t0
     n_in, n_out = g.mlp_sizes
-    theta0 = torch.from_numpy(synth.mlp_init_weights(n_in, n_out, seed=1809))
+    theta0 = synth.mlp_init_weights(n_in, n_out, seed=1809)
+    theta0[-(n_out * 256 + n_out):] = 0.0          # W3, b3: the untrained correction is zero
+    theta0 = torch.from_numpy(theta0)
     g.mlp_set_weights(theta0)
     sub = torch.randperm(X.shape[0], generator=torch.Generator().manual_seed(0))[:100000].cuda()
     Xt, Tt = X[sub].contiguous(), T[sub].contiguous()
@@ -343,6 +350,7 @@ def learned_preconditioner(train_steps=3000, max_iter=300):
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
     val1 = LR.validation_loss(g, Xv, Tv)
+    theta1 = g.mlp_get_weights()
     w6, sh6 = states[6], shifts[6]
     b = -g.residual(w6)
     g.block_setup(w6, sh6)
@@ -358,10 +366,11 @@ def learned_preconditioner(train_steps=3000, max_iter=300):
 
     run("block_jacobi", precond="bj")
     run("none", precond="none")
-    run("learned", precond="mlp")
-    run("learned_with_judge", precond="mlp", rho_ref=held["block_jacobi"]["rho"])
+    run("learned_correction", precond="mlp")
+    run("learned_correction_with_judge", precond="mlp", rho_ref=held["block_jacobi"]["rho"])
     g.mlp_set_weights(theta0)
-    run("untrained", precond="mlp")
+    run("untrained_correction", precond="mlp")
+    g.mlp_set_weights(theta1)
     orders, its = LR.mg_levels(cfg["order"])
     torch.cuda.synchronize()
     a = time.perf_counter()
@@ -371,7 +380,8 @@ def learned_preconditioner(train_steps=3000, max_iter=300):
     run("p_multigrid", precond="mg")
     held["p_multigrid"]["setup_s"] = mg_setup_s
     g.close()
-    return {"workload": "P3 32^3, backward-Euler snapshots 0/2/4 (train) and 6 (held out), CFL 100",
+    return {"workload": f"P3 32^3, backward-Euler snapshots 0/2/4 (train) and 6 (held out), CFL {cfg['cfl']:g}; "
+                        "network = correction to block Jacobi",
             "pairs_available": int(X.shape[0]), "pairs_train": int(Xt.shape[0]), "pairs_val": int(Xv.shape[0]),
             "train_steps": train_steps, "batch": 1024, "data_s": t_data, "train_s": t_train,
             "loss_first": float(hist[0]), "loss_last": float(hist[-1]), "val_loss_untrained": val0,
@@ -441,6 +451,18 @@ def main():
     wall32 = time.perf_counter() - t0
     jv_fp32 = {"value": g.ndof / (wall32 / args.steps), "unit": "DOFs/s", "ms_per_step": wall32 * 1e3 / args.steps,
                "rel_diff_vs_fp64": float((out32 - out).norm() / out.norm())}
+    # the BF16-contraction operator (BF16 operands, FP32 accumulation, FP32
+    # pointwise fluxes) on the same workload
+    for _ in range(args.warmup):
+        g.jvp(w, v, out=out32, mode="exact_bf16")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g.jvp(w, v, out=out32, mode="exact_bf16")
+    torch.cuda.synchronize()
+    wall16 = time.perf_counter() - t0
+    jv_bf16 = {"value": g.ndof / (wall16 / args.steps), "unit": "DOFs/s", "ms_per_step": wall16 * 1e3 / args.steps,
+               "rel_diff_vs_fp64": float((out32 - out).norm() / out.norm())}
     del out32
     ms_per_step = wall * 1e3 / args.steps
     value = g.ndof / (wall / args.steps)
@@ -484,7 +506,7 @@ def main():
            "config": {"workload": "exact Jv, 3D compressible NS, P3 (Nb=20), 32^3 periodic hexes, 4^3/4^2 Gauss, "
                                   "Roe + BR2, Taylor-Green-like field Mach 0.1 Re 1600",
                       "n_elem": int(32 ** 3), "ndof": int(32 ** 3 * 100), "dofs_per_variable": int(32 ** 3 * 20)},
-           "roofline": roofline, "jv_fp32": jv_fp32}
+           "roofline": roofline, "jv_fp32": jv_fp32, "jv_bf16": jv_bf16}
     if not args.no_solve:
         res["time_to_tol"] = time_to_tolerance("fp64")
         res["time_to_tol_fp32_blocks"] = time_to_tolerance("fp32")
@@ -492,6 +514,7 @@ def main():
         res["time_to_tol_pmg"] = time_to_tolerance("fp64", precond="mg")
         res["time_to_tol_pmg_fp32_smoothing"] = time_to_tolerance("fp32", precond="mg", fine_precision="fp32")
         res["time_to_tol_pmg_bf16_factors"] = time_to_tolerance("bf16", precond="mg", fine_precision="fp32")
+        res["time_to_tol_pmg_bf16_operator"] = time_to_tolerance("bf16", precond="mg", fine_precision="bf16")
         res["time_to_tol_pmg_fp32_rescaled"] = time_to_tolerance("fp32", precond="mg", fine_precision="fp32",
                                                                  rescale=True)
         res["time_to_tol_pmg_fp32_coarse_ilu"] = time_to_tolerance("fp32", precond="mg", fine_precision="fp32",

@@ -69,7 +69,7 @@ typedef enum {
 
 enum { DG_BASIS_PK = 0, DG_BASIS_QK = 1 };          /* total degree / tensor degree */
 enum { DG_FLUX_LF = 0, DG_FLUX_ROE = 1 };           /* convective numerical flux */
-enum { DG_JVP_EXACT = 0, DG_JVP_FD = 1, DG_JVP_EXACT_FP32 = 2, DG_JVP_STAB = 3 };  /* Jv mode */
+enum { DG_JVP_EXACT = 0, DG_JVP_FD = 1, DG_JVP_EXACT_FP32 = 2, DG_JVP_STAB = 3, DG_JVP_EXACT_BF16 = 4 };  /* Jv mode */
 enum { DG_FP64 = 0, DG_FP32 = 1, DG_BF16 = 2 };     /* block-factor storage */
 enum { DG_PREC_NONE = 0, DG_PREC_BJ = 1, DG_PREC_MG = 2, DG_PREC_MLP = 3 };  /* FGMRES preconditioner */
 enum { DG_ORTH_CGS2 = 0, DG_ORTH_MGS = 1 };         /* FGMRES orthogonalisation */
@@ -137,6 +137,15 @@ dg_status dg_residual(dg_context* ctx, const double* w, double* r, void* stream)
  * and smoothers; relative error of order 1e-6 against the FP64 residual. */
 dg_status dg_residual_fp32(dg_context* ctx, const double* w, double* r, void* stream);
 
+/* The same residual with BF16 contractions: every basis contraction (traces,
+ * interpolation, corrected gradients, projections) takes BF16 operands (the
+ * FP32 tables and the intermediate values rounded to nearest even) and
+ * accumulates in FP32 on the BF16 matrix cores; pointwise fluxes in FP32; w and
+ * r stay FP64.  3D P2-P4 lattices only (DG_ERR_ARG otherwise).  Relative error
+ * of order 1e-3 against the FP64 residual (BF16 keeps 8 significant bits);
+ * for preconditioners and smoothers only. */
+dg_status dg_residual_bf16(dg_context* ctx, const double* w, double* r, void* stream);
+
 /* out = shift*v + J(w) v.
  *  mode DG_JVP_EXACT: exact directional derivative of the residual (the
  *  Jacobian forms j_h of Sec. 2.2 applied to v), FP64.
@@ -145,6 +154,8 @@ dg_status dg_residual_fp32(dg_context* ctx, const double* w, double* r, void* st
  *  (device, nullable) to skip its evaluation.  ||v|| = 0 gives out = 0 + shift*v.
  *  mode DG_JVP_EXACT_FP32: the exact tangent computed like dg_residual_fp32
  *  (FP32 contractions and pointwise arithmetic; for preconditioners only).
+ *  mode DG_JVP_EXACT_BF16: the exact tangent computed like dg_residual_bf16
+ *  (BF16 contractions, FP32 accumulation and pointwise arithmetic).
  *  mode DG_JVP_STAB: J replaced by its BR2 stabilisation part (the last term
  *  of eq. jacTrilFNURef: the tangent through the face lifting argument
  *  eta {r} of the face viscous flux only), FP64; not a solver mode.
@@ -271,10 +282,12 @@ typedef struct {
   int use_graph;        /* nonzero: capture one cycle into a hipGraph at setup;
                            every apply replays it on a library stream ordered
                            against the caller's stream by events */
-  int fine_precision;   /* DG_FP64 or DG_FP32: the fine-level operator inside
-                           the cycle (smoother products and the defect) and the
-                           probing of the coarse operators as the exact FP64 Jv
-                           or its FP32 variant; the outer solve stays FP64 */
+  int fine_precision;   /* DG_FP64, DG_FP32 or DG_BF16: the fine-level operator
+                           inside the cycle (smoother products and the defect)
+                           and the probing of the coarse operators and of every
+                           column of the fine diagonal blocks, as the exact FP64
+                           Jv or its FP32 / BF16-contraction variant (BF16: 3D
+                           P2-P4 lattices); the outer solve stays FP64 */
   int cycle;            /* DG_MG_V or DG_MG_FULL */
   int rescale;          /* 1: rescaled-inherited coarse operators (App. A, eq.
                            GalProjResc): the BR2 stabilisation part of each
@@ -337,6 +350,14 @@ dg_status dg_mg_level_apply(dg_context* ctx, int level, const double* x, double*
  * over a batch of normalised pairs (x_K, z_K / s_K) with Adam (0.9, 0.999,
  * 1e-8).  All arrays are device memory. */
 int64_t dg_mlp_nparams(dg_context* ctx);
+/* Network mode.  DG_MLP_DIRECT (default): z_K = s_K * output, targets
+ * T = z_K / s_K.  DG_MLP_CORRECT_BJ: the network corrects block Jacobi,
+ * z_K = D_K^{-1} r_K + s_K * output with targets T = (z_K - D_K^{-1} r_K) / s_K,
+ * so a network whose last layer is zero is block Jacobi exactly; features
+ * with targets and the apply then need a block setup (DG_ERR_STATE
+ * otherwise) and use its factors. */
+enum { DG_MLP_DIRECT = 0, DG_MLP_CORRECT_BJ = 1 };
+dg_status dg_mlp_set_mode(dg_context* ctx, int mode);
 /* Copy the parameter vector in (resets the Adam state). */
 dg_status dg_mlp_set_weights(dg_context* ctx, const float* theta, void* stream);
 dg_status dg_mlp_get_weights(dg_context* ctx, float* theta, void* stream);

@@ -13,16 +13,17 @@ STATUS_NAMES = {0: "DG_OK", 1: "DG_NOT_CONVERGED", -1: "DG_ERR_ARG", -2: "DG_ERR
                 -4: "DG_ERR_STATE", -5: "DG_ERR_SINGULAR_BLOCK", -6: "DG_ERR_NONFINITE"}
 DG_BASIS_PK, DG_BASIS_QK = 0, 1
 DG_FLUX_LF, DG_FLUX_ROE = 0, 1
-DG_JVP_EXACT, DG_JVP_FD, DG_JVP_EXACT_FP32, DG_JVP_STAB = 0, 1, 2, 3
+DG_JVP_EXACT, DG_JVP_FD, DG_JVP_EXACT_FP32, DG_JVP_STAB, DG_JVP_EXACT_BF16 = 0, 1, 2, 3, 4
 DG_FP64, DG_FP32, DG_BF16 = 0, 1, 2
 DG_PREC_NONE, DG_PREC_BJ, DG_PREC_MG, DG_PREC_MLP = 0, 1, 2, 3
 DG_MG_V, DG_MG_FULL = 0, 1
 DG_ORTH_CGS2, DG_ORTH_MGS = 0, 1
+DG_MLP_DIRECT, DG_MLP_CORRECT_BJ = 0, 1
 
 EXPORTED = ["dg_create", "dg_destroy", "dg_ndof", "dg_nbasis", "dg_nvar", "dg_nq", "dg_volume_points",
-            "dg_project", "dg_residual", "dg_residual_fp32", "dg_jvp", "dg_jvp_noalloc", "dg_jvp_noalloc_scratch_bytes",
+            "dg_project", "dg_residual", "dg_residual_fp32", "dg_residual_bf16", "dg_jvp", "dg_jvp_noalloc", "dg_jvp_noalloc_scratch_bytes",
             "dg_block_precond_setup", "dg_block_precond_apply",
-            "dg_fgmres_solve", "dg_rosenbrock_step", "dg_mg_setup", "dg_mg_update_fine", "dg_mg_apply", "dg_mg_level_apply", "dg_mlp_nparams",
+            "dg_fgmres_solve", "dg_rosenbrock_step", "dg_mg_setup", "dg_mg_update_fine", "dg_mg_apply", "dg_mg_level_apply", "dg_mlp_nparams", "dg_mlp_set_mode",
             "dg_mlp_set_weights", "dg_mlp_get_weights", "dg_mlp_features", "dg_mlp_forward", "dg_mlp_grad",
             "dg_mlp_train_step", "dg_mlp_apply", "dg_max_wave_speed",
             "dg_set_profiling", "dg_kernel_time", "dg_last_error", "dg_sync"]
@@ -90,6 +91,7 @@ def load():
         "dg_project": (i, [ctx, vp, vp, vp]),
         "dg_residual": (i, [ctx, vp, vp, vp]),
         "dg_residual_fp32": (i, [ctx, vp, vp, vp]),
+        "dg_residual_bf16": (i, [ctx, vp, vp, vp]),
         "dg_jvp": (i, [ctx, vp, vp, vp, d, i, vp, vp]),
         "dg_jvp_noalloc": (i, [ctx, vp, vp, d, vp, vp]),
         "dg_jvp_noalloc_scratch_bytes": (ctypes.c_size_t, []),
@@ -103,6 +105,7 @@ def load():
         "dg_mg_apply": (i, [ctx, vp, vp, vp]),
         "dg_mg_level_apply": (i, [ctx, i, vp, vp, vp]),
         "dg_mlp_nparams": (i64, [ctx]),
+        "dg_mlp_set_mode": (i, [ctx, i]),
         "dg_mlp_set_weights": (i, [ctx, vp, vp]),
         "dg_mlp_get_weights": (i, [ctx, vp, vp]),
         "dg_mlp_features": (i, [ctx, vp, vp, vp, vp, vp, vp, vp]),

@@ -13,7 +13,8 @@ from . import _lib as L
 
 _FLUX = {"lf": L.DG_FLUX_LF, "roe": L.DG_FLUX_ROE}
 _BASIS = {"P": L.DG_BASIS_PK, "Q": L.DG_BASIS_QK}
-_MODE = {"exact": L.DG_JVP_EXACT, "fd": L.DG_JVP_FD, "exact_fp32": L.DG_JVP_EXACT_FP32, "stab": L.DG_JVP_STAB}
+_MODE = {"exact": L.DG_JVP_EXACT, "fd": L.DG_JVP_FD, "exact_fp32": L.DG_JVP_EXACT_FP32, "stab": L.DG_JVP_STAB,
+         "exact_bf16": L.DG_JVP_EXACT_BF16}
 _STORAGE = {"fp64": L.DG_FP64, "fp32": L.DG_FP32, "bf16": L.DG_BF16}
 _PREC = {"none": L.DG_PREC_NONE, "bj": L.DG_PREC_BJ, "mg": L.DG_PREC_MG, "mlp": L.DG_PREC_MLP}
 _ORTH = {"cgs2": L.DG_ORTH_CGS2, "mgs": L.DG_ORTH_MGS}
@@ -105,6 +106,8 @@ class DG:
         out = self.empty() if out is None else self._vec(out, "out")
         if precision == "fp32":
             L.check(self.lib.dg_residual_fp32(self.ctx, _ptr(w), _ptr(out), _stream()), "dg_residual_fp32")
+        elif precision == "bf16":
+            L.check(self.lib.dg_residual_bf16(self.ctx, _ptr(w), _ptr(out), _stream()), "dg_residual_bf16")
         else:
             L.check(self.lib.dg_residual(self.ctx, _ptr(w), _ptr(out), _stream()), "dg_residual")
         return out
@@ -197,6 +200,11 @@ class DG:
 
     def mlp_nparams(self):
         return int(self.lib.dg_mlp_nparams(self.ctx))
+
+    def mlp_set_mode(self, mode):
+        """"direct" (z = s MLP(x)) or "correct_bj" (z = D^-1 r + s MLP(x))."""
+        m = {"direct": L.DG_MLP_DIRECT, "correct_bj": L.DG_MLP_CORRECT_BJ}[mode]
+        L.check(self.lib.dg_mlp_set_mode(self.ctx, m), "dg_mlp_set_mode")
 
     def mlp_set_weights(self, theta):
         theta = torch.as_tensor(theta, dtype=torch.float32).to(self.device).contiguous()

@@ -105,6 +105,33 @@ dg_status eval_residual_f32(dg_context* c, bool jvp, const double* w, const doub
   return DG_OK;
 }
 
+dg_status eval_residual_bf16(dg_context* c, bool jvp, const double* w, const double* v, double shift, double* out,
+                             hipStream_t s) {
+  {
+    ProfScope ps(c, jvp ? "grad_jvp_bf16" : "grad_res_bf16", s);
+    HIPCHK(dgk::launch_grad_mfma_bf16(c->cfg, jvp, w, v, c->d_Gf, c->mtf, c->mesh, s));
+  }
+  {
+    ProfScope ps(c, jvp ? "face_jvp_bf16" : "face_res_bf16", s);
+    HIPCHK(dgk::launch_face_mfma_bf16(c->cfg, jvp, w, v, c->d_Hf, c->mtf, c->mesh, c->ph, s));
+  }
+  {
+    ProfScope ps(c, jvp ? "vol_jvp_bf16" : "vol_res_bf16", s);
+    HIPCHK(dgk::launch_volume_mfma_bf16(c->cfg, jvp, w, v, c->d_Gf, c->d_Hf, out, shift, c->mtf, c->mesh, c->ph, s));
+  }
+  return DG_OK;
+}
+
+dg_status eval_op(dg_context* c, int prec, bool jvp, const double* w, const double* v, double shift, double* out,
+                  hipStream_t s) {
+  if (prec == DG_FP64) return eval_residual(c, jvp, w, v, shift, out, s);
+  if (prec == DG_FP32) return eval_residual_f32(c, jvp, w, v, shift, out, s);
+  if (prec != DG_BF16) return fail(DG_ERR_ARG, "unknown operator precision");
+  if (!has_prec(c, DG_BF16))
+    return fail(DG_ERR_ARG, "the BF16-contraction operator needs a 3D P2-P4 lattice configuration (MFMA kernels)");
+  return eval_residual_bf16(c, jvp, w, v, shift, out, s);
+}
+
 dg_status eval_stab(dg_context* c, bool f32, const double* w, const double* v, double* out, hipStream_t s) {
   if (!c->d_zero) {
     dg_status st;
@@ -157,6 +184,7 @@ dg_status jvp_impl(dg_context* c, const double* w, const double* r_w, const doub
                    double* out, hipStream_t s) {
   if (mode == DG_JVP_EXACT) return eval_residual(c, true, w, v, shift, out, s);
   if (mode == DG_JVP_EXACT_FP32) return eval_residual_f32(c, true, w, v, shift, out, s);
+  if (mode == DG_JVP_EXACT_BF16) return eval_op(c, DG_BF16, true, w, v, shift, out, s);
   if (mode == DG_JVP_STAB) {
     dg_status st;
     if ((st = eval_stab(c, false, w, v, out, s)) != DG_OK) return st;
@@ -550,11 +578,18 @@ dg_status dg_residual_fp32(dg_context* c, const double* w, double* r, void* stre
   return eval_residual_f32(c, false, w, nullptr, 0.0, r, (hipStream_t)stream);
 }
 
+dg_status dg_residual_bf16(dg_context* c, const double* w, double* r, void* stream) {
+  if (!c || !w || !r) return fail(DG_ERR_ARG, "null argument");
+  if (w == r) return fail(DG_ERR_ARG, "w and r may not alias");
+  return eval_op(c, DG_BF16, false, w, nullptr, 0.0, r, (hipStream_t)stream);
+}
+
 dg_status dg_jvp(dg_context* c, const double* w, const double* r_w, const double* v, double shift, int mode,
                  double* out, void* stream) {
   if (!c || !w || !v || !out) return fail(DG_ERR_ARG, "null argument");
   if (out == w || out == v || (r_w && out == r_w)) return fail(DG_ERR_ARG, "out may not alias w, v or r_w");
-  if (mode != DG_JVP_EXACT && mode != DG_JVP_FD && mode != DG_JVP_EXACT_FP32 && mode != DG_JVP_STAB)
+  if (mode != DG_JVP_EXACT && mode != DG_JVP_FD && mode != DG_JVP_EXACT_FP32 && mode != DG_JVP_STAB &&
+      mode != DG_JVP_EXACT_BF16)
     return fail(DG_ERR_ARG, "unknown jvp mode");
   return jvp_impl(c, w, r_w, v, shift, mode, out, (hipStream_t)stream);
 }
@@ -592,20 +627,17 @@ dg_status block_alloc(dg_context* c, int storage) {
 }
 
 dg_status block_probe_invert(dg_context* c, const double* w, double shift, int storage, int skip_modes,
-                             hipStream_t s) {
+                             int probe_prec, hipStream_t s) {
   const int m = c->nv * c->nb, ld = dgk::block_ld(m);
   dg_status st;
-  // reduced-precision factors are probed with the FP32 operator where it exists
-  const bool probe_f32 = storage != DG_FP64 && has_f32(c);
+  if (!has_prec(c, probe_prec)) return fail(DG_ERR_ARG, "no operator of the probing precision");
   {
     ProfScope ps(c, "block_probe", s);
     for (int col = 0; col < c->ncolor; ++col)
       for (int l = 0; l < m; ++l) {
         if (l % c->nb < skip_modes) continue;  // column already in d_D64
         HIPCHK(dgk::launch_probe_vector(c->d_t1, c->d_color, col, l, c->nb, c->nv, c->ne, s));
-        if ((st = probe_f32 ? eval_residual_f32(c, true, w, c->d_t1, shift, c->d_t2, s)
-                            : eval_residual(c, true, w, c->d_t1, shift, c->d_t2, s)) != DG_OK)
-          return st;
+        if ((st = eval_op(c, probe_prec, true, w, c->d_t1, shift, c->d_t2, s)) != DG_OK) return st;
         HIPCHK(dgk::launch_extract_column(c->d_t2, c->d_color, col, l, m, c->ne, shift, c->d_D64, s));
       }
   }
@@ -636,7 +668,7 @@ dg_status dg_block_precond_setup(dg_context* c, const double* w, double shift, i
   mg_invalidate(c->mg);
   dg_status st;
   if ((st = block_alloc(c, storage)) != DG_OK) return st;
-  return block_probe_invert(c, w, shift, storage, 0, (hipStream_t)stream);
+  return block_probe_invert(c, w, shift, storage, 0, default_probe_prec(c, storage), (hipStream_t)stream);
 }
 
 dg_status dg_block_precond_apply(dg_context* c, const double* r, double* z, void* stream) {

@@ -144,6 +144,13 @@ struct ProfScope {
 inline bool has_f32(const dg_context* c) {
   return (c->use_mfma && c->d_mtab_f && c->d_Hf && c->d_Gf) || (c->curved && c->d_curved_f && c->d_cwork_f);
 }
+// True when the operator of precision prec (DG_FP64, DG_FP32 or DG_BF16: BF16
+// contractions, the 3D P2-P4 lattice MFMA kernels only) exists.
+inline bool has_prec(const dg_context* c, int prec) {
+  if (prec == DG_FP64) return true;
+  if (prec == DG_FP32) return has_f32(c);
+  return prec == DG_BF16 && c->use_mfma && c->d_mtab_f && c->d_Hf && c->d_Gf;
+}
 
 // Residual (jvp = false) or exact Jv plus shift*v (jvp = true) on stream s.
 dg_status eval_residual(dg_context* c, bool jvp, const double* w, const double* v, double shift, double* out,
@@ -152,16 +159,26 @@ dg_status eval_residual(dg_context* c, bool jvp, const double* w, const double* 
 // outputs FP64); 3D P2-P4 configurations only.
 dg_status eval_residual_f32(dg_context* c, bool jvp, const double* w, const double* v, double shift, double* out,
                             hipStream_t s);
+// The residual / exact Jv of the operator of precision prec (DG_FP64, DG_FP32
+// or DG_BF16); DG_ERR_ARG when the context has no such operator.
+dg_status eval_op(dg_context* c, int prec, bool jvp, const double* w, const double* v, double shift, double* out,
+                  hipStream_t s);
 // out = STB(w) v: the BR2 stabilisation part of the Jacobian (the tangent of
 // the face lifting term eta {r} of the face viscous flux only; no shift),
 // FP64 or the FP32 operator.
 dg_status eval_stab(dg_context* c, bool f32, const double* w, const double* v, double* out, hipStream_t s);
 // Element-block Jacobi setup in two steps: storage for the blocks, then the
-// coloured probing of every column whose mode index is at least skip_modes
-// (the caller has written the others into d_D64) and the inversion.
+// coloured probing, with the operator of precision probe_prec, of every column
+// whose mode index is at least skip_modes (the caller has written the others
+// into d_D64) and the inversion.
 dg_status block_alloc(dg_context* c, int storage);
 dg_status block_probe_invert(dg_context* c, const double* w, double shift, int storage, int skip_modes,
-                             hipStream_t s);
+                             int probe_prec, hipStream_t s);
+// The probing precision of a plain block setup: FP64 for FP64 factors, the
+// FP32 operator (where it exists) for FP32 and BF16 factors.
+inline int default_probe_prec(const dg_context* c, int storage) {
+  return storage != DG_FP64 && has_f32(c) ? DG_FP32 : DG_FP64;
+}
 // dout[0] = ||x||_2 over the context's DOF vector length.
 dg_status norm2(dg_context* c, const double* x, double* dout, hipStream_t s);
 // out = shift*v + J(w) v, exact or finite difference.

@@ -101,6 +101,15 @@ hipError_t launch_face_mfma_f32(int cfg, bool jvp, const double* U, const double
 hipError_t launch_volume_mfma_f32(int cfg, bool jvp, const double* U, const double* V, const float* Gm,
                                   const float* H, double* out, double shift, const MTablesF& mt, const Mesh& m,
                                   const Phys& ph, hipStream_t s);
+// BF16 contractions with FP32 accumulation, otherwise as the FP32 variant
+// (FP32 tables and buffers, FP32 pointwise arithmetic)
+hipError_t launch_grad_mfma_bf16(int cfg, bool jvp, const double* U, const double* V, float* Gm, const MTablesF& mt,
+                                 const Mesh& m, hipStream_t s);
+hipError_t launch_face_mfma_bf16(int cfg, bool jvp, const double* U, const double* V, float* H, const MTablesF& mt,
+                                 const Mesh& m, const Phys& ph, hipStream_t s);
+hipError_t launch_volume_mfma_bf16(int cfg, bool jvp, const double* U, const double* V, const float* Gm,
+                                   const float* H, double* out, double shift, const MTablesF& mt, const Mesh& m,
+                                   const Phys& ph, hipStream_t s);
 // modal corrected gradients Gm[s][p][c][b][e] (s = value, tangent)
 hipError_t launch_grad_mfma(int cfg, bool jvp, const double* U, const double* V, double* Gm, const MTables& mt,
                             const Mesh& m, hipStream_t s);

@@ -48,6 +48,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 template <class R> struct MP;
 template <> struct MP<double> {
   using frag = f64x4;
+  static constexpr bool kBf16 = false;
   static DEV frag mma(double a, double b, frag c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
   static DEV int drow(int g, int r) { return g + 4 * r; }
   static DEV int bmode(int g, int ks) { return g + 4 * ks; }
@@ -55,11 +56,58 @@ template <> struct MP<double> {
 };
 template <> struct MP<float> {
   using frag = f32x4;
+  static constexpr bool kBf16 = false;
   static DEV frag mma(float a, float b, frag c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
   static DEV int drow(int g, int r) { return 4 * g + r; }
   static DEV int bmode(int g, int ks) { return 16 * (ks >> 2) + 4 * g + (ks & 3); }
   static constexpr int ksv(int nb) { return 4 * ((nb + 15) / 16); }
 };
+// BF16 contractions with FP32 accumulation (the kernels otherwise run as the
+// FP32 operator: FP32 tables, stages and pointwise arithmetic).  The BF16
+// 16x16x16 instruction takes four k values per lane, A[i][4g + j] and
+// B[4g + j][col] in slot j of lane i + 16g (resp. col + 16g), and returns
+// D[4g + r][col] in register r: the result layout of the FP32 16x16x4
+// instruction.  Four consecutive FP32 k-steps, whose lane group g holds one k
+// value of A and the same k value of B, therefore make one BF16 MFMA with
+// k-step j in slot j: the products pair up lane by lane whatever rows the
+// k-steps stand for, so every FP32 operand table and fragment order serves
+// unchanged.
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+struct MPB : MP<float> {
+  static constexpr bool kBf16 = true;
+};
+
+// The mean mode of a state (b = 0, the element average: e.g. about 33 for the
+// total energy of the low-Mach workloads, against fluctuations of order 1e-2 of
+// it) is kept out of the BF16 products: its contribution to the value traces,
+// the value fields at the volume points and the corrected gradients is added
+// in FP32 (A(row, mode 0) * U_0), and the BF16 chains see a zero there.  BF16
+// rounding of the mean alone would make a relative residual error of 3e-2; the
+// remaining modes give 1.6e-3 (P3).
+//
+// acc + sum_{ks < NK} A(ks) B(ks) over the k-steps of one contraction chain:
+// one MFMA per k-step in FP64 / FP32, one BF16 MFMA per group of four k-steps
+// (operands rounded to BF16 to nearest even, the last group zero-padded).
+template <class MM, int NK, class FA, class FB>
+DEV typename MM::frag chain(const FA& a, const FB& b, typename MM::frag d) {
+  if constexpr (MM::kBf16) {
+#pragma unroll
+    for (int kb = 0; kb < (NK + 3) / 4; ++kb) {
+      bf16x4 av, bv;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int ks = 4 * kb + j;
+        av[j] = (__bf16)(ks < NK ? (float)a(ks) : 0.0f);
+        bv[j] = (__bf16)(ks < NK ? (float)b(ks) : 0.0f);
+      }
+      d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, d, 0, 0, 0);
+    }
+  } else {
+#pragma unroll
+    for (int ks = 0; ks < NK; ++ks) d = MM::mma(a(ks), b(ks), d);
+  }
+  return d;
+}
 
 // Tile processed by this workgroup.  Workgroups are dispatched round-robin
 // over the 8 XCDs (each with its own L2); giving every XCD a contiguous range
@@ -78,10 +126,10 @@ DEV int64_t xcd_tile(int64_t bid, int64_t nblk) {
 // one wave per (tile of 16 elements, direction p, value/tangent s), all
 // variables; B fragments straight from global memory (no LDS, no barriers).
 // Output layout Gm[s][p][c][b][e].
-template <class R, int NB>
+template <class R, int NB, class MM>
 __global__ __launch_bounds__(64) void k_grad_mfma(const double* __restrict__ U, const double* __restrict__ V,
                                                   R* __restrict__ Gm, const R* __restrict__ lA, Mesh m) {
-  using F = typename MP<R>::frag;
+  using F = typename MM::frag;
   constexpr int DIM = 3, NV = 5;
   constexpr int KSB = (NB + 3) / 4, MB = (NB + 15) / 16;
   const int lane = threadIdx.x;
@@ -97,25 +145,38 @@ __global__ __launch_bounds__(64) void k_grad_mfma(const double* __restrict__ U, 
   const int64_t es[3] = {ec, m.nbr[(2 * p + 1) * ne + ec], m.nbr[(2 * p) * ne + ec]};  // element, +p, -p
 #pragma unroll 1
   for (int c = 0; c < NV; ++c) {
-    R bf[3 * KSB];
+    R bf[3 * KSB], m0[3];
 #pragma unroll
     for (int ks3 = 0; ks3 < 3 * KSB; ++ks3) {
       const int src = ks3 / KSB, bp = g + 4 * (ks3 % KSB);
       const R x = (R)X[(size_t)(c * NB + (bp < NB ? bp : NB - 1)) * ne + es[src]];
       bf[ks3] = (ev && bp < NB) ? x : R(0);
     }
+    if constexpr (MM::kBf16) {  // mean modes in FP32, out of the BF16 chain
+#pragma unroll
+      for (int src = 0; src < 3; ++src) {
+        m0[src] = ev ? (R)X[(size_t)(c * NB) * ne + es[src]] : R(0);
+        if (g == 0) bf[src * KSB] = R(0);
+      }
+    }
     // FP64 P4: one mode block at a time (all three unrolled hold their A
     // operands in flight and leave one wave per SIMD)
     constexpr int kMbUnroll = (sizeof(R) == 8 && MB > 2) ? 1 : MB;
 #pragma unroll kMbUnroll
     for (int mb = 0; mb < MB; ++mb) {
-      F d = {0, 0, 0, 0};
+      const R* __restrict__ la = lA + ((size_t)p * MB + mb) * 3 * KSB * 64 + lane;
+      F d = chain<MM, 3 * KSB>([&](int ks3) { return la[ks3 * 64]; }, [&](int ks3) { return bf[ks3]; },
+                               F{0, 0, 0, 0});
+      if constexpr (MM::kBf16) {
+        const R* __restrict__ l0 = lA + ((size_t)p * MB + mb) * 3 * KSB * 64;
 #pragma unroll
-      for (int ks3 = 0; ks3 < 3 * KSB; ++ks3)
-        d = MP<R>::mma(lA[(((size_t)p * MB + mb) * 3 * KSB + ks3) * 64 + lane], bf[ks3], d);
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int src = 0; src < 3; ++src) d[r] += l0[src * KSB * 64 + MM::drow(g, r)] * m0[src];
+      }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int b = 16 * mb + MP<R>::drow(g, r);
+        const int b = 16 * mb + MM::drow(g, r);
         if (ev && b < NB) Gm[((size_t)((s * DIM + p) * NV + c) * NB + b) * ne + e] = d[r];
       }
     }
@@ -125,17 +186,17 @@ __global__ __launch_bounds__(64) void k_grad_mfma(const double* __restrict__ U, 
 // ------------------------------------------------------------------ volume
 // FP64 P4 runs at one wave per SIMD (no register spills; measured faster than
 // occupancy 2 with spills)
-template <class R, int NB, int NQ1, int KL, bool JVP>
+template <class R, int NB, int NQ1, int KL, bool JVP, class MM>
 __global__ __launch_bounds__(256, (NB > 20 && sizeof(R) == 8) ? 1 : 2) void k_volume_mfma(const double* __restrict__ U, const double* __restrict__ V,
                                                      const R* __restrict__ Gm, const R* __restrict__ H,
                                                      double* __restrict__ out, double shift, MTablesT<R> mt,
                                                      Mesh m, Phys ph) {
   using T = typename Scalar<JVP, R>::type;
-  using F = typename MP<R>::frag;
+  using F = typename MM::frag;
   constexpr int DIM = 3, NV = 5;
   constexpr int NQ = ipow(NQ1, 3), NFQ = ipow(NQ1, 2);
   constexpr int KSB = (NB + 3) / 4, MB = (NB + 15) / 16, RBQ = (NQ + 15) / 16;
-  constexpr int KSV = MP<R>::ksv(NB);         // fragment k-steps of the modal fields
+  constexpr int KSV = MM::ksv(NB);            // fragment k-steps of the modal fields
   constexpr int KSP = DIM * 4, KSF = (NFQ + 3) / 4;
   constexpr int NS = JVP ? 2 : 1;
   constexpr int NFC = (1 + DIM) * NV;        // (field, variable) pairs per value/tangent
@@ -160,6 +221,7 @@ __global__ __launch_bounds__(256, (NB > 20 && sizeof(R) == 8) ? 1 : 2) void k_vo
   // ---- 1. modal fields in B-fragment order: Bf[i][ks] = X[b = bmode(g, ks)][e],
   // X = U (or V) for f = 0 and the corrected gradient G_f for f = 1..3.
   R Bf[NCBW][KSV];
+  R m0[NCBW];  // BF16: the mean mode of the value fields, applied in FP32
 #pragma unroll
   for (int i = 0; i < NCBW; ++i) {
     const int s = i / (NFC / 4);
@@ -167,17 +229,22 @@ __global__ __launch_bounds__(256, (NB > 20 && sizeof(R) == 8) ? 1 : 2) void k_vo
     const int f = fc / NV, c = fc % NV;
     const double* __restrict__ X = ((s == 0) ? U : V) + (size_t)c * NB * ne;
     const R* __restrict__ Gf = Gm + (size_t)((s * DIM + (f > 0 ? f - 1 : 0)) * NV + c) * NB * ne;
+    m0[i] = R(0);
     if (f == 0) {
 #pragma unroll
       for (int ks = 0; ks < KSV; ++ks) {
-        const int b = MP<R>::bmode(g, ks);
+        const int b = MM::bmode(g, ks);
         const R x = (R)X[(size_t)(b < NB ? b : NB - 1) * ne + ec];
         Bf[i][ks] = (ev && b < NB) ? x : R(0);
+      }
+      if constexpr (MM::kBf16) {
+        m0[i] = ev ? (R)X[ec] : R(0);
+        if (g == 0) Bf[i][0] = R(0);  // mode bmode(0, 0) = 0
       }
     } else {
 #pragma unroll
       for (int ks = 0; ks < KSV; ++ks) {
-        const int b = MP<R>::bmode(g, ks);
+        const int b = MM::bmode(g, ks);
         const R x = Gf[(size_t)(b < NB ? b : NB - 1) * ne + ec];
         Bf[i][ks] = (ev && b < NB) ? x : R(0);
       }
@@ -201,11 +268,17 @@ __global__ __launch_bounds__(256, (NB > 20 && sizeof(R) == 8) ? 1 : 2) void k_vo
 #pragma unroll
       for (int i = s * (NFC / 4); i < (s + 1) * (NFC / 4); ++i) {
         const int fc = wave + 4 * (i % (NFC / 4));
-        F d = {0, 0, 0, 0};
+        const R* __restrict__ va = mt.vA + (size_t)rb * KSV * 64 + lane;
+        F d = chain<MM, KSV>([&](int ks) { return va[ks * 64]; }, [&](int ks) { return Bf[i][ks]; },
+                             F{0, 0, 0, 0});
+        if constexpr (MM::kBf16) {
+          if (fc < NV) {  // value field: its mean mode (k-step 0, lane group 0 of the table)
 #pragma unroll
-        for (int ks = 0; ks < KSV; ++ks) d = MP<R>::mma(mt.vA[((size_t)rb * KSV + ks) * 64 + lane], Bf[i][ks], d);
+            for (int r = 0; r < 4; ++r) d[r] += mt.vA[(size_t)rb * KSV * 64 + MM::drow(g, r)] * m0[i];
+          }
+        }
 #pragma unroll
-        for (int r = 0; r < 4; ++r) stage[fc][MP<R>::drow(g, r)][col] = d[r];
+        for (int r = 0; r < 4; ++r) stage[fc][MM::drow(g, r)][col] = d[r];
       }
       __syncthreads();
 #pragma unroll
@@ -254,11 +327,12 @@ __global__ __launch_bounds__(256, (NB > 20 && sizeof(R) == 8) ? 1 : 2) void k_vo
       const int pb = wave + 4 * i;
       if (pb < NPB) {
         const int c = pb / MB, mb = pb % MB;
-#pragma unroll
-        for (int ks = 0; ks < KSP; ++ks) {
-          const int k = g + 4 * ks;
-          acc[i] = MP<R>::mma(ptab[(mb * KSP + ks) * 64 + lane], stage[(k >> 4) * NV + c][k & 15][col], acc[i]);
-        }
+        acc[i] = chain<MM, KSP>([&](int ks) { return ptab[(mb * KSP + ks) * 64 + lane]; },
+                                [&](int ks) {
+                                  const int k = g + 4 * ks;
+                                  return stage[(k >> 4) * NV + c][k & 15][col];
+                                },
+                                acc[i]);
       }
     }
     __syncthreads();
@@ -278,17 +352,20 @@ __global__ __launch_bounds__(256, (NB > 20 && sizeof(R) == 8) ? 1 : 2) void k_vo
       const int pb = wave + 4 * i;
       if (pb < NPB) {
         const int c = pb / MB, mb = pb % MB;
-#pragma unroll
-        for (int side = 0; side < 2; ++side) {
-          const int64_t es = side ? ec : em;
-#pragma unroll
-          for (int ks = 0; ks < KSF; ++ks) {
-            const int fq = g + 4 * ks;
-            const R h = H[((size_t)(p * NV + c) * NFQ + (fq < NFQ ? fq : NFQ - 1)) * ne + es];
-            const R hb = (ev && fq < NFQ) ? h : R(0);
-            acc[i] = MP<R>::mma(ftab[((side * MB + mb) * KSF + ks) * 64 + lane], hb, acc[i]);
-          }
-        }
+        // k-steps (side, face point) with side 0 (the -p face, read from the
+        // -p neighbour's record) first
+        acc[i] = chain<MM, 2 * KSF>(
+            [&](int k2) {
+              const int side = k2 / KSF, ks = k2 % KSF;
+              return ftab[((side * MB + mb) * KSF + ks) * 64 + lane];
+            },
+            [&](int k2) {
+              const int side = k2 / KSF, ks = k2 % KSF;
+              const int fq = g + 4 * ks;
+              const R h = H[((size_t)(p * NV + c) * NFQ + (fq < NFQ ? fq : NFQ - 1)) * ne + (side ? ec : em)];
+              return (ev && fq < NFQ) ? h : R(0);
+            },
+            acc[i]);
       }
     }
     __syncthreads();
@@ -301,7 +378,7 @@ __global__ __launch_bounds__(256, (NB > 20 && sizeof(R) == 8) ? 1 : 2) void k_vo
       if (ev) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int b = 16 * mb + MP<R>::drow(g, r);
+          const int b = 16 * mb + MM::drow(g, r);
           if (b < NB) {
             const size_t idx = (size_t)(c * NB + b) * ne + e;
             double a = (double)acc[i][r];
@@ -327,11 +404,11 @@ struct FaceTab {
   static constexpr int occupancy = (lds && sizeof(R) == 8) ? 1 : 2;
 };
 
-template <class R, int NB, int NQ1, bool JVP, int P>
+template <class R, int NB, int NQ1, bool JVP, int P, class MM>
 DEV void face_mfma_body(const double* __restrict__ U, const double* __restrict__ V, R* __restrict__ H,
                         const MTablesT<R>& mt, const Mesh& m, const Phys& ph, R (*stage)[16][16], R* ttab) {
   using T = typename Scalar<JVP, R>::type;
-  using F = typename MP<R>::frag;
+  using F = typename MM::frag;
   constexpr int DIM = 3, NV = 5;
   constexpr int NFQ = ipow(NQ1, 2);
   constexpr int KSB = (NB + 3) / 4, RBF = (NFQ + 15) / 16;
@@ -352,6 +429,8 @@ DEV void face_mfma_body(const double* __restrict__ U, const double* __restrict__
 
   // B fragments of (value/tangent s, variable c): k-steps 0..KSB-1 from the
   // owner, KSB..2KSB-1 from the +P neighbour
+  // (BF16: entries 2KSB, 2KSB + 1 hold the mean modes of both sides, applied
+  // in FP32, and the chains see zeros at mode 0)
   auto load_b = [&](int s, int c, R* bf) {
     const double* __restrict__ X = (s == 0) ? U : V;
 #pragma unroll
@@ -361,23 +440,45 @@ DEV void face_mfma_body(const double* __restrict__ U, const double* __restrict__
       const R x = (R)X[(size_t)(c * NB + (b < NB ? b : NB - 1)) * ne + es];
       bf[ks2] = (ev && b < NB) ? x : R(0);
     }
+    if constexpr (MM::kBf16) {
+      bf[2 * KSB] = ev ? (R)X[(size_t)(c * NB) * ne + ec] : R(0);
+      bf[2 * KSB + 1] = ev ? (R)X[(size_t)(c * NB) * ne + er] : R(0);
+      if (g == 0) bf[0] = bf[KSB] = R(0);
+    }
   };
   // trace channel ch of one column block into the stage; the trace table of
   // the current point block is read from LDS when the kernel stages it there
   constexpr bool kTabLds = FaceTab<R, NB>::lds;
   auto put = [&](int ch, int c, const F& d) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) stage[ch * NV + c][MP<R>::drow(g, r)][col] = d[r];
+    for (int r = 0; r < 4; ++r) stage[ch * NV + c][MM::drow(g, r)][col] = d[r];
   };
+  // channel 0 (uL) contracts the owner's k-steps, channel 1 (uR) the
+  // neighbour's, the others both
   auto trace_d = [&](int rbf, int ch, const R* bf) {
-    const int k0 = (ch == 1) ? KSB : 0;
-    const int k1 = (ch == 0) ? KSB : 2 * KSB;
-    F d = {0, 0, 0, 0};
+    auto a_of = [&](int ks2) {
+      return kTabLds ? ttab[(ch * 2 * KSB + ks2) * 64 + lane]
+                     : mt.tA[((((size_t)P * RBF + rbf) * NCH + ch) * 2 * KSB + ks2) * 64 + lane];
+    };
+    const F z = {0, 0, 0, 0};
+    F d;
+    if (ch == 0)
+      d = chain<MM, KSB>(a_of, [&](int k) { return bf[k]; }, z);
+    else if (ch == 1)
+      d = chain<MM, KSB>([&](int k) { return a_of(KSB + k); }, [&](int k) { return bf[KSB + k]; }, z);
+    else
+      d = chain<MM, 2 * KSB>(a_of, [&](int k) { return bf[k]; }, z);
+    if constexpr (MM::kBf16) {  // mean modes of both sides (k-steps 0 and KSB, lane group 0)
+      auto a_row = [&](int ks2, int row) {
+        return kTabLds ? ttab[(ch * 2 * KSB + ks2) * 64 + row]
+                       : mt.tA[((((size_t)P * RBF + rbf) * NCH + ch) * 2 * KSB + ks2) * 64 + row];
+      };
 #pragma unroll
-    for (int ks2 = k0; ks2 < k1; ++ks2) {
-      const R a = kTabLds ? ttab[(ch * 2 * KSB + ks2) * 64 + lane]
-                          : mt.tA[((((size_t)P * RBF + rbf) * NCH + ch) * 2 * KSB + ks2) * 64 + lane];
-      d = MP<R>::mma(a, bf[ks2], d);
+      for (int r = 0; r < 4; ++r) {
+        const int row = MM::drow(g, r);
+        if (ch != 1) d[r] += a_row(0, row) * bf[2 * KSB];
+        if (ch != 0) d[r] += a_row(KSB, row) * bf[2 * KSB + 1];
+      }
     }
     return d;
   };
@@ -403,10 +504,8 @@ DEV void face_mfma_body(const double* __restrict__ U, const double* __restrict__
     }
 #pragma unroll
     for (int jt = 0; jt < 3; ++jt) {
-      F d = {0, 0, 0, 0};
-#pragma unroll
-      for (int ks = 0; ks < KT; ++ks)
-        d = MP<R>::mma(mt.dA[((P * 3 + jt) * 4 + ks) * 64 + lane], jt < 2 ? avg[ks] : jmp[ks], d);
+      const F d = chain<MM, KT>([&](int ks) { return mt.dA[((P * 3 + jt) * 4 + ks) * 64 + lane]; },
+                                [&](int ks) { return jt < 2 ? avg[ks] : jmp[ks]; }, F{0, 0, 0, 0});
       const int ch = jt == 2 ? 5 : 2 + ((jt == 0) ? (P == 0 ? 1 : 0) : (P == 2 ? 1 : 2));
       put(ch, c, d);
     }
@@ -435,7 +534,8 @@ DEV void face_mfma_body(const double* __restrict__ U, const double* __restrict__
   constexpr bool kBalanced = RBF <= 2;
   constexpr int NCB = NS * NV;               // (value/tangent, variable) column blocks
   constexpr int NCBW = kBalanced ? NS : (NCB + 3) / 4;
-  R Bf[NCBW][2 * KSB];
+  constexpr int NBF = 2 * KSB + (MM::kBf16 ? 2 : 0);  // fragment entries (BF16: + the two mean modes)
+  R Bf[NCBW][NBF];
 #pragma unroll
   for (int i = 0; i < NCBW; ++i) {
     const int cb = kBalanced ? i * NV + wave : wave + 4 * i;
@@ -443,7 +543,7 @@ DEV void face_mfma_body(const double* __restrict__ U, const double* __restrict__
       load_b(cb / NV, cb % NV, Bf[i]);
     } else {
 #pragma unroll
-      for (int ks2 = 0; ks2 < 2 * KSB; ++ks2) Bf[i][ks2] = R(0);
+      for (int ks2 = 0; ks2 < NBF; ++ks2) Bf[i][ks2] = R(0);
     }
   }
 
@@ -459,7 +559,7 @@ DEV void face_mfma_body(const double* __restrict__ U, const double* __restrict__
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       if constexpr (kBalanced) {
-        R Bs[2 * KSB];
+        R Bs[NBF];
         if constexpr (kPts) {
           if (wave != 0) load_b(s, wave == 1 ? 3 : 4, Bs);
           if (wave == 3) {
@@ -532,15 +632,15 @@ DEV void face_mfma_body(const double* __restrict__ U, const double* __restrict__
   }
 }
 
-template <class R, int NB, int NQ1, bool JVP>
+template <class R, int NB, int NQ1, bool JVP, class MM>
 __global__ __launch_bounds__(256, (FaceTab<R, NB>::occupancy)) void k_face_mfma(
     const double* __restrict__ U, const double* __restrict__ V, R* __restrict__ H, MTablesT<R> mt, Mesh m, Phys ph) {
   __shared__ R stage[6 * 5][16][16];
   __shared__ R ttab[FaceTab<R, NB>::lds ? 6 * 2 * ((NB + 3) / 4) * 64 : 1];
   switch (blockIdx.y) {
-    case 0: face_mfma_body<R, NB, NQ1, JVP, 0>(U, V, H, mt, m, ph, stage, ttab); break;
-    case 1: face_mfma_body<R, NB, NQ1, JVP, 1>(U, V, H, mt, m, ph, stage, ttab); break;
-    default: face_mfma_body<R, NB, NQ1, JVP, 2>(U, V, H, mt, m, ph, stage, ttab); break;
+    case 0: face_mfma_body<R, NB, NQ1, JVP, 0, MM>(U, V, H, mt, m, ph, stage, ttab); break;
+    case 1: face_mfma_body<R, NB, NQ1, JVP, 1, MM>(U, V, H, mt, m, ph, stage, ttab); break;
+    default: face_mfma_body<R, NB, NQ1, JVP, 2, MM>(U, V, H, mt, m, ph, stage, ttab); break;
   }
 }
 
@@ -560,16 +660,16 @@ bool has_mfma(int cfg) {
   return false;
 }
 
-template <class R>
+template <class R, class MM>
 hipError_t face_mfma_dispatch(int cfg, bool jvp, const double* U, const double* V, R* H, const MTablesT<R>& mt,
                               const Mesh& m, const Phys& ph, hipStream_t s) {
 #define X(id, nb_, nq_, kl_)                                                         \
   case id: {                                                                         \
     dim3 grid((unsigned)((m.ne + 15) / 16), 3);                                      \
     if (jvp)                                                                         \
-      k_face_mfma<R, nb_, nq_, true><<<grid, 256, 0, s>>>(U, V, H, mt, m, ph);       \
+      k_face_mfma<R, nb_, nq_, true, MM><<<grid, 256, 0, s>>>(U, V, H, mt, m, ph);       \
     else                                                                             \
-      k_face_mfma<R, nb_, nq_, false><<<grid, 256, 0, s>>>(U, V, H, mt, m, ph);      \
+      k_face_mfma<R, nb_, nq_, false, MM><<<grid, 256, 0, s>>>(U, V, H, mt, m, ph);      \
     return hipGetLastError();                                                        \
   }
   switch (cfg) { DG_MFMA_CONFIGS(X) }
@@ -577,7 +677,7 @@ hipError_t face_mfma_dispatch(int cfg, bool jvp, const double* U, const double* 
   return hipErrorInvalidValue;
 }
 
-template <class R>
+template <class R, class MM>
 hipError_t volume_mfma_dispatch(int cfg, bool jvp, const double* U, const double* V, const R* Gm, const R* H,
                                 double* out, double shift, const MTablesT<R>& mt, const Mesh& m, const Phys& ph,
                                 hipStream_t s) {
@@ -586,9 +686,9 @@ hipError_t volume_mfma_dispatch(int cfg, bool jvp, const double* U, const double
     if (mt.kl != kl_) return hipErrorInvalidValue;                                                       \
     dim3 grid((unsigned)((m.ne + 15) / 16));                                                             \
     if (jvp)                                                                                             \
-      k_volume_mfma<R, nb_, nq_, kl_, true><<<grid, 256, 0, s>>>(U, V, Gm, H, out, shift, mt, m, ph);    \
+      k_volume_mfma<R, nb_, nq_, kl_, true, MM><<<grid, 256, 0, s>>>(U, V, Gm, H, out, shift, mt, m, ph);    \
     else                                                                                                 \
-      k_volume_mfma<R, nb_, nq_, kl_, false><<<grid, 256, 0, s>>>(U, V, Gm, H, out, shift, mt, m, ph);   \
+      k_volume_mfma<R, nb_, nq_, kl_, false, MM><<<grid, 256, 0, s>>>(U, V, Gm, H, out, shift, mt, m, ph);   \
     return hipGetLastError();                                                                            \
   }
   switch (cfg) { DG_MFMA_CONFIGS(X) }
@@ -596,13 +696,13 @@ hipError_t volume_mfma_dispatch(int cfg, bool jvp, const double* U, const double
   return hipErrorInvalidValue;
 }
 
-template <class R>
+template <class R, class MM>
 hipError_t grad_mfma_dispatch(int cfg, bool jvp, const double* U, const double* V, R* Gm, const MTablesT<R>& mt,
                               const Mesh& m, hipStream_t s) {
 #define X(id, nb_, nq_, kl_)                                                                \
   case id: {                                                                                \
     dim3 grid((unsigned)((m.ne + 15) / 16), 3, jvp ? 2 : 1);                                \
-    k_grad_mfma<R, nb_><<<grid, 64, 0, s>>>(U, V, Gm, mt.lA, m);                            \
+    k_grad_mfma<R, nb_, MM><<<grid, 64, 0, s>>>(U, V, Gm, mt.lA, m);                            \
     return hipGetLastError();                                                               \
   }
   switch (cfg) { DG_MFMA_CONFIGS(X) }
@@ -612,34 +712,51 @@ hipError_t grad_mfma_dispatch(int cfg, bool jvp, const double* U, const double* 
 
 hipError_t launch_face_mfma(int cfg, bool jvp, const double* U, const double* V, double* H, const MTables& mt,
                             const Mesh& m, const Phys& ph, hipStream_t s) {
-  return face_mfma_dispatch<double>(cfg, jvp, U, V, H, mt, m, ph, s);
+  return face_mfma_dispatch<double, MP<double>>(cfg, jvp, U, V, H, mt, m, ph, s);
 }
 
 hipError_t launch_volume_mfma(int cfg, bool jvp, const double* U, const double* V, const double* Gm, const double* H,
                               double* out, double shift, const MTables& mt, const Mesh& m, const Phys& ph,
                               hipStream_t s) {
-  return volume_mfma_dispatch<double>(cfg, jvp, U, V, Gm, H, out, shift, mt, m, ph, s);
+  return volume_mfma_dispatch<double, MP<double>>(cfg, jvp, U, V, Gm, H, out, shift, mt, m, ph, s);
 }
 
 hipError_t launch_grad_mfma(int cfg, bool jvp, const double* U, const double* V, double* Gm, const MTables& mt,
                             const Mesh& m, hipStream_t s) {
-  return grad_mfma_dispatch<double>(cfg, jvp, U, V, Gm, mt, m, s);
+  return grad_mfma_dispatch<double, MP<double>>(cfg, jvp, U, V, Gm, mt, m, s);
 }
 
 hipError_t launch_grad_mfma_f32(int cfg, bool jvp, const double* U, const double* V, float* Gm, const MTablesF& mt,
                                 const Mesh& m, hipStream_t s) {
-  return grad_mfma_dispatch<float>(cfg, jvp, U, V, Gm, mt, m, s);
+  return grad_mfma_dispatch<float, MP<float>>(cfg, jvp, U, V, Gm, mt, m, s);
 }
 
 hipError_t launch_face_mfma_f32(int cfg, bool jvp, const double* U, const double* V, float* H, const MTablesF& mt,
                                 const Mesh& m, const Phys& ph, hipStream_t s) {
-  return face_mfma_dispatch<float>(cfg, jvp, U, V, H, mt, m, ph, s);
+  return face_mfma_dispatch<float, MP<float>>(cfg, jvp, U, V, H, mt, m, ph, s);
 }
 
 hipError_t launch_volume_mfma_f32(int cfg, bool jvp, const double* U, const double* V, const float* Gm,
                                   const float* H, double* out, double shift, const MTablesF& mt, const Mesh& m,
                                   const Phys& ph, hipStream_t s) {
-  return volume_mfma_dispatch<float>(cfg, jvp, U, V, Gm, H, out, shift, mt, m, ph, s);
+  return volume_mfma_dispatch<float, MP<float>>(cfg, jvp, U, V, Gm, H, out, shift, mt, m, ph, s);
+}
+
+// BF16 contractions (FP32 tables, buffers and pointwise arithmetic)
+hipError_t launch_grad_mfma_bf16(int cfg, bool jvp, const double* U, const double* V, float* Gm, const MTablesF& mt,
+                                 const Mesh& m, hipStream_t s) {
+  return grad_mfma_dispatch<float, MPB>(cfg, jvp, U, V, Gm, mt, m, s);
+}
+
+hipError_t launch_face_mfma_bf16(int cfg, bool jvp, const double* U, const double* V, float* H, const MTablesF& mt,
+                                 const Mesh& m, const Phys& ph, hipStream_t s) {
+  return face_mfma_dispatch<float, MPB>(cfg, jvp, U, V, H, mt, m, ph, s);
+}
+
+hipError_t launch_volume_mfma_bf16(int cfg, bool jvp, const double* U, const double* V, const float* Gm,
+                                   const float* H, double* out, double shift, const MTablesF& mt, const Mesh& m,
+                                   const Phys& ph, hipStream_t s) {
+  return volume_mfma_dispatch<float, MPB>(cfg, jvp, U, V, Gm, H, out, shift, mt, m, ph, s);
 }
 
 }  // namespace dgk

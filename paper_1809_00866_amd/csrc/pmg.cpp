@@ -50,7 +50,7 @@ struct MgLevel {
 
 struct MgState {
   int nlev = 0, nslot = 0, storage = DG_FP64;
-  bool fine_f32 = false;  // FP32 fine-level operator inside the cycle
+  int fine_prec = DG_FP64;  // precision of the fine-level operator inside the cycle (DG_FP64/FP32/BF16)
   bool full = false;      // Alg. fullvcic instead of Alg. vcic
   bool rescale = false;   // rescaled-inherited coarse operators (App. A)
   bool coarse_ilu = false;  // block ILU(0) preconditions the coarsest smoother
@@ -112,8 +112,7 @@ int binom(int n, int k) {
 // exact: the FP64 level operator even where the cycle applies an FP32 copy
 dg_status level_G(dg_context* c, MgState* M, int l, const double* x, double* y, hipStream_t s, bool exact = false) {
   if (l == 0)
-    return M->fine_f32 && !exact ? eval_residual_f32(c, true, M->w, x, M->shift, y, s)
-                                 : eval_residual(c, true, M->w, x, M->shift, y, s);
+    return eval_op(c, exact ? DG_FP64 : M->fine_prec, true, M->w, x, M->shift, y, s);
   const MgLevel& L = M->lev[l];
   if (L.B32 && !exact)
     HIPCHK(dgk::launch_bsr_apply_f32(L.bs, L.B32, c->mesh.nbr, 2 * c->dim, L.m, c->ne, x, y, s));
@@ -369,8 +368,8 @@ dg_status dg_mg_setup(dg_context* c, const double* w, double shift, const dg_mg_
   if (o->smooth_iters[o->n_levels - 1] < 1) return fail(DG_ERR_ARG, "the coarsest level needs >= 1 iteration");
   if (o->storage != DG_FP64 && o->storage != DG_FP32 && o->storage != DG_BF16)
     return fail(DG_ERR_ARG, "storage must be DG_FP64, DG_FP32 or DG_BF16");
-  if (o->fine_precision != DG_FP64 && o->fine_precision != DG_FP32)
-    return fail(DG_ERR_ARG, "fine_precision must be DG_FP64 or DG_FP32");
+  if (o->fine_precision != DG_FP64 && o->fine_precision != DG_FP32 && o->fine_precision != DG_BF16)
+    return fail(DG_ERR_ARG, "fine_precision must be DG_FP64, DG_FP32 or DG_BF16");
   if (o->cycle != DG_MG_V && o->cycle != DG_MG_FULL) return fail(DG_ERR_ARG, "cycle must be DG_MG_V or DG_MG_FULL");
   if (o->rescale != 0 && o->rescale != 1) return fail(DG_ERR_ARG, "rescale must be 0 or 1");
   if (o->coarse_ilu != 0 && o->coarse_ilu != 1) return fail(DG_ERR_ARG, "coarse_ilu must be 0 or 1");
@@ -378,6 +377,8 @@ dg_status dg_mg_setup(dg_context* c, const double* w, double shift, const dg_mg_
     return fail(DG_ERR_ARG, "block ILU(0) needs coarsest blocks of at most 64 rows");
   if (o->fine_precision == DG_FP32 && !has_f32(c))
     return fail(DG_ERR_ARG, "the FP32 fine operator needs a curved mesh or a 3D P2-P4 lattice configuration");
+  if (o->fine_precision == DG_BF16 && !has_prec(c, DG_BF16))
+    return fail(DG_ERR_ARG, "the BF16-contraction fine operator needs a 3D P2-P4 lattice configuration");
   hipStream_t s = (hipStream_t)stream;
   const int64_t ne = c->ne;
   const int dim = c->dim, nv = c->nv, nf = 2 * dim;
@@ -405,7 +406,7 @@ dg_status dg_mg_setup(dg_context* c, const double* w, double shift, const dg_mg_
   M->storage = o->storage;
   M->shift = shift;
   M->use_graph = o->use_graph != 0;
-  M->fine_f32 = o->fine_precision == DG_FP32;
+  M->fine_prec = o->fine_precision;
   M->full = o->cycle == DG_MG_FULL;
   M->rescale = o->rescale != 0;
   M->coarse_ilu = o->coarse_ilu != 0;
@@ -477,20 +478,19 @@ dg_status dg_mg_setup(dg_context* c, const double* w, double shift, const dg_mg_
       for (int l = 0; l < C.m; ++l) {
         const int lf = (l / C.nb) * c->nb + l % C.nb;
         HIPCHK(dgk::launch_probe_vector(c->d_t1, M->color2, col, lf, c->nb, nv, ne, s));
-        if ((st = M->fine_f32 ? eval_residual_f32(c, true, M->w, c->d_t1, shift, c->d_t2, s)
-                              : eval_residual(c, true, M->w, c->d_t1, shift, c->d_t2, s)) != DG_OK)
-          return bail(st);
+        if ((st = eval_op(c, M->fine_prec, true, M->w, c->d_t1, shift, c->d_t2, s)) != DG_OK) return bail(st);
         // the element's own rows: column lf of its fine diagonal block
         HIPCHK(dgk::launch_extract_column(c->d_t2, M->color2, col, lf, nv * c->nb, ne, shift, c->d_D64, s));
         if (M->rescale) {
-          if ((st = eval_stab(c, M->fine_f32, M->w, c->d_t1, c->d_t3, s)) != DG_OK) return bail(st);
+          if ((st = eval_stab(c, M->fine_prec != DG_FP64, M->w, c->d_t1, c->d_t3, s)) != DG_OK) return bail(st);
           HIPCHK(dgk::launch_axpby(c->ndof, 1.0, c->d_t2, -(1.0 - s01), c->d_t3, c->d_t2, s));
           HIPCHK(dgk::launch_axpby(c->ndof, s01, c->d_t3, 0.0, c->d_t3, c->d_t3, s));
           HIPCHK(dgk::launch_extract_bsr(c->d_t3, M->color2, col, l, c->mesh.nbr, nf, c->nb, C.nb, nv, ne, C.Bs, s));
         }
         HIPCHK(dgk::launch_extract_bsr(c->d_t2, M->color2, col, l, c->mesh.nbr, nf, c->nb, C.nb, nv, ne, C.B, s));
       }
-    if ((st = block_probe_invert(c, w, shift, o->storage, C.nb, s)) != DG_OK) return bail(st);
+    // the remaining columns of the fine blocks with the same operator
+    if ((st = block_probe_invert(c, w, shift, o->storage, C.nb, M->fine_prec, s)) != DG_OK) return bail(st);
   }
   for (int l = 2; l < M->nlev; ++l) {
     MgLevel& P = M->lev[l - 1];
@@ -598,7 +598,10 @@ dg_status dg_mg_update_fine(dg_context* c, const double* w, double shift, int re
   hipStream_t s = (hipStream_t)stream;
   dg_status st;
   M->ready = false;
-  if (refresh_blocks && (st = dg_block_precond_setup(c, w, shift, M->storage, stream)) != DG_OK) return st;
+  if (refresh_blocks) {  // all columns with the cycle's fine operator, as at setup
+    if ((st = block_alloc(c, M->storage)) != DG_OK) return st;
+    if ((st = block_probe_invert(c, w, shift, M->storage, 0, M->fine_prec, s)) != DG_OK) return st;
+  }
   HIPCHK(dgk::launch_axpby(c->ndof, 1.0, w, 0.0, w, M->w, s));
   M->shift = shift;
   HIPCHK(hipStreamSynchronize(s));

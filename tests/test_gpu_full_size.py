@@ -12,8 +12,10 @@ well as a 2-norm over the sample:
 * FP64 operator: both <= 1e-12 of the scale max(|R|, |R_volume|) (residual)
   or |Jv| (Jacobian-vector product);
 * FP32 operator (contractions and pointwise fluxes in FP32): <= 1e-5 of the
-  same scales, and above 1e-10 (genuinely reduced precision); the measured
-  errors are printed.
+  same scales, and above 1e-10 (genuinely reduced precision);
+* BF16-contraction operator (affine lattice only; the curved mesh refuses it):
+  <= 3e-2 of the same scales and above 1e-5;
+the measured errors are printed.
 """
 import sys
 
@@ -76,36 +78,53 @@ def _errors(got, ref, scale):
     return np.abs(d).max() / scale[0], np.linalg.norm(d) / scale[1]
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+BOUNDS = {"fp64": (0.0, 1e-12), "fp32": (1e-10, 1e-5), "bf16": (1e-5, 3e-2)}
+
+
+def _refused_on_curved(workload, precision):
+    if precision == "bf16" and workload["name"] == "cfg4":
+        from paper_1809_00866_amd._lib import DGError
+        with pytest.raises(DGError) as ei:
+            workload["g"].residual(workload["w"], precision="bf16")
+        assert ei.value.status == -1
+        return True
+    return False
+
+
+def _check(e_max, e_2, precision):
+    lo, hi = BOUNDS[precision]
+    assert lo < e_2 or lo == 0.0
+    assert e_max <= hi and e_2 <= hi
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16"])
 def test_full_size_p4_residual(workload, precision):
     o, g, s = workload["o"], workload["g"], workload["sample"]
     R, Rv = workload["R"], workload["Rv"]
     _say(f"full-size {workload['name']} residual {precision}")
+    if _refused_on_curved(workload, precision):
+        return
     Rg = o.from_flat(g.residual(workload["w"], precision=precision).cpu().numpy())[s]
     scale = (max(np.abs(R).max(), np.abs(Rv).max()), max(np.linalg.norm(R), np.linalg.norm(Rv)))
     e_max, e_2 = _errors(Rg, R, scale)
     _say(f"  residual {precision}: max-entry error {e_max:.2e}, 2-norm error {e_2:.2e}")
-    if precision == "fp64":
-        assert e_max <= 1e-12 and e_2 <= 1e-12
-    else:
-        assert 1e-10 < e_2 and e_max <= 1e-5 and e_2 <= 1e-5
+    _check(e_max, e_2, precision)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16"])
 def test_full_size_p4_jvp(workload, precision):
     o, g, s, J, V = workload["o"], workload["g"], workload["sample"], workload["J"], workload["V"]
     _say(f"full-size {workload['name']} jvp {precision}")
+    if _refused_on_curved(workload, precision):
+        return
     shift = 2.5
-    mode = "exact" if precision == "fp64" else "exact_fp32"
+    mode = {"fp64": "exact", "fp32": "exact_fp32", "bf16": "exact_bf16"}[precision]
     Jg = o.from_flat(g.jvp(workload["w"], workload["v"], shift=shift, mode=mode).cpu().numpy())[s]
     ref = J + shift * V[s]
     scale = (np.abs(ref).max(), np.linalg.norm(ref))
     e_max, e_2 = _errors(Jg, ref, scale)
     _say(f"  jvp {precision}: max-entry error {e_max:.2e}, 2-norm error {e_2:.2e}")
-    if precision == "fp64":
-        assert e_max <= 1e-12 and e_2 <= 1e-12
-    else:
-        assert 1e-10 < e_2 and e_max <= 1e-5 and e_2 <= 1e-5
+    _check(e_max, e_2, precision)
 
 
 def test_boundary_sample_covers_tiles_and_xcd_ranges():

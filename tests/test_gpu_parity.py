@@ -303,9 +303,33 @@ def test_fp32_operator_error_against_the_oracle(N, k, sp, nq, flux):
     assert 1e-10 < err_r <= 1e-5 and 1e-10 < err_j <= 1e-5
 
 
+@pytest.mark.parametrize("N,k,sp,nq,flux", [CASES[2], CASES[3], CASES[5]], ids=[IDS[2], IDS[3], IDS[5]])
+def test_bf16_contraction_operator_error_against_the_oracle(N, k, sp, nq, flux):
+    """BF16 contractions (BF16 operands, FP32 accumulation) with FP32 pointwise
+    fluxes: error against the FP64 oracle within the 3e-2 bound for BF16
+    contractions, measured and printed, and genuinely BF16 (above 1e-5)."""
+    _say(f"bf16 operator {N} {sp}{k}")
+    o, g, U, w = make_case(N, k, sp, nq, flux)
+    R, Rv = o.residual(U, return_parts=True)
+    rb = g.residual(w, precision="bf16").cpu().numpy()
+    err_r = np.linalg.norm(rb - o.to_flat(R)) / max(np.linalg.norm(R), np.linalg.norm(Rv))
+    V = np.random.default_rng(866).standard_normal(U.shape)
+    v = torch.tensor(o.to_flat(V), device="cuda")
+    ref = o.to_flat(o.jvp(U, V) + 3.0 * V)
+    jb = g.jvp(w, v, shift=3.0, mode="exact_bf16").cpu().numpy()
+    err_j = rel(jb, ref)
+    ref0 = o.to_flat(o.jvp(U, V))
+    err_j0 = rel(g.jvp(w, v, mode="exact_bf16").cpu().numpy(), ref0)
+    _say(f"  bf16 residual error {err_r:.2e}, Jv error {err_j:.2e} (shift 3), {err_j0:.2e} (no shift)")
+    assert 1e-5 < err_r <= 3e-2 and err_j <= 3e-2 and 1e-5 < err_j0 <= 3e-2
+
+
 def test_fp32_operator_rejects_configurations_without_mfma_kernels():
     from paper_1809_00866_amd._lib import DGError
     o, g, U, w = make_case((4, 4), 2, "Q", 4)
     with pytest.raises(DGError) as ei:
         g.residual(w, precision="fp32")
+    assert ei.value.status == -1
+    with pytest.raises(DGError) as ei:
+        g.residual(w, precision="bf16")
     assert ei.value.status == -1
