@@ -12,11 +12,19 @@ paper does not specify one; the choices are listed with the other readings):
   neighbour f (order -x,+x,-y,+y,-z,+z) the cell means of the n conserved
   variables of the linearisation state divided by their RMS over the mesh;
 * a multilayer perceptron n_in -> 256 -> 256 -> n*Nb with ReLU after the two
-  hidden layers; weights and activations are BF16 (round to nearest even),
-  biases and accumulation FP32 on the device (FP64 here);
-* output z_K = s_K * MLP(x_K) (positively homogeneous in r);
-* training: mean squared error on the normalised targets t_K = z_K / s_K,
-  Adam (beta1 0.9, beta2 0.999, eps 1e-8), FP32 master weights.
+  hidden layers, trained and applied in BF16 mixed precision: every operand
+  of every matrix product is a BF16 number (round to nearest even) -- in the
+  forward pass the inputs, weights and hidden activations, in the backward
+  pass also the output gradient and the back-propagated deltas -- while
+  sums, biases, the ReLU masks and the master weights keep full precision
+  (FP32 on the device, FP64 here).  round_deltas=False gives the narrower
+  reading that rounds only the forward operands;
+* output z_K = s_K * MLP(x_K) (positively homogeneous in r), or in the
+  block-Jacobi correction mode z_K = D_K^{-1} r_K + s_K * MLP(x_K), where a
+  network with a zero last layer is block Jacobi exactly;
+* training: mean squared error on the normalised targets t_K = z_K / s_K
+  (correction mode: (z_K - D_K^{-1} r_K) / s_K), Adam (beta1 0.9, beta2
+  0.999, eps 1e-8), FP32 master weights.
 
 Parameter vector (flat, FP32 on the device): W1 [256 x n_in], b1 [256],
 W2 [256 x 256], b2 [256], W3 [n_out x 256], b3 [n_out] (row-major, rows =
@@ -65,6 +73,21 @@ def cell_means(o, U):
     return np.einsum("eq,eqc->ec", et["wdet"], vals) / et["wdet"].sum(axis=1)[:, None]
 
 
+def block_apply(D, R):
+    """D_K^{-1} r_K for blocks D[e, m, m] and R[e, c, b] (LU solve), as [e, c, b]."""
+    ne = R.shape[0]
+    return np.linalg.solve(D, R.reshape(ne, -1)[..., None])[..., 0].reshape(R.shape)
+
+
+def targets(R, Z, D=None):
+    """Normalised targets z_K / s_K, or (z_K - D_K^{-1} r_K) / s_K when the
+    blocks D are given (correction mode), as [ne, n*Nb]."""
+    ne = R.shape[0]
+    s = np.linalg.norm(R.reshape(ne, -1), axis=1) + 1e-300
+    Y = Z if D is None else Z - block_apply(D, R)
+    return Y.reshape(ne, -1) / s[:, None]
+
+
 def features(o, U, R):
     """Network inputs X [ne, n_in] and scales s [ne] for residual R[e, c, b] at state U."""
     r = R.reshape(o.ne, -1)
@@ -88,13 +111,15 @@ def forward(theta, X, n_out, rounding=True):
     return y, (x, a1, a2)
 
 
-def loss_and_grad(theta, X, T, rounding=True):
+def loss_and_grad(theta, X, T, rounding=True, round_deltas=True):
     """L = mean((Y - T)^2) over batch and outputs, and dL/dtheta.  With
-    rounding, the output gradient and the back-propagated deltas are rounded
-    to BF16 like the activations (the device stores them so for its BF16
-    products); the rounding itself is differentiated as the identity."""
+    rounding, the forward operands are BF16 and (round_deltas) so are the
+    operands of the backward products: the output gradient and the
+    back-propagated deltas (BF16 mixed-precision training, see the module
+    docstring); the rounding itself is differentiated as the identity."""
     n_out = T.shape[1]
-    q = bf16_round if rounding else (lambda a: np.asarray(a, dtype=np.float64))
+    qf = bf16_round if rounding else (lambda a: np.asarray(a, dtype=np.float64))
+    q = qf if round_deltas else (lambda a: np.asarray(a, dtype=np.float64))
     W1, b1, W2, b2, W3, b3 = split(theta, X.shape[1], n_out)
     y, (x, a1, a2) = forward(theta, X, n_out, rounding)
     B = X.shape[0]
@@ -102,10 +127,10 @@ def loss_and_grad(theta, X, T, rounding=True):
     dy = q(2.0 * (y - T) / (B * n_out))
     gW3 = dy.T @ a2
     gb3 = dy.sum(axis=0)
-    d2 = q((dy @ q(W3)) * (a2 > 0))
+    d2 = q((dy @ qf(W3)) * (a2 > 0))
     gW2 = d2.T @ a1
     gb2 = d2.sum(axis=0)
-    d1 = q((d2 @ q(W2)) * (a1 > 0))
+    d1 = q((d2 @ qf(W2)) * (a1 > 0))
     gW1 = d1.T @ x
     gb1 = d1.sum(axis=0)
     g = np.concatenate([gW1.ravel(), gb1, gW2.ravel(), gb2, gW3.ravel(), gb3])
@@ -121,8 +146,10 @@ def adam_step(theta, g, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
     return theta - lr * mhat / (np.sqrt(vhat) + eps), m, v
 
 
-def apply(o, theta, U, R, rounding=True):
-    """z = s_K * MLP(x_K) for every element, returned as [e, c, b]."""
+def apply(o, theta, U, R, rounding=True, D=None):
+    """z = s_K * MLP(x_K) for every element, plus D_K^{-1} r_K when the blocks D
+    are given (correction mode), returned as [e, c, b]."""
     X, s = features(o, U, R)
     y, _ = forward(theta, X, o.nvar * o.nb, rounding)
-    return (s[:, None] * y).reshape(o.ne, o.nvar, o.nb)
+    z = (s[:, None] * y).reshape(o.ne, o.nvar, o.nb)
+    return z if D is None else z + block_apply(D, R)

@@ -31,7 +31,8 @@ hipError_t launch_adam(int64_t n, float* th, float* m, float* v, const float* g,
 hipError_t launch_pack_weight(const float* W, int rows, int cols, unsigned short* Wb, int prow, int pcol,
                               hipStream_t s);
 hipError_t launch_pack_bias(const float* b, int n, float* bp, int np, hipStream_t s);
-hipError_t launch_mlp_scatter(const float* Y, int ldy, const double* sc, int m, int64_t ne, double* z, hipStream_t s);
+hipError_t launch_mlp_scatter(const float* Y, int ldy, const double* sc, int m, int64_t ne, double* z, int add,
+                              hipStream_t s);
 }  // namespace dgk
 
 namespace dgc {
@@ -62,6 +63,9 @@ struct MlpState {
   double* s = nullptr;
   double* ss = nullptr;
   double* mref = nullptr;
+  // DG_MLP_CORRECT_BJ: z = D^-1 r + s_K MLP(x_K), targets (z - D^-1 r)/s_K
+  int mode = DG_MLP_DIRECT;
+  double* zt = nullptr;  // ndof: z - D^-1 r for the targets
 };
 
 void mlp_destroy(MlpState* M) {
@@ -69,7 +73,7 @@ void mlp_destroy(MlpState* M) {
   for (void* p : {(void*)M->theta, (void*)M->m, (void*)M->v, (void*)M->grad, (void*)M->W1b, (void*)M->W2b,
                   (void*)M->W3b, (void*)M->b1p, (void*)M->b2p, (void*)M->b3p, (void*)M->Xb, (void*)M->a1,
                   (void*)M->a2, (void*)M->dY, (void*)M->d2, (void*)M->d1, (void*)M->Y, (void*)M->part,
-                  (void*)M->loss, (void*)M->Xf, (void*)M->s, (void*)M->ss, (void*)M->mref})
+                  (void*)M->loss, (void*)M->Xf, (void*)M->s, (void*)M->ss, (void*)M->mref, (void*)M->zt})
     dfree(p);
   delete M;
 }
@@ -207,6 +211,14 @@ dg_status features_impl(dg_context* c, MlpState* M, const double* w, const doubl
     HIPCHK(dgk::launch_sum_partials(c->d_red, dgk::kRedBlocks, M->ss + v, 0, s));
   }
   HIPCHK(dgk::launch_mlp_mref(M->ss, c->nv, c->ne, 1.0 / vol, M->mref, s));
+  if (z && M->mode == DG_MLP_CORRECT_BJ) {  // the targets are the correction to block Jacobi
+    if (!c->blk_ready) return fail(DG_ERR_STATE, "the block-Jacobi correction mode needs a block setup");
+    dg_status st;
+    if ((st = dalloc(&M->zt, (size_t)c->ndof)) != DG_OK) return st;
+    HIPCHK(dgk::launch_block_apply(c->blk_storage, c->d_Dinv, c->nv * c->nb, c->ne, r, M->zt, s));
+    HIPCHK(dgk::launch_axpby(c->ndof, 1.0, z, -1.0, M->zt, M->zt, s));
+    z = M->zt;
+  }
   HIPCHK(dgk::launch_mlp_features(w, r, z, c->mesh.nbr, M->mref, c->nv, c->nb, 2 * c->dim, c->ne, 1.0 / std::sqrt(vol),
                                   X, ldx, T, sK, s));
   return DG_OK;
@@ -225,7 +237,12 @@ dg_status mlp_apply(dg_context* c, const double* w, const double* r, double* z, 
   if ((st = features_impl(c, M, w, r, nullptr, M->Xf, M->KP, nullptr, M->s, s)) != DG_OK) return st;
   HIPCHK(dgk::launch_mlp_pack_rows(M->Xf, M->KP, M->n_in, nullptr, ne, ne, M->Xb, M->KP, s));
   if ((st = forward_rows(M, ne, M->Y, M->NP, M->n_out, s)) != DG_OK) return st;
-  HIPCHK(dgk::launch_mlp_scatter(M->Y, M->NP, M->s, M->n_out, ne, z, s));
+  const int add = M->mode == DG_MLP_CORRECT_BJ;
+  if (add) {
+    if (!c->blk_ready) return fail(DG_ERR_STATE, "the block-Jacobi correction mode needs a block setup");
+    HIPCHK(dgk::launch_block_apply(c->blk_storage, c->d_Dinv, c->nv * c->nb, ne, r, z, s));
+  }
+  HIPCHK(dgk::launch_mlp_scatter(M->Y, M->NP, M->s, M->n_out, ne, z, add, s));
   return DG_OK;
 }
 
@@ -254,6 +271,16 @@ dg_status dg_mlp_set_weights(dg_context* c, const float* theta, void* stream) {
   M->step = 0;
   if ((st = pack_weights(M, s)) != DG_OK) return st;
   M->ready = true;
+  return DG_OK;
+}
+
+dg_status dg_mlp_set_mode(dg_context* c, int mode) {
+  if (!c) return fail(DG_ERR_ARG, "null argument");
+  if (mode != DG_MLP_DIRECT && mode != DG_MLP_CORRECT_BJ) return fail(DG_ERR_ARG, "unknown network mode");
+  MlpState* M;
+  dg_status st;
+  if ((st = mlp_state(c, &M)) != DG_OK) return st;
+  M->mode = mode;
   return DG_OK;
 }
 

@@ -215,13 +215,16 @@ __global__ void k_pack_bias(const float* __restrict__ b, int n, float* __restric
 }
 
 // z[j*ne + K] = s_K * Y[K][j]
+// z = s_K Y (add = 0) or z += s_K Y (add = 1; the learned correction on top
+// of the block-Jacobi vector already in z)
 __global__ void k_mlp_scatter(const float* __restrict__ Y, int ldy, const double* __restrict__ s, int m, int64_t ne,
-                              double* __restrict__ z) {
+                              double* __restrict__ z, int add) {
   const int64_t n = (int64_t)m * ne;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t K = i % ne;
     const int j = (int)(i / ne);
-    z[i] = s[K] * (double)Y[K * ldy + j];
+    const double y = s[K] * (double)Y[K * ldy + j];
+    z[i] = add ? z[i] + y : y;
   }
 }
 
@@ -295,8 +298,9 @@ hipError_t launch_pack_bias(const float* b, int n, float* bp, int np, hipStream_
   return hipGetLastError();
 }
 
-hipError_t launch_mlp_scatter(const float* Y, int ldy, const double* sc, int m, int64_t ne, double* z, hipStream_t s) {
-  k_mlp_scatter<<<grid_for((int64_t)m * ne), 256, 0, s>>>(Y, ldy, sc, m, ne, z);
+hipError_t launch_mlp_scatter(const float* Y, int ldy, const double* sc, int m, int64_t ne, double* z, int add,
+                              hipStream_t s) {
+  k_mlp_scatter<<<grid_for((int64_t)m * ne), 256, 0, s>>>(Y, ldy, sc, m, ne, z, add);
   return hipGetLastError();
 }
 

@@ -1,15 +1,17 @@
 """Training workflow of the learned element-local preconditioner.
 
-Every numerical step runs in the library (backward-Euler solves, target
+Every numerical step runs in the library (backward-Euler steps, target
 solves, features, Adam steps); this module only sequences the calls and
 samples minibatch rows.
 
-Data (one linearisation per snapshot of a backward-Euler trajectory):
-right-hand sides r = -R(w) and two Krylov vectors G r, G^2 r (scaled to
-||r||); targets z solve G z = r to a relative 1e-6; every element of every
-(r, z) pair is one training pair (x_K, z_K / s_K).  The trajectory and the
-target solves use the p-multigrid V-cycle: after the first steps of a
-low-Mach trajectory at CFL 100, block-Jacobi FGMRES(30) stagnates.
+Data (one linearisation per snapshot of a backward-Euler trajectory): input
+vectors r = R(w) and the next terms of the block-Jacobi-preconditioned
+Krylov sequence (G D^-1)^k r, which span the Arnoldi vectors that FGMRES with
+block Jacobi hands to its preconditioner; targets z solve G z = r to a
+relative 1e-6 (p-multigrid FGMRES); every element of every (r, z) pair is
+one training pair.  In the block-Jacobi correction mode the target of
+element K is (z_K - D_K^-1 r_K) / s_K.  Features and targets are normalised
+per element, so the vectors need no scaling.
 """
 import numpy as np
 import torch
@@ -35,35 +37,36 @@ def _setup(g, w, shift):
 
 
 def trajectory(g, w0, n_steps, cfl, order, h, rtol=1e-8):
-    """States after 0..n_steps backward-Euler steps (linearised, one solve each)."""
+    """States after 0..n_steps linearised backward-Euler steps (one-stage
+    Rosenbrock steps of the library, p-multigrid preconditioned)."""
+    from .schemes import LINEAR_IMPLICIT_EULER
     states = [w0.clone()]
     w = w0.clone()
     for _ in range(n_steps):
         shift = time_step(g, w, cfl, order, h)
-        b = -g.residual(w)
         _setup(g, w, shift)
-        dw, st = g.fgmres(w, shift, b, rtol=rtol, max_iter=500, precond="mg")
-        w = w + dw
+        w, st = g.rosenbrock_step(w, 1.0 / shift, LINEAR_IMPLICIT_EULER, rtol=rtol, max_iter=500, precond="mg")
+        if not st["converged"]:
+            raise RuntimeError(f"trajectory step did not converge: {st}")
         states.append(w.clone())
     return states
 
 
-def pairs(g, w, shift, rtol=1e-6, n_random=0, seed=0):
-    """(X, T) training pairs of one linearisation: r = -R(w), G r, G^2 r and
-    optionally n_random seeded Gaussian vectors (all scaled to ||R(w)||)."""
-    r0 = -g.residual(w)
-    _setup(g, w, shift)
+def pairs(g, w, shift, rtol=1e-6, n_krylov=2, n_random=0, seed=0):
+    """(X, T) training pairs of one linearisation: r = -R(w), n_krylov terms
+    (G D^-1)^k r of the block-Jacobi-preconditioned Krylov sequence and
+    optionally n_random seeded Gaussian vectors."""
+    r0 = g.residual(w)                   # the sign of a pair (r, G^-1 r) is immaterial
+    _setup(g, w, shift)                  # also the fine block-Jacobi factors at (w, shift)
     vecs = [r0]
     v = r0
-    for _ in range(2):
-        v = g.jvp(w, v, shift=shift)
-        v = v * (r0.norm() / v.norm())
+    for _ in range(n_krylov):
+        v = g.jvp(w, g.block_apply(v), shift=shift)
         vecs.append(v)
     gen = torch.Generator(device=r0.device)
     gen.manual_seed(seed)
     for _ in range(n_random):
-        v = torch.randn(r0.shape, generator=gen, device=r0.device, dtype=r0.dtype)
-        vecs.append(v * (r0.norm() / v.norm()))
+        vecs.append(torch.randn(r0.shape, generator=gen, device=r0.device, dtype=r0.dtype))
     Xs, Ts = [], []
     for r in vecs:
         z, _ = g.fgmres(w, shift, r, rtol=rtol, max_iter=500, precond="mg")

@@ -6,7 +6,8 @@ cfg2  3D compressible NS, periodic [0, 2pi]^3, 32^3 hexes, P3, 4^3 Gauss,
       Taylor-Green stand-in at Mach 0.1, Re = 1600.
 cfg3  cfg2 field at P4 on 24^3 hexes (5^3 Gauss), backward Euler at CFL 100.
 cfg4  cfg3 with every lattice vertex moved by seeded U(-0.1h, 0.1h).
-cfg5  cfg2 discretisation, learned element preconditioner workload.
+cfg5  cfg2 discretisation, learned element preconditioner workload, backward
+      Euler at CFL 30 (block-Jacobi FGMRES converges at every snapshot).
 """
 import numpy as np
 
@@ -29,7 +30,7 @@ PRESETS = {
                  cfl=100.0, mg_orders=(4, 2, 1), mg_smooth=(8, 8, 40), restart=30, rtol=1e-8),
     "cfg5": dict(dim=3, N=(32, 32, 32), L=2 * np.pi, space="P", order=3, nq1d=4, mu=1.0 / 1600.0,
                  field="taylor_green", field_seed=1600, v_seed=866, perturb=0.0, mesh_seed=None,
-                 cfl=100.0, restart=30, rtol=1e-8),
+                 cfl=30.0, restart=30, rtol=1e-8),
 }
 
 
