@@ -74,6 +74,7 @@ enum { DG_FP64 = 0, DG_FP32 = 1, DG_BF16 = 2 };     /* block-factor storage */
 enum { DG_PREC_NONE = 0, DG_PREC_BJ = 1, DG_PREC_MG = 2, DG_PREC_MLP = 3 };  /* FGMRES preconditioner */
 enum { DG_ORTH_CGS2 = 0, DG_ORTH_MGS = 1 };         /* FGMRES orthogonalisation */
 enum { DG_MG_V = 0, DG_MG_FULL = 1 };               /* p-multigrid cycle (Algs. vcic, fullvcic) */
+enum { DG_PHYS_COMPRESSIBLE = 0, DG_PHYS_INCOMPRESSIBLE = 1, DG_PHYS_DIFFUSION = 2 };  /* equations */
 
 /* Discretisation parameters.
  *  dim 2 or 3; order k >= 0; basis DG_BASIS_PK (paper's total-degree space,
@@ -82,10 +83,28 @@ enum { DG_MG_V = 0, DG_MG_FULL = 1 };               /* p-multigrid cycle (Algs. 
  *  gamma, prandtl, mu: perfect gas, constant viscosity; eta_br2: BR2
  *  stabilisation (must exceed the number of faces of an element, Sec. 2.1;
  *  <= 0 selects 2*dim+1); entropy_fix: Harten fix width of the Roe flux as a
- *  fraction of |u.n| + c (<= 0 selects 0.1). */
+ *  fraction of |u.n| + c (<= 0 selects 0.1).
+ *  physics DG_PHYS_COMPRESSIBLE (default, zero): conserved (rho, rho u, rho E).
+ *  physics DG_PHYS_INCOMPRESSIBLE: the paper's own equations (Sec. 2.1, eq.
+ *  ns): unit density, variables (u_1..u_d, p) (nvar = dim + 1), kinematic
+ *  viscosity mu, Stokes stress; the divergence constraint is the last
+ *  equation; the mass form of eq. massBil acts on the velocities only, so
+ *  every "shift*v" below (Jv, block setup, p-multigrid, FGMRES, Rosenbrock)
+ *  is shift times v on the velocity variables and 0 on the pressure (a
+ *  differential-algebraic system); the interface flux is the Lax-Friedrichs
+ *  flux of the artificial compressibility system (1/beta^2) dp/dt + div u = 0
+ *  with beta = ac_beta (<= 0 selects 1), standing in for the exact Riemann
+ *  solver of that system that the paper cites; flux and gamma/prandtl are
+ *  ignored.  Uniform lattices only (DG_ERR_ARG on curved meshes), reference
+ *  (vector-ALU) kernels, FP64 only (no FP32/BF16 operator, no network).
+ *  physics DG_PHYS_DIFFUSION: the scalar BR2 Laplacian of the paper's
+ *  Poisson assessment (App. B): one variable, residual of -div(mu grad u)
+ *  (no convective flux); uniform lattices, reference kernels, FP64 only. */
 typedef struct {
   int dim, order, basis, nq1d, flux;
   double gamma, prandtl, mu, eta_br2, entropy_fix;
+  int physics;
+  double ac_beta;
 } dg_params;
 
 /* Mesh (host memory, read during dg_create only).

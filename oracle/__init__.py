@@ -25,17 +25,20 @@ The oracle follows the paper's statement of the discretisation:
 
 Compressible Navier-Stokes fluxes (perfect gas, Stokes stress as in the
 paper's viscous flux, Fourier heat flux, Lax-Friedrichs or Roe convective
-flux) are textbook definitions; the paper's incompressible artificial
-compressibility flux is not reproduced.
+flux) are textbook definitions.  The paper's own incompressible equations
+(eq. ns, velocity and pressure, the mass form of eq. massBil) are in
+IncompressibleNS, with a Lax-Friedrichs flux of the artificial
+compressibility system standing in for the exact Riemann solver the paper
+cites.
 """
 from .quadrature import gauss_legendre, tensor_rule
 from .basis import multi_indices, legendre_orthonormal, eval_basis, basis_size
-from .physics import NavierStokes, Diffusion
+from .physics import NavierStokes, Diffusion, IncompressibleNS
 from .dg import DGOracle
 from .solvers import fgmres, block_solve, backward_euler_dt
 
 __all__ = [
     "gauss_legendre", "tensor_rule", "multi_indices", "legendre_orthonormal", "eval_basis",
-    "basis_size", "NavierStokes", "Diffusion", "DGOracle", "fgmres", "block_solve",
+    "basis_size", "NavierStokes", "Diffusion", "IncompressibleNS", "DGOracle", "fgmres", "block_solve",
     "backward_euler_dt",
 ]

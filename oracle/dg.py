@@ -265,11 +265,18 @@ class DGOracle:
             R0 = self.residual(U, elems)
         return (self.residual(U + delta * V, elems) - R0) / delta
 
+    def mass(self):
+        """Per-variable mass weights of eq. massBil (orthonormal basis): 1 for
+        every variable with a time derivative, 0 for the incompressible
+        pressure."""
+        return np.asarray(getattr(self.phys, "mass", np.ones(self.nvar)), dtype=np.float64)
+
     def operator(self, U, V, shift, elems=None):
-        """G V = shift*V + J(U) V (eq. rosSysOp with an identity mass matrix)."""
+        """G V = shift*M V + J(U) V (eq. rosSysOp; M = I on the variables with a
+        time derivative, 0 on the incompressible pressure)."""
         out = self.jvp(U, V, elems)
         Vs = V if elems is None else V[np.unique(elems)]
-        return shift * Vs + out
+        return shift * self.mass()[None, :, None] * Vs + out
 
     def coloring(self):
         """Greedy colouring of the face-neighbour graph (self-loops ignored)."""
@@ -283,7 +290,7 @@ class DGOracle:
         return color
 
     def block_diagonal(self, U, shift=0.0, method="color", h=1e-100):
-        """D_K = shift*I + dR_K/dU_K for every element, as [Ne, n*Nb, n*Nb].
+        """D_K = shift*M_K + dR_K/dU_K for every element, as [Ne, n*Nb, n*Nb].
 
         Local DOF index l = c*Nb + b.  'brute' perturbs one element at a time;
         'color' perturbs one colour class at a time (no two elements of a class
@@ -307,7 +314,7 @@ class DGOracle:
                     Vc[members, j // self.nb, j % self.nb] = 1.0
                     col = self.jvp(U, Vc)
                     D[members, :, j] = col[members].reshape(len(members), -1)
-        D += shift * np.eye(nloc)[None]
+        D += shift * np.diag(np.repeat(self.mass(), self.nb))[None]
         return D
 
     # --------------------------------------------------------------- projection

@@ -185,3 +185,77 @@ class Diffusion:
 
     def conv_numflux(self, UL, UR, n):
         return np.zeros(np.broadcast_shapes(UL.shape, UR.shape), dtype=np.result_type(UL, UR))
+
+
+class IncompressibleNS:
+    """Incompressible Navier-Stokes equations of Sec. 2.1 (eq. ns), unit
+    density, unknowns w = (u_1..u_d, p) (velocity first, pressure last):
+
+      F_p = (u_p u + p e_p,  u_p)       convective part and the mass flux
+      F^v_p = (nu (grad u + grad u^T - 2/3 div(u) I)_p.,  0)
+
+    so that the residual of eq. NSdiscrRes carries the momentum equations and
+    the divergence constraint tested with q.  The time derivative acts on the
+    velocities only (mass form m_h of eq. massBil): ``mass`` is 1 for the d
+    velocity components and 0 for the pressure.
+
+    Interface flux.  The paper takes it from the exact solution of Riemann
+    problems of an artificial compressibility perturbation of the Euler
+    equations, defined in a cited work only.  Stand-in: the Lax-Friedrichs
+    flux of that perturbed system, with the pressure equation
+    (1/beta^2) dp/dt + div u = 0 (so that its flux is the residual's u),
+        H = 1/2 (F(w_L) + F(w_R)).n - 1/2 lambda diag(1,..,1, 1/beta^2) (w_R - w_L),
+    lambda = max over both sides of |u.n| + sqrt((u.n)^2 + beta^2), the
+    largest eigenvalue modulus of that system's normal flux Jacobian.
+    """
+
+    def __init__(self, dim, nu=1e-2, beta=1.0, eta=None):
+        self.d = int(dim)
+        self.nvar = self.d + 1
+        self.nu = float(nu)
+        self.beta = float(beta)
+        self.eta = float(2 * self.d + 1) if eta is None else float(eta)
+        self.mass = np.array([1.0] * self.d + [0.0])
+
+    def conv_flux(self, U):
+        """F_p[..., p, c] (momentum: u_p u_i + p delta_pi; mass: u_p)."""
+        d = self.d
+        u = U[..., :d]
+        p = U[..., d]
+        F = np.zeros(U.shape[:-1] + (d, self.nvar), dtype=U.dtype)
+        for P in range(d):
+            for i in range(d):
+                F[..., P, i] = u[..., P] * u[..., i]
+            F[..., P, P] += p
+            F[..., P, d] = u[..., P]
+        return F
+
+    def visc_flux(self, U, G):
+        """F^v[..., p, c] from the corrected gradient G[..., c, p] (velocity rows)."""
+        d, nu = self.d, self.nu
+        dtype = np.result_type(U, G)
+        g = G[..., :d, :]                       # g[..., i, j] = d u_i / d x_j
+        div = sum(g[..., j, j] for j in range(d))
+        F = np.zeros(U.shape[:-1] + (d, self.nvar), dtype=dtype)
+        for P in range(d):
+            for i in range(d):
+                t = nu * (g[..., P, i] + g[..., i, P])
+                if i == P:
+                    t = t - (2.0 / 3.0) * nu * div
+                F[..., P, i] = t
+        return F
+
+    def wave_speed_n(self, U, n):
+        un = np.sum(U[..., :self.d] * n, axis=-1)
+        return rabs(un) + np.sqrt(un * un + self.beta ** 2)
+
+    def conv_numflux(self, UL, UR, n):
+        Fn = 0.5 * (np.einsum("...pc,...p->...c", self.conv_flux(UL), n)
+                    + np.einsum("...pc,...p->...c", self.conv_flux(UR), n))
+        lam = rmax(self.wave_speed_n(UL, n), self.wave_speed_n(UR, n))
+        scale = np.array([1.0] * self.d + [1.0 / self.beta ** 2])
+        return Fn - 0.5 * lam[..., None] * scale * (UR - UL)
+
+    def max_wave_speed(self, U):
+        q = np.sqrt(np.sum(U[..., :self.d] ** 2, axis=-1))
+        return q + np.sqrt(q * q + self.beta ** 2)

@@ -3,12 +3,13 @@
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
-For M dw/dt + R(w) = 0 (M = I with the orthonormal modal basis), one step
-from w^n of size dt with n_s stages:
+For M dw/dt + R(w) = 0 (M = I with the orthonormal modal basis, restricted
+to the velocities for the incompressible equations), one step from w^n of
+size dt with n_s stages:
 
     for s = 1..n_s:
         dp = sum_{o<s} a[s][o] dw_o,   dq = sum_{o<s} c[s][o] dw_o
-        (I/(gamma dt) + J(w^n)) dw_s = -R(w^n + dp) - dq/dt
+        (M/(gamma dt) + J(w^n)) dw_s = -R(w^n + dp) - M dq/dt
     w^{n+1} = w^n + sum_s m[s] dw_s
 
 The Jacobian (and any preconditioner) is that of w^n for every stage.  The
@@ -21,9 +22,11 @@ Blom, Hundsdorfer 1999), rewritten in the form above.
 import numpy as np
 
 
-def step(residual, solve, w, dt, gamma, a, c, m):
-    """One step.  residual(x) -> R(x); solve(rhs) -> (I/(gamma dt) + J(w^n))^-1 rhs.
-    a, c: n_s x n_s (strictly lower parts used), m: n_s.  Flat FP64 arrays."""
+def step(residual, solve, w, dt, gamma, a, c, m, mass=None):
+    """One step.  residual(x) -> R(x); solve(rhs) -> (M/(gamma dt) + J(w^n))^-1 rhs.
+    a, c: n_s x n_s (strictly lower parts used), m: n_s.  Flat FP64 arrays.
+    mass: the diagonal of M (flat, default identity); the dq/dt term of the
+    stage right-hand side is M dq / dt (eq. rossys)."""
     w = np.asarray(w, dtype=np.float64)
     dws = []
     for s in range(len(m)):
@@ -32,7 +35,7 @@ def step(residual, solve, w, dt, gamma, a, c, m):
         for o in range(s):
             dp += a[s][o] * dws[o]
             dq += c[s][o] * dws[o]
-        dws.append(solve(-residual(w + dp) - dq / dt))
+        dws.append(solve(-residual(w + dp) - (dq if mass is None else mass * dq) / dt))
     out = w.copy()
     for s in range(len(m)):
         out += m[s] * dws[s]
@@ -54,9 +57,11 @@ def ros2():
                 m=[1.5 / g, 0.5 / g])
 
 
-def dg_step(o, U, dt, coeffs):
+def dg_step(o, U, dt, coeffs, lstsq=False):
     """One step of the oracle DG discretisation (U[e, c, b]) with dense solves
-    of the stage systems (small meshes only)."""
+    of the stage systems (small meshes only).  lstsq: minimum-norm solutions
+    (for singular consistent stage systems, e.g. the incompressible equations
+    on a periodic mesh, whose pressure level is free)."""
     shift = 1.0 / (coeffs["gamma"] * dt)
     n = U.size
     G = np.zeros((n, n))
@@ -65,6 +70,7 @@ def dg_step(o, U, dt, coeffs):
         V[j] = 1.0
         G[:, j] = o.operator(U, V.reshape(U.shape), shift).reshape(-1)
     res = lambda x: o.residual(x.reshape(U.shape)).reshape(-1)
-    out = step(res, lambda r: np.linalg.solve(G, r), U.reshape(-1), dt, coeffs["gamma"], coeffs["a"], coeffs["c"],
-               coeffs["m"])
+    mass = np.broadcast_to(o.mass()[None, :, None], U.shape).reshape(-1)
+    solve = (lambda r: np.linalg.lstsq(G, r, rcond=None)[0]) if lstsq else (lambda r: np.linalg.solve(G, r))
+    out = step(res, solve, U.reshape(-1), dt, coeffs["gamma"], coeffs["a"], coeffs["c"], coeffs["m"], mass=mass)
     return out.reshape(U.shape)

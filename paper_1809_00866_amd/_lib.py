@@ -19,6 +19,7 @@ DG_PREC_NONE, DG_PREC_BJ, DG_PREC_MG, DG_PREC_MLP = 0, 1, 2, 3
 DG_MG_V, DG_MG_FULL = 0, 1
 DG_ORTH_CGS2, DG_ORTH_MGS = 0, 1
 DG_MLP_DIRECT, DG_MLP_CORRECT_BJ = 0, 1
+DG_PHYS_COMPRESSIBLE, DG_PHYS_INCOMPRESSIBLE, DG_PHYS_DIFFUSION = 0, 1, 2
 
 EXPORTED = ["dg_create", "dg_destroy", "dg_ndof", "dg_nbasis", "dg_nvar", "dg_nq", "dg_volume_points",
             "dg_project", "dg_residual", "dg_residual_fp32", "dg_residual_bf16", "dg_jvp", "dg_jvp_noalloc", "dg_jvp_noalloc_scratch_bytes",
@@ -32,7 +33,8 @@ EXPORTED = ["dg_create", "dg_destroy", "dg_ndof", "dg_nbasis", "dg_nvar", "dg_nq
 class DGParams(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("order", ctypes.c_int), ("basis", ctypes.c_int), ("nq1d", ctypes.c_int),
                 ("flux", ctypes.c_int), ("gamma", ctypes.c_double), ("prandtl", ctypes.c_double),
-                ("mu", ctypes.c_double), ("eta_br2", ctypes.c_double), ("entropy_fix", ctypes.c_double)]
+                ("mu", ctypes.c_double), ("eta_br2", ctypes.c_double), ("entropy_fix", ctypes.c_double),
+                ("physics", ctypes.c_int), ("ac_beta", ctypes.c_double)]
 
 
 class DGMesh(ctypes.Structure):

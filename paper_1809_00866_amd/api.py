@@ -36,14 +36,20 @@ class DG:
     """A DG discretisation on a periodic lattice (see include/dg.h)."""
 
     def __init__(self, mesh, order, basis="P", nq1d=None, flux="roe", gamma=1.4, prandtl=0.72, mu=1e-3,
-                 eta=0.0, entropy_fix=0.0, device="cuda"):
+                 eta=0.0, entropy_fix=0.0, physics="compressible", beta=1.0, device="cuda"):
+        """physics "compressible" (conserved rho, rho u, rho E), "incompressible"
+        (u, p; mu is the kinematic viscosity, beta the artificial compressibility
+        speed of the interface flux) or "diffusion" (scalar BR2 Laplacian, mu
+        the diffusivity)."""
         self.lib = L.load()
         self.dim = int(mesh["dim"])
         self.order = int(order)
         self.nq1d = int(nq1d if nq1d is not None else order + 1)
         self.device = torch.device(device)
+        phys = {"compressible": L.DG_PHYS_COMPRESSIBLE, "incompressible": L.DG_PHYS_INCOMPRESSIBLE,
+                "diffusion": L.DG_PHYS_DIFFUSION}[physics]
         prm = L.DGParams(self.dim, self.order, _BASIS[basis], self.nq1d, _FLUX[flux], gamma, prandtl, mu, eta,
-                         entropy_fix)
+                         entropy_fix, phys, beta)
         xyz = np.ascontiguousarray(mesh["elem_xyz"], dtype=np.float64)
         nbr = np.ascontiguousarray(mesh["elem_nbr"], dtype=np.int64)
         m = L.DGMesh(xyz.shape[0], xyz.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),

@@ -188,7 +188,7 @@ dg_status jvp_impl(dg_context* c, const double* w, const double* r_w, const doub
   if (mode == DG_JVP_STAB) {
     dg_status st;
     if ((st = eval_stab(c, false, w, v, out, s)) != DG_OK) return st;
-    if (shift != 0.0) HIPCHK(dgk::launch_axpby(c->ndof, 1.0, out, shift, v, out, s));
+    if (shift != 0.0) HIPCHK(dgk::launch_axpby(c->mass_len, 1.0, out, shift, v, out, s));
     return DG_OK;
   }
   // finite difference of eqs. (matrix-free)/(epsdef)
@@ -203,7 +203,7 @@ dg_status jvp_impl(dg_context* c, const double* w, const double* r_w, const doub
   HIPCHK(dgk::launch_fd_delta(c->d_scal, 1e-9, s));
   HIPCHK(dgk::launch_axpy_dev(c->ndof, w, c->d_scal + 2, 1.0, v, c->d_t2, s));
   if ((st = eval_residual(c, false, c->d_t2, nullptr, 0.0, c->d_t3, s)) != DG_OK) return st;
-  HIPCHK(dgk::launch_fd_combine(c->ndof, c->d_t3, r0, c->d_scal + 3, v, shift, out, s));
+  HIPCHK(dgk::launch_fd_combine(c->ndof, c->mass_len, c->d_t3, r0, c->d_scal + 3, v, shift, out, s));
   return DG_OK;
 }
 
@@ -223,8 +223,15 @@ dg_status dg_create(const dg_params* prm, const dg_mesh* mesh, dg_context** out)
   if (prm->order < 0 || prm->nq1d < 1) return fail(DG_ERR_ARG, "order must be >= 0 and nq1d >= 1");
   if (prm->basis != DG_BASIS_PK && prm->basis != DG_BASIS_QK) return fail(DG_ERR_ARG, "unknown basis");
   if (prm->flux != DG_FLUX_LF && prm->flux != DG_FLUX_ROE) return fail(DG_ERR_ARG, "unknown flux");
-  if (!(prm->gamma > 1.0) || !(prm->prandtl > 0.0) || !(prm->mu >= 0.0))
-    return fail(DG_ERR_ARG, "need gamma > 1, prandtl > 0, mu >= 0");
+  if (prm->physics != DG_PHYS_COMPRESSIBLE && prm->physics != DG_PHYS_INCOMPRESSIBLE &&
+      prm->physics != DG_PHYS_DIFFUSION)
+    return fail(DG_ERR_ARG, "unknown physics");
+  const bool ins = prm->physics == DG_PHYS_INCOMPRESSIBLE;
+  const bool diffusion = prm->physics == DG_PHYS_DIFFUSION;
+  const bool compressible = !ins && !diffusion;
+  if (compressible && (!(prm->gamma > 1.0) || !(prm->prandtl > 0.0)))
+    return fail(DG_ERR_ARG, "need gamma > 1, prandtl > 0");
+  if (!(prm->mu >= 0.0)) return fail(DG_ERR_ARG, "need mu >= 0");
   const int64_t ne = mesh->n_elem;
   if (ne < 1 || !mesh->elem_xyz || !mesh->elem_nbr) return fail(DG_ERR_ARG, "empty mesh");
   if (ne > (int64_t)1 << 31) return fail(DG_ERR_ARG, "too many elements");
@@ -259,6 +266,8 @@ dg_status dg_create(const dg_params* prm, const dg_mesh* mesh, dg_context** out)
   } catch (const std::exception& ex) {
     return fail(DG_ERR_ARG, ex.what());
   }
+  if (!compressible && !lattice)
+    return fail(DG_ERR_ARG, "the incompressible and diffusion equations run on uniform lattices only");
   dgh::CurvedHost CH;  // curved (non-lattice) meshes: built before any device work
   if (!lattice) {
     try {
@@ -268,14 +277,16 @@ dg_status dg_create(const dg_params* prm, const dg_mesh* mesh, dg_context** out)
     }
   }
   const int cfg = dgk::config_index(dim, T.nb, prm->nq1d);
-  if (cfg < 0)
-    return fail(DG_ERR_ARG, "no kernel compiled for dim=" + std::to_string(dim) + " nbasis=" + std::to_string(T.nb) +
+  if (cfg < 0 || (!lattice && !dgk::has_curved(cfg)))
+    return fail(DG_ERR_ARG, std::string("no ") + (lattice ? "" : "curved-element ") + "kernel compiled for dim=" +
+                                std::to_string(dim) + " nbasis=" + std::to_string(T.nb) +
                                 " nq1d=" + std::to_string(prm->nq1d));
 
   auto* c = new dg_context();
   c->prm = *prm;
   c->dim = dim;
-  c->nv = dim + 2;
+  c->nv = ins ? dim + 1 : (diffusion ? 1 : dim + 2);
+  c->nmass = ins ? dim : c->nv;
   c->nb = T.nb;
   c->nq1 = prm->nq1d;
   c->nq = T.nq;
@@ -283,12 +294,15 @@ dg_status dg_create(const dg_params* prm, const dg_mesh* mesh, dg_context** out)
   c->cfg = cfg;
   c->ne = ne;
   c->ndof = ne * c->nv * c->nb;
+  c->mass_len = ne * c->nmass * c->nb;
   c->ph.gamma = prm->gamma;
   c->ph.prandtl = prm->prandtl;
   c->ph.mu = prm->mu;
   c->ph.eta = prm->eta_br2 > 0.0 ? prm->eta_br2 : 2.0 * dim + 1.0;
   c->ph.efix = prm->entropy_fix > 0.0 ? prm->entropy_fix : 0.1;
   c->ph.flux = prm->flux;
+  c->ph.model = prm->physics;
+  c->ph.beta = prm->ac_beta > 0.0 ? prm->ac_beta : 1.0;
 
   auto cleanup = [&](dg_status st) {
     dg_destroy(c);
@@ -391,7 +405,8 @@ dg_status dg_create(const dg_params* prm, const dg_mesh* mesh, dg_context** out)
 
   // MFMA operand tables (3D configurations with MFMA kernels)
   const char* variant = std::getenv("DG_KERNEL_VARIANT");
-  const bool want_mfma = lattice && !(variant && std::strcmp(variant, "reference") == 0);
+  // (the MFMA kernels carry the compressible equations only)
+  const bool want_mfma = lattice && compressible && !(variant && std::strcmp(variant, "reference") == 0);
   if (want_mfma && dgk::has_mfma(cfg)) {
     dgh::MfmaHost M;
     try {
@@ -562,7 +577,7 @@ dg_status dg_project(dg_context* c, const double* f, double* w, void* stream) {
     HIPCHK(dgk::launch_project_curved(c->cfg, f, w, c->ct, c->ne, (hipStream_t)stream));
     return DG_OK;
   }
-  HIPCHK(dgk::launch_project(c->cfg, f, w, c->tb, c->mesh, (hipStream_t)stream));
+  HIPCHK(dgk::launch_project(c->cfg, c->nv, f, w, c->tb, c->mesh, (hipStream_t)stream));
   return DG_OK;
 }
 

@@ -62,7 +62,9 @@ bool mlp_ready(const MlpState* m);
 struct dg_context {
   dg_params prm{};
   int dim = 0, nv = 0, nb = 0, nq1 = 0, nq = 0, nfq = 0, cfg = -1;
+  int nmass = 0;                 // leading variables with a time derivative (mass form)
   int64_t ne = 0, ndof = 0;
+  int64_t mass_len = 0;          // nmass*nb*ne: the DOF prefix that "shift" multiplies
   dgk::Tables tb{};
   dgk::MTables mt{};
   bool use_mfma = false;

@@ -542,6 +542,18 @@ __global__ __launch_bounds__(256) void k_wave_speed_curved(double* __restrict__ 
   X(4, 3, 20, 4)             \
   X(5, 3, 35, 5)
 
+}  // namespace dgk
+
+namespace dgk {
+
+bool has_curved(int cfg) {
+#define X(id, d, nb_, nq_) \
+  if (cfg == id) return true;
+  DG_CURVED_CONFIGS(X)
+#undef X
+  return false;
+}
+
 namespace {
 
 template <class R>

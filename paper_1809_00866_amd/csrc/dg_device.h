@@ -279,4 +279,108 @@ DEV void visc_flux_dir(const ViscPrep<T, DIM>& vp, int P, double mud, double kap
 }
 
 
+// ------------------------------------------------------------------ physics policies
+// The reference kernels take the pointwise physics as a policy: the number of
+// variables, how many of them carry a time derivative (the mass form of the
+// implicit operator: a prefix of the variables), the volume flux F_j = F^c_j -
+// F^v_j of every direction j, and the face flux H^c - F^v . e_P.
+struct CompressiblePhys {
+  template <int DIM> static constexpr int nv() { return DIM + 2; }
+  template <int DIM> static constexpr int nmass() { return DIM + 2; }
+  template <class T, int DIM>
+  static DEV void volume_flux(const T* u, const T (*G)[DIM], const Phys& ph, T (*F)[DIM + 2]) {
+    const double kap = ph.mu * ph.gamma / (ph.prandtl * (ph.gamma - 1.0));
+    T rinv, vel[DIM], pr;
+    primitives<T, DIM>(u, ph.gamma, rinv, vel, pr);
+    ViscPrep<T, DIM> vp;
+    visc_prep<T, DIM>(u, G, ph.gamma, vp);
+    for (int j = 0; j < DIM; ++j) {
+      T Fc[DIM + 2], Fv[DIM + 2];
+      conv_flux_dir<T, DIM>(u, vel, pr, j, Fc);
+      visc_flux_dir<T, DIM>(vp, j, ph.mu, kap, Fv);
+      for (int c = 0; c < DIM + 2; ++c) F[j][c] = Fc[c] - Fv[c];
+    }
+  }
+  template <class T, int DIM>
+  static DEV void face_flux(const T* uL, const T* uR, const T* ua, const T (*Ga)[DIM], int P, const Phys& ph,
+                            T* Hn) {
+    const double kap = ph.mu * ph.gamma / (ph.prandtl * (ph.gamma - 1.0));
+    num_flux<T, DIM>(uL, uR, P, ph, Hn);
+    ViscPrep<T, DIM> vp;
+    visc_prep<T, DIM>(ua, Ga, ph.gamma, vp);
+    T Fv[DIM + 2];
+    visc_flux_dir<T, DIM>(vp, P, ph.mu, kap, Fv);
+    for (int c = 0; c < DIM + 2; ++c) Hn[c] = Hn[c] - Fv[c];
+  }
+};
+
+// Incompressible Navier-Stokes (Sec. 2.1, eq. ns): w = (u_1..u_d, p), unit
+// density; F_j = (u_j u + p e_j, u_j) - (nu (grad u + grad u^T - 2/3 div u I)_j., 0);
+// only the velocities carry a time derivative (eq. massBil).  Interface flux:
+// Lax-Friedrichs of the artificial compressibility system
+// (1/beta^2) dp/dt + div u = 0 (the paper's exact Riemann solver of that
+// system is defined in a cited work only): mean normal flux minus
+// lambda/2 diag(1,..,1, 1/beta^2) (w_R - w_L), lambda = max over both sides of
+// |u.n| + sqrt((u.n)^2 + beta^2).
+struct IncompressiblePhys {
+  template <int DIM> static constexpr int nv() { return DIM + 1; }
+  template <int DIM> static constexpr int nmass() { return DIM; }
+  template <class T, int DIM>
+  static DEV void visc_dir(const T (*G)[DIM], int P, double nud, T* Fv) {
+    using R = typename RealOf<T>::type;
+    const R nu = (R)nud;
+    T div = R(0);
+    for (int i = 0; i < DIM; ++i) div += G[i][i];
+    for (int i = 0; i < DIM; ++i) {
+      T t = nu * (G[P][i] + G[i][P]);
+      if (i == P) t -= (R(2) / R(3)) * nu * div;
+      Fv[i] = t;
+    }
+    Fv[DIM] = R(0);
+  }
+  template <class T, int DIM>
+  static DEV void volume_flux(const T* u, const T (*G)[DIM], const Phys& ph, T (*F)[DIM + 1]) {
+    for (int j = 0; j < DIM; ++j) {
+      T Fv[DIM + 1];
+      visc_dir<T, DIM>(G, j, ph.mu, Fv);
+      for (int i = 0; i < DIM; ++i) F[j][i] = u[j] * u[i] - Fv[i];
+      F[j][j] += u[DIM];
+      F[j][DIM] = u[j];
+    }
+  }
+  template <class T, int DIM>
+  static DEV void face_flux(const T* uL, const T* uR, const T* ua, const T (*Ga)[DIM], int P, const Phys& ph,
+                            T* Hn) {
+    using R = typename RealOf<T>::type;
+    const R b2 = (R)(ph.beta * ph.beta);
+    const T unL = uL[P], unR = uR[P];
+    const T lam = rmax(rabs(unL) + dsqrt(unL * unL + b2), rabs(unR) + dsqrt(unR * unR + b2));
+    T Fv[DIM + 1];
+    visc_dir<T, DIM>(Ga, P, ph.mu, Fv);
+    for (int i = 0; i < DIM; ++i)
+      Hn[i] = R(0.5) * (uL[i] * unL + uR[i] * unR) - R(0.5) * lam * (uR[i] - uL[i]) - Fv[i];
+    Hn[P] += R(0.5) * (uL[DIM] + uR[DIM]);
+    Hn[DIM] = R(0.5) * (unL + unR) - (R(0.5) / b2) * lam * (uR[DIM] - uL[DIM]);
+  }
+};
+
+// Scalar diffusion (the BR2 Laplacian of the paper's Poisson assessment, App.
+// B): one variable, F^c = 0, F^v = mu grad u (corrected gradient), face flux
+// -mu ({grad u} + eta {r}) . e_P.
+struct DiffusionPhys {
+  template <int DIM> static constexpr int nv() { return 1; }
+  template <int DIM> static constexpr int nmass() { return 1; }
+  template <class T, int DIM>
+  static DEV void volume_flux(const T* u, const T (*G)[DIM], const Phys& ph, T (*F)[1]) {
+    using R = typename RealOf<T>::type;
+    for (int j = 0; j < DIM; ++j) F[j][0] = -(R)ph.mu * G[0][j];
+  }
+  template <class T, int DIM>
+  static DEV void face_flux(const T* uL, const T* uR, const T* ua, const T (*Ga)[DIM], int P, const Phys& ph,
+                            T* Hn) {
+    using R = typename RealOf<T>::type;
+    Hn[0] = -(R)ph.mu * Ga[0][P];
+  }
+};
+
 }  // namespace dgk

@@ -71,6 +71,8 @@ using MTablesF = MTablesT<float>;
 struct Phys {
   double gamma, prandtl, mu, eta, efix;
   int flux;           // DG_FLUX_LF / DG_FLUX_ROE
+  int model = 0;      // DG_PHYS_COMPRESSIBLE / DG_PHYS_INCOMPRESSIBLE
+  double beta = 1.0;  // incompressible: artificial compressibility speed of the interface flux
   int stab_only = 0;  // Jv face kernels: keep only the tangent of the face lifting
                       // term eta {r} (the BR2 stabilisation part of the Jacobian)
 };
@@ -92,6 +94,8 @@ hipError_t launch_volume(int cfg, bool jvp, const double* U, const double* V, co
                          double shift, const Tables& tb, const Mesh& m, const Phys& ph, hipStream_t stream);
 // MFMA kernels (3D); return hipErrorInvalidValue when the configuration has none.
 bool has_mfma(int cfg);
+// Curved-element kernels compiled for the configuration.
+bool has_curved(int cfg);
 hipError_t launch_face_mfma(int cfg, bool jvp, const double* U, const double* V, double* H, const MTables& mt,
                             const Mesh& m, const Phys& ph, hipStream_t stream);
 // reduced precision variant: FP32 tables, FP32 face-flux buffer, FP32 MFMA and
@@ -118,7 +122,8 @@ hipError_t launch_grad_mfma_f32(int cfg, bool jvp, const double* U, const double
 hipError_t launch_volume_mfma(int cfg, bool jvp, const double* U, const double* V, const double* Gm, const double* H,
                               double* out,
                               double shift, const MTables& mt, const Mesh& m, const Phys& ph, hipStream_t stream);
-hipError_t launch_project(int cfg, const double* f, double* w, const Tables& tb, const Mesh& m, hipStream_t s);
+hipError_t launch_project(int cfg, int nv, const double* f, double* w, const Tables& tb, const Mesh& m,
+                          hipStream_t s);
 hipError_t launch_points(int cfg, double* xyz, const Tables& tb, const Mesh& m, hipStream_t s);
 hipError_t launch_wave_speed(int cfg, const double* w, double* partial, int nblocks, const Tables& tb,
                              const Mesh& m, const Phys& ph, hipStream_t s);
@@ -131,8 +136,8 @@ hipError_t launch_axpby(int64_t n, double a, const double* x, double b, const do
 // z = a*x + s*y where s = *dscale (device scalar) times c
 hipError_t launch_axpy_dev(int64_t n, const double* x, const double* dscale, double c, const double* y, double* z,
                            hipStream_t s);
-hipError_t launch_fd_combine(int64_t n, const double* rp, const double* r0, const double* dinv, const double* v,
-                             double shift, double* out, hipStream_t s);
+hipError_t launch_fd_combine(int64_t n, int64_t nm, const double* rp, const double* r0, const double* dinv,
+                             const double* v, double shift, double* out, hipStream_t s);
 hipError_t launch_scale_dev(int64_t n, const double* x, const double* dnorm, double* y, hipStream_t s);
 // Multi-dot h[j] = V_j . w for j < k (V row-major [k][n]); partial buffer [k][kRedBlocks]
 hipError_t launch_mdot(const double* V, int k, int64_t n, const double* w, double* partial, hipStream_t s);

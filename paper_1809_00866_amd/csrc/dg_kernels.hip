@@ -27,11 +27,11 @@ namespace dgk {
 // ------------------------------------------------------------------ face kernel
 // Body for one face direction p (a compile-time constant, so every index into
 // the per-lane arrays is static and nothing spills to scratch).
-template <int DIM, int NB, int NQ1, bool JVP, int p>
+template <class PHY, int DIM, int NB, int NQ1, bool JVP, int p>
 DEV void face_body(const double* __restrict__ U, const double* __restrict__ V, double* __restrict__ H,
                    const Tables& tb, const Mesh& m, const Phys& ph) {
   using T = typename Scalar<JVP>::type;
-  constexpr int NV = DIM + 2;
+  constexpr int NV = PHY::template nv<DIM>();
   constexpr int NFQ = ipow(NQ1, DIM - 1);
   const int lane = threadIdx.x & 63;
   const int slot = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -39,7 +39,6 @@ DEV void face_body(const double* __restrict__ U, const double* __restrict__ V, d
   const int64_t e = (int64_t)blockIdx.x * 64 + lane;
   if (e >= ne) return;
   const int64_t er = m.nbr[(2 * p + 1) * ne + e];
-  const double kap = ph.mu * ph.gamma / (ph.prandtl * (ph.gamma - 1.0));
   for (int fq = slot; fq < NFQ; fq += 4) {
     T uL[NV], uR[NV], gL[NV][DIM], gR[NV][DIM], rb[NV];
     for (int c = 0; c < NV; ++c) {
@@ -82,41 +81,37 @@ DEV void face_body(const double* __restrict__ U, const double* __restrict__ V, d
         }
       }
     }
-    T Hn[NV];
-    num_flux<T, DIM>(uL, uR, p, ph, Hn);
     T ua[NV], Ga[NV][DIM];
     for (int c = 0; c < NV; ++c) {
       ua[c] = 0.5 * (uL[c] + uR[c]);
       for (int j = 0; j < DIM; ++j) Ga[c][j] = 0.5 * (gL[c][j] + gR[c][j]);
       Ga[c][p] += ph.eta * rb[c];
     }
-    ViscPrep<T, DIM> vp;
-    visc_prep<T, DIM>(ua, Ga, ph.gamma, vp);
-    T Fv[NV];
-    visc_flux_dir<T, DIM>(vp, p, ph.mu, kap, Fv);
-    for (int c = 0; c < NV; ++c) H[((size_t)(p * NV + c) * NFQ + fq) * ne + e] = out_part(Hn[c] - Fv[c]);
+    T Hn[NV];
+    PHY::template face_flux<T, DIM>(uL, uR, ua, Ga, p, ph, Hn);
+    for (int c = 0; c < NV; ++c) H[((size_t)(p * NV + c) * NFQ + fq) * ne + e] = out_part(Hn[c]);
   }
 }
 
-template <int DIM, int NB, int NQ1, bool JVP>
+template <class PHY, int DIM, int NB, int NQ1, bool JVP>
 __global__ __launch_bounds__(256) void k_face(const double* __restrict__ U, const double* __restrict__ V,
                                               double* __restrict__ H, Tables tb, Mesh m, Phys ph) {
   switch (blockIdx.y) {
-    case 0: face_body<DIM, NB, NQ1, JVP, 0>(U, V, H, tb, m, ph); break;
-    case 1: face_body<DIM, NB, NQ1, JVP, 1>(U, V, H, tb, m, ph); break;
+    case 0: face_body<PHY, DIM, NB, NQ1, JVP, 0>(U, V, H, tb, m, ph); break;
+    case 1: face_body<PHY, DIM, NB, NQ1, JVP, 1>(U, V, H, tb, m, ph); break;
     default:
-      if constexpr (DIM == 3) face_body<DIM, NB, NQ1, JVP, 2>(U, V, H, tb, m, ph);
+      if constexpr (DIM == 3) face_body<PHY, DIM, NB, NQ1, JVP, 2>(U, V, H, tb, m, ph);
       break;
   }
 }
 
 // ------------------------------------------------------------------ volume kernel
-template <int DIM, int NB, int NQ1, bool JVP, int TE, int QC>
+template <class PHY, int DIM, int NB, int NQ1, bool JVP, int TE, int QC>
 __global__ __launch_bounds__(256) void k_volume(const double* __restrict__ U, const double* __restrict__ V,
                                                 const double* __restrict__ H, double* __restrict__ out, double shift,
                                                 Tables tb, Mesh m, Phys ph) {
   using T = typename Scalar<JVP>::type;
-  constexpr int NV = DIM + 2;
+  constexpr int NV = PHY::template nv<DIM>();
   constexpr int NQ = ipow(NQ1, DIM);
   constexpr int NFQ = ipow(NQ1, DIM - 1);
   constexpr int NS = JVP ? 2 : 1;
@@ -126,7 +121,6 @@ __global__ __launch_bounds__(256) void k_volume(const double* __restrict__ U, co
   const int tid = threadIdx.x;
   const int64_t ne = m.ne;
   const int64_t e0 = (int64_t)blockIdx.x * TE;
-  const double kap = ph.mu * ph.gamma / (ph.prandtl * (ph.gamma - 1.0));
 
   for (int it = tid; it < NV * NB * TE; it += 256) {
     const int t = it % TE, cb = it / TE;
@@ -195,16 +189,10 @@ __global__ __launch_bounds__(256) void k_volume(const double* __restrict__ U, co
             }
           }
         }
-        T rinv, vel[DIM], pr;
-        primitives<T, DIM>(u, ph.gamma, rinv, vel, pr);
-        ViscPrep<T, DIM> vp;
-        visc_prep<T, DIM>(u, G, ph.gamma, vp);
-        for (int j = 0; j < DIM; ++j) {
-          T Fc[NV], Fv[NV];
-          conv_flux_dir<T, DIM>(u, vel, pr, j, Fc);
-          visc_flux_dir<T, DIM>(vp, j, ph.mu, kap, Fv);
-          for (int c = 0; c < NV; ++c) sF[j][c][ql][t] = out_part(Fc[c] - Fv[c]);
-        }
+        T F[DIM][NV];
+        PHY::template volume_flux<T, DIM>(u, G, ph, F);
+        for (int j = 0; j < DIM; ++j)
+          for (int c = 0; c < NV; ++c) sF[j][c][ql][t] = out_part(F[j][c]);
       }
     }
     __syncthreads();
@@ -241,7 +229,8 @@ __global__ __launch_bounds__(256) void k_volume(const double* __restrict__ U, co
             a += wP[fq * NB] * H[hi + e] - wM[fq * NB] * H[hi + em];
           }
         }
-        if (JVP) a += shift * V[(size_t)cb * ne + e];
+        // shift times the mass form: the variables with a time derivative
+        if (JVP && c < PHY::template nmass<DIM>()) a += shift * V[(size_t)cb * ne + e];
         out[(size_t)cb * ne + e] = a;
       }
     }
@@ -250,10 +239,10 @@ __global__ __launch_bounds__(256) void k_volume(const double* __restrict__ U, co
 
 // ------------------------------------------------------------------ small kernels
 template <int DIM, int NB, int NQ1>
-__global__ void k_project(const double* __restrict__ f, double* __restrict__ w, Tables tb, int64_t ne) {
-  constexpr int NV = DIM + 2, NQ = ipow(NQ1, DIM);
+__global__ void k_project(const double* __restrict__ f, double* __restrict__ w, Tables tb, int64_t ne, int nv) {
+  constexpr int NQ = ipow(NQ1, DIM);
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (int64_t)NV * NB * ne) return;
+  if (i >= (int64_t)nv * NB * ne) return;
   const int64_t e = i % ne;
   const int cb = (int)(i / ne), c = cb / NB, b = cb % NB;
   double a = 0.0;
@@ -273,10 +262,13 @@ __global__ void k_points(double* __restrict__ xyz, Tables tb, Mesh m) {
 }
 
 // per-block maxima of |u| + c over the volume points of a grid-stride set of elements
-template <int DIM, int NB, int NQ1>
+// (incompressible: |u| + sqrt(|u|^2 + beta^2), the largest speed of the
+// artificial compressibility system of the interface flux)
+template <class PHY, int DIM, int NB, int NQ1>
 __global__ __launch_bounds__(256) void k_wave_speed(const double* __restrict__ w, double* __restrict__ partial,
                                                      Tables tb, Mesh m, Phys ph) {
-  constexpr int NV = DIM + 2, NQ = ipow(NQ1, DIM);
+  constexpr int NV = PHY::template nv<DIM>(), NQ = ipow(NQ1, DIM);
+  constexpr bool kInc = std::is_same<PHY, IncompressiblePhys>::value;
   __shared__ double red[256];
   double mx = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < (int64_t)NQ * m.ne; i += (int64_t)gridDim.x * 256) {
@@ -288,11 +280,20 @@ __global__ __launch_bounds__(256) void k_wave_speed(const double* __restrict__ w
       for (int b = 0; b < NB; ++b) a += tb.vPhi[q * NB + b] * w[((size_t)c * NB + b) * m.ne + e];
       u[c] = a;
     }
-    double rinv, vel[DIM], p;
-    primitives<double, DIM>(u, ph.gamma, rinv, vel, p);
-    double s = 0.0;
-    for (int j = 0; j < DIM; ++j) s += vel[j] * vel[j];
-    const double a = sqrt(s) + sqrt(ph.gamma * p * rinv);
+    double a;
+    if constexpr (std::is_same<PHY, DiffusionPhys>::value) {
+      a = 0.0;
+    } else if constexpr (kInc) {
+      double s = 0.0;
+      for (int j = 0; j < DIM; ++j) s += u[j] * u[j];
+      a = sqrt(s) + sqrt(s + ph.beta * ph.beta);
+    } else {
+      double rinv, vel[DIM], p;
+      primitives<double, DIM>(u, ph.gamma, rinv, vel, p);
+      double s = 0.0;
+      for (int j = 0; j < DIM; ++j) s += vel[j] * vel[j];
+      a = sqrt(s) + sqrt(ph.gamma * p * rinv);
+    }
     mx = (a > mx || a != a) ? a : mx;
   }
   red[threadIdx.x] = mx;
@@ -315,7 +316,10 @@ __global__ __launch_bounds__(256) void k_wave_speed(const double* __restrict__ w
   X(2, 3, 4, 2)         \
   X(3, 3, 10, 3)        \
   X(4, 3, 20, 4)        \
-  X(5, 3, 35, 5)
+  X(5, 3, 35, 5)        \
+  X(6, 2, 3, 3)         \
+  X(7, 2, 10, 5)        \
+  X(8, 2, 28, 8)
 
 int config_index(int dim, int nb, int nq1d) {
 #define X(id, d, nb_, nq_) \
@@ -330,15 +334,16 @@ template <int NB, bool JVP> struct VolTile {
   static constexpr int QC = 256 / TE;
 };
 
-hipError_t launch_face(int cfg, bool jvp, const double* U, const double* V, double* H, const Tables& tb,
-                       const Mesh& m, const Phys& ph, hipStream_t s) {
+template <class PHY>
+hipError_t face_dispatch(int cfg, bool jvp, const double* U, const double* V, double* H, const Tables& tb,
+                         const Mesh& m, const Phys& ph, hipStream_t s) {
 #define X(id, d, nb_, nq_)                                                                          \
   case id: {                                                                                        \
     dim3 grid((unsigned)((m.ne + 63) / 64), d);                                                     \
     if (jvp)                                                                                        \
-      k_face<d, nb_, nq_, true><<<grid, 256, 0, s>>>(U, V, H, tb, m, ph);                           \
+      k_face<PHY, d, nb_, nq_, true><<<grid, 256, 0, s>>>(U, V, H, tb, m, ph);                      \
     else                                                                                            \
-      k_face<d, nb_, nq_, false><<<grid, 256, 0, s>>>(U, V, H, tb, m, ph);                          \
+      k_face<PHY, d, nb_, nq_, false><<<grid, 256, 0, s>>>(U, V, H, tb, m, ph);                     \
     return hipGetLastError();                                                                       \
   }
   switch (cfg) { DG_CONFIGS(X) }
@@ -346,18 +351,19 @@ hipError_t launch_face(int cfg, bool jvp, const double* U, const double* V, doub
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_volume(int cfg, bool jvp, const double* U, const double* V, const double* H, double* out,
-                         double shift, const Tables& tb, const Mesh& m, const Phys& ph, hipStream_t s) {
+template <class PHY>
+hipError_t volume_dispatch(int cfg, bool jvp, const double* U, const double* V, const double* H, double* out,
+                           double shift, const Tables& tb, const Mesh& m, const Phys& ph, hipStream_t s) {
 #define X(id, d, nb_, nq_)                                                                                    \
   case id: {                                                                                                  \
     if (jvp) {                                                                                                \
       using TL = VolTile<nb_, true>;                                                                          \
       dim3 grid((unsigned)((m.ne + TL::TE - 1) / TL::TE));                                                    \
-      k_volume<d, nb_, nq_, true, TL::TE, TL::QC><<<grid, 256, 0, s>>>(U, V, H, out, shift, tb, m, ph);      \
+      k_volume<PHY, d, nb_, nq_, true, TL::TE, TL::QC><<<grid, 256, 0, s>>>(U, V, H, out, shift, tb, m, ph); \
     } else {                                                                                                  \
       using TL = VolTile<nb_, false>;                                                                         \
       dim3 grid((unsigned)((m.ne + TL::TE - 1) / TL::TE));                                                    \
-      k_volume<d, nb_, nq_, false, TL::TE, TL::QC><<<grid, 256, 0, s>>>(U, V, H, out, shift, tb, m, ph);     \
+      k_volume<PHY, d, nb_, nq_, false, TL::TE, TL::QC><<<grid, 256, 0, s>>>(U, V, H, out, shift, tb, m, ph);\
     }                                                                                                         \
     return hipGetLastError();                                                                                 \
   }
@@ -366,11 +372,28 @@ hipError_t launch_volume(int cfg, bool jvp, const double* U, const double* V, co
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_project(int cfg, const double* f, double* w, const Tables& tb, const Mesh& m, hipStream_t s) {
+hipError_t launch_face(int cfg, bool jvp, const double* U, const double* V, double* H, const Tables& tb,
+                       const Mesh& m, const Phys& ph, hipStream_t s) {
+  if (ph.model == DG_PHYS_INCOMPRESSIBLE) return face_dispatch<IncompressiblePhys>(cfg, jvp, U, V, H, tb, m, ph, s);
+  if (ph.model == DG_PHYS_DIFFUSION) return face_dispatch<DiffusionPhys>(cfg, jvp, U, V, H, tb, m, ph, s);
+  return face_dispatch<CompressiblePhys>(cfg, jvp, U, V, H, tb, m, ph, s);
+}
+
+hipError_t launch_volume(int cfg, bool jvp, const double* U, const double* V, const double* H, double* out,
+                         double shift, const Tables& tb, const Mesh& m, const Phys& ph, hipStream_t s) {
+  if (ph.model == DG_PHYS_INCOMPRESSIBLE)
+    return volume_dispatch<IncompressiblePhys>(cfg, jvp, U, V, H, out, shift, tb, m, ph, s);
+  if (ph.model == DG_PHYS_DIFFUSION)
+    return volume_dispatch<DiffusionPhys>(cfg, jvp, U, V, H, out, shift, tb, m, ph, s);
+  return volume_dispatch<CompressiblePhys>(cfg, jvp, U, V, H, out, shift, tb, m, ph, s);
+}
+
+hipError_t launch_project(int cfg, int nv, const double* f, double* w, const Tables& tb, const Mesh& m,
+                          hipStream_t s) {
 #define X(id, d, nb_, nq_)                                                          \
   case id: {                                                                        \
-    int64_t n = (int64_t)(d + 2) * nb_ * m.ne;                                      \
-    k_project<d, nb_, nq_><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(f, w, tb, m.ne); \
+    int64_t n = (int64_t)nv * nb_ * m.ne;                                           \
+    k_project<d, nb_, nq_><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(f, w, tb, m.ne, nv); \
     return hipGetLastError();                                                       \
   }
   switch (cfg) { DG_CONFIGS(X) }
@@ -394,7 +417,12 @@ hipError_t launch_wave_speed(int cfg, const double* w, double* partial, int nblo
                              const Mesh& m, const Phys& ph, hipStream_t s) {
 #define X(id, d, nb_, nq_)                                                            \
   case id: {                                                                          \
-    k_wave_speed<d, nb_, nq_><<<nblocks, 256, 0, s>>>(w, partial, tb, m, ph);         \
+    if (ph.model == DG_PHYS_INCOMPRESSIBLE)                                           \
+      k_wave_speed<IncompressiblePhys, d, nb_, nq_><<<nblocks, 256, 0, s>>>(w, partial, tb, m, ph); \
+    else if (ph.model == DG_PHYS_DIFFUSION)                                           \
+      k_wave_speed<DiffusionPhys, d, nb_, nq_><<<nblocks, 256, 0, s>>>(w, partial, tb, m, ph); \
+    else                                                                              \
+      k_wave_speed<CompressiblePhys, d, nb_, nq_><<<nblocks, 256, 0, s>>>(w, partial, tb, m, ph);   \
     return hipGetLastError();                                                         \
   }
   switch (cfg) { DG_CONFIGS(X) }

@@ -44,8 +44,10 @@ dg_status dg_rosenbrock_step(dg_context* c, const double* w, double dt, const dg
       if (k->a[si][o] != 0.0) HIPCHK(dgk::launch_axpby(n, 1.0, ws, k->a[si][o], dw + (size_t)o * n, ws, s));
     if ((st = eval_residual(c, false, ws, nullptr, 0.0, rhs, s)) != DG_OK) return st;
     HIPCHK(dgk::launch_axpby(n, -1.0, rhs, 0.0, rhs, rhs, s));
+    // (the mass form: only the variables with a time derivative)
     for (int o = 0; o < si; ++o)
-      if (k->c[si][o] != 0.0) HIPCHK(dgk::launch_axpby(n, 1.0, rhs, -k->c[si][o] / dt, dw + (size_t)o * n, rhs, s));
+      if (k->c[si][o] != 0.0)
+        HIPCHK(dgk::launch_axpby(c->mass_len, 1.0, rhs, -k->c[si][o] / dt, dw + (size_t)o * n, rhs, s));
     HIPCHK(dgk::launch_fill(dws, n, 0.0, s));
     dg_solve_stats sst{};
     st = dg_fgmres_solve(c, w, shift, rhs, dws, opts, &sst, stream);

@@ -53,12 +53,12 @@ __global__ void k_axpy_dev(int64_t n, const double* __restrict__ x, const double
 }
 
 // out = shift*v + (rp - r0) * dinv[0]
-__global__ void k_fd_combine(int64_t n, const double* __restrict__ rp, const double* __restrict__ r0,
+__global__ void k_fd_combine(int64_t n, int64_t nm, const double* __restrict__ rp, const double* __restrict__ r0,
                              const double* __restrict__ dinv, const double* __restrict__ v, double shift,
                              double* __restrict__ out) {
   const double s = dinv[0];
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    out[i] = shift * v[i] + (s == 0.0 ? 0.0 : (rp[i] - r0[i]) * s);
+    out[i] = (i < nm ? shift * v[i] : 0.0) + (s == 0.0 ? 0.0 : (rp[i] - r0[i]) * s);
 }
 
 // y = x / dnorm[0] (0 if the norm is 0)
@@ -217,9 +217,9 @@ hipError_t launch_axpy_dev(int64_t n, const double* x, const double* dscale, dou
   k_axpy_dev<<<grid_for(n), 256, 0, s>>>(n, x, dscale, c, y, z);
   return hipGetLastError();
 }
-hipError_t launch_fd_combine(int64_t n, const double* rp, const double* r0, const double* dinv, const double* v,
-                             double shift, double* out, hipStream_t s) {
-  k_fd_combine<<<grid_for(n), 256, 0, s>>>(n, rp, r0, dinv, v, shift, out);
+hipError_t launch_fd_combine(int64_t n, int64_t nm, const double* rp, const double* r0, const double* dinv,
+                             const double* v, double shift, double* out, hipStream_t s) {
+  k_fd_combine<<<grid_for(n), 256, 0, s>>>(n, nm, rp, r0, dinv, v, shift, out);
   return hipGetLastError();
 }
 hipError_t launch_scale_dev(int64_t n, const double* x, const double* dnorm, double* y, hipStream_t s) {

@@ -145,3 +145,39 @@ class TrigSum:
     def hess(self, x):  # [..., n, d, d]
         s = np.sin(self._arg(x))
         return -np.einsum("...m,cm,md,me->...cde", s, self.b, self.k, self.k)
+
+
+class IncompressibleStandIn:
+    """Velocity and pressure (u_1..u_d, p) for the incompressible equations.
+
+    3D: the solenoidal velocity of TaylorGreenStandIn (max |u| = V0);
+    2D: u = curl of the stream function psi = sum_m a_m sin(k_m . x + phi_m)
+    (k_m integer multiples of 2 pi / L, a_m ~ N(0,1)), scaled to max |u| = V0
+    on a sample lattice; both divergence-free.  p = p0 + amp * cos(k_p . x +
+    phi_p) with a |k|_inf = 2 mode.
+    """
+
+    def __init__(self, dim, seed=7, L=1.0, V0=1.0, p0=0.5, amp=0.05):
+        rng = np.random.default_rng(seed)
+        self.dim, self.p0, self.amp = int(dim), p0, amp
+        if self.dim == 3:
+            self.tg = TaylorGreenStandIn(seed=seed, L=L, V0=V0)
+        else:
+            cands = np.array([(a, b) for a in (-1, 0, 1, 2) for b in (-1, 0, 1, 2) if (a, b) != (0, 0)], float)
+            self.k2 = cands[rng.choice(len(cands), 4, replace=False)] * (2 * np.pi / L)
+            self.a2 = rng.standard_normal(4)
+            self.ph2 = rng.uniform(0, 2 * np.pi, 4)
+            s = (np.arange(64) + 0.5) * (L / 64)
+            X = np.stack(np.meshgrid(s, s, indexing="ij"), axis=-1).reshape(-1, 2)
+            self.a2 *= V0 / np.sqrt(np.max(np.sum(self._vel2(X) ** 2, axis=-1)))
+        kp = np.array([2, 1, -2][:self.dim], float) * (2 * np.pi / L)
+        self.kp, self.php = kp, rng.uniform(0, 2 * np.pi)
+
+    def _vel2(self, x):
+        c = np.cos(x @ self.k2.T + self.ph2) * self.a2       # [..., m]
+        return np.stack([c @ self.k2[:, 1], -(c @ self.k2[:, 0])], axis=-1)
+
+    def __call__(self, x):
+        vel = self.tg._vel_unscaled(x) if self.dim == 3 else self._vel2(x)
+        p = self.p0 + self.amp * np.cos(x @ self.kp + self.php)
+        return np.concatenate([vel, p[..., None]], axis=-1)

@@ -11,7 +11,7 @@ cfg5  cfg2 discretisation, learned element preconditioner workload, backward
 """
 import numpy as np
 
-from .fields import FreeStreamPlusModes, TaylorGreenStandIn
+from .fields import FreeStreamPlusModes, TaylorGreenStandIn, IncompressibleStandIn
 from .lattice import lattice_mesh
 
 GAMMA = 1.4

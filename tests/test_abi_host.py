@@ -102,3 +102,15 @@ def test_null_arguments():
     assert lib.dg_mg_level_apply(None, 0, None, None, None) == -1
     assert lib.dg_mg_update_fine(None, None, 0.0, 1, None) == -1
     assert lib.dg_rosenbrock_step(None, None, 0.1, None, None, None, None, None) == -1
+
+
+def test_create_checks_the_physics_model_on_the_host():
+    """Unknown physics and the incompressible equations on a curved mesh are
+    refused before any device work."""
+    prm = _prm(order=2, nq=3)
+    prm.physics = 7
+    st, msg = _create(prm, synth.lattice_mesh((2, 2, 2)))
+    assert st == -1 and "physics" in msg
+    prm.physics = L.DG_PHYS_INCOMPRESSIBLE
+    st, msg = _create(prm, synth.lattice_mesh((2, 2, 2), perturb=0.1, seed=1))
+    assert st == -1 and "lattice" in msg
