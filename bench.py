@@ -97,59 +97,72 @@ def measured_traffic(kernel):
     return None
 
 
-def cpu_baseline(sample_elems=1024):
-    """Oracle Jv (complex step, FP64, numpy) on a bounded sample of the P3 32^3 workload."""
+_CPU_STATE = {}
+
+
+def _oracle_rows(elems):
+    """Exact Jv rows of the given elements with the oracle prepared in
+    _CPU_STATE (worker processes inherit it through fork); returns seconds."""
+    o, U, V = _CPU_STATE["o"], _CPU_STATE["U"], _CPU_STATE["V"]
+    t = time.perf_counter()
+    J = o.jvp(U, V, elems=elems)
+    assert np.all(np.isfinite(J))
+    return time.perf_counter() - t
+
+
+def cpu_baseline(sample_elems=8192, reps=3):
+    """Oracle Jv (complex step, FP64, numpy) on a bounded sample of the P3 32^3
+    workload, timed on the host before the GPU is initialised: single-threaded
+    (BLAS pools limited to one thread) on an eighth of the sample, and on all
+    host cores as a pool of forked worker processes, one BLAS thread each,
+    over disjoint slices of the sample; median of reps runs each."""
+    import multiprocessing as mp
     import synth
     from oracle import DGOracle, NavierStokes
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
-    except Exception:
-        cores = 1
+    from threadpoolctl import threadpool_limits
     cfg, mesh, fld = synth.preset("cfg2")
     o = DGOracle(mesh, cfg["order"], cfg["space"], cfg["nq1d"], NavierStokes(3, mu=cfg["mu"], flux="roe"))
-    rng = np.random.default_rng(0)
-    sample = np.sort(rng.choice(o.ne, sample_elems, replace=False))
-    # the sample's rows need the sample and its face neighbours
-    need = np.unique(np.concatenate([sample, o.nbr[sample].reshape(-1)]))
-    U = np.zeros((o.ne, o.nvar, o.nb))
-    U[need] = o.project(fld, elems=need)
-    V = np.zeros_like(U)
-    V[need] = np.random.default_rng(866).standard_normal((len(need), o.nvar, o.nb))
-    c0 = time.process_time()
-    t0 = time.perf_counter()
-    J = o.jvp(U, V, elems=sample)
-    t = time.perf_counter() - t0
-    # threads the oracle actually kept busy: process CPU time over wall time
-    busy = (time.process_time() - c0) / t
-    dofs = sample_elems * o.nvar * o.nb
-    assert np.all(np.isfinite(J))
-    single = None
-    try:  # the same oracle restricted to one thread, on an eighth of the sample
-        from threadpoolctl import threadpool_limits
+    # a slab of whole lattice planes (every element row costs the same; the
+    # slab keeps the untimed projection of the sample's neighbours small)
+    sample = np.arange(min(sample_elems, o.ne))
+    try:
+        visible = len(os.sched_getaffinity(0))
+    except AttributeError:
+        visible = os.cpu_count() or 1
+    workers = max(1, min(16, visible))
+    with threadpool_limits(1):
+        # the sample's rows need the sample and its face neighbours
+        need = np.unique(np.concatenate([sample, o.nbr[sample].reshape(-1)]))
+        U = np.zeros((o.ne, o.nvar, o.nb))
+        U[need] = o.project(fld, elems=need)
+        V = np.zeros_like(U)
+        V[need] = np.random.default_rng(866).standard_normal((len(need), o.nvar, o.nb))
+        _CPU_STATE.update(o=o, U=U, V=V)
         sub = sample[: max(1, sample_elems // 8)]
-        with threadpool_limits(1):
-            t1 = time.perf_counter()
-            o.jvp(U, V, elems=sub)
-            single = len(sub) * o.nvar * o.nb / (time.perf_counter() - t1)
-    except Exception:
-        pass
+        single = sorted(len(sub) * o.nvar * o.nb / _oracle_rows(sub) for _ in range(reps))[reps // 2]
+        chunks = np.array_split(sample, workers)
+        ctx = mp.get_context("fork")
+        walls = []
+        with ctx.Pool(workers) as pool:
+            for _ in range(reps):
+                t = time.perf_counter()
+                pool.map(_oracle_rows, chunks)
+                walls.append(time.perf_counter() - t)
+    wall = sorted(walls)[reps // 2]
+    dofs = sample_elems * o.nvar * o.nb
     model = "unknown"
     try:
         with open("/proc/cpuinfo") as fh:
             model = next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), model)
     except OSError:
         pass
-    try:
-        visible = len(os.sched_getaffinity(0))
-    except AttributeError:
-        visible = os.cpu_count()
-    return {"value": dofs / t, "unit": "DOFs/s", "cores": max(1, int(round(busy))), "kind": "oracle",
-            "threads_available": int(cores), "cpu_busy_threads": round(busy, 2),
-            "sample": f"exact Jv rows of {sample_elems} random elements of the P3 32^3 workload "
-                      f"({dofs} DOFs), complex-step numpy oracle, {t:.2f} s; single_thread_value: the first eighth of "
-                      f"those elements with the BLAS/OpenMP pools limited to one thread",
-            "host": {"cpu_model": model, "cpus_visible": visible}, "single_thread_value": single}
+    return {"value": dofs / wall, "unit": "DOFs/s", "cores": workers, "kind": "oracle",
+            "sample": f"exact Jv rows of the first {sample_elems} elements (whole z-planes) of the P3 32^3 workload "
+                      f"({dofs} DOFs), "
+                      f"complex-step numpy oracle, {workers} forked worker processes with one BLAS thread each on "
+                      f"disjoint slices, median of {reps} runs ({wall:.2f} s); single_thread_value: the first "
+                      f"eighth of those elements in one thread, median of {reps}",
+            "single_thread_value": single, "host": {"cpu_model": model, "cpus_visible": visible}}
 
 
 PHASES = ("grad_jvp", "face_jvp", "vol_jvp", "grad_jvp_f32", "face_jvp_f32", "vol_jvp_f32", "grad_jvp_bf16",
@@ -423,6 +436,11 @@ def poisson_assessment(sizes=(32, 64, 128), shift=1.0, rtol=1e-8):
                         "V-cycle 6/3/1, smoothing 1/1/40 (coarsest: GMRES[block ILU(0)])", "rows": rows}
 
 
+def _progress(msg, t0=[time.perf_counter()]):
+    """One line per finished leg on stderr (the JSON result goes to stdout)."""
+    print(f"bench: {msg} ({time.perf_counter() - t0[0]:.1f} s)", file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -439,6 +457,12 @@ def main():
         print(f"bench.py: --gpus {args.gpus} is not supported: the library runs on one GPU "
               "(elements would shard into slabs with one halo exchange per Jv; not built)", file=sys.stderr)
         sys.exit(2)
+
+    # the oracle's CPU baseline runs first, before anything touches the GPU
+    # (its worker processes are forked)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(args.cpu_sample)
+    if cpu is not None:
+        _progress("oracle CPU baseline")
 
     import torch
     import synth
@@ -499,6 +523,7 @@ def main():
     jv_bf16 = {"value": g.ndof / (wall16 / args.steps), "unit": "DOFs/s", "ms_per_step": wall16 * 1e3 / args.steps,
                "rel_diff_vs_fp64": float((out32 - out).norm() / out.norm())}
     del out32
+    _progress("Jv legs (FP64, FP32, BF16)")
     ms_per_step = wall * 1e3 / args.steps
     value = g.ndof / (wall / args.steps)
 
@@ -544,32 +569,47 @@ def main():
            "roofline": roofline, "jv_fp32": jv_fp32, "jv_bf16": jv_bf16}
     if not args.no_solve:
         res["time_to_tol"] = time_to_tolerance("fp64")
+        _progress("time_to_tol")
         res["time_to_tol_fp32_blocks"] = time_to_tolerance("fp32")
+        _progress("time_to_tol_fp32_blocks")
         res["time_to_tol_bf16_blocks"] = time_to_tolerance("bf16")
+        _progress("time_to_tol_bf16_blocks")
         res["time_to_tol_pmg"] = time_to_tolerance("fp64", precond="mg")
+        _progress("time_to_tol_pmg")
         res["time_to_tol_pmg_fp32_smoothing"] = time_to_tolerance("fp32", precond="mg", fine_precision="fp32")
+        _progress("time_to_tol_pmg_fp32_smoothing")
         res["time_to_tol_pmg_bf16_factors"] = time_to_tolerance("bf16", precond="mg", fine_precision="fp32")
+        _progress("time_to_tol_pmg_bf16_factors")
         res["time_to_tol_pmg_bf16_operator"] = time_to_tolerance("bf16", precond="mg", fine_precision="bf16")
+        _progress("time_to_tol_pmg_bf16_operator")
         res["time_to_tol_pmg_fp32_rescaled"] = time_to_tolerance("fp32", precond="mg", fine_precision="fp32",
                                                                  rescale=True)
         res["time_to_tol_pmg_fp32_coarse_ilu"] = time_to_tolerance("fp32", precond="mg", fine_precision="fp32",
                                                                    coarse_ilu=True)
         res["time_to_tol_pmg_curved"] = time_to_tolerance("fp32", precond="mg", fine_precision="fp64", preset="cfg4")
+        _progress("time_to_tol_pmg_curved")
         res["time_to_tol_pmg_curved_fp32_smoothing"] = time_to_tolerance("fp32", precond="mg", fine_precision="fp32",
                                                                          preset="cfg4")
         res["time_to_tol_pmg_curved_bf16_factors"] = time_to_tolerance("bf16", precond="mg", fine_precision="fp32",
                                                                        preset="cfg4")
         res["time_to_tol_bj_curved"] = time_to_tolerance("fp32", preset="cfg4")
+        _progress("time_to_tol_bj_curved")
         res["trajectory_pmg"] = mg_trajectory(4, lag=1)
+        _progress("trajectory_pmg")
         res["trajectory_pmg_lag3"] = mg_trajectory(4, lag=3)
+        _progress("trajectory_pmg_lag3")
         res["trajectory_pmg_full_cycle"] = mg_trajectory(4, lag=1, cycle="full")
+        _progress("trajectory_pmg_full_cycle")
         res["trajectory_pmg_ros2"] = mg_trajectory(4, lag=1, scheme="ros2")
+        _progress("trajectory_pmg_ros2")
     if not args.no_learned:
         res["learned_precond"] = learned_preconditioner()
+        _progress("learned_precond")
     if not args.no_solve:
         res["poisson_pmg"] = poisson_assessment()
-    if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(args.cpu_sample)
+        _progress("poisson_pmg")
+    if cpu is not None:
+        res["cpu_baseline"] = cpu
     print(json.dumps(res), flush=True)
 
 
