@@ -60,7 +60,7 @@ def jv_kernel_flops(ne, nb, nq, nfq, d, pointwise=True):
     return out
 
 
-KERNEL_SOURCES = ("dg_mfma.hip", "dg_device.h", "host_setup.cpp", "dg_internal.h")
+KERNEL_SOURCES = ("dg_mfma.h", "dg_mfma_f64.hip", "dg_device.h", "host_setup.cpp", "dg_internal.h")
 KERNELS = ("grad_jvp", "face_jvp", "vol_jvp")
 
 
@@ -266,6 +266,59 @@ def time_to_tolerance(storage="fp64", precond="bj", fine_precision="fp64", resca
             "jv_ms": jv_ms,
             "seconds": t2 - t0, "setup_s": t1 - t0, "solve_s": t2 - t1, "iters": st["iters"],
             "converged": bool(st["converged"]), "rel_res_true": st["rel_res_true"], "dt": dt, **extra}
+
+
+def vcycle_tuning(storage="fp32", fine_precision="fp32", n_cycles=20):
+    """The P4/P2/P1 V-cycle of the P4 24^3 backward-Euler system (the fastest
+    solve configuration: FP32 fine operator and factors) with the built-in
+    launch shapes and with the autotuned ones: ms per captured cycle, set-up
+    seconds (the first tuned set-up of a shape includes its timing runs; later
+    ones reuse the process-wide choices), the FGMRES solve, and the chosen
+    shapes."""
+    import torch
+    import synth
+    from paper_1809_00866_amd import DG
+    cfg, mesh, fld = synth.preset("cfg3")
+    out = {"workload": "P4 24^3 hexes, CFL 100 backward-Euler operator, V-cycle P4/P2/P1 GMRES[EWBJ] 8/8/40, "
+                       f"{fine_precision} fine operator, {storage} factors"}
+    for mode in ("fixed", "auto"):
+        g = DG(mesh, cfg["order"], basis=cfg["space"], nq1d=cfg["nq1d"], flux="roe", mu=cfg["mu"])
+        g.set_tuning(mode)
+        w = g.project_field(fld)
+        smax = g.max_wave_speed(w)
+        dt = cfg["cfl"] * float(np.min(mesh["h"])) / ((2 * cfg["order"] + 1) * smax)
+        shift = 1.0 / dt
+        b = -g.residual(w)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if mode == "auto":
+            g.autotune(w)
+        g.mg_setup(w, shift, cfg["mg_orders"], cfg["mg_smooth"], storage=storage, use_graph=True,
+                   fine_precision=fine_precision)
+        torch.cuda.synchronize()
+        setup_s = time.perf_counter() - t0
+        z = g.empty()
+        for _ in range(2):
+            g.mg_apply(b, out=z)
+        torch.cuda.synchronize()
+        best = 1e30
+        for _ in range(3):
+            tv = time.perf_counter()
+            for _ in range(n_cycles):
+                g.mg_apply(b, out=z)
+            torch.cuda.synchronize()
+            best = min(best, (time.perf_counter() - tv) * 1e3 / n_cycles)
+        t1 = time.perf_counter()
+        x, st = g.fgmres(w, shift, b, restart=cfg["restart"], max_iter=3000, rtol=cfg["rtol"], precond="mg")
+        torch.cuda.synchronize()
+        out[mode] = {"vcycle_ms": best, "setup_s": setup_s, "solve_s": time.perf_counter() - t1,
+                     "iters": st["iters"], "converged": bool(st["converged"]), "rel_res_true": st["rel_res_true"],
+                     "shapes": g.tuning_report().splitlines()}
+        g.close()
+        del w, b, z, x
+        torch.cuda.empty_cache()
+    out["vcycle_speedup"] = out["fixed"]["vcycle_ms"] / out["auto"]["vcycle_ms"]
+    return out
 
 
 def mg_trajectory(n_steps=4, lag=1, cycle="v", scheme="be"):
@@ -474,6 +527,19 @@ def main():
     w = g.project_field(fld)
     v = torch.tensor(synth.random_vector(g.ndof, cfg["v_seed"]), device="cuda")
     out = g.empty()
+    # the built-in launch shapes first, then the autotuned ones (the metric)
+    g.set_tuning("fixed")
+    for _ in range(args.warmup):
+        g.jvp(w, v, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g.jvp(w, v, out=out)
+    torch.cuda.synchronize()
+    wall_fixed = time.perf_counter() - t0
+    g.set_tuning("auto")
+    g.autotune(w)
+    shapes = g.tuning_report().splitlines()
     for _ in range(args.warmup):
         g.jvp(w, v, out=out)
     torch.cuda.synchronize()
@@ -549,6 +615,7 @@ def main():
                 # instrumented pointwise value-and-tangent flops)
                 "whole_jv": {"flop_per_dof": per_dof, "achieved": value * per_dof / 1e12, "peak": PEAK_FP64,
                              "unit": "TFLOP/s", "frac": value * per_dof / 1e12 / PEAK_FP64}}
+    g_ndof = g.ndof
     g.close()
     del w, v, out
     if args.calib_copy:
@@ -566,7 +633,10 @@ def main():
            "config": {"workload": "exact Jv, 3D compressible NS, P3 (Nb=20), 32^3 periodic hexes, 4^3/4^2 Gauss, "
                                   "Roe + BR2, Taylor-Green-like field Mach 0.1 Re 1600",
                       "n_elem": int(32 ** 3), "ndof": int(32 ** 3 * 100), "dofs_per_variable": int(32 ** 3 * 20)},
-           "roofline": roofline, "jv_fp32": jv_fp32, "jv_bf16": jv_bf16}
+           "roofline": roofline, "jv_fp32": jv_fp32, "jv_bf16": jv_bf16,
+           "launch_shapes": shapes,
+           "jv_fixed_shapes": {"ms_per_step": wall_fixed * 1e3 / args.steps,
+                               "value": g_ndof / (wall_fixed / args.steps), "unit": "DOFs/s"}}
     if not args.no_solve:
         res["time_to_tol"] = time_to_tolerance("fp64")
         _progress("time_to_tol")
@@ -578,6 +648,8 @@ def main():
         _progress("time_to_tol_pmg")
         res["time_to_tol_pmg_fp32_smoothing"] = time_to_tolerance("fp32", precond="mg", fine_precision="fp32")
         _progress("time_to_tol_pmg_fp32_smoothing")
+        res["vcycle_tuning"] = vcycle_tuning()
+        _progress("vcycle_tuning")
         res["time_to_tol_pmg_bf16_factors"] = time_to_tolerance("bf16", precond="mg", fine_precision="fp32")
         _progress("time_to_tol_pmg_bf16_factors")
         res["time_to_tol_pmg_bf16_operator"] = time_to_tolerance("bf16", precond="mg", fine_precision="bf16")

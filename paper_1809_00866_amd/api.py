@@ -142,6 +142,41 @@ class DG:
                 "dg_jvp_noalloc")
         return out
 
+    def set_tuning(self, mode):
+        """"auto" (time candidate launch shapes at setup, the default) or "fixed"
+        (the built-in shapes, no timing)."""
+        m = {"fixed": L.DG_TUNE_FIXED, "auto": L.DG_TUNE_AUTO}[mode]
+        L.check(self.lib.dg_set_tuning(self.ctx, m), "dg_set_tuning")
+
+    def autotune(self, w):
+        """Time and select the fine operator's launch shapes at state w (and the
+        block apply shape when block factors exist)."""
+        self._vec(w, "w")
+        L.check(self.lib.dg_autotune(self.ctx, _ptr(w), _stream()), "dg_autotune")
+
+    def tuning_report(self):
+        """The context's launch shapes, one line per kernel family."""
+        buf = ctypes.create_string_buffer(8192)
+        L.check(self.lib.dg_tuning_report(self.ctx, buf, len(buf)), "dg_tuning_report")
+        return buf.value.decode()
+
+    def set_fine_occupancy(self, precision, jvp, face_occ, volume_occ):
+        """Pin the waves per SIMD (1, 2; 0 = default) of the MFMA face and volume
+        kernels of the operator of `precision`, residual (jvp False) or Jv."""
+        L.check(self.lib.dg_set_fine_occupancy(self.ctx, _STORAGE[precision], int(bool(jvp)), int(face_occ),
+                                               int(volume_occ)), "dg_set_fine_occupancy")
+
+    def set_apply_shape(self, level, kind, threads=0, epw=0):
+        """Pin the block-inverse apply shape of level 0 (fine block Jacobi) or a
+        coarse level: kind "default", "row" (threads 64) or "vec"."""
+        k = {"default": 0, "row": 1, "vec": 2}[kind]
+        L.check(self.lib.dg_set_apply_shape(self.ctx, int(level), k, int(threads), int(epw)), "dg_set_apply_shape")
+
+    def set_bsr_shape(self, level, workgroup, rows_per_thread, column_slices):
+        """Pin coarse level `level`'s block-sparse apply shape."""
+        L.check(self.lib.dg_set_bsr_shape(self.ctx, int(level), int(workgroup), int(rows_per_thread),
+                                          int(column_slices)), "dg_set_bsr_shape")
+
     def block_setup(self, w, shift, storage="fp64"):
         self._vec(w, "w")
         L.check(self.lib.dg_block_precond_setup(self.ctx, _ptr(w), float(shift), _STORAGE[storage], _stream()),

@@ -52,11 +52,12 @@ dg_status eval_residual(dg_context* c, bool jvp, const double* w, const double* 
     }
     {
       ProfScope ps(c, jvp ? "face_jvp" : "face_res", s);
-      HIPCHK(dgk::launch_face_mfma(c->cfg, jvp, w, v, c->d_H, c->mt, c->mesh, c->ph, s));
+      HIPCHK(dgk::launch_face_mfma(c->cfg, jvp, w, v, c->d_H, c->mt, c->mesh, c->ph, c->occ[DG_FP64][jvp][0], s));
     }
     {
       ProfScope ps(c, jvp ? "vol_jvp" : "vol_res", s);
-      HIPCHK(dgk::launch_volume_mfma(c->cfg, jvp, w, v, c->d_G, c->d_H, out, shift, c->mt, c->mesh, c->ph, s));
+      HIPCHK(dgk::launch_volume_mfma(c->cfg, jvp, w, v, c->d_G, c->d_H, out, shift, c->mt, c->mesh, c->ph,
+                                     c->occ[DG_FP64][jvp][1], s));
     }
     return DG_OK;
   }
@@ -96,11 +97,12 @@ dg_status eval_residual_f32(dg_context* c, bool jvp, const double* w, const doub
   }
   {
     ProfScope ps(c, jvp ? "face_jvp_f32" : "face_res_f32", s);
-    HIPCHK(dgk::launch_face_mfma_f32(c->cfg, jvp, w, v, c->d_Hf, c->mtf, c->mesh, c->ph, s));
+    HIPCHK(dgk::launch_face_mfma_f32(c->cfg, jvp, w, v, c->d_Hf, c->mtf, c->mesh, c->ph, c->occ[DG_FP32][jvp][0], s));
   }
   {
     ProfScope ps(c, jvp ? "vol_jvp_f32" : "vol_res_f32", s);
-    HIPCHK(dgk::launch_volume_mfma_f32(c->cfg, jvp, w, v, c->d_Gf, c->d_Hf, out, shift, c->mtf, c->mesh, c->ph, s));
+    HIPCHK(dgk::launch_volume_mfma_f32(c->cfg, jvp, w, v, c->d_Gf, c->d_Hf, out, shift, c->mtf, c->mesh, c->ph,
+                                       c->occ[DG_FP32][jvp][1], s));
   }
   return DG_OK;
 }
@@ -113,11 +115,12 @@ dg_status eval_residual_bf16(dg_context* c, bool jvp, const double* w, const dou
   }
   {
     ProfScope ps(c, jvp ? "face_jvp_bf16" : "face_res_bf16", s);
-    HIPCHK(dgk::launch_face_mfma_bf16(c->cfg, jvp, w, v, c->d_Hf, c->mtf, c->mesh, c->ph, s));
+    HIPCHK(dgk::launch_face_mfma_bf16(c->cfg, jvp, w, v, c->d_Hf, c->mtf, c->mesh, c->ph, c->occ[DG_BF16][jvp][0], s));
   }
   {
     ProfScope ps(c, jvp ? "vol_jvp_bf16" : "vol_res_bf16", s);
-    HIPCHK(dgk::launch_volume_mfma_bf16(c->cfg, jvp, w, v, c->d_Gf, c->d_Hf, out, shift, c->mtf, c->mesh, c->ph, s));
+    HIPCHK(dgk::launch_volume_mfma_bf16(c->cfg, jvp, w, v, c->d_Gf, c->d_Hf, out, shift, c->mtf, c->mesh, c->ph,
+                                        c->occ[DG_BF16][jvp][1], s));
   }
   return DG_OK;
 }
@@ -159,14 +162,16 @@ dg_status eval_stab(dg_context* c, bool f32, const double* w, const double* v, d
     if (!c->use_mfma || !c->d_mtab_f || !c->d_Hf || !c->d_Gf)
       return fail(DG_ERR_ARG, "the reduced-precision operator needs a 3D P2-P4 configuration with MFMA kernels");
     HIPCHK(dgk::launch_grad_mfma_f32(c->cfg, true, w, z, c->d_Gf, c->mtf, c->mesh, s));
-    HIPCHK(dgk::launch_face_mfma_f32(c->cfg, true, w, v, c->d_Hf, c->mtf, c->mesh, ph, s));
-    HIPCHK(dgk::launch_volume_mfma_f32(c->cfg, true, w, z, c->d_Gf, c->d_Hf, out, 0.0, c->mtf, c->mesh, c->ph, s));
+    HIPCHK(dgk::launch_face_mfma_f32(c->cfg, true, w, v, c->d_Hf, c->mtf, c->mesh, ph, c->occ[DG_FP32][1][0], s));
+    HIPCHK(dgk::launch_volume_mfma_f32(c->cfg, true, w, z, c->d_Gf, c->d_Hf, out, 0.0, c->mtf, c->mesh, c->ph,
+                                       c->occ[DG_FP32][1][1], s));
     return DG_OK;
   }
   if (c->use_mfma) {
     HIPCHK(dgk::launch_grad_mfma(c->cfg, true, w, z, c->d_G, c->mt, c->mesh, s));
-    HIPCHK(dgk::launch_face_mfma(c->cfg, true, w, v, c->d_H, c->mt, c->mesh, ph, s));
-    HIPCHK(dgk::launch_volume_mfma(c->cfg, true, w, z, c->d_G, c->d_H, out, 0.0, c->mt, c->mesh, c->ph, s));
+    HIPCHK(dgk::launch_face_mfma(c->cfg, true, w, v, c->d_H, c->mt, c->mesh, ph, c->occ[DG_FP64][1][0], s));
+    HIPCHK(dgk::launch_volume_mfma(c->cfg, true, w, z, c->d_G, c->d_H, out, 0.0, c->mt, c->mesh, c->ph,
+                                   c->occ[DG_FP64][1][1], s));
     return DG_OK;
   }
   HIPCHK(dgk::launch_face(c->cfg, true, w, v, c->d_H, c->tb, c->mesh, ph, s));
@@ -646,6 +651,7 @@ dg_status block_probe_invert(dg_context* c, const double* w, double shift, int s
   const int m = c->nv * c->nb, ld = dgk::block_ld(m);
   dg_status st;
   if (!has_prec(c, probe_prec)) return fail(DG_ERR_ARG, "no operator of the probing precision");
+  if ((st = tune_fine(c, probe_prec, w, s)) != DG_OK) return st;
   {
     ProfScope ps(c, "block_probe", s);
     for (int col = 0; col < c->ncolor; ++col)
@@ -667,6 +673,7 @@ dg_status block_probe_invert(dg_context* c, const double* w, double shift, int s
   HIPCHK(hipStreamSynchronize(s));
   if (bad) return fail(DG_ERR_SINGULAR_BLOCK, "a diagonal block has a zero or non-finite pivot");
   c->blk_storage = storage;
+  if ((st = tune_apply(c, storage, c->d_Dinv, m, &c->blk_shape, s)) != DG_OK) return st;
   c->blk_ready = true;
   return DG_OK;
 }
@@ -692,7 +699,7 @@ dg_status dg_block_precond_apply(dg_context* c, const double* r, double* z, void
   if (!c->blk_ready) return fail(DG_ERR_STATE, "dg_block_precond_setup has not succeeded");
   hipStream_t s = (hipStream_t)stream;
   ProfScope ps(c, "block_apply", s);
-  HIPCHK(dgk::launch_block_apply(c->blk_storage, c->d_Dinv, c->nv * c->nb, c->ne, r, z, s));
+  HIPCHK(dgk::launch_block_apply(c->blk_storage, c->d_Dinv, c->nv * c->nb, c->ne, r, z, s, &c->blk_shape));
   return DG_OK;
 }
 
@@ -759,7 +766,7 @@ dg_status dg_fgmres_solve(dg_context* c, const double* w, double shift, const do
     if (prec == DG_PREC_MLP) return mlp_apply(c, w, v, z, s);
     if (prec == DG_PREC_BJ) {
       ProfScope ps(c, "block_apply", s);
-      HIPCHK(dgk::launch_block_apply(c->blk_storage, c->d_Dinv, c->nv * c->nb, c->ne, v, z, s));
+      HIPCHK(dgk::launch_block_apply(c->blk_storage, c->d_Dinv, c->nv * c->nb, c->ne, v, z, s, &c->blk_shape));
       return DG_OK;
     }
     HIPCHK(dgk::launch_axpby(n, 1.0, v, 0.0, v, z, s));

@@ -242,11 +242,11 @@ __global__ __launch_bounds__(256, 1) void k_invert(const double* __restrict__ D,
   if (tid == 0 && bad) info[0] = 1;
 }
 
-// z_K = Dinv_K r_K.  16-byte loads along the (padded) columns: a thread owns
-// VEC consecutive rows of one column set (columns cs, cs + C, ...), the C
-// column sets' partial sums are added in a fixed order.  ACC is the
+// z_K = Dinv_K r_K.  16-byte loads along the (padded) columns: T threads per
+// element, a thread owns VEC consecutive rows of one column set (columns cs,
+// cs + C, ..., C = T / (ld / VEC) column sets), the C column sets' partial
+// sums are added in a fixed order; EPW elements per workgroup.  ACC is the
 // accumulation type (FP64 for FP64 factors, FP32 for FP32/BF16).
-constexpr int kApplyThreads = 256;
 template <class S> struct Vec16;
 template <> struct Vec16<double> {
   static constexpr int n = 2;
@@ -270,20 +270,22 @@ template <> struct Vec16<bf16_t> {
   }
 };
 
-template <class S, class ACC>
-__global__ __launch_bounds__(kApplyThreads) void k_apply(const S* __restrict__ Dinv, int m, int ld, int64_t ne,
-                                                         const double* __restrict__ r, double* __restrict__ z) {
+template <class S, class ACC, int T, int EPW>
+__global__ __launch_bounds__(T * EPW) void k_apply(const S* __restrict__ Dinv, int m, int ld, int64_t ne,
+                                                   const double* __restrict__ r, double* __restrict__ z) {
   using V = Vec16<S>;
   constexpr int VEC = V::n;
   extern __shared__ __align__(16) unsigned char smem[];
-  double* rk = reinterpret_cast<double*>(smem);  // [m]
-  double* part = rk + m;                         // [C][ld]
-  const int G = ld / VEC, C = kApplyThreads / G;
-  const int64_t e = blockIdx.x;
-  for (int j = threadIdx.x; j < m; j += kApplyThreads) rk[j] = r[(size_t)j * ne + e];
+  const int G = ld / VEC, C = T / G;
+  const int sub = threadIdx.x / T, t = threadIdx.x - sub * T;
+  const int64_t e = (int64_t)blockIdx.x * EPW + sub;
+  const bool live = e < ne;
+  double* rk = reinterpret_cast<double*>(smem) + (size_t)sub * (m + C * ld);  // [m]
+  double* part = rk + m;                                                       // [C][ld]
+  if (live)
+    for (int j = t; j < m; j += T) rk[j] = r[(size_t)j * ne + e];
   __syncthreads();
-  const int t = threadIdx.x;
-  if (t < G * C) {
+  if (live && t < G * C) {
     const int rg = t % G, cs = t / G;
     ACC acc[VEC];
 #pragma unroll
@@ -301,22 +303,23 @@ __global__ __launch_bounds__(kApplyThreads) void k_apply(const S* __restrict__ D
     for (int q = 0; q < VEC; ++q) part[cs * ld + rg * VEC + q] = (double)acc[q];
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < m; i += kApplyThreads) {
-    double s = 0.0;
-    for (int cs = 0; cs < C; ++cs) s += part[cs * ld + i];
-    z[(size_t)i * ne + e] = s;
-  }
+  if (live)
+    for (int i = t; i < m; i += T) {
+      double s = 0.0;
+      for (int cs = 0; cs < C; ++cs) s += part[cs * ld + i];
+      z[(size_t)i * ne + e] = s;
+    }
 }
 
-// Small blocks (m <= 64): one wave per element (four per workgroup), lane i
+// Small blocks (m <= 64): one wave per element (WPG per workgroup), lane i
 // owns row i and walks the columns (column-major storage: consecutive lanes
 // read consecutive entries); r_K sits in the wave's slice of LDS.
-template <class S, class ACC>
-__global__ __launch_bounds__(256) void k_apply_small(const S* __restrict__ Dinv, int m, int ld, int64_t ne,
-                                                     const double* __restrict__ r, double* __restrict__ z) {
-  __shared__ double rs[4][64];
+template <class S, class ACC, int WPG>
+__global__ __launch_bounds__(64 * WPG) void k_apply_small(const S* __restrict__ Dinv, int m, int ld, int64_t ne,
+                                                          const double* __restrict__ r, double* __restrict__ z) {
+  __shared__ double rs[WPG][64];
   const int wv = threadIdx.x >> 6, i = threadIdx.x & 63;
-  const int64_t e = (int64_t)blockIdx.x * 4 + wv;
+  const int64_t e = (int64_t)blockIdx.x * WPG + wv;
   const bool live = e < ne && i < m;
   if (live) rs[wv][i] = r[(size_t)i * ne + e];
   __syncthreads();
@@ -523,33 +526,97 @@ hipError_t launch_ilu_apply(const double* B, const int64_t* nbr, const int* colo
   return hipGetLastError();
 }
 
-hipError_t launch_block_apply(int storage, const void* Dinv, int m, int64_t ne, const double* r, double* z,
-                              hipStream_t s) {
-  if (m < 1 || m > 256) return hipErrorInvalidValue;
-  const int ld = block_ld(m);
-  if (m <= 64) {
-    const unsigned grid = (unsigned)((ne + 3) / 4);
-    if (storage == DG_FP64)
-      k_apply_small<double, double><<<grid, 256, 0, s>>>(static_cast<const double*>(Dinv), m, ld, ne, r, z);
-    else if (storage == DG_FP32)
-      k_apply_small<float, float><<<grid, 256, 0, s>>>(static_cast<const float*>(Dinv), m, ld, ne, r, z);
-    else if (storage == DG_BF16)
-      k_apply_small<bf16_t, float><<<grid, 256, 0, s>>>(static_cast<const bf16_t*>(Dinv), m, ld, ne, r, z);
-    else
-      return hipErrorInvalidValue;
-    return hipGetLastError();
-  }
-  constexpr int T = kApplyThreads;
-  auto lds = [&](int vec) { return (size_t)(m + (T / (ld / vec)) * ld) * sizeof(double); };
-  if (storage == DG_FP64)
-    k_apply<double, double><<<(unsigned)ne, T, lds(2), s>>>(static_cast<const double*>(Dinv), m, ld, ne, r, z);
-  else if (storage == DG_FP32)
-    k_apply<float, float><<<(unsigned)ne, T, lds(4), s>>>(static_cast<const float*>(Dinv), m, ld, ne, r, z);
-  else if (storage == DG_BF16)
-    k_apply<bf16_t, float><<<(unsigned)ne, T, lds(8), s>>>(static_cast<const bf16_t*>(Dinv), m, ld, ne, r, z);
-  else
-    return hipErrorInvalidValue;
+namespace {
+
+template <class S, class ACC, int WPG>
+hipError_t apply_small(const void* Dinv, int m, int64_t ne, const double* r, double* z, hipStream_t s) {
+  const unsigned grid = (unsigned)((ne + WPG - 1) / WPG);
+  k_apply_small<S, ACC, WPG><<<grid, 64 * WPG, 0, s>>>(static_cast<const S*>(Dinv), m, block_ld(m), ne, r, z);
   return hipGetLastError();
+}
+
+template <class S, class ACC, int T, int EPW>
+hipError_t apply_vec(const void* Dinv, int m, int64_t ne, const double* r, double* z, hipStream_t s) {
+  const int ld = block_ld(m), G = ld / Vec16<S>::n;
+  const size_t lds = (size_t)EPW * (m + (T / G) * ld) * sizeof(double);
+  const unsigned grid = (unsigned)((ne + EPW - 1) / EPW);
+  k_apply<S, ACC, T, EPW><<<grid, T * EPW, lds, s>>>(static_cast<const S*>(Dinv), m, ld, ne, r, z);
+  return hipGetLastError();
+}
+
+template <class S, class ACC>
+hipError_t apply_shape(const ApplyShape& sh, const void* Dinv, int m, int64_t ne, const double* r, double* z,
+                       hipStream_t s) {
+  if (sh.kind == kApplyRow) {
+    switch (sh.epw) {
+      case 1: return apply_small<S, ACC, 1>(Dinv, m, ne, r, z, s);
+      case 2: return apply_small<S, ACC, 2>(Dinv, m, ne, r, z, s);
+      case 4: return apply_small<S, ACC, 4>(Dinv, m, ne, r, z, s);
+      case 8: return apply_small<S, ACC, 8>(Dinv, m, ne, r, z, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  if (sh.kind != kApplyVec) return hipErrorInvalidValue;
+  if (sh.threads == 64) {
+    switch (sh.epw) {
+      case 1: return apply_vec<S, ACC, 64, 1>(Dinv, m, ne, r, z, s);
+      case 2: return apply_vec<S, ACC, 64, 2>(Dinv, m, ne, r, z, s);
+      case 4: return apply_vec<S, ACC, 64, 4>(Dinv, m, ne, r, z, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  if (sh.epw != 1) return hipErrorInvalidValue;
+  switch (sh.threads) {
+    case 128: return apply_vec<S, ACC, 128, 1>(Dinv, m, ne, r, z, s);
+    case 256: return apply_vec<S, ACC, 256, 1>(Dinv, m, ne, r, z, s);
+    case 512: return apply_vec<S, ACC, 512, 1>(Dinv, m, ne, r, z, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+bool apply_shape_fits(const ApplyShape& sh, int m, int storage) {
+  if (m < 1 || m > 256 || (storage != DG_FP64 && storage != DG_FP32 && storage != DG_BF16)) return false;
+  if (sh.kind == kApplyDefault) return true;
+  const bool e1248 = sh.epw == 1 || sh.epw == 2 || sh.epw == 4 || sh.epw == 8;
+  if (sh.kind == kApplyRow) return m <= 64 && sh.threads == 64 && e1248;
+  if (sh.kind != kApplyVec) return false;
+  if (sh.threads == 64) {
+    if (sh.epw != 1 && sh.epw != 2 && sh.epw != 4) return false;
+  } else if (sh.threads == 128 || sh.threads == 256 || sh.threads == 512) {
+    if (sh.epw != 1) return false;
+  } else {
+    return false;
+  }
+  const int vec = storage == DG_FP64 ? 2 : (storage == DG_FP32 ? 4 : 8);
+  const int ld = block_ld(m), G = ld / vec;
+  if (G > sh.threads) return false;  // every thread group needs one column set at least
+  return (size_t)sh.epw * (m + (sh.threads / G) * ld) * sizeof(double) <= 65536;
+}
+
+ApplyShape default_apply_shape(int m) {
+  ApplyShape sh;
+  if (m <= 64) {
+    sh.kind = kApplyRow;
+    sh.threads = 64;
+    sh.epw = 4;
+  } else {
+    sh.kind = kApplyVec;
+    sh.threads = 256;
+    sh.epw = 1;
+  }
+  return sh;
+}
+
+hipError_t launch_block_apply(int storage, const void* Dinv, int m, int64_t ne, const double* r, double* z,
+                              hipStream_t s, const ApplyShape* shape) {
+  const ApplyShape sh = (shape && shape->kind) ? *shape : default_apply_shape(m);
+  if (!apply_shape_fits(sh, m, storage)) return hipErrorInvalidValue;
+  if (storage == DG_FP64) return apply_shape<double, double>(sh, Dinv, m, ne, r, z, s);
+  if (storage == DG_FP32) return apply_shape<float, float>(sh, Dinv, m, ne, r, z, s);
+  if (storage == DG_BF16) return apply_shape<bf16_t, float>(sh, Dinv, m, ne, r, z, s);
+  return hipErrorInvalidValue;
 }
 
 }  // namespace dgk

@@ -115,6 +115,11 @@ struct dg_context {
   dgc::MgState* mg = nullptr;    // p-multigrid preconditioner (dg_mg_setup)
   dgc::MlpState* mlp = nullptr;  // learned preconditioner (dg_mlp_*)
   void* d_scratch = nullptr;     // device address of the static scratch array on this device (dg_jvp_noalloc)
+  // launch shapes (autotuner, tune.cpp; 0 / kind 0 = the built-in default)
+  int tune_mode = DG_TUNE_AUTO;
+  int occ[3][2][2] = {};         // [precision][residual, Jv][face, volume kernel]: waves per SIMD
+  bool fine_tuned[3] = {};       // the fine operator of this precision has been timed
+  dgk::ApplyShape blk_shape{};   // fine block-Jacobi apply
 };
 
 
@@ -186,6 +191,27 @@ dg_status norm2(dg_context* c, const double* x, double* dout, hipStream_t s);
 // out = shift*v + J(w) v, exact or finite difference.
 dg_status jvp_impl(dg_context* c, const double* w, const double* r_w, const double* v, double shift, int mode,
                    double* out, hipStream_t s);
+
+// Autotuner (tune.cpp).  tune_fine times the waves-per-SIMD candidates of the
+// MFMA face and volume kernels of the operator of precision prec (residual and
+// Jv, at state w) and stores the fastest in c->occ; tune_apply and tune_bsr
+// time the block-inverse and block-sparse apply shapes of an m x m block
+// structure.  All do nothing (keeping the defaults) in DG_TUNE_FIXED mode or
+// while the stream is being captured, use the context's work vectors d_t1..3,
+// synchronise the stream, and reuse a process-wide cache keyed by kernel and
+// problem shape.
+dg_status tune_fine(dg_context* c, int prec, const double* w, hipStream_t s);
+dg_status tune_apply(dg_context* c, int storage, const void* Dinv, int m, dgk::ApplyShape* out, hipStream_t s);
+dg_status tune_bsr(dg_context* c, const double* B, const float* B32, int m, dgk::BsrShape* out, hipStream_t s);
+std::string apply_shape_name(const dgk::ApplyShape& sh, int m);
+std::string bsr_shape_name(const dgk::BsrShape& sh, int m, bool f32);
+// one line per p-multigrid level with its shapes (pmg.cpp)
+std::string mg_tuning_report(const MgState* m);
+// Pins the launch shapes of coarse level `level` (null: keep) and re-captures
+// the cycle graph; DG_ERR_ARG for a shape that does not fit.
+dg_status mg_set_level_shape(dg_context* c, int level, const dgk::BsrShape* b, const dgk::ApplyShape* a);
+// Re-captures the cycle graph of a ready hierarchy (fine-level shapes changed).
+dg_status mg_recapture(dg_context* c);
 
 // z = MG_V(0, r, 0) with the context's p-multigrid state (must be ready).
 dg_status mg_apply(dg_context* c, const double* r, double* z, hipStream_t s);

@@ -96,32 +96,37 @@ hipError_t launch_volume(int cfg, bool jvp, const double* U, const double* V, co
 bool has_mfma(int cfg);
 // Curved-element kernels compiled for the configuration.
 bool has_curved(int cfg);
+// occ: minimum waves per SIMD of the face / volume kernel's launch bound (1 or
+// 2; 0 = the configuration's default); hipErrorInvalidValue for a shape the
+// configuration does not have (mfma_occ_fits).  Every occupancy computes the
+// same bits.
+bool mfma_occ_fits(int cfg, int prec, int face_occ, int volume_occ);
 hipError_t launch_face_mfma(int cfg, bool jvp, const double* U, const double* V, double* H, const MTables& mt,
-                            const Mesh& m, const Phys& ph, hipStream_t stream);
+                            const Mesh& m, const Phys& ph, int occ, hipStream_t stream);
 // reduced precision variant: FP32 tables, FP32 face-flux buffer, FP32 MFMA and
 // pointwise arithmetic, FP64 inputs and outputs
 hipError_t launch_face_mfma_f32(int cfg, bool jvp, const double* U, const double* V, float* H, const MTablesF& mt,
-                                const Mesh& m, const Phys& ph, hipStream_t s);
+                                const Mesh& m, const Phys& ph, int occ, hipStream_t s);
 hipError_t launch_volume_mfma_f32(int cfg, bool jvp, const double* U, const double* V, const float* Gm,
                                   const float* H, double* out, double shift, const MTablesF& mt, const Mesh& m,
-                                  const Phys& ph, hipStream_t s);
+                                  const Phys& ph, int occ, hipStream_t s);
 // BF16 contractions with FP32 accumulation, otherwise as the FP32 variant
 // (FP32 tables and buffers, FP32 pointwise arithmetic)
 hipError_t launch_grad_mfma_bf16(int cfg, bool jvp, const double* U, const double* V, float* Gm, const MTablesF& mt,
                                  const Mesh& m, hipStream_t s);
 hipError_t launch_face_mfma_bf16(int cfg, bool jvp, const double* U, const double* V, float* H, const MTablesF& mt,
-                                 const Mesh& m, const Phys& ph, hipStream_t s);
+                                 const Mesh& m, const Phys& ph, int occ, hipStream_t s);
 hipError_t launch_volume_mfma_bf16(int cfg, bool jvp, const double* U, const double* V, const float* Gm,
                                    const float* H, double* out, double shift, const MTablesF& mt, const Mesh& m,
-                                   const Phys& ph, hipStream_t s);
+                                   const Phys& ph, int occ, hipStream_t s);
 // modal corrected gradients Gm[s][p][c][b][e] (s = value, tangent)
 hipError_t launch_grad_mfma(int cfg, bool jvp, const double* U, const double* V, double* Gm, const MTables& mt,
                             const Mesh& m, hipStream_t s);
 hipError_t launch_grad_mfma_f32(int cfg, bool jvp, const double* U, const double* V, float* Gm, const MTablesF& mt,
                                 const Mesh& m, hipStream_t s);
 hipError_t launch_volume_mfma(int cfg, bool jvp, const double* U, const double* V, const double* Gm, const double* H,
-                              double* out,
-                              double shift, const MTables& mt, const Mesh& m, const Phys& ph, hipStream_t stream);
+                              double* out, double shift, const MTables& mt, const Mesh& m, const Phys& ph, int occ,
+                              hipStream_t stream);
 hipError_t launch_project(int cfg, int nv, const double* f, double* w, const Tables& tb, const Mesh& m,
                           hipStream_t s);
 hipError_t launch_points(int cfg, double* xyz, const Tables& tb, const Mesh& m, hipStream_t s);
@@ -168,8 +173,21 @@ hipError_t launch_ilu_factor(const double* B, const int64_t* nbr, const int* col
                              int64_t ne, double* Dinv, int* info, hipStream_t s);
 hipError_t launch_ilu_apply(const double* B, const int64_t* nbr, const int* color, int ncolor, int nf, int m,
                             int64_t ne, const double* Dinv, const double* r, double* z, hipStream_t s);
+// Launch shape of the block-inverse apply: kApplyRow = one lane per row
+// (m <= 64; epw waves = elements per workgroup, 1/2/4/8), kApplyVec =
+// 16-byte column loads by `threads` threads per element (64, 128, 256, 512;
+// epw elements per workgroup: 1, 2 or 4 with 64 threads, else 1); kind 0 =
+// the default for m.  The shapes compute the same products; their sums run
+// in shape-dependent order.
+enum { kApplyDefault = 0, kApplyRow = 1, kApplyVec = 2 };
+struct ApplyShape {
+  int kind = kApplyDefault, threads = 0, epw = 0;
+};
+ApplyShape default_apply_shape(int m);
+// The shape exists for blocks of m rows stored as `storage` (kind 0 always).
+bool apply_shape_fits(const ApplyShape& sh, int m, int storage);
 hipError_t launch_block_apply(int storage, const void* Dinv, int m, int64_t ne, const double* r, double* z,
-                              hipStream_t s);
+                              hipStream_t s, const ApplyShape* shape = nullptr);
 
 // p-multigrid kernels (level transfer, inherited BSR operators, fixed-count
 // GMRES bookkeeping).  Device scalar block of one smoother, in doubles:
@@ -183,10 +201,21 @@ hipError_t launch_extract_bsr(const double* Jv, const int* color, int col, int l
                               int nbf, int nbc, int nv, int64_t ne, double* B, hipStream_t s);
 hipError_t launch_truncate_bsr(const double* B1, int nb1, double* B2, int nb2, int nv, int nslot, int64_t ne,
                                hipStream_t s);
-hipError_t launch_bsr_apply(int bs, const double* B, const int64_t* nbr, int nf, int m, int64_t ne, const double* x,
-                            double* y, hipStream_t s);
+// Launch shape of the block-sparse level apply: workgroup size (256, 512 or
+// 1024), rows per thread (1, 2, 4 (FP32 blocks only); 0 = the widest vector
+// load that m allows) and column slices per row (1, 2, 4 or 8).  Shapes that
+// do not fit return hipErrorInvalidValue.
+struct BsrShape {
+  int bs = 512, rpt = 0, cs = 4;
+};
+inline int bsr_widest_rpt(int m, size_t elem) { return (elem == 4 && m % 4 == 0) ? 4 : (m % 2 == 0 ? 2 : 1); }
+// The shape fits blocks of m rows with entries of elem bytes (8 or 4) and nf
+// face neighbours: at least one element row per workgroup, within 64 KB of LDS.
+bool bsr_shape_fits(const BsrShape& sh, int m, size_t elem, int nf);
+hipError_t launch_bsr_apply(const BsrShape& sh, const double* B, const int64_t* nbr, int nf, int m, int64_t ne,
+                            const double* x, double* y, hipStream_t s);
 // The same with FP32 blocks (FP64 sums); FP64 -> FP32 copy of n entries.
-hipError_t launch_bsr_apply_f32(int bs, const float* B, const int64_t* nbr, int nf, int m, int64_t ne,
+hipError_t launch_bsr_apply_f32(const BsrShape& sh, const float* B, const int64_t* nbr, int nf, int m, int64_t ne,
                                 const double* x, double* y, hipStream_t s);
 hipError_t launch_to_f32(const double* x, float* y, int64_t n, hipStream_t s);
 hipError_t launch_gmres_init(double* sc, int m, hipStream_t s);

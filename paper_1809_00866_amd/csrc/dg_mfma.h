@@ -1,5 +1,7 @@
-// FP64 MFMA kernels for the 3D residual and exact Jacobian-vector product
-// (gfx950, v_mfma_f64_16x16x4).  Same arithmetic as the reference kernels in
+// MFMA kernels for the 3D residual and exact Jacobian-vector product
+// (gfx950: v_mfma_f64_16x16x4, v_mfma_f32_16x16x4 and the BF16 16x16x16
+// instruction), instantiated per precision in dg_mfma_f64.hip,
+// dg_mfma_f32.hip and dg_mfma_bf16.hip.  Same arithmetic as the reference kernels in
 // dg_kernels.hip (eq. NSdiscrRes with BR2 liftings, Sec. 2.1-2.2); the dense
 // contractions run as MFMA tiles of 16 elements (or faces) x 16 quadrature
 // points, the pointwise fluxes on the vector ALU.
@@ -30,6 +32,7 @@
 // With one 16-point block (P2, P3) only the two value traces and the normal
 // averaged gradient contract over modes; the tangential averaged gradients
 // and the averaged lifting are point-to-point products of those traces.
+#pragma once
 #include "dg_device.h"
 
 namespace dgk {
@@ -184,10 +187,16 @@ __global__ __launch_bounds__(64) void k_grad_mfma(const double* __restrict__ U, 
 }
 
 // ------------------------------------------------------------------ volume
-// FP64 P4 runs at one wave per SIMD (no register spills; measured faster than
-// occupancy 2 with spills)
-template <class R, int NB, int NQ1, int KL, bool JVP, class MM>
-__global__ __launch_bounds__(256, (NB > 20 && sizeof(R) == 8) ? 1 : 2) void k_volume_mfma(const double* __restrict__ U, const double* __restrict__ V,
+// OCC is the minimum number of waves per SIMD the register allocation must
+// allow (launch bound): 2 caps a lane at 256 registers, 1 lets it use 512
+// (the accumulation registers too) without spilling.  The default is 1 for
+// FP64 P4 (measured faster than occupancy 2 with spills) and 2 otherwise;
+// the autotuner may pick the other one per configuration.
+template <class R, int NB>
+constexpr int volume_occupancy() { return (NB > 20 && sizeof(R) == 8) ? 1 : 2; }
+
+template <class R, int NB, int NQ1, int KL, bool JVP, class MM, int OCC>
+__global__ __launch_bounds__(256, OCC) void k_volume_mfma(const double* __restrict__ U, const double* __restrict__ V,
                                                      const R* __restrict__ Gm, const R* __restrict__ H,
                                                      double* __restrict__ out, double shift, MTablesT<R> mt,
                                                      Mesh m, Phys ph) {
@@ -398,10 +407,13 @@ __global__ __launch_bounds__(256, (NB > 20 && sizeof(R) == 8) ? 1 : 2) void k_vo
 // per SIMD, which makes room for the table and removes the register spills of
 // the dual-number flux.  The smaller configurations read the table from L2 at
 // occupancy 2 or more (staging it measured slower there).
+// The staged FP64 P4 table takes 116 KB of LDS, one workgroup per CU: that
+// configuration exists at occupancy 1 only.
 template <class R, int NB>
 struct FaceTab {
   static constexpr bool lds = NB > 20;
   static constexpr int occupancy = (lds && sizeof(R) == 8) ? 1 : 2;
+  static constexpr bool only_default = lds && sizeof(R) == 8;
 };
 
 template <class R, int NB, int NQ1, bool JVP, int P, class MM>
@@ -632,8 +644,8 @@ DEV void face_mfma_body(const double* __restrict__ U, const double* __restrict__
   }
 }
 
-template <class R, int NB, int NQ1, bool JVP, class MM>
-__global__ __launch_bounds__(256, (FaceTab<R, NB>::occupancy)) void k_face_mfma(
+template <class R, int NB, int NQ1, bool JVP, class MM, int OCC>
+__global__ __launch_bounds__(256, OCC) void k_face_mfma(
     const double* __restrict__ U, const double* __restrict__ V, R* __restrict__ H, MTablesT<R> mt, Mesh m, Phys ph) {
   __shared__ R stage[6 * 5][16][16];
   __shared__ R ttab[FaceTab<R, NB>::lds ? 6 * 2 * ((NB + 3) / 4) * 64 : 1];
@@ -652,25 +664,34 @@ __global__ __launch_bounds__(256, (FaceTab<R, NB>::occupancy)) void k_face_mfma(
   X(4, 20, 4, 4)           \
   X(5, 35, 5, 5)
 
-bool has_mfma(int cfg) {
-#define X(id, nb_, nq_, kl_) \
-  if (cfg == id) return true;
-  DG_MFMA_CONFIGS(X)
-#undef X
-  return false;
-}
-
+// occ: waves per SIMD of the launch bound, 0 for the configuration's default;
+// a shape the configuration does not have returns hipErrorInvalidValue.
 template <class R, class MM>
 hipError_t face_mfma_dispatch(int cfg, bool jvp, const double* U, const double* V, R* H, const MTablesT<R>& mt,
-                              const Mesh& m, const Phys& ph, hipStream_t s) {
-#define X(id, nb_, nq_, kl_)                                                         \
-  case id: {                                                                         \
-    dim3 grid((unsigned)((m.ne + 15) / 16), 3);                                      \
-    if (jvp)                                                                         \
-      k_face_mfma<R, nb_, nq_, true, MM><<<grid, 256, 0, s>>>(U, V, H, mt, m, ph);       \
-    else                                                                             \
-      k_face_mfma<R, nb_, nq_, false, MM><<<grid, 256, 0, s>>>(U, V, H, mt, m, ph);      \
-    return hipGetLastError();                                                        \
+                              const Mesh& m, const Phys& ph, int occ, hipStream_t s) {
+#define X(id, nb_, nq_, kl_)                                                               \
+  case id: {                                                                               \
+    using FT = FaceTab<R, nb_>;                                                            \
+    const int o = occ ? occ : FT::occupancy;                                               \
+    dim3 grid((unsigned)((m.ne + 15) / 16), 3);                                            \
+    if (o == 1) {                                                                          \
+      if (jvp)                                                                             \
+        k_face_mfma<R, nb_, nq_, true, MM, 1><<<grid, 256, 0, s>>>(U, V, H, mt, m, ph);    \
+      else                                                                                 \
+        k_face_mfma<R, nb_, nq_, false, MM, 1><<<grid, 256, 0, s>>>(U, V, H, mt, m, ph);   \
+    } else if (o == 2) {                                                                   \
+      if constexpr (FT::only_default) {                                                    \
+        return hipErrorInvalidValue;                                                       \
+      } else {                                                                             \
+        if (jvp)                                                                           \
+          k_face_mfma<R, nb_, nq_, true, MM, 2><<<grid, 256, 0, s>>>(U, V, H, mt, m, ph);  \
+        else                                                                               \
+          k_face_mfma<R, nb_, nq_, false, MM, 2><<<grid, 256, 0, s>>>(U, V, H, mt, m, ph); \
+      }                                                                                    \
+    } else {                                                                               \
+      return hipErrorInvalidValue;                                                         \
+    }                                                                                      \
+    return hipGetLastError();                                                              \
   }
   switch (cfg) { DG_MFMA_CONFIGS(X) }
 #undef X
@@ -680,16 +701,26 @@ hipError_t face_mfma_dispatch(int cfg, bool jvp, const double* U, const double* 
 template <class R, class MM>
 hipError_t volume_mfma_dispatch(int cfg, bool jvp, const double* U, const double* V, const R* Gm, const R* H,
                                 double* out, double shift, const MTablesT<R>& mt, const Mesh& m, const Phys& ph,
-                                hipStream_t s) {
-#define X(id, nb_, nq_, kl_)                                                                             \
-  case id: {                                                                                             \
-    if (mt.kl != kl_) return hipErrorInvalidValue;                                                       \
-    dim3 grid((unsigned)((m.ne + 15) / 16));                                                             \
-    if (jvp)                                                                                             \
-      k_volume_mfma<R, nb_, nq_, kl_, true, MM><<<grid, 256, 0, s>>>(U, V, Gm, H, out, shift, mt, m, ph);    \
-    else                                                                                                 \
-      k_volume_mfma<R, nb_, nq_, kl_, false, MM><<<grid, 256, 0, s>>>(U, V, Gm, H, out, shift, mt, m, ph);   \
-    return hipGetLastError();                                                                            \
+                                int occ, hipStream_t s) {
+#define X(id, nb_, nq_, kl_)                                                                                    \
+  case id: {                                                                                                    \
+    if (mt.kl != kl_) return hipErrorInvalidValue;                                                              \
+    const int o = occ ? occ : volume_occupancy<R, nb_>();                                                       \
+    dim3 grid((unsigned)((m.ne + 15) / 16));                                                                    \
+    if (o == 1) {                                                                                               \
+      if (jvp)                                                                                                  \
+        k_volume_mfma<R, nb_, nq_, kl_, true, MM, 1><<<grid, 256, 0, s>>>(U, V, Gm, H, out, shift, mt, m, ph);  \
+      else                                                                                                      \
+        k_volume_mfma<R, nb_, nq_, kl_, false, MM, 1><<<grid, 256, 0, s>>>(U, V, Gm, H, out, shift, mt, m, ph); \
+    } else if (o == 2) {                                                                                        \
+      if (jvp)                                                                                                  \
+        k_volume_mfma<R, nb_, nq_, kl_, true, MM, 2><<<grid, 256, 0, s>>>(U, V, Gm, H, out, shift, mt, m, ph);  \
+      else                                                                                                      \
+        k_volume_mfma<R, nb_, nq_, kl_, false, MM, 2><<<grid, 256, 0, s>>>(U, V, Gm, H, out, shift, mt, m, ph); \
+    } else {                                                                                                    \
+      return hipErrorInvalidValue;                                                                              \
+    }                                                                                                           \
+    return hipGetLastError();                                                                                   \
   }
   switch (cfg) { DG_MFMA_CONFIGS(X) }
 #undef X
@@ -708,55 +739,6 @@ hipError_t grad_mfma_dispatch(int cfg, bool jvp, const double* U, const double* 
   switch (cfg) { DG_MFMA_CONFIGS(X) }
 #undef X
   return hipErrorInvalidValue;
-}
-
-hipError_t launch_face_mfma(int cfg, bool jvp, const double* U, const double* V, double* H, const MTables& mt,
-                            const Mesh& m, const Phys& ph, hipStream_t s) {
-  return face_mfma_dispatch<double, MP<double>>(cfg, jvp, U, V, H, mt, m, ph, s);
-}
-
-hipError_t launch_volume_mfma(int cfg, bool jvp, const double* U, const double* V, const double* Gm, const double* H,
-                              double* out, double shift, const MTables& mt, const Mesh& m, const Phys& ph,
-                              hipStream_t s) {
-  return volume_mfma_dispatch<double, MP<double>>(cfg, jvp, U, V, Gm, H, out, shift, mt, m, ph, s);
-}
-
-hipError_t launch_grad_mfma(int cfg, bool jvp, const double* U, const double* V, double* Gm, const MTables& mt,
-                            const Mesh& m, hipStream_t s) {
-  return grad_mfma_dispatch<double, MP<double>>(cfg, jvp, U, V, Gm, mt, m, s);
-}
-
-hipError_t launch_grad_mfma_f32(int cfg, bool jvp, const double* U, const double* V, float* Gm, const MTablesF& mt,
-                                const Mesh& m, hipStream_t s) {
-  return grad_mfma_dispatch<float, MP<float>>(cfg, jvp, U, V, Gm, mt, m, s);
-}
-
-hipError_t launch_face_mfma_f32(int cfg, bool jvp, const double* U, const double* V, float* H, const MTablesF& mt,
-                                const Mesh& m, const Phys& ph, hipStream_t s) {
-  return face_mfma_dispatch<float, MP<float>>(cfg, jvp, U, V, H, mt, m, ph, s);
-}
-
-hipError_t launch_volume_mfma_f32(int cfg, bool jvp, const double* U, const double* V, const float* Gm,
-                                  const float* H, double* out, double shift, const MTablesF& mt, const Mesh& m,
-                                  const Phys& ph, hipStream_t s) {
-  return volume_mfma_dispatch<float, MP<float>>(cfg, jvp, U, V, Gm, H, out, shift, mt, m, ph, s);
-}
-
-// BF16 contractions (FP32 tables, buffers and pointwise arithmetic)
-hipError_t launch_grad_mfma_bf16(int cfg, bool jvp, const double* U, const double* V, float* Gm, const MTablesF& mt,
-                                 const Mesh& m, hipStream_t s) {
-  return grad_mfma_dispatch<float, MPB>(cfg, jvp, U, V, Gm, mt, m, s);
-}
-
-hipError_t launch_face_mfma_bf16(int cfg, bool jvp, const double* U, const double* V, float* H, const MTablesF& mt,
-                                 const Mesh& m, const Phys& ph, hipStream_t s) {
-  return face_mfma_dispatch<float, MPB>(cfg, jvp, U, V, H, mt, m, ph, s);
-}
-
-hipError_t launch_volume_mfma_bf16(int cfg, bool jvp, const double* U, const double* V, const float* Gm,
-                                   const float* H, double* out, double shift, const MTablesF& mt, const Mesh& m,
-                                   const Phys& ph, hipStream_t s) {
-  return volume_mfma_dispatch<float, MPB>(cfg, jvp, U, V, Gm, H, out, shift, mt, m, ph, s);
 }
 
 }  // namespace dgk

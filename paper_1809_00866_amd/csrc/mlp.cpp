@@ -215,7 +215,7 @@ dg_status features_impl(dg_context* c, MlpState* M, const double* w, const doubl
     if (!c->blk_ready) return fail(DG_ERR_STATE, "the block-Jacobi correction mode needs a block setup");
     dg_status st;
     if ((st = dalloc(&M->zt, (size_t)c->ndof)) != DG_OK) return st;
-    HIPCHK(dgk::launch_block_apply(c->blk_storage, c->d_Dinv, c->nv * c->nb, c->ne, r, M->zt, s));
+    HIPCHK(dgk::launch_block_apply(c->blk_storage, c->d_Dinv, c->nv * c->nb, c->ne, r, M->zt, s, &c->blk_shape));
     HIPCHK(dgk::launch_axpby(c->ndof, 1.0, z, -1.0, M->zt, M->zt, s));
     z = M->zt;
   }
@@ -240,7 +240,7 @@ dg_status mlp_apply(dg_context* c, const double* w, const double* r, double* z, 
   const int add = M->mode == DG_MLP_CORRECT_BJ;
   if (add) {
     if (!c->blk_ready) return fail(DG_ERR_STATE, "the block-Jacobi correction mode needs a block setup");
-    HIPCHK(dgk::launch_block_apply(c->blk_storage, c->d_Dinv, c->nv * c->nb, ne, r, z, s));
+    HIPCHK(dgk::launch_block_apply(c->blk_storage, c->d_Dinv, c->nv * c->nb, ne, r, z, s, &c->blk_shape));
   }
   HIPCHK(dgk::launch_mlp_scatter(M->Y, M->NP, M->s, M->n_out, ne, z, add, s));
   return DG_OK;

@@ -45,7 +45,8 @@ struct MgLevel {
   double* h = nullptr;         // full cycle: prolonged coarser solution
   double* V = nullptr;         // Krylov basis [(iters+1)][n]
   double* sc = nullptr;        // smoother scalars (kScSize)
-  int bs = 1024;               // BSR apply workgroup size (autotuned; same arithmetic for every size)
+  dgk::BsrShape bshape{};      // coarse levels: launch shape of the block-sparse apply (autotuned)
+  dgk::ApplyShape ashape{};    // coarse levels: launch shape of the block-Jacobi apply (autotuned)
 };
 
 struct MgState {
@@ -100,6 +101,19 @@ void mg_invalidate(MgState* M) {
 
 bool mg_ready(const MgState* M) { return M && M->ready; }
 
+std::string mg_tuning_report(const MgState* M) {
+  std::string r;
+  if (!M) return r;
+  for (int l = 1; l < M->nlev; ++l) {
+    const MgLevel& L = M->lev[l];
+    const char* st = M->storage == DG_FP64 ? "fp64" : (M->storage == DG_FP32 ? "fp32" : "bf16");
+    r += "mg level " + std::to_string(l) + " (P" + std::to_string(L.order) + ", m=" + std::to_string(L.m) +
+         "): " + bsr_shape_name(L.bshape, L.m, L.B32 != nullptr) + (L.B32 ? " (fp32 blocks)" : " (fp64 blocks)") +
+         "; block apply " + st + ": " + apply_shape_name(L.ashape, L.m) + "\n";
+  }
+  return r;
+}
+
 namespace {
 
 int binom(int n, int k) {
@@ -115,21 +129,23 @@ dg_status level_G(dg_context* c, MgState* M, int l, const double* x, double* y, 
     return eval_op(c, exact ? DG_FP64 : M->fine_prec, true, M->w, x, M->shift, y, s);
   const MgLevel& L = M->lev[l];
   if (L.B32 && !exact)
-    HIPCHK(dgk::launch_bsr_apply_f32(L.bs, L.B32, c->mesh.nbr, 2 * c->dim, L.m, c->ne, x, y, s));
+    HIPCHK(dgk::launch_bsr_apply_f32(L.bshape, L.B32, c->mesh.nbr, 2 * c->dim, L.m, c->ne, x, y, s));
+  else if (L.B32)  // the shape was tuned for the FP32 copy: the FP64 blocks take the default
+    HIPCHK(dgk::launch_bsr_apply(dgk::BsrShape{}, L.B, c->mesh.nbr, 2 * c->dim, L.m, c->ne, x, y, s));
   else
-    HIPCHK(dgk::launch_bsr_apply(L.bs, L.B, c->mesh.nbr, 2 * c->dim, L.m, c->ne, x, y, s));
+    HIPCHK(dgk::launch_bsr_apply(L.bshape, L.B, c->mesh.nbr, 2 * c->dim, L.m, c->ne, x, y, s));
   return DG_OK;
 }
 
 dg_status level_Minv(dg_context* c, MgState* M, int l, const double* r, double* z, hipStream_t s) {
   if (l == 0) {
-    HIPCHK(dgk::launch_block_apply(c->blk_storage, c->d_Dinv, c->nv * c->nb, c->ne, r, z, s));
+    HIPCHK(dgk::launch_block_apply(c->blk_storage, c->d_Dinv, c->nv * c->nb, c->ne, r, z, s, &c->blk_shape));
   } else if (l == M->nlev - 1 && M->coarse_ilu) {
     const MgLevel& L = M->lev[l];
     HIPCHK(dgk::launch_ilu_apply(L.B, c->mesh.nbr, c->d_color, c->ncolor, 2 * c->dim, L.m, c->ne, L.Ilu, r, z, s));
   } else {
     const MgLevel& L = M->lev[l];
-    HIPCHK(dgk::launch_block_apply(M->storage, L.Dinv, L.m, c->ne, r, z, s));
+    HIPCHK(dgk::launch_block_apply(M->storage, L.Dinv, L.m, c->ne, r, z, s, &L.ashape));
   }
   return DG_OK;
 }
@@ -348,6 +364,29 @@ dg_status mg_apply(dg_context* c, const double* r, double* z, hipStream_t s) {
   return DG_OK;
 }
 
+dg_status mg_set_level_shape(dg_context* c, int level, const dgk::BsrShape* b, const dgk::ApplyShape* a) {
+  MgState* M = c->mg;
+  if (!mg_ready(M)) return fail(DG_ERR_STATE, "dg_mg_setup has not succeeded since the last block setup");
+  if (level < 1 || level >= M->nlev) return fail(DG_ERR_ARG, "coarse level out of range");
+  MgLevel& L = M->lev[level];
+  if (b) {
+    if (!dgk::bsr_shape_fits(*b, L.m, L.B32 ? 4 : 8, 2 * c->dim))
+      return fail(DG_ERR_ARG, "block-sparse apply shape does not fit this level");
+    L.bshape = *b;
+  }
+  if (a) {
+    if (!dgk::apply_shape_fits(*a, L.m, M->storage)) return fail(DG_ERR_ARG, "block apply shape does not fit this level");
+    L.ashape = *a;
+  }
+  return mg_recapture(c);
+}
+
+dg_status mg_recapture(dg_context* c) {
+  MgState* M = c->mg;
+  if (!mg_ready(M) || !M->use_graph) return DG_OK;
+  return capture(c, M);
+}
+
 }  // namespace dgc
 
 using namespace dgc;
@@ -473,6 +512,7 @@ dg_status dg_mg_setup(dg_context* c, const double* w, double shift, const dg_mg_
       HIPCHK(dgk::launch_fill(C.Bs, (int64_t)nB, 0.0, s));
     }
     const double s01 = scale(0);
+    if ((st = tune_fine(c, M->fine_prec, M->w, s)) != DG_OK) return bail(st);
     ProfScope ps(c, "mg_probe", s);
     for (int col = 0; col < M->ncolor2; ++col)
       for (int l = 0; l < C.m; ++l) {
@@ -547,36 +587,11 @@ dg_status dg_mg_setup(dg_context* c, const double* w, double shift, const dg_mg_
       if ((st = dalloc(&C.B32, (size_t)nB)) != DG_OK) return bail(st);
       HIPCHK(dgk::launch_to_f32(C.B, C.B32, nB, s));
     }
-  // autotune the BSR apply workgroup size per coarse level
-  {
-    hipEvent_t a, b;
-    HIPCHK(hipEventCreate(&a));
-    HIPCHK(hipEventCreate(&b));
-    for (int l = 1; l < M->nlev; ++l) {
-      MgLevel& C = M->lev[l];
-      HIPCHK(dgk::launch_fill(C.g, C.n, 0.5, s));
-      float best = 1e30f;
-      for (int bs : {256, 512, 1024}) {
-        if (bs < 4 * C.m) continue;
-        auto apply = [&]() {
-          return C.B32 ? dgk::launch_bsr_apply_f32(bs, C.B32, c->mesh.nbr, nf, C.m, ne, C.g, C.t, s)
-                       : dgk::launch_bsr_apply(bs, C.B, c->mesh.nbr, nf, C.m, ne, C.g, C.t, s);
-        };
-        HIPCHK(apply());
-        HIPCHK(hipEventRecord(a, s));
-        for (int k = 0; k < 5; ++k) HIPCHK(apply());
-        HIPCHK(hipEventRecord(b, s));
-        HIPCHK(hipEventSynchronize(b));
-        float ms = 0.f;
-        HIPCHK(hipEventElapsedTime(&ms, a, b));
-        if (ms < best) {
-          best = ms;
-          C.bs = bs;
-        }
-      }
-    }
-    (void)hipEventDestroy(a);
-    (void)hipEventDestroy(b);
+  // launch shapes of every coarse level's block-sparse and block-Jacobi applies
+  for (int l = 1; l < M->nlev; ++l) {
+    MgLevel& C = M->lev[l];
+    if ((st = tune_bsr(c, C.B, C.B32, C.m, &C.bshape, s)) != DG_OK) return bail(st);
+    if ((st = tune_apply(c, M->storage, C.Dinv, C.m, &C.ashape, s)) != DG_OK) return bail(st);
   }
   HIPCHK(hipEventCreateWithFlags(&M->ev_a, hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&M->ev_b, hipEventDisableTiming));

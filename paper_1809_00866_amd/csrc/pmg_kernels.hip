@@ -91,10 +91,12 @@ __global__ void k_truncate_bsr(const double* __restrict__ B1, int nb1, double* _
 }
 
 // y_K = sum_s B[s][K] x_{elem(K, s)}.  A row of the level operator is
-// summed by 4 threads per matrix row (columns c, c+4, c+8, ... of the
-// (2d+1)*m gathered x values) and the 4 partial sums are added in a fixed
-// order, so the result does not depend on the workgroup size BS, which only
-// sets how many element rows (BS / 4m) share a workgroup.  The blocks are
+// summed by CS threads (column slices: columns c, c+CS, c+2CS, ... of the
+// (2d+1)*m gathered x values), each owning RPT consecutive rows (one vector
+// load per column), and the CS partial sums are added in a fixed order.  The
+// result depends on CS (summation order) but not on the workgroup size BS,
+// which only sets how many element rows (BS / (CS m / RPT)) share a
+// workgroup; the autotuner picks (BS, RPT, CS) per level.  The blocks are
 // stored in S (FP64, or an FP32 copy for the reduced-precision smoothers);
 // the sums are FP64.
 template <class S, int RPT>
@@ -134,19 +136,17 @@ struct RowVec<float, 4> {
   }
 };
 
-// Each thread owns RPT consecutive rows (one vector load per column; m is a
-// multiple of RPT) and one of 4 column slices; partial sums land in
-// part[element][slice][row].
-template <int BS, class S, int RPT>
+// part[element][slice][row] holds the slices' partial sums.
+template <int BS, class S, int RPT, int CS>
 __global__ __launch_bounds__(BS) void k_bsr_apply(const S* __restrict__ B, const int64_t* __restrict__ nbr,
                                                   int nf, int m, int R, int64_t ne, const double* __restrict__ x,
                                                   double* __restrict__ y) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int mr = m / RPT;          // row groups
-  const int tpr = 4 * mr;          // threads per element row; R element rows per workgroup
+  const int tpr = CS * mr;         // threads per element row; R element rows per workgroup
   const int ncol = (nf + 1) * m;
   double* xs = reinterpret_cast<double*>(smem);  // [R][ncol]
-  double* part = xs + R * ncol;                  // [R][4][m]
+  double* part = xs + R * ncol;                  // [R][CS][m]
   const int64_t K0 = (int64_t)blockIdx.x * R;
   for (int t = threadIdx.x; t < R * ncol; t += BS) {
     const int rr = t / ncol, q = t - rr * ncol;
@@ -167,7 +167,7 @@ __global__ __launch_bounds__(BS) void k_bsr_apply(const S* __restrict__ B, const
   if (rr < R && K < ne) {
     const double* xr = xs + rr * ncol;
 #pragma unroll 8
-    for (int col = cc; col < ncol; col += 4) {
+    for (int col = cc; col < ncol; col += CS) {
       const int s = col / m, j = col - s * m;
       double v[RPT];
       RowVec<S, RPT>::ld(B + ((int64_t)s * ne + K) * m * m + (int64_t)j * m + ig * RPT, v);
@@ -178,13 +178,16 @@ __global__ __launch_bounds__(BS) void k_bsr_apply(const S* __restrict__ B, const
   }
   if (rr < R)
 #pragma unroll
-    for (int u = 0; u < RPT; ++u) part[(rr * 4 + cc) * m + ig * RPT + u] = a[u];
+    for (int u = 0; u < RPT; ++u) part[(rr * CS + cc) * m + ig * RPT + u] = a[u];
   __syncthreads();
-  if ((int)threadIdx.x < R * m) {
-    const int r2 = threadIdx.x / m, i2 = threadIdx.x - r2 * m;
+  for (int t = threadIdx.x; t < R * m; t += BS) {
+    const int r2 = t / m, i2 = t - r2 * m;
     const int64_t K2 = K0 + r2;
-    const double* p = part + r2 * 4 * m + i2;
-    if (K2 < ne) y[(int64_t)i2 * ne + K2] = ((p[0] + p[m]) + p[2 * m]) + p[3 * m];
+    const double* p = part + r2 * CS * m + i2;
+    double acc = p[0];
+#pragma unroll
+    for (int k = 1; k < CS; ++k) acc += p[k * m];
+    if (K2 < ne) y[(int64_t)i2 * ne + K2] = acc;
   }
 }
 
@@ -289,31 +292,49 @@ hipError_t launch_truncate_bsr(const double* B1, int nb1, double* B2, int nb2, i
 
 namespace {
 
-template <class S, int RPT>
-hipError_t bsr_apply_rpt(int bs, const S* B, const int64_t* nbr, int nf, int m, int64_t ne, const double* x,
-                         double* y, hipStream_t s) {
-  // element rows per workgroup: as many as the threads allow, within 64 KB of LDS
-  const size_t per = ((size_t)(nf + 1) * m + (size_t)4 * m) * sizeof(double);
-  const int R = std::min<int>(bs / (4 * (m / RPT)), (int)(65536 / per));
-  if (R < 1) return hipErrorInvalidValue;
+template <class S, int RPT, int CS>
+hipError_t bsr_apply_shape(int bs, const S* B, const int64_t* nbr, int nf, int m, int64_t ne, const double* x,
+                           double* y, hipStream_t s) {
+  // element rows per workgroup: as many as the threads allow, within 64 KB of
+  // LDS (at least one: bsr_shape_fits)
+  const size_t per = ((size_t)(nf + 1) * m + (size_t)CS * m) * sizeof(double);
+  const int R = std::min<int>(bs / (CS * (m / RPT)), (int)(65536 / per));
   const unsigned grid = (unsigned)((ne + R - 1) / R);
   const size_t lds = (size_t)R * per;
   switch (bs) {
-    case 256: k_bsr_apply<256, S, RPT><<<grid, 256, lds, s>>>(B, nbr, nf, m, R, ne, x, y); break;
-    case 512: k_bsr_apply<512, S, RPT><<<grid, 512, lds, s>>>(B, nbr, nf, m, R, ne, x, y); break;
-    case 1024: k_bsr_apply<1024, S, RPT><<<grid, 1024, lds, s>>>(B, nbr, nf, m, R, ne, x, y); break;
+    case 256: k_bsr_apply<256, S, RPT, CS><<<grid, 256, lds, s>>>(B, nbr, nf, m, R, ne, x, y); break;
+    case 512: k_bsr_apply<512, S, RPT, CS><<<grid, 512, lds, s>>>(B, nbr, nf, m, R, ne, x, y); break;
+    case 1024: k_bsr_apply<1024, S, RPT, CS><<<grid, 1024, lds, s>>>(B, nbr, nf, m, R, ne, x, y); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
+template <class S, int RPT>
+hipError_t bsr_apply_rpt(const BsrShape& sh, const S* B, const int64_t* nbr, int nf, int m, int64_t ne,
+                         const double* x, double* y, hipStream_t s) {
+  switch (sh.cs) {
+    case 1: return bsr_apply_shape<S, RPT, 1>(sh.bs, B, nbr, nf, m, ne, x, y, s);
+    case 2: return bsr_apply_shape<S, RPT, 2>(sh.bs, B, nbr, nf, m, ne, x, y, s);
+    case 4: return bsr_apply_shape<S, RPT, 4>(sh.bs, B, nbr, nf, m, ne, x, y, s);
+    case 8: return bsr_apply_shape<S, RPT, 8>(sh.bs, B, nbr, nf, m, ne, x, y, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <class S>
-hipError_t bsr_apply(int bs, const S* B, const int64_t* nbr, int nf, int m, int64_t ne, const double* x, double* y,
-                     hipStream_t s) {
-  if (m < 1 || 4 * m > bs || ne < 1) return hipErrorInvalidValue;
-  if (sizeof(S) == 4 && m % 4 == 0) return bsr_apply_rpt<S, sizeof(S) == 4 ? 4 : 2>(bs, B, nbr, nf, m, ne, x, y, s);
-  if (m % 2 == 0) return bsr_apply_rpt<S, 2>(bs, B, nbr, nf, m, ne, x, y, s);
-  return bsr_apply_rpt<S, 1>(bs, B, nbr, nf, m, ne, x, y, s);
+hipError_t bsr_apply(const BsrShape& sh, const S* B, const int64_t* nbr, int nf, int m, int64_t ne,
+                     const double* x, double* y, hipStream_t s) {
+  if (ne < 1 || !bsr_shape_fits(sh, m, sizeof(S), nf)) return hipErrorInvalidValue;
+  const int rpt = sh.rpt ? sh.rpt : bsr_widest_rpt(m, sizeof(S));
+  switch (rpt) {
+    case 1: return bsr_apply_rpt<S, 1>(sh, B, nbr, nf, m, ne, x, y, s);
+    case 2: return bsr_apply_rpt<S, 2>(sh, B, nbr, nf, m, ne, x, y, s);
+    case 4:
+      if constexpr (sizeof(S) == 4) return bsr_apply_rpt<S, 4>(sh, B, nbr, nf, m, ne, x, y, s);
+      return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+  }
 }
 
 __global__ void k_to_f32(const double* __restrict__ x, float* __restrict__ y, int64_t n) {
@@ -323,14 +344,25 @@ __global__ void k_to_f32(const double* __restrict__ x, float* __restrict__ y, in
 
 }  // namespace
 
-hipError_t launch_bsr_apply(int bs, const double* B, const int64_t* nbr, int nf, int m, int64_t ne, const double* x,
-                            double* y, hipStream_t s) {
-  return bsr_apply<double>(bs, B, nbr, nf, m, ne, x, y, s);
+bool bsr_shape_fits(const BsrShape& sh, int m, size_t elem, int nf) {
+  if (m < 1 || nf < 0 || (elem != 4 && elem != 8)) return false;
+  if (sh.bs != 256 && sh.bs != 512 && sh.bs != 1024) return false;
+  if (sh.cs != 1 && sh.cs != 2 && sh.cs != 4 && sh.cs != 8) return false;
+  const int rpt = sh.rpt ? sh.rpt : bsr_widest_rpt(m, elem);
+  if (rpt != 1 && rpt != 2 && !(rpt == 4 && elem == 4)) return false;
+  if (m % rpt != 0) return false;
+  const size_t per = ((size_t)(nf + 1) * m + (size_t)sh.cs * m) * sizeof(double);
+  return sh.bs >= sh.cs * (m / rpt) && per <= 65536;
 }
 
-hipError_t launch_bsr_apply_f32(int bs, const float* B, const int64_t* nbr, int nf, int m, int64_t ne,
+hipError_t launch_bsr_apply(const BsrShape& sh, const double* B, const int64_t* nbr, int nf, int m, int64_t ne,
+                            const double* x, double* y, hipStream_t s) {
+  return bsr_apply<double>(sh, B, nbr, nf, m, ne, x, y, s);
+}
+
+hipError_t launch_bsr_apply_f32(const BsrShape& sh, const float* B, const int64_t* nbr, int nf, int m, int64_t ne,
                                 const double* x, double* y, hipStream_t s) {
-  return bsr_apply<float>(bs, B, nbr, nf, m, ne, x, y, s);
+  return bsr_apply<float>(sh, B, nbr, nf, m, ne, x, y, s);
 }
 
 hipError_t launch_to_f32(const double* x, float* y, int64_t n, hipStream_t s) {
