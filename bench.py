@@ -504,7 +504,11 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=8192)
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner experiment")
     ap.add_argument("--calib-copy", action="store_true",
-                    help="also run a plain 256 MiB device copy (reference kernel for HBM counters)")
+                    help="also run a plain streaming kernel of known size (c = a - b over 256 MiB vectors: "
+                         "512 MiB read, 256 MiB written), the reference for the HBM counters")
+    ap.add_argument("--tuning", choices=("auto", "fixed"), default="auto",
+                    help="launch shapes of the Jv legs: autotuned (default) or the built-in ones only "
+                         "(counter runs: no tuning launches beside the timed kernels)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported: the library runs on one GPU "
@@ -527,27 +531,30 @@ def main():
     w = g.project_field(fld)
     v = torch.tensor(synth.random_vector(g.ndof, cfg["v_seed"]), device="cuda")
     out = g.empty()
-    # the built-in launch shapes first, then the autotuned ones (the metric)
+
+    def timed_pass():
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            g.jvp(w, v, out=out)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t
+
+    # the built-in launch shapes, then the autotuned ones (the metric), each
+    # timed over K steps after the same warm-up
     g.set_tuning("fixed")
     for _ in range(args.warmup):
         g.jvp(w, v, out=out)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        g.jvp(w, v, out=out)
-    torch.cuda.synchronize()
-    wall_fixed = time.perf_counter() - t0
-    g.set_tuning("auto")
-    g.autotune(w)
+    wall_fixed = timed_pass()
+    if args.tuning == "auto":
+        g.set_tuning("auto")
+        g.autotune(w)
+        for _ in range(args.warmup):
+            g.jvp(w, v, out=out)
+        wall = timed_pass()
+    else:
+        wall = wall_fixed
     shapes = g.tuning_report().splitlines()
-    for _ in range(args.warmup):
-        g.jvp(w, v, out=out)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        g.jvp(w, v, out=out)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
     # per-kernel HIP events (on the stream of each launch) over a second pass
     # of the same K steps: the event records themselves cost ~0.02 ms per Jv,
     # so the throughput above is taken without them
@@ -620,11 +627,12 @@ def main():
     del w, v, out
     if args.calib_copy:
         a = torch.ones(1 << 25, dtype=torch.float64, device="cuda")
-        b = torch.empty_like(a)
+        b = torch.ones_like(a)
+        c = torch.empty_like(a)
         for _ in range(3):
-            b.copy_(a)
+            torch.sub(a, b, out=c)
         torch.cuda.synchronize()
-        del a, b
+        del a, b, c
     torch.cuda.empty_cache()
 
     res = {"metric": METRIC, "value": value, "unit": "DOFs/s", "n_gpus": 1, "steps": args.steps,
