@@ -414,9 +414,11 @@ dg_status dg_kernel_time(dg_context* ctx, const char* name, double* ms, int64_t*
  * candidate launch shapes of the kernels they set up, at the problem's own
  * size and on the caller's stream, and keep the fastest (a candidate replaces
  * the built-in default only when it is at least 3 % faster):
- *   - the waves per SIMD (1 or 2) of the 3D MFMA face and volume kernels, per
- *     operator precision, residual and Jv (dg_autotune: every precision the
- *     context has; the setups: the precision they probe with);
+ *   - the waves per SIMD (1 or 2) of the 3D MFMA face and volume kernels and
+ *     whether the volume kernel forms the corrected gradients itself (no
+ *     gradient kernel and buffer), per operator precision, residual and Jv
+ *     (dg_autotune: every precision the context has; the setups: the
+ *     precision they probe with);
  *   - the block-inverse apply: one lane per row with 1-8 elements per
  *     workgroup (blocks of at most 64 rows), or 16-byte column loads by
  *     64-512 threads per element with 1-4 elements per workgroup; per level
@@ -425,7 +427,8 @@ dg_status dg_kernel_time(dg_context* ctx, const char* name, double* ms, int64_t*
  *     rows per thread and column slices per row, per level.
  * Choices are kept in a process-wide cache keyed by kernel and problem shape,
  * so later setups and contexts of the same shape reuse them without timing.
- * The MFMA occupancy changes no result bit; the apply shapes change the order
+ * The MFMA occupancy and the gradient fusion change no result bit; the apply
+ * shapes change the order
  * of the sums (results differ in the last bits between shapes, never between
  * calls with the same shapes).  A setup that runs while its stream is being
  * captured keeps the defaults.  DG_TUNE_FIXED: the built-in defaults and no
@@ -446,9 +449,11 @@ dg_status dg_autotune(dg_context* ctx, const double* w, void* stream);
  * earlier tuned run without timing, or to compare shapes).  DG_ERR_ARG for a
  * shape the kernel does not have for this problem; a ready p-multigrid
  * hierarchy re-captures its cycle graph.
- *   dg_set_fine_occupancy: waves per SIMD (1, 2; 0 = default) of the MFMA
- *     face and volume kernels of the operator of `precision` (DG_FP64/FP32/
- *     BF16), residual (jvp = 0) or Jv (jvp = 1); later setups keep it.
+ *   dg_set_fine_shape: waves per SIMD (1, 2; 0 = default) of the MFMA face
+ *     and volume kernels of the operator of `precision` (DG_FP64/FP32/BF16),
+ *     residual (jvp = 0) or Jv (jvp = 1), and fused_gradients (1: the volume
+ *     kernel forms the corrected gradients; 0: the gradient kernel writes
+ *     them to a buffer); later setups keep it.
  *   dg_set_apply_shape: block-inverse apply of level 0 (the fine block-Jacobi
  *     factors; needs a block setup) or of coarse level >= 1 of the hierarchy:
  *     kind 1 = one lane per row (threads = 64, epw = 1/2/4/8 elements per
@@ -459,12 +464,13 @@ dg_status dg_autotune(dg_context* ctx, const double* w, void* stream);
  *     512 or 1024 threads, rows per thread 1, 2 or 4 (4: FP32 copies only; 0 =
  *     the widest the block size allows), column slices 1, 2, 4 or 8.  Applies
  *     to the blocks the cycle uses (the FP32 copies with FP32/BF16 storage). */
-dg_status dg_set_fine_occupancy(dg_context* ctx, int precision, int jvp, int face_occ, int volume_occ);
+dg_status dg_set_fine_shape(dg_context* ctx, int precision, int jvp, int face_occ, int volume_occ,
+                            int fused_gradients);
 dg_status dg_set_apply_shape(dg_context* ctx, int level, int kind, int threads, int epw);
 dg_status dg_set_bsr_shape(dg_context* ctx, int level, int workgroup, int rows_per_thread, int column_slices);
 
 /* Writes the current launch shapes as NUL-terminated text, one line per
- * kernel family ("fine fp64 residual: face occ 2, volume occ 2", "block apply
+ * kernel family ("fine fp64 residual: face occ 2, volume occ 2, gradients separate", "block apply
  * m=175 fp32: vec 256x1", "mg level 1 ...").  DG_ERR_ARG when buf is null or
  * len is too small (4096 bytes always suffice). */
 dg_status dg_tuning_report(const dg_context* ctx, char* buf, size_t len);

@@ -28,7 +28,7 @@ EXPORTED = ["dg_create", "dg_destroy", "dg_ndof", "dg_nbasis", "dg_nvar", "dg_nq
             "dg_fgmres_solve", "dg_rosenbrock_step", "dg_mg_setup", "dg_mg_update_fine", "dg_mg_apply", "dg_mg_level_apply", "dg_mlp_nparams", "dg_mlp_set_mode",
             "dg_mlp_set_weights", "dg_mlp_get_weights", "dg_mlp_features", "dg_mlp_forward", "dg_mlp_grad",
             "dg_mlp_train_step", "dg_mlp_apply", "dg_max_wave_speed",
-            "dg_set_tuning", "dg_autotune", "dg_tuning_report", "dg_set_fine_occupancy", "dg_set_apply_shape",
+            "dg_set_tuning", "dg_autotune", "dg_tuning_report", "dg_set_fine_shape", "dg_set_apply_shape",
             "dg_set_bsr_shape",
             "dg_set_profiling", "dg_kernel_time", "dg_last_error", "dg_sync"]
 
@@ -122,7 +122,7 @@ def load():
         "dg_set_tuning": (i, [ctx, i]),
         "dg_autotune": (i, [ctx, vp, vp]),
         "dg_tuning_report": (i, [ctx, ctypes.c_char_p, ctypes.c_size_t]),
-        "dg_set_fine_occupancy": (i, [ctx, i, i, i, i]),
+        "dg_set_fine_shape": (i, [ctx, i, i, i, i]),
         "dg_set_apply_shape": (i, [ctx, i, i, i, i]),
         "dg_set_bsr_shape": (i, [ctx, i, i, i, i]),
         "dg_set_profiling": (i, [ctx, i]),

@@ -160,11 +160,12 @@ class DG:
         L.check(self.lib.dg_tuning_report(self.ctx, buf, len(buf)), "dg_tuning_report")
         return buf.value.decode()
 
-    def set_fine_occupancy(self, precision, jvp, face_occ, volume_occ):
+    def set_fine_shape(self, precision, jvp, face_occ, volume_occ, fused_gradients=False):
         """Pin the waves per SIMD (1, 2; 0 = default) of the MFMA face and volume
-        kernels of the operator of `precision`, residual (jvp False) or Jv."""
-        L.check(self.lib.dg_set_fine_occupancy(self.ctx, _STORAGE[precision], int(bool(jvp)), int(face_occ),
-                                               int(volume_occ)), "dg_set_fine_occupancy")
+        kernels of the operator of `precision`, residual (jvp False) or Jv, and
+        whether the volume kernel forms the corrected gradients itself."""
+        L.check(self.lib.dg_set_fine_shape(self.ctx, _STORAGE[precision], int(bool(jvp)), int(face_occ),
+                                           int(volume_occ), int(bool(fused_gradients))), "dg_set_fine_shape")
 
     def set_apply_shape(self, level, kind, threads=0, epw=0):
         """Pin the block-inverse apply shape of level 0 (fine block Jacobi) or a

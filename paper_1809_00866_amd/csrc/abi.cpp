@@ -46,7 +46,8 @@ dg_status eval_residual(dg_context* c, bool jvp, const double* w, const double* 
     return DG_OK;
   }
   if (c->use_mfma) {
-    {
+    const bool fg = c->fuse_grad[DG_FP64][jvp];
+    if (!fg) {
       ProfScope ps(c, jvp ? "grad_jvp" : "grad_res", s);
       HIPCHK(dgk::launch_grad_mfma(c->cfg, jvp, w, v, c->d_G, c->mt, c->mesh, s));
     }
@@ -57,7 +58,7 @@ dg_status eval_residual(dg_context* c, bool jvp, const double* w, const double* 
     {
       ProfScope ps(c, jvp ? "vol_jvp" : "vol_res", s);
       HIPCHK(dgk::launch_volume_mfma(c->cfg, jvp, w, v, c->d_G, c->d_H, out, shift, c->mt, c->mesh, c->ph,
-                                     c->occ[DG_FP64][jvp][1], s));
+                                     c->occ[DG_FP64][jvp][1], fg, s));
     }
     return DG_OK;
   }
@@ -91,7 +92,8 @@ dg_status eval_residual_f32(dg_context* c, bool jvp, const double* w, const doub
     }
     return DG_OK;
   }
-  {
+  const bool fg = c->fuse_grad[DG_FP32][jvp];
+  if (!fg) {
     ProfScope ps(c, jvp ? "grad_jvp_f32" : "grad_res_f32", s);
     HIPCHK(dgk::launch_grad_mfma_f32(c->cfg, jvp, w, v, c->d_Gf, c->mtf, c->mesh, s));
   }
@@ -102,14 +104,15 @@ dg_status eval_residual_f32(dg_context* c, bool jvp, const double* w, const doub
   {
     ProfScope ps(c, jvp ? "vol_jvp_f32" : "vol_res_f32", s);
     HIPCHK(dgk::launch_volume_mfma_f32(c->cfg, jvp, w, v, c->d_Gf, c->d_Hf, out, shift, c->mtf, c->mesh, c->ph,
-                                       c->occ[DG_FP32][jvp][1], s));
+                                       c->occ[DG_FP32][jvp][1], fg, s));
   }
   return DG_OK;
 }
 
 dg_status eval_residual_bf16(dg_context* c, bool jvp, const double* w, const double* v, double shift, double* out,
                              hipStream_t s) {
-  {
+  const bool fg = c->fuse_grad[DG_BF16][jvp];
+  if (!fg) {
     ProfScope ps(c, jvp ? "grad_jvp_bf16" : "grad_res_bf16", s);
     HIPCHK(dgk::launch_grad_mfma_bf16(c->cfg, jvp, w, v, c->d_Gf, c->mtf, c->mesh, s));
   }
@@ -120,7 +123,7 @@ dg_status eval_residual_bf16(dg_context* c, bool jvp, const double* w, const dou
   {
     ProfScope ps(c, jvp ? "vol_jvp_bf16" : "vol_res_bf16", s);
     HIPCHK(dgk::launch_volume_mfma_bf16(c->cfg, jvp, w, v, c->d_Gf, c->d_Hf, out, shift, c->mtf, c->mesh, c->ph,
-                                        c->occ[DG_BF16][jvp][1], s));
+                                        c->occ[DG_BF16][jvp][1], fg, s));
   }
   return DG_OK;
 }
@@ -164,14 +167,14 @@ dg_status eval_stab(dg_context* c, bool f32, const double* w, const double* v, d
     HIPCHK(dgk::launch_grad_mfma_f32(c->cfg, true, w, z, c->d_Gf, c->mtf, c->mesh, s));
     HIPCHK(dgk::launch_face_mfma_f32(c->cfg, true, w, v, c->d_Hf, c->mtf, c->mesh, ph, c->occ[DG_FP32][1][0], s));
     HIPCHK(dgk::launch_volume_mfma_f32(c->cfg, true, w, z, c->d_Gf, c->d_Hf, out, 0.0, c->mtf, c->mesh, c->ph,
-                                       c->occ[DG_FP32][1][1], s));
+                                       c->occ[DG_FP32][1][1], false, s));
     return DG_OK;
   }
   if (c->use_mfma) {
     HIPCHK(dgk::launch_grad_mfma(c->cfg, true, w, z, c->d_G, c->mt, c->mesh, s));
     HIPCHK(dgk::launch_face_mfma(c->cfg, true, w, v, c->d_H, c->mt, c->mesh, ph, c->occ[DG_FP64][1][0], s));
     HIPCHK(dgk::launch_volume_mfma(c->cfg, true, w, z, c->d_G, c->d_H, out, 0.0, c->mt, c->mesh, c->ph,
-                                   c->occ[DG_FP64][1][1], s));
+                                   c->occ[DG_FP64][1][1], false, s));
     return DG_OK;
   }
   HIPCHK(dgk::launch_face(c->cfg, true, w, v, c->d_H, c->tb, c->mesh, ph, s));

@@ -118,6 +118,7 @@ struct dg_context {
   // launch shapes (autotuner, tune.cpp; 0 / kind 0 = the built-in default)
   int tune_mode = DG_TUNE_AUTO;
   int occ[3][2][2] = {};         // [precision][residual, Jv][face, volume kernel]: waves per SIMD
+  bool fuse_grad[3][2] = {};     // [precision][residual, Jv]: corrected gradients formed in the volume kernel
   bool fine_tuned[3] = {};       // the fine operator of this precision has been timed
   dgk::ApplyShape blk_shape{};   // fine block-Jacobi apply
 };

@@ -99,7 +99,9 @@ bool has_curved(int cfg);
 // occ: minimum waves per SIMD of the face / volume kernel's launch bound (1 or
 // 2; 0 = the configuration's default); hipErrorInvalidValue for a shape the
 // configuration does not have (mfma_occ_fits).  Every occupancy computes the
-// same bits.
+// same bits.  fused (volume kernel): form the corrected gradients in the
+// kernel from U / V (Gm unused) instead of reading them from Gm written by
+// launch_grad_mfma; the same chains, so the same bits.
 bool mfma_occ_fits(int cfg, int prec, int face_occ, int volume_occ);
 hipError_t launch_face_mfma(int cfg, bool jvp, const double* U, const double* V, double* H, const MTables& mt,
                             const Mesh& m, const Phys& ph, int occ, hipStream_t stream);
@@ -109,7 +111,7 @@ hipError_t launch_face_mfma_f32(int cfg, bool jvp, const double* U, const double
                                 const Mesh& m, const Phys& ph, int occ, hipStream_t s);
 hipError_t launch_volume_mfma_f32(int cfg, bool jvp, const double* U, const double* V, const float* Gm,
                                   const float* H, double* out, double shift, const MTablesF& mt, const Mesh& m,
-                                  const Phys& ph, int occ, hipStream_t s);
+                                  const Phys& ph, int occ, bool fused, hipStream_t s);
 // BF16 contractions with FP32 accumulation, otherwise as the FP32 variant
 // (FP32 tables and buffers, FP32 pointwise arithmetic)
 hipError_t launch_grad_mfma_bf16(int cfg, bool jvp, const double* U, const double* V, float* Gm, const MTablesF& mt,
@@ -118,7 +120,7 @@ hipError_t launch_face_mfma_bf16(int cfg, bool jvp, const double* U, const doubl
                                  const Mesh& m, const Phys& ph, int occ, hipStream_t s);
 hipError_t launch_volume_mfma_bf16(int cfg, bool jvp, const double* U, const double* V, const float* Gm,
                                    const float* H, double* out, double shift, const MTablesF& mt, const Mesh& m,
-                                   const Phys& ph, int occ, hipStream_t s);
+                                   const Phys& ph, int occ, bool fused, hipStream_t s);
 // modal corrected gradients Gm[s][p][c][b][e] (s = value, tangent)
 hipError_t launch_grad_mfma(int cfg, bool jvp, const double* U, const double* V, double* Gm, const MTables& mt,
                             const Mesh& m, hipStream_t s);
@@ -126,7 +128,7 @@ hipError_t launch_grad_mfma_f32(int cfg, bool jvp, const double* U, const double
                                 const Mesh& m, hipStream_t s);
 hipError_t launch_volume_mfma(int cfg, bool jvp, const double* U, const double* V, const double* Gm, const double* H,
                               double* out, double shift, const MTables& mt, const Mesh& m, const Phys& ph, int occ,
-                              hipStream_t stream);
+                              bool fused, hipStream_t stream);
 hipError_t launch_project(int cfg, int nv, const double* f, double* w, const Tables& tb, const Mesh& m,
                           hipStream_t s);
 hipError_t launch_points(int cfg, double* xyz, const Tables& tb, const Mesh& m, hipStream_t s);

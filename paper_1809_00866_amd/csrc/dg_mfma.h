@@ -195,7 +195,10 @@ __global__ __launch_bounds__(64) void k_grad_mfma(const double* __restrict__ U, 
 template <class R, int NB>
 constexpr int volume_occupancy() { return (NB > 20 && sizeof(R) == 8) ? 1 : 2; }
 
-template <class R, int NB, int NQ1, int KL, bool JVP, class MM, int OCC>
+// FG: the corrected gradients are formed in the kernel from the element and
+// its +/-p neighbours (the chains of k_grad_mfma, same operands and order,
+// so the same bits) instead of being read from the buffer Gm.
+template <class R, int NB, int NQ1, int KL, bool JVP, class MM, int OCC, bool FG>
 __global__ __launch_bounds__(256, OCC) void k_volume_mfma(const double* __restrict__ U, const double* __restrict__ V,
                                                      const R* __restrict__ Gm, const R* __restrict__ H,
                                                      double* __restrict__ out, double shift, MTablesT<R> mt,
@@ -237,7 +240,7 @@ __global__ __launch_bounds__(256, OCC) void k_volume_mfma(const double* __restri
     const int fc = wave + 4 * (i % (NFC / 4));
     const int f = fc / NV, c = fc % NV;
     const double* __restrict__ X = ((s == 0) ? U : V) + (size_t)c * NB * ne;
-    const R* __restrict__ Gf = Gm + (size_t)((s * DIM + (f > 0 ? f - 1 : 0)) * NV + c) * NB * ne;
+    const R* __restrict__ Gf = FG ? nullptr : Gm + (size_t)((s * DIM + (f > 0 ? f - 1 : 0)) * NV + c) * NB * ne;
     m0[i] = R(0);
     if (f == 0) {
 #pragma unroll
@@ -249,6 +252,43 @@ __global__ __launch_bounds__(256, OCC) void k_volume_mfma(const double* __restri
       if constexpr (MM::kBf16) {
         m0[i] = ev ? (R)X[ec] : R(0);
         if (g == 0) Bf[i][0] = R(0);  // mode bmode(0, 0) = 0
+      }
+    } else if constexpr (FG) {
+      // G_p = L_{p,0} X_e + L_{p,1} X_{e+p} + L_{p,2} X_{e-p} by MFMA, the
+      // chains of k_grad_mfma: result block mb, register r holds mode
+      // 16 mb + drow(g, r) = bmode(g, 4 mb + r), i.e. k-step 4 mb + r of
+      // this B fragment (modes >= NB come out zero: zero table rows)
+      const int pd = f - 1;
+      const int64_t es3[3] = {ec, m.nbr[(2 * pd + 1) * ne + ec], m.nbr[(2 * pd) * ne + ec]};
+      R bf3[3 * KSB], g0[3];
+#pragma unroll
+      for (int ks3 = 0; ks3 < 3 * KSB; ++ks3) {
+        const int src = ks3 / KSB, bp = g + 4 * (ks3 % KSB);
+        const R x = (R)X[(size_t)(bp < NB ? bp : NB - 1) * ne + es3[src]];
+        bf3[ks3] = (ev && bp < NB) ? x : R(0);
+      }
+      if constexpr (MM::kBf16) {
+#pragma unroll
+        for (int src = 0; src < 3; ++src) {
+          g0[src] = ev ? (R)X[es3[src]] : R(0);
+          if (g == 0) bf3[src * KSB] = R(0);
+        }
+      }
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) {
+        const R* __restrict__ la = mt.lA + ((size_t)pd * MB + mb) * 3 * KSB * 64 + lane;
+        F d = chain<MM, 3 * KSB>([&](int ks3) { return la[ks3 * 64]; }, [&](int ks3) { return bf3[ks3]; },
+                                 F{0, 0, 0, 0});
+        if constexpr (MM::kBf16) {
+          const R* __restrict__ l0 = mt.lA + ((size_t)pd * MB + mb) * 3 * KSB * 64;
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int src = 0; src < 3; ++src) d[r] += l0[src * KSB * 64 + MM::drow(g, r)] * g0[src];
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (4 * mb + r < KSV) Bf[i][4 * mb + r] = d[r];
       }
     } else {
 #pragma unroll
@@ -698,32 +738,47 @@ hipError_t face_mfma_dispatch(int cfg, bool jvp, const double* U, const double* 
   return hipErrorInvalidValue;
 }
 
+template <class R, class MM, int OCC, bool FG>
+hipError_t volume_launch(int nb, int nq, int kl, bool jvp, const double* U, const double* V, const R* Gm,
+                         const R* H, double* out, double shift, const MTablesT<R>& mt, const Mesh& m, const Phys& ph,
+                         hipStream_t s) {
+  const dim3 grid((unsigned)((m.ne + 15) / 16));
+#define X(id, nb_, nq_, kl_)                                                                                       \
+  if (nb == nb_ && nq == nq_ && kl == kl_) {                                                                       \
+    if (jvp)                                                                                                       \
+      k_volume_mfma<R, nb_, nq_, kl_, true, MM, OCC, FG><<<grid, 256, 0, s>>>(U, V, Gm, H, out, shift, mt, m, ph);  \
+    else                                                                                                           \
+      k_volume_mfma<R, nb_, nq_, kl_, false, MM, OCC, FG><<<grid, 256, 0, s>>>(U, V, Gm, H, out, shift, mt, m, ph); \
+    return hipGetLastError();                                                                                      \
+  }
+  DG_MFMA_CONFIGS(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+// occ as for the face kernel; fused: form the corrected gradients in the
+// volume kernel (Gm unused) instead of reading them.
 template <class R, class MM>
 hipError_t volume_mfma_dispatch(int cfg, bool jvp, const double* U, const double* V, const R* Gm, const R* H,
                                 double* out, double shift, const MTablesT<R>& mt, const Mesh& m, const Phys& ph,
-                                int occ, hipStream_t s) {
-#define X(id, nb_, nq_, kl_)                                                                                    \
-  case id: {                                                                                                    \
-    if (mt.kl != kl_) return hipErrorInvalidValue;                                                              \
-    const int o = occ ? occ : volume_occupancy<R, nb_>();                                                       \
-    dim3 grid((unsigned)((m.ne + 15) / 16));                                                                    \
-    if (o == 1) {                                                                                               \
-      if (jvp)                                                                                                  \
-        k_volume_mfma<R, nb_, nq_, kl_, true, MM, 1><<<grid, 256, 0, s>>>(U, V, Gm, H, out, shift, mt, m, ph);  \
-      else                                                                                                      \
-        k_volume_mfma<R, nb_, nq_, kl_, false, MM, 1><<<grid, 256, 0, s>>>(U, V, Gm, H, out, shift, mt, m, ph); \
-    } else if (o == 2) {                                                                                        \
-      if (jvp)                                                                                                  \
-        k_volume_mfma<R, nb_, nq_, kl_, true, MM, 2><<<grid, 256, 0, s>>>(U, V, Gm, H, out, shift, mt, m, ph);  \
-      else                                                                                                      \
-        k_volume_mfma<R, nb_, nq_, kl_, false, MM, 2><<<grid, 256, 0, s>>>(U, V, Gm, H, out, shift, mt, m, ph); \
-    } else {                                                                                                    \
-      return hipErrorInvalidValue;                                                                              \
-    }                                                                                                           \
-    return hipGetLastError();                                                                                   \
+                                int occ, bool fused, hipStream_t s) {
+  int nb = 0, nq = 0, kl = 0, o = 0;
+#define X(id, nb_, nq_, kl_)                                 \
+  if (cfg == id) {                                           \
+    nb = nb_;                                                \
+    nq = nq_;                                                \
+    kl = kl_;                                                \
+    o = occ ? occ : volume_occupancy<R, nb_>();              \
   }
-  switch (cfg) { DG_MFMA_CONFIGS(X) }
+  DG_MFMA_CONFIGS(X)
 #undef X
+  if (nb == 0 || mt.kl != kl) return hipErrorInvalidValue;
+  if (o == 1)
+    return fused ? volume_launch<R, MM, 1, true>(nb, nq, kl, jvp, U, V, Gm, H, out, shift, mt, m, ph, s)
+                 : volume_launch<R, MM, 1, false>(nb, nq, kl, jvp, U, V, Gm, H, out, shift, mt, m, ph, s);
+  if (o == 2)
+    return fused ? volume_launch<R, MM, 2, true>(nb, nq, kl, jvp, U, V, Gm, H, out, shift, mt, m, ph, s)
+                 : volume_launch<R, MM, 2, false>(nb, nq, kl, jvp, U, V, Gm, H, out, shift, mt, m, ph, s);
   return hipErrorInvalidValue;
 }
 

@@ -17,8 +17,8 @@ hipError_t launch_face_mfma_f32(int cfg, bool jvp, const double* U, const double
 
 hipError_t launch_volume_mfma_f32(int cfg, bool jvp, const double* U, const double* V, const float* Gm,
                                   const float* H, double* out, double shift, const MTablesF& mt, const Mesh& m,
-                                  const Phys& ph, int occ, hipStream_t s) {
-  return volume_mfma_dispatch<float, MP<float>>(cfg, jvp, U, V, Gm, H, out, shift, mt, m, ph, occ, s);
+                                  const Phys& ph, int occ, bool fused, hipStream_t s) {
+  return volume_mfma_dispatch<float, MP<float>>(cfg, jvp, U, V, Gm, H, out, shift, mt, m, ph, occ, fused, s);
 }
 
 }  // namespace dgk

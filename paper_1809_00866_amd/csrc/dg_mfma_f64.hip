@@ -28,8 +28,8 @@ hipError_t launch_face_mfma(int cfg, bool jvp, const double* U, const double* V,
 
 hipError_t launch_volume_mfma(int cfg, bool jvp, const double* U, const double* V, const double* Gm, const double* H,
                               double* out, double shift, const MTables& mt, const Mesh& m, const Phys& ph, int occ,
-                              hipStream_t s) {
-  return volume_mfma_dispatch<double, MP<double>>(cfg, jvp, U, V, Gm, H, out, shift, mt, m, ph, occ, s);
+                              bool fused, hipStream_t s) {
+  return volume_mfma_dispatch<double, MP<double>>(cfg, jvp, U, V, Gm, H, out, shift, mt, m, ph, occ, fused, s);
 }
 
 hipError_t launch_grad_mfma(int cfg, bool jvp, const double* U, const double* V, double* Gm, const MTables& mt,

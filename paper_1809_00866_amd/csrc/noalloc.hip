@@ -102,7 +102,7 @@ dg_status dg_jvp_noalloc(dg_context* c, const double* w, const double* v, double
     HIPCHK(dgk::launch_grad_mfma(c->cfg, true, w, v, G, c->mt, c->mesh, s));
     HIPCHK(dgk::launch_face_mfma(c->cfg, true, w, v, H, c->mt, c->mesh, c->ph, c->occ[DG_FP64][1][0], s));
     HIPCHK(dgk::launch_volume_mfma(c->cfg, true, w, v, G, H, out, shift, c->mt, c->mesh, c->ph,
-                                   c->occ[DG_FP64][1][1], s));
+                                   c->occ[DG_FP64][1][1], false, s));
     return DG_OK;
   }
   const size_t need = round_up(nfp);

@@ -124,8 +124,10 @@ dg_status tune_fine(dg_context* c, int prec, const double* w, hipStream_t s) {
     return DG_OK;
   }
   if (capturing(s)) return DG_OK;
-  // (face occ, volume occ); 0 = the configuration's default
-  static const int cand[5][2] = {{0, 0}, {1, 1}, {1, 2}, {2, 1}, {2, 2}};
+  // (face occ, volume occ, corrected gradients fused into the volume
+  // kernel); occupancy 0 = the configuration's default
+  static const int cand[10][3] = {{0, 0, 0}, {1, 1, 0}, {1, 2, 0}, {2, 1, 0}, {2, 2, 0},
+                                  {0, 0, 1}, {1, 1, 1}, {1, 2, 1}, {2, 1, 1}, {2, 2, 1}};
   for (int jvp = 0; jvp < 2; ++jvp) {
     const Key k = {kFamFine, c->cfg, prec, jvp, c->ph.model, c->ne, device_id()};
     std::array<int, 3> v{};
@@ -134,18 +136,21 @@ dg_status tune_fine(dg_context* c, int prec, const double* w, hipStream_t s) {
       auto launch = [&](int i) {
         c->occ[prec][jvp][0] = cand[i][0];
         c->occ[prec][jvp][1] = cand[i][1];
+        c->fuse_grad[prec][jvp] = cand[i][2] != 0;
         return eval_op(c, prec, jvp == 1, w, w, 0.0, c->d_t3, s) == DG_OK;
       };
-      dg_status st = pick_fastest(5, s, launch, &best);
+      dg_status st = pick_fastest(10, s, launch, &best);
       if (st != DG_OK) {
         c->occ[prec][jvp][0] = c->occ[prec][jvp][1] = 0;
+        c->fuse_grad[prec][jvp] = false;
         return st;
       }
-      v = {cand[best][0], cand[best][1], 0};
+      v = {cand[best][0], cand[best][1], cand[best][2]};
       store(k, v);
     }
     c->occ[prec][jvp][0] = v[0];
     c->occ[prec][jvp][1] = v[1];
+    c->fuse_grad[prec][jvp] = v[2] != 0;
   }
   c->fine_tuned[prec] = true;
   return DG_OK;
@@ -234,14 +239,19 @@ dg_status dg_set_tuning(dg_context* c, int mode) {
   c->tune_mode = mode;
   for (int p = 0; p < 3; ++p) {
     c->fine_tuned[p] = false;
-    for (int j = 0; j < 2; ++j) c->occ[p][j][0] = c->occ[p][j][1] = 0;
+    for (int j = 0; j < 2; ++j) {
+      c->occ[p][j][0] = c->occ[p][j][1] = 0;
+      c->fuse_grad[p][j] = false;
+    }
   }
   c->blk_shape = dgk::ApplyShape{};
   return DG_OK;
 }
 
-dg_status dg_set_fine_occupancy(dg_context* c, int precision, int jvp, int face_occ, int volume_occ) {
+dg_status dg_set_fine_shape(dg_context* c, int precision, int jvp, int face_occ, int volume_occ,
+                            int fused_gradients) {
   if (!c) return fail(DG_ERR_ARG, "null context");
+  if (fused_gradients != 0 && fused_gradients != 1) return fail(DG_ERR_ARG, "fused_gradients must be 0 or 1");
   if (precision < DG_FP64 || precision > DG_BF16 || (jvp != 0 && jvp != 1))
     return fail(DG_ERR_ARG, "precision must be DG_FP64/FP32/BF16 and jvp 0 or 1");
   if (!c->use_mfma || c->curved || !has_prec(c, precision))
@@ -250,6 +260,7 @@ dg_status dg_set_fine_occupancy(dg_context* c, int precision, int jvp, int face_
     return fail(DG_ERR_ARG, "occupancy not available for this configuration");
   c->occ[precision][jvp][0] = face_occ;
   c->occ[precision][jvp][1] = volume_occ;
+  c->fuse_grad[precision][jvp] = fused_gradients != 0;
   c->fine_tuned[precision] = true;
   return mg_recapture(c);
 }
@@ -298,9 +309,9 @@ dg_status dg_tuning_report(const dg_context* c, char* buf, size_t len) {
       for (int j = 0; j < 2; ++j) {
         char b[160];
         auto occ = [](int o) { return o ? std::to_string(o) : std::string("default"); };
-        std::snprintf(b, sizeof b, "fine %s %s: face occ %s, volume occ %s%s\n", prec_name(p),
+        std::snprintf(b, sizeof b, "fine %s %s: face occ %s, volume occ %s, gradients %s%s\n", prec_name(p),
                       j ? "jv" : "residual", occ(c->occ[p][j][0]).c_str(), occ(c->occ[p][j][1]).c_str(),
-                      c->fine_tuned[p] ? "" : " (not tuned)");
+                      c->fuse_grad[p][j] ? "fused" : "separate", c->fine_tuned[p] ? "" : " (not tuned)");
         r += b;
       }
     }

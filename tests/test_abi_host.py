@@ -105,7 +105,7 @@ def test_null_arguments():
     assert lib.dg_set_tuning(None, L.DG_TUNE_AUTO) == -1
     assert lib.dg_autotune(None, None, None) == -1
     assert lib.dg_tuning_report(None, None, 0) == -1
-    assert lib.dg_set_fine_occupancy(None, 0, 1, 1, 1) == -1
+    assert lib.dg_set_fine_shape(None, 0, 1, 1, 1, 0) == -1
     assert lib.dg_set_apply_shape(None, 0, 1, 64, 4) == -1
     assert lib.dg_set_bsr_shape(None, 1, 512, 2, 4) == -1
 

@@ -332,16 +332,17 @@ def test_fp32_fine_operator_inside_the_cycle_keeps_the_fp64_solution(case):
     g2.close()
 
 
-def test_fastest_solve_configuration_fp32_fine_operator_bf16_factors_p4():
-    """The benchmark's fastest solve configuration at P4 (V-cycle P4/P2/P1 with
-    8/8/40 smoothing steps, FP32 fine operator inside the cycle, BF16 block
-    factors on every level, one captured graph) on a 4^3 lattice with the
-    workload's field and a CFL-100 backward-Euler shift: graph replays equal
-    the eager cycle bit for bit (with eager work between replays), and the
-    outer FP64 FGMRES reaches 1e-10 on the true residual, re-checked with the
-    oracle operator (1e-9)."""
+@pytest.mark.parametrize("fine", ["fp32", "bf16"])
+def test_fastest_solve_configurations_bf16_factors_p4(fine):
+    """The benchmark's fastest solve configurations at P4 (V-cycle P4/P2/P1 with
+    8/8/40 smoothing steps, FP32 or BF16-contraction fine operator inside the
+    cycle, BF16 block factors on every level, one captured graph) on a 4^3
+    lattice with the workload's field and a CFL-100 backward-Euler shift:
+    graph replays equal the eager cycle bit for bit (with eager work between
+    replays), and the outer FP64 FGMRES reaches 1e-10 on the true residual,
+    re-checked with the oracle operator (1e-9)."""
     from paper_1809_00866_amd import DG
-    _say("fastest solve configuration: P4, fp32 fine operator, bf16 factors")
+    _say(f"fastest solve configuration: P4, {fine} fine operator, bf16 factors")
     cfg, mesh, fld = synth.preset("cfg3", N=(4, 4, 4))
     o = DGOracle(mesh, cfg["order"], cfg["space"], cfg["nq1d"], NavierStokes(3, mu=cfg["mu"], flux="roe"))
     U = o.project(fld)
@@ -349,7 +350,7 @@ def test_fastest_solve_configuration_fp32_fine_operator_bf16_factors_p4():
     smax = o.phys.max_wave_speed(np.einsum("eqb,ecb->eqc", et["phi"], U)).max()
     shift = (2 * cfg["order"] + 1) * smax / (cfg["cfl"] * float(np.min(mesh["h"])))
     w = torch.tensor(o.to_flat(U), device="cuda")
-    opts = dict(storage="bf16", fine_precision="fp32")
+    opts = dict(storage="bf16", fine_precision=fine)
     gg = DG(mesh, cfg["order"], nq1d=cfg["nq1d"], mu=cfg["mu"])
     gg.mg_setup(w, shift, cfg["mg_orders"], cfg["mg_smooth"], use_graph=True, **opts)
     ge = DG(mesh, cfg["order"], nq1d=cfg["nq1d"], mu=cfg["mu"])

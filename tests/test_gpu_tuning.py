@@ -1,10 +1,11 @@
 """GPU tests of the launch-shape autotuner and of every launch shape it can
 choose, through the C ABI.
 
-* MFMA occupancy (waves per SIMD of the face and volume kernels): every
-  variant computes the same bits as the default, residual and Jv, FP64, FP32
-  and BF16 operators, P2-P4 on a lattice of several 16-element tiles with a
-  ragged tail.
+* MFMA occupancy (waves per SIMD of the face and volume kernels) and the
+  volume kernel forming the corrected gradients itself: every variant
+  computes the same bits as the default, residual and Jv, FP64, FP32 and
+  BF16 operators, P2-P4 on a lattice of several 16-element tiles with a
+  ragged tail, and at P4 24^3 (the solve workload's launch shape).
 * Block-inverse apply shapes (one lane per row, 16-byte column loads with
   64-512 threads and 1-4 elements per workgroup): FP64 factors against the
   oracle's block solves (1e-12), FP32 / BF16 factors against the default
@@ -60,7 +61,7 @@ def _state(mesh, k, nq, seed=3):
 
 
 @pytest.mark.parametrize("k,nq", [(2, 3), (3, 4), (4, 5)], ids=["P2", "P3", "P4"])
-def test_every_occupancy_computes_the_same_bits(k, nq):
+def test_every_fine_shape_computes_the_same_bits(k, nq):
     from paper_1809_00866_amd import DG
     from paper_1809_00866_amd._lib import DGError
     _say(f"occupancy variants P{k}")
@@ -78,19 +79,46 @@ def test_every_occupancy_computes_the_same_bits(k, nq):
     n_run = 0
     for p, (res, jv) in runs.items():
         for jvp in (0, 1):
-            for fo in (1, 2):
-                for vo in (1, 2):
-                    try:
-                        g.set_fine_occupancy(p, jvp, fo, vo)
-                    except DGError as e:
-                        # only the FP64 P4 face kernel (its trace table fills the LDS) lacks occupancy 2
-                        assert e.status == -1 and (k, p, fo) == (4, "fp64", 2), (p, jvp, fo, vo)
-                        continue
-                    out = (jv if jvp else res)()
-                    assert torch.equal(out, ref[p][jvp]), (p, jvp, fo, vo)
-                    n_run += 1
-            g.set_fine_occupancy(p, jvp, 0, 0)
-    assert n_run >= 20
+            for fused in (0, 1):
+                for fo in (1, 2):
+                    for vo in (1, 2):
+                        try:
+                            g.set_fine_shape(p, jvp, fo, vo, fused)
+                        except DGError as e:
+                            # only the FP64 P4 face kernel (its trace table fills the LDS) lacks occupancy 2
+                            assert e.status == -1 and (k, p, fo) == (4, "fp64", 2), (p, jvp, fo, vo)
+                            continue
+                        out = (jv if jvp else res)()
+                        assert torch.equal(out, ref[p][jvp]), (p, jvp, fused, fo, vo)
+                        n_run += 1
+            g.set_fine_shape(p, jvp, 0, 0, 0)
+    assert n_run >= 40
+    g.close()
+
+
+def test_fused_gradients_at_full_size():
+    """P4 24^3: the fused-gradient volume kernel (every occupancy) gives the
+    bits of the two-kernel path, FP64 / FP32 / BF16, residual and Jv."""
+    from paper_1809_00866_amd import DG
+    from paper_1809_00866_amd._lib import DGError
+    _say("fused gradients, P4 24^3")
+    cfg, mesh, fld = synth.preset("cfg3")
+    g = DG(mesh, cfg["order"], basis=cfg["space"], nq1d=cfg["nq1d"], flux="roe", mu=cfg["mu"])
+    g.set_tuning("fixed")
+    w = g.project_field(fld)
+    v = torch.tensor(synth.random_vector(g.ndof, cfg["v_seed"]), device="cuda")
+    modes = {"fp64": "exact", "fp32": "exact_fp32", "bf16": "exact_bf16"}
+    for p, mode in modes.items():
+        ref = (g.residual(w, precision=p).clone(), g.jvp(w, v, shift=2.0, mode=mode).clone())
+        for jvp in (0, 1):
+            for vo in (1, 2):
+                try:
+                    g.set_fine_shape(p, jvp, 0, vo, 1)
+                except DGError:
+                    continue
+                out = g.jvp(w, v, shift=2.0, mode=mode) if jvp else g.residual(w, precision=p)
+                assert torch.equal(out, ref[jvp]), (p, jvp, vo)
+            g.set_fine_shape(p, jvp, 0, 0, 0)
     g.close()
 
 
