@@ -620,6 +620,22 @@ def main():
     else:
         wall = wall_fixed
     shapes = g.tuning_report().splitlines()
+    # the survey's protocol beside the contract's single pass: 5 passes of 100
+    # Jv calls (after 10 warm-up calls), HIP events around each pass, median
+    proto = []
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(10):
+        g.jvp(w, v, out=out)
+    for _ in range(5):
+        ev0.record()
+        for _ in range(100):
+            g.jvp(w, v, out=out)
+        ev1.record()
+        ev1.synchronize()
+        proto.append(ev0.elapsed_time(ev1) / 100)
+    proto.sort()
+    jv_protocol = {"passes": 5, "calls_per_pass": 100, "median_ms": proto[2], "min_ms": proto[0], "max_ms": proto[-1],
+                   "median_value": g.ndof / (proto[2] * 1e-3), "unit": "DOFs/s"}
     # per-kernel HIP events (on the stream of each launch) over a second pass
     # of the same K steps: the event records themselves cost ~0.02 ms per Jv,
     # so the throughput above is taken without them
@@ -711,7 +727,7 @@ def main():
                                   "Roe + BR2, Taylor-Green-like field Mach 0.1 Re 1600",
                       "n_elem": int(32 ** 3), "ndof": int(32 ** 3 * 100), "dofs_per_variable": int(32 ** 3 * 20)},
            "roofline": roofline, "jv_fp32": jv_fp32, "jv_bf16": jv_bf16,
-           "launch_shapes": shapes,
+           "launch_shapes": shapes, "jv_protocol": jv_protocol,
            "jv_fixed_shapes": {"ms_per_step": wall_fixed * 1e3 / args.steps,
                                "value": g_ndof / (wall_fixed / args.steps), "unit": "DOFs/s"}}
     if not args.no_solve:

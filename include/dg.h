@@ -231,6 +231,12 @@ typedef struct {
   int orth;        /* Arnoldi: DG_ORTH_CGS2 (classical Gram-Schmidt with one
                       re-orthogonalisation, two fused passes over the basis) or
                       DG_ORTH_MGS (modified Gram-Schmidt, one vector at a time) */
+  int check_every; /* the host applies the Givens rotations of the Hessenberg
+                      columns that arrived and tests convergence every
+                      check_every iterations and at the end of a restart cycle
+                      (0 or 1: every iteration; < 0: DG_ERR_ARG); the GPU runs
+                      ahead meanwhile, and iterations enqueued past the
+                      converged one are discarded */
 } dg_solve_opts;
 
 typedef struct {
@@ -238,13 +244,17 @@ typedef struct {
   double rel_res_est, rel_res_true, rho; /* rho: convergence factor */
   double ms_solve;
   int fallbacks;   /* switches from DG_PREC_MLP to block Jacobi */
+  double ms_setup; /* wall time of the last setup of the preconditioner used
+                      (dg_block_precond_setup or dg_mg_setup, including their
+                      autotuning); 0 for none and the learned preconditioner */
 } dg_solve_stats;
 
 /* Right-preconditioned flexible GMRES(m) for (shift*I + J(w)) x = b.
  * Classical Gram-Schmidt with one re-orthogonalisation, Givens rotations,
  * restarts from the true residual.  x: device, in = initial guess, out =
- * solution.  b = 0 returns x = 0.  Synchronises the stream once per
- * iteration.  opts/stats are host memory; stats may be NULL. */
+ * solution.  b = 0 returns x = 0.  Synchronises the stream at every
+ * convergence check (opts->check_every).  opts/stats are host memory; stats
+ * may be NULL. */
 dg_status dg_fgmres_solve(dg_context* ctx, const double* w, double shift, const double* b, double* x,
                           const dg_solve_opts* opts, dg_solve_stats* stats, void* stream);
 
@@ -263,8 +273,9 @@ dg_status dg_fgmres_solve(dg_context* ctx, const double* w, double shift, const 
  * live in a library buffer grown on demand.  stats (host, nullable): iters
  * and restarts summed over the stages, converged = all stages converged,
  * rel_res_est / rel_res_true / rho = the largest over the stages, ms_solve
- * summed.  Returns DG_NOT_CONVERGED (w_next still written) if a stage did
- * not converge.  Synchronises the stream (once per FGMRES iteration). */
+ * summed, ms_setup that of the preconditioner's last setup.  Returns
+ * DG_NOT_CONVERGED (w_next still written) if a stage did not converge.
+ * Synchronises the stream (at every convergence check of the stage solves). */
 enum { DG_ROS_MAX_STAGES = 6 };
 typedef struct {
   int n_stages;                                  /* 1..DG_ROS_MAX_STAGES */

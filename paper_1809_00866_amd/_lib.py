@@ -48,7 +48,7 @@ class DGMesh(ctypes.Structure):
 class SolveOpts(ctypes.Structure):
     _fields_ = [("restart", ctypes.c_int), ("max_iter", ctypes.c_int), ("rtol", ctypes.c_double),
                 ("precond", ctypes.c_int), ("jvp_mode", ctypes.c_int), ("rho_ref", ctypes.c_double),
-                ("judge_after", ctypes.c_int), ("orth", ctypes.c_int)]
+                ("judge_after", ctypes.c_int), ("orth", ctypes.c_int), ("check_every", ctypes.c_int)]
 
 
 ROS_MAX_STAGES = 6
@@ -69,7 +69,7 @@ class MgOpts(ctypes.Structure):
 class SolveStats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("restarts", ctypes.c_int), ("converged", ctypes.c_int),
                 ("rel_res_est", ctypes.c_double), ("rel_res_true", ctypes.c_double), ("rho", ctypes.c_double),
-                ("ms_solve", ctypes.c_double), ("fallbacks", ctypes.c_int)]
+                ("ms_solve", ctypes.c_double), ("fallbacks", ctypes.c_int), ("ms_setup", ctypes.c_double)]
 
 
 _lib = None

@@ -309,12 +309,12 @@ class DG:
         return out
 
     def fgmres(self, w, shift, b, x=None, restart=30, max_iter=1000, rtol=1e-8, precond="bj", jvp_mode="exact",
-               rho_ref=0.0, judge_after=5, orth="cgs2"):
+               rho_ref=0.0, judge_after=5, orth="cgs2", check_every=1):
         self._vec(w, "w")
         self._vec(b, "b")
         x = torch.zeros_like(b) if x is None else self._vec(x, "x")
         opts = L.SolveOpts(restart, max_iter, rtol, _PREC[precond], _MODE[jvp_mode], float(rho_ref), int(judge_after),
-                           _ORTH[orth])
+                           _ORTH[orth], int(check_every))
         st = L.SolveStats()
         status = self.lib.dg_fgmres_solve(self.ctx, _ptr(w), float(shift), _ptr(b), _ptr(x), ctypes.byref(opts),
                                           ctypes.byref(st), _stream())
@@ -338,7 +338,7 @@ class DG:
             for o in range(s):
                 k.a[s][o] = float(coeffs["a"][s][o])
                 k.c[s][o] = float(coeffs["c"][s][o])
-        opts = L.SolveOpts(restart, max_iter, rtol, _PREC[precond], _MODE[jvp_mode], 0.0, 0, L.DG_ORTH_CGS2)
+        opts = L.SolveOpts(restart, max_iter, rtol, _PREC[precond], _MODE[jvp_mode], 0.0, 0, L.DG_ORTH_CGS2, 1)
         st = L.SolveStats()
         status = self.lib.dg_rosenbrock_step(self.ctx, _ptr(w), float(dt), ctypes.byref(k), ctypes.byref(opts),
                                              _ptr(out), ctypes.byref(st), _stream())

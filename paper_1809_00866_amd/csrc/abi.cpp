@@ -512,7 +512,8 @@ dg_status dg_create(const dg_params* prm, const dg_mesh* mesh, dg_context** out)
   if ((st = dalloc(&c->d_red, (size_t)64 * dgk::kRedBlocks)) != DG_OK) return cleanup(st);
   if ((st = dalloc(&c->d_scal, (size_t)256)) != DG_OK) return cleanup(st);
   if ((st = dalloc(&c->d_flag, (size_t)16)) != DG_OK) return cleanup(st);
-  if (hipHostMalloc((void**)&c->h_pin, 512 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+  if (hipHostMalloc((void**)&c->h_pin, (kRbSlots * kRbStride + 64) * sizeof(double), hipHostMallocDefault) !=
+      hipSuccess) {
     c->h_pin = nullptr;
     return cleanup(fail(DG_ERR_OOM, "pinned host allocation failed"));
   }
@@ -558,7 +559,7 @@ void dg_destroy(dg_context* c) {
   mg_destroy(c->mg);
   mlp_destroy(c->mlp);
   if (c->h_pin) (void)hipHostFree(c->h_pin);
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < kRbSlots; ++i)
     if (c->ev_rb[i]) (void)hipEventDestroy(c->ev_rb[i]);
   delete c;
 }
@@ -692,8 +693,11 @@ dg_status dg_block_precond_setup(dg_context* c, const double* w, double shift, i
   if (c->nv * c->nb > 256) return fail(DG_ERR_ARG, "block size above 256");
   mg_invalidate(c->mg);
   dg_status st;
+  const auto t0 = std::chrono::steady_clock::now();
   if ((st = block_alloc(c, storage)) != DG_OK) return st;
-  return block_probe_invert(c, w, shift, storage, 0, default_probe_prec(c, storage), (hipStream_t)stream);
+  st = block_probe_invert(c, w, shift, storage, 0, default_probe_prec(c, storage), (hipStream_t)stream);
+  c->ms_setup_bj = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return st;
 }
 
 dg_status dg_block_precond_apply(dg_context* c, const double* r, double* z, void* stream) {
@@ -737,6 +741,8 @@ dg_status dg_fgmres_solve(dg_context* c, const double* w, double shift, const do
     return fail(DG_ERR_ARG, "the solve's operator is the exact FP64 or the finite-difference Jv");
   if (opts->orth != DG_ORTH_CGS2 && opts->orth != DG_ORTH_MGS) return fail(DG_ERR_ARG, "unknown orthogonalisation");
   const bool mgs = opts->orth == DG_ORTH_MGS;
+  if (opts->check_every < 0) return fail(DG_ERR_ARG, "check_every must be >= 0");
+  const int check_every = opts->check_every > 0 ? opts->check_every : 1;
   const double rtol = opts->rtol > 0.0 ? opts->rtol : 1e-8;
   const int max_iter = opts->max_iter > 0 ? opts->max_iter : 1000;
   hipStream_t s = (hipStream_t)stream;
@@ -752,7 +758,7 @@ dg_status dg_fgmres_solve(dg_context* c, const double* w, double shift, const do
     if ((st = dalloc(&c->d_Z, (size_t)m * n)) != DG_OK) return st;
     c->kry_m = m;
   }
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < m; ++i)
     if (!c->ev_rb[i]) HIPCHK(hipEventCreateWithFlags(&c->ev_rb[i], hipEventDisableTiming));
   const double* rw = nullptr;
   if (opts->jvp_mode == DG_JVP_FD) {
@@ -819,16 +825,17 @@ dg_status dg_fgmres_solve(dg_context* c, const double* w, double shift, const do
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
     // The Hessenberg column of iteration j travels to the host asynchronously
-    // (pinned slot j % 2, event ev_rb[j % 2]); the host applies its Givens
-    // rotation and tests convergence while iteration j + 1 runs on the GPU.
-    // An iteration enqueued past the stopping point is discarded (with the
-    // V-cycle as preconditioner every column is processed before the next
-    // iteration is enqueued).
-    int k = 0, pend = -1;
+    // (pinned slot j, event ev_rb[j]); every check_every iterations the host
+    // applies the Givens rotations of the columns that arrived and tests
+    // convergence, keeping the newest iteration in flight on the GPU.
+    // Iterations enqueued past the stopping point are discarded (with the
+    // V-cycle as preconditioner no iteration is left in flight at a check).
+    int k = 0;
+    std::vector<int> pend;
     bool stop = false;
     auto process = [&](int jj) -> dg_status {
-      HIPCHK(hipEventSynchronize(c->ev_rb[jj & 1]));
-      const double* hp = c->h_pin + 256 * (jj & 1);
+      HIPCHK(hipEventSynchronize(c->ev_rb[jj]));
+      const double* hp = c->h_pin + (size_t)kRbStride * jj;
       const double w0 = mgs ? hp[2] : std::sqrt(hp[16 + jj + 1]), hn = hp[3];
       if (!std::isfinite(hn)) return fail(DG_ERR_NONFINITE, "Arnoldi vector is not finite");
       double* Hc = &H[(size_t)jj * (m + 1)];  // column jj, rows 0..jj+1
@@ -889,17 +896,21 @@ dg_status dg_fgmres_solve(dg_context* c, const double* w, double shift, const do
         }
       }
       if ((st = norm2(c, Wn, dS + 3, s)) != DG_OK) return st;
-      HIPCHK(hipMemcpyAsync(c->h_pin + 256 * (j & 1), dS, 144 * sizeof(double), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipEventRecord(c->ev_rb[j & 1], s));
+      HIPCHK(hipMemcpyAsync(c->h_pin + (size_t)kRbStride * j, dS, 144 * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipEventRecord(c->ev_rb[j], s));
       HIPCHK(dgk::launch_scale_dev(n, Wn, dS + 3, Wn, s));
-      if (prec == DG_PREC_MG) {  // a V-cycle per iteration: no speculative iteration past the stop
-        if ((st = process(j)) != DG_OK) return st;
-      } else {
-        if (pend >= 0 && (st = process(pend)) != DG_OK) return st;
-        pend = j;
+      pend.push_back(j);
+      if ((j + 1) % check_every == 0 || j == m - 1) {
+        // a V-cycle per iteration is too costly to run past the stop speculatively
+        const size_t keep = (prec == DG_PREC_MG || j == m - 1) ? 0 : 1;
+        size_t done = 0;
+        while (pend.size() - done > keep && !stop)
+          if ((st = process(pend[done++])) != DG_OK) return st;
+        pend.erase(pend.begin(), pend.begin() + done);
       }
     }
-    if (!stop && pend >= 0 && (st = process(pend)) != DG_OK) return st;
+    for (size_t i = 0; i < pend.size() && !stop; ++i)
+      if ((st = process(pend[i])) != DG_OK) return st;
     // y = H_k^{-1} g (upper triangular back substitution)
     for (int i = k - 1; i >= 0; --i) {
       double a = g[i];
@@ -907,8 +918,9 @@ dg_status dg_fgmres_solve(dg_context* c, const double* w, double shift, const do
       const double d = H[(size_t)i * (m + 1) + i];
       y[i] = d != 0.0 ? a / d : 0.0;
     }
-    for (int i = 0; i < k; ++i) c->h_pin[400 + i] = y[i];
-    HIPCHK(hipMemcpyAsync(dS + 144, c->h_pin + 400, k * sizeof(double), hipMemcpyHostToDevice, s));
+    double* hy = c->h_pin + (size_t)kRbSlots * kRbStride;
+    for (int i = 0; i < k; ++i) hy[i] = y[i];
+    HIPCHK(hipMemcpyAsync(dS + 144, hy, k * sizeof(double), hipMemcpyHostToDevice, s));
     HIPCHK(dgk::launch_mupdate_add(Z, k, n, dS + 144, x, s));
     if ((st = applyG(x, c->d_t1)) != DG_OK) return st;
     HIPCHK(dgk::launch_axpby(n, 1.0, b, -1.0, c->d_t1, V, s));
@@ -924,6 +936,7 @@ dg_status dg_fgmres_solve(dg_context* c, const double* w, double shift, const do
   S.rel_res_true = beta / bnorm;
   S.rho = (iters > 0 && beta > 0.0 && d0 > 0.0) ? std::exp(std::log(beta / d0) / iters) : 0.0;
   S.ms_solve = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  S.ms_setup = opts->precond == DG_PREC_BJ ? c->ms_setup_bj : (opts->precond == DG_PREC_MG ? c->ms_setup_mg : 0.0);
   if (stats) *stats = S;
   return converged ? DG_OK : DG_NOT_CONVERGED;
 }

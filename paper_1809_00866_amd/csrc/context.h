@@ -59,6 +59,10 @@ bool mlp_ready(const MlpState* m);
 
 }  // namespace dgc
 
+// FGMRES read-back slots: one per Arnoldi column of a restart cycle (restart
+// <= 60), kRbStride doubles each, then the back-substitution vector.
+constexpr int kRbSlots = 64, kRbStride = 160;
+
 struct dg_context {
   dg_params prm{};
   int dim = 0, nv = 0, nb = 0, nq1 = 0, nq = 0, nfq = 0, cfg = -1;
@@ -106,7 +110,9 @@ struct dg_context {
   double* d_Z = nullptr;
   int kry_m = 0;
   double* h_pin = nullptr;
-  hipEvent_t ev_rb[2] = {nullptr, nullptr};  // FGMRES: Hessenberg columns copied to h_pin
+  hipEvent_t ev_rb[kRbSlots] = {};  // FGMRES: Hessenberg column j copied to pinned slot j
+  double ms_setup_bj = 0.0;        // wall time of the last dg_block_precond_setup
+  double ms_setup_mg = 0.0;        // wall time of the last dg_mg_setup
   bool prof = false;
   std::map<std::string, dgc::Timer> timers;
   double* d_zero = nullptr;      // ndof zeros (stabilisation-only Jv)

@@ -422,6 +422,7 @@ dg_status dg_mg_setup(dg_context* c, const double* w, double shift, const dg_mg_
   const int64_t ne = c->ne;
   const int dim = c->dim, nv = c->nv, nf = 2 * dim;
   dg_status st;
+  const auto t_setup = std::chrono::steady_clock::now();
 
   mg_destroy(c->mg);
   c->mg = nullptr;
@@ -601,6 +602,7 @@ dg_status dg_mg_setup(dg_context* c, const double* w, double shift, const dg_mg_
     if ((st = capture(c, M)) != DG_OK) return bail(st);
   }
   M->ready = true;
+  c->ms_setup_mg = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_setup).count();
   return DG_OK;
 }
 

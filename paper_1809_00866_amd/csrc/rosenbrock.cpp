@@ -60,6 +60,7 @@ dg_status dg_rosenbrock_step(dg_context* c, const double* w, double dt, const dg
     tot.rho = std::max(tot.rho, sst.rho);
     tot.ms_solve += sst.ms_solve;
     tot.fallbacks += sst.fallbacks;
+    tot.ms_setup = sst.ms_setup;
   }
   HIPCHK(dgk::launch_axpby(n, 1.0, w, 0.0, w, w_next, s));
   for (int si = 0; si < ns; ++si)

@@ -333,3 +333,34 @@ def test_fp32_operator_rejects_configurations_without_mfma_kernels():
     with pytest.raises(DGError) as ei:
         g.residual(w, precision="bf16")
     assert ei.value.status == -1
+
+
+@pytest.mark.parametrize("check_every", [1, 4, 7])
+def test_fgmres_check_every_and_setup_time(check_every):
+    """Convergence tested every check_every iterations (the GPU runs ahead,
+    iterations past the converged one are discarded): the same iterations
+    and solution bits as checking every iteration, the true residual
+    re-checked with the oracle operator; ms_setup reports the block setup."""
+    from paper_1809_00866_amd import DG
+    mesh = synth.lattice_mesh((3, 3, 2), L=1.0)
+    o = DGOracle(mesh, 3, "P", 4, NavierStokes(3, mu=1e-2))
+    U = o.project(synth.TaylorGreenStandIn(seed=2, L=1.0))
+    g = DG(mesh, 3, nq1d=4, mu=1e-2)
+    w = torch.tensor(o.to_flat(U), device="cuda")
+    shift = 20.0  # 99 block-Jacobi FGMRES(12) iterations to 1e-10 (the oracle's count)
+    g.block_setup(w, shift, storage="fp64")
+    B = np.random.default_rng(3).standard_normal(U.shape)
+    b = torch.tensor(o.to_flat(B), device="cuda")
+    x1, s1 = g.fgmres(w, shift, b, restart=12, rtol=1e-10, max_iter=400, precond="bj")
+    xk, sk = g.fgmres(w, shift, b, restart=12, rtol=1e-10, max_iter=400, precond="bj", check_every=check_every)
+    assert s1["converged"] == 1 and sk["converged"] == 1
+    # the stop is found at the same column and the columns enqueued past it
+    # are discarded: the same iterations and the same solution bits
+    assert sk["iters"] == s1["iters"] and sk["restarts"] == s1["restarts"]
+    assert torch.equal(xk, x1)
+    assert sk["rel_res_true"] <= 1e-10
+    X = o.from_flat(xk.cpu().numpy())
+    res = np.linalg.norm(o.to_flat(o.operator(U, X, shift)) - o.to_flat(B)) / np.linalg.norm(B)
+    assert res <= 1e-9
+    assert sk["ms_setup"] > 0.0 and s1["ms_setup"] == sk["ms_setup"]
+    g.close()

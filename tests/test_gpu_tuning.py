@@ -14,7 +14,9 @@ choose, through the C ABI.
   column slices): the inherited P2 and P1 operators of a P3/P2/P1 hierarchy
   against the oracle's Galerkin operators (eq. GalProj, 1e-12), and one
   V-cycle with every coarse shape pinned against the oracle's V-cycle (Alg.
-  vcic, 1e-9), the captured graph re-captured after each change.
+  vcic, 1e-9), the captured graph re-captured after each change; every shape
+  of the FP32 copies the cycle applies with FP32 storage against the built-in
+  one (1e-5).
 * The tuned set-up (DG_TUNE_AUTO) against the fixed one: bitwise equal
   operator, block apply within 1e-13, V-cycle within 1e-10, and the report.
 """
@@ -212,6 +214,38 @@ def test_every_bsr_shape_matches_the_inherited_operators(hierarchy):
         g.set_apply_shape(2, *a2)
         z = g.mg_apply(r).cpu().numpy()
         assert rel(z, z_o) <= 1e-9
+
+
+def test_every_bsr_shape_of_the_fp32_copies_in_the_cycle(hierarchy):
+    """With FP32 storage the cycle applies FP32 copies of the coarse operators
+    (FP64 sums); every block-sparse shape of those copies gives the V-cycle of
+    the built-in shape to 1e-5 relative (the same FP32 products, summed in
+    another order, through a nonlinear cycle), and the default cycle stays
+    within 1e-4 of the oracle's FP64 cycle."""
+    from paper_1809_00866_amd._lib import DGError
+    h = hierarchy
+    o, mg, g = h["o"], h["mg"], h["g"]
+    g.set_tuning("fixed")
+    g.mg_setup(h["w"], h["shift"], h["orders"], h["iters"], storage="fp32", use_graph=True)
+    R = np.random.default_rng(11).standard_normal(h["U"].shape)
+    r = torch.tensor(o.to_flat(R), device="cuda")
+    z_def = g.mg_apply(r).cpu().numpy()
+    assert rel(z_def, o.to_flat(mg.apply(R))) <= 1e-4
+    for l in (1, 2):
+        m = o.nvar * mg.nbs[l]
+        ok = 0
+        for bs, rpt, cs in BSR_SHAPES:
+            try:
+                g.set_bsr_shape(l, bs, rpt, cs)
+            except DGError as err:
+                assert err.status == -1
+                r_eff = rpt or (4 if m % 4 == 0 else 2 if m % 2 == 0 else 1)
+                assert m % r_eff or bs < cs * (m // r_eff), (l, bs, rpt, cs)
+                continue
+            assert rel(g.mg_apply(r).cpu().numpy(), z_def) <= 1e-5, (l, bs, rpt, cs)
+            ok += 1
+        assert ok >= 25
+        g.set_bsr_shape(l, 512, 0, 4)
 
 
 def test_autotuned_setup_matches_the_fixed_one(hierarchy):
