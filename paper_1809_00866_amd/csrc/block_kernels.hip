@@ -311,6 +311,185 @@ __global__ __launch_bounds__(T * EPW) void k_apply(const S* __restrict__ Dinv, i
     }
 }
 
+// LDS of one register-resident inversion (buffers double buffered by step
+// parity) and the per-thread context of a step.
+template <class S>
+struct GjShared {
+  S prow[2][256];     // scaled pivot row
+  S colk[2][256];     // multipliers A[i][k]
+  double redv[2][16];  // per-wave pivot candidates: |value|, row, value
+  int redi[2][16];
+  S redp[2][16];
+  int pivrow[256], kinv[256];
+  int bad;
+};
+struct GjThread {
+  int m, R, lane, wave, sl, i;
+  bool own;
+};
+
+// Step k = sk * CW + KK (KK a compile-time column of the thread's registers).
+template <class S, int CW, int KK>
+DEVI void gj_regs_step(S (&a)[CW], bool& used, int sk, const GjThread& t, GjShared<S>& sh) {
+  const int k = sk * CW + KK;
+  if (k >= t.m) return;  // uniform
+  const int par = k & 1;
+  // pivot candidates: the threads of slice sk hold column k
+  double best = -1.0;
+  int bi = 0x7fffffff;
+  S pv = S(0);
+  if (t.sl == sk && t.own && !used) {
+    pv = a[KK];
+    const double v = fabs((double)pv);
+    best = (v != v) ? 1e308 : v;
+    bi = t.i;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ob = __shfl_xor(best, off);
+    const int oi = __shfl_xor(bi, off);
+    const S op = __shfl_xor(pv, off);
+    if (ob > best || (ob == best && oi < bi)) {
+      best = ob;
+      bi = oi;
+      pv = op;
+    }
+  }
+  if (t.lane == 0) {
+    sh.redv[par][t.wave] = best;
+    sh.redi[par][t.wave] = bi;
+    sh.redp[par][t.wave] = pv;
+  }
+  __syncthreads();
+  const int w0 = sk * t.R / 64;
+  best = sh.redv[par][w0];
+  bi = sh.redi[par][w0];
+  pv = sh.redp[par][w0];
+  for (int w = w0 + 1; w < w0 + t.R / 64; ++w) {
+    const double ob = sh.redv[par][w];
+    const int oi = sh.redi[par][w];
+    if (ob > best || (ob == best && oi < bi)) {
+      best = ob;
+      bi = oi;
+      pv = sh.redp[par][w];
+    }
+  }
+  const int p = bi;
+  const bool okp = pv != S(0) && (double)pv - (double)pv == 0.0;
+  const S pinv = okp ? S(1) / pv : S(0);
+  if (t.i == p) {
+#pragma unroll
+    for (int jj = 0; jj < CW; ++jj) {
+      const int j = t.sl * CW + jj;
+      if (j < t.m) sh.prow[par][j] = (t.sl == sk && jj == KK) ? pinv : a[jj] * pinv;
+    }
+  }
+  if (t.sl == sk && t.own) sh.colk[par][t.i] = a[KK];
+  if (threadIdx.x == 0) {
+    sh.pivrow[k] = p < t.m ? p : 0;
+    if (p < t.m) sh.kinv[p] = k;
+    if (!okp) sh.bad = 1;
+  }
+  __syncthreads();
+  if (t.own) {
+    // row p becomes the scaled pivot row (multiplier -1, old value dropped);
+    // every other row i: A[i][j] -= A[i][k] prow[j], and column k holds
+    // -A[i][k] / A[p][k]
+    const bool rowp = t.i == p;
+    const S c = rowp ? S(-1) : sh.colk[par][t.i];
+#pragma unroll
+    for (int jj = 0; jj < CW; ++jj) {
+      const int j = t.sl * CW + jj;
+      const bool drop = rowp || (t.sl == sk && jj == KK);
+      if (j < t.m) a[jj] = fma_s(-c, sh.prow[par][j], drop ? S(0) : a[jj]);
+    }
+    used = used || rowp;
+  }
+}
+
+// The CW steps of one column slice, unrolled by template recursion (the
+// loop unroller refuses bodies this large, and a runtime column index would
+// move the register array to scratch).
+template <class S, int CW, int KK>
+struct GjSteps {
+  static DEVI void run(S (&a)[CW], bool& used, int sk, const GjThread& t, GjShared<S>& sh) {
+    gj_regs_step<S, CW, KK>(a, used, sk, t, sh);
+    GjSteps<S, CW, KK + 1>::run(a, used, sk, t, sh);
+  }
+};
+template <class S, int CW>
+struct GjSteps<S, CW, CW> {
+  static DEVI void run(S (&)[CW], bool&, int, const GjThread&, GjShared<S>&) {}
+};
+
+// Register-resident Gauss-Jordan for the larger blocks (64 < m <= 175): one
+// block per workgroup of NS * R threads (R = m rounded up to 64, NS =
+// ceil(m / CW) column slices), thread (s, i) holding row i's columns
+// s*CW .. s*CW + CW - 1 in registers, so every step updates the whole block
+// with CW fused multiply-adds per thread and LDS carries only the pivot row
+// and the multipliers.  Partial pivoting without row interchanges: step k
+// takes, among the rows not yet used as pivot rows, the one with the largest
+// |A[i][k]| (ties: the smallest row index), p_k; row p_k is scaled by
+// 1/A[p_k][k] and subtracted from every other row, and column k (which would
+// become the unit vector e_{p_k}) stores the new column p_k of the
+// accumulated inverse instead.  At the end the stored array S satisfies
+// inv(A)[k][p_j] = S[p_k][j], which the write-out applies.  Two barriers per
+// step.  D and out may be the same array (every load precedes every store).
+// The inverse is stored as S, or (S = float, out_bf16) rounded to BF16.
+template <class S, int CW>
+__global__ __launch_bounds__(1024) void k_invert_regs(const double* D, int ldd, void* out, int out_bf16, int ldo,
+                                                      int m, int* __restrict__ info) {
+  __shared__ GjShared<S> sh;
+  GjThread t;
+  t.m = m;
+  t.R = (m + 63) & ~63;
+  const int NS = (m + CW - 1) / CW;
+  const int tid = threadIdx.x;
+  t.lane = tid & 63;
+  t.wave = tid >> 6;
+  t.sl = tid / t.R;
+  t.i = tid - t.sl * t.R;
+  t.own = t.i < m;
+  const double* Dg = D + (size_t)blockIdx.x * m * ldd;
+  S a[CW];
+#pragma unroll
+  for (int jj = 0; jj < CW; ++jj) {
+    const int j = t.sl * CW + jj;
+    a[jj] = (t.own && j < m) ? (S)Dg[(size_t)j * ldd + t.i] : S(0);
+  }
+  if (tid == 0) sh.bad = 0;
+  if (tid < 256) sh.kinv[tid] = tid < m ? tid : 0;  // every row is a pivot row once; a safe start
+  bool used = false;
+  __syncthreads();  // every load of the block precedes every store (out may be D)
+  for (int sk = 0; sk < NS; ++sk) GjSteps<S, CW, 0>::run(a, used, sk, t, sh);
+  __syncthreads();  // pivrow / kinv complete
+  const size_t ob = (size_t)blockIdx.x * m * ldo;
+  auto put = [&](size_t idx, S v) {
+    if constexpr (sizeof(S) == 4) {
+      if (out_bf16) {
+        store_as(static_cast<bf16_t*>(out)[ob + idx], v);
+        return;
+      }
+    }
+    static_cast<S*>(out)[ob + idx] = v;
+  };
+  if (t.own) {
+    const int row = sh.kinv[t.i];
+#pragma unroll
+    for (int jj = 0; jj < CW; ++jj) {
+      const int j = t.sl * CW + jj;
+      if (j < m) put((size_t)sh.pivrow[j] * ldo + row, a[jj]);
+    }
+  } else if (t.i < ldo) {  // padding rows of this slice's columns
+#pragma unroll
+    for (int jj = 0; jj < CW; ++jj) {
+      const int j = t.sl * CW + jj;
+      if (j < m) put((size_t)j * ldo + t.i, S(0));
+    }
+  }
+  if (tid == 0 && sh.bad) info[0] = 1;
+}
+
 // Small blocks (m <= 64): one wave per element (WPG per workgroup), lane i
 // owns row i and walks the columns (column-major storage: consecutive lanes
 // read consecutive entries); r_K sits in the wave's slice of LDS.
@@ -464,10 +643,44 @@ hipError_t launch_extract_column(const double* Jv, const int* color, int col, in
 
 static constexpr size_t kMaxLds = 160 * 1024;
 
+namespace {
+
+// Column-slice width of the register-resident kernel: 16 or 35, the smaller
+// with ceil(m / CW) * roundup(m, 64) <= 1024 threads (65 <= m <= 175); 0 (the
+// LDS kernel) otherwise.
+int regs_width(int m) {
+  if (m <= 64 || m > 175) return 0;
+  const int R = (m + 63) & ~63;
+  for (int cw : {16, 35})
+    if ((m + cw - 1) / cw * R <= 1024) return cw;
+  return 0;
+}
+
+template <class S>
+hipError_t invert_regs(double* D64, int ldd, void* out, int out_bf16, int ldo, int m, int64_t ne, int* info,
+                       hipStream_t s) {
+  const int cw = regs_width(m);
+  const unsigned threads = (unsigned)((m + cw - 1) / cw * ((m + 63) & ~63));
+  switch (cw) {
+    case 16: k_invert_regs<S, 16><<<(unsigned)ne, threads, 0, s>>>(D64, ldd, out, out_bf16, ldo, m, info); break;
+    case 35: k_invert_regs<S, 35><<<(unsigned)ne, threads, 0, s>>>(D64, ldd, out, out_bf16, ldo, m, info); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
 hipError_t launch_block_invert(int storage, double* D64, int ldd, void* Dout, int m, int64_t ne, int* info,
                               hipStream_t s) {
   if (m < 1 || m > 256) return hipErrorInvalidValue;
   const int ldo = block_ld(m);
+  if (regs_width(m) > 0) {  // register-resident Gauss-Jordan
+    if (storage == DG_FP64) return invert_regs<double>(D64, ldd, Dout, 0, ldo, m, ne, info, s);
+    if (storage == DG_FP32) return invert_regs<float>(D64, ldd, Dout, 0, ldo, m, ne, info, s);
+    if (storage == DG_BF16) return invert_regs<float>(D64, ldd, Dout, 1, ldo, m, ne, info, s);
+    return hipErrorInvalidValue;
+  }
   constexpr int kRegCols = 72;  // FP64 columns kept in registers when the block does not fit LDS
   // static LDS: pivot rows (2 x 2 x 256 entries), reductions, pivots
   auto fixed = [](size_t es) { return (4 * 256 + 8) * es + 2 * 4 * (sizeof(double) + sizeof(int)) + 257 * sizeof(int) + 64; };
