@@ -315,7 +315,7 @@ __global__ __launch_bounds__(T * EPW) void k_apply(const S* __restrict__ Dinv, i
 // parity) and the per-thread context of a step.
 template <class S>
 struct GjShared {
-  S prow[2][256];     // scaled pivot row
+  S prow[2][256];     // scaled pivot row (zero beyond the block's columns)
   S colk[2][256];     // multipliers A[i][k]
   double redv[2][16];  // per-wave pivot candidates: |value|, row, value
   int redi[2][16];
@@ -377,12 +377,9 @@ DEVI void gj_regs_step(S (&a)[CW], bool& used, int sk, const GjThread& t, GjShar
   const int p = bi;
   const bool okp = pv != S(0) && (double)pv - (double)pv == 0.0;
   const S pinv = okp ? S(1) / pv : S(0);
-  if (t.i == p) {
+  if (t.i == p) {  // columns >= m of the last slice hold zeros (a stays 0 there)
 #pragma unroll
-    for (int jj = 0; jj < CW; ++jj) {
-      const int j = t.sl * CW + jj;
-      if (j < t.m) sh.prow[par][j] = (t.sl == sk && jj == KK) ? pinv : a[jj] * pinv;
-    }
+    for (int jj = 0; jj < CW; ++jj) sh.prow[par][t.sl * CW + jj] = (t.sl == sk && jj == KK) ? pinv : a[jj] * pinv;
   }
   if (t.sl == sk && t.own) sh.colk[par][t.i] = a[KK];
   if (threadIdx.x == 0) {
@@ -395,13 +392,22 @@ DEVI void gj_regs_step(S (&a)[CW], bool& used, int sk, const GjThread& t, GjShar
     // row p becomes the scaled pivot row (multiplier -1, old value dropped);
     // every other row i: A[i][j] -= A[i][k] prow[j], and column k holds
     // -A[i][k] / A[p][k]
+    // FP32: branch-free over the thread's columns (padding columns stay 0 =
+    // fma(-c, 0, 0)), the pivot-row reads issued together.  FP64: one column
+    // at a time behind its bounds test, which keeps the pivot-row values from
+    // being hoisted next to the 35 register-resident doubles (measured at
+    // P4: 43 ms against 76 ms with the hoisted reads spilling)
     const bool rowp = t.i == p;
     const S c = rowp ? S(-1) : sh.colk[par][t.i];
+    const S* pr = &sh.prow[par][t.sl * CW];
 #pragma unroll
     for (int jj = 0; jj < CW; ++jj) {
-      const int j = t.sl * CW + jj;
       const bool drop = rowp || (t.sl == sk && jj == KK);
-      if (j < t.m) a[jj] = fma_s(-c, sh.prow[par][j], drop ? S(0) : a[jj]);
+      if constexpr (sizeof(S) == 8) {
+        if (t.sl * CW + jj < t.m) a[jj] = fma_s(-c, pr[jj], drop ? S(0) : a[jj]);
+      } else {
+        a[jj] = fma_s(-c, pr[jj], drop ? S(0) : a[jj]);
+      }
     }
     used = used || rowp;
   }
@@ -645,9 +651,9 @@ static constexpr size_t kMaxLds = 160 * 1024;
 
 namespace {
 
-// Column-slice width of the register-resident kernel: 16 or 35, the smaller
-// with ceil(m / CW) * roundup(m, 64) <= 1024 threads (65 <= m <= 175); 0 (the
-// LDS kernel) otherwise.
+// Column-slice width of the register-resident kernel for blocks of 65 to 175
+// rows (0: the LDS kernel): 16 or 35, the smaller with ceil(m / CW) *
+// roundup(m, 64) <= 1024 threads.
 int regs_width(int m) {
   if (m <= 64 || m > 175) return 0;
   const int R = (m + 63) & ~63;
@@ -661,11 +667,12 @@ hipError_t invert_regs(double* D64, int ldd, void* out, int out_bf16, int ldo, i
                        hipStream_t s) {
   const int cw = regs_width(m);
   const unsigned threads = (unsigned)((m + cw - 1) / cw * ((m + 63) & ~63));
-  switch (cw) {
-    case 16: k_invert_regs<S, 16><<<(unsigned)ne, threads, 0, s>>>(D64, ldd, out, out_bf16, ldo, m, info); break;
-    case 35: k_invert_regs<S, 35><<<(unsigned)ne, threads, 0, s>>>(D64, ldd, out, out_bf16, ldo, m, info); break;
-    default: return hipErrorInvalidValue;
-  }
+  if (cw == 16)
+    k_invert_regs<S, 16><<<(unsigned)ne, threads, 0, s>>>(D64, ldd, out, out_bf16, ldo, m, info);
+  else if (cw == 35)
+    k_invert_regs<S, 35><<<(unsigned)ne, threads, 0, s>>>(D64, ldd, out, out_bf16, ldo, m, info);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
