@@ -229,22 +229,26 @@ def gpu_small_time_to_tolerance():
 
 PHASES = ("grad_jvp", "face_jvp", "vol_jvp", "grad_jvp_f32", "face_jvp_f32", "vol_jvp_f32", "grad_jvp_bf16",
           "face_jvp_bf16", "vol_jvp_bf16", "block_probe", "block_invert", "block_apply", "arnoldi", "mg_vcycle",
-          "mlp_apply")
+          "mg_probe", "mg_coarse_invert", "mlp_apply")
 STORAGE_BYTES = {"fp64": 8, "fp32": 4, "bf16": 2}
 
 
-def solve_phases(g, w, shift, b, cfg, precond, storage, curved):
-    """Per-phase breakdown of one solve: the block setup (block Jacobi) and
-    the solve again with HIP events around each phase (the timed run above
-    carries no events).  Each phase: total ms, calls, ms per call; the Jv
-    phases with their contraction flops against the FP64 (or FP32) matrix
-    peak on affine meshes, the block apply with its bytes against HBM."""
+def solve_phases(g, w, shift, b, cfg, precond, storage, curved, mg_setup=None):
+    """Per-phase breakdown of one solve: the setup (block Jacobi, or the
+    hierarchy through mg_setup()) and the solve again with HIP events around
+    each phase (the timed run above carries no events).  Each phase: total ms,
+    calls, ms per call; the Jv phases with their contraction flops against the
+    FP64 (or FP32) matrix peak on affine meshes, the block apply with its bytes
+    against HBM.  mg_probe is the whole hierarchy probing and includes the
+    fine block probing and inversion."""
     import torch
     g.set_profiling(True)
     for k in PHASES:
         g.kernel_time(k)  # reset
     if precond != "mg":
         g.block_setup(w, shift, storage=storage)
+    elif mg_setup is not None:
+        mg_setup()
     g.fgmres(w, shift, b, restart=cfg["restart"], max_iter=3000, rtol=cfg["rtol"], precond=precond)
     torch.cuda.synchronize()
     g.set_profiling(False)
@@ -298,10 +302,13 @@ def time_to_tolerance(storage="fp64", precond="bj", fine_precision="fp64", resca
         g.jvp(w, b, shift=shift)
     torch.cuda.synchronize()
     jv_ms = (time.perf_counter() - tj) * 100.0
-    t0 = time.perf_counter()
-    if precond == "mg":
+    def setup_mg():
         g.mg_setup(w, shift, cfg["mg_orders"], cfg["mg_smooth"], storage=storage, use_graph=True,
                    fine_precision=fine_precision, rescale=rescale, coarse_ilu=coarse_ilu)
+
+    t0 = time.perf_counter()
+    if precond == "mg":
+        setup_mg()
     else:
         g.block_setup(w, shift, storage=storage)
     torch.cuda.synchronize()
@@ -309,7 +316,8 @@ def time_to_tolerance(storage="fp64", precond="bj", fine_precision="fp64", resca
     x, st = g.fgmres(w, shift, b, restart=cfg["restart"], max_iter=3000, rtol=cfg["rtol"], precond=precond)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    extra = {"phases": solve_phases(g, w, shift, b, cfg, precond, storage, curved=preset != "cfg3")}
+    extra = {"phases": solve_phases(g, w, shift, b, cfg, precond, storage, curved=preset != "cfg3",
+                                    mg_setup=setup_mg)}
     if precond == "mg":  # one preconditioner application (the captured V-cycle), outside the solve
         z = g.empty()
         g.mg_apply(b, out=z)
