@@ -57,7 +57,6 @@ struct MgState {
   bool coarse_ilu = false;  // block ILU(0) preconditions the coarsest smoother
   double shift = 0.0;
   bool use_graph = false, ready = false;
-  double ms_capture = 0.0;     // host time of the last cycle capture + instantiation
   MgLevel lev[3];
   double* w = nullptr;         // linearisation state (own copy)
   double* red = nullptr;       // reduction partials [kMaxSmooth+4][kRedBlocks]
@@ -603,9 +602,7 @@ dg_status dg_mg_setup(dg_context* c, const double* w, double shift, const dg_mg_
   HIPCHK(hipStreamSynchronize(s));
   if (M->use_graph) {
     HIPCHK(hipStreamCreateWithFlags(&M->gs, hipStreamNonBlocking));
-    const auto t_cap = std::chrono::steady_clock::now();
     if ((st = capture(c, M)) != DG_OK) return bail(st);
-    M->ms_capture = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_cap).count();
   }
   M->ready = true;
   c->ms_setup_mg = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_setup).count();
