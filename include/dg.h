@@ -444,9 +444,9 @@ dg_status dg_kernel_time(dg_context* ctx, const char* name, double* ms, int64_t*
  * calls with the same shapes).  A setup that runs while its stream is being
  * captured keeps the defaults.  DG_TUNE_FIXED: the built-in defaults and no
  * timing, bitwise reproducible across processes; setting it resets the
- * context's operator and fine block-apply shapes at once, while an existing
- * p-multigrid hierarchy keeps the coarse shapes of its setup until the next
- * dg_mg_setup.  DG_ERR_ARG for another mode. */
+ * context's operator and fine block-apply shapes at once (a ready hierarchy
+ * re-captures its cycle graph), while the hierarchy keeps the coarse shapes
+ * of its setup until the next dg_mg_setup.  DG_ERR_ARG for another mode. */
 enum { DG_TUNE_FIXED = 0, DG_TUNE_AUTO = 1 };
 dg_status dg_set_tuning(dg_context* ctx, int mode);
 

@@ -245,7 +245,7 @@ dg_status dg_set_tuning(dg_context* c, int mode) {
     }
   }
   c->blk_shape = dgk::ApplyShape{};
-  return DG_OK;
+  return mg_recapture(c);  // a captured cycle follows the fine apply shape
 }
 
 dg_status dg_set_fine_shape(dg_context* c, int precision, int jvp, int face_occ, int volume_occ,

@@ -40,6 +40,9 @@ CASES = {
     "P4-P2-P1": ((1, 2, 2), 4, 5, (4, 2, 1), (2, 2, 6), 6.0),
     "2d-P2-P1-P0": ((3, 4), 2, 4, (2, 1, 0), (3, 3, 12), 6.0),
     "P2-P1-4x2x2": ((4, 2, 2), 2, 3, (2, 1), (3, 10), 6.0),
+    # a coarse level with blocks of 100 rows (the register-resident inversion,
+    # input column stride m)
+    "P4-P3": ((2, 2, 1), 4, 5, (4, 3), (2, 6), 6.0),
 }
 
 
@@ -253,7 +256,8 @@ def test_coarse_block_ilu0_matches_the_oracle(case):
     from paper_1809_00866_amd._lib import DGError
     o, mg, U, w, shift = case["o"], case["mg"], case["U"], case["w"], case["shift"]
     _say("coarse block ILU(0)")
-    if 3 in case["mesh"]["N"]:      # a periodic ring of three elements: triangles, refused
+    if 3 in case["mesh"]["N"] or o.nvar * mg.nbs[mg.L] > 64:
+        # a periodic ring of three elements (triangles) or coarsest blocks above 64 rows: refused
         gx = DG(case["mesh"], case["k"], nq1d=case["nq"], mu=1e-2)
         with pytest.raises(DGError) as ei:
             gx.mg_setup(w, shift, case["orders"], case["iters"], coarse_ilu=True)
