@@ -28,6 +28,7 @@
 // finally L^{-1}.
 #include "dg_device.h"
 
+
 namespace dgk {
 
 namespace {
@@ -306,19 +307,71 @@ __global__ __launch_bounds__(128) void k_volume_curved(const double* __restrict_
   const int wv = tid >> 6, ln = tid & 63, li = ln & 15, lg = ln >> 4;
   R* sXs = sB;                  // [NR][NFQ]
   R* sPs = sB + NR * NFQ;       // [NFQ][NB]
-  for (int hf = 0; hf < 2 * DIM; ++hf) {
-    const int p = hf >> 1, h = hf & 1;
-    const size_t f = (size_t)p * ne + (h ? m.nbr[(size_t)(2 * p) * ne + e] : e);
-    const int ls = h ? 2 * p : 2 * p + 1;
+  // FP64: the loads of face hf + 1 are issued before the products of face hf
+  // and land in registers while those run (the staging loads' latency was a
+  // fifth of the kernel); the products w n_j [[U]] are formed at the LDS
+  // write.  FP32 keeps the loads in each face's own step: the prefetch
+  // registers (and those of the blocked triangular products below) would
+  // halve its waves per SIMD, measured slower.
+  constexpr bool kPre = sizeof(R) == 8;
+  constexpr int NXE = NS * NC * NFQ, NHE = NV * NFQ, NPE = NFQ * NB;
+  constexpr int PX = kPre ? (NXE + 127) / 128 : 1, PH = kPre ? (NHE + 127) / 128 : 1;
+  constexpr int PP = kPre ? (NPE + 127) / 128 : 1;
+  // face record of the 2d faces: own +p faces, the -p neighbours' +p faces
+  auto face_of = [&](int hf) {
+    return (size_t)(hf >> 1) * ne + ((hf & 1) ? m.nbr[(size_t)(2 * (hf >> 1)) * ne + e] : e);
+  };
+  size_t fidx[kPre ? 2 * DIM : 1];
+  if constexpr (kPre) {
+#pragma unroll
+    for (int hf = 0; hf < 2 * DIM; ++hf) fidx[hf] = face_of(hf);
+  }
+  R pw[PX], pn[PX], pj[PX], ph_[PH], pp[PP];
+  auto fetch = [&](int hf) {
+    const size_t f = fidx[kPre ? hf : 0];
+    const int p = hf >> 1, ls = (hf & 1) ? 2 * p : 2 * p + 1;
     const R* geo = ct.fGeo + f * GF * NFQ;
-    __syncthreads();
-    for (int i = tid; i < NS * NC * NFQ; i += 128) {
+#pragma unroll
+    for (int u = 0; u < PX; ++u) {
+      const int i = tid + 128 * u < NXE ? tid + 128 * u : NXE - 1;
       const int gq = i % NFQ, k = (i / NFQ) % NC, s = i / (NC * NFQ), c = k / DIM, j = k % DIM;
-      sXs[i] = geo[(size_t)DIM * NFQ + gq] * geo[(size_t)j * NFQ + gq] * ct.fJmp[((f * 2 + s) * NV + c) * NFQ + gq];
+      pw[u] = geo[(size_t)DIM * NFQ + gq];
+      pn[u] = geo[(size_t)j * NFQ + gq];
+      pj[u] = ct.fJmp[((f * 2 + s) * NV + c) * NFQ + gq];
     }
-    for (int i = tid; i < NV * NFQ; i += 128) sXs[NS * NC * NFQ + i] = ct.fHn[f * NV * NFQ + i] * (h ? -1.0 : 1.0);
-    for (int i = tid; i < NFQ * NB; i += 128) sPs[i] = ct.rFPsi[(size_t)ls * NFQ * NB + i];
+#pragma unroll
+    for (int u = 0; u < PH; ++u) ph_[u] = ct.fHn[f * NHE + (tid + 128 * u < NHE ? tid + 128 * u : NHE - 1)];
+#pragma unroll
+    for (int u = 0; u < PP; ++u) pp[u] = ct.rFPsi[(size_t)ls * NPE + (tid + 128 * u < NPE ? tid + 128 * u : NPE - 1)];
+  };
+  if constexpr (kPre) fetch(0);
+  for (int hf = 0; hf < 2 * DIM; ++hf) {
+    const int h = hf & 1;
     __syncthreads();
+    if constexpr (kPre) {
+#pragma unroll
+      for (int u = 0; u < PX; ++u)
+        if (tid + 128 * u < NXE) sXs[tid + 128 * u] = pw[u] * pn[u] * pj[u];
+#pragma unroll
+      for (int u = 0; u < PH; ++u)
+        if (tid + 128 * u < NHE) sXs[NXE + tid + 128 * u] = ph_[u] * (h ? -1.0 : 1.0);
+#pragma unroll
+      for (int u = 0; u < PP; ++u)
+        if (tid + 128 * u < NPE) sPs[tid + 128 * u] = pp[u];
+      __syncthreads();
+      if (hf + 1 < 2 * DIM) fetch(hf + 1);
+    } else {
+      const size_t f = face_of(hf);
+      const int p = hf >> 1, ls = h ? 2 * p : 2 * p + 1;
+      const R* geo = ct.fGeo + f * GF * NFQ;
+      for (int i = tid; i < NXE; i += 128) {
+        const int gq = i % NFQ, k = (i / NFQ) % NC, s = i / (NC * NFQ), c = k / DIM, j = k % DIM;
+        sXs[i] = geo[(size_t)DIM * NFQ + gq] * geo[(size_t)j * NFQ + gq] * ct.fJmp[((f * 2 + s) * NV + c) * NFQ + gq];
+      }
+      for (int i = tid; i < NHE; i += 128) sXs[NXE + i] = ct.fHn[f * NHE + i] * (h ? -1.0 : 1.0);
+      for (int i = tid; i < NPE; i += 128) sPs[i] = ct.rFPsi[(size_t)ls * NPE + i];
+      __syncthreads();
+    }
 #pragma unroll
     for (int t = 0; t < NTW; ++t) {
       const int tile = wv + 2 * t;
@@ -353,25 +406,43 @@ __global__ __launch_bounds__(128) void k_volume_curved(const double* __restrict_
   __syncthreads();
   // the triangular products run uniform loops (one index for every lane) over
   // the row- or column-packed copy that makes neighbouring lanes read
-  // neighbouring words
-  for (int i = tid; i < NA; i += 128) {  // L^{-1} rho_t
-    const int b = i % NB, col = i - b;
-    R acc = 0.0;
+  // neighbouring words; in FP64 each thread takes one mode of RG rows, so
+  // every entry of L^{-1} it reads serves RG products (the sums keep their
+  // order; FP32 keeps one row per thread, see the staging above)
+  constexpr int NROW = NS * NC, RG = sizeof(R) == 8 ? (NROW + 2) / 3 : 1;
+  constexpr int NRG = (NROW + RG - 1) / RG;
+  for (int it = tid; it < NB * NRG; it += 128) {  // L^{-1} rho_t
+    const int b = it % NB, r0 = (it / NB) * RG;
+    R acc[RG];
+#pragma unroll
+    for (int rr = 0; rr < RG; ++rr) acc[rr] = R(0);
     for (int a = 0; a < NB; ++a) {
       const R l = sLc[a * NB - a * (a - 1) / 2 + b - a];
-      acc += (a <= b ? l : R(0)) * sA[col + a];
+      const R lm = a <= b ? l : R(0);
+#pragma unroll
+      for (int rr = 0; rr < RG; ++rr) acc[rr] += lm * sA[(r0 + rr < NROW ? r0 + rr : NROW - 1) * NB + a];
     }
-    sB[i] = acc;
+#pragma unroll
+    for (int rr = 0; rr < RG; ++rr)
+      if (r0 + rr < NROW) sB[(r0 + rr) * NB + b] = acc[rr];
   }
   __syncthreads();
-  for (int i = tid; i < NA; i += 128) {  // Rt = L^{-T} L^{-1} rho_t, value and tangent interleaved
-    const int a = i % NB, col = i - a;
-    R acc = 0.0;
+  for (int it = tid; it < NB * NRG; it += 128) {  // Rt = L^{-T} L^{-1} rho_t, value and tangent interleaved
+    const int a = it % NB, r0 = (it / NB) * RG;
+    R acc[RG];
+#pragma unroll
+    for (int rr = 0; rr < RG; ++rr) acc[rr] = R(0);
     for (int b = 0; b < NB; ++b) {
       const R l = sL[b * (b + 1) / 2 + a];
-      acc += (b >= a ? l : R(0)) * sB[col + b];
+      const R lm = b >= a ? l : R(0);
+#pragma unroll
+      for (int rr = 0; rr < RG; ++rr) acc[rr] += lm * sB[(r0 + rr < NROW ? r0 + rr : NROW - 1) * NB + b];
     }
-    sA[(i % (NC * NB)) * NS + i / (NC * NB)] = acc;
+#pragma unroll
+    for (int rr = 0; rr < RG; ++rr) {
+      const int row = r0 + rr;  // (value/tangent, variable-direction)
+      if (row < NROW) sA[((row % NC) * NB + a) * NS + row / NC] = acc[rr];
+    }
   }
   __syncthreads();
 
