@@ -256,8 +256,11 @@ __global__ __launch_bounds__(64) void k_face_curved(CurvedTablesT<R> ct, Mesh m,
 
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 
+// Launch bound: FP32 at three waves per SIMD (at most 170 registers: room for
+// the prefetched face data below without spills; measured faster than four
+// waves with spills and than the register-lean form at four)
 template <class R, int DIM, int NB, int NQ1, bool JVP>
-__global__ __launch_bounds__(128) void k_volume_curved(const double* __restrict__ V, CurvedTablesT<R> ct,
+__global__ __launch_bounds__(128, sizeof(R) == 8 ? 1 : 3) void k_volume_curved(const double* __restrict__ V, CurvedTablesT<R> ct,
                                                       double* __restrict__ out, double shift, Mesh m, Phys ph) {
   using T = typename Scalar<JVP, R>::type;
   constexpr int NV = DIM + 2, NQ = ipow(NQ1, DIM), NFQ = ipow(NQ1, DIM - 1), NS = JVP ? 2 : 1;
@@ -307,28 +310,18 @@ __global__ __launch_bounds__(128) void k_volume_curved(const double* __restrict_
   const int wv = tid >> 6, ln = tid & 63, li = ln & 15, lg = ln >> 4;
   R* sXs = sB;                  // [NR][NFQ]
   R* sPs = sB + NR * NFQ;       // [NFQ][NB]
-  // FP64: the loads of face hf + 1 are issued before the products of face hf
-  // and land in registers while those run (the staging loads' latency was a
-  // fifth of the kernel); the products w n_j [[U]] are formed at the LDS
-  // write.  FP32 keeps the loads in each face's own step: the prefetch
-  // registers (and those of the blocked triangular products below) would
-  // halve its waves per SIMD, measured slower.
-  constexpr bool kPre = sizeof(R) == 8;
+  // The loads of face hf + 1 are issued before the products of face hf and
+  // land in registers while those run (the staging loads' latency was a fifth
+  // of the kernel); the products w n_j [[U]] are formed at the LDS write.
   constexpr int NXE = NS * NC * NFQ, NHE = NV * NFQ, NPE = NFQ * NB;
-  constexpr int PX = kPre ? (NXE + 127) / 128 : 1, PH = kPre ? (NHE + 127) / 128 : 1;
-  constexpr int PP = kPre ? (NPE + 127) / 128 : 1;
-  // face record of the 2d faces: own +p faces, the -p neighbours' +p faces
-  auto face_of = [&](int hf) {
-    return (size_t)(hf >> 1) * ne + ((hf & 1) ? m.nbr[(size_t)(2 * (hf >> 1)) * ne + e] : e);
-  };
-  size_t fidx[kPre ? 2 * DIM : 1];
-  if constexpr (kPre) {
+  constexpr int PX = (NXE + 127) / 128, PH = (NHE + 127) / 128, PP = (NPE + 127) / 128;
+  size_t fidx[2 * DIM];  // face record of the 2d faces: own +p faces, the -p neighbours' +p faces
 #pragma unroll
-    for (int hf = 0; hf < 2 * DIM; ++hf) fidx[hf] = face_of(hf);
-  }
+  for (int hf = 0; hf < 2 * DIM; ++hf)
+    fidx[hf] = (size_t)(hf >> 1) * ne + ((hf & 1) ? m.nbr[(size_t)(2 * (hf >> 1)) * ne + e] : e);
   R pw[PX], pn[PX], pj[PX], ph_[PH], pp[PP];
   auto fetch = [&](int hf) {
-    const size_t f = fidx[kPre ? hf : 0];
+    const size_t f = fidx[hf];
     const int p = hf >> 1, ls = (hf & 1) ? 2 * p : 2 * p + 1;
     const R* geo = ct.fGeo + f * GF * NFQ;
 #pragma unroll
@@ -344,34 +337,21 @@ __global__ __launch_bounds__(128) void k_volume_curved(const double* __restrict_
 #pragma unroll
     for (int u = 0; u < PP; ++u) pp[u] = ct.rFPsi[(size_t)ls * NPE + (tid + 128 * u < NPE ? tid + 128 * u : NPE - 1)];
   };
-  if constexpr (kPre) fetch(0);
+  fetch(0);
   for (int hf = 0; hf < 2 * DIM; ++hf) {
     const int h = hf & 1;
     __syncthreads();
-    if constexpr (kPre) {
 #pragma unroll
-      for (int u = 0; u < PX; ++u)
-        if (tid + 128 * u < NXE) sXs[tid + 128 * u] = pw[u] * pn[u] * pj[u];
+    for (int u = 0; u < PX; ++u)
+      if (tid + 128 * u < NXE) sXs[tid + 128 * u] = pw[u] * pn[u] * pj[u];
 #pragma unroll
-      for (int u = 0; u < PH; ++u)
-        if (tid + 128 * u < NHE) sXs[NXE + tid + 128 * u] = ph_[u] * (h ? -1.0 : 1.0);
+    for (int u = 0; u < PH; ++u)
+      if (tid + 128 * u < NHE) sXs[NXE + tid + 128 * u] = ph_[u] * (h ? -1.0 : 1.0);
 #pragma unroll
-      for (int u = 0; u < PP; ++u)
-        if (tid + 128 * u < NPE) sPs[tid + 128 * u] = pp[u];
-      __syncthreads();
-      if (hf + 1 < 2 * DIM) fetch(hf + 1);
-    } else {
-      const size_t f = face_of(hf);
-      const int p = hf >> 1, ls = h ? 2 * p : 2 * p + 1;
-      const R* geo = ct.fGeo + f * GF * NFQ;
-      for (int i = tid; i < NXE; i += 128) {
-        const int gq = i % NFQ, k = (i / NFQ) % NC, s = i / (NC * NFQ), c = k / DIM, j = k % DIM;
-        sXs[i] = geo[(size_t)DIM * NFQ + gq] * geo[(size_t)j * NFQ + gq] * ct.fJmp[((f * 2 + s) * NV + c) * NFQ + gq];
-      }
-      for (int i = tid; i < NHE; i += 128) sXs[NXE + i] = ct.fHn[f * NHE + i] * (h ? -1.0 : 1.0);
-      for (int i = tid; i < NPE; i += 128) sPs[i] = ct.rFPsi[(size_t)ls * NPE + i];
-      __syncthreads();
-    }
+    for (int u = 0; u < PP; ++u)
+      if (tid + 128 * u < NPE) sPs[tid + 128 * u] = pp[u];
+    __syncthreads();
+    if (hf + 1 < 2 * DIM) fetch(hf + 1);
 #pragma unroll
     for (int t = 0; t < NTW; ++t) {
       const int tile = wv + 2 * t;
@@ -406,11 +386,9 @@ __global__ __launch_bounds__(128) void k_volume_curved(const double* __restrict_
   __syncthreads();
   // the triangular products run uniform loops (one index for every lane) over
   // the row- or column-packed copy that makes neighbouring lanes read
-  // neighbouring words; in FP64 each thread takes one mode of RG rows, so
-  // every entry of L^{-1} it reads serves RG products (the sums keep their
-  // order; FP32 keeps one row per thread, see the staging above)
-  constexpr int NROW = NS * NC, RG = sizeof(R) == 8 ? (NROW + 2) / 3 : 1;
-  constexpr int NRG = (NROW + RG - 1) / RG;
+  // neighbouring words; each thread takes one mode of RG rows, so every
+  // entry of L^{-1} it reads serves RG products (the sums keep their order)
+  constexpr int NROW = NS * NC, RG = (NROW + 2) / 3, NRG = (NROW + RG - 1) / RG;
   for (int it = tid; it < NB * NRG; it += 128) {  // L^{-1} rho_t
     const int b = it % NB, r0 = (it / NB) * RG;
     R acc[RG];
