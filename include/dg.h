@@ -99,7 +99,10 @@ enum { DG_PHYS_COMPRESSIBLE = 0, DG_PHYS_INCOMPRESSIBLE = 1, DG_PHYS_DIFFUSION =
  *  (vector-ALU) kernels, FP64 only (no FP32/BF16 operator, no network).
  *  physics DG_PHYS_DIFFUSION: the scalar BR2 Laplacian of the paper's
  *  Poisson assessment (App. B): one variable, residual of -div(mu grad u)
- *  (no convective flux); uniform lattices, reference kernels, FP64 only. */
+ *  (no convective flux); FP64 only, reference kernels on uniform lattices,
+ *  the curved-element kernels on distorted 2D meshes at P2, P3 and P6
+ *  (DG_ERR_ARG for other curved configurations); dg_max_wave_speed refuses
+ *  it on curved meshes. */
 typedef struct {
   int dim, order, basis, nq1d, flux;
   double gamma, prandtl, mu, eta_br2, entropy_fix;

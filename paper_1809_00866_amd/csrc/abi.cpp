@@ -274,8 +274,7 @@ dg_status dg_create(const dg_params* prm, const dg_mesh* mesh, dg_context** out)
   } catch (const std::exception& ex) {
     return fail(DG_ERR_ARG, ex.what());
   }
-  if (!compressible && !lattice)
-    return fail(DG_ERR_ARG, "the incompressible and diffusion equations run on uniform lattices only");
+  if (ins && !lattice) return fail(DG_ERR_ARG, "the incompressible equations run on uniform lattices only");
   dgh::CurvedHost CH;  // curved (non-lattice) meshes: built before any device work
   if (!lattice) {
     try {
@@ -285,7 +284,7 @@ dg_status dg_create(const dg_params* prm, const dg_mesh* mesh, dg_context** out)
     }
   }
   const int cfg = dgk::config_index(dim, T.nb, prm->nq1d);
-  if (cfg < 0 || (!lattice && !dgk::has_curved(cfg)))
+  if (cfg < 0 || (!lattice && !dgk::has_curved(cfg, diffusion)))
     return fail(DG_ERR_ARG, std::string("no ") + (lattice ? "" : "curved-element ") + "kernel compiled for dim=" +
                                 std::to_string(dim) + " nbasis=" + std::to_string(T.nb) +
                                 " nq1d=" + std::to_string(prm->nq1d));
@@ -408,6 +407,7 @@ dg_status dg_create(const dg_params* prm, const dg_mesh* mesh, dg_context** out)
       c->ctf.fJmp = c->d_cwork_f + 2 * nx;
       c->ctf.fHn = c->d_cwork_f + 2 * nx + 2 * nfp;
     }
+    c->ct.diffusion = c->ctf.diffusion = diffusion ? 1 : 0;
     c->curved = true;
   }
 
@@ -714,6 +714,8 @@ dg_status dg_max_wave_speed(dg_context* c, const double* w, double* out, void* s
   if (!c || !w || !out) return fail(DG_ERR_ARG, "null argument");
   hipStream_t s = (hipStream_t)stream;
   const int nblk = 1024;
+  if (c->curved && c->ct.diffusion)
+    return fail(DG_ERR_ARG, "the maximum wave speed is defined for the compressible equations on curved meshes");
   if (c->curved)
     HIPCHK(dgk::launch_wave_speed_curved(c->cfg, w, c->d_red, nblk, c->ct, c->mesh, c->ph, s));
   else

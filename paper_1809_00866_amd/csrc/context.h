@@ -156,7 +156,8 @@ struct ProfScope {
 // True when the reduced-precision (FP32) operator exists for this context:
 // the 3D P2-P4 MFMA kernels on lattices, the curved kernels on curved meshes.
 inline bool has_f32(const dg_context* c) {
-  return (c->use_mfma && c->d_mtab_f && c->d_Hf && c->d_Gf) || (c->curved && c->d_curved_f && c->d_cwork_f);
+  return (c->use_mfma && c->d_mtab_f && c->d_Hf && c->d_Gf) ||
+         (c->curved && c->d_curved_f && c->d_cwork_f && !c->ct.diffusion);
 }
 // True when the operator of precision prec (DG_FP64, DG_FP32 or DG_BF16: BF16
 // contractions, the 3D P2-P4 lattice MFMA kernels only) exists.

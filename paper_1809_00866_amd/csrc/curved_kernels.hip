@@ -73,10 +73,13 @@ struct CMma<float> {
   static DEV int drow(int g, int r) { return 4 * g + r; }
 };
 
-template <class R, int DIM, int NB, bool JVP>
+// DIFF (all kernels below): the scalar Laplacian of the Poisson assessment
+// (one variable, no convective flux, F^v = mu grad u) instead of the
+// compressible equations.
+template <class R, int DIM, int NB, bool JVP, bool DIFF = false>
 __global__ __launch_bounds__(64) void k_modal_curved(const double* __restrict__ U, const double* __restrict__ V,
                                                      CurvedTablesT<R> ct, int64_t ne) {
-  constexpr int NV = DIM + 2, NBT = NB * (NB + 1) / 2, NS = JVP ? 2 : 1, NX = NV * NB;
+  constexpr int NV = DIFF ? 1 : DIM + 2, NBT = NB * (NB + 1) / 2, NS = JVP ? 2 : 1, NX = NV * NB;
   __shared__ R sL[NBT];
   __shared__ R sX[NS * NX];
   const int tid = threadIdx.x;
@@ -95,10 +98,10 @@ __global__ __launch_bounds__(64) void k_modal_curved(const double* __restrict__ 
   }
 }
 
-template <class R, int DIM, int NB, int NQ1, bool JVP>
+template <class R, int DIM, int NB, int NQ1, bool JVP, bool DIFF = false>
 __global__ __launch_bounds__(64) void k_face_curved(CurvedTablesT<R> ct, Mesh m, Phys ph) {
   using T = typename Scalar<JVP, R>::type;
-  constexpr int NV = DIM + 2, NFQ = ipow(NQ1, DIM - 1), NS = JVP ? 2 : 1, NC = NV * DIM, NX = NV * NB;
+  constexpr int NV = DIFF ? 1 : DIM + 2, NFQ = ipow(NQ1, DIM - 1), NS = JVP ? 2 : 1, NC = NV * DIM, NX = NV * NB;
   constexpr int GF = DIM + 1 + 2 * DIM * DIM, NTR = NV * (1 + DIM);
   static_assert(NFQ <= 32, "one lane per (side, face point)");
   constexpr int NW = 2 * NS * NX > NS * NC * NFQ ? 2 * NS * NX : NS * NC * NFQ;
@@ -221,14 +224,17 @@ __global__ __launch_bounds__(64) void k_face_curved(CurvedTablesT<R> ct, Mesh m,
   if (act) {
     T Hp[NV];
     if (side == 0) {
-      T uL[NV], uR[NV];
-      for (int c = 0; c < NV; ++c) {
-        uL[c] = mk<JVP, R>(sT[0][0][c][fq], tr ? sT[0][NS - 1][c][fq] : R(0));
-        uR[c] = mk<JVP, R>(sT[1][0][c][fq], tr ? sT[1][NS - 1][c][fq] : R(0));
+      if constexpr (DIFF) {
+        Hp[0] = R(0);  // no convective flux
+      } else {
+        T uL[NV], uR[NV];
+        for (int c = 0; c < NV; ++c) {
+          uL[c] = mk<JVP, R>(sT[0][0][c][fq], tr ? sT[0][NS - 1][c][fq] : R(0));
+          uR[c] = mk<JVP, R>(sT[1][0][c][fq], tr ? sT[1][NS - 1][c][fq] : R(0));
+        }
+        num_flux_n<T, DIM>(uL, uR, n, ph, Hp);
       }
-      num_flux_n<T, DIM>(uL, uR, n, ph, Hp);
     } else {
-      const double kap = ph.mu * ph.gamma / (ph.prandtl * (ph.gamma - 1.0));
       T ua[NV], Ga[NV][DIM];
       for (int c = 0; c < NV; ++c) {
         ua[c] = R(0.5) * mk<JVP, R>(sT[0][0][c][fq] + sT[1][0][c][fq],
@@ -240,13 +246,19 @@ __global__ __launch_bounds__(64) void k_face_curved(CurvedTablesT<R> ct, Mesh m,
                      (R)ph.eta * mk<JVP, R>(sR[0][c * DIM + i][fq], sR[NS - 1][c * DIM + i][fq]);
         }
       }
-      ViscPrep<T, DIM> vp;
-      visc_prep<T, DIM>(ua, Ga, ph.gamma, vp);
-      for (int c = 0; c < NV; ++c) Hp[c] = 0.0;
-      for (int j = 0; j < DIM; ++j) {
-        T Fv[NV];
-        visc_flux_dir<T, DIM>(vp, j, ph.mu, kap, Fv);
-        for (int c = 0; c < NV; ++c) Hp[c] -= (R)n[j] * Fv[c];
+      if constexpr (DIFF) {  // -mu {grad u + eta r}.n
+        Hp[0] = 0.0;
+        for (int j = 0; j < DIM; ++j) Hp[0] -= (R)n[j] * ((R)ph.mu * Ga[0][j]);
+      } else {
+        const double kap = ph.mu * ph.gamma / (ph.prandtl * (ph.gamma - 1.0));
+        ViscPrep<T, DIM> vp;
+        visc_prep<T, DIM>(ua, Ga, ph.gamma, vp);
+        for (int c = 0; c < NV; ++c) Hp[c] = 0.0;
+        for (int j = 0; j < DIM; ++j) {
+          T Fv[NV];
+          visc_flux_dir<T, DIM>(vp, j, ph.mu, kap, Fv);
+          for (int c = 0; c < NV; ++c) Hp[c] -= (R)n[j] * Fv[c];
+        }
       }
     }
     for (int c = 0; c < NV; ++c) sH[side][c][fq] = out_part(Hp[c]);
@@ -263,11 +275,11 @@ constexpr int cmax(int a, int b) { return a > b ? a : b; }
 // Launch bound: FP32 at three waves per SIMD (at most 170 registers: room for
 // the prefetched face data below without spills; measured faster than four
 // waves with spills and than the register-lean form at four)
-template <class R, int DIM, int NB, int NQ1, bool JVP>
+template <class R, int DIM, int NB, int NQ1, bool JVP, bool DIFF = false>
 __global__ __launch_bounds__(128, sizeof(R) == 8 ? 1 : 3) void k_volume_curved(const double* __restrict__ V, CurvedTablesT<R> ct,
                                                       double* __restrict__ out, double shift, Mesh m, Phys ph) {
   using T = typename Scalar<JVP, R>::type;
-  constexpr int NV = DIM + 2, NQ = ipow(NQ1, DIM), NFQ = ipow(NQ1, DIM - 1), NS = JVP ? 2 : 1;
+  constexpr int NV = DIFF ? 1 : DIM + 2, NQ = ipow(NQ1, DIM), NFQ = ipow(NQ1, DIM - 1), NS = JVP ? 2 : 1;
   constexpr int NBT = NB * (NB + 1) / 2, NC = NV * DIM, NX = NV * NB, GV = DIM * DIM + 1;
   constexpr int GF = DIM + 1 + 2 * DIM * DIM;
   constexpr int NA = NS * NC * NB, NF = NQ * DIM * NV;
@@ -471,20 +483,27 @@ __global__ __launch_bounds__(128, sizeof(R) == 8 ? 1 : 3) void k_volume_curved(c
         for (int r = 0; r < DIM; ++r)
           G[c][r] += pb * ld2<JVP, R>(sA + ((c * DIM + r) * NB + b) * NS);
     }
-    T rinv, vel[DIM], pr;
-    primitives<T, DIM>(u, ph.gamma, rinv, vel, pr);
-    ViscPrep<T, DIM> vp;
-    visc_prep<T, DIM>(u, G, ph.gamma, vp);
     R Ft[DIM][NV];
     for (int r = 0; r < DIM; ++r)
       for (int c = 0; c < NV; ++c) Ft[r][c] = 0.0;
-    for (int p = 0; p < DIM; ++p) {
-      T Fc[NV], Fv[NV];
-      conv_flux_dir<T, DIM>(u, vel, pr, p, Fc);
-      visc_flux_dir<T, DIM>(vp, p, ph.mu, kap, Fv);
-      for (int c = 0; c < NV; ++c) {
-        const R fp = out_part(Fc[c] - Fv[c]);
-        for (int r = 0; r < DIM; ++r) Ft[r][c] += K[p][r] * fp;
+    if constexpr (DIFF) {  // F_p = -mu G_p
+      for (int p = 0; p < DIM; ++p) {
+        const R fp = out_part(-(R)ph.mu * G[0][p]);
+        for (int r = 0; r < DIM; ++r) Ft[r][0] += K[p][r] * fp;
+      }
+    } else {
+      T rinv, vel[DIM], pr;
+      primitives<T, DIM>(u, ph.gamma, rinv, vel, pr);
+      ViscPrep<T, DIM> vp;
+      visc_prep<T, DIM>(u, G, ph.gamma, vp);
+      for (int p = 0; p < DIM; ++p) {
+        T Fc[NV], Fv[NV];
+        conv_flux_dir<T, DIM>(u, vel, pr, p, Fc);
+        visc_flux_dir<T, DIM>(vp, p, ph.mu, kap, Fv);
+        for (int c = 0; c < NV; ++c) {
+          const R fp = out_part(Fc[c] - Fv[c]);
+          for (int r = 0; r < DIM; ++r) Ft[r][c] += K[p][r] * fp;
+        }
       }
     }
     for (int r = 0; r < DIM; ++r)
@@ -527,10 +546,10 @@ __global__ __launch_bounds__(128, sizeof(R) == 8 ? 1 : 3) void k_volume_curved(c
 }
 
 // w = L^{-1} sum_q w_q|J_q| psi(xi_q) f_q
-template <int DIM, int NB, int NQ1>
+template <int DIM, int NB, int NQ1, bool DIFF = false>
 __global__ __launch_bounds__(64) void k_project_curved(const double* __restrict__ f, double* __restrict__ w,
                                                        CurvedTables ct, int64_t ne) {
-  constexpr int NV = DIM + 2, NQ = ipow(NQ1, DIM), NBT = NB * (NB + 1) / 2, GV = DIM * DIM + 1;
+  constexpr int NV = DIFF ? 1 : DIM + 2, NQ = ipow(NQ1, DIM), NBT = NB * (NB + 1) / 2, GV = DIM * DIM + 1;
   __shared__ double sT[NV * NB];
   const int64_t e = blockIdx.x;
   const double* wd = ct.vGeo + ((size_t)e * GV + DIM * DIM) * NQ;
@@ -596,15 +615,24 @@ __global__ __launch_bounds__(256) void k_wave_speed_curved(double* __restrict__ 
   X(3, 3, 10, 3)             \
   X(4, 3, 20, 4)             \
   X(5, 3, 35, 5)
+// the scalar Laplacian of the Poisson assessment: 2D P2 / P3 / P6, FP64
+#define DG_CURVED_DIFF_CONFIGS(X) \
+  X(1, 2, 6, 4)                   \
+  X(7, 2, 10, 5)                  \
+  X(8, 2, 28, 8)
 
 }  // namespace dgk
 
 namespace dgk {
 
-bool has_curved(int cfg) {
+bool has_curved(int cfg, bool diffusion) {
 #define X(id, d, nb_, nq_) \
   if (cfg == id) return true;
-  DG_CURVED_CONFIGS(X)
+  if (diffusion) {
+    DG_CURVED_DIFF_CONFIGS(X)
+  } else {
+    DG_CURVED_CONFIGS(X)
+  }
 #undef X
   return false;
 }
@@ -614,6 +642,21 @@ namespace {
 template <class R>
 hipError_t modal_curved(int cfg, bool jvp, const double* U, const double* V, const CurvedTablesT<R>& ct, int64_t ne,
                         hipStream_t s) {
+  if (ct.diffusion) {  // FP64 only
+    if constexpr (sizeof(R) == 8) {
+#define X(id, d, nb_, nq_)                                                                  \
+  case id: {                                                                                \
+    if (jvp)                                                                                \
+      k_modal_curved<R, d, nb_, true, true><<<(unsigned)ne, 64, 0, s>>>(U, V, ct, ne);      \
+    else                                                                                    \
+      k_modal_curved<R, d, nb_, false, true><<<(unsigned)ne, 64, 0, s>>>(U, V, ct, ne);     \
+    return hipGetLastError();                                                               \
+  }
+      switch (cfg) { DG_CURVED_DIFF_CONFIGS(X) }
+#undef X
+    }
+    return hipErrorInvalidValue;
+  }
 #define X(id, d, nb_, nq_)                                                          \
   case id: {                                                                        \
     if (jvp)                                                                        \
@@ -629,6 +672,22 @@ hipError_t modal_curved(int cfg, bool jvp, const double* U, const double* V, con
 
 template <class R>
 hipError_t face_curved(int cfg, bool jvp, const CurvedTablesT<R>& ct, const Mesh& m, const Phys& ph, hipStream_t s) {
+  if (ct.diffusion) {
+    if constexpr (sizeof(R) == 8) {
+#define X(id, d, nb_, nq_)                                                          \
+  case id: {                                                                        \
+    dim3 grid((unsigned)m.ne, d);                                                   \
+    if (jvp)                                                                        \
+      k_face_curved<R, d, nb_, nq_, true, true><<<grid, 64, 0, s>>>(ct, m, ph);     \
+    else                                                                            \
+      k_face_curved<R, d, nb_, nq_, false, true><<<grid, 64, 0, s>>>(ct, m, ph);    \
+    return hipGetLastError();                                                       \
+  }
+      switch (cfg) { DG_CURVED_DIFF_CONFIGS(X) }
+#undef X
+    }
+    return hipErrorInvalidValue;
+  }
 #define X(id, d, nb_, nq_)                                                          \
   case id: {                                                                        \
     dim3 grid((unsigned)m.ne, d);                                                   \
@@ -646,6 +705,21 @@ hipError_t face_curved(int cfg, bool jvp, const CurvedTablesT<R>& ct, const Mesh
 template <class R>
 hipError_t volume_curved(int cfg, bool jvp, const double* V, const CurvedTablesT<R>& ct, double* out, double shift,
                          const Mesh& m, const Phys& ph, hipStream_t s) {
+  if (ct.diffusion) {
+    if constexpr (sizeof(R) == 8) {
+#define X(id, d, nb_, nq_)                                                                                \
+  case id: {                                                                                              \
+    if (jvp)                                                                                              \
+      k_volume_curved<R, d, nb_, nq_, true, true><<<(unsigned)m.ne, 128, 0, s>>>(V, ct, out, shift, m, ph);  \
+    else                                                                                                  \
+      k_volume_curved<R, d, nb_, nq_, false, true><<<(unsigned)m.ne, 128, 0, s>>>(V, ct, out, shift, m, ph); \
+    return hipGetLastError();                                                                             \
+  }
+      switch (cfg) { DG_CURVED_DIFF_CONFIGS(X) }
+#undef X
+    }
+    return hipErrorInvalidValue;
+  }
 #define X(id, d, nb_, nq_)                                                                          \
   case id: {                                                                                        \
     if (jvp)                                                                                        \
@@ -688,6 +762,16 @@ hipError_t launch_volume_curved_f32(int cfg, bool jvp, const double* V, const Cu
 
 hipError_t launch_project_curved(int cfg, const double* f, double* w, const CurvedTables& ct, int64_t ne,
                                  hipStream_t s) {
+  if (ct.diffusion) {
+#define X(id, d, nb_, nq_)                                                               \
+  case id: {                                                                             \
+    k_project_curved<d, nb_, nq_, true><<<(unsigned)ne, 64, 0, s>>>(f, w, ct, ne);       \
+    return hipGetLastError();                                                            \
+  }
+    switch (cfg) { DG_CURVED_DIFF_CONFIGS(X) }
+#undef X
+    return hipErrorInvalidValue;
+  }
 #define X(id, d, nb_, nq_)                                                         \
   case id: {                                                                       \
     k_project_curved<d, nb_, nq_><<<(unsigned)ne, 64, 0, s>>>(f, w, ct, ne);       \
@@ -700,6 +784,7 @@ hipError_t launch_project_curved(int cfg, const double* f, double* w, const Curv
 
 hipError_t launch_wave_speed_curved(int cfg, const double* w, double* partial, int nblocks, const CurvedTables& ct,
                                     const Mesh& m, const Phys& ph, hipStream_t s) {
+  if (ct.diffusion) return hipErrorInvalidValue;  // the wave speed of the compressible equations
 #define X(id, d, nb_, nq_)                                                                  \
   case id: {                                                                                \
     k_modal_curved<double, d, nb_, false><<<(unsigned)m.ne, 64, 0, s>>>(w, w, ct, m.ne);            \

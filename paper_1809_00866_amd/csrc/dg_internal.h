@@ -42,6 +42,7 @@ struct CurvedTablesT {
   R *Ut, *Vt;  // [ne][nv][nb]          L^{-T} U and L^{-T} V
   R* fJmp;     // [dim*ne][2][nv][nfq]  [[U]] at the face points (value, tangent)
   R* fHn;      // [dim*ne][nv][nfq]     w_f|J_f| times the normal flux (or its tangent)
+  int diffusion = 0;  // the scalar BR2 Laplacian (nv = 1) instead of the compressible equations
 };
 using CurvedTables = CurvedTablesT<double>;
 using CurvedTablesF = CurvedTablesT<float>;  // the reduced-precision curved operator
@@ -94,8 +95,9 @@ hipError_t launch_volume(int cfg, bool jvp, const double* U, const double* V, co
                          double shift, const Tables& tb, const Mesh& m, const Phys& ph, hipStream_t stream);
 // MFMA kernels (3D); return hipErrorInvalidValue when the configuration has none.
 bool has_mfma(int cfg);
-// Curved-element kernels compiled for the configuration.
-bool has_curved(int cfg);
+// Curved-element kernels compiled for the configuration (the compressible
+// equations, or the scalar Laplacian on 2D P2/P3/P6 meshes).
+bool has_curved(int cfg, bool diffusion = false);
 // occ: minimum waves per SIMD of the face / volume kernel's launch bound (1 or
 // 2; 0 = the configuration's default); hipErrorInvalidValue for a shape the
 // configuration does not have (mfma_occ_fits).  Every occupancy computes the

@@ -111,8 +111,8 @@ def test_null_arguments():
 
 
 def test_create_checks_the_physics_model_on_the_host():
-    """Unknown physics and the incompressible equations on a curved mesh are
-    refused before any device work."""
+    """Unknown physics, the incompressible equations on a curved mesh and the
+    Laplacian on a 3D curved mesh are refused before any device work."""
     prm = _prm(order=2, nq=3)
     prm.physics = 7
     st, msg = _create(prm, synth.lattice_mesh((2, 2, 2)))
@@ -120,3 +120,6 @@ def test_create_checks_the_physics_model_on_the_host():
     prm.physics = L.DG_PHYS_INCOMPRESSIBLE
     st, msg = _create(prm, synth.lattice_mesh((2, 2, 2), perturb=0.1, seed=1))
     assert st == -1 and "lattice" in msg
+    prm.physics = L.DG_PHYS_DIFFUSION  # the Laplacian on distorted meshes: 2D P2/P3/P6 only
+    st, msg = _create(prm, synth.lattice_mesh((2, 2, 2), perturb=0.1, seed=1))
+    assert st == -1 and "curved-element kernel" in msg

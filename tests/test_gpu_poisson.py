@@ -3,7 +3,10 @@ assessment, App. B) against the FP64 oracle, through the C ABI: residual and
 Jv at 2D P2/P3/P6 (1e-12), the BR2 stabilisation part of the Jacobian that
 the rescaled-inherited coarse operators need (1e-12), and the k = 6 V-cycle
 with three levels 6/3/1 (Table Poisson3L's coarsening), inherited and
-rescaled-inherited (App. A), coarse operators 1e-12 and one cycle 1e-9.
+rescaled-inherited (App. A), coarse operators 1e-12 and one cycle 1e-9 --
+on uniform lattices and on distorted quadrilaterals (every vertex moved by
+up to 0.1 h: the curved-element kernels with per-element orthonormal bases,
+standing in for the paper's distorted-quadrilateral meshes).
 """
 import sys
 
@@ -25,9 +28,9 @@ def _say(msg):
     sys.stdout.flush()
 
 
-def make_case(N, k, nq, seed=3):
+def make_case(N, k, nq, seed=3, perturb=0.0):
     from paper_1809_00866_amd import DG
-    mesh = synth.lattice_mesh(N, L=1.0)
+    mesh = synth.lattice_mesh(N, L=1.0, perturb=perturb, seed=seed + 100 if perturb else None)
     o = DGOracle(mesh, k, "P", nq, Diffusion(len(N), mu=MU))
     U = np.random.default_rng(seed).standard_normal((o.ne, 1, o.nb))
     g = DG(mesh, k, nq1d=nq, mu=MU, physics="diffusion")
@@ -39,10 +42,11 @@ def rel(a, b):
     return np.linalg.norm(np.asarray(a) - b) / max(np.linalg.norm(b), 1e-300)
 
 
+@pytest.mark.parametrize("perturb", [0.0, 0.1], ids=["lattice", "distorted"])
 @pytest.mark.parametrize("N,k,nq", [((4, 3), 2, 4), ((3, 5), 3, 5), ((3, 2), 6, 8)], ids=["P2", "P3", "P6"])
-def test_laplacian_residual_jvp_and_stabilisation_parity(N, k, nq):
-    _say(f"BR2 Laplacian {N} P{k}")
-    o, g, U, w = make_case(N, k, nq)
+def test_laplacian_residual_jvp_and_stabilisation_parity(N, k, nq, perturb):
+    _say(f"BR2 Laplacian {N} P{k} perturb {perturb}")
+    o, g, U, w = make_case(N, k, nq, perturb=perturb)
     assert g.nv == 1
     R, Rv = o.residual(U, return_parts=True)
     err = np.linalg.norm(g.residual(w).cpu().numpy() - o.to_flat(R)) / max(np.linalg.norm(R), np.linalg.norm(Rv))
@@ -54,10 +58,11 @@ def test_laplacian_residual_jvp_and_stabilisation_parity(N, k, nq):
     g.close()
 
 
+@pytest.mark.parametrize("perturb", [0.0, 0.1], ids=["lattice", "distorted"])
 @pytest.mark.parametrize("rescale", [False, True], ids=["inherited", "rescaled"])
-def test_k6_three_level_vcycle_matches_the_oracle(rescale):
-    _say(f"k=6 V-cycle 6/3/1, rescale={rescale}")
-    o, g, U, w = make_case((4, 4), 6, 8)
+def test_k6_three_level_vcycle_matches_the_oracle(rescale, perturb):
+    _say(f"k=6 V-cycle 6/3/1, rescale={rescale}, perturb {perturb}")
+    o, g, U, w = make_case((4, 4), 6, 8, perturb=perturb)
     shift, orders, iters = 1.0, (6, 3, 1), (1, 1, 40)
     mg = PMultigrid(o, U, shift, orders, iters, rescale=rescale)
     g.mg_setup(w, shift, orders, iters, storage="fp64", use_graph=True, rescale=rescale)
@@ -75,4 +80,20 @@ def test_k6_three_level_vcycle_matches_the_oracle(rescale):
     b = torch.tensor(o.to_flat(rng.standard_normal(U.shape)), device="cuda")
     x, st = g.fgmres(w, shift, b, restart=30, rtol=1e-10, max_iter=200, precond="mg")
     assert st["converged"] == 1 and st["rel_res_true"] <= 1e-10
+    g.close()
+
+
+def test_distorted_mesh_refusals():
+    """On distorted quadrilaterals the Laplacian has no FP32 operator and no
+    wave speed (the compressible equations' quantity): both are refused with
+    DG_ERR_ARG, and nothing is written."""
+    from paper_1809_00866_amd._lib import DGError
+    _say("distorted-mesh refusals")
+    o, g, U, w = make_case((3, 3), 2, 4, perturb=0.1)
+    with pytest.raises(DGError) as ei:
+        g.residual(w, precision="fp32")
+    assert ei.value.status == -1
+    with pytest.raises(DGError) as ei:
+        g.max_wave_speed(w)
+    assert ei.value.status == -1
     g.close()
