@@ -422,7 +422,7 @@ dg_status dg_create(const dg_params* prm, const dg_mesh* mesh, dg_context** out)
     } catch (const std::exception& ex) {
       return cleanup(fail(DG_ERR_ARG, ex.what()));
     }
-    std::vector<const std::vector<double>*> mp = {&M.vA, &M.pA, &M.fA, &M.tA, &M.lA, &M.dA};
+    std::vector<const std::vector<double>*> mp = {&M.vA, &M.pA64, &M.fA64, &M.tA, &M.lA64, &M.dA};
     size_t mtot = 0;
     for (auto* v : mp) mtot += v->size();
     if ((st = dalloc(&c->d_mtab, mtot)) != DG_OK) return cleanup(st);

@@ -287,6 +287,10 @@ CurvedHost build_curved_tables(const HostTables& T, int order, const double* xyz
 
 struct MfmaHost {
   std::vector<double> vA, pA, fA, tA, lA;
+  // FP64 copies of pA, fA, lA whose last mode block, when it holds at most 4
+  // live rows (P3, P4), is laid out for the 4-block 4x4x4 FP64 MFMA: lane l
+  // of a k-step fragment holds A[row l % 4][k-step row l / 16]
+  std::vector<double> pA64, fA64, lA64;
   std::vector<double> vAf;  // interpolation table in the FP32 fragment order (4 MB k-steps per point block)
   std::vector<double> dA, dAf;  // face point-to-point maps, FP64 / FP32 result-row order
   int kl = 0;

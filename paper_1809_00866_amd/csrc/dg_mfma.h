@@ -112,6 +112,27 @@ DEV typename MM::frag chain(const FA& a, const FB& b, typename MM::frag d) {
   return d;
 }
 
+// FP64 contractions over the modes whose last 16-row mode block holds at most
+// 4 live rows (P3: modes 16-19, P4: 32-34) run that block on the 4-block
+// 4x4x4 instruction instead of a 16x16x4 tile three quarters zeros: the same
+// rate per flop, a quarter of the passes.  Block v of the instruction takes
+// A[w][k] from lane 16 k + 4 v + w (the FP64 tables' last mode block holds
+// row l % 4 in lane l), B[k][u] from lane 16 k + 4 v + u -- the 16x16x4 B
+// fragment unchanged, column 4 v + u -- and returns D[w][u] in lane
+// 16 w + 4 v + u: row g = lane / 16 of column lane % 16, where the 16x16x4
+// result keeps row g in its register 0 (measured on the device).
+template <class MM, int NB>
+constexpr bool rem4() {
+  constexpr int MB = (NB + 15) / 16;
+  return std::is_same<MM, MP<double>>::value && MB >= 2 && NB - 16 * (MB - 1) <= 4;
+}
+template <int NK, class FA, class FB>
+DEV double chain4(const FA& a, const FB& b, double d) {
+#pragma unroll
+  for (int ks = 0; ks < NK; ++ks) d = __builtin_amdgcn_mfma_f64_4x4x4f64(a(ks), b(ks), d, 0, 0, 0);
+  return d;
+}
+
 // Tile processed by this workgroup.  Workgroups are dispatched round-robin
 // over the 8 XCDs (each with its own L2); giving every XCD a contiguous range
 // of tiles keeps a tile's face neighbours (x: adjacent tiles, y: 2 tiles
@@ -164,9 +185,11 @@ __global__ __launch_bounds__(64) void k_grad_mfma(const double* __restrict__ U, 
     }
     // FP64 P4: one mode block at a time (all three unrolled hold their A
     // operands in flight and leave one wave per SIMD)
+    constexpr bool kRem = rem4<MM, NB>();
+    constexpr int MBM = kRem ? MB - 1 : MB;  // 16x16x4 mode blocks
     constexpr int kMbUnroll = (sizeof(R) == 8 && MB > 2) ? 1 : MB;
 #pragma unroll kMbUnroll
-    for (int mb = 0; mb < MB; ++mb) {
+    for (int mb = 0; mb < MBM; ++mb) {
       const R* __restrict__ la = lA + ((size_t)p * MB + mb) * 3 * KSB * 64 + lane;
       F d = chain<MM, 3 * KSB>([&](int ks3) { return la[ks3 * 64]; }, [&](int ks3) { return bf[ks3]; },
                                F{0, 0, 0, 0});
@@ -182,6 +205,12 @@ __global__ __launch_bounds__(64) void k_grad_mfma(const double* __restrict__ U, 
         const int b = 16 * mb + MM::drow(g, r);
         if (ev && b < NB) Gm[((size_t)((s * DIM + p) * NV + c) * NB + b) * ne + e] = d[r];
       }
+    }
+    if constexpr (kRem) {  // the last mode block: row g of column col
+      const R* __restrict__ la = lA + ((size_t)p * MB + MB - 1) * 3 * KSB * 64 + lane;
+      const double d0 = chain4<3 * KSB>([&](int ks3) { return la[ks3 * 64]; }, [&](int ks3) { return bf[ks3]; }, 0.0);
+      const int b = 16 * (MB - 1) + g;
+      if (ev && b < NB) Gm[((size_t)((s * DIM + p) * NV + c) * NB + b) * ne + e] = d0;
     }
   }
 }
@@ -215,6 +244,20 @@ __global__ __launch_bounds__(256, OCC) void k_volume_mfma(const double* __restri
   constexpr int NCBW = NS * NFC / 4;          // column blocks per wave
   constexpr int NPB = NV * MB;                // projection accumulator blocks (variable, mode block)
   constexpr int NPBW = (NPB + 3) / 4;
+  // FP64 P3/P4: the last mode block of every contraction over the modes on
+  // the 4x4x4 instruction (rem4); the 16x16x4 projection blocks come first in
+  // the block order, so they spread evenly over the waves
+  constexpr bool kRem = rem4<MM, NB>();
+  constexpr int MBM = kRem ? MB - 1 : MB;
+  auto pblock = [](int pb, int& c, int& mb) {
+    if (pb < NV * MBM) {
+      c = pb / MBM;
+      mb = pb % MBM;
+    } else {
+      c = pb - NV * MBM;
+      mb = MB - 1;
+    }
+  };
   static_assert(NFC % 4 == 0, "column blocks must split over 4 waves");
   __shared__ R stage[NFC][16][16];
   __shared__ R ptab[MB * KSP * 64];  // projection table of the current point block (A operands of every wave)
@@ -275,7 +318,7 @@ __global__ __launch_bounds__(256, OCC) void k_volume_mfma(const double* __restri
         }
       }
 #pragma unroll
-      for (int mb = 0; mb < MB; ++mb) {
+      for (int mb = 0; mb < MBM; ++mb) {
         const R* __restrict__ la = mt.lA + ((size_t)pd * MB + mb) * 3 * KSB * 64 + lane;
         F d = chain<MM, 3 * KSB>([&](int ks3) { return la[ks3 * 64]; }, [&](int ks3) { return bf3[ks3]; },
                                  F{0, 0, 0, 0});
@@ -289,6 +332,11 @@ __global__ __launch_bounds__(256, OCC) void k_volume_mfma(const double* __restri
 #pragma unroll
         for (int r = 0; r < 4; ++r)
           if (4 * mb + r < KSV) Bf[i][4 * mb + r] = d[r];
+      }
+      if constexpr (kRem) {  // k-step 4 (MB - 1) holds mode 16 (MB - 1) + g
+        const R* __restrict__ la = mt.lA + ((size_t)pd * MB + MB - 1) * 3 * KSB * 64 + lane;
+        Bf[i][4 * (MB - 1)] =
+            chain4<3 * KSB>([&](int ks3) { return la[ks3 * 64]; }, [&](int ks3) { return bf3[ks3]; }, 0.0);
       }
     } else {
 #pragma unroll
@@ -375,13 +423,18 @@ __global__ __launch_bounds__(256, OCC) void k_volume_mfma(const double* __restri
     for (int i = 0; i < NPBW; ++i) {
       const int pb = wave + 4 * i;
       if (pb < NPB) {
-        const int c = pb / MB, mb = pb % MB;
-        acc[i] = chain<MM, KSP>([&](int ks) { return ptab[(mb * KSP + ks) * 64 + lane]; },
-                                [&](int ks) {
-                                  const int k = g + 4 * ks;
-                                  return stage[(k >> 4) * NV + c][k & 15][col];
-                                },
-                                acc[i]);
+        int c, mb;
+        pblock(pb, c, mb);
+        auto aop = [&](int ks) { return ptab[(mb * KSP + ks) * 64 + lane]; };
+        auto bop = [&](int ks) {
+          const int k = g + 4 * ks;
+          return stage[(k >> 4) * NV + c][k & 15][col];
+        };
+        if (kRem && mb == MB - 1) {
+          if constexpr (kRem) acc[i][0] = chain4<KSP>(aop, bop, acc[i][0]);
+        } else {
+          acc[i] = chain<MM, KSP>(aop, bop, acc[i]);
+        }
       }
     }
     __syncthreads();
@@ -400,21 +453,25 @@ __global__ __launch_bounds__(256, OCC) void k_volume_mfma(const double* __restri
     for (int i = 0; i < NPBW; ++i) {
       const int pb = wave + 4 * i;
       if (pb < NPB) {
-        const int c = pb / MB, mb = pb % MB;
+        int c, mb;
+        pblock(pb, c, mb);
         // k-steps (side, face point) with side 0 (the -p face, read from the
         // -p neighbour's record) first
-        acc[i] = chain<MM, 2 * KSF>(
-            [&](int k2) {
-              const int side = k2 / KSF, ks = k2 % KSF;
-              return ftab[((side * MB + mb) * KSF + ks) * 64 + lane];
-            },
-            [&](int k2) {
-              const int side = k2 / KSF, ks = k2 % KSF;
-              const int fq = g + 4 * ks;
-              const R h = H[((size_t)(p * NV + c) * NFQ + (fq < NFQ ? fq : NFQ - 1)) * ne + (side ? ec : em)];
-              return (ev && fq < NFQ) ? h : R(0);
-            },
-            acc[i]);
+        auto aop = [&](int k2) {
+          const int side = k2 / KSF, ks = k2 % KSF;
+          return ftab[((side * MB + mb) * KSF + ks) * 64 + lane];
+        };
+        auto bop = [&](int k2) {
+          const int side = k2 / KSF, ks = k2 % KSF;
+          const int fq = g + 4 * ks;
+          const R h = H[((size_t)(p * NV + c) * NFQ + (fq < NFQ ? fq : NFQ - 1)) * ne + (side ? ec : em)];
+          return (ev && fq < NFQ) ? h : R(0);
+        };
+        if (kRem && mb == MB - 1) {
+          if constexpr (kRem) acc[i][0] = chain4<2 * KSF>(aop, bop, acc[i][0]);
+        } else {
+          acc[i] = chain<MM, 2 * KSF>(aop, bop, acc[i]);
+        }
       }
     }
     __syncthreads();
@@ -423,7 +480,8 @@ __global__ __launch_bounds__(256, OCC) void k_volume_mfma(const double* __restri
   for (int i = 0; i < NPBW; ++i) {
     const int pb = wave + 4 * i;
     if (pb < NPB) {
-      const int c = pb / MB, mb = pb % MB;
+      int c, mb;  // the last mode block holds rows 16 mb + g in register 0 only
+      pblock(pb, c, mb);
       if (ev) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {

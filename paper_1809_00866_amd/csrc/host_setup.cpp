@@ -589,6 +589,23 @@ MfmaHost build_mfma_tables(const HostTables& T) {
               M.fA[((((size_t)p * 2 + side) * MB + mb) * KSF + ks) * 64 + l] =
                   (side ? 1.0 : -1.0) * T.fWPhi[(((size_t)p * 2 + side) * nfq + fq) * nb + b];
           }
+  // FP64 copies for the 4-block 4x4x4 MFMA on a last mode block of <= 4 rows:
+  // tables of layout [outer][MB][KS][64]; lane l = 16 k + 4 v + w of the
+  // instruction's A operand feeds block v with A[w][k], the same rows for
+  // every block v (the 16 result columns are the blocks' 4 x 4)
+  auto rem_layout = [&](const std::vector<double>& src, int ks) {
+    std::vector<double> out = src;
+    if (MB < 2 || nb - 16 * (MB - 1) > 4) return out;
+    const size_t frag = 64, blk = (size_t)ks * frag, outer = src.size() / (MB * blk);
+    for (size_t o = 0; o < outer; ++o)
+      for (int k = 0; k < ks; ++k) {
+        const size_t base = (o * MB + MB - 1) * blk + (size_t)k * frag;
+        for (int l = 0; l < 64; ++l) out[base + l] = src[base + (l & 3) + 16 * (l >> 4)];
+      }
+    return out;
+  };
+  M.pA64 = rem_layout(M.pA, KSP);
+  M.fA64 = rem_layout(M.fA, KSF);
   M.tA.assign((size_t)dim * RBF * 6 * 2 * KSB * 64, 0.0);
   for (int p = 0; p < dim; ++p)
     for (int rbf = 0; rbf < RBF; ++rbf)
@@ -681,6 +698,7 @@ MfmaHost build_mfma_tables(const HostTables& T) {
             M.lA[(((size_t)p * MB + mb) * 3 * KSB + ks3) * 64 + l] =
                 T.vLift[(((size_t)p * 3 + src) * nb + b) * nb + bp];
         }
+  M.lA64 = rem_layout(M.lA, 3 * KSB);
   // the maps act along tensor lines: at most p+1 nonzeros per row
   double big = 0.0;
   for (double v : T.vLift) big = std::max(big, std::fabs(v));
