@@ -1,5 +1,8 @@
 // DG residual and exact Jv on curved (multilinear) elements (Sec. 2.1-2.2,
-// eq. NSdiscrRes), FP64 on the vector ALU (dual numbers for Jv).
+// eq. NSdiscrRes): the compressible equations in FP64 and FP32, the scalar
+// BR2 Laplacian of the Poisson assessment (App. B) in FP64; dual numbers for
+// Jv; the face products of pass 3 on the matrix cores, the rest on the vector
+// ALU.
 //
 // Element K's orthonormal basis is phi = L^{-1} psi, with L L^T the mass
 // matrix of the reference basis psi on K.  Every contraction therefore runs
@@ -27,7 +30,6 @@
 // face fluxes gathered on psi of each face (+ owner, - neighbour side); and
 // finally L^{-1}.
 #include "dg_device.h"
-
 
 namespace dgk {
 

@@ -60,6 +60,8 @@ struct MTablesT {
   const R* fA;     // [DIM][2][MB][KSF][64]     face projection: +/- w_f|J_f| phi(fq, b)
   const R* tA;     // [DIM][RBF][6][2*KSB][64]  face traces (uL, uR, G_1..3 averaged, {r})
   const R* lA;     // [DIM][MB][3*KSB][64]      modal corrected gradient [L0 | L1 | L2]
+                   // (FP64 pA, fA, lA: a last mode block of <= 4 rows in the lane
+                   // order of the 4-block 4x4x4 instruction, row l % 4 in lane l)
   const R* dA;     // [DIM][3][4][64]           maps between the points of one face: d/dx_t
                    //                           (t: the two tangential directions) and the
                    //                           averaged lifting from the jump; k = face point in
