@@ -109,7 +109,15 @@ __global__ __launch_bounds__(64) void k_face_curved(CurvedTablesT<R> ct, Mesh m,
   constexpr int NW = 2 * NS * NX > NS * NC * NFQ ? 2 * NS * NX : NS * NC * NFQ;
   constexpr int NKL = (NC + 1) / 2;  // {r} columns per lane half
   __shared__ __align__(16) R sW[NW];     // coefficients of both sides, then sX, then sR
-  __shared__ R sT[2][NS][NTR][NFQ];      // traces of both sides: values, physical gradients
+  // Traces of both sides: values and physical gradients.  FP64 (kSum): the
+  // gradients enter the flux only as the sum of the two sides, which both
+  // sides add into one slot (two LDS atomic adds onto zero: a + b either way,
+  // so the sum is deterministic); the 6 KB saved let 8 instead of 6
+  // workgroups share a CU (P4: face 0.60 -> 0.51 ms).  FP32 keeps both sides'
+  // gradients (the atomic form measured 0.29 -> 0.51 ms there).
+  constexpr bool kSum = sizeof(R) == 8;
+  __shared__ R sT[2][NS][kSum ? NV : NTR][NFQ];  // values (and FP32 gradients) per side
+  __shared__ R sG[kSum ? NS : 1][kSum ? NC : 1][NFQ];     // FP64 gradient sums
   __shared__ R sH[2][NV][NFQ];           // convective and viscous parts of the normal flux
   R* sU = sW;                                               // [side][c][a][value/tangent]
   auto sX = reinterpret_cast<R(*)[NC][NFQ]>(sW);            // [s][c*DIM+j][fq]: w n_j [[U_c]]
@@ -127,6 +135,8 @@ __global__ __launch_bounds__(64) void k_face_curved(CurvedTablesT<R> ct, Mesh m,
     const int sd = i / (NS * NX), s = (i / NX) % NS;
     sU[(sd * NX + i % NX) * NS + s] = (s ? ct.Vt : ct.Ut)[(size_t)(sd ? er : e) * NX + (i % NX)];
   }
+  if constexpr (kSum)
+    for (int i = tid; i < NS * NC * NFQ; i += 64) (&sG[0][0][0])[i] = R(0);
   __syncthreads();
 
   // traces of this lane's side at face point fq
@@ -164,8 +174,13 @@ __global__ __launch_bounds__(64) void k_face_curved(CurvedTablesT<R> ct, Mesh m,
       for (int i = 0; i < DIM; ++i) {  // reference to physical gradient
         T t = 0.0;
         for (int r = 0; r < DIM; ++r) t += K[i][r] * g[c][r];
-        sT[side][0][NV + c * DIM + i][fq] = val(t);
-        if constexpr (JVP) sT[side][NS - 1][NV + c * DIM + i][fq] = out_part(t);
+        if constexpr (kSum) {
+          atomicAdd(&sG[0][c * DIM + i][fq], val(t));
+          if constexpr (JVP) atomicAdd(&sG[NS - 1][c * DIM + i][fq], out_part(t));
+        } else {
+          sT[side][0][NV + c * DIM + i][fq] = val(t);
+          if constexpr (JVP) sT[side][NS - 1][NV + c * DIM + i][fq] = out_part(t);
+        }
       }
     }
   }
@@ -243,9 +258,13 @@ __global__ __launch_bounds__(64) void k_face_curved(CurvedTablesT<R> ct, Mesh m,
                                     tr ? sT[0][NS - 1][c][fq] + sT[1][NS - 1][c][fq] : R(0));
         for (int i = 0; i < DIM; ++i) {
           const int k = NV + c * DIM + i;
-          Ga[c][i] = R(0.5) * mk<JVP, R>(sT[0][0][k][fq] + sT[1][0][k][fq],
-                                         tr ? sT[0][NS - 1][k][fq] + sT[1][NS - 1][k][fq] : R(0)) +
-                     (R)ph.eta * mk<JVP, R>(sR[0][c * DIM + i][fq], sR[NS - 1][c * DIM + i][fq]);
+          if constexpr (kSum)  // owner + neighbour gradient trace
+            Ga[c][i] = R(0.5) * mk<JVP, R>(sG[0][k - NV][fq], tr ? sG[NS - 1][k - NV][fq] : R(0)) +
+                       (R)ph.eta * mk<JVP, R>(sR[0][c * DIM + i][fq], sR[NS - 1][c * DIM + i][fq]);
+          else
+            Ga[c][i] = R(0.5) * mk<JVP, R>(sT[0][0][k][fq] + sT[1][0][k][fq],
+                                           tr ? sT[0][NS - 1][k][fq] + sT[1][NS - 1][k][fq] : R(0)) +
+                       (R)ph.eta * mk<JVP, R>(sR[0][c * DIM + i][fq], sR[NS - 1][c * DIM + i][fq]);
         }
       }
       if constexpr (DIFF) {  // -mu {grad u + eta r}.n
