@@ -203,7 +203,8 @@ dg_status dg_jvp_noalloc(dg_context* ctx, const double* w, const double* v, doub
 size_t dg_jvp_noalloc_scratch_bytes(void);
 
 /* EWBJ setup: D_K = shift*I + dR_K/dU_K for every element (exact, by
- * coloured probing with exact Jv), factored by Gauss-Jordan with partial
+ * probing with exact Jv: element-local where dg_set_block_probing allows it,
+ * else coloured), factored by Gauss-Jordan with partial
  * pivoting into explicit inverses, stored as `storage`: DG_FP64 (FP64
  * elimination), DG_FP32 (FP32 elimination) or DG_BF16 (FP32 elimination,
  * inverse rounded to BF16; the apply accumulates in FP32).  With DG_FP32 or
@@ -213,6 +214,24 @@ size_t dg_jvp_noalloc_scratch_bytes(void);
  * Returns DG_ERR_SINGULAR_BLOCK if a pivot is exactly zero or non-finite
  * (synchronises the stream). */
 dg_status dg_block_precond_setup(dg_context* ctx, const double* w, double shift, int storage, void* stream);
+
+/* How the diagonal blocks dR_K/dU_K are probed (Sec. 2.3: the blocks of the
+ * element-wise block Jacobi are the exact Jacobian's diagonal blocks; the
+ * p-multigrid setup probes its fine blocks the same way).
+ *   DG_PROBE_AUTO (default of a new context): element-local probing where the
+ *     kernels allow it -- the MFMA operators of 3D P2-P4 lattices on meshes
+ *     where no element is its own face neighbour: one pass per block column
+ *     with every element perturbed at once, the face kernel run once per face
+ *     side so that each flux tangent reaches only the perturbed element's own
+ *     rows (half the passes of a two-colour lattice); coloured elsewhere.
+ *   DG_PROBE_COLOURED: one exact Jv per block column and colour of the
+ *     face-neighbour graph (e_l in the elements of one colour, whose
+ *     neighbours all carry zero).
+ * Both give the same blocks bit for bit (the local tangents are the coloured
+ * probe's, with the other side's tangent zero instead of a zero input).
+ * DG_ERR_ARG for another mode; takes effect at the next setup. */
+enum { DG_PROBE_AUTO = 0, DG_PROBE_COLOURED = 1 };
+dg_status dg_set_block_probing(dg_context* ctx, int mode);
 
 /* z_K = D_K^{-1} r_K for every element (needs a prior setup; DG_ERR_STATE
  * otherwise).  r and z may not alias. */

@@ -21,10 +21,11 @@ DG_ORTH_CGS2, DG_ORTH_MGS = 0, 1
 DG_MLP_DIRECT, DG_MLP_CORRECT_BJ = 0, 1
 DG_PHYS_COMPRESSIBLE, DG_PHYS_INCOMPRESSIBLE, DG_PHYS_DIFFUSION = 0, 1, 2
 DG_TUNE_FIXED, DG_TUNE_AUTO = 0, 1
+DG_PROBE_AUTO, DG_PROBE_COLOURED = 0, 1
 
 EXPORTED = ["dg_create", "dg_destroy", "dg_ndof", "dg_nbasis", "dg_nvar", "dg_nq", "dg_volume_points",
             "dg_project", "dg_residual", "dg_residual_fp32", "dg_residual_bf16", "dg_jvp", "dg_jvp_noalloc", "dg_jvp_noalloc_scratch_bytes",
-            "dg_block_precond_setup", "dg_block_precond_apply",
+            "dg_block_precond_setup", "dg_set_block_probing", "dg_block_precond_apply",
             "dg_fgmres_solve", "dg_rosenbrock_step", "dg_mg_setup", "dg_mg_update_fine", "dg_mg_apply", "dg_mg_level_apply", "dg_mlp_nparams", "dg_mlp_set_mode",
             "dg_mlp_set_weights", "dg_mlp_get_weights", "dg_mlp_features", "dg_mlp_forward", "dg_mlp_grad",
             "dg_mlp_train_step", "dg_mlp_apply", "dg_max_wave_speed",
@@ -120,6 +121,7 @@ def load():
         "dg_mlp_apply": (i, [ctx, vp, vp, vp, vp]),
         "dg_max_wave_speed": (i, [ctx, vp, ctypes.POINTER(ctypes.c_double), vp]),
         "dg_set_tuning": (i, [ctx, i]),
+        "dg_set_block_probing": (i, [ctx, i]),
         "dg_autotune": (i, [ctx, vp, vp]),
         "dg_tuning_report": (i, [ctx, ctypes.c_char_p, ctypes.c_size_t]),
         "dg_set_fine_shape": (i, [ctx, i, i, i, i]),

@@ -148,6 +148,12 @@ class DG:
         m = {"fixed": L.DG_TUNE_FIXED, "auto": L.DG_TUNE_AUTO}[mode]
         L.check(self.lib.dg_set_tuning(self.ctx, m), "dg_set_tuning")
 
+    def set_block_probing(self, mode):
+        """"auto" (element-local probing of the diagonal blocks where the kernels
+        allow it, the default) or "coloured" (one Jv per column and colour)."""
+        m = {"auto": L.DG_PROBE_AUTO, "coloured": L.DG_PROBE_COLOURED}[mode]
+        L.check(self.lib.dg_set_block_probing(self.ctx, m), "dg_set_block_probing")
+
     def autotune(self, w):
         """Time and select the fine operator's launch shapes at state w (and the
         block apply shape when block factors exist)."""

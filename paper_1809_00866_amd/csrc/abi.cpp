@@ -138,12 +138,65 @@ dg_status eval_op(dg_context* c, int prec, bool jvp, const double* w, const doub
   return eval_residual_bf16(c, jvp, w, v, shift, out, s);
 }
 
-dg_status eval_stab(dg_context* c, bool f32, const double* w, const double* v, double* out, hipStream_t s) {
-  if (!c->d_zero) {
-    dg_status st;
-    if ((st = dalloc(&c->d_zero, (size_t)c->ndof)) != DG_OK) return st;
-    HIPCHK(dgk::launch_fill(c->d_zero, c->ndof, 0.0, s));
+// c->d_zero: ndof zeros, allocated and cleared on first use (never written after)
+static dg_status zeros(dg_context* c, hipStream_t s) {
+  if (c->d_zero) return DG_OK;
+  dg_status st;
+  if ((st = dalloc(&c->d_zero, (size_t)c->ndof)) != DG_OK) return st;
+  HIPCHK(dgk::launch_fill(c->d_zero, c->ndof, 0.0, s));
+  return DG_OK;
+}
+
+dg_status eval_local(dg_context* c, int prec, const double* w, const double* v, double shift, double* out,
+                     hipStream_t s) {
+  if (!local_probe_ok(c, prec)) return fail(DG_ERR_ARG, "no element-local probing for this operator");
+  dg_status st;
+  if ((st = zeros(c, s)) != DG_OK) return st;
+  const double* z = c->d_zero;
+  // face fluxes of the owners' tangents (read on the +p faces) and of the
+  // +p neighbours' tangents (read on the -p faces); gradients without the
+  // neighbours' tangents
+  if (prec == DG_FP64) {
+    if (!c->d_H2 && (st = dalloc(&c->d_H2, (size_t)c->dim * c->nv * c->nfq * c->ne)) != DG_OK) return st;
+    const bool fg = c->fuse_grad[DG_FP64][1];
+    const int* occ = c->occ[DG_FP64][1];
+    if (!fg) {
+      ProfScope ps(c, "grad_jvp", s);
+      HIPCHK(dgk::launch_grad_mfma(c->cfg, true, w, v, c->d_G, c->mt, c->mesh, s, z));
+    }
+    {
+      ProfScope ps(c, "face_jvp", s);
+      HIPCHK(dgk::launch_face_mfma(c->cfg, true, w, v, c->d_H, c->mt, c->mesh, c->ph, occ[0], s, z));
+      HIPCHK(dgk::launch_face_mfma(c->cfg, true, w, z, c->d_H2, c->mt, c->mesh, c->ph, occ[0], s, v));
+    }
+    ProfScope ps(c, "vol_jvp", s);
+    HIPCHK(dgk::launch_volume_mfma(c->cfg, true, w, v, c->d_G, c->d_H, out, shift, c->mt, c->mesh, c->ph, occ[1], fg,
+                                   s, c->d_H2, z));
+    return DG_OK;
   }
+  if (!c->d_Hf2 && (st = dalloc(&c->d_Hf2, (size_t)c->dim * c->nv * c->nfq * c->ne)) != DG_OK) return st;
+  const bool f32 = prec == DG_FP32, fg = c->fuse_grad[prec][1];
+  const int* occ = c->occ[prec][1];
+  const auto grad = f32 ? dgk::launch_grad_mfma_f32 : dgk::launch_grad_mfma_bf16;
+  const auto face = f32 ? dgk::launch_face_mfma_f32 : dgk::launch_face_mfma_bf16;
+  const auto vol = f32 ? dgk::launch_volume_mfma_f32 : dgk::launch_volume_mfma_bf16;
+  if (!fg) {
+    ProfScope ps(c, f32 ? "grad_jvp_f32" : "grad_jvp_bf16", s);
+    HIPCHK(grad(c->cfg, true, w, v, c->d_Gf, c->mtf, c->mesh, s, z));
+  }
+  {
+    ProfScope ps(c, f32 ? "face_jvp_f32" : "face_jvp_bf16", s);
+    HIPCHK(face(c->cfg, true, w, v, c->d_Hf, c->mtf, c->mesh, c->ph, occ[0], s, z));
+    HIPCHK(face(c->cfg, true, w, z, c->d_Hf2, c->mtf, c->mesh, c->ph, occ[0], s, v));
+  }
+  ProfScope ps(c, f32 ? "vol_jvp_f32" : "vol_jvp_bf16", s);
+  HIPCHK(vol(c->cfg, true, w, v, c->d_Gf, c->d_Hf, out, shift, c->mtf, c->mesh, c->ph, occ[1], fg, s, c->d_Hf2, z));
+  return DG_OK;
+}
+
+dg_status eval_stab(dg_context* c, bool f32, const double* w, const double* v, double* out, hipStream_t s) {
+  dg_status st;
+  if ((st = zeros(c, s)) != DG_OK) return st;
   dgk::Phys ph = c->ph;
   ph.stab_only = 1;
   const double* z = c->d_zero;  // no tangent in the volume terms and the gradients
@@ -486,6 +539,9 @@ dg_status dg_create(const dg_params* prm, const dg_mesh* mesh, dg_context** out)
   c->mesh.x0 = c->d_x0;
   for (int i = 0; i < 3; ++i) c->mesh.h[i] = h[i];
 
+  for (int64_t e = 0; e < ne && !c->self_nbr; ++e)
+    for (int k = 0; k < 2 * dim; ++k) c->self_nbr = c->self_nbr || mesh->elem_nbr[e * 2 * dim + k] == e;
+
   // greedy colouring of the face-neighbour graph (self loops ignored)
   std::vector<int> color(ne, -1);
   int ncol = 0;
@@ -538,6 +594,8 @@ void dg_destroy(dg_context* c) {
   dfree(c->d_nbr);
   dfree(c->d_x0);
   dfree(c->d_H);
+  dfree(c->d_H2);
+  dfree(c->d_Hf2);
   dfree(c->d_t1);
   dfree(c->d_t2);
   dfree(c->d_t3);
@@ -658,11 +716,16 @@ dg_status block_probe_invert(dg_context* c, const double* w, double shift, int s
   if ((st = tune_fine(c, probe_prec, w, s)) != DG_OK) return st;
   {
     ProfScope ps(c, "block_probe", s);
-    for (int col = 0; col < c->ncolor; ++col)
+    // element-local: one pass per column, all elements at once (colour -1);
+    // coloured: one Jv per column and colour
+    const bool local = local_probe_ok(c, probe_prec);
+    for (int col = local ? -1 : 0; col < (local ? 0 : c->ncolor); ++col)
       for (int l = 0; l < m; ++l) {
         if (l % c->nb < skip_modes) continue;  // column already in d_D64
         HIPCHK(dgk::launch_probe_vector(c->d_t1, c->d_color, col, l, c->nb, c->nv, c->ne, s));
-        if ((st = eval_op(c, probe_prec, true, w, c->d_t1, shift, c->d_t2, s)) != DG_OK) return st;
+        st = local ? eval_local(c, probe_prec, w, c->d_t1, shift, c->d_t2, s)
+                   : eval_op(c, probe_prec, true, w, c->d_t1, shift, c->d_t2, s);
+        if (st != DG_OK) return st;
         HIPCHK(dgk::launch_extract_column(c->d_t2, c->d_color, col, l, m, c->ne, shift, c->d_D64, s));
       }
   }
@@ -685,6 +748,13 @@ dg_status block_probe_invert(dg_context* c, const double* w, double shift, int s
 }  // namespace dgc
 
 extern "C" {
+
+dg_status dg_set_block_probing(dg_context* c, int mode) {
+  if (!c) return fail(DG_ERR_ARG, "null context");
+  if (mode != DG_PROBE_AUTO && mode != DG_PROBE_COLOURED) return fail(DG_ERR_ARG, "unknown probing mode");
+  c->probe_mode = mode;
+  return DG_OK;
+}
 
 dg_status dg_block_precond_setup(dg_context* c, const double* w, double shift, int storage, void* stream) {
   if (!c || !w) return fail(DG_ERR_ARG, "null argument");

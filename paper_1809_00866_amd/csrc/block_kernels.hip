@@ -26,11 +26,12 @@ __global__ void k_probe(double* __restrict__ P, const int* __restrict__ color, i
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t e = i % ne;
     const int r = (int)(i / ne);
-    P[i] = (r == l && color[e] == col) ? 1.0 : 0.0;
+    P[i] = (r == l && (col < 0 || color[e] == col)) ? 1.0 : 0.0;
   }
 }
 
-// D[e][l][r] = Jv[r*ne + e] for every element of colour `col` (Jv already includes shift*P);
+// D[e][l][r] = Jv[r*ne + e] for every element of colour `col`, every element
+// if col < 0 (Jv already includes shift*P);
 // block e starts at e*m*ld, column l at l*ld
 __global__ void k_extract(const double* __restrict__ Jv, const int* __restrict__ color, int col, int l, int m,
                           int ld, int64_t ne, double* __restrict__ D) {
@@ -38,7 +39,7 @@ __global__ void k_extract(const double* __restrict__ Jv, const int* __restrict__
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t e = i % ne;
     const int r = (int)(i / ne);
-    if (color[e] == col) D[((size_t)e * m + l) * ld + r] = Jv[i];
+    if (col < 0 || color[e] == col) D[((size_t)e * m + l) * ld + r] = Jv[i];
   }
 }
 

@@ -92,6 +92,10 @@ struct dg_context {
   int64_t* d_nbr = nullptr;
   double* d_x0 = nullptr;
   double* d_H = nullptr;
+  double* d_H2 = nullptr;        // element-local probing: face fluxes of the +face neighbours' tangents
+  float* d_Hf2 = nullptr;        // the same for the FP32 / BF16-contraction operators
+  bool self_nbr = false;         // some element is its own face neighbour (a periodic direction of one element)
+  int probe_mode = DG_PROBE_AUTO;
   double* d_t1 = nullptr;
   double* d_t2 = nullptr;
   double* d_t3 = nullptr;
@@ -167,6 +171,13 @@ inline bool has_prec(const dg_context* c, int prec) {
   return prec == DG_BF16 && c->use_mfma && c->d_mtab_f && c->d_Hf && c->d_Gf;
 }
 
+// True when the diagonal blocks of the operator of precision prec can be
+// probed element-locally (every element perturbed at once): the MFMA kernels
+// of a 3D P2-P4 lattice, where no element is its own face neighbour.
+inline bool local_probe_ok(const dg_context* c, int prec) {
+  return c->probe_mode == DG_PROBE_AUTO && c->use_mfma && !c->curved && !c->self_nbr && has_prec(c, prec);
+}
+
 // Residual (jvp = false) or exact Jv plus shift*v (jvp = true) on stream s.
 dg_status eval_residual(dg_context* c, bool jvp, const double* w, const double* v, double shift, double* out,
                         hipStream_t s);
@@ -178,6 +189,12 @@ dg_status eval_residual_f32(dg_context* c, bool jvp, const double* w, const doub
 // or DG_BF16); DG_ERR_ARG when the context has no such operator.
 dg_status eval_op(dg_context* c, int prec, bool jvp, const double* w, const double* v, double shift, double* out,
                   hipStream_t s);
+// Element-local Jv of the operator of precision prec (local_probe_ok): out_K =
+// shift v_K + (dR_K/dU_K) v_K for every element K, i.e. the Jv with each
+// element perturbed alone.  v = e_l in every element gives column l of every
+// diagonal block in one pass.
+dg_status eval_local(dg_context* c, int prec, const double* w, const double* v, double shift, double* out,
+                     hipStream_t s);
 // out = STB(w) v: the BR2 stabilisation part of the Jacobian (the tangent of
 // the face lifting term eta {r} of the face viscous flux only; no shift),
 // FP64 or the FP32 operator.

@@ -106,33 +106,43 @@ bool has_curved(int cfg, bool diffusion = false);
 // same bits.  fused (volume kernel): form the corrected gradients in the
 // kernel from U / V (Gm unused) instead of reading them from Gm written by
 // launch_grad_mfma; the same chains, so the same bits.
+// Probing the diagonal blocks element by element (the last arguments, null
+// for the ordinary operator): Vr (face kernel) the tangent of every face's +p
+// neighbour in place of V; Hm (volume kernel) the fluxes read on the
+// element's -p faces in place of H, Vn the neighbours' tangents of the
+// corrected gradients formed in the kernel in place of V.
 bool mfma_occ_fits(int cfg, int prec, int face_occ, int volume_occ);
 hipError_t launch_face_mfma(int cfg, bool jvp, const double* U, const double* V, double* H, const MTables& mt,
-                            const Mesh& m, const Phys& ph, int occ, hipStream_t stream);
+                            const Mesh& m, const Phys& ph, int occ, hipStream_t stream, const double* Vr = nullptr);
 // reduced precision variant: FP32 tables, FP32 face-flux buffer, FP32 MFMA and
 // pointwise arithmetic, FP64 inputs and outputs
 hipError_t launch_face_mfma_f32(int cfg, bool jvp, const double* U, const double* V, float* H, const MTablesF& mt,
-                                const Mesh& m, const Phys& ph, int occ, hipStream_t s);
+                                const Mesh& m, const Phys& ph, int occ, hipStream_t s, const double* Vr = nullptr);
 hipError_t launch_volume_mfma_f32(int cfg, bool jvp, const double* U, const double* V, const float* Gm,
                                   const float* H, double* out, double shift, const MTablesF& mt, const Mesh& m,
-                                  const Phys& ph, int occ, bool fused, hipStream_t s);
+                                  const Phys& ph, int occ, bool fused, hipStream_t s, const float* Hm = nullptr,
+                                  const double* Vn = nullptr);
 // BF16 contractions with FP32 accumulation, otherwise as the FP32 variant
 // (FP32 tables and buffers, FP32 pointwise arithmetic)
 hipError_t launch_grad_mfma_bf16(int cfg, bool jvp, const double* U, const double* V, float* Gm, const MTablesF& mt,
-                                 const Mesh& m, hipStream_t s);
+                                 const Mesh& m, hipStream_t s, const double* Vn = nullptr);
 hipError_t launch_face_mfma_bf16(int cfg, bool jvp, const double* U, const double* V, float* H, const MTablesF& mt,
-                                 const Mesh& m, const Phys& ph, int occ, hipStream_t s);
+                                 const Mesh& m, const Phys& ph, int occ, hipStream_t s, const double* Vr = nullptr);
 hipError_t launch_volume_mfma_bf16(int cfg, bool jvp, const double* U, const double* V, const float* Gm,
                                    const float* H, double* out, double shift, const MTablesF& mt, const Mesh& m,
-                                   const Phys& ph, int occ, bool fused, hipStream_t s);
-// modal corrected gradients Gm[s][p][c][b][e] (s = value, tangent)
+                                   const Phys& ph, int occ, bool fused, hipStream_t s, const float* Hm = nullptr,
+                                  const double* Vn = nullptr);
+// modal corrected gradients Gm[s][p][c][b][e] (s = value, tangent); Vn: the
+// neighbours' tangent coefficients in place of V (zeros when probing the
+// diagonal blocks element by element)
 hipError_t launch_grad_mfma(int cfg, bool jvp, const double* U, const double* V, double* Gm, const MTables& mt,
-                            const Mesh& m, hipStream_t s);
+                            const Mesh& m, hipStream_t s, const double* Vn = nullptr);
 hipError_t launch_grad_mfma_f32(int cfg, bool jvp, const double* U, const double* V, float* Gm, const MTablesF& mt,
-                                const Mesh& m, hipStream_t s);
+                                const Mesh& m, hipStream_t s, const double* Vn = nullptr);
 hipError_t launch_volume_mfma(int cfg, bool jvp, const double* U, const double* V, const double* Gm, const double* H,
                               double* out, double shift, const MTables& mt, const Mesh& m, const Phys& ph, int occ,
-                              bool fused, hipStream_t stream);
+                              bool fused, hipStream_t stream,
+                              const double* Hm = nullptr, const double* Vn = nullptr);
 hipError_t launch_project(int cfg, int nv, const double* f, double* w, const Tables& tb, const Mesh& m,
                           hipStream_t s);
 hipError_t launch_points(int cfg, double* xyz, const Tables& tb, const Mesh& m, hipStream_t s);
@@ -162,7 +172,9 @@ hipError_t launch_fd_delta(double* d, double eps, hipStream_t s);
 hipError_t launch_max_partials(const double* partial, int np, double* out, hipStream_t s);
 hipError_t launch_nonfinite_check(const double* x, int64_t n, int* flag, hipStream_t s);
 
-// Block-Jacobi kernels.
+// Block-Jacobi kernels.  Probe vector: e_l in every element of colour col
+// (col < 0: in every element); extraction: column l of the diagonal block of
+// the same elements.
 hipError_t launch_probe_vector(double* P, const int* color, int col, int l, int nb, int nv, int64_t ne,
                                hipStream_t s);
 hipError_t launch_extract_column(const double* Jv, const int* color, int col, int l, int m, int64_t ne,

@@ -149,10 +149,13 @@ DEV int64_t xcd_tile(int64_t bid, int64_t nblk) {
 //   G_p = L_{p,0} U_e + L_{p,1} U_{e+p} + L_{p,2} U_{e-p},
 // one wave per (tile of 16 elements, direction p, value/tangent s), all
 // variables; B fragments straight from global memory (no LDS, no barriers).
-// Output layout Gm[s][p][c][b][e].
+// Output layout Gm[s][p][c][b][e].  The tangent (s = 1) reads the element's
+// own coefficients from V and its neighbours' from Vn (V for the ordinary Jv;
+// zeros when probing the diagonal blocks element by element).
 template <class R, int NB, class MM>
 __global__ __launch_bounds__(64) void k_grad_mfma(const double* __restrict__ U, const double* __restrict__ V,
-                                                  R* __restrict__ Gm, const R* __restrict__ lA, Mesh m) {
+                                                  const double* __restrict__ Vn, R* __restrict__ Gm,
+                                                  const R* __restrict__ lA, Mesh m) {
   using F = typename MM::frag;
   constexpr int DIM = 3, NV = 5;
   constexpr int KSB = (NB + 3) / 4, MB = (NB + 15) / 16;
@@ -163,6 +166,7 @@ __global__ __launch_bounds__(64) void k_grad_mfma(const double* __restrict__ U, 
   const bool ev = e < ne;
   const int p = blockIdx.y, s = blockIdx.z;
   const double* __restrict__ X = (s == 0) ? U : V;
+  const double* __restrict__ Xn = (s == 0) ? U : Vn;
   // Loads use clamped, always valid addresses and a select instead of a branch
   // (a branch per load keeps the scheduler from batching them).
   const int64_t ec = ev ? e : ne - 1;
@@ -173,13 +177,13 @@ __global__ __launch_bounds__(64) void k_grad_mfma(const double* __restrict__ U, 
 #pragma unroll
     for (int ks3 = 0; ks3 < 3 * KSB; ++ks3) {
       const int src = ks3 / KSB, bp = g + 4 * (ks3 % KSB);
-      const R x = (R)X[(size_t)(c * NB + (bp < NB ? bp : NB - 1)) * ne + es[src]];
+      const R x = (R)(src == 0 ? X : Xn)[(size_t)(c * NB + (bp < NB ? bp : NB - 1)) * ne + es[src]];
       bf[ks3] = (ev && bp < NB) ? x : R(0);
     }
     if constexpr (MM::kBf16) {  // mean modes in FP32, out of the BF16 chain
 #pragma unroll
       for (int src = 0; src < 3; ++src) {
-        m0[src] = ev ? (R)X[(size_t)(c * NB) * ne + es[src]] : R(0);
+        m0[src] = ev ? (R)(src == 0 ? X : Xn)[(size_t)(c * NB) * ne + es[src]] : R(0);
         if (g == 0) bf[src * KSB] = R(0);
       }
     }
@@ -227,11 +231,16 @@ constexpr int volume_occupancy() { return (NB > 20 && sizeof(R) == 8) ? 1 : 2; }
 // FG: the corrected gradients are formed in the kernel from the element and
 // its +/-p neighbours (the chains of k_grad_mfma, same operands and order,
 // so the same bits) instead of being read from the buffer Gm.
+// Hm: the face fluxes read on the element's -p faces; Vn: the neighbours'
+// tangent coefficients of the corrected gradients formed in the kernel (FG).
+// H and V for the ordinary operator; probing the diagonal blocks element by
+// element passes the fluxes of the +face neighbours' tangents and zeros.
 template <class R, int NB, int NQ1, int KL, bool JVP, class MM, int OCC, bool FG>
 __global__ __launch_bounds__(256, OCC) void k_volume_mfma(const double* __restrict__ U, const double* __restrict__ V,
+                                                     const double* __restrict__ Vn,
                                                      const R* __restrict__ Gm, const R* __restrict__ H,
-                                                     double* __restrict__ out, double shift, MTablesT<R> mt,
-                                                     Mesh m, Phys ph) {
+                                                     const R* __restrict__ Hm, double* __restrict__ out,
+                                                     double shift, MTablesT<R> mt, Mesh m, Phys ph) {
   using T = typename Scalar<JVP, R>::type;
   using F = typename MM::frag;
   constexpr int DIM = 3, NV = 5;
@@ -303,17 +312,18 @@ __global__ __launch_bounds__(256, OCC) void k_volume_mfma(const double* __restri
       // this B fragment (modes >= NB come out zero: zero table rows)
       const int pd = f - 1;
       const int64_t es3[3] = {ec, m.nbr[(2 * pd + 1) * ne + ec], m.nbr[(2 * pd) * ne + ec]};
+      const double* __restrict__ Xn = ((s == 0) ? U : Vn) + (size_t)c * NB * ne;
       R bf3[3 * KSB], g0[3];
 #pragma unroll
       for (int ks3 = 0; ks3 < 3 * KSB; ++ks3) {
         const int src = ks3 / KSB, bp = g + 4 * (ks3 % KSB);
-        const R x = (R)X[(size_t)(bp < NB ? bp : NB - 1) * ne + es3[src]];
+        const R x = (R)(src == 0 ? X : Xn)[(size_t)(bp < NB ? bp : NB - 1) * ne + es3[src]];
         bf3[ks3] = (ev && bp < NB) ? x : R(0);
       }
       if constexpr (MM::kBf16) {
 #pragma unroll
         for (int src = 0; src < 3; ++src) {
-          g0[src] = ev ? (R)X[es3[src]] : R(0);
+          g0[src] = ev ? (R)(src == 0 ? X : Xn)[es3[src]] : R(0);
           if (g == 0) bf3[src * KSB] = R(0);
         }
       }
@@ -464,7 +474,7 @@ __global__ __launch_bounds__(256, OCC) void k_volume_mfma(const double* __restri
         auto bop = [&](int k2) {
           const int side = k2 / KSF, ks = k2 % KSF;
           const int fq = g + 4 * ks;
-          const R h = H[((size_t)(p * NV + c) * NFQ + (fq < NFQ ? fq : NFQ - 1)) * ne + (side ? ec : em)];
+          const R h = (side ? H : Hm)[((size_t)(p * NV + c) * NFQ + (fq < NFQ ? fq : NFQ - 1)) * ne + (side ? ec : em)];
           return (ev && fq < NFQ) ? h : R(0);
         };
         if (kRem && mb == MB - 1) {
@@ -515,7 +525,8 @@ struct FaceTab {
 };
 
 template <class R, int NB, int NQ1, bool JVP, int P, class MM>
-DEV void face_mfma_body(const double* __restrict__ U, const double* __restrict__ V, R* __restrict__ H,
+DEV void face_mfma_body(const double* __restrict__ U, const double* __restrict__ V,
+                        const double* __restrict__ Vr, R* __restrict__ H,
                         const MTablesT<R>& mt, const Mesh& m, const Phys& ph, R (*stage)[16][16], R* ttab) {
   using T = typename Scalar<JVP, R>::type;
   using F = typename MM::frag;
@@ -541,18 +552,20 @@ DEV void face_mfma_body(const double* __restrict__ U, const double* __restrict__
   // owner, KSB..2KSB-1 from the +P neighbour
   // (BF16: entries 2KSB, 2KSB + 1 hold the mean modes of both sides, applied
   // in FP32, and the chains see zeros at mode 0)
+  // (tangent: the owner's coefficients from V, the neighbour's from Vr)
   auto load_b = [&](int s, int c, R* bf) {
     const double* __restrict__ X = (s == 0) ? U : V;
+    const double* __restrict__ Xr = (s == 0) ? U : Vr;
 #pragma unroll
     for (int ks2 = 0; ks2 < 2 * KSB; ++ks2) {
       const int b = g + 4 * (ks2 < KSB ? ks2 : ks2 - KSB);
       const int64_t es = ks2 < KSB ? ec : er;
-      const R x = (R)X[(size_t)(c * NB + (b < NB ? b : NB - 1)) * ne + es];
+      const R x = (R)(ks2 < KSB ? X : Xr)[(size_t)(c * NB + (b < NB ? b : NB - 1)) * ne + es];
       bf[ks2] = (ev && b < NB) ? x : R(0);
     }
     if constexpr (MM::kBf16) {
       bf[2 * KSB] = ev ? (R)X[(size_t)(c * NB) * ne + ec] : R(0);
-      bf[2 * KSB + 1] = ev ? (R)X[(size_t)(c * NB) * ne + er] : R(0);
+      bf[2 * KSB + 1] = ev ? (R)Xr[(size_t)(c * NB) * ne + er] : R(0);
       if (g == 0) bf[0] = bf[KSB] = R(0);
     }
   };
@@ -742,15 +755,19 @@ DEV void face_mfma_body(const double* __restrict__ U, const double* __restrict__
   }
 }
 
+// The Jv tangent of the face's owner comes from V, that of its +P neighbour
+// from Vr (V for the ordinary Jv; probing the diagonal blocks element by
+// element passes zeros for one of the two).
 template <class R, int NB, int NQ1, bool JVP, class MM, int OCC>
-__global__ __launch_bounds__(256, OCC) void k_face_mfma(
-    const double* __restrict__ U, const double* __restrict__ V, R* __restrict__ H, MTablesT<R> mt, Mesh m, Phys ph) {
+__global__ __launch_bounds__(256, OCC) void k_face_mfma(const double* __restrict__ U, const double* __restrict__ V,
+                                                   const double* __restrict__ Vr, R* __restrict__ H,
+                                                   MTablesT<R> mt, Mesh m, Phys ph) {
   __shared__ R stage[6 * 5][16][16];
   __shared__ R ttab[FaceTab<R, NB>::lds ? 6 * 2 * ((NB + 3) / 4) * 64 : 1];
   switch (blockIdx.y) {
-    case 0: face_mfma_body<R, NB, NQ1, JVP, 0, MM>(U, V, H, mt, m, ph, stage, ttab); break;
-    case 1: face_mfma_body<R, NB, NQ1, JVP, 1, MM>(U, V, H, mt, m, ph, stage, ttab); break;
-    default: face_mfma_body<R, NB, NQ1, JVP, 2, MM>(U, V, H, mt, m, ph, stage, ttab); break;
+    case 0: face_mfma_body<R, NB, NQ1, JVP, 0, MM>(U, V, Vr, H, mt, m, ph, stage, ttab); break;
+    case 1: face_mfma_body<R, NB, NQ1, JVP, 1, MM>(U, V, Vr, H, mt, m, ph, stage, ttab); break;
+    default: face_mfma_body<R, NB, NQ1, JVP, 2, MM>(U, V, Vr, H, mt, m, ph, stage, ttab); break;
   }
 }
 
@@ -766,7 +783,8 @@ __global__ __launch_bounds__(256, OCC) void k_face_mfma(
 // a shape the configuration does not have returns hipErrorInvalidValue.
 template <class R, class MM>
 hipError_t face_mfma_dispatch(int cfg, bool jvp, const double* U, const double* V, R* H, const MTablesT<R>& mt,
-                              const Mesh& m, const Phys& ph, int occ, hipStream_t s) {
+                              const Mesh& m, const Phys& ph, int occ, hipStream_t s, const double* Vr) {
+  if (!Vr) Vr = V;
 #define X(id, nb_, nq_, kl_)                                                               \
   case id: {                                                                               \
     using FT = FaceTab<R, nb_>;                                                            \
@@ -774,17 +792,17 @@ hipError_t face_mfma_dispatch(int cfg, bool jvp, const double* U, const double* 
     dim3 grid((unsigned)((m.ne + 15) / 16), 3);                                            \
     if (o == 1) {                                                                          \
       if (jvp)                                                                             \
-        k_face_mfma<R, nb_, nq_, true, MM, 1><<<grid, 256, 0, s>>>(U, V, H, mt, m, ph);    \
+        k_face_mfma<R, nb_, nq_, true, MM, 1><<<grid, 256, 0, s>>>(U, V, Vr, H, mt, m, ph);    \
       else                                                                                 \
-        k_face_mfma<R, nb_, nq_, false, MM, 1><<<grid, 256, 0, s>>>(U, V, H, mt, m, ph);   \
+        k_face_mfma<R, nb_, nq_, false, MM, 1><<<grid, 256, 0, s>>>(U, V, Vr, H, mt, m, ph);   \
     } else if (o == 2) {                                                                   \
       if constexpr (FT::only_default) {                                                    \
         return hipErrorInvalidValue;                                                       \
       } else {                                                                             \
         if (jvp)                                                                           \
-          k_face_mfma<R, nb_, nq_, true, MM, 2><<<grid, 256, 0, s>>>(U, V, H, mt, m, ph);  \
+          k_face_mfma<R, nb_, nq_, true, MM, 2><<<grid, 256, 0, s>>>(U, V, Vr, H, mt, m, ph);  \
         else                                                                               \
-          k_face_mfma<R, nb_, nq_, false, MM, 2><<<grid, 256, 0, s>>>(U, V, H, mt, m, ph); \
+          k_face_mfma<R, nb_, nq_, false, MM, 2><<<grid, 256, 0, s>>>(U, V, Vr, H, mt, m, ph); \
       }                                                                                    \
     } else {                                                                               \
       return hipErrorInvalidValue;                                                         \
@@ -797,16 +815,16 @@ hipError_t face_mfma_dispatch(int cfg, bool jvp, const double* U, const double* 
 }
 
 template <class R, class MM, int OCC, bool FG>
-hipError_t volume_launch(int nb, int nq, int kl, bool jvp, const double* U, const double* V, const R* Gm,
-                         const R* H, double* out, double shift, const MTablesT<R>& mt, const Mesh& m, const Phys& ph,
-                         hipStream_t s) {
+hipError_t volume_launch(int nb, int nq, int kl, bool jvp, const double* U, const double* V, const double* Vn,
+                         const R* Gm, const R* H, const R* Hm, double* out, double shift, const MTablesT<R>& mt,
+                         const Mesh& m, const Phys& ph, hipStream_t s) {
   const dim3 grid((unsigned)((m.ne + 15) / 16));
 #define X(id, nb_, nq_, kl_)                                                                                       \
   if (nb == nb_ && nq == nq_ && kl == kl_) {                                                                       \
     if (jvp)                                                                                                       \
-      k_volume_mfma<R, nb_, nq_, kl_, true, MM, OCC, FG><<<grid, 256, 0, s>>>(U, V, Gm, H, out, shift, mt, m, ph);  \
+      k_volume_mfma<R, nb_, nq_, kl_, true, MM, OCC, FG><<<grid, 256, 0, s>>>(U, V, Vn, Gm, H, Hm, out, shift, mt, m, ph);  \
     else                                                                                                           \
-      k_volume_mfma<R, nb_, nq_, kl_, false, MM, OCC, FG><<<grid, 256, 0, s>>>(U, V, Gm, H, out, shift, mt, m, ph); \
+      k_volume_mfma<R, nb_, nq_, kl_, false, MM, OCC, FG><<<grid, 256, 0, s>>>(U, V, Vn, Gm, H, Hm, out, shift, mt, m, ph); \
     return hipGetLastError();                                                                                      \
   }
   DG_MFMA_CONFIGS(X)
@@ -819,7 +837,9 @@ hipError_t volume_launch(int nb, int nq, int kl, bool jvp, const double* U, cons
 template <class R, class MM>
 hipError_t volume_mfma_dispatch(int cfg, bool jvp, const double* U, const double* V, const R* Gm, const R* H,
                                 double* out, double shift, const MTablesT<R>& mt, const Mesh& m, const Phys& ph,
-                                int occ, bool fused, hipStream_t s) {
+                                int occ, bool fused, hipStream_t s, const R* Hm, const double* Vn) {
+  if (!Hm) Hm = H;
+  if (!Vn) Vn = V;
   int nb = 0, nq = 0, kl = 0, o = 0;
 #define X(id, nb_, nq_, kl_)                                 \
   if (cfg == id) {                                           \
@@ -832,21 +852,21 @@ hipError_t volume_mfma_dispatch(int cfg, bool jvp, const double* U, const double
 #undef X
   if (nb == 0 || mt.kl != kl) return hipErrorInvalidValue;
   if (o == 1)
-    return fused ? volume_launch<R, MM, 1, true>(nb, nq, kl, jvp, U, V, Gm, H, out, shift, mt, m, ph, s)
-                 : volume_launch<R, MM, 1, false>(nb, nq, kl, jvp, U, V, Gm, H, out, shift, mt, m, ph, s);
+    return fused ? volume_launch<R, MM, 1, true>(nb, nq, kl, jvp, U, V, Vn, Gm, H, Hm, out, shift, mt, m, ph, s)
+                 : volume_launch<R, MM, 1, false>(nb, nq, kl, jvp, U, V, Vn, Gm, H, Hm, out, shift, mt, m, ph, s);
   if (o == 2)
-    return fused ? volume_launch<R, MM, 2, true>(nb, nq, kl, jvp, U, V, Gm, H, out, shift, mt, m, ph, s)
-                 : volume_launch<R, MM, 2, false>(nb, nq, kl, jvp, U, V, Gm, H, out, shift, mt, m, ph, s);
+    return fused ? volume_launch<R, MM, 2, true>(nb, nq, kl, jvp, U, V, Vn, Gm, H, Hm, out, shift, mt, m, ph, s)
+                 : volume_launch<R, MM, 2, false>(nb, nq, kl, jvp, U, V, Vn, Gm, H, Hm, out, shift, mt, m, ph, s);
   return hipErrorInvalidValue;
 }
 
 template <class R, class MM>
 hipError_t grad_mfma_dispatch(int cfg, bool jvp, const double* U, const double* V, R* Gm, const MTablesT<R>& mt,
-                              const Mesh& m, hipStream_t s) {
+                              const Mesh& m, hipStream_t s, const double* Vn) {
 #define X(id, nb_, nq_, kl_)                                                                \
   case id: {                                                                                \
     dim3 grid((unsigned)((m.ne + 15) / 16), 3, jvp ? 2 : 1);                                \
-    k_grad_mfma<R, nb_, MM><<<grid, 64, 0, s>>>(U, V, Gm, mt.lA, m);                            \
+    k_grad_mfma<R, nb_, MM><<<grid, 64, 0, s>>>(U, V, Vn ? Vn : V, Gm, mt.lA, m);               \
     return hipGetLastError();                                                               \
   }
   switch (cfg) { DG_MFMA_CONFIGS(X) }

@@ -22,19 +22,20 @@ bool mfma_occ_fits(int cfg, int prec, int face_occ, int volume_occ) {
 }
 
 hipError_t launch_face_mfma(int cfg, bool jvp, const double* U, const double* V, double* H, const MTables& mt,
-                            const Mesh& m, const Phys& ph, int occ, hipStream_t s) {
-  return face_mfma_dispatch<double, MP<double>>(cfg, jvp, U, V, H, mt, m, ph, occ, s);
+                            const Mesh& m, const Phys& ph, int occ, hipStream_t s, const double* Vr) {
+  return face_mfma_dispatch<double, MP<double>>(cfg, jvp, U, V, H, mt, m, ph, occ, s, Vr);
 }
 
 hipError_t launch_volume_mfma(int cfg, bool jvp, const double* U, const double* V, const double* Gm, const double* H,
                               double* out, double shift, const MTables& mt, const Mesh& m, const Phys& ph, int occ,
-                              bool fused, hipStream_t s) {
-  return volume_mfma_dispatch<double, MP<double>>(cfg, jvp, U, V, Gm, H, out, shift, mt, m, ph, occ, fused, s);
+                              bool fused, hipStream_t s, const double* Hm,
+                                  const double* Vn) {
+  return volume_mfma_dispatch<double, MP<double>>(cfg, jvp, U, V, Gm, H, out, shift, mt, m, ph, occ, fused, s, Hm, Vn);
 }
 
 hipError_t launch_grad_mfma(int cfg, bool jvp, const double* U, const double* V, double* Gm, const MTables& mt,
-                            const Mesh& m, hipStream_t s) {
-  return grad_mfma_dispatch<double, MP<double>>(cfg, jvp, U, V, Gm, mt, m, s);
+                            const Mesh& m, hipStream_t s, const double* Vn) {
+  return grad_mfma_dispatch<double, MP<double>>(cfg, jvp, U, V, Gm, mt, m, s, Vn);
 }
 
 }  // namespace dgk

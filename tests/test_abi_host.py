@@ -103,6 +103,7 @@ def test_null_arguments():
     assert lib.dg_mg_update_fine(None, None, 0.0, 1, None) == -1
     assert lib.dg_rosenbrock_step(None, None, 0.1, None, None, None, None, None) == -1
     assert lib.dg_set_tuning(None, L.DG_TUNE_AUTO) == -1
+    assert lib.dg_set_block_probing(None, L.DG_PROBE_AUTO) == -1
     assert lib.dg_autotune(None, None, None) == -1
     assert lib.dg_tuning_report(None, None, 0) == -1
     assert lib.dg_set_fine_shape(None, 0, 1, 1, 1, 0) == -1

@@ -134,6 +134,40 @@ def test_block_jacobi_parity(N, k, sp, nq, flux):
         assert np.all(err <= 2.0 ** -8 * bound + 1e-12), (err / bound).max()
 
 
+PROBE_CASES = [((4, 4, 3), 4, 5), ((5, 2, 3), 3, 4), ((3, 3, 2), 2, 3)]
+
+
+@pytest.mark.parametrize("N,k,nq", PROBE_CASES, ids=[f"N{'x'.join(map(str, c[0]))}-P{c[1]}" for c in PROBE_CASES])
+def test_element_local_probing_matches_coloured_bitwise(N, k, nq):
+    """Element-local probing of the diagonal blocks (every element perturbed at
+    once, the face kernel run once per side) gives the coloured probe's blocks
+    bit for bit (Sec. 2.3: both read the exact Jacobian's diagonal blocks, the
+    local one with the other side's tangent zero instead of a zero input):
+    FP64 and FP32 probing in the block setup, the FP32 and BF16-contraction
+    operators in the p-multigrid setup's fine blocks; several tiles, ragged
+    last tiles, a direction of two elements (both neighbours the same
+    element)."""
+    _say(f"local vs coloured probing {N} P{k}")
+    o, g, U, w = make_case(N, k, "P", nq)
+    g.set_tuning("fixed")  # the same launch shapes for both setups
+    shift = 25.0
+    r = torch.randn(g.ndof, dtype=torch.float64, device="cuda", generator=torch.Generator(device="cuda").manual_seed(3))
+    out = {}
+    for mode in ("coloured", "auto"):
+        g.set_block_probing(mode)
+        for storage in ("fp64", "fp32"):
+            g.block_setup(w, shift, storage=storage)
+            out[mode, storage] = g.block_apply(r).clone()
+        for fp in ("fp64", "fp32", "bf16"):
+            g.mg_setup(w, shift, [k, 1], [2, 4], storage="fp32", fine_precision=fp)
+            out[mode, "mg", fp] = g.mg_apply(r).clone()
+    for key, z in out.items():
+        if key[0] == "auto":
+            assert torch.isfinite(z).all(), key
+            assert torch.equal(z, out[("coloured",) + key[1:]]), key
+    g.close()
+
+
 def test_block_apply_before_setup_is_state_error():
     from paper_1809_00866_amd._lib import DGError
     o, g, U, w = make_case((2, 2, 2), 1, "P", 2)
