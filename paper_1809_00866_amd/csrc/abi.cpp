@@ -156,6 +156,45 @@ dg_status eval_local(dg_context* c, int prec, const double* w, const double* v, 
   // face fluxes of the owners' tangents (read on the +p faces) and of the
   // +p neighbours' tangents (read on the -p faces); gradients without the
   // neighbours' tangents
+  if (c->curved) {
+    // the same with the curved kernels: the second face pass reads the
+    // owner's tangent as zero and writes the jump and flux records that the
+    // volume kernel reads on the -p faces
+    const size_t nfp = (size_t)c->dim * c->ne * c->nv * c->nfq;
+    auto run = [&](auto ct, auto* loc, auto modal, auto face, auto volume, const char* sfx) -> dg_status {
+      using R = std::remove_cv_t<std::remove_pointer_t<decltype(loc)>>;
+      const R* zr = reinterpret_cast<const R*>(z);  // all-zero bits: +0 in either precision
+      auto own = ct, nbr = ct, vol = ct;
+      own.VtN = zr;
+      nbr.Vt = const_cast<R*>(zr);  // read only by the face kernel
+      nbr.VtN = ct.Vt;
+      nbr.fJmp = loc;
+      nbr.fHn = loc + 2 * nfp;
+      vol.fJmpN = nbr.fJmp;
+      vol.fHnN = nbr.fHn;
+      const std::string g = std::string("grad_jvp") + sfx, f = std::string("face_jvp") + sfx,
+                        v2 = std::string("vol_jvp") + sfx;
+      {
+        ProfScope ps(c, g.c_str(), s);
+        HIPCHK(modal(c->cfg, true, w, v, ct, c->ne, s));
+      }
+      {
+        ProfScope ps(c, f.c_str(), s);
+        HIPCHK(face(c->cfg, true, own, c->mesh, c->ph, s));
+        HIPCHK(face(c->cfg, true, nbr, c->mesh, c->ph, s));
+      }
+      ProfScope ps(c, v2.c_str(), s);
+      HIPCHK(volume(c->cfg, true, v, vol, out, shift, c->mesh, c->ph, s));
+      return DG_OK;
+    };
+    if (prec == DG_FP64) {
+      if (!c->d_cloc && (st = dalloc(&c->d_cloc, 3 * nfp)) != DG_OK) return st;
+      return run(c->ct, c->d_cloc, dgk::launch_modal_curved, dgk::launch_face_curved, dgk::launch_volume_curved, "");
+    }
+    if (!c->d_cloc_f && (st = dalloc(&c->d_cloc_f, 3 * nfp)) != DG_OK) return st;
+    return run(c->ctf, c->d_cloc_f, dgk::launch_modal_curved_f32, dgk::launch_face_curved_f32,
+               dgk::launch_volume_curved_f32, "_f32");
+  }
   if (prec == DG_FP64) {
     if (!c->d_H2 && (st = dalloc(&c->d_H2, (size_t)c->dim * c->nv * c->nfq * c->ne)) != DG_OK) return st;
     const bool fg = c->fuse_grad[DG_FP64][1];
@@ -596,6 +635,8 @@ void dg_destroy(dg_context* c) {
   dfree(c->d_H);
   dfree(c->d_H2);
   dfree(c->d_Hf2);
+  dfree(c->d_cloc);
+  dfree(c->d_cloc_f);
   dfree(c->d_t1);
   dfree(c->d_t2);
   dfree(c->d_t3);

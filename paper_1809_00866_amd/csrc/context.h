@@ -94,6 +94,8 @@ struct dg_context {
   double* d_H = nullptr;
   double* d_H2 = nullptr;        // element-local probing: face fluxes of the +face neighbours' tangents
   float* d_Hf2 = nullptr;        // the same for the FP32 / BF16-contraction operators
+  double* d_cloc = nullptr;      // the same on curved meshes: jump and flux records [3][dim*ne*nv*nfq]
+  float* d_cloc_f = nullptr;     // (FP32 curved operator)
   bool self_nbr = false;         // some element is its own face neighbour (a periodic direction of one element)
   int probe_mode = DG_PROBE_AUTO;
   double* d_t1 = nullptr;
@@ -173,9 +175,10 @@ inline bool has_prec(const dg_context* c, int prec) {
 
 // True when the diagonal blocks of the operator of precision prec can be
 // probed element-locally (every element perturbed at once): the MFMA kernels
-// of a 3D P2-P4 lattice, where no element is its own face neighbour.
+// of 3D P2-P4 lattices and the curved-element kernels, on meshes where no
+// element is its own face neighbour.
 inline bool local_probe_ok(const dg_context* c, int prec) {
-  return c->probe_mode == DG_PROBE_AUTO && c->use_mfma && !c->curved && !c->self_nbr && has_prec(c, prec);
+  return c->probe_mode == DG_PROBE_AUTO && (c->use_mfma || c->curved) && !c->self_nbr && has_prec(c, prec);
 }
 
 // Residual (jvp = false) or exact Jv plus shift*v (jvp = true) on stream s.

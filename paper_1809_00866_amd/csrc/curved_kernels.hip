@@ -131,9 +131,10 @@ __global__ __launch_bounds__(64) void k_face_curved(CurvedTablesT<R> ct, Mesh m,
   const R* geo = ct.fGeo + f * GF * NFQ;
   const bool act = fq < NFQ;
 
+  const R* __restrict__ vtn = ct.VtN ? ct.VtN : ct.Vt;  // the neighbour's tangent
   for (int i = tid; i < 2 * NS * NX; i += 64) {  // [side][c][a][value/tangent]
     const int sd = i / (NS * NX), s = (i / NX) % NS;
-    sU[(sd * NX + i % NX) * NS + s] = (s ? ct.Vt : ct.Ut)[(size_t)(sd ? er : e) * NX + (i % NX)];
+    sU[(sd * NX + i % NX) * NS + s] = (s ? (sd ? vtn : ct.Vt) : ct.Ut)[(size_t)(sd ? er : e) * NX + (i % NX)];
   }
   if constexpr (kSum)
     for (int i = tid; i < NS * NC * NFQ; i += 64) (&sG[0][0][0])[i] = R(0);
@@ -357,20 +358,24 @@ __global__ __launch_bounds__(128, sizeof(R) == 8 ? 1 : 3) void k_volume_curved(c
   for (int hf = 0; hf < 2 * DIM; ++hf)
     fidx[hf] = (size_t)(hf >> 1) * ne + ((hf & 1) ? m.nbr[(size_t)(2 * (hf >> 1)) * ne + e] : e);
   R pw[PX], pn[PX], pj[PX], ph_[PH], pp[PP];
+  const R* __restrict__ jmpN = ct.fJmpN ? ct.fJmpN : ct.fJmp;  // records of the -p faces
+  const R* __restrict__ hnN = ct.fHnN ? ct.fHnN : ct.fHn;
   auto fetch = [&](int hf) {
     const size_t f = fidx[hf];
     const int p = hf >> 1, ls = (hf & 1) ? 2 * p : 2 * p + 1;
     const R* geo = ct.fGeo + f * GF * NFQ;
+    const R* __restrict__ jmp = (hf & 1) ? jmpN : ct.fJmp;
+    const R* __restrict__ hn = (hf & 1) ? hnN : ct.fHn;
 #pragma unroll
     for (int u = 0; u < PX; ++u) {
       const int i = tid + 128 * u < NXE ? tid + 128 * u : NXE - 1;
       const int gq = i % NFQ, k = (i / NFQ) % NC, s = i / (NC * NFQ), c = k / DIM, j = k % DIM;
       pw[u] = geo[(size_t)DIM * NFQ + gq];
       pn[u] = geo[(size_t)j * NFQ + gq];
-      pj[u] = ct.fJmp[((f * 2 + s) * NV + c) * NFQ + gq];
+      pj[u] = jmp[((f * 2 + s) * NV + c) * NFQ + gq];
     }
 #pragma unroll
-    for (int u = 0; u < PH; ++u) ph_[u] = ct.fHn[f * NHE + (tid + 128 * u < NHE ? tid + 128 * u : NHE - 1)];
+    for (int u = 0; u < PH; ++u) ph_[u] = hn[f * NHE + (tid + 128 * u < NHE ? tid + 128 * u : NHE - 1)];
 #pragma unroll
     for (int u = 0; u < PP; ++u) pp[u] = ct.rFPsi[(size_t)ls * NPE + (tid + 128 * u < NPE ? tid + 128 * u : NPE - 1)];
   };

@@ -42,6 +42,12 @@ struct CurvedTablesT {
   R *Ut, *Vt;  // [ne][nv][nb]          L^{-T} U and L^{-T} V
   R* fJmp;     // [dim*ne][2][nv][nfq]  [[U]] at the face points (value, tangent)
   R* fHn;      // [dim*ne][nv][nfq]     w_f|J_f| times the normal flux (or its tangent)
+  // Probing the diagonal blocks element by element (null: the fields above):
+  // the tangent read for every face's +p neighbour (face kernel), and the
+  // jump and flux records read on an element's -p faces (volume kernel).
+  const R* VtN = nullptr;
+  const R* fJmpN = nullptr;
+  const R* fHnN = nullptr;
   int diffusion = 0;  // the scalar BR2 Laplacian (nv = 1) instead of the compressible equations
 };
 using CurvedTables = CurvedTablesT<double>;

@@ -123,6 +123,34 @@ def test_curved_block_jacobi_and_vcycle():
     g.close()
 
 
+@pytest.mark.parametrize("N,k,sp,nq", [((3, 2, 3), 3, "P", 4), ((3, 4), 2, "P", 4)], ids=["3d-P3", "2d-P2"])
+def test_curved_element_local_probing_matches_coloured_bitwise(N, k, sp, nq):
+    """On curved elements too, probing the diagonal blocks element by element
+    (the face kernel run once per side, the second run writing the jump and
+    flux records that the volume kernel reads on the -p faces) gives the
+    coloured probe's blocks bit for bit (Sec. 2.3): FP64 and FP32 probing in
+    the block setup and in the p-multigrid setup's fine blocks."""
+    _say(f"curved local vs coloured probing {N} {sp}{k}")
+    mesh, o, g, U, w, fld = make_curved(N, k, sp, nq)
+    g.set_tuning("fixed")
+    shift = 8.0
+    r = torch.randn(g.ndof, dtype=torch.float64, device="cuda", generator=torch.Generator(device="cuda").manual_seed(3))
+    out = {}
+    for mode in ("coloured", "auto"):
+        g.set_block_probing(mode)
+        for storage in ("fp64", "fp32"):
+            g.block_setup(w, shift, storage=storage)
+            out[mode, storage] = g.block_apply(r).clone()
+        for fp in ("fp64", "fp32"):
+            g.mg_setup(w, shift, (k, 1), (3, 10), storage="fp32", use_graph=True, fine_precision=fp)
+            out[mode, "mg", fp] = g.mg_apply(r).clone()
+    for key, z in out.items():
+        if key[0] == "auto":
+            assert torch.isfinite(z).all(), key
+            assert torch.equal(z, out[("coloured",) + key[1:]]), key
+    g.close()
+
+
 @pytest.mark.parametrize("N,k,sp,nq,flux", [CASES[0], CASES[3], CASES[5]], ids=[IDS[0], IDS[3], IDS[5]])
 def test_curved_fp32_operator_error_against_the_oracle(N, k, sp, nq, flux):
     """The curved kernels in FP32 (tables, contractions, pointwise fluxes;
