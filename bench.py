@@ -306,12 +306,21 @@ def time_to_tolerance(storage="fp64", precond="bj", fine_precision="fp64", resca
         g.mg_setup(w, shift, cfg["mg_orders"], cfg["mg_smooth"], storage=storage, use_graph=True,
                    fine_precision=fine_precision, rescale=rescale, coarse_ilu=coarse_ilu)
 
+    def setup():
+        if precond == "mg":
+            setup_mg()
+        else:
+            g.block_setup(w, shift, storage=storage)
+        torch.cuda.synchronize()
+
+    # a first, untimed setup: the autotuner times its candidate launch shapes
+    # once per problem shape and process (the choices are cached), so the
+    # timed setup is what every later solve of this shape pays
+    tf = time.perf_counter()
+    setup()
+    first_setup_s = time.perf_counter() - tf
     t0 = time.perf_counter()
-    if precond == "mg":
-        setup_mg()
-    else:
-        g.block_setup(w, shift, storage=storage)
-    torch.cuda.synchronize()
+    setup()
     t1 = time.perf_counter()
     x, st = g.fgmres(w, shift, b, restart=cfg["restart"], max_iter=3000, rtol=cfg["rtol"], precond=precond)
     torch.cuda.synchronize()
@@ -335,7 +344,8 @@ def time_to_tolerance(storage="fp64", precond="bj", fine_precision="fp64", resca
     mesh_name = "P4 24^3 hexes" if preset == "cfg3" else "P4 24^3 curved hexes (vertices moved by +-0.1h)"
     return {"workload": f"backward Euler, {mesh_name}, CFL 100, FGMRES(30), " + name, "create_s": t_create,
             "jv_ms": jv_ms,
-            "seconds": t2 - t0, "setup_s": t1 - t0, "solve_s": t2 - t1, "iters": st["iters"],
+            "seconds": t2 - t0, "setup_s": t1 - t0, "first_setup_s": first_setup_s, "solve_s": t2 - t1,
+            "iters": st["iters"],
             "converged": bool(st["converged"]), "rel_res_true": st["rel_res_true"], "dt": dt, **extra}
 
 
