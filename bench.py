@@ -229,7 +229,8 @@ def gpu_small_time_to_tolerance():
 
 PHASES = ("grad_jvp", "face_jvp", "vol_jvp", "grad_jvp_f32", "face_jvp_f32", "vol_jvp_f32", "grad_jvp_bf16",
           "face_jvp_bf16", "vol_jvp_bf16", "block_probe", "block_invert", "block_apply", "arnoldi", "mg_vcycle",
-          "mg_probe", "mg_coarse_invert", "mlp_apply")
+          "mg_probe", "mg_coarse_invert", "mlp_apply", "grad_probe", "face_probe", "vol_probe", "grad_probe_f32",
+          "face_probe_f32", "vol_probe_f32", "grad_probe_bf16", "face_probe_bf16", "vol_probe_bf16")
 STORAGE_BYTES = {"fp64": 8, "fp32": 4, "bf16": 2}
 
 

@@ -438,7 +438,10 @@ dg_status dg_max_wave_speed(dg_context* ctx, const double* w, double* out, void*
  * milliseconds and launch count of a named kernel ("face_jvp", "vol_jvp",
  * "face_res", "vol_res", "face_jvp_f32", "vol_jvp_f32", "block_probe",
  * "block_invert", "block_apply", "arnoldi", "mg_probe", "mg_vcycle",
- * "mlp_apply") and resets it.  Synchronises. */
+ * "mlp_apply"; the element-local probing passes inside "block_probe" as
+ * "grad_probe", "face_probe" (both face passes) and "vol_probe", with the
+ * suffix "_f32" / "_bf16" for the reduced-precision operators) and resets
+ * it.  Synchronises. */
 dg_status dg_set_profiling(dg_context* ctx, int on);
 dg_status dg_kernel_time(dg_context* ctx, const char* name, double* ms, int64_t* launches);
 

@@ -172,8 +172,8 @@ dg_status eval_local(dg_context* c, int prec, const double* w, const double* v, 
       nbr.fHn = loc + 2 * nfp;
       vol.fJmpN = nbr.fJmp;
       vol.fHnN = nbr.fHn;
-      const std::string g = std::string("grad_jvp") + sfx, f = std::string("face_jvp") + sfx,
-                        v2 = std::string("vol_jvp") + sfx;
+      const std::string g = std::string("grad_probe") + sfx, f = std::string("face_probe") + sfx,
+                        v2 = std::string("vol_probe") + sfx;
       {
         ProfScope ps(c, g.c_str(), s);
         HIPCHK(modal(c->cfg, true, w, v, ct, c->ne, s));
@@ -200,15 +200,15 @@ dg_status eval_local(dg_context* c, int prec, const double* w, const double* v, 
     const bool fg = c->fuse_grad[DG_FP64][1];
     const int* occ = c->occ[DG_FP64][1];
     if (!fg) {
-      ProfScope ps(c, "grad_jvp", s);
+      ProfScope ps(c, "grad_probe", s);
       HIPCHK(dgk::launch_grad_mfma(c->cfg, true, w, v, c->d_G, c->mt, c->mesh, s, z));
     }
     {
-      ProfScope ps(c, "face_jvp", s);
+      ProfScope ps(c, "face_probe", s);
       HIPCHK(dgk::launch_face_mfma(c->cfg, true, w, v, c->d_H, c->mt, c->mesh, c->ph, occ[0], s, z));
       HIPCHK(dgk::launch_face_mfma(c->cfg, true, w, z, c->d_H2, c->mt, c->mesh, c->ph, occ[0], s, v));
     }
-    ProfScope ps(c, "vol_jvp", s);
+    ProfScope ps(c, "vol_probe", s);
     HIPCHK(dgk::launch_volume_mfma(c->cfg, true, w, v, c->d_G, c->d_H, out, shift, c->mt, c->mesh, c->ph, occ[1], fg,
                                    s, c->d_H2, z));
     return DG_OK;
@@ -220,15 +220,15 @@ dg_status eval_local(dg_context* c, int prec, const double* w, const double* v, 
   const auto face = f32 ? dgk::launch_face_mfma_f32 : dgk::launch_face_mfma_bf16;
   const auto vol = f32 ? dgk::launch_volume_mfma_f32 : dgk::launch_volume_mfma_bf16;
   if (!fg) {
-    ProfScope ps(c, f32 ? "grad_jvp_f32" : "grad_jvp_bf16", s);
+    ProfScope ps(c, f32 ? "grad_probe_f32" : "grad_probe_bf16", s);
     HIPCHK(grad(c->cfg, true, w, v, c->d_Gf, c->mtf, c->mesh, s, z));
   }
   {
-    ProfScope ps(c, f32 ? "face_jvp_f32" : "face_jvp_bf16", s);
+    ProfScope ps(c, f32 ? "face_probe_f32" : "face_probe_bf16", s);
     HIPCHK(face(c->cfg, true, w, v, c->d_Hf, c->mtf, c->mesh, c->ph, occ[0], s, z));
     HIPCHK(face(c->cfg, true, w, z, c->d_Hf2, c->mtf, c->mesh, c->ph, occ[0], s, v));
   }
-  ProfScope ps(c, f32 ? "vol_jvp_f32" : "vol_jvp_bf16", s);
+  ProfScope ps(c, f32 ? "vol_probe_f32" : "vol_probe_bf16", s);
   HIPCHK(vol(c->cfg, true, w, v, c->d_Gf, c->d_Hf, out, shift, c->mtf, c->mesh, c->ph, occ[1], fg, s, c->d_Hf2, z));
   return DG_OK;
 }
