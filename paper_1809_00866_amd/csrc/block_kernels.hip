@@ -271,6 +271,15 @@ template <> struct Vec16<bf16_t> {
   }
 };
 
+template <class VT>
+DEVI VT nt_load(const void* p) {
+  typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+  const u4 w = __builtin_nontemporal_load(reinterpret_cast<const u4*>(p));
+  VT out;
+  __builtin_memcpy(&out, &w, sizeof(out));
+  return out;
+}
+
 template <class S, class ACC, int T, int EPW>
 __global__ __launch_bounds__(T * EPW) void k_apply(const S* __restrict__ Dinv, int m, int ld, int64_t ne,
                                                    const double* __restrict__ r, double* __restrict__ z) {
@@ -293,7 +302,7 @@ __global__ __launch_bounds__(T * EPW) void k_apply(const S* __restrict__ Dinv, i
     for (int q = 0; q < VEC; ++q) acc[q] = 0;
     const S* A = Dinv + (size_t)e * m * ld + rg * VEC;
     for (int j = cs; j < m; j += C) {
-      const typename V::T v = *reinterpret_cast<const typename V::T*>(A + (size_t)j * ld);
+      const typename V::T v = nt_load<typename V::T>(A + (size_t)j * ld);
       ACC x[VEC];
       V::get(v, x);
       const ACC rj = (ACC)rk[j];
