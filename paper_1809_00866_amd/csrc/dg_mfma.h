@@ -522,12 +522,18 @@ struct FaceTab {
   static constexpr bool lds = NB > 20;
   static constexpr int occupancy = (lds && sizeof(R) == 8) ? 1 : 2;
   static constexpr bool only_default = lds && sizeof(R) == 8;
+  // work units (tile, direction) in a 1D grid with the direction fastest (the
+  // three directions of a tile back to back on one XCD) instead of one grid
+  // row per direction: P4 FP32 face Jv 0.177 -> 0.165 ms at 24^3, FP64 level;
+  // at P3 the row form measured 1 % faster in FP64
+  static constexpr bool dir_fast = lds;
 };
 
 template <class R, int NB, int NQ1, bool JVP, int P, class MM>
 DEV void face_mfma_body(const double* __restrict__ U, const double* __restrict__ V,
                         const double* __restrict__ Vr, R* __restrict__ H,
-                        const MTablesT<R>& mt, const Mesh& m, const Phys& ph, R (*stage)[16][16], R* ttab) {
+                        const MTablesT<R>& mt, const Mesh& m, const Phys& ph, R (*stage)[16][16], R* ttab,
+                        int64_t tile) {
   using T = typename Scalar<JVP, R>::type;
   using F = typename MM::frag;
   constexpr int DIM = 3, NV = 5;
@@ -541,7 +547,7 @@ DEV void face_mfma_body(const double* __restrict__ U, const double* __restrict__
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int g = lane >> 4, col = lane & 15;
   const int64_t ne = m.ne;
-  const int64_t e0 = xcd_tile(blockIdx.x, gridDim.x) * 16;
+  const int64_t e0 = (FaceTab<R, NB>::dir_fast ? tile : xcd_tile(blockIdx.x, gridDim.x)) * 16;
   const int64_t e = e0 + col;
   const bool ev = e < ne;
   const int64_t ec = ev ? e : ne - 1;  // clamped element: loads stay branch-free
@@ -764,10 +770,17 @@ __global__ __launch_bounds__(256, OCC) void k_face_mfma(const double* __restrict
                                                    MTablesT<R> mt, Mesh m, Phys ph) {
   __shared__ R stage[6 * 5][16][16];
   __shared__ R ttab[FaceTab<R, NB>::lds ? 6 * 2 * ((NB + 3) / 4) * 64 : 1];
-  switch (blockIdx.y) {
-    case 0: face_mfma_body<R, NB, NQ1, JVP, 0, MM>(U, V, Vr, H, mt, m, ph, stage, ttab); break;
-    case 1: face_mfma_body<R, NB, NQ1, JVP, 1, MM>(U, V, Vr, H, mt, m, ph, stage, ttab); break;
-    default: face_mfma_body<R, NB, NQ1, JVP, 2, MM>(U, V, Vr, H, mt, m, ph, stage, ttab); break;
+  int64_t tile = 0;  // (the row form computes its tile in the body)
+  int P = blockIdx.y;
+  if constexpr (FaceTab<R, NB>::dir_fast) {
+    const int64_t u = xcd_tile(blockIdx.x, gridDim.x);
+    tile = u / 3;
+    P = (int)(u % 3);
+  }
+  switch (P) {
+    case 0: face_mfma_body<R, NB, NQ1, JVP, 0, MM>(U, V, Vr, H, mt, m, ph, stage, ttab, tile); break;
+    case 1: face_mfma_body<R, NB, NQ1, JVP, 1, MM>(U, V, Vr, H, mt, m, ph, stage, ttab, tile); break;
+    default: face_mfma_body<R, NB, NQ1, JVP, 2, MM>(U, V, Vr, H, mt, m, ph, stage, ttab, tile); break;
   }
 }
 
@@ -789,7 +802,8 @@ hipError_t face_mfma_dispatch(int cfg, bool jvp, const double* U, const double* 
   case id: {                                                                               \
     using FT = FaceTab<R, nb_>;                                                            \
     const int o = occ ? occ : FT::occupancy;                                               \
-    dim3 grid((unsigned)((m.ne + 15) / 16), 3);                                            \
+    const unsigned nt = (unsigned)((m.ne + 15) / 16);                                      \
+    const dim3 grid = FT::dir_fast ? dim3(nt * 3) : dim3(nt, 3);                           \
     if (o == 1) {                                                                          \
       if (jvp)                                                                             \
         k_face_mfma<R, nb_, nq_, true, MM, 1><<<grid, 256, 0, s>>>(U, V, Vr, H, mt, m, ph);    \
