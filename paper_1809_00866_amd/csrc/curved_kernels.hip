@@ -35,6 +35,14 @@ namespace dgk {
 
 namespace {
 
+// block id -> work unit: consecutive units on one XCD (blocks are dealt to
+// the 8 XCDs in turn, each with its own L2)
+DEV int64_t xcd_unit(int64_t bid, int64_t nblk) {
+  constexpr int64_t kXcd = 8;
+  const int64_t q = nblk / kXcd, r = nblk % kXcd, x = bid % kXcd;
+  return x * q + (x < r ? x : r) + bid / kXcd;
+}
+
 template <bool JVP, class R>
 DEV typename Scalar<JVP, R>::type mk(R v, R t) {
   if constexpr (JVP)
@@ -123,9 +131,12 @@ __global__ __launch_bounds__(64) void k_face_curved(CurvedTablesT<R> ct, Mesh m,
   auto sX = reinterpret_cast<R(*)[NC][NFQ]>(sW);            // [s][c*DIM+j][fq]: w n_j [[U_c]]
   auto sR = reinterpret_cast<R(*)[NC][NFQ]>(sW);            // {r}_cj at the face points (over sX)
   const int tid = threadIdx.x, side = tid >> 5, fq = tid & 31;
-  const int P = blockIdx.y;
+  // work units (element, direction), direction fastest, a contiguous range
+  // of elements per XCD (blocks are dealt to the 8 XCDs in turn)
   const int64_t ne = m.ne;
-  const int64_t e = blockIdx.x;
+  const int64_t u = xcd_unit(blockIdx.x, gridDim.x);
+  const int P = (int)(u % DIM);
+  const int64_t e = u / DIM;
   const int64_t er = m.nbr[(size_t)(2 * P + 1) * ne + e];
   const size_t f = (size_t)P * ne + e;
   const R* geo = ct.fGeo + f * GF * NFQ;
@@ -319,7 +330,7 @@ __global__ __launch_bounds__(128, sizeof(R) == 8 ? 1 : 3) void k_volume_curved(c
   __shared__ R sY[NX];                         // projection on psi
   const int tid = threadIdx.x;
   const int64_t ne = m.ne;
-  const int64_t e = blockIdx.x;
+  const int64_t e = xcd_unit(blockIdx.x, gridDim.x);
   const bool vt = JVP && !ph.stab_only;  // tangent of the volume terms
 
   for (int i = tid; i < NB * NB; i += 128) {
@@ -702,7 +713,7 @@ hipError_t face_curved(int cfg, bool jvp, const CurvedTablesT<R>& ct, const Mesh
     if constexpr (sizeof(R) == 8) {
 #define X(id, d, nb_, nq_)                                                          \
   case id: {                                                                        \
-    dim3 grid((unsigned)m.ne, d);                                                   \
+    const unsigned grid = (unsigned)m.ne * d;                                       \
     if (jvp)                                                                        \
       k_face_curved<R, d, nb_, nq_, true, true><<<grid, 64, 0, s>>>(ct, m, ph);     \
     else                                                                            \
@@ -716,7 +727,7 @@ hipError_t face_curved(int cfg, bool jvp, const CurvedTablesT<R>& ct, const Mesh
   }
 #define X(id, d, nb_, nq_)                                                          \
   case id: {                                                                        \
-    dim3 grid((unsigned)m.ne, d);                                                   \
+    const unsigned grid = (unsigned)m.ne * d;                                       \
     if (jvp)                                                                        \
       k_face_curved<R, d, nb_, nq_, true><<<grid, 64, 0, s>>>(ct, m, ph);           \
     else                                                                            \
