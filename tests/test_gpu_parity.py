@@ -165,6 +165,7 @@ def test_element_local_probing_matches_coloured_bitwise(N, k, nq):
         if key[0] == "auto":
             assert torch.isfinite(z).all(), key
             assert torch.equal(z, out[("coloured",) + key[1:]]), key
+    assert g.lib.dg_set_block_probing(g.ctx, 7) == -1  # DG_ERR_ARG: unknown mode
     g.close()
 
 
