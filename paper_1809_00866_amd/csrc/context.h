@@ -203,9 +203,10 @@ dg_status eval_local(dg_context* c, int prec, const double* w, const double* v, 
 // FP64 or the FP32 operator.
 dg_status eval_stab(dg_context* c, bool f32, const double* w, const double* v, double* out, hipStream_t s);
 // Element-block Jacobi setup in two steps: storage for the blocks, then the
-// coloured probing, with the operator of precision probe_prec, of every column
-// whose mode index is at least skip_modes (the caller has written the others
-// into d_D64) and the inversion.
+// probing (element-local where local_probe_ok allows it, else coloured), with
+// the operator of precision probe_prec, of every column whose mode index is at
+// least skip_modes (the caller has written the others into d_D64) and the
+// inversion.
 dg_status block_alloc(dg_context* c, int storage);
 dg_status block_probe_invert(dg_context* c, const double* w, double shift, int storage, int skip_modes,
                              int probe_prec, hipStream_t s);
