@@ -15,7 +15,9 @@ well as a 2-norm over the sample:
   same scales, and above 1e-10 (genuinely reduced precision);
 * BF16-contraction operator (affine lattice only; the curved mesh refuses it):
   <= 3e-2 of the same scales and above 1e-5;
-the measured errors are printed.
+the measured errors are printed.  The diagonal blocks of block Jacobi, probed
+element by element, are checked against the oracle's blocks of four sampled
+elements (z = D^-1 r to 1e-11 with FP64 factors, 1e-4 with FP32 factors).
 """
 import sys
 
@@ -125,6 +127,56 @@ def test_full_size_p4_jvp(workload, precision):
     e_max, e_2 = _errors(Jg, ref, scale)
     _say(f"  jvp {precision}: max-entry error {e_max:.2e}, 2-norm error {e_2:.2e}")
     _check(e_max, e_2, precision)
+
+
+def _oracle_block(o, U, K, shift, h=1e-100):
+    """D_K = shift*M_K + dR_K/dU_K of one element, column by column from the
+    oracle's residual of element K alone under a complex-step perturbation of
+    one of its coefficients (Sec. 2.3: the block of EWBJ is the Jacobian's
+    diagonal block)."""
+    nloc = o.nvar * o.nb
+    Uc = U.astype(np.complex128)
+    D = np.zeros((nloc, nloc))
+    for j in range(nloc):
+        c, b = divmod(j, o.nb)
+        Uc[K, c, b] += 1j * h
+        D[:, j] = (np.imag(o.residual(Uc, elems=[K]))[0] / h).reshape(-1)
+        Uc[K, c, b] -= 1j * h
+    D += shift * np.diag(np.repeat(o.mass(), o.nb))
+    return D
+
+
+BLOCK_BOUNDS = {"fp64": 1e-11, "fp32": 1e-4}
+
+
+@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+def test_full_size_p4_block_jacobi(workload, storage):
+    """The diagonal blocks of the P4 24^3 systems, probed element by element
+    (the default probing) in the launch configuration the benchmark times:
+    z_K = D_K^-1 r_K against the oracle's own blocks on sampled elements (the
+    first element, the first of the second tile, the first of the fifth XCD
+    range, the last), relative error <= 1e-11 with FP64 factors and <= 1e-4
+    with FP32 factors (probed with the FP32 operator)."""
+    o, g, w = workload["o"], workload["g"], workload["w"]
+    ne = o.ne
+    nblk = (ne + TILE - 1) // TILE
+    q, r = divmod(nblk, N_XCD)
+    elems = [0, TILE, (4 * q + min(4, r)) * TILE, ne - 1]
+    shift = 25.0
+    if "blocks" not in workload:
+        _say(f"full-size {workload['name']}: oracle blocks of elements {elems}")
+        U = o.from_flat(w.cpu().numpy())
+        workload["blocks"] = {K: _oracle_block(o, U, K, shift) for K in elems}
+    rv = torch.tensor(synth.random_vector(g.ndof, 4), device="cuda")
+    g.block_setup(w, shift, storage=storage)
+    z = o.from_flat(g.block_apply(rv).cpu().numpy())
+    R = o.from_flat(rv.cpu().numpy())
+    for K in elems:
+        D = workload["blocks"][K]
+        ref = np.linalg.solve(D, R[K].reshape(-1))
+        err = np.linalg.norm(z[K].reshape(-1) - ref) / np.linalg.norm(ref)
+        _say(f"  block {storage} element {K}: relative error {err:.2e}, cond {np.linalg.cond(D):.1e}")
+        assert err <= BLOCK_BOUNDS[storage], (K, err)
 
 
 def test_boundary_sample_covers_tiles_and_xcd_ranges():
